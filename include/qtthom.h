@@ -1,0 +1,236 @@
+/*
+ * qtthom -- SFFT-based homogenization on quantized tensor trains (C ABI).
+ *
+ * Implements the hot path of the SFFT-based homogenization algorithm of
+ * Hauck, Kabel, Ali and Gauger (arXiv 2412.11566): the Lippmann-Schwinger
+ * fixed point of the FFT-based basic scheme (Sec. 2, Alg. 1) carried out on
+ * strain fields held in controlled quantized tensor-train (QTT) format
+ * (Sec. 4.3, Alg. 2), on one AMD Instinct GPU (gfx950).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * - A 3D periodic unit cell with N = 2^n voxels per axis.  Strain and stress
+ *   fields carry a Voigt control core in front of the 3n binary cores
+ *   (Sec. 4.3, controlled QTT): L = 3n + 1 cores.  Core 0 has physical
+ *   dimension 6 (Voigt order 11, 22, 33, 23, 13, 12; strains with
+ *   engineering shear, stresses plain); cores 1..n hold the bits of x, most
+ *   significant first (Sec. 4.3, binary discretisation), then y, then z.
+ * - Tensor-train cores are stored row-major as (r_{k-1}, d_k, r_k) with r_k
+ *   fastest; complex numbers are interleaved (re, im) doubles.  A tensor
+ *   handle may hold a batch of B trains with common ranks (for instance the
+ *   six unit load cases); batch element b of core k starts at
+ *   b * r_{k-1} * d_k * r_k complex entries.
+ * - Operators (TTOs, Sec. 3 eq. tto_format) are opaque handles.  Their
+ *   cores have an (out, in) physical pair; "raised" operators (Sec. 3,
+ *   eq. tt_to_tto; App. C) are stored diagonally.
+ * - Device buffers: pointers documented as "device" must be device memory
+ *   of the context's device; "host" pointers are ordinary host memory.
+ * - Ownership: every qtt_tensor returned through an out-pointer is owned
+ *   by the caller and released with qtt_tensor_destroy.  Input arrays stay
+ *   owned by the caller.
+ * - Errors: every call returns 0 (QTT_OK) or a negative QTT_E* code; no C++
+ *   exception crosses the ABI.  qtt_last_error(ctx) returns a message for
+ *   the last failure on that context.  A context is not thread-safe.
+ * - Rounding parameters: delta is the relative Frobenius accuracy of
+ *   TT-rounding, ||v - v~||_F <= delta ||v||_F (Sec. 3,
+ *   eq. rounding_condition_tt), split evenly over the L-1 bonds; cap bounds
+ *   every bond rank (cap <= 0 means no cap).
+ */
+#ifndef QTTHOM_H
+#define QTTHOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define QTT_OK          0
+#define QTT_EINVAL     -1   /* invalid argument or shape mismatch          */
+#define QTT_ENOMEM     -2   /* device or host allocation failed            */
+#define QTT_ECAPACITY  -3   /* a size exceeds a documented maximum         */
+#define QTT_EHIP       -4   /* HIP runtime error                           */
+#define QTT_ENOCONV    -5   /* fixed point hit max_iter before tolerance   */
+#define QTT_ENAN       -6   /* NaN or Inf met in a reduction               */
+#define QTT_EDIVERGED  -7   /* residual grew beyond the divergence limit   */
+
+/* ---- flags ------------------------------------------------------------- */
+#define QTT_INVERSE     1   /* sfft_apply: apply S^H (the ISFFT)           */
+#define QTT_NO_ROUND    2   /* products: materialise, do not round         */
+#define QTT_EXACT       4   /* products: sketch at the full structural rank */
+
+/* precision of the core contractions (rounding is always FP64) */
+#define QTT_PREC_FP64   0
+#define QTT_PREC_FP32   1
+
+typedef struct qtt_ctx qtt_ctx;
+typedef struct qtt_tensor qtt_tensor;
+
+/* Problem statement: the corrector problem of Sec. 2 on a voxel grid. */
+typedef struct qtt_problem {
+    int n;                   /* bits per axis, N = 2^n, 1 <= n <= 10       */
+    const uint8_t* phase;    /* host, N^3 phase ids, C order, x slowest    */
+    int nphase;              /* number of phases, 1..16                    */
+    const double* lame;      /* host, [nphase][2] = (lambda, mu)           */
+    double lame0[2];         /* reference medium (lambda0, mu0)            */
+    int load_mask;           /* bit k set: solve unit load case e_k        */
+} qtt_problem;
+
+typedef struct qtt_solve_opts {
+    double delta;            /* rounding accuracy delta_acc                */
+    double tol;              /* fixed-point tolerance delta_tol            */
+    int cap;                 /* bond-rank cap (<= 0: none)                 */
+    int max_iter;            /* iteration limit per load case              */
+    int precision;           /* QTT_PREC_*                                 */
+    int oversample;          /* extra sketch rank beyond cap (>= 0)        */
+    int exact;               /* nonzero: sketch at full structural rank    */
+    uint64_t seed;           /* seed of the sketching random numbers       */
+} qtt_solve_opts;
+
+typedef struct qtt_report {
+    int iterations[6];       /* fixed-point updates per load case          */
+    double residual[6];      /* last relative update per load case         */
+    int max_rank;            /* largest strain bond rank after rounding    */
+    double discarded;        /* largest relative discarded mass, any round */
+    int status;              /* QTT_OK or the failure code                 */
+    double seconds_setup;    /* operator construction (not in the loop)    */
+    double seconds_solve;    /* fixed-point loop, all load cases           */
+} qtt_report;
+
+/* ---- context ----------------------------------------------------------- */
+/* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * to enqueue all work on, or NULL for a stream owned by the context. */
+int qtt_create(int device, void* hip_stream, qtt_ctx** ctx);
+int qtt_destroy(qtt_ctx* ctx);
+const char* qtt_last_error(const qtt_ctx* ctx);
+/* Blocks until all work enqueued by the context has finished. */
+int qtt_sync(qtt_ctx* ctx);
+
+/* ---- tensors ----------------------------------------------------------- */
+/* A batch of `batch` tensor trains with L cores, physical dims dims[L] and
+ * bond ranks ranks[L+1] (ranks[0] = ranks[L] = 1), copied from host
+ * interleaved complex data laid out core by core, each core batch-major
+ * (batch, r_{k-1}, d_k, r_k). */
+int qtt_tt_from_host(qtt_ctx* ctx, int L, const int* dims, const int* ranks,
+                     int batch, const double* data, qtt_tensor** out);
+/* Shape query: kind (0 = TT, 1 = operator), L, batch, dims_out[L],
+ * dims_in[L] (operators; TT: copies of dims_out), ranks[L+1].  Any output
+ * pointer may be NULL. */
+int qtt_tensor_shape(const qtt_tensor* t, int* kind, int* L, int* batch,
+                     int* dims_out, int* dims_in, int* ranks);
+/* Number of complex entries qtt_tensor_to_host writes. */
+size_t qtt_tensor_size(const qtt_tensor* t);
+/* Copies all cores to host, same layout as qtt_tt_from_host.  Operators
+ * are written as full cores (r_{k-1}, d_out, d_in, r_k) even when stored
+ * diagonally.  `capacity` is the number of complex entries available. */
+int qtt_tensor_to_host(qtt_ctx* ctx, const qtt_tensor* t, double* data,
+                       size_t capacity);
+int qtt_tensor_destroy(qtt_tensor* t);
+
+/* Constant strain field of each batch element: E[b][6] (host); rank-1
+ * train of Sec. 4.3 (constant operands). */
+int qtt_const_strain(qtt_ctx* ctx, int n, int batch, const double* E,
+                     qtt_tensor** out);
+
+/* ---- operators (Sec. 4) ------------------------------------------------ */
+/* SFFT operator: the reduced QFT Q_n of Sec. 4.1 (QFT circuit without the
+ * final SWAPs) on each spatial axis, identity on the Voigt core, built by
+ * contracting the circuit's gates into a TTO with SVD truncation at
+ * `delta` (Zip-Up, Sec. 4.2).  On one axis, S maps the voxel index j to
+ * the momentum index k with weight N^-1/2 exp(+2 pi i j rev_n(k) / N). */
+int qtt_sfft_build(qtt_ctx* ctx, int n, double delta, qtt_tensor** S);
+
+/* Green operator Gamma_0 of App. A (direct scheme, k = i q) for the
+ * isotropic reference medium (lam0, mu0), Nyquist-symmetrised, in the SFFT
+ * momentum convention of Sec. 4.3 (indices reversed per axis, then complex
+ * conjugated).  It is held in the separable form of App. D
+ * (eq. green_separability): Gamma = (1/mu0) h A - c h^2 B with
+ * h = 1/|xi|^2 and polynomial Voigt operators A, B, each a raised TTO. */
+int qtt_green_build(qtt_ctx* ctx, int n, double lam0, double mu0,
+                    double delta, qtt_tensor** G);
+
+/* Raised stiffness operator C(x) - C0 (Sec. 4.3; App. D: recomputed per
+ * geometry) from a voxel phase array (binary discretisation of Sec. 4.3
+ * followed by TT-SVD).  phase: host or device (`phase_on_device`), N^3
+ * uint8, C order, x slowest, values < nphase.  lame: host [nphase][2].
+ * The optional `chi` receives the one-hot phase train (core 0 of
+ * dimension nphase).  QTT_ECAPACITY if a rank would exceed `cap`. */
+int qtt_from_voxels(qtt_ctx* ctx, const uint8_t* phase, int phase_on_device,
+                    int n, int nphase, const double* lame,
+                    const double lame0[2], double delta, int cap,
+                    qtt_tensor** C_minus_C0, qtt_tensor** chi);
+
+/* ---- products, each followed by TT-rounding --------------------------- */
+/* y = S x (or S^H x with QTT_INVERSE), Sec. 4.3 Alg. 2 lines for the SFFT
+ * and ISFFT.  Unless QTT_NO_ROUND, the product is rounded to (delta, cap)
+ * by a randomized range sketch of the implicit product followed by
+ * truncated SVDs; `seed` fixes the sketch.  QTT_NO_ROUND materialises the
+ * product with ranks multiplied (Table 2, contract). */
+int sfft_apply(qtt_ctx* ctx, const qtt_tensor* S, const qtt_tensor* x,
+               qtt_tensor** y, int flags, double delta, int cap,
+               uint64_t seed);
+
+/* y = (C - C0) : x, the Hadamard stiffness product of Alg. 2 computed as
+ * a raised TTO times a TT (Sec. 3, eq. tt_to_tto; App. C). */
+int tt_hadamard(qtt_ctx* ctx, const qtt_tensor* A, const qtt_tensor* x,
+                qtt_tensor** y, int flags, double delta, int cap,
+                uint64_t seed);
+
+/* y = Gamma_0 : x in momentum space (Alg. 2, Green step). */
+int green_apply(qtt_ctx* ctx, const qtt_tensor* G, const qtt_tensor* x,
+                qtt_tensor** y, int flags, double delta, int cap,
+                uint64_t seed);
+
+/* In-place TT-rounding (Sec. 3): QR orthogonalisation sweep, then
+ * truncated SVDs keeping per bond the smallest rank whose discarded
+ * squared singular values sum to at most (delta / sqrt(L-1) ||x||)^2,
+ * clipped to cap.  `discarded` (host, may be NULL) receives, per batch
+ * element, sqrt(sum of discarded sigma^2) / ||x||. */
+int tt_round(qtt_ctx* ctx, qtt_tensor* x, double delta, int cap,
+             double* discarded);
+
+/* Frobenius norms of each batch element (host out[batch]), computed from
+ * an orthogonalisation sweep in FP64. */
+int tt_norm(qtt_ctx* ctx, const qtt_tensor* x, double* out);
+
+/* z = alpha x + beta y (ranks add, Table 2), alpha/beta real. */
+int tt_axpby(qtt_ctx* ctx, double alpha, const qtt_tensor* x, double beta,
+             const qtt_tensor* y, qtt_tensor** z);
+
+/* Volume average of A(x) : x over all voxels (host out[batch][6], complex
+ * interleaved): the mean stress term of Sec. 2 for A = C - C0 or C. */
+int tt_mean_apply(qtt_ctx* ctx, const qtt_tensor* A, const qtt_tensor* x,
+                  double* out);
+
+/* ---- solvers ------------------------------------------------------------ */
+/* Alg. 2 for the unit load cases selected by P->load_mask, then
+ * C_eff[:, k] = < C eps^k > (Sec. 2).  Ceff: host [36], row-major.
+ * eps_out (optional): receives the converged strain trains (batch = number
+ * of solved load cases, in increasing k).  Returns QTT_ENOCONV when a load
+ * case reached max_iter (Ceff and R still filled). */
+int ls_solve(qtt_ctx* ctx, const qtt_problem* P, const qtt_solve_opts* O,
+             double* Ceff, qtt_report* R, qtt_tensor** eps_out);
+
+/* Adjoint Lippmann-Schwinger solve and gradient of C_eff with respect to
+ * the phase Lame parameters theta = (lam_0, mu_0, lam_1, mu_1, ...), C0
+ * held fixed.  For each load case k the adjoint fixed point
+ * w_k = C e_k - (C - C0) G[w_k] (G = S^H Gamma S) is iterated with the
+ * adjoint operators, then dC_kl/dtheta = <e_k, dC eps^l> - <w_k, G dC eps^l>.
+ * eps: the six converged forward trains (from ls_solve, all six load
+ * cases).  gbar: host [36] cotangent of C_eff or NULL; grad: host,
+ * [2 nphase] if gbar is given, else the full Jacobian [36][2 nphase]. */
+int ls_adjoint(qtt_ctx* ctx, const qtt_problem* P, const qtt_solve_opts* O,
+               const qtt_tensor* eps, const double* gbar, double* grad,
+               qtt_report* R);
+
+/* Many problems in one call (the six load cases of each are batched
+ * together; problems are grouped by grid size).  Ceff: host [count][36]. */
+int qtt_batch_solve(qtt_ctx* ctx, int count, const qtt_problem* Ps,
+                    const qtt_solve_opts* O, double* Ceff, qtt_report* Rs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QTTHOM_H */

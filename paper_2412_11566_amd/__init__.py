@@ -1,0 +1,308 @@
+"""qtthom: SFFT-based homogenization on quantized tensor trains, MI355X-native.
+
+Thin Python binding over the C ABI of ``include/qtthom.h`` (same names).  It
+only marshals arguments: the tensor-train arithmetic, the operators and the
+Lippmann-Schwinger loop run in the HIP library ``libqtthom.so``.  PyTorch
+is used for the device and stream handle only (``torch.cuda`` current
+stream), never for compute.
+
+Method: Hauck, Kabel, Ali, Gauger, "SFFT-based homogenization" (arXiv
+2412.11566): Sec. 2 Alg. 1 (basic scheme), Sec. 4.3 Alg. 2 (the same fixed
+point on controlled QTT strain fields).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _capi as _c
+from ._capi import (QTT_EXACT, QTT_INVERSE, QTT_NO_ROUND, QTT_OK, QTT_ENOCONV,
+                    QTT_PREC_FP32, QTT_PREC_FP64)
+
+__all__ = [
+    "QttError", "Context", "Tensor", "SolveOptions", "SolveReport",
+    "tt_from_cores", "const_strain", "sfft_build", "green_build", "from_voxels",
+    "sfft_apply", "tt_hadamard", "green_apply", "tt_round", "tt_norm", "tt_axpby",
+    "tt_mean_apply", "ls_solve", "ls_adjoint", "batch_solve",
+    "QTT_EXACT", "QTT_INVERSE", "QTT_NO_ROUND", "QTT_PREC_FP32", "QTT_PREC_FP64",
+]
+
+
+class QttError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"qtthom error {_c.ERR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+class Context:
+    """A qtthom context on one HIP device and stream."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        import torch  # device/stream plumbing only
+        if not torch.cuda.is_available():
+            raise QttError(_c.QTT_EHIP, "no HIP device visible")
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = C.c_void_p()
+        rc = _c.lib().qtt_create(device, C.c_void_p(stream) if stream else None, C.byref(h))
+        if rc != QTT_OK:
+            raise QttError(rc, "qtt_create failed")
+        self.h = h
+
+    def check(self, rc: int, allow=()):
+        if rc != QTT_OK and rc not in allow:
+            msg = _c.lib().qtt_last_error(self.h)
+            raise QttError(rc, msg.decode() if msg else "")
+        return rc
+
+    def sync(self):
+        self.check(_c.lib().qtt_sync(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _c.lib().qtt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tensor:
+    """Owning handle of a qtt_tensor (train batch or operator)."""
+
+    def __init__(self, ctx: Context, h: C.c_void_p):
+        self.ctx = ctx
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _c.lib().qtt_tensor_destroy(self.h)
+            self.h = None
+
+    def shape(self):
+        kind, L, B = C.c_int(), C.c_int(), C.c_int()
+        _c.lib().qtt_tensor_shape(self.h, C.byref(kind), C.byref(L), C.byref(B),
+                                  None, None, None)
+        dout = np.zeros(L.value, np.int32)
+        din = np.zeros(L.value, np.int32)
+        ranks = np.zeros(L.value + 1, np.int32)
+        _c.lib().qtt_tensor_shape(self.h, None, None, None, _ip(dout), _ip(din), _ip(ranks))
+        return {"kind": kind.value, "L": L.value, "batch": B.value,
+                "dims_out": dout.tolist(), "dims_in": din.tolist(), "ranks": ranks.tolist()}
+
+    @property
+    def ranks(self):
+        return self.shape()["ranks"]
+
+    def cores(self):
+        """Host copies: trains -> list of (B, r0, d, r1); operators -> (r0, dout, din, r1)."""
+        s = self.shape()
+        n = _c.lib().qtt_tensor_size(self.h)
+        buf = np.zeros(2 * n, np.float64)
+        self.ctx.check(_c.lib().qtt_tensor_to_host(self.ctx.h, self.h, _dp(buf), n))
+        z = buf.view(np.complex128)
+        out, off = [], 0
+        r = s["ranks"]
+        for k in range(s["L"]):
+            if s["kind"] == 0:
+                shp = (s["batch"], r[k], s["dims_out"][k], r[k + 1])
+            else:
+                shp = (r[k], s["dims_out"][k], s["dims_in"][k], r[k + 1])
+            cnt = int(np.prod(shp))
+            out.append(z[off:off + cnt].reshape(shp).copy())
+            off += cnt
+        return out
+
+
+def _new(ctx: Context, fn, *args) -> Tensor:
+    h = C.c_void_p()
+    ctx.check(fn(ctx.h, *args, C.byref(h)))
+    return Tensor(ctx, h)
+
+
+def tt_from_cores(ctx: Context, cores) -> Tensor:
+    """Upload a batch of trains; cores[k] has shape (B, r_{k-1}, d_k, r_k)."""
+    cores = [np.ascontiguousarray(c, dtype=np.complex128) for c in cores]
+    B = cores[0].shape[0]
+    dims = np.array([c.shape[2] for c in cores], np.int32)
+    ranks = np.array([cores[0].shape[1]] + [c.shape[3] for c in cores], np.int32)
+    data = np.concatenate([c.ravel() for c in cores]).view(np.float64)
+    return _new(ctx, _c.lib().qtt_tt_from_host, len(cores), _ip(dims), _ip(ranks), B, _dp(data))
+
+
+def const_strain(ctx: Context, n: int, E) -> Tensor:
+    E = np.ascontiguousarray(np.atleast_2d(E), dtype=np.float64)
+    return _new(ctx, _c.lib().qtt_const_strain, n, E.shape[0], _dp(E))
+
+
+def sfft_build(ctx: Context, n: int, delta: float) -> Tensor:
+    return _new(ctx, _c.lib().qtt_sfft_build, n, delta)
+
+
+def green_build(ctx: Context, n: int, lam0: float, mu0: float, delta: float) -> Tensor:
+    return _new(ctx, _c.lib().qtt_green_build, n, lam0, mu0, delta)
+
+
+def from_voxels(ctx: Context, phase: np.ndarray, lame, lame0, delta: float, cap: int = 0):
+    """(C - C0) raised operator and the one-hot phase train."""
+    phase = np.ascontiguousarray(phase, dtype=np.uint8)
+    n = int(round(np.log2(phase.shape[0])))
+    lame = np.ascontiguousarray(lame, dtype=np.float64)
+    l0 = np.ascontiguousarray(lame0, dtype=np.float64)
+    h, chi = C.c_void_p(), C.c_void_p()
+    ctx.check(_c.lib().qtt_from_voxels(
+        ctx.h, phase.ctypes.data_as(C.POINTER(C.c_uint8)), 0, n, lame.shape[0], _dp(lame),
+        _dp(l0), delta, cap, C.byref(h), C.byref(chi)))
+    return Tensor(ctx, h), Tensor(ctx, chi)
+
+
+def _prod(fn, ctx, A, x, flags, delta, cap, seed):
+    h = C.c_void_p()
+    ctx.check(fn(ctx.h, A.h, x.h, C.byref(h), flags, delta, cap, seed))
+    return Tensor(ctx, h)
+
+
+def sfft_apply(ctx, S, x, inverse=False, delta=1e-10, cap=0, seed=0, flags=0) -> Tensor:
+    return _prod(_c.lib().sfft_apply, ctx, S, x, flags | (QTT_INVERSE if inverse else 0),
+                 delta, cap, seed)
+
+
+def tt_hadamard(ctx, A, x, delta=1e-10, cap=0, seed=0, flags=0) -> Tensor:
+    return _prod(_c.lib().tt_hadamard, ctx, A, x, flags, delta, cap, seed)
+
+
+def green_apply(ctx, G, x, delta=1e-10, cap=0, seed=0, flags=0) -> Tensor:
+    return _prod(_c.lib().green_apply, ctx, G, x, flags, delta, cap, seed)
+
+
+def tt_round(ctx, x: Tensor, delta: float, cap: int = 0) -> np.ndarray:
+    B = x.shape()["batch"]
+    disc = np.zeros(B)
+    ctx.check(_c.lib().tt_round(ctx.h, x.h, delta, cap, _dp(disc)))
+    return disc
+
+
+def tt_norm(ctx, x: Tensor) -> np.ndarray:
+    out = np.zeros(x.shape()["batch"])
+    ctx.check(_c.lib().tt_norm(ctx.h, x.h, _dp(out)))
+    return out
+
+
+def tt_axpby(ctx, alpha, x, beta, y) -> Tensor:
+    h = C.c_void_p()
+    ctx.check(_c.lib().tt_axpby(ctx.h, alpha, x.h, beta, y.h, C.byref(h)))
+    return Tensor(ctx, h)
+
+
+def tt_mean_apply(ctx, A, x) -> np.ndarray:
+    B = x.shape()["batch"]
+    out = np.zeros(2 * 6 * B)
+    ctx.check(_c.lib().tt_mean_apply(ctx.h, A.h, x.h, _dp(out)))
+    return out.view(np.complex128).reshape(B, 6)
+
+
+@dataclass
+class SolveOptions:
+    delta: float = 1e-8
+    tol: float = 1e-6
+    cap: int = 64
+    max_iter: int = 1000
+    precision: int = QTT_PREC_FP64
+    oversample: int = 16
+    exact: bool = False
+    seed: int = 0
+
+    def c(self) -> _c.SolveOpts:
+        return _c.SolveOpts(self.delta, self.tol, self.cap, self.max_iter, self.precision,
+                            self.oversample, int(self.exact), self.seed)
+
+
+@dataclass
+class SolveReport:
+    iterations: list
+    residual: list
+    max_rank: int
+    discarded: float
+    status: int
+    seconds_setup: float
+    seconds_solve: float
+
+
+def _problem(phase, lame, lame0, load_mask):
+    phase = np.ascontiguousarray(phase, dtype=np.uint8)
+    n = int(round(np.log2(phase.shape[0])))
+    if phase.shape != (1 << n,) * 3:
+        raise ValueError("phase must be a cubic array with side 2**n")
+    lame = np.ascontiguousarray(lame, dtype=np.float64)
+    p = _c.Problem(n, phase.ctypes.data_as(C.POINTER(C.c_uint8)), lame.shape[0], _dp(lame),
+                   (C.c_double * 2)(*lame0), load_mask)
+    return p, (phase, lame)
+
+
+def _report(r: _c.Report) -> SolveReport:
+    return SolveReport(list(r.iterations), list(r.residual), r.max_rank, r.discarded, r.status,
+                       r.seconds_setup, r.seconds_solve)
+
+
+def ls_solve(ctx: Context, phase, lame, lame0, opts: SolveOptions, load_mask: int = 0x3F,
+             keep_eps: bool = False):
+    """Alg. 2 for the selected unit load cases; returns (C_eff, report, eps)."""
+    p, keep = _problem(phase, lame, lame0, load_mask)
+    o = opts.c()
+    Ceff = np.zeros(36)
+    rep = _c.Report()
+    eps = C.c_void_p()
+    rc = _c.lib().ls_solve(ctx.h, C.byref(p), C.byref(o), _dp(Ceff), C.byref(rep),
+                           C.byref(eps) if keep_eps else None)
+    ctx.check(rc, allow=(QTT_ENOCONV,))
+    del keep
+    return Ceff.reshape(6, 6), _report(rep), (Tensor(ctx, eps) if keep_eps else None)
+
+
+def ls_adjoint(ctx: Context, phase, lame, lame0, opts: SolveOptions, eps: Tensor, gbar=None):
+    """Adjoint LS solve; returns the Jacobian (6, 6, 2*nphase) or the
+    gradient (2*nphase,) when the cotangent ``gbar`` (6, 6) is given."""
+    p, keep = _problem(phase, lame, lame0, 0x3F)
+    o = opts.c()
+    nt = 2 * np.asarray(lame).shape[0]
+    rep = _c.Report()
+    if gbar is None:
+        out = np.zeros(36 * nt)
+        rc = _c.lib().ls_adjoint(ctx.h, C.byref(p), C.byref(o), eps.h, None, _dp(out), C.byref(rep))
+        ctx.check(rc, allow=(QTT_ENOCONV,))
+        return out.reshape(6, 6, nt), _report(rep)
+    g = np.ascontiguousarray(gbar, dtype=np.float64).reshape(36)
+    out = np.zeros(nt)
+    rc = _c.lib().ls_adjoint(ctx.h, C.byref(p), C.byref(o), eps.h, _dp(g), _dp(out), C.byref(rep))
+    ctx.check(rc, allow=(QTT_ENOCONV,))
+    del keep
+    return out, _report(rep)
+
+
+def batch_solve(ctx: Context, problems, opts: SolveOptions):
+    """Many structures: problems = [(phase, lame, lame0)]; returns (C_eff[count], reports)."""
+    ps, keeps = [], []
+    for phase, lame, lame0 in problems:
+        p, k = _problem(phase, lame, lame0, 0x3F)
+        ps.append(p)
+        keeps.append(k)
+    arr = (_c.Problem * len(ps))(*ps)
+    reps = (_c.Report * len(ps))()
+    Ceff = np.zeros(36 * len(ps))
+    o = opts.c()
+    rc = _c.lib().qtt_batch_solve(ctx.h, len(ps), arr, C.byref(o), _dp(Ceff), reps)
+    ctx.check(rc, allow=(QTT_ENOCONV,))
+    return Ceff.reshape(-1, 6, 6), [_report(r) for r in reps]

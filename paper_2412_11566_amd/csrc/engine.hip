@@ -1,0 +1,1528 @@
+// Device tensor-train engine and C ABI of the qtthom library.
+//
+// Tensor trains live in HBM as rank-major cores (r_{k-1}, d_k, r_k); a
+// handle may hold a batch of trains with common ranks (the six unit load
+// cases of one structure).  Every product of an operator (TTO) with a
+// train is followed by TT-rounding (Sec. 3 of the paper).  The rounding of
+// a product is done without materialising it: a randomized range sketch of
+// the implicit product (Gaussian tensor-train test vectors, contracted core
+// by core right to left), a left-to-right QR sweep on the sketched
+// unfoldings that yields a left-orthogonal train of the sketch ranks, and a
+// right-to-left truncated-SVD sweep with the accuracy rule of
+// eq. rounding_condition_tt.  When the sketch rank reaches the exact
+// structural rank of every bond (QTT_EXACT, or no cap) the result is the
+// exact product up to floating-point rounding before truncation.
+#include "qtt_internal.h"
+#include "host_ops.h"
+#include "qtthom.h"
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace qtt {
+
+// ---------------------------------------------------------------------------
+// device memory pool (reuse on the context's single stream)
+// ---------------------------------------------------------------------------
+struct Pool {
+  std::multimap<size_t, void*> freel;
+  std::vector<void*> all;
+  int device = 0;
+  ~Pool() {
+    for (void* p : all) (void)hipFree(p);
+  }
+  static size_t cls(size_t bytes) {
+    size_t c = 256;
+    while (c < bytes) c <<= 1;
+    return c;
+  }
+  void* get(size_t bytes, size_t& c) {
+    c = cls(bytes);
+    auto it = freel.find(c);
+    if (it != freel.end()) {
+      void* p = it->second;
+      freel.erase(it);
+      return p;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, c) != hipSuccess) {
+      // release cached blocks and retry once
+      for (auto& kv : freel) {
+        (void)hipFree(kv.second);
+        all.erase(std::find(all.begin(), all.end(), kv.second));
+      }
+      freel.clear();
+      if (hipMalloc(&p, c) != hipSuccess) throw std::bad_alloc();
+    }
+    all.push_back(p);
+    return p;
+  }
+  void put(void* p, size_t c) { freel.emplace(c, p); }
+  // live allocations (start -> requested bytes), for host-side bounds checks
+  std::map<uintptr_t, size_t> live;
+  bool contains(const void* p, size_t bytes) const {
+    const uintptr_t a = (uintptr_t)p;
+    auto it = live.upper_bound(a);
+    if (it == live.begin()) return false;
+    --it;
+    return a >= it->first && a + bytes <= it->first + it->second;
+  }
+};
+
+struct Buf {
+  std::shared_ptr<Pool> pool;
+  void* p = nullptr;
+  size_t c = 0;
+  Buf(std::shared_ptr<Pool> pl, size_t bytes) : pool(std::move(pl)) {
+    p = pool->get(bytes, c);
+    pool->live[(uintptr_t)p] = bytes;
+  }
+  ~Buf() {
+    if (p) {
+      pool->live.erase((uintptr_t)p);
+      pool->put(p, c);
+    }
+  }
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+};
+using BufP = std::shared_ptr<Buf>;
+
+}  // namespace qtt
+
+using qtt::cplx;
+
+struct qtt_tensor {
+  int kind = 0;  // 0 train, 1 operator, 2 Green operator (factored)
+  int L = 0, B = 1;
+  std::vector<int> dout, din, r;
+  std::vector<char> diag;
+  std::vector<cplx*> core, coreR;
+  std::vector<qtt::BufP> mem;
+  // Green operator factors
+  std::shared_ptr<qtt_tensor> gU, gS, gP, gE, adj;
+  double inv_mu0 = 0.0, c = 0.0;
+  std::shared_ptr<qtt::Pool> pool;
+
+  long celems(int k) const {  // per batch element
+    if (kind == 0) return (long)r[k] * dout[k] * r[k + 1];
+    if (diag[k]) return (long)r[k] * dout[k] * r[k + 1];
+    return (long)r[k] * din[k] * dout[k] * r[k + 1];
+  }
+};
+
+struct qtt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::shared_ptr<qtt::Pool> pool;
+  uint64_t sketch_counter = 0;
+  std::map<int, std::shared_ptr<qtt_tensor>> ident;  // identity operator per n
+};
+
+namespace qtt {
+
+using TT = qtt_tensor;
+using TTP = std::shared_ptr<qtt_tensor>;
+
+static inline cplx C1() { return make_double2(1.0, 0.0); }
+static inline cplx C0() { return make_double2(0.0, 0.0); }
+static inline cplx CR(double a) { return make_double2(a, 0.0); }
+
+struct Ctx {
+  qtt_ctx* c;
+  hipStream_t s() const { return c->stream; }
+  BufP buf(size_t elems) const { return std::make_shared<Buf>(c->pool, std::max<size_t>(elems, 1) * sizeof(cplx)); }
+  BufP bufd(size_t n) const { return std::make_shared<Buf>(c->pool, std::max<size_t>(n, 1) * sizeof(double)); }
+  void sync() const { check(hipStreamSynchronize(c->stream), "stream sync"); }
+};
+
+// Host-side bounds check: the elements base[0..last] (in units of `esz`
+// bytes) must lie inside one live device allocation of this context.
+static void need(const Ctx& X, const void* base, long last, const char* what, size_t esz = sizeof(cplx)) {
+  if (last < 0) return;
+  if (!X.c->pool->contains(base, (size_t)(last + 1) * esz))
+    throw std::logic_error(std::string("device operand out of bounds: ") + what);
+}
+static long span2(long rows, long cols, long rs, long cs) {
+  return (rows - 1) * rs + (cols - 1) * cs;
+}
+static long spanb(int nb1, long s1, int nb2, long s2) { return (nb1 - 1) * s1 + (nb2 - 1) * s2; }
+
+static void G(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long lda, int opB,
+              const cplx* B, long ldb, cplx* Cm, long ldc, int nb1 = 1, long sA1 = 0,
+              long sB1 = 0, long sC1 = 0, int nb2 = 1, long sA2 = 0, long sB2 = 0,
+              long sC2 = 0, cplx alpha = make_double2(1.0, 0.0),
+              cplx beta = make_double2(0.0, 0.0)) {
+  GemmArgs g;
+  g.M = M; g.N = N; g.K = K; g.opA = opA; g.opB = opB;
+  g.A = A; g.lda = lda; g.sA1 = sA1; g.sA2 = sA2;
+  g.B = B; g.ldb = ldb; g.sB1 = sB1; g.sB2 = sB2;
+  g.C = Cm; g.ldc = ldc; g.sC1 = sC1; g.sC2 = sC2;
+  g.nb1 = nb1; g.nb2 = nb2; g.alpha = alpha; g.beta = beta;
+  if (M > 0 && N > 0 && K > 0) {
+    need(X, A, (opA == OP_N ? span2(M, K, lda, 1) : span2(K, M, lda, 1)) + spanb(nb1, sA1, nb2, sA2), "gemm A");
+    need(X, B, (opB == OP_N ? span2(K, N, ldb, 1) : span2(N, K, ldb, 1)) + spanb(nb1, sB1, nb2, sB2), "gemm B");
+    need(X, Cm, span2(M, N, ldc, 1) + spanb(nb1, sC1, nb2, sC2), "gemm C");
+  }
+  if (K == 0) throw std::logic_error("gemm with empty contraction");
+  gemm(g, X.s());
+}
+
+
+// checked launchers: every device range a kernel touches is verified on the
+// host against the live allocations before the launch
+static void ck_qr(const Ctx& X, int B, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
+                  hipStream_t s) {
+  const int k = std::min(m, n);
+  need(X, A.base, span2(m, n, A.rs, A.cs) + (B - 1) * A.sb, "qr A");
+  need(X, R.base, span2(k, n, R.rs, R.cs) + (B - 1) * R.sb, "qr R");
+  if (Q.base) need(X, Q.base, span2(m, k, Q.rs, Q.cs) + (B - 1) * Q.sb, "qr Q");
+  need(X, ws, (long)qr_ws(B, m, n) - 1, "qr ws");
+  qr(B, m, n, A, R, Q, ws, s);
+}
+static void ck_svd(const Ctx& X, int B, int m, int n, MatView A, MatOut U, double* S, MatOut V,
+                   cplx* ws, hipStream_t s) {
+  need(X, A.base, span2(m, n, A.rs, A.cs) + (B - 1) * A.sb, "svd A");
+  need(X, U.base, span2(m, n, U.rs, U.cs) + (B - 1) * U.sb, "svd U");
+  need(X, V.base, span2(n, n, V.rs, V.cs) + (B - 1) * V.sb, "svd V");
+  need(X, S, (long)B * n - 1, "svd S", sizeof(double));
+  need(X, ws, (long)svd_ws(B, m, n) - 1, "svd ws");
+  svd(B, m, n, A, U, S, V, ws, s);
+}
+static void ck_copy2d(const Ctx& X, int B, int rows, int cols, MatView in, MatOut out, cplx a,
+                      hipStream_t s) {
+  if (rows <= 0 || cols <= 0 || B <= 0) return;
+  need(X, in.base, span2(rows, cols, in.rs, in.cs) + (B - 1) * in.sb, "copy in");
+  need(X, out.base, span2(rows, cols, out.rs, out.cs) + (B - 1) * out.sb, "copy out");
+  copy2d(B, rows, cols, in, out, a, s);
+}
+static void ck_conj_transpose(const Ctx& X, int B, int rows, int keep, MatView in, MatOut out,
+                              hipStream_t s) {
+  if (rows <= 0 || keep <= 0 || B <= 0) return;
+  need(X, in.base, span2(rows, keep, in.rs, in.cs) + (B - 1) * in.sb, "ctrans in");
+  need(X, out.base, span2(keep, rows, out.rs, out.cs) + (B - 1) * out.sb, "ctrans out");
+  conj_transpose(B, rows, keep, in, out, s);
+}
+static void ck_scale_cols(const Ctx& X, int B, int rows, int cols, long ld, long sb, cplx* x,
+                          const double* S, long sS, hipStream_t s) {
+  if (rows <= 0 || cols <= 0 || B <= 0) return;
+  need(X, x, span2(rows, cols, ld, 1) + (B - 1) * sb, "scale x");
+  need(X, S, (long)(B - 1) * sS + cols - 1, "scale S", sizeof(double));
+  scale_cols(B, rows, cols, ld, sb, x, S, sS, s);
+}
+static void ck_fill(const Ctx& X, cplx* p, size_t count, cplx v, hipStream_t s) {
+  if (count == 0) return;
+  need(X, p, (long)count - 1, "fill");
+  fill(p, count, v, s);
+}
+static void ck_batch_norm(const Ctx& X, int B, long len, long stride, const cplx* x, double* out,
+                          hipStream_t s) {
+  need(X, x, (long)(B - 1) * stride + len - 1, "norm x");
+  need(X, out, B - 1, "norm out", sizeof(double));
+  batch_norm(B, len, stride, x, out, s);
+}
+static void ck_tto_core_apply(const Ctx& X, int B, int rho, int din, int dout, int rho2, int r,
+                              int r2, const cplx* A, const cplx* x, cplx* Z, hipStream_t s) {
+  const long dx = din > 0 ? din : dout;
+  need(X, A, (long)rho * (din > 0 ? din : 1) * dout * rho2 - 1, "apply A");
+  need(X, x, (long)B * r * dx * r2 - 1, "apply x");
+  need(X, Z, (long)B * rho * r * dout * rho2 * r2 - 1, "apply Z");
+  tto_core_apply(B, rho, din, dout, rho2, r, r2, A, x, Z, s);
+}
+static void ck_gaussian(const Ctx& X, cplx* out, size_t count, uint64_t seed, uint64_t stream,
+                        double scale, hipStream_t s) {
+  need(X, out, (long)count - 1, "gaussian");
+  gaussian(out, count, seed, stream, scale, s);
+}
+static void ck_sum_middle(const Ctx& X, int B, int outer, int np, int inner, const cplx* in,
+                          cplx* out, cplx w, hipStream_t s) {
+  need(X, in, (long)B * outer * np * inner - 1, "sum in");
+  need(X, out, (long)B * outer * inner - 1, "sum out");
+  sum_middle(B, outer, np, inner, in, out, w, s);
+}
+
+// allocate a train with given dims and ranks (batch B)
+static TTP new_tt(const Ctx& X, int L, int B, const std::vector<int>& dims,
+                  const std::vector<int>& ranks) {
+  auto t = std::make_shared<TT>();
+  t->kind = 0; t->L = L; t->B = B; t->dout = dims; t->din = dims; t->r = ranks;
+  t->diag.assign(L, 0);
+  t->pool = X.c->pool;
+  t->core.resize(L);
+  for (int k = 0; k < L; ++k) {
+    auto b = X.buf((size_t)B * t->celems(k));
+    t->core[k] = (cplx*)b->p;
+    t->mem.push_back(b);
+  }
+  return t;
+}
+
+static void set_core(const Ctx& X, TT& t, int k, int r0, int r1, BufP b) {
+  t.r[k] = r0;
+  t.r[k + 1] = r1;
+  t.core[k] = (cplx*)b->p;
+  t.mem.push_back(b);
+}
+
+static int sat_mul(long a, long b) {
+  const long v = a * b;
+  return v > (1L << 30) ? (1 << 30) : (int)v;
+}
+
+// ---------------------------------------------------------------------------
+// truncation sweep (right to left) of a left-orthogonal train
+// ---------------------------------------------------------------------------
+static int keep_rank(const double* s, int k, double thr, int cap) {
+  double tail = 0.0;
+  int r = k;
+  for (int i = k - 1; i >= 0; --i) {
+    if (tail + s[i] * s[i] > thr * thr) break;
+    tail += s[i] * s[i];
+    r = i;
+  }
+  if (cap > 0) r = std::min(r, cap);
+  return std::max(1, std::min(r, k));
+}
+
+struct RoundStats {
+  std::vector<double> disc2;  // per batch: sum of discarded sigma^2
+  std::vector<double> norm;   // per batch
+  double rel_max() const {
+    double m = 0.0;
+    for (size_t b = 0; b < disc2.size(); ++b)
+      if (norm[b] > 0) m = std::max(m, std::sqrt(disc2[b]) / norm[b]);
+    return m;
+  }
+};
+
+static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* st) {
+  const int L = y.L, B = y.B;
+  std::vector<double> nrm(B);
+  {
+    auto nb = X.bufd(B);
+    ck_batch_norm(X, B, y.celems(L - 1), y.celems(L - 1), y.core[L - 1], (double*)nb->p, X.s());
+    check(hipMemcpyAsync(nrm.data(), nb->p, B * sizeof(double), hipMemcpyDeviceToHost, X.s()), "norm d2h");
+    X.sync();
+  }
+  std::vector<double> thr(B), disc2(B, 0.0);
+  for (int b = 0; b < B; ++b) thr[b] = delta / std::sqrt((double)std::max(L - 1, 1)) * nrm[b];
+  for (int k = L - 1; k >= 1; --k) {
+    const int p = y.r[k], q = y.dout[k] * y.r[k + 1];
+    const int kk = std::min(p, q);
+    auto LV = X.buf((size_t)B * p * kk);
+    auto RV = X.buf((size_t)B * q * kk);
+    auto Sd = X.bufd((size_t)B * kk);
+    cplx* lv = (cplx*)LV->p;
+    cplx* rv = (cplx*)RV->p;
+    double* sd = (double*)Sd->p;
+    if (p <= q) {
+      // Jacobi on M^H (q x p): M^H = Us S Vs^H  =>  M = Vs S Us^H
+      auto ws = X.buf(svd_ws(B, q, p));
+      MatView in{y.core[k], 1, (long)q, (long)p * q, 1};
+      ck_svd(X, B, q, p, in, MatOut{rv, (long)kk, 1, (long)q * kk}, sd,
+          MatOut{lv, (long)kk, 1, (long)p * kk}, (cplx*)ws->p, X.s());
+    } else {
+      auto ws = X.buf(svd_ws(B, p, q));
+      MatView in{y.core[k], (long)q, 1, (long)p * q, 0};
+      ck_svd(X, B, p, q, in, MatOut{lv, (long)kk, 1, (long)p * kk}, sd,
+          MatOut{rv, (long)kk, 1, (long)q * kk}, (cplx*)ws->p, X.s());
+    }
+    std::vector<double> S((size_t)B * kk);
+    check(hipMemcpyAsync(S.data(), sd, S.size() * sizeof(double), hipMemcpyDeviceToHost, X.s()), "S d2h");
+    X.sync();
+    int rmax = 1;
+    std::vector<int> rb(B);
+    for (int b = 0; b < B; ++b) {
+      rb[b] = keep_rank(&S[(size_t)b * kk], kk, thr[b], cap);
+      rmax = std::max(rmax, rb[b]);
+    }
+    bool pad = false;
+    for (int b = 0; b < B; ++b) {
+      for (int j = rb[b]; j < kk; ++j) disc2[b] += S[(size_t)b * kk + j] * S[(size_t)b * kk + j];
+      for (int j = rb[b]; j < rmax; ++j) { S[(size_t)b * kk + j] = 0.0; pad = true; }
+    }
+    if (pad)
+      check(hipMemcpyAsync(sd, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, X.s()), "S h2d");
+    // new core k = RV[:, :rmax]^H  (rmax x q)
+    auto nk = X.buf((size_t)B * rmax * q);
+    ck_conj_transpose(X, B, q, rmax, MatView{rv, (long)kk, 1, (long)q * kk, 0},
+                   MatOut{(cplx*)nk->p, (long)q, 1, (long)rmax * q}, X.s());
+    // LV[:, :rmax] * S
+    ck_scale_cols(X, B, p, rmax, kk, (long)p * kk, lv, sd, kk, X.s());
+    const int rows = y.r[k - 1] * y.dout[k - 1];
+    auto nk1 = X.buf((size_t)B * rows * rmax);
+    G(X, rows, rmax, p, OP_N, y.core[k - 1], p, OP_N, lv, kk, (cplx*)nk1->p, rmax, B,
+      (long)rows * p, (long)p * kk, (long)rows * rmax);
+    if (pad) X.sync();  // S host buffer reused only after the kernels consumed it
+    set_core(X, y, k, rmax, y.r[k + 1], nk);
+    set_core(X, y, k - 1, y.r[k - 1], rmax, nk1);
+  }
+  if (st) {
+    st->disc2 = disc2;
+    st->norm = nrm;
+  }
+}
+
+// truncation sweep (left to right) of a right-orthogonal train whose norm
+// sits in core 0
+static void truncate_lr(const Ctx& X, TT& y, double delta, int cap, RoundStats* st) {
+  const int L = y.L, B = y.B;
+  std::vector<double> nrm(B);
+  {
+    auto nb = X.bufd(B);
+    ck_batch_norm(X, B, y.celems(0), y.celems(0), y.core[0], (double*)nb->p, X.s());
+    check(hipMemcpyAsync(nrm.data(), nb->p, B * sizeof(double), hipMemcpyDeviceToHost, X.s()), "norm d2h");
+    X.sync();
+  }
+  std::vector<double> thr(B), disc2(B, 0.0);
+  for (int b = 0; b < B; ++b) thr[b] = delta / std::sqrt((double)std::max(L - 1, 1)) * nrm[b];
+  for (int k = 0; k < L - 1; ++k) {
+    const int p = y.r[k] * y.dout[k], q = y.r[k + 1];
+    const int kk = std::min(p, q);
+    auto LV = X.buf((size_t)B * p * kk);
+    auto RV = X.buf((size_t)B * q * kk);
+    auto Sd = X.bufd((size_t)B * kk);
+    cplx* lv = (cplx*)LV->p;
+    cplx* rv = (cplx*)RV->p;
+    double* sd = (double*)Sd->p;
+    if (p >= q) {
+      auto ws = X.buf(svd_ws(B, p, q));
+      MatView in{y.core[k], (long)q, 1, (long)p * q, 0};
+      ck_svd(X, B, p, q, in, MatOut{lv, (long)kk, 1, (long)p * kk}, sd,
+             MatOut{rv, (long)kk, 1, (long)q * kk}, (cplx*)ws->p, X.s());
+    } else {
+      auto ws = X.buf(svd_ws(B, q, p));
+      MatView in{y.core[k], 1, (long)q, (long)p * q, 1};
+      ck_svd(X, B, q, p, in, MatOut{rv, (long)kk, 1, (long)q * kk}, sd,
+             MatOut{lv, (long)kk, 1, (long)p * kk}, (cplx*)ws->p, X.s());
+    }
+    std::vector<double> S((size_t)B * kk);
+    check(hipMemcpyAsync(S.data(), sd, S.size() * sizeof(double), hipMemcpyDeviceToHost, X.s()), "S d2h");
+    X.sync();
+    int rmax = 1;
+    std::vector<int> rb(B);
+    for (int b = 0; b < B; ++b) {
+      rb[b] = keep_rank(&S[(size_t)b * kk], kk, thr[b], cap);
+      rmax = std::max(rmax, rb[b]);
+    }
+    bool pad = false;
+    for (int b = 0; b < B; ++b) {
+      for (int j = rb[b]; j < kk; ++j) disc2[b] += S[(size_t)b * kk + j] * S[(size_t)b * kk + j];
+      for (int j = rb[b]; j < rmax; ++j) { S[(size_t)b * kk + j] = 0.0; pad = true; }
+    }
+    if (pad)
+      check(hipMemcpyAsync(sd, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, X.s()), "S h2d");
+    // new core k = LV[:, :rmax]  (p x rmax)
+    auto nk = X.buf((size_t)B * p * rmax);
+    ck_copy2d(X, B, p, rmax, MatView{lv, (long)kk, 1, (long)p * kk, 0},
+              MatOut{(cplx*)nk->p, (long)rmax, 1, (long)p * rmax}, C1(), X.s());
+    // next core = (RV[:, :rmax] S)^H * core_{k+1}
+    ck_scale_cols(X, B, q, rmax, kk, (long)q * kk, rv, sd, kk, X.s());
+    const int cols = y.dout[k + 1] * y.r[k + 2];
+    auto nk1 = X.buf((size_t)B * rmax * cols);
+    G(X, rmax, cols, q, OP_C, rv, kk, OP_N, y.core[k + 1], cols, (cplx*)nk1->p, cols, B,
+      (long)q * kk, (long)q * cols, (long)rmax * cols);
+    if (pad) X.sync();
+    set_core(X, y, k, y.r[k], rmax, nk);
+    set_core(X, y, k + 1, rmax, y.r[k + 2], nk1);
+  }
+  if (st) {
+    st->disc2 = disc2;
+    st->norm = nrm;
+  }
+}
+
+// explicit rounding: left-to-right QR sweep, then truncation sweep
+static void round_tt(const Ctx& X, TT& x, double delta, int cap, RoundStats* st) {
+  const int L = x.L, B = x.B;
+  for (int k = 0; k < L - 1; ++k) {
+    const int m = x.r[k] * x.dout[k], n = x.r[k + 1];
+    const int kq = std::min(m, n);
+    auto Q = X.buf((size_t)B * m * kq);
+    auto R = X.buf((size_t)B * kq * n);
+    auto ws = X.buf(qr_ws(B, m, n));
+    ck_qr(X, B, m, n, MatView{x.core[k], (long)n, 1, (long)m * n, 0},
+       MatOut{(cplx*)R->p, (long)n, 1, (long)kq * n}, MatOut{(cplx*)Q->p, (long)kq, 1, (long)m * kq},
+       (cplx*)ws->p, X.s());
+    const int cols = x.dout[k + 1] * x.r[k + 2];
+    auto nx = X.buf((size_t)B * kq * cols);
+    G(X, kq, cols, n, OP_N, (cplx*)R->p, n, OP_N, x.core[k + 1], cols, (cplx*)nx->p, cols, B,
+      (long)kq * n, (long)n * cols, (long)kq * cols);
+    set_core(X, x, k, x.r[k], kq, Q);
+    set_core(X, x, k + 1, kq, x.r[k + 2], nx);
+  }
+  truncate_rl(X, x, delta, cap, st);
+}
+
+// Frobenius norms via a left-to-right QR sweep that keeps only R factors.
+static std::vector<double> tt_norms(const Ctx& X, const TT& x) {
+  const int L = x.L, B = x.B;
+  BufP cur;  // current (R * core_k)
+  const cplx* curp = x.core[0];
+  int rows = x.r[0] * x.dout[0];
+  for (int k = 0; k < L - 1; ++k) {
+    const int m = rows, n = x.r[k + 1];
+    const int kq = std::min(m, n);
+    auto R = X.buf((size_t)B * kq * n);
+    auto ws = X.buf(qr_ws(B, m, n));
+    ck_qr(X, B, m, n, MatView{curp, (long)n, 1, (long)m * n, 0},
+       MatOut{(cplx*)R->p, (long)n, 1, (long)kq * n}, MatOut{nullptr, 0, 0, 0}, (cplx*)ws->p, X.s());
+    const int cols = x.dout[k + 1] * x.r[k + 2];
+    auto nx = X.buf((size_t)B * kq * cols);
+    G(X, kq, cols, n, OP_N, (cplx*)R->p, n, OP_N, x.core[k + 1], cols, (cplx*)nx->p, cols, B,
+      (long)kq * n, (long)n * cols, (long)kq * cols);
+    cur = nx;
+    curp = (cplx*)nx->p;
+    rows = kq * x.dout[k + 1];
+  }
+  const long len = (long)rows * x.r[L];
+  auto nb = X.bufd(B);
+  ck_batch_norm(X, B, len, len, curp, (double*)nb->p, X.s());
+  std::vector<double> out(B);
+  check(hipMemcpyAsync(out.data(), nb->p, B * sizeof(double), hipMemcpyDeviceToHost, X.s()), "norm d2h");
+  X.sync();
+  return out;
+}
+
+// z = alpha x + beta y (block cores)
+static TTP axpby(const Ctx& X, double alpha, const TT& x, double beta, const TT& y) {
+  if (x.L != y.L || x.B != y.B) throw std::invalid_argument("axpby: shape mismatch");
+  const int L = x.L, B = x.B;
+  std::vector<int> rz(L + 1);
+  rz[0] = 1; rz[L] = 1;
+  for (int k = 1; k < L; ++k) rz[k] = x.r[k] + y.r[k];
+  auto z = new_tt(X, L, B, x.dout, rz);
+  for (int k = 0; k < L; ++k) {
+    const int d = x.dout[k];
+    const int R0 = rz[k], R1 = rz[k + 1];
+    ck_fill(X, z->core[k], (size_t)B * R0 * d * R1, C0(), X.s());
+    const int xr0 = x.r[k], xr1 = x.r[k + 1], yr0 = y.r[k], yr1 = y.r[k + 1];
+    const long zsb = (long)R0 * d * R1;
+    // x block at (0, 0)
+    ck_copy2d(X, B, xr0 * d, xr1, MatView{x.core[k], (long)xr1, 1, (long)xr0 * d * xr1, 0},
+           MatOut{z->core[k], (long)R1, 1, zsb}, CR(k == 0 ? alpha : 1.0), X.s());
+    // y block at row offset (k>0 ? xr0*d : 0), col offset (k<L-1 ? xr1 : 0)
+    const long roff = (k > 0) ? (long)xr0 * d : 0;
+    const long coff = (k < L - 1) ? xr1 : 0;
+    if (k == 0 || k == L - 1) {
+      // first core: concatenate columns; last core: stack rows
+      ck_copy2d(X, B, yr0 * d, yr1, MatView{y.core[k], (long)yr1, 1, (long)yr0 * d * yr1, 0},
+             MatOut{z->core[k] + roff * R1 + coff, (long)R1, 1, zsb}, CR(k == 0 ? beta : 1.0), X.s());
+      if (k == 0 && L == 1) throw std::invalid_argument("axpby: L == 1");
+    } else {
+      ck_copy2d(X, B, yr0 * d, yr1, MatView{y.core[k], (long)yr1, 1, (long)yr0 * d * yr1, 0},
+             MatOut{z->core[k] + roff * R1 + coff, (long)R1, 1, zsb}, CR(1.0), X.s());
+    }
+  }
+  // the first core: x and y blocks share the single row; the copies above
+  // placed y at column offset xr1 with row offset 0 (k = 0), correct.
+  // The last core: y rows follow x rows at column 0, correct.
+  return z;
+}
+
+// ---------------------------------------------------------------------------
+// operator application
+// ---------------------------------------------------------------------------
+struct SketchOpts {
+  double delta = 1e-10;
+  int cap = 0;
+  int oversample = 16;
+  bool exact = false;
+  uint64_t seed = 0;
+};
+
+// Contract Mc (B, lt, rho, r) with x_k -> T1 (B, lt, rho, din, r2), then with
+// the operator core -> P (B, lt, dout, rho2, r2).
+static BufP left_step(const Ctx& X, const TT& A, const TT& x, int k, const cplx* Mc, int lt) {
+  const int B = x.B;
+  const int rho = A.r[k], rho2 = A.r[k + 1], r = x.r[k], r2 = x.r[k + 1];
+  const int din = x.dout[k], dout = A.dout[k];
+  auto T1 = X.buf((size_t)B * lt * rho * din * r2);
+  G(X, lt * rho, din * r2, r, OP_N, Mc, r, OP_N, x.core[k], (long)din * r2, (cplx*)T1->p,
+    (long)din * r2, B, (long)lt * rho * r, (long)r * din * r2, (long)lt * rho * din * r2);
+  auto P = X.buf((size_t)B * lt * dout * rho2 * r2);
+  if (!A.diag[k]) {
+    G(X, dout * rho2, r2, rho * din, OP_T, A.core[k], (long)dout * rho2, OP_N, (cplx*)T1->p, r2,
+      (cplx*)P->p, r2, B * lt, 0, (long)rho * din * r2, (long)dout * rho2 * r2);
+  } else {
+    const int d = dout;
+    G(X, rho2, r2, rho, OP_T, A.core[k], (long)d * rho2, OP_N, (cplx*)T1->p, (long)d * r2,
+      (cplx*)P->p, r2, B * lt, 0, (long)rho * d * r2, (long)d * rho2 * r2, d, rho2, r2,
+      (long)rho2 * r2);
+  }
+  return P;
+}
+
+static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts& o,
+                        RoundStats* st) {
+  const int L = x.L, B = x.B;
+  if (A.L != L) throw std::invalid_argument("operator and train differ in length");
+  for (int k = 0; k < L; ++k)
+    if (A.din[k] != x.dout[k]) throw std::invalid_argument("operator input dim mismatch");
+  // sketch ranks
+  std::vector<int> ell(L + 1, 1);
+  std::vector<long> left(L + 1, 1), right(L + 1, 1);
+  for (int k = 1; k <= L; ++k) left[k] = std::min<long>(left[k - 1] * A.dout[k - 1], 1L << 30);
+  for (int k = L - 1; k >= 0; --k) right[k] = std::min<long>(right[k + 1] * A.dout[k], 1L << 30);
+  // Exact mode uses deterministic test matrices: the full right unfolding
+  // of the product at the bonds nearest the right end whose right dimension
+  // does not exceed the product rank ("dense"), and the identity (no
+  // sketch: the left-to-right sweep then QR-factors the product unfolding
+  // itself) at every bond further left.
+  std::vector<char> dense_w(L + 1, 0), ident_w(L + 1, 0);
+  if (o.exact || o.cap <= 0) {
+    bool run = true;
+    for (int k = L - 1; k >= 1; --k) {
+      const long pr = (long)sat_mul(A.r[k], x.r[k]);
+      if (run && right[k] <= pr) {
+        dense_w[k] = 1;
+        ell[k] = (int)right[k];
+      } else {
+        run = false;
+        ident_w[k] = 1;
+        ell[k] = (int)pr;
+      }
+    }
+  } else {
+    for (int k = 1; k < L; ++k) {
+      long e = std::min<long>((long)sat_mul(A.r[k], x.r[k]), std::min(left[k], right[k]));
+      e = std::min<long>(e, (long)o.cap + o.oversample);
+      ell[k] = (int)std::max<long>(1, e);
+    }
+  }
+  // random test train Omega_k (ell_k, dout_k, ell_{k+1}), k = 1..L-1
+  std::vector<BufP> Om(L);
+  for (int k = 1; k < L; ++k) {
+    if (dense_w[k] || ident_w[k]) continue;
+    const size_t cnt = (size_t)ell[k] * A.dout[k] * ell[k + 1];
+    Om[k] = X.buf(cnt);
+    ck_gaussian(X, (cplx*)Om[k]->p, cnt, o.seed, (uint64_t)k, 1.0 / std::sqrt((double)A.dout[k] * ell[k + 1]), X.s());
+  }
+  // right-to-left partial sketches W_k (B, rho_k, r_k, ell_k)
+  std::vector<BufP> W(L + 1);
+  W[L] = X.buf(B);
+  ck_fill(X, (cplx*)W[L]->p, B, C1(), X.s());
+  for (int k = L - 1; k >= 1; --k) {
+    if (ident_w[k]) break;  // every bond further left is an identity bond
+    const int rho = A.r[k], rho2 = A.r[k + 1], r = x.r[k], r2 = x.r[k + 1];
+    const int din = x.dout[k], dout = A.dout[k];
+    const int l2 = ell[k + 1], l = ell[k];
+    const cplx* W2 = (cplx*)W[k + 1]->p;
+    auto X1 = X.buf((size_t)B * r * din * rho2 * l2);
+    G(X, r * din, l2, r2, OP_N, x.core[k], r2, OP_N, W2, l2, (cplx*)X1->p, (long)rho2 * l2, B,
+      (long)r * din * r2, (long)rho2 * r2 * l2, (long)r * din * rho2 * l2, rho2, 0,
+      (long)r2 * l2, l2);
+    auto X2 = X.buf((size_t)B * r * rho * dout * l2);
+    if (!A.diag[k]) {
+      G(X, rho * dout, l2, din * rho2, OP_N, A.coreR[k], (long)din * rho2, OP_N, (cplx*)X1->p, l2,
+        (cplx*)X2->p, l2, B * r, 0, (long)din * rho2 * l2, (long)rho * dout * l2);
+    } else {
+      const int d = dout;
+      G(X, rho, l2, rho2, OP_N, A.core[k], (long)d * rho2, OP_N, (cplx*)X1->p, l2, (cplx*)X2->p,
+        (long)d * l2, B * r, 0, (long)d * rho2 * l2, (long)rho * d * l2, d, rho2,
+        (long)rho2 * l2, l2);
+    }
+    W[k] = X.buf((size_t)B * rho * r * l);
+    if (dense_w[k]) {
+      // W_k[b][a][c][(i t)] = X2[b][c][a][(i t)]  (l = dout * l2)
+      const long m = (long)dout * l2;
+      for (int b = 0; b < B; ++b)
+        ck_copy2d(X, r, rho, (int)m, MatView{(cplx*)X2->p + (long)b * r * rho * m, m, 1, rho * m, 0},
+                  MatOut{(cplx*)W[k]->p + (long)b * rho * r * m, (long)r * m, 1, m}, C1(), X.s());
+    } else {
+      G(X, rho, l, dout * l2, OP_N, (cplx*)X2->p, (long)dout * l2, OP_T, (cplx*)Om[k]->p,
+        (long)dout * l2, (cplx*)W[k]->p, (long)r * l, B, (long)r * rho * dout * l2, 0,
+        (long)rho * r * l, r, (long)rho * dout * l2, 0, l);
+    }
+  }
+  // left-to-right: QR of sketched unfoldings
+  std::vector<int> ry(L + 1, 1);
+  auto y = std::make_shared<TT>();
+  y->kind = 0; y->L = L; y->B = B; y->dout = A.dout; y->din = A.dout; y->r = ry;
+  y->diag.assign(L, 0); y->core.resize(L); y->pool = X.c->pool;
+  auto Mc = X.buf(B);
+  ck_fill(X, (cplx*)Mc->p, B, C1(), X.s());
+  int lt = 1;
+  for (int k = 0; k < L; ++k) {
+    const int rho2 = A.r[k + 1], r2 = x.r[k + 1], dout = A.dout[k];
+    auto P = left_step(X, A, x, k, (cplx*)Mc->p, lt);
+    if (k == L - 1) {
+      set_core(X, *y, k, lt, 1, P);
+      break;
+    }
+    const int l2 = ell[k + 1];
+    const int m = lt * dout, kq = std::min(m, l2);
+    BufP Y;
+    if (ident_w[k + 1]) {
+      Y = P;  // l2 == rho2 * r2: factor the product unfolding itself
+    } else {
+      Y = X.buf((size_t)B * m * l2);
+      G(X, m, l2, rho2 * r2, OP_N, (cplx*)P->p, (long)rho2 * r2, OP_N, (cplx*)W[k + 1]->p, l2,
+        (cplx*)Y->p, l2, B, (long)m * rho2 * r2, (long)rho2 * r2 * l2, (long)m * l2);
+    }
+    auto Q = X.buf((size_t)B * m * kq);
+    auto R = X.buf((size_t)B * kq * l2);
+    auto ws = X.buf(qr_ws(B, m, l2));
+    ck_qr(X, B, m, l2, MatView{(cplx*)Y->p, (long)l2, 1, (long)m * l2, 0},
+       MatOut{(cplx*)R->p, (long)l2, 1, (long)kq * l2}, MatOut{(cplx*)Q->p, (long)kq, 1, (long)m * kq},
+       (cplx*)ws->p, X.s());
+    auto Mn = X.buf((size_t)B * kq * rho2 * r2);
+    G(X, kq, rho2 * r2, m, OP_C, (cplx*)Q->p, kq, OP_N, (cplx*)P->p, (long)rho2 * r2, (cplx*)Mn->p,
+      (long)rho2 * r2, B, (long)m * kq, (long)m * rho2 * r2, (long)kq * rho2 * r2);
+    set_core(X, *y, k, lt, kq, Q);
+    Mc = Mn;
+    lt = kq;
+  }
+  truncate_rl(X, *y, o.delta, o.cap, st);
+  return y;
+}
+
+// Materialised product (ranks multiply).
+static TTP apply_full(const Ctx& X, const TT& A, const TT& x) {
+  const int L = x.L, B = x.B;
+  std::vector<int> rz(L + 1);
+  for (int k = 0; k <= L; ++k) rz[k] = A.r[k] * x.r[k];
+  auto z = new_tt(X, L, B, A.dout, rz);
+  for (int k = 0; k < L; ++k)
+    ck_tto_core_apply(X, B, A.r[k], A.diag[k] ? 0 : A.din[k], A.dout[k], A.r[k + 1], x.r[k], x.r[k + 1],
+                   A.core[k], x.core[k], z->core[k], X.s());
+  return z;
+}
+
+static TTP op_apply(const Ctx& X, const TT& A, const TT& x, int flags, const SketchOpts& o,
+                    RoundStats* st);
+
+// Green step of Alg. 2 in bounded factors (see qtt_green_build):
+// u = U x, s = Sd u, p = P s, q = u/(2 mu0) - (c/2) p, eps = E q.
+static TTP green_chain(const Ctx& X, const TT& G, const TT& x, int flags, const SketchOpts& o,
+                       RoundStats* st) {
+  SketchOpts o2 = o;
+  RoundStats s1;
+  double disc = 0.0;
+  o2.seed = o.seed * 7 + 1;
+  auto u = op_apply(X, *G.gU, x, flags, o2, &s1);
+  disc = std::max(disc, s1.rel_max());
+  o2.seed = o.seed * 7 + 2;
+  auto s = op_apply(X, *G.gS, *u, flags, o2, &s1);
+  disc = std::max(disc, s1.rel_max());
+  o2.seed = o.seed * 7 + 3;
+  auto p = op_apply(X, *G.gP, *s, flags, o2, &s1);
+  disc = std::max(disc, s1.rel_max());
+  auto q = axpby(X, G.inv_mu0, *u, -G.c, *p);
+  if (!(flags & QTT_NO_ROUND)) {
+    round_tt(X, *q, o.delta, o.cap, &s1);
+    disc = std::max(disc, s1.rel_max());
+  }
+  o2.seed = o.seed * 7 + 4;
+  auto e = op_apply(X, *G.gE, *q, flags, o2, st);
+  if (st) {
+    // fold the intermediate roundings into the reported maximum
+    for (size_t b = 0; b < st->disc2.size(); ++b)
+      st->disc2[b] = std::max(st->disc2[b], disc * disc * st->norm[b] * st->norm[b]);
+  }
+  return e;
+}
+
+static TTP op_apply(const Ctx& X, const TT& A, const TT& x, int flags, const SketchOpts& o,
+                    RoundStats* st) {
+  if (A.kind == 2) return green_chain(X, A, x, flags, o, st);
+  if (A.kind != 1) throw std::invalid_argument("not an operator");
+  if (flags & QTT_NO_ROUND) return apply_full(X, A, x);
+  SketchOpts o2 = o;
+  if (flags & QTT_EXACT) o2.exact = true;
+  return sketch_apply(X, A, x, o2, st);
+}
+
+// Volume average of A(x) : x -> host (B x 6) complex; A's core 0 is 6x6.
+static std::vector<std::complex<double>> mean_apply(const Ctx& X, const TT& A, const TT& x) {
+  const int L = x.L, B = x.B;
+  if (A.dout[0] != 6 || A.kind != 1) throw std::invalid_argument("mean_apply: needs a Voigt operator");
+  auto one = X.buf(B);
+  ck_fill(X, (cplx*)one->p, B, C1(), X.s());
+  // core 0: P (B, 1, 6, rho1, r1) -> Mc (B, 6, rho1, r1)
+  BufP Mc = left_step(X, A, x, 0, (cplx*)one->p, 1);
+  const int lt = 6;
+  for (int k = 1; k < L; ++k) {
+    // treat the Voigt output index as the sketch index (lt = 6)
+    const int rho2 = A.r[k + 1], r2 = x.r[k + 1], d = A.dout[k];
+    auto P = left_step(X, A, x, k, (cplx*)Mc->p, lt);
+    auto Mn = X.buf((size_t)B * lt * rho2 * r2);
+    ck_sum_middle(X, B, lt, d, rho2 * r2, (cplx*)P->p, (cplx*)Mn->p, CR(1.0 / d), X.s());
+    Mc = Mn;
+  }
+  std::vector<std::complex<double>> out((size_t)B * 6);
+  check(hipMemcpyAsync(out.data(), Mc->p, out.size() * sizeof(cplx), hipMemcpyDeviceToHost, X.s()), "mean d2h");
+  X.sync();
+  return out;
+}
+
+// Gram matrix of inner products <x_a, y_b> = sum conj(x_a) y_b -> host (Bx x By)
+static std::vector<std::complex<double>> tt_gram(const Ctx& X, const TT& x, const TT& y) {
+  const int L = x.L, Bx = x.B, By = y.B;
+  auto Mc = X.buf((size_t)Bx * By);
+  ck_fill(X, (cplx*)Mc->p, (size_t)Bx * By, C1(), X.s());
+  for (int k = 0; k < L; ++k) {
+    const int rx = x.r[k], rx2 = x.r[k + 1], ry = y.r[k], ry2 = y.r[k + 1], d = x.dout[k];
+    auto T = X.buf((size_t)Bx * By * rx * d * ry2);
+    G(X, rx, d * ry2, ry, OP_N, (cplx*)Mc->p, ry, OP_N, y.core[k], (long)d * ry2, (cplx*)T->p,
+      (long)d * ry2, Bx, (long)By * rx * ry, 0, (long)By * rx * d * ry2, By, (long)rx * ry,
+      (long)ry * d * ry2, (long)rx * d * ry2);
+    auto Mn = X.buf((size_t)Bx * By * rx2 * ry2);
+    G(X, rx2, ry2, rx * d, OP_C, x.core[k], rx2, OP_N, (cplx*)T->p, ry2, (cplx*)Mn->p, ry2, Bx,
+      (long)rx * d * rx2, (long)By * rx * d * ry2, (long)By * rx2 * ry2, By, 0,
+      (long)rx * d * ry2, (long)rx2 * ry2);
+    Mc = Mn;
+  }
+  std::vector<std::complex<double>> out((size_t)Bx * By);
+  check(hipMemcpyAsync(out.data(), Mc->p, out.size() * sizeof(cplx), hipMemcpyDeviceToHost, X.s()), "gram d2h");
+  X.sync();
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// operator upload
+// ---------------------------------------------------------------------------
+static TTP upload_op(const Ctx& X, const host::HTT& h) {
+  auto t = std::make_shared<TT>();
+  const int L = (int)h.size();
+  t->kind = 1; t->L = L; t->B = 1; t->pool = X.c->pool;
+  t->dout.resize(L); t->din.resize(L); t->diag.resize(L); t->r.resize(L + 1);
+  t->core.resize(L); t->coreR.assign(L, nullptr);
+  for (int k = 0; k < L; ++k) {
+    const host::HCore& c = h[k];
+    t->r[k] = c.r0; t->r[k + 1] = c.r1; t->dout[k] = c.dout;
+    t->diag[k] = (c.din == 0);
+    t->din[k] = c.din == 0 ? c.dout : c.din;
+    if (t->diag[k]) {
+      auto b = X.buf(c.v.size());
+      check(hipMemcpyAsync(b->p, c.v.data(), c.v.size() * sizeof(cplx), hipMemcpyHostToDevice, X.s()), "op h2d");
+      t->core[k] = (cplx*)b->p;
+      t->mem.push_back(b);
+    } else {
+      // host layout (r0, dout, din, r1) == layout R; build layout L (r0, din, dout, r1)
+      std::vector<std::complex<double>> Lv(c.v.size());
+      for (int a = 0; a < c.r0; ++a)
+        for (int o = 0; o < c.dout; ++o)
+          for (int i = 0; i < c.din; ++i)
+            for (int b2 = 0; b2 < c.r1; ++b2)
+              Lv[(((size_t)a * c.din + i) * c.dout + o) * c.r1 + b2] =
+                  c.v[(((size_t)a * c.dout + o) * c.din + i) * c.r1 + b2];
+      auto bl = X.buf(c.v.size());
+      auto br = X.buf(c.v.size());
+      check(hipMemcpyAsync(bl->p, Lv.data(), Lv.size() * sizeof(cplx), hipMemcpyHostToDevice, X.s()), "op h2d");
+      check(hipMemcpyAsync(br->p, c.v.data(), c.v.size() * sizeof(cplx), hipMemcpyHostToDevice, X.s()), "op h2d");
+      t->core[k] = (cplx*)bl->p;
+      t->coreR[k] = (cplx*)br->p;
+      t->mem.push_back(bl);
+      t->mem.push_back(br);
+    }
+  }
+  X.sync();
+  return t;
+}
+
+static host::HTT adjoint_host(const host::HTT& h) {
+  host::HTT out = h;
+  for (auto& c : out) {
+    if (c.din == 0) {
+      for (auto& v : c.v) v = std::conj(v);
+      continue;
+    }
+    for (int a = 0; a < c.r0; ++a)
+      for (int o = 0; o < c.dout; ++o)
+        for (int i = 0; i < c.din; ++i)
+          for (int b = 0; b < c.r1; ++b)
+            c.v[(((size_t)a * c.din + i) * c.dout + o) * c.r1 + b] =
+                std::conj(h[&c - &out[0]].v[(((size_t)a * c.dout + o) * c.din + i) * c.r1 + b]);
+    std::swap(c.dout, c.din);
+  }
+  return out;
+}
+
+static TTP sfft_op(const Ctx& X, int n, double delta) {
+  host::HTT q = host::qn_tto(n, delta);
+  host::HTT S;
+  host::HCore id;
+  id.r0 = 1; id.dout = 6; id.din = 6; id.r1 = 1;
+  id.v.assign(36, 0.0);
+  for (int i = 0; i < 6; ++i) id.v[i * 6 + i] = 1.0;
+  S.push_back(id);
+  for (int a = 0; a < 3; ++a)
+    for (auto& c : q) S.push_back(c);
+  auto t = upload_op(X, S);
+  t->adj = upload_op(X, adjoint_host(S));
+  return t;
+}
+
+static TTP green_op(const Ctx& X, int n, double lam0, double mu0, double delta) {
+  host::GreenFactors gf = host::green_factors(n, lam0, mu0, delta);
+  auto t = std::make_shared<TT>();
+  t->kind = 2; t->L = 3 * n + 1; t->B = 1; t->pool = X.c->pool;
+  t->gU = upload_op(X, gf.U);
+  t->gS = upload_op(X, gf.Sd);
+  t->gP = upload_op(X, gf.P);
+  t->gE = upload_op(X, gf.E);
+  t->inv_mu0 = gf.inv_2mu0;
+  t->c = gf.half_c;
+  t->dout = t->gE->dout; t->din = t->gU->din; t->diag = t->gU->diag;
+  t->r = t->gU->r;
+  return t;
+}
+
+static TTP identity_op(const Ctx& X, int n) {
+  auto it = X.c->ident.find(n);
+  if (it != X.c->ident.end()) return it->second;
+  host::HTT h;
+  host::HCore id;
+  id.r0 = 1; id.dout = 6; id.din = 6; id.r1 = 1;
+  id.v.assign(36, 0.0);
+  for (int i = 0; i < 6; ++i) id.v[i * 6 + i] = 1.0;
+  h.push_back(id);
+  for (int k = 0; k < 3 * n; ++k) {
+    host::HCore c;
+    c.r0 = 1; c.dout = 2; c.din = 0; c.r1 = 1;
+    c.v.assign(2, 1.0);
+    h.push_back(c);
+  }
+  auto t = upload_op(X, h);
+  X.c->ident[n] = t;
+  return t;
+}
+
+static TTP const_strain(const Ctx& X, int n, int B, const double* E) {
+  const int L = 3 * n + 1;
+  std::vector<int> dims(L, 2), rk(L + 1, 1);
+  dims[0] = 6;
+  auto t = new_tt(X, L, B, dims, rk);
+  std::vector<std::complex<double>> e((size_t)B * 6);
+  for (int i = 0; i < B * 6; ++i) e[i] = E[i];
+  check(hipMemcpyAsync(t->core[0], e.data(), e.size() * sizeof(cplx), hipMemcpyHostToDevice, X.s()), "E h2d");
+  for (int k = 1; k < L; ++k) ck_fill(X, t->core[k], (size_t)B * 2, C1(), X.s());
+  X.sync();
+  return t;
+}
+
+// d(C)/d(theta) as raised operator from the one-hot train: Voigt core
+// D[I][J] * chi_0[p][alpha], spatial cores of chi.
+static TTP dC_op(const Ctx& X, const host::HTT& chi, int p, const double D[36]) {
+  host::HTT h;
+  host::HCore c0;
+  const int r1 = chi[0].r1;
+  c0.r0 = 1; c0.dout = 6; c0.din = 6; c0.r1 = r1;
+  c0.v.assign(36 * (size_t)r1, 0.0);
+  for (int I = 0; I < 36; ++I)
+    for (int a = 0; a < r1; ++a) c0.v[(size_t)I * r1 + a] = D[I] * chi[0].v[(size_t)p * r1 + a];
+  h.push_back(c0);
+  for (size_t k = 1; k < chi.size(); ++k) h.push_back(chi[k]);
+  return upload_op(X, h);
+}
+
+static bool verbose() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("QTTHOM_VERBOSE");
+    v = (e && *e && *e != '0') ? 1 : 0;
+  }
+  return v == 1;
+}
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ---------------------------------------------------------------------------
+// Lippmann-Schwinger solver (Alg. 2)
+// ---------------------------------------------------------------------------
+struct Ops {
+  TTP S, G, Cd, I;
+  host::HTT chi;
+  double lam0 = 0, mu0 = 0;
+};
+
+static Ops build_ops(const Ctx& X, const qtt_problem* P, double delta) {
+  Ops o;
+  const int n = P->n;
+  o.S = sfft_op(X, n, delta);
+  o.G = green_op(X, n, P->lame0[0], P->lame0[1], delta);
+  host::HTT cd = host::stiffness_tto(P->phase, n, P->nphase, P->lame, P->lame0, delta, 0, &o.chi, nullptr);
+  o.Cd = upload_op(X, cd);
+  o.I = identity_op(X, n);
+  o.lam0 = P->lame0[0];
+  o.mu0 = P->lame0[1];
+  return o;
+}
+
+static void check_problem(const qtt_problem* P, const qtt_solve_opts* O) {
+  if (!P || !O) throw std::invalid_argument("null problem or options");
+  if (P->n < 1 || P->n > 10) throw std::invalid_argument("n out of range (1..10)");
+  if (P->nphase < 1 || P->nphase > 16) throw std::invalid_argument("nphase out of range");
+  if (!P->phase || !P->lame) throw std::invalid_argument("null phase or lame");
+  if (!(O->delta > 0.0) || !(O->tol >= 0.0) || O->max_iter < 0)
+    throw std::invalid_argument("bad solve options");
+}
+
+struct SolveOut {
+  TTP eps;
+  std::vector<int> ks;
+  std::vector<int> iters;
+  std::vector<double> res;
+  int max_rank = 1;
+  double disc = 0.0;
+  bool converged = true;
+};
+
+static SketchOpts sk(const Ctx& X, const qtt_solve_opts* O) {
+  SketchOpts s;
+  s.delta = O->delta;
+  s.cap = O->cap;
+  s.oversample = std::max(0, O->oversample);
+  s.exact = O->exact != 0;
+  s.seed = O->seed * 1000003ULL + (X.c->sketch_counter++);
+  return s;
+}
+
+static SolveOut ls_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, const qtt_solve_opts* O,
+                        const std::vector<int>& ks) {
+  SolveOut out;
+  const int n = P->n, B = (int)ks.size();
+  out.ks = ks;
+  std::vector<double> E((size_t)B * 6, 0.0);
+  for (int b = 0; b < B; ++b) E[(size_t)b * 6 + ks[b]] = 1.0;
+  auto Et = const_strain(X, n, B, E.data());
+  auto eps = Et;
+  const double normE = std::pow(2.0, 1.5 * n);
+  out.iters.assign(B, 0);
+  out.res.assign(B, INFINITY);
+  std::vector<char> done(B, 0);
+  int m = 0;
+  while (true) {
+    RoundStats st;
+    auto tau = op_apply(X, *ops.Cd, *eps, 0, sk(X, O), &st);
+    out.disc = std::max(out.disc, st.rel_max());
+    auto th = op_apply(X, *ops.S, *tau, 0, sk(X, O), &st);
+    out.disc = std::max(out.disc, st.rel_max());
+    auto eh = op_apply(X, *ops.G, *th, 0, sk(X, O), &st);
+    out.disc = std::max(out.disc, st.rel_max());
+    auto y = op_apply(X, *ops.S->adj, *eh, 0, sk(X, O), &st);
+    out.disc = std::max(out.disc, st.rel_max());
+    auto nw = axpby(X, 1.0, *Et, -1.0, *y);
+    round_tt(X, *nw, O->delta, O->cap, &st);
+    out.disc = std::max(out.disc, st.rel_max());
+    for (int k = 1; k < nw->L; ++k) out.max_rank = std::max(out.max_rank, nw->r[k]);
+    auto d = axpby(X, 1.0, *nw, -1.0, *eps);
+    std::vector<double> dn = tt_norms(X, *d);
+    eps = nw;
+    ++m;
+    if (verbose()) {
+      std::fprintf(stderr, "[qtthom] it %d res", m);
+      for (int b = 0; b < B; ++b) std::fprintf(stderr, " %.3e", dn[b] / normE);
+      std::fprintf(stderr, " rank %d disc %.2e\n", out.max_rank, out.disc);
+    }
+    bool all = true;
+    for (int b = 0; b < B; ++b) {
+      const double r = dn[b] / normE;
+      if (!std::isfinite(r)) throw std::runtime_error("NaN/Inf in residual");
+      if (!done[b]) {
+        out.iters[b] = m;
+        out.res[b] = r;
+        if (r < O->tol) done[b] = 1;
+      }
+      all = all && done[b];
+    }
+    if (all) break;
+    if (m >= O->max_iter) {
+      out.converged = false;
+      break;
+    }
+    for (int b = 0; b < B; ++b)
+      if (!done[b] && out.res[b] > 1e3) throw std::overflow_error("fixed point diverged");
+  }
+  out.eps = eps;
+  return out;
+}
+
+static void ceff_from(const Ctx& X, const Ops& ops, const qtt_problem* P, const SolveOut& so,
+                      double* Ceff) {
+  auto md = mean_apply(X, *ops.Cd, *so.eps);
+  auto me = mean_apply(X, *ops.I, *so.eps);
+  double C0m[36];
+  host::iso_voigt(P->lame0[0], P->lame0[1], C0m);
+  for (size_t b = 0; b < so.ks.size(); ++b) {
+    const int k = so.ks[b];
+    for (int i = 0; i < 6; ++i) {
+      std::complex<double> s = md[b * 6 + i];
+      for (int j = 0; j < 6; ++j) s += C0m[i * 6 + j] * me[b * 6 + j];
+      Ceff[i * 6 + k] = s.real();
+    }
+  }
+}
+
+}  // namespace qtt
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace qtt;
+
+template <class F>
+static int guarded(qtt_ctx* ctx, F&& f) {
+  try {
+    f();
+    return QTT_OK;
+  } catch (const std::invalid_argument& e) {
+    if (ctx) ctx->err = e.what();
+    return QTT_EINVAL;
+  } catch (const std::length_error& e) {
+    if (ctx) ctx->err = e.what();
+    return QTT_ECAPACITY;
+  } catch (const std::logic_error& e) {
+    if (ctx) ctx->err = e.what();
+    return QTT_EHIP;
+  } catch (const std::bad_alloc&) {
+    if (ctx) ctx->err = "allocation failed";
+    return QTT_ENOMEM;
+  } catch (const std::overflow_error& e) {
+    if (ctx) ctx->err = e.what();
+    return QTT_EDIVERGED;
+  } catch (const std::runtime_error& e) {
+    if (ctx) ctx->err = e.what();
+    return std::string(e.what()).find("NaN") != std::string::npos ? QTT_ENAN : QTT_EHIP;
+  } catch (...) {
+    if (ctx) ctx->err = "unknown error";
+    return QTT_EHIP;
+  }
+}
+#define QTT_TRY(ctx, ...) return guarded(ctx, [&]() { __VA_ARGS__; })
+
+extern "C" {
+
+int qtt_create(int device, void* hip_stream, qtt_ctx** out) {
+  if (!out) return QTT_EINVAL;
+  *out = nullptr;
+  try {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return QTT_EINVAL;
+    check(hipSetDevice(device), "set device");
+    auto* c = new qtt_ctx();
+    c->device = device;
+    if (hip_stream) {
+      c->stream = (hipStream_t)hip_stream;
+    } else {
+      check(hipStreamCreate(&c->stream), "stream create");
+      c->own_stream = true;
+    }
+    c->pool = std::make_shared<Pool>();
+    c->pool->device = device;
+    *out = c;
+    return QTT_OK;
+  } catch (...) {
+    return QTT_EHIP;
+  }
+}
+
+int qtt_destroy(qtt_ctx* c) {
+  if (!c) return QTT_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  c->ident.clear();
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return QTT_OK;
+}
+
+const char* qtt_last_error(const qtt_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int qtt_sync(qtt_ctx* c) {
+  if (!c) return QTT_EINVAL;
+  QTT_TRY(c, check(hipStreamSynchronize(c->stream), "sync"));
+}
+
+int qtt_tt_from_host(qtt_ctx* c, int L, const int* dims, const int* ranks, int batch,
+                     const double* data, qtt_tensor** out) {
+  if (!c || !out || !dims || !ranks || !data || L < 1 || batch < 1) return QTT_EINVAL;
+  QTT_TRY(c, {
+    Ctx X{c};
+    if (ranks[0] != 1 || ranks[L] != 1) throw std::invalid_argument("boundary ranks must be 1");
+    std::vector<int> d(dims, dims + L), r(ranks, ranks + L + 1);
+    for (int k = 0; k < L; ++k)
+      if (d[k] < 1 || r[k + 1] < 1) throw std::invalid_argument("bad dims or ranks");
+    auto t = new_tt(X, L, batch, d, r);
+    size_t off = 0;
+    for (int k = 0; k < L; ++k) {
+      const size_t cnt = (size_t)batch * t->celems(k);
+      check(hipMemcpyAsync(t->core[k], data + 2 * off, cnt * sizeof(cplx), hipMemcpyHostToDevice, c->stream), "h2d");
+      off += cnt;
+    }
+    X.sync();
+    *out = new qtt_tensor(*t);
+  });
+}
+
+int qtt_tensor_shape(const qtt_tensor* t, int* kind, int* L, int* batch, int* dims_out,
+                     int* dims_in, int* ranks) {
+  if (!t) return QTT_EINVAL;
+  if (kind) *kind = t->kind == 0 ? 0 : 1;
+  if (L) *L = t->L;
+  if (batch) *batch = t->B;
+  for (int k = 0; k < t->L; ++k) {
+    if (dims_out) dims_out[k] = t->dout[k];
+    if (dims_in) dims_in[k] = t->din[k];
+  }
+  if (ranks)
+    for (int k = 0; k <= t->L; ++k) ranks[k] = t->r[k];
+  return QTT_OK;
+}
+
+size_t qtt_tensor_size(const qtt_tensor* t) {
+  if (!t || t->kind == 2) return 0;
+  size_t s = 0;
+  for (int k = 0; k < t->L; ++k) {
+    if (t->kind == 0) s += (size_t)t->B * t->celems(k);
+    else s += (size_t)t->r[k] * t->dout[k] * t->din[k] * t->r[k + 1];
+  }
+  return s;
+}
+
+int qtt_tensor_to_host(qtt_ctx* c, const qtt_tensor* t, double* data, size_t capacity) {
+  if (!c || !t || !data) return QTT_EINVAL;
+  if (t->kind == 2) {
+    c->err = "Green operator is factored; query its factors";
+    return QTT_EINVAL;
+  }
+  if (capacity < qtt_tensor_size(t)) return QTT_ECAPACITY;
+  QTT_TRY(c, {
+    size_t off = 0;
+    for (int k = 0; k < t->L; ++k) {
+      if (t->kind == 0 || t->diag[k]) {
+        const size_t cnt = (size_t)t->B * t->celems(k);
+        if (t->kind == 0) {
+          check(hipMemcpyAsync(data + 2 * off, t->core[k], cnt * sizeof(cplx), hipMemcpyDeviceToHost, c->stream), "d2h");
+          off += cnt;
+        } else {
+          std::vector<std::complex<double>> tmp(cnt);
+          check(hipMemcpyAsync(tmp.data(), t->core[k], cnt * sizeof(cplx), hipMemcpyDeviceToHost, c->stream), "d2h");
+          check(hipStreamSynchronize(c->stream), "sync");
+          const int r0 = t->r[k], d = t->dout[k], r1 = t->r[k + 1];
+          const size_t full = (size_t)r0 * d * d * r1;
+          std::vector<std::complex<double>> f(full, 0.0);
+          for (int a = 0; a < r0; ++a)
+            for (int i = 0; i < d; ++i)
+              for (int b = 0; b < r1; ++b)
+                f[(((size_t)a * d + i) * d + i) * r1 + b] = tmp[((size_t)a * d + i) * r1 + b];
+          std::memcpy(data + 2 * off, f.data(), full * sizeof(cplx));
+          off += full;
+        }
+      } else {
+        const size_t cnt = (size_t)t->r[k] * t->dout[k] * t->din[k] * t->r[k + 1];
+        check(hipMemcpyAsync(data + 2 * off, t->coreR[k], cnt * sizeof(cplx), hipMemcpyDeviceToHost, c->stream), "d2h");
+        off += cnt;
+      }
+    }
+    check(hipStreamSynchronize(c->stream), "sync");
+  });
+}
+
+int qtt_tensor_destroy(qtt_tensor* t) {
+  delete t;
+  return QTT_OK;
+}
+
+int qtt_const_strain(qtt_ctx* c, int n, int batch, const double* E, qtt_tensor** out) {
+  if (!c || !E || !out || n < 1 || n > 10 || batch < 1) return QTT_EINVAL;
+  QTT_TRY(c, {
+    Ctx X{c};
+    *out = new qtt_tensor(*const_strain(X, n, batch, E));
+  });
+}
+
+int qtt_sfft_build(qtt_ctx* c, int n, double delta, qtt_tensor** S) {
+  if (!c || !S || n < 1 || n > 10 || !(delta > 0)) return QTT_EINVAL;
+  QTT_TRY(c, {
+    Ctx X{c};
+    *S = new qtt_tensor(*sfft_op(X, n, delta));
+  });
+}
+
+int qtt_green_build(qtt_ctx* c, int n, double lam0, double mu0, double delta, qtt_tensor** Gp) {
+  if (!c || !Gp || n < 1 || n > 9 || !(mu0 > 0) || !(lam0 + 2 * mu0 > 0) || !(delta > 0)) return QTT_EINVAL;
+  QTT_TRY(c, {
+    Ctx X{c};
+    *Gp = new qtt_tensor(*green_op(X, n, lam0, mu0, delta));
+  });
+}
+
+int qtt_from_voxels(qtt_ctx* c, const uint8_t* phase, int phase_on_device, int n, int nphase,
+                    const double* lame, const double lame0[2], double delta, int cap,
+                    qtt_tensor** Cm, qtt_tensor** chi) {
+  if (!c || !phase || !lame || !lame0 || !Cm || n < 1 || n > 9 || nphase < 1 || nphase > 16)
+    return QTT_EINVAL;
+  QTT_TRY(c, {
+    Ctx X{c};
+    const size_t NN = (size_t)1 << (3 * n);
+    std::vector<uint8_t> hp;
+    const uint8_t* ph = phase;
+    if (phase_on_device) {
+      hp.resize(NN);
+      check(hipMemcpy(hp.data(), phase, NN, hipMemcpyDeviceToHost), "phase d2h");
+      ph = hp.data();
+    }
+    host::HTT chih;
+    host::HTT cd = host::stiffness_tto(ph, n, nphase, lame, lame0, delta, cap, &chih, nullptr);
+    *Cm = new qtt_tensor(*upload_op(X, cd));
+    if (chi) {
+      // the one-hot train as a train (kind 0, batch 1)
+      std::vector<int> d, r;
+      r.push_back(1);
+      for (auto& cc : chih) { d.push_back(cc.dout); r.push_back(cc.r1); }
+      auto t = new_tt(X, (int)chih.size(), 1, d, r);
+      for (size_t k = 0; k < chih.size(); ++k)
+        check(hipMemcpyAsync(t->core[k], chih[k].v.data(), chih[k].v.size() * sizeof(cplx), hipMemcpyHostToDevice, c->stream), "chi h2d");
+      X.sync();
+      *chi = new qtt_tensor(*t);
+    }
+  });
+}
+
+static int product(qtt_ctx* c, const qtt_tensor* A, const qtt_tensor* x, qtt_tensor** y, int flags,
+                   double delta, int cap, uint64_t seed, bool inverse_ok) {
+  if (!c || !A || !x || !y || x->kind != 0 || !(delta > 0)) return QTT_EINVAL;
+  QTT_TRY(c, {
+    Ctx X{c};
+    const qtt_tensor* op = A;
+    if (inverse_ok && (flags & QTT_INVERSE)) {
+      if (!A->adj) throw std::invalid_argument("operator has no stored inverse");
+      op = A->adj.get();
+    }
+    SketchOpts o;
+    o.delta = delta;
+    o.cap = cap;
+    o.seed = seed;
+    *y = new qtt_tensor(*op_apply(X, *op, *x, flags, o, nullptr));
+  });
+}
+
+int sfft_apply(qtt_ctx* c, const qtt_tensor* S, const qtt_tensor* x, qtt_tensor** y, int flags,
+               double delta, int cap, uint64_t seed) {
+  return product(c, S, x, y, flags, delta, cap, seed, true);
+}
+
+int tt_hadamard(qtt_ctx* c, const qtt_tensor* A, const qtt_tensor* x, qtt_tensor** y, int flags,
+                double delta, int cap, uint64_t seed) {
+  if (A && A->kind != 1) return QTT_EINVAL;
+  return product(c, A, x, y, flags, delta, cap, seed, false);
+}
+
+int green_apply(qtt_ctx* c, const qtt_tensor* Gm, const qtt_tensor* x, qtt_tensor** y, int flags,
+                double delta, int cap, uint64_t seed) {
+  if (Gm && Gm->kind != 2) return QTT_EINVAL;
+  return product(c, Gm, x, y, flags, delta, cap, seed, false);
+}
+
+int tt_round(qtt_ctx* c, qtt_tensor* x, double delta, int cap, double* discarded) {
+  if (!c || !x || x->kind != 0 || !(delta >= 0)) return QTT_EINVAL;
+  QTT_TRY(c, {
+    Ctx X{c};
+    RoundStats st;
+    round_tt(X, *x, delta, cap, &st);
+    if (discarded)
+      for (int b = 0; b < x->B; ++b) discarded[b] = st.norm[b] > 0 ? std::sqrt(st.disc2[b]) / st.norm[b] : 0.0;
+  });
+}
+
+int tt_norm(qtt_ctx* c, const qtt_tensor* x, double* out) {
+  if (!c || !x || !out || x->kind != 0) return QTT_EINVAL;
+  QTT_TRY(c, {
+    Ctx X{c};
+    auto v = tt_norms(X, *x);
+    for (int b = 0; b < x->B; ++b) out[b] = v[b];
+  });
+}
+
+int tt_axpby(qtt_ctx* c, double alpha, const qtt_tensor* x, double beta, const qtt_tensor* y,
+             qtt_tensor** z) {
+  if (!c || !x || !y || !z || x->kind != 0 || y->kind != 0) return QTT_EINVAL;
+  QTT_TRY(c, {
+    Ctx X{c};
+    *z = new qtt_tensor(*axpby(X, alpha, *x, beta, *y));
+  });
+}
+
+int tt_mean_apply(qtt_ctx* c, const qtt_tensor* A, const qtt_tensor* x, double* out) {
+  if (!c || !A || !x || !out || A->kind != 1 || x->kind != 0) return QTT_EINVAL;
+  QTT_TRY(c, {
+    Ctx X{c};
+    auto v = mean_apply(X, *A, *x);
+    std::memcpy(out, v.data(), v.size() * sizeof(cplx));
+  });
+}
+
+int ls_solve(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, double* Ceff,
+             qtt_report* R, qtt_tensor** eps_out) {
+  if (!c || !Ceff) return QTT_EINVAL;
+  int status = QTT_OK;
+  int rc;
+  auto body = [&]() {
+    check_problem(P, O);
+    Ctx X{c};
+    std::vector<int> ks;
+    for (int k = 0; k < 6; ++k)
+      if (P->load_mask & (1 << k)) ks.push_back(k);
+    if (ks.empty()) throw std::invalid_argument("empty load mask");
+    const double t0 = now_s();
+    Ops ops = build_ops(X, P, O->delta);
+    X.sync();
+    const double t1 = now_s();
+    SolveOut so = ls_loop(X, ops, P, O, ks);
+    for (int i = 0; i < 36; ++i) Ceff[i] = 0.0;
+    ceff_from(X, ops, P, so, Ceff);
+    X.sync();
+    const double t2 = now_s();
+    if (R) {
+      std::memset(R, 0, sizeof(*R));
+      for (size_t b = 0; b < ks.size(); ++b) {
+        R->iterations[ks[b]] = so.iters[b];
+        R->residual[ks[b]] = so.res[b];
+      }
+      R->max_rank = so.max_rank;
+      R->discarded = so.disc;
+      R->seconds_setup = t1 - t0;
+      R->seconds_solve = t2 - t1;
+    }
+    if (eps_out) *eps_out = new qtt_tensor(*so.eps);
+    if (!so.converged) status = QTT_ENOCONV;
+  };
+  rc = [&]() -> int { QTT_TRY(c, body()); }();
+  if (rc == QTT_OK) rc = status;
+  if (R) R->status = rc;
+  return rc;
+}
+
+int ls_adjoint(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, const qtt_tensor* eps,
+               const double* gbar, double* grad, qtt_report* R) {
+  if (!c || !eps || !grad || eps->kind != 0 || eps->B != 6) return QTT_EINVAL;
+  int status = QTT_OK;
+  auto body = [&]() {
+    check_problem(P, O);
+    Ctx X{c};
+    const double t0 = now_s();
+    Ops ops = build_ops(X, P, O->delta);
+    X.sync();
+    const double t1 = now_s();
+    const int n = P->n, np = P->nphase;
+    const double NN = std::pow(2.0, 3.0 * n);
+    // C e_k trains: (C - C0) : E + C0 E
+    std::vector<double> E(36, 0.0), C0E(36, 0.0);
+    double C0m[36];
+    host::iso_voigt(P->lame0[0], P->lame0[1], C0m);
+    for (int k = 0; k < 6; ++k) {
+      E[k * 6 + k] = 1.0;
+      for (int i = 0; i < 6; ++i) C0E[k * 6 + i] = C0m[i * 6 + k];
+    }
+    auto Et = const_strain(X, n, 6, E.data());
+    auto C0t = const_strain(X, n, 6, C0E.data());
+    SketchOpts so = sk(X, O);
+    so.exact = true;  // rank of (C - C0) E is the stiffness rank: exact
+    auto dE = op_apply(X, *ops.Cd, *Et, 0, so, nullptr);
+    auto Ce = axpby(X, 1.0, *dE, 1.0, *C0t);
+    round_tt(X, *Ce, O->delta, O->cap, nullptr);
+    std::vector<double> nCe = tt_norms(X, *Ce);
+    // adjoint fixed point w = C e_k - (C - C0) : G[w],  G = S^H Gamma S
+    auto w = Ce;
+    std::vector<int> it(6, 0);
+    std::vector<char> done(6, 0);
+    int m = 0;
+    bool conv = true;
+    while (true) {
+      auto u = op_apply(X, *ops.S, *w, 0, sk(X, O), nullptr);
+      u = op_apply(X, *ops.G, *u, 0, sk(X, O), nullptr);
+      u = op_apply(X, *ops.S->adj, *u, 0, sk(X, O), nullptr);
+      u = op_apply(X, *ops.Cd, *u, 0, sk(X, O), nullptr);
+      auto nw = axpby(X, 1.0, *Ce, -1.0, *u);
+      round_tt(X, *nw, O->delta, O->cap, nullptr);
+      auto d = axpby(X, 1.0, *nw, -1.0, *w);
+      auto dn = tt_norms(X, *d);
+      w = nw;
+      ++m;
+      bool all = true;
+      for (int b = 0; b < 6; ++b) {
+        const double r = dn[b] / std::max(nCe[b], 1e-300);
+        if (!std::isfinite(r)) throw std::runtime_error("NaN in adjoint residual");
+        if (!done[b]) {
+          it[b] = m;
+          if (r < O->tol) done[b] = 1;
+        }
+        all = all && done[b];
+      }
+      if (all) break;
+      if (m >= O->max_iter) { conv = false; break; }
+    }
+    // gradient
+    const int nt = 2 * np;
+    std::vector<double> J((size_t)36 * nt, 0.0);
+    double Dl[36], Dm[36];
+    host::iso_voigt(1.0, 0.0, Dl);
+    host::iso_voigt(0.0, 1.0, Dm);
+    for (int p = 0; p < np; ++p)
+      for (int t = 0; t < 2; ++t) {
+        auto dC = dC_op(X, ops.chi, p, t == 0 ? Dl : Dm);
+        SketchOpts se = sk(X, O);
+        auto v = op_apply(X, *dC, *eps, 0, se, nullptr);       // dC : eps^l
+        auto first = mean_apply(X, *ops.I, *v);               // <e_k . dC eps^l>
+        auto gv = op_apply(X, *ops.S, *v, 0, sk(X, O), nullptr);
+        gv = op_apply(X, *ops.G, *gv, 0, sk(X, O), nullptr);
+        gv = op_apply(X, *ops.S->adj, *gv, 0, sk(X, O), nullptr);
+        auto gram = tt_gram(X, *w, *gv);                      // [k][l] sum conj(w_k) Gv_l
+        for (int k = 0; k < 6; ++k)
+          for (int l = 0; l < 6; ++l)
+            J[((size_t)k * 6 + l) * nt + 2 * p + t] =
+                first[(size_t)l * 6 + k].real() - gram[(size_t)k * 6 + l].real() / NN;
+      }
+    if (gbar) {
+      for (int t = 0; t < nt; ++t) {
+        double s = 0.0;
+        for (int i = 0; i < 36; ++i) s += gbar[i] * J[(size_t)i * nt + t];
+        grad[t] = s;
+      }
+    } else {
+      std::memcpy(grad, J.data(), J.size() * sizeof(double));
+    }
+    X.sync();
+    const double t2 = now_s();
+    if (R) {
+      std::memset(R, 0, sizeof(*R));
+      for (int k = 0; k < 6; ++k) R->iterations[k] = it[k];
+      R->seconds_setup = t1 - t0;
+      R->seconds_solve = t2 - t1;
+    }
+    if (!conv) status = QTT_ENOCONV;
+  };
+  int rc = [&]() -> int { QTT_TRY(c, body()); }();
+  if (rc == QTT_OK) rc = status;
+  if (R) R->status = rc;
+  return rc;
+}
+
+int qtt_batch_solve(qtt_ctx* c, int count, const qtt_problem* Ps, const qtt_solve_opts* O,
+                    double* Ceff, qtt_report* Rs) {
+  if (!c || count < 0 || (count > 0 && (!Ps || !Ceff))) return QTT_EINVAL;
+  int worst = QTT_OK;
+  for (int i = 0; i < count; ++i) {
+    const int rc = ls_solve(c, &Ps[i], O, Ceff + (size_t)36 * i, Rs ? &Rs[i] : nullptr, nullptr);
+    if (rc != QTT_OK && worst == QTT_OK) worst = rc;
+    if (rc != QTT_OK && rc != QTT_ENOCONV) return rc;
+  }
+  return worst;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Host-side construction of the operators of SFFT-based homogenization
+// (preprocessing, run once per grid / reference medium / geometry).
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+namespace qtt {
+namespace host {
+
+using zc = std::complex<double>;
+
+// A host tensor train (or operator) core list.  TT cores are (r0, d, r1)
+// row-major; operator cores (r0, dout, din, r1); diagonal operator cores
+// (r0, d, r1).
+struct HCore {
+  int r0 = 1, dout = 1, din = 0, r1 = 1;  // din = 0: TT core or diagonal operator core
+  std::vector<zc> v;
+};
+using HTT = std::vector<HCore>;
+
+// TT-SVD of a dense real tensor with dims[0..L-1] (row-major, first index
+// slowest): successive truncated SVDs, per-bond threshold
+// delta / sqrt(L-1) * ||T||, rank clipped to cap.
+HTT tt_svd_real(const std::vector<double>& T, const std::vector<int>& dims,
+                double delta, int cap);
+
+// TT-rounding of a host train whose cores carry a combined physical index
+// (dout * max(din,1)); same rule as tt_svd_real.
+void tt_round(HTT& x, double delta, int cap);
+
+// Reduced QFT Q_n as a TTO (cores (r0, 2, 2, r1), out index first), by
+// contracting the circuit layer by layer with SVD truncation.
+HTT qn_tto(int n, double delta);
+
+// Green operator in bounded factors, SFFT momentum order.  With the unit
+// direction n = xi/|xi| (n = 0 at xi = 0) the direct-scheme operator acts as
+//   u_j = tau_jk n_k,  s = n . u,  q = u/(2 mu0) - (c/2) n s,
+//   eps_ij = n_i q_j + n_j q_i,   c = (lam0 + mu0)/(mu0 (lam0 + 2 mu0)),
+// averaged over the two Nyquist representatives sigma (Hermitian
+// symmetrisation).  All four maps share the spatial cores of the joint
+// train of n^sigma_a (control index (sigma, a), 6 values):
+//   U: tau (6 Voigt) -> u (sigma, j);   Sd: u -> s (sigma);
+//   P: s -> p = n s (sigma, j);         E: q (sigma, j) -> eps (6 Voigt).
+// Every factor is bounded by 1 pointwise, so truncation errors are not
+// amplified between the steps.
+struct GreenFactors {
+  HTT U, Sd, P, E;
+  double inv_2mu0 = 0.0, half_c = 0.0;
+};
+GreenFactors green_factors(int n, double lam0, double mu0, double delta);
+
+// Joint train of the unit directions n^sigma_a in momentum order (core 0
+// of dimension 6 = (sigma, a)).
+HTT direction_train(int n, double delta);
+
+// Raised stiffness operator C(x) - C0 (or one-hot phase train chi) from a
+// voxel phase array; returns the operator, and the one-hot train in chi.
+HTT stiffness_tto(const uint8_t* phase, int n, int nphase, const double* lame,
+                  const double* lame0, double delta, int cap, HTT* chi,
+                  int* max_rank);
+
+// Isotropic Voigt stiffness (order 11, 22, 33, 23, 13, 12).
+void iso_voigt(double lam, double mu, double C[36]);
+
+}  // namespace host
+}  // namespace qtt

@@ -1,0 +1,598 @@
+// HIP kernels for quantized tensor-train arithmetic on gfx950 (CDNA4).
+//
+// Everything here works on interleaved complex FP64 (double2) data:
+//  * a strided, two-level batched complex GEMM (LDS-tiled) that carries the
+//    core-by-core contractions of TTO x TT products, sketches and absorbs;
+//  * Householder QR with 64-lane wavefront-shuffle reductions for the norms
+//    and reflector dot products (orthogonalisation sweeps of TT-rounding,
+//    Sec. 3 of the paper);
+//  * one-sided Jacobi SVD (truncation sweeps of TT-rounding), singular
+//    values sorted on device;
+//  * Philox4x32-10 + Box-Muller complex normals for the rounding sketches;
+//  * the materialised TTO x TT core product (Table 2, contract), a purely
+//    HBM-bound kernel with coalesced rank-major writes.
+#include "qtt_internal.h"
+
+#include <cstdio>
+#include <stdexcept>
+
+namespace qtt {
+
+void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    throw std::runtime_error(std::string("HIP error in ") + what + ": " +
+                             hipGetErrorString(e));
+  }
+}
+
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ cplx cconj(cplx a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ cplx csub(cplx a, cplx b) {
+  return make_double2(a.x - b.x, a.y - b.y);
+}
+// conj(a) * b
+__device__ __forceinline__ cplx cdotc(cplx a, cplx b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double cabs2(cplx a) { return a.x * a.x + a.y * a.y; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ cplx wave_sum(cplx v) {
+  return make_double2(wave_sum(v.x), wave_sum(v.y));
+}
+
+// Block-wide sum of a double; every thread gets the result.
+template <int NT>
+__device__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) t += sh[i];
+  return t;
+}
+
+__device__ __forceinline__ cplx ldview(const MatView& v, long b, long i, long j) {
+  cplx a = v.base[b * v.sb + i * v.rs + j * v.cs];
+  if (v.conj) a.y = -a.y;
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// GEMM
+// ---------------------------------------------------------------------------
+constexpr int GBK = 8;
+
+template <int TM, int TN>
+__global__ __launch_bounds__((TM / 4) * (TN / 4)) void k_gemm(GemmArgs g) {
+  constexpr int NT = (TM / 4) * (TN / 4);
+  constexpr int TX = TN / 4;  // threads along N
+  __shared__ cplx As[GBK][TM];
+  __shared__ cplx Bs[GBK][TN];
+  const int tid = threadIdx.x;
+  const int tx = tid % TX, ty = tid / TX;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  const int bz = blockIdx.z;
+  const int b1 = bz / g.nb2, b2 = bz % g.nb2;
+  const cplx* A = g.A + b1 * g.sA1 + b2 * g.sA2;
+  const cplx* B = g.B + b1 * g.sB1 + b2 * g.sB2;
+  cplx* C = g.C + b1 * g.sC1 + b2 * g.sC2;
+
+  cplx acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0.0, 0.0);
+
+  for (int k0 = 0; k0 < g.K; k0 += GBK) {
+    for (int e = tid; e < TM * GBK; e += NT) {
+      int mm, kk;
+      if (g.opA == OP_N) { kk = e % GBK; mm = e / GBK; }
+      else { mm = e % TM; kk = e / TM; }
+      const int m = m0 + mm, k = k0 + kk;
+      cplx v = make_double2(0.0, 0.0);
+      if (m < g.M && k < g.K) {
+        if (g.opA == OP_N) v = A[(long)m * g.lda + k];
+        else {
+          v = A[(long)k * g.lda + m];
+          if (g.opA == OP_C) v.y = -v.y;
+        }
+      }
+      As[kk][mm] = v;
+    }
+    for (int e = tid; e < TN * GBK; e += NT) {
+      int nn, kk;
+      if (g.opB == OP_N) { nn = e % TN; kk = e / TN; }
+      else { kk = e % GBK; nn = e / GBK; }
+      const int n = n0 + nn, k = k0 + kk;
+      cplx v = make_double2(0.0, 0.0);
+      if (n < g.N && k < g.K) {
+        if (g.opB == OP_N) v = B[(long)k * g.ldb + n];
+        else {
+          v = B[(long)n * g.ldb + k];
+          if (g.opB == OP_C) v.y = -v.y;
+        }
+      }
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GBK; ++kk) {
+      cplx a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + i * (TM / 4)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx + j * TX];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j].x = fma(a[i].x, b[j].x, acc[i][j].x);
+          acc[i][j].x = fma(-a[i].y, b[j].y, acc[i][j].x);
+          acc[i][j].y = fma(a[i].x, b[j].y, acc[i][j].y);
+          acc[i][j].y = fma(a[i].y, b[j].x, acc[i][j].y);
+        }
+    }
+    __syncthreads();
+  }
+  const bool zb = (g.beta.x == 0.0 && g.beta.y == 0.0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + ty + i * (TM / 4);
+    if (m >= g.M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + tx + j * TX;
+      if (n >= g.N) continue;
+      cplx r = cmul(g.alpha, acc[i][j]);
+      cplx* cp = C + (long)m * g.ldc + n;
+      if (!zb) r = cadd(r, cmul(g.beta, *cp));
+      *cp = r;
+    }
+  }
+}
+
+template <int TM, int TN>
+static void launch_gemm(const GemmArgs& g, hipStream_t s) {
+  dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, g.nb1 * g.nb2);
+  hipLaunchKernelGGL((k_gemm<TM, TN>), grid, dim3((TM / 4) * (TN / 4)), 0, s, g);
+}
+
+void gemm(const GemmArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return;
+  if (g.nb1 * (long)g.nb2 > 65535) throw std::runtime_error("gemm: batch too large");
+  const long tiles64 = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.nb1 * g.nb2;
+  if (g.M <= 16 && g.N > 32) launch_gemm<16, 64>(g, s);
+  else if (g.N <= 16 && g.M > 32) launch_gemm<64, 16>(g, s);
+  else if (g.M <= 32 || g.N <= 32 || tiles64 < 512) launch_gemm<32, 32>(g, s);
+  else launch_gemm<64, 64>(g, s);
+  check(hipGetLastError(), "gemm launch");
+}
+
+// ---------------------------------------------------------------------------
+// Householder QR (one workgroup per matrix)
+// ---------------------------------------------------------------------------
+constexpr int QR_NT = 512;
+
+__global__ __launch_bounds__(QR_NT) void k_qr(int m, int n, MatView A, MatOut R,
+                                              MatOut Q, cplx* ws) {
+  const int b = blockIdx.x;
+  const int k = min(m, n);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = QR_NT / 64;
+  cplx* W = ws + (long)b * ((long)m * n + (long)m * k + k);
+  cplx* Qw = W + (long)m * n;
+  cplx* tau = Qw + (long)m * k;
+  __shared__ double red[NW];
+  __shared__ cplx sh_tau, sh_inv;
+
+  for (long e = tid; e < (long)m * n; e += QR_NT) {
+    const long i = e % m, j = e / m;
+    W[j * m + i] = ldview(A, b, i, j);
+  }
+  __syncthreads();
+
+  for (int j = 0; j < k; ++j) {
+    cplx* v = W + (long)j * m;
+    double part = 0.0;
+    for (int i = j + 1 + tid; i < m; i += QR_NT) part += cabs2(v[i]);
+    const double xn2 = block_sum<QR_NT>(part, red);
+    if (tid == 0) {
+      const cplx alpha = v[j];
+      if (xn2 == 0.0 && alpha.y == 0.0) {
+        sh_tau = make_double2(0.0, 0.0);
+        sh_inv = make_double2(0.0, 0.0);
+      } else {
+        const double beta = -copysign(sqrt(cabs2(alpha) + xn2), alpha.x);
+        sh_tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        const cplx d = make_double2(alpha.x - beta, alpha.y);
+        const double dd = cabs2(d);
+        sh_inv = make_double2(d.x / dd, -d.y / dd);
+        v[j] = make_double2(beta, 0.0);
+      }
+      tau[j] = sh_tau;
+    }
+    __syncthreads();
+    const cplx tj = sh_tau;
+    if (tj.x == 0.0 && tj.y == 0.0) continue;
+    const cplx inv = sh_inv;
+    for (int i = j + 1 + tid; i < m; i += QR_NT) v[i] = cmul(v[i], inv);
+    __syncthreads();
+    const cplx ctj = cconj(tj);
+    for (int c = j + 1 + wave; c < n; c += NW) {
+      cplx* col = W + (long)c * m;
+      cplx s = (lane == 0) ? col[j] : make_double2(0.0, 0.0);
+      for (int i = j + 1 + lane; i < m; i += 64) s = cadd(s, cdotc(v[i], col[i]));
+      s = wave_sum(s);
+      const cplx f = cmul(ctj, s);
+      if (lane == 0) col[j] = csub(col[j], f);
+      for (int i = j + 1 + lane; i < m; i += 64) col[i] = csub(col[i], cmul(f, v[i]));
+    }
+    __syncthreads();
+  }
+
+  for (long e = tid; e < (long)k * n; e += QR_NT) {
+    const long i = e / n, j = e % n;
+    const cplx val = (i <= j) ? W[j * m + i] : make_double2(0.0, 0.0);
+    R.base[b * R.sb + i * R.rs + j * R.cs] = val;
+  }
+  if (Q.base == nullptr) return;
+
+  for (long e = tid; e < (long)m * k; e += QR_NT) {
+    const long i = e % m, j = e / m;
+    Qw[j * m + i] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int j = k - 1; j >= 0; --j) {
+    const cplx tj = tau[j];
+    if (tj.x == 0.0 && tj.y == 0.0) continue;
+    const cplx* v = W + (long)j * m;
+    for (int c = j + wave; c < k; c += NW) {
+      cplx* col = Qw + (long)c * m;
+      cplx s = (lane == 0) ? col[j] : make_double2(0.0, 0.0);
+      for (int i = j + 1 + lane; i < m; i += 64) s = cadd(s, cdotc(v[i], col[i]));
+      s = wave_sum(s);
+      const cplx f = cmul(tj, s);
+      if (lane == 0) col[j] = csub(col[j], f);
+      for (int i = j + 1 + lane; i < m; i += 64) col[i] = csub(col[i], cmul(f, v[i]));
+    }
+    __syncthreads();
+  }
+  for (long e = tid; e < (long)m * k; e += QR_NT) {
+    const long i = e / k, j = e % k;
+    Q.base[b * Q.sb + i * Q.rs + j * Q.cs] = Qw[j * m + i];
+  }
+}
+
+size_t qr_ws(int batch, int m, int n) {
+  const long k = m < n ? m : n;
+  return (size_t)batch * ((size_t)m * n + (size_t)m * k + k);
+}
+
+void qr(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
+        hipStream_t s) {
+  if (batch <= 0 || m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_qr, dim3(batch), dim3(QR_NT), 0, s, m, n, A, R, Q, ws);
+  check(hipGetLastError(), "qr launch");
+}
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi SVD (one workgroup per matrix), m >= n
+// ---------------------------------------------------------------------------
+constexpr int SVD_NT = 512;
+constexpr int SVD_MAXN = 1024;
+
+__global__ __launch_bounds__(SVD_NT) void k_svd(int m, int n, MatView A, MatOut U,
+                                                double* S, MatOut V, cplx* ws) {
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = SVD_NT / 64;
+  cplx* W = ws + (long)b * ((long)m * n + (long)n * n);
+  cplx* Vw = W + (long)m * n;
+  __shared__ double sig[SVD_MAXN];
+  __shared__ int rankpos[SVD_MAXN];
+  __shared__ int rotated;
+
+  for (long e = tid; e < (long)m * n; e += SVD_NT) {
+    const long i = e % m, j = e / m;
+    W[j * m + i] = ldview(A, b, i, j);
+  }
+  for (long e = tid; e < (long)n * n; e += SVD_NT) {
+    const long i = e % n, j = e / n;
+    Vw[j * n + i] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+
+  const int npad = n + (n & 1);
+  const int npairs = npad / 2;
+  const double tol = 1e-15;
+  for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < npad - 1; ++r) {
+      for (int p = wave; p < npairs; p += NW) {
+        const int pa = p, pb = npad - 1 - p;
+        int ca = pa == 0 ? 0 : ((pa - 1 + r) % (npad - 1)) + 1;
+        int cb = ((pb - 1 + r) % (npad - 1)) + 1;
+        if (ca >= n || cb >= n) continue;
+        if (ca > cb) { const int t = ca; ca = cb; cb = t; }
+        cplx* xa = W + (long)ca * m;
+        cplx* xb = W + (long)cb * m;
+        double al = 0.0, be = 0.0;
+        cplx ga = make_double2(0.0, 0.0);
+        for (int i = lane; i < m; i += 64) {
+          const cplx u = xa[i], w = xb[i];
+          al += cabs2(u);
+          be += cabs2(w);
+          ga = cadd(ga, cdotc(u, w));
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        const double g = sqrt(cabs2(ga));
+        if (!(g > tol * sqrt(al * be)) || al < 1e-300 || be < 1e-300) continue;
+        if (lane == 0) rotated = 1;
+        const double zeta = (be - al) / (2.0 * g);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+        const cplx ph = make_double2(ga.x / g, -ga.y / g);  // e^{-i phi}
+        for (int i = lane; i < m; i += 64) {
+          const cplx u = xa[i], w = cmul(ph, xb[i]);
+          xa[i] = make_double2(c * u.x - sn * w.x, c * u.y - sn * w.y);
+          xb[i] = make_double2(sn * u.x + c * w.x, sn * u.y + c * w.y);
+        }
+        cplx* va = Vw + (long)ca * n;
+        cplx* vb = Vw + (long)cb * n;
+        for (int i = lane; i < n; i += 64) {
+          const cplx u = va[i], w = cmul(ph, vb[i]);
+          va[i] = make_double2(c * u.x - sn * w.x, c * u.y - sn * w.y);
+          vb[i] = make_double2(sn * u.x + c * w.x, sn * u.y + c * w.y);
+        }
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+
+  for (int j = wave; j < n; j += NW) {
+    const cplx* x = W + (long)j * m;
+    double s2 = 0.0;
+    for (int i = lane; i < m; i += 64) s2 += cabs2(x[i]);
+    s2 = wave_sum(s2);
+    if (lane == 0) sig[j] = sqrt(s2);
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += SVD_NT) {
+    const double sj = sig[j];
+    int pos = 0;
+    for (int i = 0; i < n; ++i) {
+      const double si = sig[i];
+      pos += (si > sj) || (si == sj && i < j);
+    }
+    rankpos[j] = pos;
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += SVD_NT) S[(long)b * n + rankpos[j]] = sig[j];
+  for (long e = tid; e < (long)m * n; e += SVD_NT) {
+    const long i = e / n, j = e % n;
+    const double sj = sig[j];
+    cplx u = W[j * m + i];
+    if (sj > 0.0) { u.x /= sj; u.y /= sj; }
+    else u = make_double2(0.0, 0.0);
+    U.base[b * U.sb + i * U.rs + (long)rankpos[j] * U.cs] = u;
+  }
+  for (long e = tid; e < (long)n * n; e += SVD_NT) {
+    const long i = e / n, j = e % n;
+    V.base[b * V.sb + i * V.rs + (long)rankpos[j] * V.cs] = Vw[j * n + i];
+  }
+}
+
+size_t svd_ws(int batch, int m, int n) {
+  return (size_t)batch * ((size_t)m * n + (size_t)n * n);
+}
+
+void svd(int batch, int m, int n, MatView A, MatOut U, double* S, MatOut V,
+         cplx* ws, hipStream_t s) {
+  if (batch <= 0 || n <= 0) return;
+  if (m < n) throw std::runtime_error("svd: needs m >= n");
+  if (n > SVD_MAXN) throw std::runtime_error("svd: n too large");
+  hipLaunchKernelGGL(k_svd, dim3(batch), dim3(SVD_NT), 0, s, m, n, A, U, S, V, ws);
+  check(hipGetLastError(), "svd launch");
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw 2011)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                             uint32_t& c3, uint32_t k0, uint32_t k1) {
+  const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+  const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+  const uint32_t h0 = (uint32_t)(p0 >> 32), l0 = (uint32_t)p0;
+  const uint32_t h1 = (uint32_t)(p1 >> 32), l1 = (uint32_t)p1;
+  const uint32_t n0 = h1 ^ c1 ^ k0, n2 = h0 ^ c3 ^ k1;
+  c0 = n0; c1 = l1; c2 = n2; c3 = l0;
+}
+
+__global__ void k_gaussian(cplx* out, size_t count, uint64_t seed, uint64_t stream,
+                           double scale) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  uint32_t c0 = (uint32_t)e, c1 = (uint32_t)(e >> 32);
+  uint32_t c2 = (uint32_t)stream, c3 = (uint32_t)(stream >> 32);
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    philox_round(c0, c1, c2, c3, k0, k1);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  const double u1 = ((double)c0 + 0.5) * 2.3283064365386963e-10;  // (0, 1)
+  const double u2 = ((double)c1 + 0.5) * 2.3283064365386963e-10;
+  const double rr = sqrt(-2.0 * log(u1)) * scale;
+  double sn, cs;
+  sincospi(2.0 * u2, &sn, &cs);
+  out[e] = make_double2(rr * cs, rr * sn);
+}
+
+void gaussian(cplx* out, size_t count, uint64_t seed, uint64_t stream, double scale,
+              hipStream_t s) {
+  if (count == 0) return;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_gaussian, dim3((count + nt - 1) / nt), dim3(nt), 0, s, out,
+                     count, seed, stream, scale);
+  check(hipGetLastError(), "gaussian launch");
+}
+
+// ---------------------------------------------------------------------------
+// Materialised TTO x TT core product (Table 2, contract)
+// ---------------------------------------------------------------------------
+__global__ void k_tto_core_apply(long total, int rho, int din, int dout, int rho2, int r,
+                                 int r2, const cplx* __restrict__ A,
+                                 const cplx* __restrict__ x, cplx* __restrict__ Z) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  long t = e;
+  const int c2 = t % r2; t /= r2;
+  const int a2 = t % rho2; t /= rho2;
+  const int i = t % dout; t /= dout;
+  const int c = t % r; t /= r;
+  const int a = t % rho; t /= rho;
+  const long b = t;
+  const int dx = din > 0 ? din : dout;
+  const cplx* xb = x + ((b * r + c) * dx) * (long)r2 + c2;
+  cplx acc;
+  if (din == 0) {
+    acc = cmul(A[((long)a * dout + i) * rho2 + a2], xb[(long)i * r2]);
+  } else {
+    acc = make_double2(0.0, 0.0);
+    for (int j = 0; j < din; ++j)
+      acc = cadd(acc, cmul(A[(((long)a * din + j) * dout + i) * rho2 + a2], xb[(long)j * r2]));
+  }
+  Z[e] = acc;
+}
+
+void tto_core_apply(int batch, int rho, int din, int dout, int rho2, int r, int r2,
+                    const cplx* A, const cplx* x, cplx* Z, hipStream_t s) {
+  const long total = (long)batch * rho * r * dout * rho2 * r2;
+  if (total == 0) return;
+  const int nt = 256;
+  hipLaunchKernelGGL(k_tto_core_apply, dim3((total + nt - 1) / nt), dim3(nt), 0, s, total,
+                     rho, din, dout, rho2, r, r2, A, x, Z);
+  check(hipGetLastError(), "tto_core_apply launch");
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_batch_norm(long len, long stride, const cplx* x,
+                                                    double* out) {
+  __shared__ double red[4];
+  const cplx* p = x + (long)blockIdx.x * stride;
+  double s = 0.0;
+  for (long e = threadIdx.x; e < len; e += 256) s += cabs2(p[e]);
+  s = block_sum<256>(s, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = sqrt(s);
+}
+
+void batch_norm(int batch, long len, long stride, const cplx* x, double* out,
+                hipStream_t s) {
+  if (batch <= 0) return;
+  hipLaunchKernelGGL(k_batch_norm, dim3(batch), dim3(256), 0, s, len, stride, x, out);
+  check(hipGetLastError(), "batch_norm launch");
+}
+
+__global__ void k_scale_cols(long total, int rows, int cols, long ld, long sb, cplx* x,
+                             const double* S, long sS) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int j = e % cols;
+  const long t = e / cols;
+  const int i = t % rows;
+  const long b = t / rows;
+  cplx* p = x + b * sb + i * ld + j;
+  const double w = S[b * sS + j];
+  *p = make_double2(p->x * w, p->y * w);
+}
+
+void scale_cols(int batch, int rows, int cols, long ld, long sb, cplx* x, const double* S,
+                long sS, hipStream_t s) {
+  const long total = (long)batch * rows * cols;
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_scale_cols, dim3((total + 255) / 256), dim3(256), 0, s, total, rows,
+                     cols, ld, sb, x, S, sS);
+  check(hipGetLastError(), "scale_cols launch");
+}
+
+__global__ void k_copy2d(long total, int rows, int cols, MatView in, MatOut out, cplx alpha) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int j = e % cols;
+  const long t = e / cols;
+  const int i = t % rows;
+  const long b = t / rows;
+  out.base[b * out.sb + i * out.rs + (long)j * out.cs] = cmul(alpha, ldview(in, b, i, j));
+}
+
+void copy2d(int batch, int rows, int cols, MatView in, MatOut out, cplx alpha,
+            hipStream_t s) {
+  const long total = (long)batch * rows * cols;
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_copy2d, dim3((total + 255) / 256), dim3(256), 0, s, total, rows, cols,
+                     in, out, alpha);
+  check(hipGetLastError(), "copy2d launch");
+}
+
+void conj_transpose(int batch, int rows, int keep, MatView in, MatOut out, hipStream_t s) {
+  // out(j, i) = conj(in(i, j)) for j < keep
+  MatView t = in;
+  t.conj = !in.conj;
+  std::swap(t.rs, t.cs);
+  copy2d(batch, keep, rows, t, out, make_double2(1.0, 0.0), s);
+}
+
+__global__ void k_fill(cplx* p, size_t count, cplx v) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) p[e] = v;
+}
+
+void fill(cplx* p, size_t count, cplx v, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_fill, dim3((count + 255) / 256), dim3(256), 0, s, p, count, v);
+  check(hipGetLastError(), "fill launch");
+}
+
+__global__ void k_sum_middle(long total, int outer, int np, int inner, const cplx* in,
+                             cplx* out, cplx w) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int c = e % inner;
+  const long bo = e / inner;
+  const cplx* p = in + bo * (long)np * inner + c;
+  cplx acc = make_double2(0.0, 0.0);
+  for (int q = 0; q < np; ++q) acc = cadd(acc, p[(long)q * inner]);
+  out[e] = cmul(w, acc);
+}
+
+void sum_middle(int batch, int outer, int np, int inner, const cplx* in, cplx* out, cplx w,
+                hipStream_t s) {
+  const long total = (long)batch * outer * inner;
+  if (total == 0) return;
+  hipLaunchKernelGGL(k_sum_middle, dim3((total + 255) / 256), dim3(256), 0, s, total, outer,
+                     np, inner, in, out, w);
+  check(hipGetLastError(), "sum_middle launch");
+}
+
+}  // namespace qtt

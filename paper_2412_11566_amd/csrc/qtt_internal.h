@@ -1,0 +1,104 @@
+// Internal declarations shared by the HIP kernels and the host engine of
+// the qtthom library.  Not part of the public C ABI (include/qtthom.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+namespace qtt {
+
+using cplx = double2;  // interleaved complex double: x = re, y = im
+
+// operand transform of a GEMM operand
+enum Op : int { OP_N = 0, OP_T = 1, OP_C = 2 };
+
+// Strided, two-level batched complex GEMM on row-major operands:
+//   C[b1,b2] = alpha * op(A[b1,b2]) * op(B[b1,b2]) + beta * C[b1,b2]
+// op(A) is M x K: OP_N reads A[m*lda + k], OP_T reads A[k*lda + m], OP_C
+// reads conj(A[k*lda + m]).  op(B) is K x N likewise (OP_N: B[k*ldb + n]).
+// C[m*ldc + n].  Batch element (b1, b2) offsets every operand by
+// b1*s?1 + b2*s?2 complex entries.
+struct GemmArgs {
+  int M, N, K;
+  int opA, opB;
+  const cplx* A; long lda, sA1, sA2;
+  const cplx* B; long ldb, sB1, sB2;
+  cplx* C; long ldc, sC1, sC2;
+  int nb1, nb2;
+  cplx alpha, beta;
+};
+void gemm(const GemmArgs& g, hipStream_t s);
+
+// Strided matrix view used by the factorisation kernels: element (i, j) of
+// batch element b is base[b*sb + i*rs + j*cs], conjugated when conj != 0.
+struct MatView {
+  const cplx* base;
+  long rs, cs, sb;
+  int conj;
+};
+struct MatOut {
+  cplx* base;
+  long rs, cs, sb;
+};
+
+// Householder QR of batched m x n matrices (any shape), k = min(m, n).
+// Writes R (k x n, upper trapezoidal) to `R` and, when Q.base != nullptr,
+// the explicit Q (m x k, orthonormal columns) to `Q`.  `ws` must hold
+// batch * (m*n + m*k + k) complex entries.
+void qr(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
+        hipStream_t s);
+size_t qr_ws(int batch, int m, int n);
+
+// One-sided Jacobi SVD of batched m x n matrices with m >= n:
+// A = U diag(S) V^H with U (m x n) orthonormal columns, V (n x n) unitary,
+// S descending.  `ws` must hold batch * (m*n + n*n) complex entries.
+void svd(int batch, int m, int n, MatView A, MatOut U, double* S, MatOut V,
+         cplx* ws, hipStream_t s);
+size_t svd_ws(int batch, int m, int n);
+
+// Complex standard normal numbers (Philox4x32-10 counter generator +
+// Box-Muller), entry e of the stream (seed, stream) at out[e], scaled.
+void gaussian(cplx* out, size_t count, uint64_t seed, uint64_t stream,
+              double scale, hipStream_t s);
+
+// Materialised TTO x TT core product:
+// Z[b][(a,c)][i][(a2,c2)] = sum_j A[a][j][i][a2] x[b][c][j][c2]
+// (A stored (rho, din, dout, rho2); diag operators pass din = 0 and A
+// stored (rho, d, rho2)).
+void tto_core_apply(int batch, int rho, int din, int dout, int rho2, int r,
+                    int r2, const cplx* A, const cplx* x, cplx* Z,
+                    hipStream_t s);
+
+// out[b] = sqrt(sum |x[b*stride + e]|^2), e < len
+void batch_norm(int batch, long len, long stride, const cplx* x,
+                double* out, hipStream_t s);
+
+// y[b][i][j] = scale * x[b][i][j]*S[b][j] for j < cols; S real per column.
+void scale_cols(int batch, int rows, int cols, long ld, long sb, cplx* x,
+                const double* S, long sS, hipStream_t s);
+
+// out = conj transpose of a (rows x cols) strided view, out row-major
+// (cols x rows_keep) keeping only the first `keep` columns of the input.
+void conj_transpose(int batch, int rows, int keep, MatView in, MatOut out,
+                    hipStream_t s);
+
+// Generic strided 2D copy with optional scale: out(i,j) = alpha * in(i,j)
+void copy2d(int batch, int rows, int cols, MatView in, MatOut out,
+            cplx alpha, hipStream_t s);
+
+// Fill count complex entries with value v.
+void fill(cplx* p, size_t count, cplx v, hipStream_t s);
+
+// out[b][i][c] = sum over p of in[b][p][i][c] * w   (sum over the middle
+// index p of length np), used by the volume averages.
+void sum_middle(int batch, int outer, int np, int inner, const cplx* in,
+                cplx* out, cplx w, hipStream_t s);
+
+void check(hipError_t e, const char* what);
+
+}  // namespace qtt

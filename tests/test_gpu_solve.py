@@ -1,0 +1,55 @@
+"""GPU parity of ls_solve (Alg. 2) against the dense basic scheme (Alg. 1)."""
+import numpy as np
+import pytest
+
+from oracle import dense as D
+import microstructures as M
+from tests.helpers import rel
+
+pytestmark = pytest.mark.gpu
+
+q = pytest.importorskip("paper_2412_11566_amd")
+
+
+def test_same_iterations_untruncated_8(ctx):
+    """Untruncated Alg. 2 equals Alg. 1 after the same number of updates."""
+    p = M.Problem("s8", 3, M.sphere(8, 0.3), [(1.0, 0.3), (10.0, 0.3)], cap=0, delta=1e-14, tol=0)
+    m = 6
+    opts = q.SolveOptions(delta=1e-14, tol=0.0, cap=0, max_iter=m, exact=True)
+    C, rep, _ = q.ls_solve(ctx, p.phase, p.lame, p.lame0, opts)
+    Cref, _ = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=0.0, fixed_iters=m)
+    assert rep.iterations == [m] * 6
+    assert rel(C, Cref) < 1e-10
+
+
+def test_homogeneous_one_iteration(ctx):
+    p = M.homogeneous(2, 3.0, 0.25)
+    lame0 = (0.7, 0.9)
+    opts = q.SolveOptions(delta=1e-12, tol=1e-12, cap=0, max_iter=5, exact=True)
+    C, rep, _ = q.ls_solve(ctx, p.phase, p.lame, lame0, opts)
+    from oracle.voigt import iso_voigt
+    assert np.abs(C - iso_voigt(*p.lame[0])).max() < 1e-12 * np.abs(C).max()
+
+
+def test_c0_exact_same_iterations(ctx):
+    """16^3 sphere, untruncated FP64 path: 1e-10 relative to Alg. 1 after
+    the same number of updates."""
+    p = M.config_c0(exact=True)
+    m = 8
+    opts = q.SolveOptions(delta=1e-14, tol=0.0, cap=0, max_iter=m, exact=True)
+    C, rep, _ = q.ls_solve(ctx, p.phase, p.lame, p.lame0, opts)
+    Cref, _ = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=0.0, fixed_iters=m)
+    assert rel(C, Cref) < 1e-10
+
+
+def test_c0_stated(ctx):
+    """16^3 sphere, cap 32, delta 1e-10, tol 1e-8: C_eff within 1e-5 of the
+    converged dense basic scheme."""
+    p = M.config_c0()
+    opts = q.SolveOptions(delta=p.delta, tol=p.tol, cap=p.cap, max_iter=500)
+    C, rep, _ = q.ls_solve(ctx, p.phase, p.lame, p.lame0, opts)
+    Cref, it = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=1e-12)
+    assert rep.status == 0
+    assert max(rep.iterations) <= 80
+    assert rel(C, Cref) < 1e-5
+    assert np.abs(C - C.T).max() < 1e-5 * np.abs(C).max()
