@@ -18,13 +18,13 @@ LIB = os.path.join(HERE, "libqtthom.so")
 HOSTLIB = os.path.join(HERE, "libqtthom_host.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "engine.hip", "host_ops.cpp", "host_capi.cpp"]
+SOURCES = ["kernels.hip", "kernels_fact.hip", "engine.hip", "host_ops.cpp", "host_capi.cpp"]
 ARCH = os.environ.get("QTTHOM_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}"]
 # Packed FP32 instructions are disabled for all device code.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
-          "-packed-fp32-ops", "-munsafe-fp-atomics"]
+          "-packed-fp32-ops"]
 
 
 def _hipcc() -> str:

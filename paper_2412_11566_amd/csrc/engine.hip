@@ -307,6 +307,23 @@ struct RoundStats {
   }
 };
 
+// Choose per-batch ranks from singular values S (host, B x kk), zero the
+// padded ones, return the common rank; accumulates discarded mass.
+static int choose_rank(std::vector<double>& S, int B, int kk, const std::vector<double>& thr, int cap,
+                       std::vector<double>& disc2) {
+  int rmax = 1;
+  std::vector<int> rb(B);
+  for (int b = 0; b < B; ++b) {
+    rb[b] = keep_rank(&S[(size_t)b * kk], kk, thr[b], cap);
+    rmax = std::max(rmax, rb[b]);
+  }
+  for (int b = 0; b < B; ++b) {
+    for (int j = rb[b]; j < kk; ++j) disc2[b] += S[(size_t)b * kk + j] * S[(size_t)b * kk + j];
+    for (int j = rb[b]; j < rmax; ++j) S[(size_t)b * kk + j] = 0.0;
+  }
+  return rmax;
+}
+
 static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* st) {
   const int L = y.L, B = y.B;
   std::vector<double> nrm(B);
@@ -321,6 +338,76 @@ static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* 
   for (int k = L - 1; k >= 1; --k) {
     const int p = y.r[k], q = y.dout[k] * y.r[k + 1];
     const int kk = std::min(p, q);
+    const int rows = y.r[k - 1] * y.dout[k - 1];
+    const long msz = (long)p * q;
+    if (kk <= 96 && std::max(p, q) <= 192) {
+      // small square factor: R of the tall orientation, Jacobi on it in LDS
+      auto R = X.buf((size_t)B * kk * kk);
+      auto U = X.buf((size_t)B * kk * kk);
+      auto Sd = X.bufd((size_t)B * kk);
+      BufP Qb;
+      if (p <= q) {
+        auto ws = X.buf(qr_ws(B, q, p));
+        ck_qr(X, B, q, p, MatView{y.core[k], 1, (long)q, msz, 1},
+              MatOut{(cplx*)R->p, (long)kk, 1, (long)kk * kk}, MatOut{nullptr, 0, 0, 0}, (cplx*)ws->p, X.s());
+        // Jacobi on R^H: left singular vectors of M
+        need(X, R->p, (long)B * kk * kk - 1, "jac in");
+        need(X, U->p, (long)B * kk * kk - 1, "jac U");
+        need(X, Sd->p, (long)B * kk - 1, "jac S", sizeof(double));
+        if (!jacobi_square(B, kk, MatView{(cplx*)R->p, 1, (long)kk, (long)kk * kk, 1},
+                           MatOut{(cplx*)U->p, (long)kk, 1, (long)kk * kk}, (double*)Sd->p, X.s()))
+          throw std::logic_error("jacobi size");
+      } else {
+        Qb = X.buf((size_t)B * p * q);
+        auto ws = X.buf(qr_ws(B, p, q));
+        ck_qr(X, B, p, q, MatView{y.core[k], (long)q, 1, msz, 0},
+              MatOut{(cplx*)R->p, (long)kk, 1, (long)kk * kk}, MatOut{(cplx*)Qb->p, (long)q, 1, msz},
+              (cplx*)ws->p, X.s());
+        need(X, R->p, (long)B * kk * kk - 1, "jac in");
+        need(X, U->p, (long)B * kk * kk - 1, "jac U");
+        need(X, Sd->p, (long)B * kk - 1, "jac S", sizeof(double));
+        if (!jacobi_square(B, kk, MatView{(cplx*)R->p, (long)kk, 1, (long)kk * kk, 0},
+                           MatOut{(cplx*)U->p, (long)kk, 1, (long)kk * kk}, (double*)Sd->p, X.s()))
+          throw std::logic_error("jacobi size");
+      }
+      std::vector<double> S((size_t)B * kk);
+      check(hipMemcpyAsync(S.data(), Sd->p, S.size() * sizeof(double), hipMemcpyDeviceToHost, X.s()), "S d2h");
+      X.sync();
+      const int rmax = choose_rank(S, B, kk, thr, cap, disc2);
+      std::vector<double> SI(S.size());
+      for (size_t e = 0; e < S.size(); ++e) SI[e] = S[e] > 0.0 ? 1.0 / S[e] : 0.0;
+      auto Sdev = X.bufd(S.size());
+      auto SIdev = X.bufd(S.size());
+      check(hipMemcpyAsync(Sdev->p, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, X.s()), "S h2d");
+      check(hipMemcpyAsync(SIdev->p, SI.data(), SI.size() * sizeof(double), hipMemcpyHostToDevice, X.s()), "S h2d");
+      auto U2 = X.buf((size_t)B * kk * kk);
+      ck_copy2d(X, B, kk, kk, MatView{(cplx*)U->p, (long)kk, 1, (long)kk * kk, 0},
+                MatOut{(cplx*)U2->p, (long)kk, 1, (long)kk * kk}, C1(), X.s());
+      ck_scale_cols(X, B, kk, rmax, kk, (long)kk * kk, (cplx*)U->p, (double*)SIdev->p, kk, X.s());
+      ck_scale_cols(X, B, kk, rmax, kk, (long)kk * kk, (cplx*)U2->p, (double*)Sdev->p, kk, X.s());
+      auto nk = X.buf((size_t)B * rmax * q);
+      auto nk1 = X.buf((size_t)B * rows * rmax);
+      if (p <= q) {
+        // new core = (U S^-1)^H M ; absorbed = U S
+        G(X, rmax, q, p, OP_C, (cplx*)U->p, kk, OP_N, y.core[k], q, (cplx*)nk->p, q, B,
+          (long)kk * kk, msz, (long)rmax * q);
+        G(X, rows, rmax, p, OP_N, y.core[k - 1], p, OP_N, (cplx*)U2->p, kk, (cplx*)nk1->p, rmax, B,
+          (long)rows * p, (long)kk * kk, (long)rows * rmax);
+      } else {
+        // M = Q R, R = U S W^H: new core = (U S^-1)^H R ; absorbed = Q U S
+        G(X, rmax, q, q, OP_C, (cplx*)U->p, kk, OP_N, (cplx*)R->p, kk, (cplx*)nk->p, q, B,
+          (long)kk * kk, (long)kk * kk, (long)rmax * q);
+        auto T = X.buf((size_t)B * p * rmax);
+        G(X, p, rmax, q, OP_N, (cplx*)Qb->p, q, OP_N, (cplx*)U2->p, kk, (cplx*)T->p, rmax, B, msz,
+          (long)kk * kk, (long)p * rmax);
+        G(X, rows, rmax, p, OP_N, y.core[k - 1], p, OP_N, (cplx*)T->p, rmax, (cplx*)nk1->p, rmax, B,
+          (long)rows * p, (long)p * rmax, (long)rows * rmax);
+      }
+      X.sync();  // host S buffers are reused next step
+      set_core(X, y, k, rmax, y.r[k + 1], nk);
+      set_core(X, y, k - 1, y.r[k - 1], rmax, nk1);
+      continue;
+    }
     auto LV = X.buf((size_t)B * p * kk);
     auto RV = X.buf((size_t)B * q * kk);
     auto Sd = X.bufd((size_t)B * kk);
@@ -328,115 +415,29 @@ static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* 
     cplx* rv = (cplx*)RV->p;
     double* sd = (double*)Sd->p;
     if (p <= q) {
-      // Jacobi on M^H (q x p): M^H = Us S Vs^H  =>  M = Vs S Us^H
       auto ws = X.buf(svd_ws(B, q, p));
-      MatView in{y.core[k], 1, (long)q, (long)p * q, 1};
-      ck_svd(X, B, q, p, in, MatOut{rv, (long)kk, 1, (long)q * kk}, sd,
-          MatOut{lv, (long)kk, 1, (long)p * kk}, (cplx*)ws->p, X.s());
+      ck_svd(X, B, q, p, MatView{y.core[k], 1, (long)q, msz, 1}, MatOut{rv, (long)kk, 1, (long)q * kk}, sd,
+             MatOut{lv, (long)kk, 1, (long)p * kk}, (cplx*)ws->p, X.s());
     } else {
       auto ws = X.buf(svd_ws(B, p, q));
-      MatView in{y.core[k], (long)q, 1, (long)p * q, 0};
-      ck_svd(X, B, p, q, in, MatOut{lv, (long)kk, 1, (long)p * kk}, sd,
-          MatOut{rv, (long)kk, 1, (long)q * kk}, (cplx*)ws->p, X.s());
+      ck_svd(X, B, p, q, MatView{y.core[k], (long)q, 1, msz, 0}, MatOut{lv, (long)kk, 1, (long)p * kk}, sd,
+             MatOut{rv, (long)kk, 1, (long)q * kk}, (cplx*)ws->p, X.s());
     }
     std::vector<double> S((size_t)B * kk);
     check(hipMemcpyAsync(S.data(), sd, S.size() * sizeof(double), hipMemcpyDeviceToHost, X.s()), "S d2h");
     X.sync();
-    int rmax = 1;
-    std::vector<int> rb(B);
-    for (int b = 0; b < B; ++b) {
-      rb[b] = keep_rank(&S[(size_t)b * kk], kk, thr[b], cap);
-      rmax = std::max(rmax, rb[b]);
-    }
-    bool pad = false;
-    for (int b = 0; b < B; ++b) {
-      for (int j = rb[b]; j < kk; ++j) disc2[b] += S[(size_t)b * kk + j] * S[(size_t)b * kk + j];
-      for (int j = rb[b]; j < rmax; ++j) { S[(size_t)b * kk + j] = 0.0; pad = true; }
-    }
-    if (pad)
-      check(hipMemcpyAsync(sd, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, X.s()), "S h2d");
-    // new core k = RV[:, :rmax]^H  (rmax x q)
+    const int rmax = choose_rank(S, B, kk, thr, cap, disc2);
+    check(hipMemcpyAsync(sd, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, X.s()), "S h2d");
     auto nk = X.buf((size_t)B * rmax * q);
     ck_conj_transpose(X, B, q, rmax, MatView{rv, (long)kk, 1, (long)q * kk, 0},
-                   MatOut{(cplx*)nk->p, (long)q, 1, (long)rmax * q}, X.s());
-    // LV[:, :rmax] * S
+                      MatOut{(cplx*)nk->p, (long)q, 1, (long)rmax * q}, X.s());
     ck_scale_cols(X, B, p, rmax, kk, (long)p * kk, lv, sd, kk, X.s());
-    const int rows = y.r[k - 1] * y.dout[k - 1];
     auto nk1 = X.buf((size_t)B * rows * rmax);
     G(X, rows, rmax, p, OP_N, y.core[k - 1], p, OP_N, lv, kk, (cplx*)nk1->p, rmax, B,
       (long)rows * p, (long)p * kk, (long)rows * rmax);
-    if (pad) X.sync();  // S host buffer reused only after the kernels consumed it
+    X.sync();
     set_core(X, y, k, rmax, y.r[k + 1], nk);
     set_core(X, y, k - 1, y.r[k - 1], rmax, nk1);
-  }
-  if (st) {
-    st->disc2 = disc2;
-    st->norm = nrm;
-  }
-}
-
-// truncation sweep (left to right) of a right-orthogonal train whose norm
-// sits in core 0
-static void truncate_lr(const Ctx& X, TT& y, double delta, int cap, RoundStats* st) {
-  const int L = y.L, B = y.B;
-  std::vector<double> nrm(B);
-  {
-    auto nb = X.bufd(B);
-    ck_batch_norm(X, B, y.celems(0), y.celems(0), y.core[0], (double*)nb->p, X.s());
-    check(hipMemcpyAsync(nrm.data(), nb->p, B * sizeof(double), hipMemcpyDeviceToHost, X.s()), "norm d2h");
-    X.sync();
-  }
-  std::vector<double> thr(B), disc2(B, 0.0);
-  for (int b = 0; b < B; ++b) thr[b] = delta / std::sqrt((double)std::max(L - 1, 1)) * nrm[b];
-  for (int k = 0; k < L - 1; ++k) {
-    const int p = y.r[k] * y.dout[k], q = y.r[k + 1];
-    const int kk = std::min(p, q);
-    auto LV = X.buf((size_t)B * p * kk);
-    auto RV = X.buf((size_t)B * q * kk);
-    auto Sd = X.bufd((size_t)B * kk);
-    cplx* lv = (cplx*)LV->p;
-    cplx* rv = (cplx*)RV->p;
-    double* sd = (double*)Sd->p;
-    if (p >= q) {
-      auto ws = X.buf(svd_ws(B, p, q));
-      MatView in{y.core[k], (long)q, 1, (long)p * q, 0};
-      ck_svd(X, B, p, q, in, MatOut{lv, (long)kk, 1, (long)p * kk}, sd,
-             MatOut{rv, (long)kk, 1, (long)q * kk}, (cplx*)ws->p, X.s());
-    } else {
-      auto ws = X.buf(svd_ws(B, q, p));
-      MatView in{y.core[k], 1, (long)q, (long)p * q, 1};
-      ck_svd(X, B, q, p, in, MatOut{rv, (long)kk, 1, (long)q * kk}, sd,
-             MatOut{lv, (long)kk, 1, (long)p * kk}, (cplx*)ws->p, X.s());
-    }
-    std::vector<double> S((size_t)B * kk);
-    check(hipMemcpyAsync(S.data(), sd, S.size() * sizeof(double), hipMemcpyDeviceToHost, X.s()), "S d2h");
-    X.sync();
-    int rmax = 1;
-    std::vector<int> rb(B);
-    for (int b = 0; b < B; ++b) {
-      rb[b] = keep_rank(&S[(size_t)b * kk], kk, thr[b], cap);
-      rmax = std::max(rmax, rb[b]);
-    }
-    bool pad = false;
-    for (int b = 0; b < B; ++b) {
-      for (int j = rb[b]; j < kk; ++j) disc2[b] += S[(size_t)b * kk + j] * S[(size_t)b * kk + j];
-      for (int j = rb[b]; j < rmax; ++j) { S[(size_t)b * kk + j] = 0.0; pad = true; }
-    }
-    if (pad)
-      check(hipMemcpyAsync(sd, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice, X.s()), "S h2d");
-    // new core k = LV[:, :rmax]  (p x rmax)
-    auto nk = X.buf((size_t)B * p * rmax);
-    ck_copy2d(X, B, p, rmax, MatView{lv, (long)kk, 1, (long)p * kk, 0},
-              MatOut{(cplx*)nk->p, (long)rmax, 1, (long)p * rmax}, C1(), X.s());
-    // next core = (RV[:, :rmax] S)^H * core_{k+1}
-    ck_scale_cols(X, B, q, rmax, kk, (long)q * kk, rv, sd, kk, X.s());
-    const int cols = y.dout[k + 1] * y.r[k + 2];
-    auto nk1 = X.buf((size_t)B * rmax * cols);
-    G(X, rmax, cols, q, OP_C, rv, kk, OP_N, y.core[k + 1], cols, (cplx*)nk1->p, cols, B,
-      (long)q * kk, (long)q * cols, (long)rmax * cols);
-    if (pad) X.sync();
-    set_core(X, y, k, y.r[k], rmax, nk);
-    set_core(X, y, k + 1, rmax, y.r[k + 2], nk1);
   }
   if (st) {
     st->disc2 = disc2;
@@ -703,6 +704,20 @@ static TTP apply_full(const Ctx& X, const TT& A, const TT& x) {
 
 static TTP op_apply(const Ctx& X, const TT& A, const TT& x, int flags, const SketchOpts& o,
                     RoundStats* st);
+static TTP identity_op(const Ctx& X, int n);
+
+// Rounding of an explicit train (e.g. a sum of two trains): with a rank cap
+// the randomized sketch (identity operator) keeps every factorisation at the
+// sketch size; without a cap (or in exact mode) the deterministic
+// QR + SVD rounding is used.
+static TTP round_any(const Ctx& X, const TTP& x, const SketchOpts& o, RoundStats* st) {
+  if (o.cap > 0 && !o.exact && x->dout[0] == 6 && (x->L - 1) % 3 == 0) {
+    auto I = identity_op(X, (x->L - 1) / 3);
+    return sketch_apply(X, *I, *x, o, st);
+  }
+  round_tt(X, *x, o.delta, o.cap, st);
+  return x;
+}
 
 // Green step of Alg. 2 in bounded factors (see qtt_green_build):
 // u = U x, s = Sd u, p = P s, q = u/(2 mu0) - (c/2) p, eps = E q.
@@ -722,7 +737,10 @@ static TTP green_chain(const Ctx& X, const TT& G, const TT& x, int flags, const 
   disc = std::max(disc, s1.rel_max());
   auto q = axpby(X, G.inv_mu0, *u, -G.c, *p);
   if (!(flags & QTT_NO_ROUND)) {
-    round_tt(X, *q, o.delta, o.cap, &s1);
+    o2.seed = o.seed * 7 + 5;
+    SketchOpts o3 = o2;
+    if (flags & QTT_EXACT) o3.exact = true;
+    q = round_any(X, q, o3, &s1);
     disc = std::max(disc, s1.rel_max());
   }
   o2.seed = o.seed * 7 + 4;
@@ -1017,8 +1035,7 @@ static SolveOut ls_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, cons
     out.disc = std::max(out.disc, st.rel_max());
     auto y = op_apply(X, *ops.S->adj, *eh, 0, sk(X, O), &st);
     out.disc = std::max(out.disc, st.rel_max());
-    auto nw = axpby(X, 1.0, *Et, -1.0, *y);
-    round_tt(X, *nw, O->delta, O->cap, &st);
+    auto nw = round_any(X, axpby(X, 1.0, *Et, -1.0, *y), sk(X, O), &st);
     out.disc = std::max(out.disc, st.rel_max());
     for (int k = 1; k < nw->L; ++k) out.max_rank = std::max(out.max_rank, nw->r[k]);
     auto d = axpby(X, 1.0, *nw, -1.0, *eps);
@@ -1448,8 +1465,7 @@ int ls_adjoint(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, const 
       u = op_apply(X, *ops.G, *u, 0, sk(X, O), nullptr);
       u = op_apply(X, *ops.S->adj, *u, 0, sk(X, O), nullptr);
       u = op_apply(X, *ops.Cd, *u, 0, sk(X, O), nullptr);
-      auto nw = axpby(X, 1.0, *Ce, -1.0, *u);
-      round_tt(X, *nw, O->delta, O->cap, nullptr);
+      auto nw = round_any(X, axpby(X, 1.0, *Ce, -1.0, *u), sk(X, O), nullptr);
       auto d = axpby(X, 1.0, *nw, -1.0, *w);
       auto dn = tt_norms(X, *d);
       w = nw;

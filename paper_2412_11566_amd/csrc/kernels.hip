@@ -284,6 +284,7 @@ size_t qr_ws(int batch, int m, int n) {
 void qr(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
         hipStream_t s) {
   if (batch <= 0 || m <= 0 || n <= 0) return;
+  if (qr_fast(batch, m, n, A, R, Q, ws, s)) return;
   hipLaunchKernelGGL(k_qr, dim3(batch), dim3(QR_NT), 0, s, m, n, A, R, Q, ws);
   check(hipGetLastError(), "qr launch");
 }
@@ -317,7 +318,7 @@ __global__ __launch_bounds__(SVD_NT) void k_svd(int m, int n, MatView A, MatOut 
 
   const int npad = n + (n & 1);
   const int npairs = npad / 2;
-  const double tol = 1e-15;
+  const double tol = 8.0 * 2.220446049250313e-16 * sqrt((double)m);
   for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();

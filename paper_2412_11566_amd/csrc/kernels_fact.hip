@@ -1,0 +1,554 @@
+// Latency-optimised factorisation kernels for the small matrices of
+// TT-rounding (one workgroup per matrix, batch = trains processed together):
+//
+//  * k_qr_reg: Householder QR with the matrix held in registers.  Lane l of
+//    every wave owns columns l, l + 64, ...; wave w owns a block of rows.
+//    Reflector norms and dot products are reduced first over the wave's
+//    rows (in registers) and then across the 8 waves through LDS; the
+//    reflector itself is broadcast through LDS.
+//  * k_jacobi_lds: one-sided Jacobi (Hestenes) on a square matrix resident
+//    in LDS; 16 lanes cooperate on a column pair with shuffle reductions,
+//    column norms are carried analytically within a sweep and recomputed
+//    at its start.
+#include "qtt_internal.h"
+
+#include <stdexcept>
+
+namespace qtt {
+
+namespace {
+
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ cplx cdotc(cplx a, cplx b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double cabs2(cplx a) { return a.x * a.x + a.y * a.y; }
+
+__device__ __forceinline__ cplx ldv(const MatView& v, long b, long i, long j) {
+  cplx a = v.base[b * v.sb + i * v.rs + j * v.cs];
+  if (v.conj) a.y = -a.y;
+  return a;
+}
+
+// QNW waves per workgroup; wave w holds rows [w*RPW, (w+1)*RPW), lane l
+// holds columns l + 64*c, c < CPL.
+template <int QNW, int RPW, int CPL>
+__global__ __launch_bounds__(QNW * 64) void k_qr_reg(int m, int n, MatView A, MatOut R, MatOut Q,
+                                                    cplx* ws) {
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int k = min(m, n);
+  cplx* V = ws + (long)b * ((long)m * k + k);
+  __shared__ cplx vsh[QNW * RPW];
+  __shared__ cplx part[QNW][64 * CPL];
+  __shared__ double pn[QNW];
+  __shared__ cplx sh_alpha, sh_tau, sh_inv;
+  __shared__ double sh_beta;
+  __shared__ cplx taus[64 * CPL];
+
+  const int row0 = w * RPW;
+  cplx a[RPW][CPL];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int row = row0 + i, col = lane + 64 * c;
+      a[i][c] = (row < m && col < n) ? ldv(A, b, row, col) : make_double2(0.0, 0.0);
+    }
+
+  for (int j = 0; j < k; ++j) {
+    const int jl = j & 63, jc = j >> 6;
+    if (lane == jl) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        if (c != jc) continue;
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          const int row = row0 + i;
+          if (row > j && row < m) s += cabs2(a[i][c]);
+          if (row == j) sh_alpha = a[i][c];
+        }
+      }
+      pn[w] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double xn2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < QNW; ++q) xn2 += pn[q];
+      const cplx alpha = sh_alpha;
+      if (xn2 == 0.0 && alpha.y == 0.0) {
+        sh_tau = make_double2(0.0, 0.0);
+        sh_inv = make_double2(0.0, 0.0);
+        sh_beta = alpha.x;
+      } else {
+        const double beta = -copysign(sqrt(cabs2(alpha) + xn2), alpha.x);
+        sh_tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        const cplx d = make_double2(alpha.x - beta, alpha.y);
+        const double dd = cabs2(d);
+        sh_inv = make_double2(d.x / dd, -d.y / dd);
+        sh_beta = beta;
+      }
+      taus[j] = sh_tau;
+      V[(long)m * k + j] = sh_tau;
+    }
+    __syncthreads();
+    const cplx tj = sh_tau;
+    if (tj.x == 0.0 && tj.y == 0.0) continue;
+    const cplx inv = sh_inv;
+    const double beta = sh_beta;
+    if (lane == jl) {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        if (c != jc) continue;
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          const int row = row0 + i;
+          if (row > j && row < m) {
+            a[i][c] = cmul(a[i][c], inv);
+            vsh[row] = a[i][c];
+            V[(long)j * m + row] = a[i][c];
+          } else if (row == j) {
+            vsh[row] = make_double2(1.0, 0.0);
+            a[i][c] = make_double2(beta, 0.0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int col = lane + 64 * c;
+      if (col > j && col < n) {
+        cplx s = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          const int row = row0 + i;
+          if (row >= j && row < m) {
+            const cplx t = cdotc(vsh[row], a[i][c]);
+            s = make_double2(s.x + t.x, s.y + t.y);
+          }
+        }
+        part[w][col] = s;
+      }
+    }
+    __syncthreads();
+    const cplx ctj = make_double2(tj.x, -tj.y);
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int col = lane + 64 * c;
+      if (col > j && col < n) {
+        cplx tot = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < QNW; ++q) tot = make_double2(tot.x + part[q][col].x, tot.y + part[q][col].y);
+        const cplx f = cmul(ctj, tot);
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          const int row = row0 + i;
+          if (row >= j && row < m) {
+            const cplx fv = cmul(f, vsh[row]);
+            a[i][c] = make_double2(a[i][c].x - fv.x, a[i][c].y - fv.y);
+          }
+        }
+      }
+    }
+  }
+  // R (k x n, upper trapezoidal)
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int row = row0 + i, col = lane + 64 * c;
+      if (row < k && col < n)
+        R.base[b * R.sb + (long)row * R.rs + (long)col * R.cs] =
+            (row <= col) ? a[i][c] : make_double2(0.0, 0.0);
+    }
+  if (Q.base == nullptr) return;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int row = row0 + i, col = lane + 64 * c;
+      a[i][c] = make_double2((row == col && col < k && row < m) ? 1.0 : 0.0, 0.0);
+    }
+  for (int j = k - 1; j >= 0; --j) {
+    const cplx tj = taus[j];
+    if (tj.x == 0.0 && tj.y == 0.0) continue;
+    for (int r = j + tid; r < m; r += QNW * 64)
+      vsh[r] = (r == j) ? make_double2(1.0, 0.0) : V[(long)j * m + r];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int col = lane + 64 * c;
+      if (col >= j && col < k) {
+        cplx s = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          const int row = row0 + i;
+          if (row >= j && row < m) {
+            const cplx t = cdotc(vsh[row], a[i][c]);
+            s = make_double2(s.x + t.x, s.y + t.y);
+          }
+        }
+        part[w][col] = s;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int col = lane + 64 * c;
+      if (col >= j && col < k) {
+        cplx tot = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < QNW; ++q) tot = make_double2(tot.x + part[q][col].x, tot.y + part[q][col].y);
+        const cplx f = cmul(tj, tot);
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          const int row = row0 + i;
+          if (row >= j && row < m) {
+            const cplx fv = cmul(f, vsh[row]);
+            a[i][c] = make_double2(a[i][c].x - fv.x, a[i][c].y - fv.y);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int row = row0 + i, col = lane + 64 * c;
+      if (row < m && col < k) Q.base[b * Q.sb + (long)row * Q.rs + (long)col * Q.cs] = a[i][c];
+    }
+}
+
+template <int QNW, int RPW, int CPL>
+bool try_qr(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q, cplx* ws,
+            hipStream_t s) {
+  if (m > QNW * RPW || n > 64 * CPL) return false;
+  hipLaunchKernelGGL((k_qr_reg<QNW, RPW, CPL>), dim3(batch), dim3(QNW * 64), 0, s, m, n, A, R, Q, ws);
+  check(hipGetLastError(), "qr_reg launch");
+  return true;
+}
+
+
+// Register QR, transposed layout: lane l holds rows l + 64*i (i < RPL),
+// wave w holds columns w*CPW + c (c < CPW).  Column norms and reflector
+// dot products are 64-lane shuffle reductions inside one wave.
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int RPL, int CPW, bool WANTQ>
+__global__ __launch_bounds__(512) void k_qr_rows(int m, int n, MatView A, MatOut R, MatOut Q,
+                                                 cplx* ws) {
+  constexpr int NW = 8;
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int k = min(m, n);
+  cplx* V = ws + (long)b * ((long)m * k + k);
+  __shared__ cplx vsh[64 * RPL];
+  __shared__ cplx taus[NW * CPW];
+  const int col0 = w * CPW;
+  cplx a[RPL][CPW];
+#pragma unroll
+  for (int i = 0; i < RPL; ++i)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int row = lane + 64 * i, col = col0 + c;
+      a[i][c] = (row < m && col < n) ? ldv(A, b, row, col) : make_double2(0.0, 0.0);
+    }
+  for (int j = 0; j < k; ++j) {
+    const int jw = j / CPW, jc = j - jw * CPW;
+    if (w == jw) {
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        if (c != jc) continue;
+        double s = 0.0;
+        cplx al = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int row = lane + 64 * i;
+          if (row > j && row < m) s += cabs2(a[i][c]);
+          if (row == j) al = a[i][c];
+        }
+        s = wsum(s);
+        al.x = wsum(al.x);
+        al.y = wsum(al.y);
+        cplx tau, inv;
+        double beta;
+        if (s == 0.0 && al.y == 0.0) {
+          tau = make_double2(0.0, 0.0);
+          inv = make_double2(0.0, 0.0);
+          beta = al.x;
+        } else {
+          beta = -copysign(sqrt(cabs2(al) + s), al.x);
+          tau = make_double2((beta - al.x) / beta, -al.y / beta);
+          const cplx d = make_double2(al.x - beta, al.y);
+          const double dd = cabs2(d);
+          inv = make_double2(d.x / dd, -d.y / dd);
+        }
+        const bool zero = (tau.x == 0.0 && tau.y == 0.0);
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int row = lane + 64 * i;
+          if (row < m) {
+            if (row > j) {
+              if (!zero) a[i][c] = cmul(a[i][c], inv);
+              vsh[row] = zero ? make_double2(0.0, 0.0) : a[i][c];
+              V[(long)j * m + row] = vsh[row];
+            } else if (row == j) {
+              vsh[row] = make_double2(1.0, 0.0);
+              a[i][c] = make_double2(beta, 0.0);
+            }
+          }
+        }
+        if (lane == 0) {
+          taus[j - 0] = tau;
+          V[(long)m * k + j] = tau;
+        }
+      }
+    }
+    __syncthreads();
+    const cplx tj = taus[j];
+    if (!(tj.x == 0.0 && tj.y == 0.0)) {
+      cplx v[RPL];
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = lane + 64 * i;
+        v[i] = (row >= j && row < m) ? vsh[row] : make_double2(0.0, 0.0);
+      }
+      const cplx ctj = make_double2(tj.x, -tj.y);
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int col = col0 + c;
+        if (col <= j || col >= n) continue;
+        double sx = 0.0, sy = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const cplx t = cdotc(v[i], a[i][c]);
+          sx += t.x;
+          sy += t.y;
+        }
+        sx = wsum(sx);
+        sy = wsum(sy);
+        const cplx f = cmul(ctj, make_double2(sx, sy));
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const cplx fv = cmul(f, v[i]);
+          a[i][c] = make_double2(a[i][c].x - fv.x, a[i][c].y - fv.y);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < RPL; ++i)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int row = lane + 64 * i, col = col0 + c;
+      if (row < k && col < n)
+        R.base[b * R.sb + (long)row * R.rs + (long)col * R.cs] =
+            (row <= col) ? a[i][c] : make_double2(0.0, 0.0);
+    }
+  if (!WANTQ || Q.base == nullptr) return;
+#pragma unroll
+  for (int i = 0; i < RPL; ++i)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int row = lane + 64 * i, col = col0 + c;
+      a[i][c] = make_double2((row == col && col < k && row < m) ? 1.0 : 0.0, 0.0);
+    }
+  __syncthreads();
+  for (int j = k - 1; j >= 0; --j) {
+    const cplx tj = taus[j];
+    if (tj.x == 0.0 && tj.y == 0.0) continue;
+    cplx v[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int row = lane + 64 * i;
+      v[i] = (row < m && row > j) ? V[(long)j * m + row]
+                                  : make_double2(row == j ? 1.0 : 0.0, 0.0);
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int col = col0 + c;
+      if (col < j || col >= k) continue;
+      double sx = 0.0, sy = 0.0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const cplx t = cdotc(v[i], a[i][c]);
+        sx += t.x;
+        sy += t.y;
+      }
+      sx = wsum(sx);
+      sy = wsum(sy);
+      const cplx f = cmul(tj, make_double2(sx, sy));
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const cplx fv = cmul(f, v[i]);
+        a[i][c] = make_double2(a[i][c].x - fv.x, a[i][c].y - fv.y);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RPL; ++i)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int row = lane + 64 * i, col = col0 + c;
+      if (row < m && col < k) Q.base[b * Q.sb + (long)row * Q.rs + (long)col * Q.cs] = a[i][c];
+    }
+}
+
+template <int RPL, int CPW, bool WANTQ = true>
+bool try_qr_rows(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q, cplx* ws,
+                 hipStream_t s) {
+  if (m > 64 * RPL || n > 8 * CPW) return false;
+  if (WANTQ != (Q.base != nullptr) && !WANTQ) return false;
+  hipLaunchKernelGGL((k_qr_rows<RPL, CPW, WANTQ>), dim3(batch), dim3(512), 0, s, m, n, A, R, Q, ws);
+  check(hipGetLastError(), "qr_rows launch");
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+constexpr int JNT = 1024;
+constexpr int JMAXN = 96;
+
+__global__ __launch_bounds__(JNT) void k_jacobi_lds(int n, MatView A, MatOut U, double* S) {
+  extern __shared__ cplx Wl[];  // n x n, column-major
+  __shared__ double nrm2[JMAXN];
+  __shared__ double sig[JMAXN];
+  __shared__ int rankpos[JMAXN];
+  __shared__ int rotated;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int g = tid >> 4, sub = tid & 15;  // 64 groups of 16 lanes
+  constexpr int NG = JNT / 16;
+  for (int e = tid; e < n * n; e += JNT) {
+    const int i = e % n, j = e / n;
+    Wl[e] = ldv(A, b, i, j);
+  }
+  __syncthreads();
+  const int npad = n + (n & 1);
+  const int npairs = npad / 2;
+  const double tol = 8.0 * 2.220446049250313e-16 * sqrt((double)n);
+  for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
+    for (int c = tid; c < n; c += JNT) {
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) s += cabs2(Wl[c * n + i]);
+      nrm2[c] = s;
+    }
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < npad - 1; ++r) {
+      for (int p = g; p < npairs; p += NG) {
+        const int pa = p, pb = npad - 1 - p;
+        int ca = pa == 0 ? 0 : ((pa - 1 + r) % (npad - 1)) + 1;
+        int cb = ((pb - 1 + r) % (npad - 1)) + 1;
+        if (ca >= n || cb >= n) continue;
+        if (ca > cb) { const int t = ca; ca = cb; cb = t; }
+        cplx* xa = Wl + ca * n;
+        cplx* xb = Wl + cb * n;
+        cplx ga = make_double2(0.0, 0.0);
+        for (int i = sub; i < n; i += 16) {
+          const cplx t = cdotc(xa[i], xb[i]);
+          ga = make_double2(ga.x + t.x, ga.y + t.y);
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+          ga.x += __shfl_xor(ga.x, o, 16);
+          ga.y += __shfl_xor(ga.y, o, 16);
+        }
+        const double al = nrm2[ca], be = nrm2[cb];
+        const double gg = sqrt(cabs2(ga));
+        if (!(gg > tol * sqrt(al * be)) || al < 1e-300 || be < 1e-300) continue;
+        const double zeta = (be - al) / (2.0 * gg);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+        const cplx ph = make_double2(ga.x / gg, -ga.y / gg);
+        for (int i = sub; i < n; i += 16) {
+          const cplx u = xa[i], wv = cmul(ph, xb[i]);
+          xa[i] = make_double2(cs * u.x - sn * wv.x, cs * u.y - sn * wv.y);
+          xb[i] = make_double2(sn * u.x + cs * wv.x, sn * u.y + cs * wv.y);
+        }
+        if (sub == 0) {
+          nrm2[ca] = al - t * gg;
+          nrm2[cb] = be + t * gg;
+          rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  for (int c = tid; c < n; c += JNT) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += cabs2(Wl[c * n + i]);
+    sig[c] = sqrt(s);
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += JNT) {
+    const double sj = sig[j];
+    int pos = 0;
+    for (int i = 0; i < n; ++i) {
+      const double si = sig[i];
+      pos += (si > sj) || (si == sj && i < j);
+    }
+    rankpos[j] = pos;
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += JNT) S[(long)b * n + rankpos[j]] = sig[j];
+  for (int e = tid; e < n * n; e += JNT) {
+    const int i = e / n, j = e % n;
+    const double sj = sig[j];
+    cplx u = Wl[j * n + i];
+    if (sj > 0.0) { u.x /= sj; u.y /= sj; }
+    else u = make_double2(0.0, 0.0);
+    U.base[b * U.sb + (long)i * U.rs + (long)rankpos[j] * U.cs] = u;
+  }
+}
+
+}  // namespace
+
+size_t qr_fast_ws(int batch, int m, int n) {
+  const long k = m < n ? m : n;
+  return (size_t)batch * ((size_t)m * k + k);
+}
+
+bool qr_fast(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, hipStream_t s) {
+  if (batch <= 0 || m <= 0 || n <= 0) return true;
+  if (n <= 64) {
+    return try_qr<8, 2, 1>(batch, m, n, A, R, Q, ws, s) || try_qr<8, 4, 1>(batch, m, n, A, R, Q, ws, s) ||
+           try_qr<8, 8, 1>(batch, m, n, A, R, Q, ws, s) || try_qr<8, 16, 1>(batch, m, n, A, R, Q, ws, s) ||
+           try_qr<8, 24, 1>(batch, m, n, A, R, Q, ws, s) || try_qr_rows<4, 8>(batch, m, n, A, R, Q, ws, s);
+  }
+  return try_qr<8, 8, 2>(batch, m, n, A, R, Q, ws, s) ||
+         try_qr_rows<2, 10>(batch, m, n, A, R, Q, ws, s) || try_qr_rows<3, 10>(batch, m, n, A, R, Q, ws, s) ||
+         try_qr_rows<2, 16>(batch, m, n, A, R, Q, ws, s) || try_qr_rows<3, 16>(batch, m, n, A, R, Q, ws, s) ||
+         (Q.base == nullptr && try_qr_rows<4, 16, false>(batch, m, n, A, R, Q, ws, s));
+}
+
+bool jacobi_square(int batch, int n, MatView A, MatOut U, double* S, hipStream_t s) {
+  if (batch <= 0 || n <= 0) return true;
+  if (n > JMAXN) return false;
+  static bool attr = false;
+  if (!attr) {
+    check(hipFuncSetAttribute((const void*)k_jacobi_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              JMAXN * JMAXN * (int)sizeof(cplx)),
+          "jacobi lds attribute");
+    attr = true;
+  }
+  const size_t shm = (size_t)n * n * sizeof(cplx);
+  hipLaunchKernelGGL(k_jacobi_lds, dim3(batch), dim3(JNT), shm, s, n, A, U, S);
+  check(hipGetLastError(), "jacobi_lds launch");
+  return true;
+}
+
+}  // namespace qtt

@@ -54,6 +54,17 @@ void qr(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
         hipStream_t s);
 size_t qr_ws(int batch, int m, int n);
 
+// Register-resident Householder QR for m <= 256, n <= 128 (see
+// kernels_fact.hip); returns false when the shape does not fit.  Uses
+// qr_fast_ws(batch, m, n) <= qr_ws(batch, m, n) workspace entries.
+bool qr_fast(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, hipStream_t s);
+size_t qr_fast_ws(int batch, int m, int n);
+
+// One-sided Jacobi of batched square n x n matrices (n <= 96) resident in
+// LDS: A V = U diag(S) with U orthonormal columns and S descending (V is not
+// formed).  Returns false when n is too large.
+bool jacobi_square(int batch, int n, MatView A, MatOut U, double* S, hipStream_t s);
+
 // One-sided Jacobi SVD of batched m x n matrices with m >= n:
 // A = U diag(S) V^H with U (m x n) orthonormal columns, V (n x n) unitary,
 // S descending.  `ws` must hold batch * (m*n + n*n) complex entries.
