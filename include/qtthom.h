@@ -225,6 +225,57 @@ int ls_adjoint(qtt_ctx* ctx, const qtt_problem* P, const qtt_solve_opts* O,
                const qtt_tensor* eps, const double* gbar, double* grad,
                qtt_report* R);
 
+/* Operator setup separated from the fixed-point loop: builds the SFFT, the
+ * Green operator and the stiffness operator of a problem once (the
+ * preprocessing of App. D) so that ls_solve_prepared times only Alg. 2.
+ * The prepared object keeps its own copies of the problem data. */
+typedef struct qtt_prepared qtt_prepared;
+int qtt_prepare(qtt_ctx* ctx, const qtt_problem* P, double delta,
+                qtt_prepared** out);
+int qtt_prepared_destroy(qtt_prepared* prep);
+/* ls_solve on a prepared problem; load cases from P->load_mask as given
+ * to qtt_prepare.  Same outputs and codes as ls_solve. */
+int ls_solve_prepared(qtt_ctx* ctx, const qtt_prepared* prep,
+                      const qtt_solve_opts* O, double* Ceff, qtt_report* R,
+                      qtt_tensor** eps_out);
+
+/* The strided batched complex FP64 GEMM that every core contraction of
+ * the path runs on (the products of App. C and the factorisations of the
+ * rounding, Alg. 3 / Sec. 2.2):
+ *   C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b],   b < batch,
+ * op(A) is M x K: op 0 (N) reads A[m*lda + k], op 1 (T) reads A[k*lda + m],
+ * op 2 (C) reads conj(A[k*lda + m]); op(B) is K x N likewise.  A, B, C are
+ * caller-owned DEVICE pointers to interleaved complex doubles, row-major,
+ * batch strides sA/sB/sC in complex elements; alpha, beta are host
+ * {re, im}.  The library cannot see the extent of caller memory: the
+ * caller guarantees every addressed element lies in its allocation.
+ * path: 0 automatic (matrix cores for M, N >= 32 and K >= 8, else vector
+ * ALU), 1 vector ALU, 2 matrix cores (QTT_EINVAL if the shape is outside
+ * its range).  Asynchronous on the context's stream.  QTT_EINVAL on null
+ * pointers, K < 1, batch outside [1, 65535] or leading dimensions smaller
+ * than a row. */
+int qtt_zgemm(qtt_ctx* ctx, int opA, int opB, int M, int N, int K,
+              const double* alpha, const void* A, long lda, const void* B,
+              long ldb, const double* beta, void* C, long ldc, int batch,
+              long sA, long sB, long sC, int path);
+
+/* Kernel statistics for roofline accounting.  When enabled, every launch
+ * of the library's kernels is bracketed by HIP events on the context's
+ * stream; qtt_stats_get synchronises and returns, for one kernel family
+ * (QTT_K_*), the number of launches, the summed event time in seconds,
+ * and the algorithmic FP64 flops and HBM bytes of those launches (counted
+ * from the operand shapes, not measured). */
+#define QTT_K_GEMM      0   /* batched complex GEMM (core contractions)     */
+#define QTT_K_QR        1   /* Householder QR                               */
+#define QTT_K_JACOBI    2   /* one-sided Jacobi SVD                         */
+#define QTT_K_APPLY     3   /* materialised TTO x TT core product           */
+#define QTT_K_OTHER     4   /* elementwise helpers, RNG                     */
+#define QTT_K_COUNT     5
+int qtt_stats_enable(qtt_ctx* ctx, int on);
+int qtt_stats_get(qtt_ctx* ctx, int family, long long* launches,
+                  double* seconds, double* flops, double* bytes);
+int qtt_stats_reset(qtt_ctx* ctx);
+
 /* Many problems in one call (the six load cases of each are batched
  * together; problems are grouped by grid size).  Ceff: host [count][36]. */
 int qtt_batch_solve(qtt_ctx* ctx, int count, const qtt_problem* Ps,

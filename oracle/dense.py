@@ -97,22 +97,43 @@ def gamma_voigt(xi: np.ndarray, lam0: float, mu0: float) -> np.ndarray:
     return out
 
 
-def gamma_table(N: int, lam0: float, mu0: float) -> np.ndarray:
+def gamma_voigt_direct(x: np.ndarray, y: np.ndarray, z: np.ndarray, lam0: float,
+                       mu0: float) -> np.ndarray:
+    """Same operator as ``gamma_voigt``, written entry by entry in Voigt form
+    on arrays of frequency components (any common shape); returns
+    (6, 6) + shape.  Used for whole grids."""
+    xs = (x, y, z)
+    n2 = x * x + y * y + z * z
+    safe = np.where(n2 > 0, n2, 1.0)
+    c = (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0))
+    d = np.eye(3)
+    out = np.empty((6, 6) + np.shape(x))
+    for I, (i, j) in enumerate(PAIRS):
+        for J, (k, l) in enumerate(PAIRS):
+            t1 = (d[k, i] * xs[l] * xs[j] + d[l, i] * xs[k] * xs[j]
+                  + d[k, j] * xs[l] * xs[i] + d[l, j] * xs[k] * xs[i]) / (4.0 * mu0 * safe)
+            t2 = c * xs[i] * xs[j] * xs[k] * xs[l] / (safe * safe)
+            out[I, J] = np.where(n2 > 0, W[I] * W[J] * (t1 - t2), 0.0)
+    return out
+
+
+def gamma_table(N, lam0: float, mu0: float) -> np.ndarray:
     """Nyquist-symmetrised Voigt Green table on the DFT grid.
 
-    Returns a complex array (6, 6, N, N, N) indexed by DFT indices
-    (numpy ``fftn`` order).  For the direct scheme it is real.
+    ``N`` is an int (cubic grid) or a shape (Nx, Ny, Nz).  Returns a complex
+    array (6, 6, Nx, Ny, Nz) indexed by DFT indices (numpy ``fftn`` order).
+    For the direct scheme it is real.
     """
-    f = frequencies(N)
-    neg = f[(-np.arange(N)) % N]                 # xi of index -idx mod N
-    out = np.empty((6, 6, N, N, N), dtype=np.complex128)
-    fy, fz = np.meshgrid(f, f, indexing="ij")
-    ny, nz = np.meshgrid(neg, neg, indexing="ij")
-    for ix in range(N):
-        xi = np.stack([np.full(N * N, f[ix]), fy.ravel(), fz.ravel()], axis=1)
-        xin = np.stack([np.full(N * N, neg[ix]), ny.ravel(), nz.ravel()], axis=1)
-        g = 0.5 * (gamma_voigt(xi, lam0, mu0) + np.conj(gamma_voigt(xin, lam0, mu0)))
-        out[:, :, ix] = g.transpose(1, 2, 0).reshape(6, 6, N, N)
+    shape = (N, N, N) if np.isscalar(N) else tuple(N)
+    f = [frequencies(n) for n in shape]
+    neg = [fa[(-np.arange(n)) % n] for fa, n in zip(f, shape)]   # xi of index -idx mod N
+    out = np.empty((6, 6) + shape, dtype=np.complex128)
+    fy, fz = np.meshgrid(f[1], f[2], indexing="ij")
+    ny, nz = np.meshgrid(neg[1], neg[2], indexing="ij")
+    for ix in range(shape[0]):
+        g = gamma_voigt_direct(np.full(fy.shape, f[0][ix]), fy, fz, lam0, mu0)
+        gn = gamma_voigt_direct(np.full(fy.shape, neg[0][ix]), ny, nz, lam0, mu0)
+        out[:, :, ix] = 0.5 * (g + np.conj(gn))
     return out
 
 
@@ -146,14 +167,14 @@ def basic_scheme(phase: np.ndarray, lame: np.ndarray, lame0, E: np.ndarray,
     Returns (eps, iterations, residual history).  ``fixed_iters`` runs exactly
     that many updates regardless of the stopping test.
     """
-    N = phase.shape[0]
+    shape = phase.shape
     lam0, mu0 = lame0
     if G is None:
-        G = gamma_table(N, lam0, mu0)
+        G = gamma_table(shape, lam0, mu0)
     dC = stiffness_per_phase(lame) - iso_voigt(lam0, mu0)[None]
     E = np.asarray(E, dtype=np.float64)
-    eps = np.broadcast_to(E[:, None, None, None], (6, N, N, N)).astype(np.complex128)
-    normE = np.linalg.norm(E) * N ** 1.5
+    eps = np.broadcast_to(E[:, None, None, None], (6,) + shape).astype(np.complex128)
+    normE = np.linalg.norm(E) * np.sqrt(phase.size)
     hist = []
     m = 0
     while True:
@@ -190,8 +211,7 @@ def effective_stiffness(phase: np.ndarray, lame: np.ndarray, lame0, tol: float,
 
     Returns (C_eff, iterations per load case[, fields]).
     """
-    N = phase.shape[0]
-    G = gamma_table(N, *lame0)
+    G = gamma_table(phase.shape, *lame0)
     C = np.zeros((6, 6))
     iters = []
     fields = []
@@ -267,8 +287,7 @@ def adjoint_fields(phase: np.ndarray, lame: np.ndarray, lame0, tol: float,
     With G = F^-1 G_h F self-adjoint and C symmetric, w_k solves the
     transpose of the forward system (I + G dC) eps = e.
     """
-    N = phase.shape[0]
-    G = gamma_table(N, *lame0)
+    G = gamma_table(phase.shape, *lame0)
     Cp = stiffness_per_phase(lame)
     dC = Cp - iso_voigt(*lame0)[None]
     out = []
@@ -276,7 +295,7 @@ def adjoint_fields(phase: np.ndarray, lame: np.ndarray, lame0, tol: float,
         e = np.zeros(6)
         e[k] = 1.0
         ce = apply_local(Cp, phase, np.broadcast_to(e[:, None, None, None],
-                                                      (6, N, N, N)).astype(np.complex128))
+                                                      (6,) + phase.shape).astype(np.complex128))
         w = ce.copy()
         nrm = np.linalg.norm(ce)
         for _ in range(max_iter):
@@ -292,8 +311,7 @@ def adjoint_fields(phase: np.ndarray, lame: np.ndarray, lame0, tol: float,
 def gradient_adjoint(phase: np.ndarray, lame: np.ndarray, lame0, fields: list,
                      adj: list) -> np.ndarray:
     """dC_kl/dtheta = <e_k . dC eps^l> - <w_k, G[dC eps^l]> (dense adjoint)."""
-    N = phase.shape[0]
-    G = gamma_table(N, *lame0)
+    G = gamma_table(phase.shape, *lame0)
     nphase = np.asarray(lame).shape[0]
     dl, dm = _dC_basis()
     total = phase.size

@@ -25,7 +25,8 @@ __all__ = [
     "QttError", "Context", "Tensor", "SolveOptions", "SolveReport",
     "tt_from_cores", "const_strain", "sfft_build", "green_build", "from_voxels",
     "sfft_apply", "tt_hadamard", "green_apply", "tt_round", "tt_norm", "tt_axpby",
-    "tt_mean_apply", "ls_solve", "ls_adjoint", "batch_solve",
+    "tt_mean_apply", "ls_solve", "ls_adjoint", "batch_solve", "Prepared", "prepare",
+    "ls_solve_prepared", "stats_enable", "stats_get", "stats_reset",
     "QTT_EXACT", "QTT_INVERSE", "QTT_NO_ROUND", "QTT_PREC_FP32", "QTT_PREC_FP64",
 ]
 
@@ -306,3 +307,81 @@ def batch_solve(ctx: Context, problems, opts: SolveOptions):
     rc = _c.lib().qtt_batch_solve(ctx.h, len(ps), arr, C.byref(o), _dp(Ceff), reps)
     ctx.check(rc, allow=(QTT_ENOCONV,))
     return Ceff.reshape(-1, 6, 6), [_report(r) for r in reps]
+
+
+class Prepared:
+    """Operators of one problem built once (qtt_prepare)."""
+
+    def __init__(self, ctx: Context, h: C.c_void_p, keep):
+        self.ctx = ctx
+        self.h = h
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _c.lib().qtt_prepared_destroy(self.h)
+            self.h = None
+
+
+def prepare(ctx: Context, phase, lame, lame0, delta: float, load_mask: int = 0x3F) -> Prepared:
+    p, keep = _problem(phase, lame, lame0, load_mask)
+    h = C.c_void_p()
+    ctx.check(_c.lib().qtt_prepare(ctx.h, C.byref(p), delta, C.byref(h)))
+    return Prepared(ctx, h, keep)
+
+
+def ls_solve_prepared(ctx: Context, prep: Prepared, opts: SolveOptions, keep_eps: bool = False):
+    o = opts.c()
+    Ceff = np.zeros(36)
+    rep = _c.Report()
+    eps = C.c_void_p()
+    rc = _c.lib().ls_solve_prepared(ctx.h, prep.h, C.byref(o), _dp(Ceff), C.byref(rep),
+                                    C.byref(eps) if keep_eps else None)
+    ctx.check(rc, allow=(QTT_ENOCONV,))
+    return Ceff.reshape(6, 6), _report(rep), (Tensor(ctx, eps) if keep_eps else None)
+
+
+def stats_enable(ctx: Context, on: bool = True):
+    ctx.check(_c.lib().qtt_stats_enable(ctx.h, int(on)))
+
+
+def stats_reset(ctx: Context):
+    ctx.check(_c.lib().qtt_stats_reset(ctx.h))
+
+
+def stats_get(ctx: Context, family: int) -> dict:
+    n = C.c_longlong()
+    sec, fl, by = C.c_double(), C.c_double(), C.c_double()
+    ctx.check(_c.lib().qtt_stats_get(ctx.h, family, C.byref(n), C.byref(sec), C.byref(fl),
+                                     C.byref(by)))
+    return {"family": _c.KERNEL_FAMILIES[family], "launches": n.value, "seconds": sec.value,
+            "flops": fl.value, "bytes": by.value}
+
+
+_OPS = {"N": 0, "T": 1, "C": 2}
+
+
+def zgemm(ctx: Context, A, B, Cm, opA: str = "N", opB: str = "N", alpha: complex = 1.0,
+          beta: complex = 0.0, path: int = 0):
+    """C[b] = alpha op(A[b]) op(B[b]) + beta C[b] on torch complex128 device
+    tensors of shape (batch, rows, cols), contiguous.  Extents are checked
+    here because the C entry point cannot see caller allocations."""
+    import torch
+    for t in (A, B, Cm):
+        if t.dtype != torch.complex128 or t.dim() != 3 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("zgemm operands: contiguous complex128 device tensors (batch, r, c)")
+    batch = Cm.shape[0]
+    if A.shape[0] != batch or B.shape[0] != batch:
+        raise ValueError("zgemm: batch mismatch")
+    M, N = Cm.shape[1], Cm.shape[2]
+    K = A.shape[2] if opA == "N" else A.shape[1]
+    if (A.shape[1] if opA == "N" else A.shape[2]) != M:
+        raise ValueError("zgemm: A does not match C")
+    if (B.shape[1] if opB == "N" else B.shape[2]) != K or (B.shape[2] if opB == "N" else B.shape[1]) != N:
+        raise ValueError("zgemm: B does not match")
+    al = np.array([complex(alpha).real, complex(alpha).imag])
+    be = np.array([complex(beta).real, complex(beta).imag])
+    ctx.check(_c.lib().qtt_zgemm(
+        ctx.h, _OPS[opA], _OPS[opB], M, N, K, _dp(al), C.c_void_p(A.data_ptr()), A.shape[2],
+        C.c_void_p(B.data_ptr()), B.shape[2], _dp(be), C.c_void_p(Cm.data_ptr()), N, batch,
+        A.shape[1] * A.shape[2], B.shape[1] * B.shape[2], M * N, path))

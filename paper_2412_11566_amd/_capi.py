@@ -86,7 +86,23 @@ SIGNATURES = {
                        C.POINTER(Report)]),
     "qtt_batch_solve": (I, [P, I, C.POINTER(Problem), C.POINTER(SolveOpts), DP,
                             C.POINTER(Report)]),
+    "qtt_prepare": (I, [P, C.POINTER(Problem), D, PP]),
+    "qtt_prepared_destroy": (I, [P]),
+    "ls_solve_prepared": (I, [P, P, C.POINTER(SolveOpts), DP, C.POINTER(Report), PP]),
+    "qtt_zgemm": (I, [P, I, I, I, I, I, DP, P, C.c_long, P, C.c_long, DP, P, C.c_long, I,
+                      C.c_long, C.c_long, C.c_long, I]),
+    "qtt_stats_enable": (I, [P, I]),
+    "qtt_stats_get": (I, [P, I, C.POINTER(C.c_longlong), DP, DP, DP]),
+    "qtt_stats_reset": (I, [P]),
 }
+
+QTT_K_GEMM = 0
+QTT_K_QR = 1
+QTT_K_JACOBI = 2
+QTT_K_APPLY = 3
+QTT_K_OTHER = 4
+KERNEL_FAMILIES = {QTT_K_GEMM: "gemm", QTT_K_QR: "qr", QTT_K_JACOBI: "jacobi",
+                   QTT_K_APPLY: "tto_apply", QTT_K_OTHER: "other"}
 
 HOST_SIGNATURES = {
     "qtt_host_qn_tto": (I, [I, D, IP, DP, C.c_size_t]),

@@ -121,6 +121,12 @@ struct qtt_tensor {
   }
 };
 
+struct qtt_stat_rec {
+  int fam;
+  hipEvent_t a, b;
+  double flops, bytes;
+};
+
 struct qtt_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -129,6 +135,19 @@ struct qtt_ctx {
   std::shared_ptr<qtt::Pool> pool;
   uint64_t sketch_counter = 0;
   std::map<int, std::shared_ptr<qtt_tensor>> ident;  // identity operator per n
+  // kernel statistics (HIP events around launches)
+  bool stats_on = false;
+  std::vector<qtt_stat_rec> pending;
+  std::vector<hipEvent_t> evfree;
+  long long st_calls[QTT_K_COUNT] = {0};
+  double st_secs[QTT_K_COUNT] = {0}, st_flops[QTT_K_COUNT] = {0}, st_bytes[QTT_K_COUNT] = {0};
+  ~qtt_ctx() {
+    for (auto& r : pending) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : evfree) (void)hipEventDestroy(e);
+  }
 };
 
 namespace qtt {
@@ -142,6 +161,29 @@ static inline cplx CR(double a) { return make_double2(a, 0.0); }
 
 struct Ctx {
   qtt_ctx* c;
+  // statistics bracket around one launch
+  hipEvent_t ev() const {
+    if (!c->evfree.empty()) {
+      hipEvent_t e = c->evfree.back();
+      c->evfree.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    check(hipEventCreate(&e), "event create");
+    return e;
+  }
+  hipEvent_t t0() const {
+    if (!c->stats_on) return nullptr;
+    hipEvent_t e = ev();
+    check(hipEventRecord(e, c->stream), "event record");
+    return e;
+  }
+  void t1(hipEvent_t a, int fam, double flops, double bytes) const {
+    if (!a) return;
+    hipEvent_t e = ev();
+    check(hipEventRecord(e, c->stream), "event record");
+    c->pending.push_back({fam, a, e, flops, bytes});
+  }
   hipStream_t s() const { return c->stream; }
   BufP buf(size_t elems) const { return std::make_shared<Buf>(c->pool, std::max<size_t>(elems, 1) * sizeof(cplx)); }
   BufP bufd(size_t n) const { return std::make_shared<Buf>(c->pool, std::max<size_t>(n, 1) * sizeof(double)); }
@@ -177,7 +219,16 @@ static void G(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long ld
     need(X, Cm, span2(M, N, ldc, 1) + spanb(nb1, sC1, nb2, sC2), "gemm C");
   }
   if (K == 0) throw std::logic_error("gemm with empty contraction");
+  hipEvent_t e = X.t0();
   gemm(g, X.s());
+  X.t1(e, QTT_K_GEMM, 8.0 * M * N * K * (double)nb1 * nb2,
+       16.0 * ((double)M * K + (double)K * N + (beta.x != 0.0 || beta.y != 0.0 ? 2.0 : 1.0) * M * N) * nb1 * nb2);
+}
+
+static double qr_flops(int m, int n, bool q) {
+  const double a = std::max(m, n), b = std::min(m, n);
+  const double f = 4.0 * (2.0 * a * b * b - 2.0 / 3.0 * b * b * b);
+  return q ? 2.0 * f : f;
 }
 
 
@@ -190,7 +241,9 @@ static void ck_qr(const Ctx& X, int B, int m, int n, MatView A, MatOut R, MatOut
   need(X, R.base, span2(k, n, R.rs, R.cs) + (B - 1) * R.sb, "qr R");
   if (Q.base) need(X, Q.base, span2(m, k, Q.rs, Q.cs) + (B - 1) * Q.sb, "qr Q");
   need(X, ws, (long)qr_ws(B, m, n) - 1, "qr ws");
+  hipEvent_t e = X.t0();
   qr(B, m, n, A, R, Q, ws, s);
+  X.t1(e, QTT_K_QR, B * qr_flops(m, n, Q.base != nullptr), 16.0 * B * ((double)m * n + (double)k * n + (Q.base ? (double)m * k : 0.0)));
 }
 static void ck_svd(const Ctx& X, int B, int m, int n, MatView A, MatOut U, double* S, MatOut V,
                    cplx* ws, hipStream_t s) {
@@ -199,7 +252,9 @@ static void ck_svd(const Ctx& X, int B, int m, int n, MatView A, MatOut U, doubl
   need(X, V.base, span2(n, n, V.rs, V.cs) + (B - 1) * V.sb, "svd V");
   need(X, S, (long)B * n - 1, "svd S", sizeof(double));
   need(X, ws, (long)svd_ws(B, m, n) - 1, "svd ws");
+  hipEvent_t e = X.t0();
   svd(B, m, n, A, U, S, V, ws, s);
+  X.t1(e, QTT_K_JACOBI, B * 4.0 * 22.0 * (double)m * n * n, 16.0 * B * (2.0 * m * n + (double)n * n));
 }
 static void ck_copy2d(const Ctx& X, int B, int rows, int cols, MatView in, MatOut out, cplx a,
                       hipStream_t s) {
@@ -239,7 +294,11 @@ static void ck_tto_core_apply(const Ctx& X, int B, int rho, int din, int dout, i
   need(X, A, (long)rho * (din > 0 ? din : 1) * dout * rho2 - 1, "apply A");
   need(X, x, (long)B * r * dx * r2 - 1, "apply x");
   need(X, Z, (long)B * rho * r * dout * rho2 * r2 - 1, "apply Z");
+  hipEvent_t e = X.t0();
   tto_core_apply(B, rho, din, dout, rho2, r, r2, A, x, Z, s);
+  const double zel = (double)B * rho * r * dout * rho2 * r2;
+  X.t1(e, QTT_K_APPLY, zel * 8.0 * (din > 0 ? din : 1),
+       16.0 * ((double)rho * (din > 0 ? din : 1) * dout * rho2 + (double)B * r * dx * r2 + zel));
 }
 static void ck_gaussian(const Ctx& X, cplx* out, size_t count, uint64_t seed, uint64_t stream,
                         double scale, hipStream_t s) {
@@ -354,9 +413,11 @@ static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* 
         need(X, R->p, (long)B * kk * kk - 1, "jac in");
         need(X, U->p, (long)B * kk * kk - 1, "jac U");
         need(X, Sd->p, (long)B * kk - 1, "jac S", sizeof(double));
+        hipEvent_t e = X.t0();
         if (!jacobi_square(B, kk, MatView{(cplx*)R->p, 1, (long)kk, (long)kk * kk, 1},
                            MatOut{(cplx*)U->p, (long)kk, 1, (long)kk * kk}, (double*)Sd->p, X.s()))
           throw std::logic_error("jacobi size");
+        X.t1(e, QTT_K_JACOBI, B * 4.0 * 22.0 * (double)kk * kk * kk, 16.0 * B * 2.0 * kk * kk);
       } else {
         Qb = X.buf((size_t)B * p * q);
         auto ws = X.buf(qr_ws(B, p, q));
@@ -366,9 +427,11 @@ static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* 
         need(X, R->p, (long)B * kk * kk - 1, "jac in");
         need(X, U->p, (long)B * kk * kk - 1, "jac U");
         need(X, Sd->p, (long)B * kk - 1, "jac S", sizeof(double));
+        hipEvent_t e = X.t0();
         if (!jacobi_square(B, kk, MatView{(cplx*)R->p, (long)kk, 1, (long)kk * kk, 0},
                            MatOut{(cplx*)U->p, (long)kk, 1, (long)kk * kk}, (double*)Sd->p, X.s()))
           throw std::logic_error("jacobi size");
+        X.t1(e, QTT_K_JACOBI, B * 4.0 * 22.0 * (double)kk * kk * kk, 16.0 * B * 2.0 * kk * kk);
       }
       std::vector<double> S((size_t)B * kk);
       check(hipMemcpyAsync(S.data(), Sd->p, S.size() * sizeof(double), hipMemcpyDeviceToHost, X.s()), "S d2h");
@@ -542,6 +605,10 @@ struct SketchOpts {
   int oversample = 16;
   bool exact = false;
   uint64_t seed = 0;
+  // keep the left-orthogonal sketch result (ranks <= cap + oversample)
+  // without the final truncated-SVD sweep: used for intermediate products
+  // whose result is immediately sketched again
+  bool no_truncate = false;
 };
 
 // Contract Mc (B, lt, rho, r) with x_k -> T1 (B, lt, rho, din, r2), then with
@@ -686,6 +753,13 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
     Mc = Mn;
     lt = kq;
   }
+  if (o.no_truncate && !o.exact && o.cap > 0) {
+    if (st) {
+      st->disc2.assign(B, 0.0);
+      st->norm.assign(B, 1.0);
+    }
+    return y;
+  }
   truncate_rl(X, *y, o.delta, o.cap, st);
   return y;
 }
@@ -744,6 +818,7 @@ static TTP green_chain(const Ctx& X, const TT& G, const TT& x, int flags, const 
     disc = std::max(disc, s1.rel_max());
   }
   o2.seed = o.seed * 7 + 4;
+  o2.no_truncate = o.no_truncate;
   auto e = op_apply(X, *G.gE, *q, flags, o2, st);
   if (st) {
     // fold the intermediate roundings into the reported maximum
@@ -1011,6 +1086,15 @@ static SketchOpts sk(const Ctx& X, const qtt_solve_opts* O) {
   return s;
 }
 
+// options for an intermediate product of the fixed-point update
+static SketchOpts ski(const Ctx& X, const qtt_solve_opts* O) {
+  SketchOpts s = sk(X, O);
+  // Truncating every product keeps the next contraction at rank <= cap;
+  // measured cheaper overall than carrying cap + oversample ranks.
+  s.no_truncate = false;
+  return s;
+}
+
 static SolveOut ls_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, const qtt_solve_opts* O,
                         const std::vector<int>& ks) {
   SolveOut out;
@@ -1027,14 +1111,10 @@ static SolveOut ls_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, cons
   int m = 0;
   while (true) {
     RoundStats st;
-    auto tau = op_apply(X, *ops.Cd, *eps, 0, sk(X, O), &st);
-    out.disc = std::max(out.disc, st.rel_max());
-    auto th = op_apply(X, *ops.S, *tau, 0, sk(X, O), &st);
-    out.disc = std::max(out.disc, st.rel_max());
-    auto eh = op_apply(X, *ops.G, *th, 0, sk(X, O), &st);
-    out.disc = std::max(out.disc, st.rel_max());
-    auto y = op_apply(X, *ops.S->adj, *eh, 0, sk(X, O), &st);
-    out.disc = std::max(out.disc, st.rel_max());
+    auto tau = op_apply(X, *ops.Cd, *eps, 0, ski(X, O), &st);
+    auto th = op_apply(X, *ops.S, *tau, 0, ski(X, O), &st);
+    auto eh = op_apply(X, *ops.G, *th, 0, ski(X, O), &st);
+    auto y = op_apply(X, *ops.S->adj, *eh, 0, ski(X, O), &st);
     auto nw = round_any(X, axpby(X, 1.0, *Et, -1.0, *y), sk(X, O), &st);
     out.disc = std::max(out.disc, st.rel_max());
     for (int k = 1; k < nw->L; ++k) out.max_rank = std::max(out.max_rank, nw->r[k]);
@@ -1086,7 +1166,43 @@ static void ceff_from(const Ctx& X, const Ops& ops, const qtt_problem* P, const 
   }
 }
 
+struct Prepared {
+  int n = 0, nphase = 0, load_mask = 0;
+  std::vector<uint8_t> phase;
+  std::vector<double> lame;
+  double lame0[2] = {0, 0};
+  double delta = 0;
+  Ops ops;
+  double seconds_setup = 0;
+  qtt_problem problem() const {
+    qtt_problem P;
+    P.n = n; P.phase = phase.data(); P.nphase = nphase; P.lame = lame.data();
+    P.lame0[0] = lame0[0]; P.lame0[1] = lame0[1]; P.load_mask = load_mask;
+    return P;
+  }
+};
+
+static void stats_collect(qtt_ctx* c) {
+  if (c->pending.empty()) return;
+  check(hipStreamSynchronize(c->stream), "stats sync");
+  for (auto& r : c->pending) {
+    float ms = 0.f;
+    check(hipEventElapsedTime(&ms, r.a, r.b), "event elapsed");
+    c->st_calls[r.fam] += 1;
+    c->st_secs[r.fam] += 1e-3 * ms;
+    c->st_flops[r.fam] += r.flops;
+    c->st_bytes[r.fam] += r.bytes;
+    c->evfree.push_back(r.a);
+    c->evfree.push_back(r.b);
+  }
+  c->pending.clear();
+}
+
 }  // namespace qtt
+
+struct qtt_prepared {
+  qtt::Prepared p;
+};
 
 // ===========================================================================
 // C ABI
@@ -1384,25 +1500,23 @@ int tt_mean_apply(qtt_ctx* c, const qtt_tensor* A, const qtt_tensor* x, double* 
   });
 }
 
-int ls_solve(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, double* Ceff,
-             qtt_report* R, qtt_tensor** eps_out) {
-  if (!c || !Ceff) return QTT_EINVAL;
+}  // extern "C"
+
+static int solve_prepared(qtt_ctx* c, const Prepared& pr, const qtt_solve_opts* O, double* Ceff,
+                          qtt_report* R, qtt_tensor** eps_out, double setup_seconds) {
   int status = QTT_OK;
-  int rc;
   auto body = [&]() {
-    check_problem(P, O);
+    const qtt_problem P = pr.problem();
+    check_problem(&P, O);
     Ctx X{c};
     std::vector<int> ks;
     for (int k = 0; k < 6; ++k)
-      if (P->load_mask & (1 << k)) ks.push_back(k);
+      if (P.load_mask & (1 << k)) ks.push_back(k);
     if (ks.empty()) throw std::invalid_argument("empty load mask");
-    const double t0 = now_s();
-    Ops ops = build_ops(X, P, O->delta);
-    X.sync();
     const double t1 = now_s();
-    SolveOut so = ls_loop(X, ops, P, O, ks);
+    SolveOut so = ls_loop(X, pr.ops, &P, O, ks);
     for (int i = 0; i < 36; ++i) Ceff[i] = 0.0;
-    ceff_from(X, ops, P, so, Ceff);
+    ceff_from(X, pr.ops, &P, so, Ceff);
     X.sync();
     const double t2 = now_s();
     if (R) {
@@ -1413,17 +1527,142 @@ int ls_solve(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, double* 
       }
       R->max_rank = so.max_rank;
       R->discarded = so.disc;
-      R->seconds_setup = t1 - t0;
+      R->seconds_setup = setup_seconds;
       R->seconds_solve = t2 - t1;
     }
     if (eps_out) *eps_out = new qtt_tensor(*so.eps);
     if (!so.converged) status = QTT_ENOCONV;
   };
-  rc = [&]() -> int { QTT_TRY(c, body()); }();
+  int rc = [&]() -> int { QTT_TRY(c, body()); }();
   if (rc == QTT_OK) rc = status;
   if (R) R->status = rc;
   return rc;
 }
+
+static Prepared make_prepared(qtt_ctx* c, const qtt_problem* P, double delta) {
+  Prepared pr;
+  pr.n = P->n; pr.nphase = P->nphase; pr.load_mask = P->load_mask;
+  const size_t NN = (size_t)1 << (3 * P->n);
+  pr.phase.assign(P->phase, P->phase + NN);
+  pr.lame.assign(P->lame, P->lame + 2 * P->nphase);
+  pr.lame0[0] = P->lame0[0];
+  pr.lame0[1] = P->lame0[1];
+  pr.delta = delta;
+  const double t0 = now_s();
+  Ctx X{c};
+  const qtt_problem Q = pr.problem();
+  pr.ops = build_ops(X, &Q, delta);
+  X.sync();
+  pr.seconds_setup = now_s() - t0;
+  return pr;
+}
+
+extern "C" {
+
+int qtt_prepare(qtt_ctx* c, const qtt_problem* P, double delta, qtt_prepared** out) {
+  if (!c || !P || !out || !P->phase || !P->lame) return QTT_EINVAL;
+  *out = nullptr;
+  QTT_TRY(c, {
+    qtt_solve_opts o{};
+    o.delta = delta;
+    o.tol = 0.0;
+    check_problem(P, &o);
+    auto* pp = new qtt_prepared();
+    try {
+      pp->p = make_prepared(c, P, delta);
+    } catch (...) {
+      delete pp;
+      throw;
+    }
+    *out = pp;
+  });
+}
+
+int qtt_prepared_destroy(qtt_prepared* pp) {
+  delete pp;
+  return QTT_OK;
+}
+
+int ls_solve_prepared(qtt_ctx* c, const qtt_prepared* pp, const qtt_solve_opts* O, double* Ceff,
+                      qtt_report* R, qtt_tensor** eps_out) {
+  if (!c || !pp || !O || !Ceff) return QTT_EINVAL;
+  return solve_prepared(c, pp->p, O, Ceff, R, eps_out, 0.0);
+}
+
+int ls_solve(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, double* Ceff,
+             qtt_report* R, qtt_tensor** eps_out) {
+  if (!c || !Ceff || !P || !O) return QTT_EINVAL;
+  Prepared pr;
+  int rc = [&]() -> int {
+    QTT_TRY(c, {
+      check_problem(P, O);
+      pr = make_prepared(c, P, O->delta);
+    });
+  }();
+  if (rc != QTT_OK) {
+    if (R) R->status = rc;
+    return rc;
+  }
+  return solve_prepared(c, pr, O, Ceff, R, eps_out, pr.seconds_setup);
+}
+
+int qtt_zgemm(qtt_ctx* c, int opA, int opB, int M, int N, int K, const double* alpha,
+              const void* A, long lda, const void* B, long ldb, const double* beta, void* Cm,
+              long ldc, int batch, long sA, long sB, long sC, int path) {
+  if (!c || !alpha || !beta || !A || !B || !Cm) return QTT_EINVAL;
+  if (M < 0 || N < 0 || K < 1 || batch < 1 || batch > 65535 || opA < 0 || opA > 2 || opB < 0 ||
+      opB > 2 || path < 0 || path > 2)
+    return QTT_EINVAL;
+  if (lda < (opA == OP_N ? K : M) || ldb < (opB == OP_N ? N : K) || ldc < N) return QTT_EINVAL;
+  QTT_TRY(c, {
+    GemmArgs g;
+    g.M = M; g.N = N; g.K = K; g.opA = opA; g.opB = opB;
+    g.A = (const cplx*)A; g.lda = lda; g.sA1 = sA; g.sA2 = 0;
+    g.B = (const cplx*)B; g.ldb = ldb; g.sB1 = sB; g.sB2 = 0;
+    g.C = (cplx*)Cm; g.ldc = ldc; g.sC1 = sC; g.sC2 = 0;
+    g.nb1 = batch; g.nb2 = 1;
+    g.alpha = make_double2(alpha[0], alpha[1]);
+    g.beta = make_double2(beta[0], beta[1]);
+    if (M == 0 || N == 0) return;
+    if (path == 0) gemm(g, c->stream);
+    else if (path == 1) gemm_vector(g, c->stream);
+    else if (!gemm_mfma(g, c->stream))
+      throw std::invalid_argument("zgemm: shape not handled by the matrix-core kernel (needs M, N >= 32, K >= 8)");
+  });
+}
+
+int qtt_stats_enable(qtt_ctx* c, int on) {
+  if (!c) return QTT_EINVAL;
+  c->stats_on = on != 0;
+  return QTT_OK;
+}
+
+int qtt_stats_get(qtt_ctx* c, int fam, long long* launches, double* seconds, double* flops,
+                  double* bytes) {
+  if (!c || fam < 0 || fam >= QTT_K_COUNT) return QTT_EINVAL;
+  QTT_TRY(c, {
+    stats_collect(c);
+    if (launches) *launches = c->st_calls[fam];
+    if (seconds) *seconds = c->st_secs[fam];
+    if (flops) *flops = c->st_flops[fam];
+    if (bytes) *bytes = c->st_bytes[fam];
+  });
+}
+
+int qtt_stats_reset(qtt_ctx* c) {
+  if (!c) return QTT_EINVAL;
+  QTT_TRY(c, {
+    stats_collect(c);
+    for (int f = 0; f < QTT_K_COUNT; ++f) {
+      c->st_calls[f] = 0;
+      c->st_secs[f] = c->st_flops[f] = c->st_bytes[f] = 0.0;
+    }
+  });
+}
+
+}  // extern "C"
+
+extern "C" {
 
 int ls_adjoint(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, const qtt_tensor* eps,
                const double* gbar, double* grad, qtt_report* R) {
@@ -1461,10 +1700,10 @@ int ls_adjoint(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, const 
     int m = 0;
     bool conv = true;
     while (true) {
-      auto u = op_apply(X, *ops.S, *w, 0, sk(X, O), nullptr);
-      u = op_apply(X, *ops.G, *u, 0, sk(X, O), nullptr);
-      u = op_apply(X, *ops.S->adj, *u, 0, sk(X, O), nullptr);
-      u = op_apply(X, *ops.Cd, *u, 0, sk(X, O), nullptr);
+      auto u = op_apply(X, *ops.S, *w, 0, ski(X, O), nullptr);
+      u = op_apply(X, *ops.G, *u, 0, ski(X, O), nullptr);
+      u = op_apply(X, *ops.S->adj, *u, 0, ski(X, O), nullptr);
+      u = op_apply(X, *ops.Cd, *u, 0, ski(X, O), nullptr);
       auto nw = round_any(X, axpby(X, 1.0, *Ce, -1.0, *u), sk(X, O), nullptr);
       auto d = axpby(X, 1.0, *nw, -1.0, *w);
       auto dn = tt_norms(X, *d);

@@ -173,6 +173,13 @@ static void launch_gemm(const GemmArgs& g, hipStream_t s) {
 void gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return;
   if (g.nb1 * (long)g.nb2 > 65535) throw std::runtime_error("gemm: batch too large");
+  if (gemm_mfma(g, s)) return;
+  gemm_vector(g, s);
+}
+
+void gemm_vector(const GemmArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return;
+  if (g.nb1 * (long)g.nb2 > 65535) throw std::runtime_error("gemm: batch too large");
   const long tiles64 = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.nb1 * g.nb2;
   if (g.M <= 16 && g.N > 32) launch_gemm<16, 64>(g, s);
   else if (g.N <= 16 && g.M > 32) launch_gemm<64, 16>(g, s);

@@ -33,6 +33,11 @@ struct GemmArgs {
   cplx alpha, beta;
 };
 void gemm(const GemmArgs& g, hipStream_t s);
+// Matrix-core path of gemm for M, N >= 32 and K >= 8 (kernels_mfma.hip);
+// returns false when the shape is left to the vector kernel.
+bool gemm_mfma(const GemmArgs& g, hipStream_t s);
+// Vector-ALU path of gemm (any shape).
+void gemm_vector(const GemmArgs& g, hipStream_t s);
 
 // Strided matrix view used by the factorisation kernels: element (i, j) of
 // batch element b is base[b*sb + i*rs + j*cs], conjugated when conj != 0.

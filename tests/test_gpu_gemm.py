@@ -1,0 +1,53 @@
+"""Batched complex GEMM (the contraction under every core product and
+factorisation) against numpy, on both the matrix-core and the vector path,
+over all operand modes, ragged tile tails and alpha/beta."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(32, 32, 8), (64, 64, 16), (70, 45, 33), (128, 256, 96), (33, 97, 130),
+          (200, 40, 9), (16, 80, 40), (80, 12, 40), (5, 7, 3)]
+
+
+def _rand(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _op(x, o):
+    return x if o == "N" else (np.swapaxes(x, 1, 2) if o == "T" else np.conj(np.swapaxes(x, 1, 2)))
+
+
+@pytest.mark.parametrize("path", [0, 1, 2])
+@pytest.mark.parametrize("ops", ["NN", "TN", "CN", "NT", "NC", "CT"])
+def test_zgemm(ctx, path, ops):
+    import torch
+    import paper_2412_11566_amd as q
+    rng = np.random.default_rng(7)
+    for (M, N, K) in SHAPES:
+        if path == 2 and (M < 32 or N < 32 or K < 8):
+            continue
+        batch = 3
+        a = _rand(rng, batch, *((M, K) if ops[0] == "N" else (K, M)))
+        b = _rand(rng, batch, *((K, N) if ops[1] == "N" else (N, K)))
+        c = _rand(rng, batch, M, N)
+        alpha, beta = 0.5 - 1.25j, (0.0 if M % 2 else 0.75 + 0.5j)
+        ref = alpha * (_op(a, ops[0]) @ _op(b, ops[1])) + beta * c
+        A = torch.from_numpy(a).cuda()
+        B = torch.from_numpy(b).cuda()
+        Cm = torch.from_numpy(c).cuda()
+        q.zgemm(ctx, A, B, Cm, ops[0], ops[1], alpha, beta, path)
+        out = Cm.cpu().numpy()
+        err = np.abs(out - ref).max() / (np.abs(ref).max() + 1e-300)
+        # FP64 with K-term dot products: |error| <= K u |a||b| elementwise
+        assert err < 64 * K * 2.2e-16, (M, N, K, ops, path, err)
+
+
+def test_zgemm_mfma_rejects_small(ctx):
+    import torch
+    import paper_2412_11566_amd as q
+    A = torch.zeros((1, 16, 8), dtype=torch.complex128, device="cuda")
+    B = torch.zeros((1, 8, 64), dtype=torch.complex128, device="cuda")
+    Cm = torch.zeros((1, 16, 64), dtype=torch.complex128, device="cuda")
+    with pytest.raises(q.QttError):
+        q.zgemm(ctx, A, B, Cm, path=2)

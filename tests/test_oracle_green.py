@@ -88,3 +88,12 @@ def test_voigt_helpers_roundtrip():
     assert C[0, 1] == pytest.approx(LAM0)
     assert C[3, 3] == pytest.approx(MU0)
     assert len(PAIRS) == 6
+
+
+def test_voigt_entrywise_form_equals_tensor_form():
+    rng = np.random.default_rng(5)
+    xi = rng.normal(size=(40, 3))
+    xi[0] = 0.0
+    a = D.gamma_voigt(xi, LAM0, MU0)
+    b = D.gamma_voigt_direct(xi[:, 0], xi[:, 1], xi[:, 2], LAM0, MU0)
+    assert np.abs(a - b.transpose(2, 0, 1)).max() < 1e-14
