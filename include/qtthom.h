@@ -265,12 +265,13 @@ int qtt_zgemm(qtt_ctx* ctx, int opA, int opB, int M, int N, int K,
  * (QTT_K_*), the number of launches, the summed event time in seconds,
  * and the algorithmic FP64 flops and HBM bytes of those launches (counted
  * from the operand shapes, not measured). */
-#define QTT_K_GEMM      0   /* batched complex GEMM (core contractions)     */
+#define QTT_K_GEMM      0   /* batched complex GEMM, vector ALU kernel      */
 #define QTT_K_QR        1   /* Householder QR                               */
 #define QTT_K_JACOBI    2   /* one-sided Jacobi SVD                         */
 #define QTT_K_APPLY     3   /* materialised TTO x TT core product           */
 #define QTT_K_OTHER     4   /* elementwise helpers, RNG                     */
-#define QTT_K_COUNT     5
+#define QTT_K_MFMA      5   /* batched complex GEMM on the matrix cores     */
+#define QTT_K_COUNT     6
 int qtt_stats_enable(qtt_ctx* ctx, int on);
 int qtt_stats_get(qtt_ctx* ctx, int family, long long* launches,
                   double* seconds, double* flops, double* bytes);

@@ -101,8 +101,9 @@ QTT_K_QR = 1
 QTT_K_JACOBI = 2
 QTT_K_APPLY = 3
 QTT_K_OTHER = 4
+QTT_K_MFMA = 5
 KERNEL_FAMILIES = {QTT_K_GEMM: "gemm", QTT_K_QR: "qr", QTT_K_JACOBI: "jacobi",
-                   QTT_K_APPLY: "tto_apply", QTT_K_OTHER: "other"}
+                   QTT_K_APPLY: "tto_apply", QTT_K_OTHER: "other", QTT_K_MFMA: "gemm_mfma"}
 
 HOST_SIGNATURES = {
     "qtt_host_qn_tto": (I, [I, D, IP, DP, C.c_size_t]),
@@ -132,6 +133,9 @@ _hostlib = None
 def lib() -> C.CDLL:
     global _lib
     if _lib is None:
+        # torch first: the library then binds to the HIP runtime torch has
+        # already loaded, so both share one runtime and one device context.
+        import torch  # noqa: F401
         _lib = _bind(LIB_PATH, SIGNATURES)
     return _lib
 

@@ -40,7 +40,8 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [_hipcc(), *COMMON, *DEVICE, "-x", "hip", "-c", path, "-o", obj]
     else:
-        cmd = [_hipcc(), *COMMON, "-c", path, "-o", obj]
+        # host-only C++: plain g++, so the host library pulls in no HIP runtime
+        cmd = ["g++", *COMMON, "-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -53,10 +54,10 @@ def build(verbose: bool = True) -> str:
         objs = list(ex.map(_compile, SOURCES))
     gpu_objs = [o for o in objs if not o.endswith("host_capi.o")]
     host_objs = [o for o in objs if o.endswith(("host_ops.o", "host_capi.o"))]
-    for out, parts, extra in ((LIB, gpu_objs, [f"--offload-arch={ARCH}"]),
-                              (HOSTLIB, host_objs, [])):
+    for out, parts, linker in ((LIB, gpu_objs, [_hipcc(), f"--offload-arch={ARCH}"]),
+                               (HOSTLIB, host_objs, ["g++"])):
         tmp = out + ".tmp"
-        cmd = [_hipcc(), "-shared", *extra, "-fPIC", *parts, "-o", tmp]
+        cmd = [*linker, "-shared", "-fPIC", *parts, "-o", tmp]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

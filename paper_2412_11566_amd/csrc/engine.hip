@@ -220,8 +220,8 @@ static void G(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long ld
   }
   if (K == 0) throw std::logic_error("gemm with empty contraction");
   hipEvent_t e = X.t0();
-  gemm(g, X.s());
-  X.t1(e, QTT_K_GEMM, 8.0 * M * N * K * (double)nb1 * nb2,
+  const bool mc = gemm(g, X.s());
+  X.t1(e, mc ? QTT_K_MFMA : QTT_K_GEMM, 8.0 * M * N * K * (double)nb1 * nb2,
        16.0 * ((double)M * K + (double)K * N + (beta.x != 0.0 || beta.y != 0.0 ? 2.0 : 1.0) * M * N) * nb1 * nb2);
 }
 

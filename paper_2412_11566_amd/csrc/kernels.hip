@@ -170,11 +170,12 @@ static void launch_gemm(const GemmArgs& g, hipStream_t s) {
   hipLaunchKernelGGL((k_gemm<TM, TN>), grid, dim3((TM / 4) * (TN / 4)), 0, s, g);
 }
 
-void gemm(const GemmArgs& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return;
+bool gemm(const GemmArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return false;
   if (g.nb1 * (long)g.nb2 > 65535) throw std::runtime_error("gemm: batch too large");
-  if (gemm_mfma(g, s)) return;
+  if (gemm_mfma(g, s)) return true;
   gemm_vector(g, s);
+  return false;
 }
 
 void gemm_vector(const GemmArgs& g, hipStream_t s) {

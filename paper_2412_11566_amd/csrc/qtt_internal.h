@@ -32,7 +32,8 @@ struct GemmArgs {
   int nb1, nb2;
   cplx alpha, beta;
 };
-void gemm(const GemmArgs& g, hipStream_t s);
+// Returns true when the matrix-core kernel ran, false for the vector kernel.
+bool gemm(const GemmArgs& g, hipStream_t s);
 // Matrix-core path of gemm for M, N >= 32 and K >= 8 (kernels_mfma.hip);
 // returns false when the shape is left to the vector kernel.
 bool gemm_mfma(const GemmArgs& g, hipStream_t s);
