@@ -259,6 +259,25 @@ int qtt_zgemm(qtt_ctx* ctx, int opA, int opB, int M, int N, int K,
               long ldb, const double* beta, void* C, long ldc, int batch,
               long sA, long sB, long sC, int path);
 
+/* The two small dense factorisations of TT-rounding (Sec. 2.2, Alg. 3),
+ * exposed for direct testing and timing.  Device pointers, interleaved
+ * complex doubles, row-major, batch stride = one matrix, caller-owned.
+ *
+ * qtt_zqr: Householder QR of batch m x n matrices A (k = min(m, n)):
+ * R (k x n, upper trapezoidal, real diagonal) and, if Q != NULL, Q (m x k,
+ * orthonormal columns) with A = Q R.  path 0: the kernels the library
+ * uses (register-resident where the shape fits), 1: the global-memory
+ * kernel.  Synchronises the stream before returning.
+ *
+ * qtt_zjacobi: one-sided Jacobi of batch n x n matrices A (n <= 96):
+ * A V = U diag(S) with U (n x n) orthonormal columns for the nonzero S
+ * (zero columns otherwise) and S (batch x n) descending; V is not formed.
+ * QTT_EINVAL for n > 96. */
+int qtt_zqr(qtt_ctx* ctx, int batch, int m, int n, const void* A, void* R,
+            void* Q, int path);
+int qtt_zjacobi(qtt_ctx* ctx, int batch, int n, const void* A, void* U,
+                double* S);
+
 /* Kernel statistics for roofline accounting.  When enabled, every launch
  * of the library's kernels is bracketed by HIP events on the context's
  * stream; qtt_stats_get synchronises and returns, for one kernel family

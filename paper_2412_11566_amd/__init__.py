@@ -385,3 +385,43 @@ def zgemm(ctx: Context, A, B, Cm, opA: str = "N", opB: str = "N", alpha: complex
         ctx.h, _OPS[opA], _OPS[opB], M, N, K, _dp(al), C.c_void_p(A.data_ptr()), A.shape[2],
         C.c_void_p(B.data_ptr()), B.shape[2], _dp(be), C.c_void_p(Cm.data_ptr()), N, batch,
         A.shape[1] * A.shape[2], B.shape[1] * B.shape[2], M * N, path))
+
+
+def _dev3(t, name):
+    import torch
+    if t.dtype != torch.complex128 or t.dim() != 3 or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{name}: contiguous complex128 device tensor (batch, rows, cols)")
+
+
+def zqr(ctx: Context, A, R, Q=None, path: int = 0):
+    """Householder QR of a batch of matrices: A (batch, m, n) -> R (batch,
+    k, n) and optionally Q (batch, m, k), k = min(m, n)."""
+    _dev3(A, "A")
+    _dev3(R, "R")
+    batch, m, n = A.shape
+    k = min(m, n)
+    if tuple(R.shape) != (batch, k, n):
+        raise ValueError("zqr: R must be (batch, min(m, n), n)")
+    qp = None
+    if Q is not None:
+        _dev3(Q, "Q")
+        if tuple(Q.shape) != (batch, m, k):
+            raise ValueError("zqr: Q must be (batch, m, min(m, n))")
+        qp = C.c_void_p(Q.data_ptr())
+    ctx.check(_c.lib().qtt_zqr(ctx.h, batch, m, n, C.c_void_p(A.data_ptr()),
+                               C.c_void_p(R.data_ptr()), qp, path))
+
+
+def zjacobi(ctx: Context, A, U, S):
+    """One-sided Jacobi of square matrices: A (batch, n, n) -> U (batch, n,
+    n), S (batch, n) float64 descending, with A V = U diag(S)."""
+    import torch
+    _dev3(A, "A")
+    _dev3(U, "U")
+    batch, n, n2 = A.shape
+    if n != n2 or tuple(U.shape) != (batch, n, n):
+        raise ValueError("zjacobi: square A and U of the same shape")
+    if S.dtype != torch.float64 or tuple(S.shape) != (batch, n) or not S.is_contiguous() or not S.is_cuda:
+        raise ValueError("zjacobi: S must be a contiguous float64 device tensor (batch, n)")
+    ctx.check(_c.lib().qtt_zjacobi(ctx.h, batch, n, C.c_void_p(A.data_ptr()),
+                                   C.c_void_p(U.data_ptr()), C.c_void_p(S.data_ptr())))

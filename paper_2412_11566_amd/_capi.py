@@ -91,6 +91,8 @@ SIGNATURES = {
     "ls_solve_prepared": (I, [P, P, C.POINTER(SolveOpts), DP, C.POINTER(Report), PP]),
     "qtt_zgemm": (I, [P, I, I, I, I, I, DP, P, C.c_long, P, C.c_long, DP, P, C.c_long, I,
                       C.c_long, C.c_long, C.c_long, I]),
+    "qtt_zqr": (I, [P, I, I, I, P, P, P, I]),
+    "qtt_zjacobi": (I, [P, I, I, P, P, P]),
     "qtt_stats_enable": (I, [P, I]),
     "qtt_stats_get": (I, [P, I, C.POINTER(C.c_longlong), DP, DP, DP]),
     "qtt_stats_reset": (I, [P]),

@@ -293,6 +293,12 @@ void qr(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
         hipStream_t s) {
   if (batch <= 0 || m <= 0 || n <= 0) return;
   if (qr_fast(batch, m, n, A, R, Q, ws, s)) return;
+  qr_generic(batch, m, n, A, R, Q, ws, s);
+}
+
+void qr_generic(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
+                hipStream_t s) {
+  if (batch <= 0 || m <= 0 || n <= 0) return;
   hipLaunchKernelGGL(k_qr, dim3(batch), dim3(QR_NT), 0, s, m, n, A, R, Q, ws);
   check(hipGetLastError(), "qr launch");
 }

@@ -25,6 +25,19 @@ __device__ __forceinline__ cplx cdotc(cplx a, cplx b) {  // conj(a) * b
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 __device__ __forceinline__ double cabs2(cplx a) { return a.x * a.x + a.y * a.y; }
+// p += conj(x) * a and a -= f * v as four fused multiply-adds each
+__device__ __forceinline__ void cdot_acc(cplx& p, cplx x, cplx a) {
+  p.x = fma(x.x, a.x, p.x);
+  p.x = fma(x.y, a.y, p.x);
+  p.y = fma(x.x, a.y, p.y);
+  p.y = fma(-x.y, a.x, p.y);
+}
+__device__ __forceinline__ void caxpy_sub(cplx& a, cplx f, cplx v) {
+  a.x = fma(-f.x, v.x, a.x);
+  a.x = fma(f.y, v.y, a.x);
+  a.y = fma(-f.x, v.y, a.y);
+  a.y = fma(-f.y, v.x, a.y);
+}
 
 __device__ __forceinline__ cplx ldv(const MatView& v, long b, long i, long j) {
   cplx a = v.base[b * v.sb + i * v.rs + j * v.cs];
@@ -407,6 +420,235 @@ __global__ __launch_bounds__(512) void k_qr_rows(int m, int n, MatView A, MatOut
     }
 }
 
+// ---------------------------------------------------------------------------
+// Householder QR with one workgroup barrier per column.
+//
+// Wave w owns rows [w*RPW, (w+1)*RPW); lane l owns columns l + 64 c
+// (c < CPL).  Step j: every wave broadcasts column j of its own rows inside
+// the wave (wave-private LDS) and forms partial inner products
+// sum_r conj(x_r) a[r][col] over its rows r > j for every column; the wave
+// holding row j publishes that row.  After the single barrier every thread
+// sums the partials and rebuilds the same reflector (norm, beta, tau) from
+// them, so the reflector needs no broadcast of its own.  Partials and row j
+// are double-buffered across steps, which makes one barrier per step
+// sufficient.  Q is then accumulated in place (Q = H_0 ... H_{k-1} [I; 0])
+// from the reflectors left below the diagonal, again one barrier per step.
+template <int NW, int RPW, int CPL>
+__global__ __launch_bounds__(NW * 64) void k_qr_lc(int m, int n, MatView A, MatOut R, MatOut Q) {
+  constexpr int NC = 64 * CPL;
+  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  // wave index as a scalar: branches on it stay uniform (no divergent
+  // merges that would keep two copies of the register-resident matrix)
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int k = min(m, n);
+  __shared__ cplx part[2][NW][NC];
+  __shared__ cplx rowj[2][NC];
+  __shared__ cplx colb[NW][RPW];
+  __shared__ cplx taus[NC];
+  const int row0 = w * RPW;
+  cplx a[RPW][CPL];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int row = row0 + i, col = lane + 64 * c;
+      a[i][c] = (row < m && col < n) ? ldv(A, b, row, col) : make_double2(0.0, 0.0);
+    }
+
+  for (int j = 0; j < k; ++j) {
+    const int buf = j & 1, jl = j & 63, jc = j >> 6;
+    const bool live = row0 + RPW > j;  // this wave still has rows >= j
+    if (live) {
+      if (lane == jl) {
+        // static register indices only (a select between columns would
+        // turn `a` into an indexed array in scratch memory)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+          if (jc == c) {
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) colb[w][i] = a[i][c];
+          }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      cplx p[CPL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) p[c] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        const int row = row0 + i;
+        if (row > j && row < m) {
+          const cplx x = colb[w][i];
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) cdot_acc(p[c], x, a[i][c]);
+        }
+        if (row == j) {
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) rowj[buf][lane + 64 * c] = a[i][c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) part[buf][w][lane + 64 * c] = p[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) part[buf][w][lane + 64 * c] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    // the reflector, rebuilt identically by every thread
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) s += part[buf][q][j].x;
+    const cplx al = rowj[buf][j];
+    cplx tau, inv;
+    double beta;
+    if (s == 0.0 && al.y == 0.0) {
+      tau = make_double2(0.0, 0.0);
+      inv = make_double2(0.0, 0.0);
+      beta = al.x;
+    } else {
+      beta = -copysign(sqrt(cabs2(al) + s), al.x);
+      tau = make_double2((beta - al.x) / beta, -al.y / beta);
+      const cplx d = make_double2(al.x - beta, al.y);
+      const double dd = cabs2(d);
+      inv = make_double2(d.x / dd, -d.y / dd);
+    }
+    if (tid == 0) taus[j] = tau;
+    if (!live) continue;
+    // f_col = conj(tau) * v^H a_col, with v_j = 1 and v_r = x_r * inv
+    const cplx cinv = make_double2(inv.x, -inv.y), ctau = make_double2(tau.x, -tau.y);
+    cplx f[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int col = lane + 64 * c;
+      f[c] = make_double2(0.0, 0.0);
+      if (col > j && col < n) {
+        cplx P = make_double2(0.0, 0.0);
+#pragma unroll 4
+        for (int q = 0; q < NW; ++q) P = make_double2(P.x + part[buf][q][col].x, P.y + part[buf][q][col].y);
+        const cplx cp = cmul(cinv, P);
+        const cplx rj = rowj[buf][col];
+        f[c] = cmul(ctau, make_double2(cp.x + rj.x, cp.y + rj.y));
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int row = row0 + i;
+      if (row < j || row >= m) continue;
+      const cplx v = (row == j) ? make_double2(1.0, 0.0) : cmul(colb[w][i], inv);
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int col = lane + 64 * c;
+        if (col > j) {
+          caxpy_sub(a[i][c], f[c], v);
+        } else if (col == j) {
+          a[i][c] = (row == j) ? make_double2(beta, 0.0) : v;
+        }
+      }
+      // keep the scheduler from hoisting every row's LDS read (register
+      // pressure would force the matrix into scratch)
+      if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // R (k x n, upper trapezoidal)
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int row = row0 + i, col = lane + 64 * c;
+      if (row < k && col < n)
+        R.base[b * R.sb + (long)row * R.rs + (long)col * R.cs] =
+            (row <= col) ? a[i][c] : make_double2(0.0, 0.0);
+    }
+  if (Q.base == nullptr) return;
+  // in-place accumulation: clear the upper part (R is written out), keep
+  // the reflectors below the diagonal; columns >= k are not part of Q
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int row = row0 + i, col = lane + 64 * c;
+      if (row <= col || col >= k) a[i][c] = make_double2(0.0, 0.0);
+    }
+  __syncthreads();  // taus complete
+  for (int j = k - 1; j >= 0; --j) {
+    const int buf = j & 1, jl = j & 63, jc = j >> 6;
+    const bool live = row0 + RPW > j;
+    const cplx tj = taus[j];
+    if (live) {
+      // column j: publish v (rows > j), then turn it into e_j
+      if (lane == jl) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+          if (jc == c) {
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) {
+              colb[w][i] = a[i][c];
+              a[i][c] = make_double2(row0 + i == j ? 1.0 : 0.0, 0.0);
+            }
+          }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      cplx p[CPL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) p[c] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        const int row = row0 + i;
+        if (row < j || row >= m) continue;
+        const cplx v = (row == j) ? make_double2(1.0, 0.0) : colb[w][i];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) cdot_acc(p[c], v, a[i][c]);
+      }
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) part[buf][w][lane + 64 * c] = p[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) part[buf][w][lane + 64 * c] = make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    if (!live || (tj.x == 0.0 && tj.y == 0.0)) continue;
+    cplx f[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int col = lane + 64 * c;
+      cplx P = make_double2(0.0, 0.0);
+      if (col >= j && col < k) {
+#pragma unroll 4
+        for (int q = 0; q < NW; ++q) P = make_double2(P.x + part[buf][q][col].x, P.y + part[buf][q][col].y);
+      }
+      f[c] = cmul(tj, P);
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int row = row0 + i;
+      if (row < j || row >= m) continue;
+      const cplx v = (row == j) ? make_double2(1.0, 0.0) : colb[w][i];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) caxpy_sub(a[i][c], f[c], v);
+      if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RPW; ++i)
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int row = row0 + i, col = lane + 64 * c;
+      if (row < m && col < k) Q.base[b * Q.sb + (long)row * Q.rs + (long)col * Q.cs] = a[i][c];
+    }
+}
+
+template <int NW, int RPW, int CPL>
+bool try_qr_lc(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q,
+               hipStream_t s) {
+  if (m > NW * RPW || n > 64 * CPL) return false;
+  hipLaunchKernelGGL((k_qr_lc<NW, RPW, CPL>), dim3(batch), dim3(NW * 64), 0, s, m, n, A, R, Q);
+  check(hipGetLastError(), "qr_lc launch");
+  return true;
+}
+
 template <int RPL, int CPW, bool WANTQ = true>
 bool try_qr_rows(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q, cplx* ws,
                  hipStream_t s) {
@@ -525,13 +767,16 @@ size_t qr_fast_ws(int batch, int m, int n) {
 bool qr_fast(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, hipStream_t s) {
   if (batch <= 0 || m <= 0 || n <= 0) return true;
   if (n <= 64) {
-    return try_qr<8, 2, 1>(batch, m, n, A, R, Q, ws, s) || try_qr<8, 4, 1>(batch, m, n, A, R, Q, ws, s) ||
-           try_qr<8, 8, 1>(batch, m, n, A, R, Q, ws, s) || try_qr<8, 16, 1>(batch, m, n, A, R, Q, ws, s) ||
-           try_qr<8, 24, 1>(batch, m, n, A, R, Q, ws, s) || try_qr_rows<4, 8>(batch, m, n, A, R, Q, ws, s);
+    if (try_qr_lc<4, 4, 1>(batch, m, n, A, R, Q, s) || try_qr_lc<4, 8, 1>(batch, m, n, A, R, Q, s) ||
+        try_qr_lc<8, 8, 1>(batch, m, n, A, R, Q, s) || try_qr_lc<8, 16, 1>(batch, m, n, A, R, Q, s) ||
+        try_qr_lc<8, 24, 1>(batch, m, n, A, R, Q, s) || try_qr_lc<8, 32, 1>(batch, m, n, A, R, Q, s))
+      return true;
+    return try_qr_rows<4, 8>(batch, m, n, A, R, Q, ws, s);
   }
-  return try_qr<8, 8, 2>(batch, m, n, A, R, Q, ws, s) ||
-         try_qr_rows<2, 10>(batch, m, n, A, R, Q, ws, s) || try_qr_rows<3, 10>(batch, m, n, A, R, Q, ws, s) ||
-         try_qr_rows<2, 16>(batch, m, n, A, R, Q, ws, s) || try_qr_rows<3, 16>(batch, m, n, A, R, Q, ws, s) ||
+  if (try_qr_lc<8, 8, 2>(batch, m, n, A, R, Q, s) || try_qr_lc<8, 16, 2>(batch, m, n, A, R, Q, s) ||
+      try_qr_lc<16, 10, 2>(batch, m, n, A, R, Q, s))
+    return true;
+  return try_qr_rows<2, 16>(batch, m, n, A, R, Q, ws, s) || try_qr_rows<3, 16>(batch, m, n, A, R, Q, ws, s) ||
          (Q.base == nullptr && try_qr_rows<4, 16, false>(batch, m, n, A, R, Q, ws, s));
 }
 

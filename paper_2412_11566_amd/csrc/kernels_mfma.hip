@@ -5,11 +5,19 @@
 // complex product is four real MFMAs per block (re*re, -im*im, re*im,
 // im*re) into separate real and imaginary accumulators.  A and B stage
 // through LDS in split real/imaginary planes, 16 complex values of K per
-// stage.  Operand lane layout of the 16x16x4 FP64 instruction:
+// stage; the next stage is fetched into registers while the matrix cores
+// work on the current one.  Operand lane layout of the 16x16x4 FP64
+// instruction:
 //   A: lane l holds A[l % 16][l / 16];  B: lane l holds B[l / 16][l % 16];
 //   D: lane l, register r holds D[4 r + l / 16][l % 16].
+//
+// Shapes with few output tiles and a long contraction (the sketch products
+// of TT-rounding: 160 x 80 outputs over K = 800) split K over workgroups;
+// each slice writes its partial sums to a workspace and a second kernel
+// adds the slices in fixed order (deterministic) and applies alpha, beta.
 #include "qtt_internal.h"
 
+#include <algorithm>
 #include <stdexcept>
 
 namespace qtt {
@@ -20,18 +28,20 @@ typedef double dv4 __attribute__((ext_vector_type(4)));
 
 constexpr int MT = 64, NT = 64, KT = 16;
 constexpr int PAD = 2;
+constexpr int NTHR = 256;
+constexpr int PER_T = MT * KT / NTHR;  // staged elements per thread and operand (4)
 
-__global__ __launch_bounds__(256) void k_zgemm_mfma(GemmArgs g) {
+__global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int kchunk) {
   __shared__ double Ar[KT][MT + PAD], Ai[KT][MT + PAD];
   __shared__ double Br[KT][NT + PAD], Bi[KT][NT + PAD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;   // wave position in the 2 x 2 grid
   const int m0 = blockIdx.y * MT, n0 = blockIdx.x * NT;
-  const int bz = blockIdx.z;
+  const int bz = blockIdx.z / ksplit, slice = blockIdx.z % ksplit;
   const int b1 = bz / g.nb2, b2 = bz % g.nb2;
   const cplx* A = g.A + b1 * g.sA1 + b2 * g.sA2;
   const cplx* B = g.B + b1 * g.sB1 + b2 * g.sB2;
-  cplx* C = g.C + b1 * g.sC1 + b2 * g.sC2;
+  const int kbeg = slice * kchunk, kend = min(g.K, kbeg + kchunk);
 
   dv4 cr[2][2], ci[2][2];
 #pragma unroll
@@ -42,41 +52,69 @@ __global__ __launch_bounds__(256) void k_zgemm_mfma(GemmArgs g) {
       ci[i][j] = dv4{0.0, 0.0, 0.0, 0.0};
     }
 
-  for (int k0 = 0; k0 < g.K; k0 += KT) {
-    // stage A (MT x KT) and B (KT x NT)
-    for (int e = tid; e < MT * KT; e += 256) {
+  cplx ra[PER_T], rb[PER_T];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < PER_T; ++t) {
+      const int e = tid + NTHR * t;
       int mm, kk;
       if (g.opA == OP_N) { kk = e % KT; mm = e / KT; }
       else { mm = e % MT; kk = e / MT; }
       const int m = m0 + mm, k = k0 + kk;
       cplx v = make_double2(0.0, 0.0);
-      if (m < g.M && k < g.K) {
+      if (m < g.M && k < kend) {
         if (g.opA == OP_N) v = A[(long)m * g.lda + k];
         else {
           v = A[(long)k * g.lda + m];
           if (g.opA == OP_C) v.y = -v.y;
         }
       }
-      Ar[kk][mm] = v.x;
-      Ai[kk][mm] = v.y;
+      ra[t] = v;
     }
-    for (int e = tid; e < NT * KT; e += 256) {
+#pragma unroll
+    for (int t = 0; t < PER_T; ++t) {
+      const int e = tid + NTHR * t;
       int nn, kk;
       if (g.opB == OP_N) { nn = e % NT; kk = e / NT; }
       else { kk = e % KT; nn = e / KT; }
       const int n = n0 + nn, k = k0 + kk;
       cplx v = make_double2(0.0, 0.0);
-      if (n < g.N && k < g.K) {
+      if (n < g.N && k < kend) {
         if (g.opB == OP_N) v = B[(long)k * g.ldb + n];
         else {
           v = B[(long)n * g.ldb + k];
           if (g.opB == OP_C) v.y = -v.y;
         }
       }
-      Br[kk][nn] = v.x;
-      Bi[kk][nn] = v.y;
+      rb[t] = v;
     }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int t = 0; t < PER_T; ++t) {
+      const int e = tid + NTHR * t;
+      int mm, kk;
+      if (g.opA == OP_N) { kk = e % KT; mm = e / KT; }
+      else { mm = e % MT; kk = e / MT; }
+      Ar[kk][mm] = ra[t].x;
+      Ai[kk][mm] = ra[t].y;
+    }
+#pragma unroll
+    for (int t = 0; t < PER_T; ++t) {
+      const int e = tid + NTHR * t;
+      int nn, kk;
+      if (g.opB == OP_N) { nn = e % NT; kk = e / NT; }
+      else { kk = e % KT; nn = e / KT; }
+      Br[kk][nn] = rb[t].x;
+      Bi[kk][nn] = rb[t].y;
+    }
+  };
+
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += KT) {
+    stage();
     __syncthreads();
+    if (k0 + KT < kend) fetch(k0 + KT);  // in flight during the MFMAs below
 #pragma unroll
     for (int k4 = 0; k4 < KT / 4; ++k4) {
       const int kk = k4 * 4 + (lane >> 4);
@@ -106,6 +144,23 @@ __global__ __launch_bounds__(256) void k_zgemm_mfma(GemmArgs g) {
     }
     __syncthreads();
   }
+
+  if (ksplit > 1) {
+    // raw partial sums of this K slice: ws[slice][bz][m][n]
+    cplx* P = g.ws + ((long)slice * g.nb1 * g.nb2 + bz) * (long)g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * 32 + i * 16 + 4 * r + (lane >> 4);
+          const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+          if (m < g.M && n < g.N) P[(long)m * g.N + n] = make_double2(cr[i][j][r], ci[i][j][r]);
+        }
+    return;
+  }
+  cplx* C = g.C + b1 * g.sC1 + b2 * g.sC2;
   const bool zb = (g.beta.x == 0.0 && g.beta.y == 0.0);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -128,14 +183,68 @@ __global__ __launch_bounds__(256) void k_zgemm_mfma(GemmArgs g) {
       }
 }
 
+// C = alpha * sum_s ws[s] + beta * C, slices added in order s = 0, 1, ...
+__global__ __launch_bounds__(256) void k_zgemm_reduce(GemmArgs g, int ksplit) {
+  const long mn = (long)g.M * g.N, nb = (long)g.nb1 * g.nb2;
+  const long total = nb * mn;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256L) {
+    const long bz = e / mn, r = e % mn;
+    const int m = (int)(r / g.N), n = (int)(r % g.N);
+    double sx = 0.0, sy = 0.0;
+    for (int s = 0; s < ksplit; ++s) {
+      const cplx p = g.ws[((long)s * nb + bz) * mn + r];
+      sx += p.x;
+      sy += p.y;
+    }
+    const int b1 = (int)(bz / g.nb2), b2 = (int)(bz % g.nb2);
+    cplx* cp = g.C + b1 * g.sC1 + b2 * g.sC2 + (long)m * g.ldc + n;
+    cplx out = make_double2(g.alpha.x * sx - g.alpha.y * sy, g.alpha.x * sy + g.alpha.y * sx);
+    if (g.beta.x != 0.0 || g.beta.y != 0.0) {
+      const cplx c0 = *cp;
+      out.x += g.beta.x * c0.x - g.beta.y * c0.y;
+      out.y += g.beta.x * c0.y + g.beta.y * c0.x;
+    }
+    *cp = out;
+  }
+}
+
 }  // namespace
 
+bool gemm_mfma_ok(int M, int N, int K) { return M >= 32 && N >= 32 && K >= 8 && (M + MT - 1) / MT <= 65535; }
+
+int gemm_ksplit(int M, int N, int K, long nbatch) {
+  if (!gemm_mfma_ok(M, N, K)) return 1;
+  const long tiles = (long)((M + MT - 1) / MT) * ((N + NT - 1) / NT) * nbatch;
+  if (tiles >= 192 || K < 4 * KT) return 1;
+  // aim at ~512 workgroups, every slice at least 2 stages of K
+  long s = std::min<long>((512 + tiles - 1) / tiles, K / (2 * KT));
+  s = std::min<long>(s, 32);
+  if (tiles * s > 65535) s = 65535 / tiles;
+  return (int)std::max<long>(1, s);
+}
+
+size_t gemm_ws_elems(const GemmArgs& g, int ksplit) {
+  return ksplit > 1 ? (size_t)ksplit * g.nb1 * g.nb2 * (size_t)g.M * g.N : 0;
+}
+
 bool gemm_mfma(const GemmArgs& g, hipStream_t s) {
-  if (g.M < 32 || g.N < 32 || g.K < 8) return false;
-  dim3 grid((g.N + NT - 1) / NT, (g.M + MT - 1) / MT, g.nb1 * g.nb2);
-  if (grid.x > 2147483647u || grid.y > 65535u) return false;
-  hipLaunchKernelGGL(k_zgemm_mfma, grid, dim3(256), 0, s, g);
+  if (!gemm_mfma_ok(g.M, g.N, g.K)) return false;
+  int ks = g.ksplit > 1 && g.ws ? g.ksplit : 1;
+  const long nb = (long)g.nb1 * g.nb2;
+  if (nb * ks > 65535) ks = 1;
+  // slice length: a multiple of the stage depth
+  const int per = (g.K + ks - 1) / ks;
+  const int kchunk = (per + KT - 1) / KT * KT;
+  ks = (g.K + kchunk - 1) / kchunk;
+  dim3 grid((g.N + NT - 1) / NT, (g.M + MT - 1) / MT, (unsigned)(nb * ks));
+  hipLaunchKernelGGL(k_zgemm_mfma, grid, dim3(NTHR), 0, s, g, ks, kchunk);
   check(hipGetLastError(), "zgemm_mfma launch");
+  if (ks > 1) {
+    const long total = nb * g.M * (long)g.N;
+    const long blocks = std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)blocks), dim3(256), 0, s, g, ks);
+    check(hipGetLastError(), "zgemm_reduce launch");
+  }
   return true;
 }
 

@@ -31,12 +31,20 @@ struct GemmArgs {
   cplx* C; long ldc, sC1, sC2;
   int nb1, nb2;
   cplx alpha, beta;
+  // split-K workspace of the matrix-core path (gemm_ws_elems entries for
+  // ksplit slices); ksplit = 1 or ws = nullptr: no split
+  cplx* ws = nullptr;
+  int ksplit = 1;
 };
 // Returns true when the matrix-core kernel ran, false for the vector kernel.
 bool gemm(const GemmArgs& g, hipStream_t s);
 // Matrix-core path of gemm for M, N >= 32 and K >= 8 (kernels_mfma.hip);
 // returns false when the shape is left to the vector kernel.
 bool gemm_mfma(const GemmArgs& g, hipStream_t s);
+// The K split the matrix-core path wants for this shape (1: none) and the
+// workspace it then needs.
+int gemm_ksplit(int M, int N, int K, long nbatch);
+size_t gemm_ws_elems(const GemmArgs& g, int ksplit);
 // Vector-ALU path of gemm (any shape).
 void gemm_vector(const GemmArgs& g, hipStream_t s);
 
@@ -59,6 +67,10 @@ struct MatOut {
 void qr(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
         hipStream_t s);
 size_t qr_ws(int batch, int m, int n);
+// The global-memory kernel behind qr() for shapes the register kernels do
+// not hold (same contract as qr).
+void qr_generic(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
+                hipStream_t s);
 
 // Register-resident Householder QR for m <= 256, n <= 128 (see
 // kernels_fact.hip); returns false when the shape does not fit.  Uses

@@ -1,0 +1,99 @@
+"""The small dense factorisations of TT-rounding (Householder QR and the
+one-sided Jacobi SVD of the square factor) against the definitions and
+numpy, on shapes that reach every kernel variant, ragged tails, wide and
+rank-deficient matrices."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+QR_SHAPES = [(6, 6), (16, 40), (30, 20), (64, 64), (50, 64), (100, 64), (128, 33), (160, 64),
+             (192, 50), (256, 64), (200, 64), (64, 100), (40, 128), (128, 80), (100, 128),
+             (160, 80), (150, 128), (160, 128), (192, 80), (300, 70), (20, 300), (1, 5), (7, 1)]
+
+
+def _rand(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _check_qr(a, R, Q, full_rank=True):
+    batch, m, n = a.shape
+    k = min(m, n)
+    scale = np.linalg.norm(a.reshape(batch, -1), axis=1)[:, None, None]
+    assert np.all(np.tril(R, -1) == 0)
+    assert np.abs(np.diagonal(R, axis1=1, axis2=2).imag).max() == 0.0
+    rec = Q @ R
+    assert np.abs(rec - a).max() / scale.max() < 1e-13 * np.sqrt(m)
+    eye = np.eye(k)[None]
+    assert np.abs(np.conj(np.swapaxes(Q, 1, 2)) @ Q - eye).max() < 1e-13 * np.sqrt(m)
+    if full_rank:
+        _, Rn = np.linalg.qr(a)
+        assert np.abs(np.abs(R) - np.abs(Rn)).max() / scale.max() < 1e-12
+
+
+@pytest.mark.parametrize("shape", QR_SHAPES)
+def test_zqr(ctx, shape):
+    import torch
+    import paper_2412_11566_amd as q
+    m, n = shape
+    k = min(m, n)
+    rng = np.random.default_rng(m * 1000 + n)
+    a = _rand(rng, 3, m, n)
+    A = torch.from_numpy(a).cuda()
+    R = torch.zeros((3, k, n), dtype=torch.complex128, device="cuda")
+    Q = torch.zeros((3, m, k), dtype=torch.complex128, device="cuda")
+    q.zqr(ctx, A, R, Q)
+    _check_qr(a, R.cpu().numpy(), Q.cpu().numpy())
+    # R alone must equal the R of the Q-forming call
+    R2 = torch.zeros_like(R)
+    q.zqr(ctx, A, R2)
+    assert torch.equal(R, R2)
+
+
+@pytest.mark.parametrize("shape", [(160, 80), (64, 40), (128, 128)])
+def test_zqr_rank_deficient_and_generic_path(ctx, shape):
+    import torch
+    import paper_2412_11566_amd as q
+    m, n = shape
+    k = min(m, n)
+    rng = np.random.default_rng(5)
+    a = _rand(rng, 2, m, 5) @ _rand(rng, 2, 5, n)
+    a[:, :, 3] = 0.0                       # an exactly zero column
+    for path in (0, 1):
+        A = torch.from_numpy(a).cuda()
+        R = torch.zeros((2, k, n), dtype=torch.complex128, device="cuda")
+        Q = torch.zeros((2, m, k), dtype=torch.complex128, device="cuda")
+        q.zqr(ctx, A, R, Q, path=path)
+        _check_qr(a, R.cpu().numpy(), Q.cpu().numpy(), full_rank=False)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 16, 33, 64, 80, 96])
+def test_zjacobi(ctx, n):
+    import torch
+    import paper_2412_11566_amd as q
+    rng = np.random.default_rng(n)
+    a = _rand(rng, 3, n, n)
+    if n >= 16:   # graded singular values down to 1e-12 in the last matrix
+        u, _, vh = np.linalg.svd(a[2])
+        a[2] = (u * np.logspace(0, -12, n)) @ vh
+    A = torch.from_numpy(a).cuda()
+    U = torch.zeros_like(A)
+    S = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+    q.zjacobi(ctx, A, U, S)
+    U, S = U.cpu().numpy(), S.cpu().numpy()
+    for b in range(3):
+        sv = np.linalg.svd(a[b], compute_uv=False)
+        assert np.all(np.diff(S[b]) <= 0)
+        assert np.abs(S[b] - sv).max() < 1e-13 * sv[0] * np.sqrt(n)
+        # U^H A A^H U = diag(S^2) and U has orthonormal columns
+        g = np.conj(U[b].T) @ a[b]
+        assert np.abs(g @ np.conj(g.T) - np.diag(S[b] ** 2)).max() < 1e-12 * sv[0] ** 2
+        assert np.abs(np.conj(U[b].T) @ U[b] - np.eye(n)).max() < 1e-12 * n
+
+
+def test_zjacobi_rejects_large(ctx):
+    import torch
+    import paper_2412_11566_amd as q
+    A = torch.zeros((1, 97, 97), dtype=torch.complex128, device="cuda")
+    with pytest.raises(q.QttError):
+        q.zjacobi(ctx, A, torch.zeros_like(A), torch.zeros((1, 97), dtype=torch.float64, device="cuda"))

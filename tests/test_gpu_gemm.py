@@ -7,7 +7,9 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(32, 32, 8), (64, 64, 16), (70, 45, 33), (128, 256, 96), (33, 97, 130),
-          (200, 40, 9), (16, 80, 40), (80, 12, 40), (5, 7, 3)]
+          (200, 40, 9), (16, 80, 40), (80, 12, 40), (5, 7, 3),
+          # long contractions over few output tiles: the split-K path
+          (160, 80, 800), (96, 40, 517), (64, 64, 2000)]
 
 
 def _rand(rng, *shape):
