@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=8, help="bits per axis (8: 256^3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gradient", action="store_true",
+                    help="skip the adjoint solve (gradient cost ratio)")
     ap.add_argument("--max-iter", type=int, default=110,
                     help="updates per load case (the cap-64 strain plateaus above tol; 110 "
                          "is the dense scheme's count to 1e-6 on this geometry)")
@@ -143,8 +145,10 @@ def main():
     t0 = time.perf_counter()
     iters = 0
     reps = []
+    eps = None
     for s in range(args.steps):
-        C, rep, _ = q.ls_solve_prepared(ctx, prep, opts)
+        eps = None
+        C, rep, eps = q.ls_solve_prepared(ctx, prep, opts, keep_eps=True)
         iters += sum(rep.iterations)
         reps.append(rep)
     torch.cuda.synchronize()
@@ -152,6 +156,20 @@ def main():
     elapsed = t1 - t0
     fam = [q.stats_get(ctx, f) for f in range(6)]
     q.stats_enable(ctx, False)
+    grad = None
+    if not args.no_gradient:
+        # adjoint LS solve + gradient of sum(C_eff) wrt (lambda, mu) of both
+        # phases, C0 fixed; same options as the forward
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        g, arep = q.ls_adjoint_prepared(ctx, prep, opts, eps, gbar=np.ones((6, 6)))
+        torch.cuda.synchronize()
+        adj_s = time.perf_counter() - ta
+        fwd_s = elapsed / args.steps
+        grad = {"fwd_s": fwd_s, "adj_s": adj_s, "grad_over_fwd": (fwd_s + adj_s) / fwd_s,
+                "adjoint_iterations": arep.iterations, "dsumC_dlame": g.tolist()}
+        log(f"adjoint {adj_s:.2f} s, (fwd + adj) / fwd = {(fwd_s + adj_s) / fwd_s:.3f}")
+    del eps
     log("iterations per load case", reps[-1].iterations, "status", reps[-1].status,
         "max rank", reps[-1].max_rank)
     for f in fam:
@@ -192,6 +210,7 @@ def main():
         "setup_seconds": setup_s,
         "roofline": roofline,
         "tto_apply": tto,
+        "gradient": grad,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

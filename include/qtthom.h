@@ -238,6 +238,12 @@ int qtt_prepared_destroy(qtt_prepared* prep);
 int ls_solve_prepared(qtt_ctx* ctx, const qtt_prepared* prep,
                       const qtt_solve_opts* O, double* Ceff, qtt_report* R,
                       qtt_tensor** eps_out);
+/* ls_adjoint on a prepared problem (the operators are not rebuilt): eps
+ * from ls_solve_prepared of the same prepared object; same outputs and
+ * codes as ls_adjoint. */
+int ls_adjoint_prepared(qtt_ctx* ctx, const qtt_prepared* prep,
+                        const qtt_solve_opts* O, const qtt_tensor* eps,
+                        const double* gbar, double* grad, qtt_report* R);
 
 /* The strided batched complex FP64 GEMM that every core contraction of
  * the path runs on (the products of App. C and the factorisations of the

@@ -425,3 +425,67 @@ def zjacobi(ctx: Context, A, U, S):
         raise ValueError("zjacobi: S must be a contiguous float64 device tensor (batch, n)")
     ctx.check(_c.lib().qtt_zjacobi(ctx.h, batch, n, C.c_void_p(A.data_ptr()),
                                    C.c_void_p(U.data_ptr()), C.c_void_p(S.data_ptr())))
+
+
+def ls_adjoint_prepared(ctx: Context, prep: Prepared, opts: SolveOptions, eps: Tensor, gbar=None):
+    """ls_adjoint on a prepared problem (operators not rebuilt); eps from
+    ls_solve_prepared(..., keep_eps=True) of the same prepared object."""
+    o = opts.c()
+    nt = 2 * prep._keep[1].shape[0]
+    rep = _c.Report()
+    if gbar is None:
+        out = np.zeros(36 * nt)
+        rc = _c.lib().ls_adjoint_prepared(ctx.h, prep.h, C.byref(o), eps.h, None, _dp(out),
+                                          C.byref(rep))
+        ctx.check(rc, allow=(QTT_ENOCONV,))
+        return out.reshape(6, 6, nt), _report(rep)
+    g = np.ascontiguousarray(gbar, dtype=np.float64).reshape(36)
+    out = np.zeros(nt)
+    rc = _c.lib().ls_adjoint_prepared(ctx.h, prep.h, C.byref(o), eps.h, _dp(g), _dp(out),
+                                      C.byref(rep))
+    ctx.check(rc, allow=(QTT_ENOCONV,))
+    return out, _report(rep)
+
+
+def _autograd_function():
+    import torch
+
+    class CeffFn(torch.autograd.Function):
+        """C_eff as a differentiable function of the phase Lame parameters.
+
+        forward(lame (nphase, 2) float64 tensor, phase, lame0, ctx, opts)
+        -> C_eff (6, 6) float64.  The forward solve keeps its strain
+        trains; backward runs the adjoint LS solve (ls_adjoint_prepared)
+        with the incoming cotangent and returns dL/dlame.  The reference
+        medium lame0 is held fixed (not differentiated)."""
+
+        @staticmethod
+        def forward(actx, lame, phase, lame0, qctx, opts):
+            lam = lame.detach().cpu().numpy().astype(np.float64)
+            prep = prepare(qctx, phase, lam, lame0, opts.delta)
+            Ceff, rep, eps = ls_solve_prepared(qctx, prep, opts, keep_eps=True)
+            actx.saved = (qctx, prep, opts, eps, lame.shape, lame.dtype, lame.device)
+            actx.report = rep
+            return torch.as_tensor(Ceff, dtype=torch.float64, device=lame.device)
+
+        @staticmethod
+        def backward(actx, gC):
+            qctx, prep, opts, eps, shape, dtype, device = actx.saved
+            g = gC.detach().cpu().numpy().astype(np.float64)
+            grad, _ = ls_adjoint_prepared(qctx, prep, opts, eps, gbar=g)
+            return (torch.as_tensor(grad.reshape(shape), dtype=dtype, device=device),
+                    None, None, None, None)
+
+    return CeffFn
+
+
+_CeffFn = None
+
+
+def ceff(lame, phase, lame0, ctx: Context, opts: SolveOptions):
+    """Differentiable C_eff: ``ceff(lame_tensor, ...)`` returns a (6, 6)
+    torch tensor whose backward is the adjoint solve."""
+    global _CeffFn
+    if _CeffFn is None:
+        _CeffFn = _autograd_function()
+    return _CeffFn.apply(lame, phase, lame0, ctx, opts)

@@ -93,6 +93,7 @@ SIGNATURES = {
                       C.c_long, C.c_long, C.c_long, I]),
     "qtt_zqr": (I, [P, I, I, I, P, P, P, I]),
     "qtt_zjacobi": (I, [P, I, I, P, P, P]),
+    "ls_adjoint_prepared": (I, [P, P, C.POINTER(SolveOpts), P, DP, DP, C.POINTER(Report)]),
     "qtt_stats_enable": (I, [P, I]),
     "qtt_stats_get": (I, [P, I, C.POINTER(C.c_longlong), DP, DP, DP]),
     "qtt_stats_reset": (I, [P]),

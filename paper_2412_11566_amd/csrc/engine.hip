@@ -1707,18 +1707,17 @@ int qtt_stats_reset(qtt_ctx* c) {
 
 extern "C" {
 
-int ls_adjoint(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, const qtt_tensor* eps,
-               const double* gbar, double* grad, qtt_report* R) {
-  if (!c || !eps || !grad || eps->kind != 0 || eps->B != 6) return QTT_EINVAL;
+// Adjoint fixed point and gradient on built operators (see ls_adjoint).
+static int adjoint_ops(qtt_ctx* c, const Ops& ops, const qtt_problem* P, const qtt_solve_opts* O,
+                       const qtt_tensor* eps, const double* gbar, double* grad, qtt_report* R,
+                       double seconds_setup) {
   int status = QTT_OK;
   auto body = [&]() {
     check_problem(P, O);
     Ctx X{c};
-    const double t0 = now_s();
-    Ops ops = build_ops(X, P, O->delta);
-    X.sync();
     const double t1 = now_s();
     const int n = P->n, np = P->nphase;
+    if (eps->L != 3 * n + 1) throw std::invalid_argument("eps does not match the problem size");
     const double NN = std::pow(2.0, 3.0 * n);
     // C e_k trains: (C - C0) : E + C0 E
     std::vector<double> E(36, 0.0), C0E(36, 0.0);
@@ -1739,6 +1738,7 @@ int ls_adjoint(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, const 
     // adjoint fixed point w = C e_k - (C - C0) : G[w],  G = S^H Gamma S
     auto w = Ce;
     std::vector<int> it(6, 0);
+    std::vector<double> res(6, 0.0);
     std::vector<char> done(6, 0);
     int m = 0;
     bool conv = true;
@@ -1758,14 +1758,20 @@ int ls_adjoint(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, const 
         if (!std::isfinite(r)) throw std::runtime_error("NaN in adjoint residual");
         if (!done[b]) {
           it[b] = m;
+          res[b] = r;
           if (r < O->tol) done[b] = 1;
         }
         all = all && done[b];
       }
+      if (verbose()) {
+        std::fprintf(stderr, "[qtthom] adjoint it %d res", m);
+        for (int b = 0; b < 6; ++b) std::fprintf(stderr, " %.3e", res[b]);
+        std::fprintf(stderr, "\n");
+      }
       if (all) break;
       if (m >= O->max_iter) { conv = false; break; }
     }
-    // gradient
+    // gradient: dC_kl/dtheta = <e_k . dC eps^l> - <w_k, G[dC eps^l]>
     const int nt = 2 * np;
     std::vector<double> J((size_t)36 * nt, 0.0);
     double Dl[36], Dm[36];
@@ -1774,13 +1780,12 @@ int ls_adjoint(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, const 
     for (int p = 0; p < np; ++p)
       for (int t = 0; t < 2; ++t) {
         auto dC = dC_op(X, ops.chi, p, t == 0 ? Dl : Dm);
-        SketchOpts se = sk(X, O);
-        auto v = op_apply(X, *dC, *eps, 0, se, nullptr);       // dC : eps^l
-        auto first = mean_apply(X, *ops.I, *v);               // <e_k . dC eps^l>
-        auto gv = op_apply(X, *ops.S, *v, 0, sk(X, O), nullptr);
-        gv = op_apply(X, *ops.G, *gv, 0, sk(X, O), nullptr);
+        auto v = op_apply(X, *dC, *eps, 0, sk(X, O), nullptr);   // dC : eps^l
+        auto first = mean_apply(X, *ops.I, *v);                 // <e_k . dC eps^l>
+        auto gv = op_apply(X, *ops.S, *v, 0, ski(X, O), nullptr);
+        gv = op_apply(X, *ops.G, *gv, 0, ski(X, O), nullptr);
         gv = op_apply(X, *ops.S->adj, *gv, 0, sk(X, O), nullptr);
-        auto gram = tt_gram(X, *w, *gv);                      // [k][l] sum conj(w_k) Gv_l
+        auto gram = tt_gram(X, *w, *gv);                        // [k][l] sum conj(w_k) Gv_l
         for (int k = 0; k < 6; ++k)
           for (int l = 0; l < 6; ++l)
             J[((size_t)k * 6 + l) * nt + 2 * p + t] =
@@ -1799,8 +1804,11 @@ int ls_adjoint(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, const 
     const double t2 = now_s();
     if (R) {
       std::memset(R, 0, sizeof(*R));
-      for (int k = 0; k < 6; ++k) R->iterations[k] = it[k];
-      R->seconds_setup = t1 - t0;
+      for (int k = 0; k < 6; ++k) {
+        R->iterations[k] = it[k];
+        R->residual[k] = res[k];
+      }
+      R->seconds_setup = seconds_setup;
       R->seconds_solve = t2 - t1;
     }
     if (!conv) status = QTT_ENOCONV;
@@ -1810,6 +1818,37 @@ int ls_adjoint(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, const 
   if (R) R->status = rc;
   return rc;
 }
+
+int ls_adjoint(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, const qtt_tensor* eps,
+               const double* gbar, double* grad, qtt_report* R) {
+  if (!c || !P || !O || !eps || !grad || eps->kind != 0 || eps->B != 6) return QTT_EINVAL;
+  Ops ops;
+  double setup = 0.0;
+  int rc = [&]() -> int {
+    QTT_TRY(c, {
+      check_problem(P, O);
+      Ctx X{c};
+      const double t0 = now_s();
+      ops = build_ops(X, P, O->delta);
+      X.sync();
+      setup = now_s() - t0;
+    });
+  }();
+  if (rc != QTT_OK) {
+    if (R) R->status = rc;
+    return rc;
+  }
+  return adjoint_ops(c, ops, P, O, eps, gbar, grad, R, setup);
+}
+
+int ls_adjoint_prepared(qtt_ctx* c, const qtt_prepared* pp, const qtt_solve_opts* O,
+                        const qtt_tensor* eps, const double* gbar, double* grad, qtt_report* R) {
+  if (!c || !pp || !O || !eps || !grad || eps->kind != 0 || eps->B != 6) return QTT_EINVAL;
+  const Prepared& pr = pp->p;
+  qtt_problem P = pr.problem();
+  return adjoint_ops(c, pr.ops, &P, O, eps, gbar, grad, R, pr.seconds_setup);
+}
+
 
 int qtt_batch_solve(qtt_ctx* c, int count, const qtt_problem* Ps, const qtt_solve_opts* O,
                     double* Ceff, qtt_report* Rs) {
