@@ -25,6 +25,11 @@ __device__ __forceinline__ cplx cdotc(cplx a, cplx b) {  // conj(a) * b
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 __device__ __forceinline__ double cabs2(cplx a) { return a.x * a.x + a.y * a.y; }
+// value select (a ternary between two lvalues of a struct type selects an
+// address, which pushes register arrays into scratch memory)
+__device__ __forceinline__ cplx csel(bool c, cplx a, cplx b) {
+  return make_double2(c ? a.x : b.x, c ? a.y : b.y);
+}
 // p += conj(x) * a and a -= f * v as four fused multiply-adds each
 __device__ __forceinline__ void cdot_acc(cplx& p, cplx x, cplx a) {
   p.x = fma(x.x, a.x, p.x);
@@ -640,6 +645,278 @@ __global__ __launch_bounds__(NW * 64) void k_qr_lc(int m, int n, MatView A, MatO
     }
 }
 
+// ---------------------------------------------------------------------------
+// Householder QR over a 2D wave grid with quad reductions.
+//
+// Wave (rb, cg) holds row block rb (4*RPL rows) of column group cg (16
+// columns); inside the wave lane l = rs + 4*cl holds column cg*16 + cl at
+// rows rb*4*RPL + rs + 4*i, i < RPL.  The four lanes of a quad hold the same
+// column, so a column's inner product over the wave's rows is an in-lane
+// sum plus two DPP quad exchanges; row blocks meet in LDS.  A column group
+// whose columns are all factored drops out of the loop, so the trailing
+// work shrinks with j.  Step j: [barrier] partial inner products with
+// x = column j (published in LDS by its owners) [barrier] every thread
+// rebuilds the reflector from the partials, updates its columns, and the
+// owners of column j+1 publish it.  Q is accumulated in place afterwards
+// (Q = H_0 ... H_{k-1} [I; 0]) with the same two barriers per step.
+// bound the LDS loads kept in flight inside the row loops to a window of 4
+// rows (a compiler-only memory clobber; hoisting every row's load would
+// spill the register-resident matrix)
+#define QR2D_WINDOW(i) \
+  if (((i) & 3) == 3) asm volatile("" ::: "memory")
+
+__device__ __forceinline__ double dpp_xor1(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double dpp_xor2(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x4E, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x4E, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ cplx quad_sum(cplx p) {
+  p.x += dpp_xor1(p.x);
+  p.y += dpp_xor1(p.y);
+  p.x += dpp_xor2(p.x);
+  p.y += dpp_xor2(p.y);
+  return p;
+}
+
+template <int RB, int RPL, int CG>
+__global__ __launch_bounds__(RB * CG * 64) void k_qr_2d(int m, int n, MatView A, MatOut R, MatOut Q) {
+  constexpr int NC = 16 * CG, RBS = 4 * RPL, MR = RB * RBS;
+  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rb = w / CG, cg = w % CG;
+  const int rs = lane & 3, cl = lane >> 2;
+  const int col = cg * 16 + cl;
+  const int base = rb * RBS;  // first row of this wave's block
+  const int k = min(m, n);
+  __shared__ cplx part[RB][NC];
+  __shared__ cplx rowj[NC];
+  // xbuf holds the published column for the rows strictly below the
+  // diagonal of the current step and zero elsewhere, so the inner loops
+  // run branch-free over every row of the block
+  __shared__ cplx xbuf[2][MR];
+  __shared__ cplx taus[NC], invs[NC];
+  __shared__ double betas[NC];
+  cplx a[RPL];
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int row = base + rs + 4 * i;
+    a[i] = (row < m && col < n) ? ldv(A, b, row, col) : make_double2(0.0, 0.0);
+    QR2D_WINDOW(i);
+  }
+  const cplx zero = make_double2(0.0, 0.0);
+  if (col == 0) {
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int row = base + rs + 4 * i;
+      xbuf[0][row] = csel(row > 0 && row < m, a[i], zero);
+    }
+  }
+  for (int j = 0; j < k; ++j) {
+    const int xb = j & 1, jg = j >> 4;
+    const bool colsLive = cg >= jg;          // uniform
+    const bool rowsLive = base + RBS > j;    // uniform: block has rows >= j
+    const bool holdsRowJ = j >= base && j < base + RBS;
+    __syncthreads();
+    if (colsLive) {
+      cplx p = zero;
+      if (rowsLive) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          cdot_acc(p, xbuf[xb][base + rs + 4 * i], a[i]);
+          QR2D_WINDOW(i);
+        }
+      }
+      p = quad_sum(p);
+      if (rs == 0) part[rb][col] = p;
+      if (holdsRowJ) {
+        // one-hot sums instead of a compare-and-pick: a pick lets the
+        // compiler form a computed register index (scratch memory)
+        cplx r = zero;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const double e = (base + rs + 4 * i == j) ? 1.0 : 0.0;
+          r.x = fma(e, a[i].x, r.x);
+          r.y = fma(e, a[i].y, r.y);
+        }
+        if (j - base - rs >= 0 && ((j - base - rs) & 3) == 0) rowj[col] = r;
+      }
+    }
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) s += part[q][j].x;
+    const cplx al = rowj[j];
+    cplx tau, inv;
+    double beta;
+    if (s == 0.0 && al.y == 0.0) {
+      tau = zero;
+      inv = zero;
+      beta = al.x;
+    } else {
+      beta = -copysign(sqrt(cabs2(al) + s), al.x);
+      const cplx d = make_double2(al.x - beta, al.y);
+      const double dd = cabs2(d);
+      const double r = 1.0 / (beta * dd);  // one division: 1/beta = dd r, 1/dd = beta r
+      const double ib = dd * r, idd = beta * r;
+      tau = make_double2((beta - al.x) * ib, -al.y * ib);
+      inv = make_double2(d.x * idd, -d.y * idd);
+    }
+    if (tid == 0) {
+      taus[j] = tau;
+      invs[j] = inv;
+      betas[j] = beta;
+    }
+    if (colsLive && rowsLive) {
+      // v^H a_col = conj(inv) P + a[j][col];  a -= f v with v = x inv below
+      // the diagonal and v_j = 1:  a -= (f inv) x,  a[j] -= f
+      cplx f = zero, g = zero;
+      if (col > j && col < n) {
+        cplx P = zero;
+#pragma unroll
+        for (int q = 0; q < RB; ++q) P = make_double2(P.x + part[q][col].x, P.y + part[q][col].y);
+        const cplx cp = cmul(make_double2(inv.x, -inv.y), P);
+        const cplx rj = rowj[col];
+        f = cmul(make_double2(tau.x, -tau.y), make_double2(cp.x + rj.x, cp.y + rj.y));
+        g = cmul(f, inv);
+      }
+      // column j itself is left as x (f = g = 0 there); it becomes beta and
+      // v = x inv in one pass after the loop
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        caxpy_sub(a[i], g, xbuf[xb][base + rs + 4 * i]);
+        QR2D_WINDOW(i);
+      }
+      if (holdsRowJ) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const double e = (base + rs + 4 * i == j) ? 1.0 : 0.0;
+          a[i].x = fma(-e, f.x, a[i].x);
+          a[i].y = fma(-e, f.y, a[i].y);
+        }
+      }
+    }
+    // owners of column j + 1 publish it below its diagonal
+    if (j + 1 < k && col == j + 1) {
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = base + rs + 4 * i;
+        xbuf[xb ^ 1][row] = csel(row > j + 1 && row < m, a[i], zero);
+      }
+    }
+  }
+  __syncthreads();  // betas, invs complete
+  if (col < k) {
+    const cplx ic = invs[col];
+    const double bc = betas[col];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int row = base + rs + 4 * i;
+      const cplx v = cmul(a[i], ic);
+      a[i] = csel(row > col, v, csel(row == col, make_double2(bc, 0.0), a[i]));
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int row = base + rs + 4 * i;
+    if (row < k && col < n)
+      R.base[b * R.sb + (long)row * R.rs + (long)col * R.cs] = csel(row <= col, a[i], zero);
+    QR2D_WINDOW(i);
+  }
+  if (Q.base == nullptr) return;
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int row = base + rs + 4 * i;
+    if (row <= col || col >= k) a[i] = zero;
+  }
+  for (int j = k - 1; j >= 0; --j) {
+    const int xb = j & 1, jg = j >> 4;
+    const bool colsLive = cg >= jg;
+    const bool rowsLive = base + RBS > j;
+    const bool holdsRowJ = j >= base && j < base + RBS;
+    // column j: publish v below the diagonal, then turn it into e_j (the
+    // register update is a select, not a divergent branch)
+    if (cg == jg) {
+      const bool isJ = col == j;
+      if (isJ) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int row = base + rs + 4 * i;
+          xbuf[xb][row] = csel(row > j && row < m, a[i], zero);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = base + rs + 4 * i;
+        a[i] = csel(isJ, make_double2(row == j ? 1.0 : 0.0, 0.0), a[i]);
+      }
+    }
+    __syncthreads();
+    if (colsLive) {
+      cplx p = zero;
+      if (rowsLive) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          cdot_acc(p, xbuf[xb][base + rs + 4 * i], a[i]);
+          QR2D_WINDOW(i);
+        }
+        if (holdsRowJ) {
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const double e = (base + rs + 4 * i == j) ? 1.0 : 0.0;
+            p.x = fma(e, a[i].x, p.x);
+            p.y = fma(e, a[i].y, p.y);
+          }
+        }
+      }
+      p = quad_sum(p);
+      if (rs == 0) part[rb][col] = p;
+    }
+    __syncthreads();
+    const cplx tj = taus[j];
+    if (!colsLive || !rowsLive || (tj.x == 0.0 && tj.y == 0.0)) continue;
+    cplx f = zero;
+    if (col >= j && col < k) {
+      cplx P = zero;
+#pragma unroll
+      for (int q = 0; q < RB; ++q) P = make_double2(P.x + part[q][col].x, P.y + part[q][col].y);
+      f = cmul(tj, P);
+    }
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      caxpy_sub(a[i], f, xbuf[xb][base + rs + 4 * i]);
+      QR2D_WINDOW(i);
+    }
+    if (holdsRowJ) {
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const double e = (base + rs + 4 * i == j) ? 1.0 : 0.0;
+        a[i].x = fma(-e, f.x, a[i].x);
+        a[i].y = fma(-e, f.y, a[i].y);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int row = base + rs + 4 * i;
+    if (row < m && col < k) Q.base[b * Q.sb + (long)row * Q.rs + (long)col * Q.cs] = a[i];
+    QR2D_WINDOW(i);
+  }
+}
+
+template <int RB, int RPL, int CG>
+bool try_qr_2d(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q,
+               hipStream_t s) {
+  if (m > RB * 4 * RPL || n > 16 * CG) return false;
+  hipLaunchKernelGGL((k_qr_2d<RB, RPL, CG>), dim3(batch), dim3(RB * CG * 64), 0, s, m, n, A, R, Q);
+  check(hipGetLastError(), "qr_2d launch");
+  return true;
+}
+
 template <int NW, int RPW, int CPL>
 bool try_qr_lc(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q,
                hipStream_t s) {
@@ -764,20 +1041,38 @@ size_t qr_fast_ws(int batch, int m, int n) {
   return (size_t)batch * ((size_t)m * k + k);
 }
 
+template <int RB, int CG>
+bool qr2d_any(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q, hipStream_t s) {
+  return try_qr_2d<RB, 4, CG>(batch, m, n, A, R, Q, s) || try_qr_2d<RB, 8, CG>(batch, m, n, A, R, Q, s) ||
+         try_qr_2d<RB, 12, CG>(batch, m, n, A, R, Q, s) || try_qr_2d<RB, 14, CG>(batch, m, n, A, R, Q, s);
+}
+
 bool qr_fast(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, hipStream_t s) {
   if (batch <= 0 || m <= 0 || n <= 0) return true;
+  // 2D wave grid: RB row blocks x CG groups of 16 columns (<= 16 waves);
+  // variants that would spill registers are left out
+  bool done = false;
+  switch ((n + 15) / 16) {
+    case 1: done = qr2d_any<8, 1>(batch, m, n, A, R, Q, s) || try_qr_2d<8, 16, 1>(batch, m, n, A, R, Q, s); break;
+    case 2: done = qr2d_any<8, 2>(batch, m, n, A, R, Q, s); break;
+    case 3: done = qr2d_any<5, 3>(batch, m, n, A, R, Q, s); break;
+    case 4: done = qr2d_any<4, 4>(batch, m, n, A, R, Q, s); break;
+    case 5: done = qr2d_any<3, 5>(batch, m, n, A, R, Q, s); break;
+    case 6: done = qr2d_any<2, 6>(batch, m, n, A, R, Q, s) || try_qr_2d<2, 16, 6>(batch, m, n, A, R, Q, s); break;
+    case 7: done = qr2d_any<2, 7>(batch, m, n, A, R, Q, s); break;
+    case 8: done = qr2d_any<2, 8>(batch, m, n, A, R, Q, s); break;
+    default: break;
+  }
+  if (done) return true;
   if (n <= 64) {
-    if (try_qr_lc<4, 4, 1>(batch, m, n, A, R, Q, s) || try_qr_lc<4, 8, 1>(batch, m, n, A, R, Q, s) ||
-        try_qr_lc<8, 8, 1>(batch, m, n, A, R, Q, s) || try_qr_lc<8, 16, 1>(batch, m, n, A, R, Q, s) ||
-        try_qr_lc<8, 24, 1>(batch, m, n, A, R, Q, s) || try_qr_lc<8, 32, 1>(batch, m, n, A, R, Q, s))
+    if (try_qr_lc<8, 16, 1>(batch, m, n, A, R, Q, s) || try_qr_lc<8, 24, 1>(batch, m, n, A, R, Q, s) ||
+        try_qr_lc<8, 32, 1>(batch, m, n, A, R, Q, s))
       return true;
     return try_qr_rows<4, 8>(batch, m, n, A, R, Q, ws, s);
   }
-  if (try_qr_lc<8, 8, 2>(batch, m, n, A, R, Q, s) || try_qr_lc<8, 16, 2>(batch, m, n, A, R, Q, s) ||
-      try_qr_lc<16, 10, 2>(batch, m, n, A, R, Q, s))
+  if (try_qr_lc<8, 16, 2>(batch, m, n, A, R, Q, s) || try_qr_lc<16, 10, 2>(batch, m, n, A, R, Q, s))
     return true;
-  return try_qr_rows<2, 16>(batch, m, n, A, R, Q, ws, s) || try_qr_rows<3, 16>(batch, m, n, A, R, Q, ws, s) ||
-         (Q.base == nullptr && try_qr_rows<4, 16, false>(batch, m, n, A, R, Q, ws, s));
+  return try_qr_rows<2, 16>(batch, m, n, A, R, Q, ws, s) || try_qr_rows<3, 16>(batch, m, n, A, R, Q, ws, s);
 }
 
 bool jacobi_square(int batch, int n, MatView A, MatOut U, double* S, hipStream_t s) {

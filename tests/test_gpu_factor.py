@@ -9,7 +9,9 @@ pytestmark = pytest.mark.gpu
 
 QR_SHAPES = [(6, 6), (16, 40), (30, 20), (64, 64), (50, 64), (100, 64), (128, 33), (160, 64),
              (192, 50), (256, 64), (200, 64), (64, 100), (40, 128), (128, 80), (100, 128),
-             (160, 80), (150, 128), (160, 128), (192, 80), (300, 70), (20, 300), (1, 5), (7, 1)]
+             (160, 80), (150, 128), (160, 128), (192, 80), (300, 70), (20, 300), (1, 5), (7, 1),
+             (16, 16), (33, 16), (200, 16), (100, 30), (300, 30), (70, 48), (250, 40), (224, 64),
+             (168, 80), (96, 96), (150, 96), (110, 112), (112, 128), (128, 128), (80, 80)]
 
 
 def _rand(rng, *shape):
