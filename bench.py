@@ -213,7 +213,24 @@ def main():
         "gradient": grad,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
+    bad = []
+
+    def finite(v, path):
+        # the line must stay strict JSON: non-finite numbers become null and
+        # are listed, never silently dropped
+        if isinstance(v, float) and not math.isfinite(v):
+            bad.append(path)
+            return None
+        if isinstance(v, dict):
+            return {k: finite(x, f"{path}.{k}") for k, x in v.items()}
+        if isinstance(v, list):
+            return [finite(x, f"{path}[{i}]") for i, x in enumerate(v)]
+        return v
+
+    out = finite(out, "")
+    if bad:
+        out["nonfinite_fields"] = bad
+    print(json.dumps(out, allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":

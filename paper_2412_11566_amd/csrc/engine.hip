@@ -777,9 +777,31 @@ static TTP apply_full(const Ctx& X, const TT& A, const TT& x) {
   std::vector<int> rz(L + 1);
   for (int k = 0; k <= L; ++k) rz[k] = A.r[k] * x.r[k];
   auto z = new_tt(X, L, B, A.dout, rz);
-  for (int k = 0; k < L; ++k)
-    ck_tto_core_apply(X, B, A.r[k], A.diag[k] ? 0 : A.din[k], A.dout[k], A.r[k + 1], x.r[k], x.r[k + 1],
-                   A.core[k], x.core[k], z->core[k], X.s());
+  // one launch for every core (descriptors uploaded with the call)
+  std::vector<TtoDesc> d(L);
+  long blocks = 0;
+  double flops = 0.0, bytes = 0.0;
+  for (int k = 0; k < L; ++k) {
+    const int rho = A.r[k], din = A.diag[k] ? 0 : A.din[k], dout = A.dout[k], rho2 = A.r[k + 1];
+    const int r = x.r[k], r2 = x.r[k + 1];
+    const long dx = din > 0 ? din : dout;
+    const long total = (long)B * rho * r * dout * rho2 * r2;
+    if (total >= (1L << 31)) throw std::invalid_argument("product core too large for one launch");
+    need(X, A.core[k], (long)rho * (din > 0 ? din : 1) * dout * rho2 - 1, "apply A");
+    need(X, x.core[k], (long)B * r * dx * r2 - 1, "apply x");
+    need(X, z->core[k], total - 1, "apply Z");
+    d[k] = TtoDesc{A.core[k], x.core[k], z->core[k], B, rho, din, dout, rho2, r, r2, total, blocks};
+    blocks += tto_apply_blocks(total);
+    flops += (double)total * 8.0 * (din > 0 ? din : 1);
+    bytes += 16.0 * ((double)rho * (din > 0 ? din : 1) * dout * rho2 + (double)B * r * dx * r2 + (double)total);
+  }
+  auto dd = X.buf((d.size() * sizeof(TtoDesc) + sizeof(cplx) - 1) / sizeof(cplx));
+  check(hipMemcpyAsync(dd->p, d.data(), d.size() * sizeof(TtoDesc), hipMemcpyHostToDevice, X.s()),
+        "descriptor upload");
+  hipEvent_t e = X.t0();
+  tto_apply_all(L, (const TtoDesc*)dd->p, blocks, X.s());
+  X.t1(e, QTT_K_APPLY, flops, bytes);
+  X.sync();  // the host descriptor array is released on return
   return z;
 }
 

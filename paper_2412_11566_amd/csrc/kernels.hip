@@ -219,7 +219,7 @@ __global__ __launch_bounds__(QR_NT) void k_qr(int m, int n, MatView A, MatOut R,
     const double xn2 = block_sum<QR_NT>(part, red);
     if (tid == 0) {
       const cplx alpha = v[j];
-      if (xn2 == 0.0 && alpha.y == 0.0) {
+      if ((xn2 == 0.0 && alpha.y == 0.0) || cabs2(alpha) + xn2 < QR_TINY) {
         sh_tau = make_double2(0.0, 0.0);
         sh_inv = make_double2(0.0, 0.0);
       } else {
@@ -507,6 +507,56 @@ void tto_core_apply(int batch, int rho, int din, int dout, int rho2, int r, int 
   hipLaunchKernelGGL(k_tto_core_apply, dim3((total + nt - 1) / nt), dim3(nt), 0, s, total,
                      rho, din, dout, rho2, r, r2, A, x, Z);
   check(hipGetLastError(), "tto_core_apply launch");
+}
+
+// All cores of a materialised TTO x TT product in one launch.  Block ranges
+// are assigned to cores by the descriptors' start_block prefix; inside a
+// core the output is walked row-major with the (a2, c2) index innermost, so
+// consecutive lanes write consecutive output entries and read consecutive
+// x entries.  32-bit index arithmetic (every core has < 2^31 entries).
+constexpr int TTO_NT = 256, TTO_EPT = 4;
+
+__global__ __launch_bounds__(TTO_NT) void k_tto_apply_all(int ncores, const TtoDesc* __restrict__ D) {
+  int kc = 0;
+  for (int q = 1; q < ncores; ++q)
+    if ((long)blockIdx.x >= D[q].start_block) kc = q;
+  const TtoDesc d = D[kc];
+  const long blk = (long)blockIdx.x - d.start_block;
+  const int inner = d.rho2 * d.r2;
+  const int dx = d.din > 0 ? d.din : d.dout;
+#pragma unroll
+  for (int u = 0; u < TTO_EPT; ++u) {
+    const long el = (blk * TTO_EPT + u) * TTO_NT + threadIdx.x;
+    if (el >= d.total) return;
+    const int row = (int)(el / inner), colx = (int)(el - (long)row * inner);
+    const int a2 = colx / d.r2, c2 = colx - a2 * d.r2;
+    int t = row;
+    const int i = t % d.dout;
+    t /= d.dout;
+    const int c = t % d.r;
+    t /= d.r;
+    const int a = t % d.rho;
+    const int b = t / d.rho;
+    const cplx* xb = d.x + ((long)(b * d.r + c) * dx) * d.r2 + c2;
+    cplx acc;
+    if (d.din == 0) {
+      acc = cmul(d.A[((long)a * d.dout + i) * d.rho2 + a2], xb[(long)i * d.r2]);
+    } else {
+      acc = make_double2(0.0, 0.0);
+      for (int j = 0; j < d.din; ++j)
+        acc = cadd(acc, cmul(d.A[(((long)a * d.din + j) * d.dout + i) * d.rho2 + a2], xb[(long)j * d.r2]));
+    }
+    d.Z[el] = acc;
+  }
+}
+
+long tto_apply_blocks(long total) { return (total + (long)TTO_NT * TTO_EPT - 1) / ((long)TTO_NT * TTO_EPT); }
+
+void tto_apply_all(int ncores, const TtoDesc* D_dev, long nblocks, hipStream_t s) {
+  if (ncores <= 0 || nblocks <= 0) return;
+  if (nblocks > 2147483647L) throw std::runtime_error("tto_apply_all: grid too large");
+  hipLaunchKernelGGL(k_tto_apply_all, dim3((unsigned)nblocks), dim3(TTO_NT), 0, s, ncores, D_dev);
+  check(hipGetLastError(), "tto_apply_all launch");
 }
 
 // ---------------------------------------------------------------------------

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(QNW * 64) void k_qr_reg(int m, int n, MatView A, Ma
 #pragma unroll
       for (int q = 0; q < QNW; ++q) xn2 += pn[q];
       const cplx alpha = sh_alpha;
-      if (xn2 == 0.0 && alpha.y == 0.0) {
+      if ((xn2 == 0.0 && alpha.y == 0.0) || cabs2(alpha) + xn2 < QR_TINY) {
         sh_tau = make_double2(0.0, 0.0);
         sh_inv = make_double2(0.0, 0.0);
         sh_beta = alpha.x;
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(512) void k_qr_rows(int m, int n, MatView A, MatOut
         al.y = wsum(al.y);
         cplx tau, inv;
         double beta;
-        if (s == 0.0 && al.y == 0.0) {
+        if ((s == 0.0 && al.y == 0.0) || cabs2(al) + s < QR_TINY) {
           tau = make_double2(0.0, 0.0);
           inv = make_double2(0.0, 0.0);
           beta = al.x;
@@ -507,7 +507,7 @@ __global__ __launch_bounds__(NW * 64) void k_qr_lc(int m, int n, MatView A, MatO
     const cplx al = rowj[buf][j];
     cplx tau, inv;
     double beta;
-    if (s == 0.0 && al.y == 0.0) {
+    if ((s == 0.0 && al.y == 0.0) || cabs2(al) + s < QR_TINY) {
       tau = make_double2(0.0, 0.0);
       inv = make_double2(0.0, 0.0);
       beta = al.x;
@@ -753,7 +753,7 @@ __global__ __launch_bounds__(RB * CG * 64) void k_qr_2d(int m, int n, MatView A,
     const cplx al = rowj[j];
     cplx tau, inv;
     double beta;
-    if (s == 0.0 && al.y == 0.0) {
+    if ((s == 0.0 && al.y == 0.0) || cabs2(al) + s < QR_TINY) {
       tau = zero;
       inv = zero;
       beta = al.x;
@@ -761,10 +761,8 @@ __global__ __launch_bounds__(RB * CG * 64) void k_qr_2d(int m, int n, MatView A,
       beta = -copysign(sqrt(cabs2(al) + s), al.x);
       const cplx d = make_double2(al.x - beta, al.y);
       const double dd = cabs2(d);
-      const double r = 1.0 / (beta * dd);  // one division: 1/beta = dd r, 1/dd = beta r
-      const double ib = dd * r, idd = beta * r;
-      tau = make_double2((beta - al.x) * ib, -al.y * ib);
-      inv = make_double2(d.x * idd, -d.y * idd);
+      tau = make_double2((beta - al.x) / beta, -al.y / beta);
+      inv = make_double2(d.x / dd, -d.y / dd);
     }
     if (tid == 0) {
       taus[j] = tau;

@@ -14,6 +14,11 @@ namespace qtt {
 
 using cplx = double2;  // interleaved complex double: x = re, y = im
 
+// Householder columns with squared norm below this are treated as zero
+// (identity reflector): beta^2 and |alpha - beta|^2 stay far from the
+// bottom of the double range, so tau and 1/(alpha - beta) stay finite.
+constexpr double QR_TINY = 1e-292;
+
 // operand transform of a GEMM operand
 enum Op : int { OP_N = 0, OP_T = 1, OP_C = 2 };
 
@@ -102,6 +107,21 @@ void gaussian(cplx* out, size_t count, uint64_t seed, uint64_t stream,
 void tto_core_apply(int batch, int rho, int din, int dout, int rho2, int r,
                     int r2, const cplx* A, const cplx* x, cplx* Z,
                     hipStream_t s);
+
+// One core of a product for the single-launch form: the same contraction
+// as tto_core_apply, batch folded into the row index, output Z of `total`
+// entries, blocks [start_block, start_block + tto_apply_blocks(total)).
+struct TtoDesc {
+  const cplx* A;
+  const cplx* x;
+  cplx* Z;
+  int batch, rho, din, dout, rho2, r, r2;
+  long total, start_block;
+};
+long tto_apply_blocks(long total);
+// Every core of a product in one launch; D_dev: ncores descriptors in
+// device memory, nblocks = sum of the cores' blocks.
+void tto_apply_all(int ncores, const TtoDesc* D_dev, long nblocks, hipStream_t s);
 
 // out[b] = sqrt(sum |x[b*stride + e]|^2), e < len
 void batch_norm(int batch, long len, long stride, const cplx* x,

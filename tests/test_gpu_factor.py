@@ -69,6 +69,27 @@ def test_zqr_rank_deficient_and_generic_path(ctx, shape):
         _check_qr(a, R.cpu().numpy(), Q.cpu().numpy(), full_rank=False)
 
 
+@pytest.mark.parametrize("shape", [(160, 80), (64, 64), (200, 40)])
+def test_zqr_tiny_columns(ctx, shape):
+    """Columns with norms near the bottom of the double range (numerically
+    zero directions of a sketch) must not produce inf or NaN."""
+    import torch
+    import paper_2412_11566_amd as q
+    m, n = shape
+    k = min(m, n)
+    rng = np.random.default_rng(11)
+    a = _rand(rng, 2, m, n)
+    a[:, :, 1] *= 1e-155
+    a[:, :, 5] *= 1e-300
+    A = torch.from_numpy(a).cuda()
+    R = torch.zeros((2, k, n), dtype=torch.complex128, device="cuda")
+    Q = torch.zeros((2, m, k), dtype=torch.complex128, device="cuda")
+    q.zqr(ctx, A, R, Q)
+    R, Q = R.cpu().numpy(), Q.cpu().numpy()
+    assert np.all(np.isfinite(R)) and np.all(np.isfinite(Q))
+    _check_qr(a, R, Q, full_rank=False)
+
+
 @pytest.mark.parametrize("n", [1, 2, 7, 16, 33, 64, 80, 96])
 def test_zjacobi(ctx, n):
     import torch
