@@ -24,6 +24,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <thread>
+#include <atomic>
+#include <exception>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -109,9 +112,17 @@ struct qtt_tensor {
   std::vector<char> diag;
   std::vector<cplx*> core, coreR;
   std::vector<qtt::BufP> mem;
+  // operators: number of instances stacked per core (a batch of
+  // structures), each padded to the common ranks; train batch element b
+  // uses instance b / (B / opb)
+  int opb = 1;
   // Green operator factors
   std::shared_ptr<qtt_tensor> gU, gS, gP, gE, adj;
   double inv_mu0 = 0.0, c = 0.0;
+  // per-structure Green scalars (device arrays over the train batch) when
+  // one factor set serves several reference media
+  std::shared_ptr<qtt::Buf> inv_mu0_b, c_b;
+  int nbatch_scalars = 0;
   std::shared_ptr<qtt::Pool> pool;
 
   long celems(int k) const {  // per batch element
@@ -135,6 +146,9 @@ struct qtt_ctx {
   std::shared_ptr<qtt::Pool> pool;
   uint64_t sketch_counter = 0;
   std::map<int, std::shared_ptr<qtt_tensor>> ident;  // identity operator per n
+  // SFFT and Green factors per (n, delta): shared by every problem of that
+  // grid size (the factors do not depend on the reference medium)
+  std::map<std::pair<int, double>, std::shared_ptr<qtt_tensor>> sfft_cache, green_cache;
   // kernel statistics (HIP events around launches)
   bool stats_on = false;
   std::vector<qtt_stat_rec> pending;
@@ -200,27 +214,40 @@ static void need(const Ctx& X, const void* base, long last, const char* what, si
 static long span2(long rows, long cols, long rs, long cs) {
   return (rows - 1) * rs + (cols - 1) * cs;
 }
-static long spanb(int nb1, long s1, int nb2, long s2) { return (nb1 - 1) * s1 + (nb2 - 1) * s2; }
+// batch layout of a GEMM call: up to three levels (see GemmArgs)
+struct Bat {
+  int nb1 = 1;
+  long sA1 = 0, sB1 = 0, sC1 = 0;
+  int nb2 = 1;
+  long sA2 = 0, sB2 = 0, sC2 = 0;
+  int nb3 = 1;
+  long sA3 = 0, sB3 = 0, sC3 = 0;
+};
+static long spanb(const Bat& t, int w) {
+  const long s1 = w == 0 ? t.sA1 : (w == 1 ? t.sB1 : t.sC1);
+  const long s2 = w == 0 ? t.sA2 : (w == 1 ? t.sB2 : t.sC2);
+  const long s3 = w == 0 ? t.sA3 : (w == 1 ? t.sB3 : t.sC3);
+  return (t.nb1 - 1) * s1 + (t.nb2 - 1) * s2 + (t.nb3 - 1) * s3;
+}
 
-static void G(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long lda, int opB,
-              const cplx* B, long ldb, cplx* Cm, long ldc, int nb1 = 1, long sA1 = 0,
-              long sB1 = 0, long sC1 = 0, int nb2 = 1, long sA2 = 0, long sB2 = 0,
-              long sC2 = 0, cplx alpha = make_double2(1.0, 0.0),
-              cplx beta = make_double2(0.0, 0.0)) {
+static void GB(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long lda, int opB,
+               const cplx* B, long ldb, cplx* Cm, long ldc, const Bat& t,
+               cplx alpha = make_double2(1.0, 0.0), cplx beta = make_double2(0.0, 0.0)) {
   GemmArgs g;
   g.M = M; g.N = N; g.K = K; g.opA = opA; g.opB = opB;
-  g.A = A; g.lda = lda; g.sA1 = sA1; g.sA2 = sA2;
-  g.B = B; g.ldb = ldb; g.sB1 = sB1; g.sB2 = sB2;
-  g.C = Cm; g.ldc = ldc; g.sC1 = sC1; g.sC2 = sC2;
-  g.nb1 = nb1; g.nb2 = nb2; g.alpha = alpha; g.beta = beta;
+  g.A = A; g.lda = lda; g.sA1 = t.sA1; g.sA2 = t.sA2; g.sA3 = t.sA3;
+  g.B = B; g.ldb = ldb; g.sB1 = t.sB1; g.sB2 = t.sB2; g.sB3 = t.sB3;
+  g.C = Cm; g.ldc = ldc; g.sC1 = t.sC1; g.sC2 = t.sC2; g.sC3 = t.sC3;
+  g.nb1 = t.nb1; g.nb2 = t.nb2; g.nb3 = t.nb3; g.alpha = alpha; g.beta = beta;
   if (M > 0 && N > 0 && K > 0) {
-    need(X, A, (opA == OP_N ? span2(M, K, lda, 1) : span2(K, M, lda, 1)) + spanb(nb1, sA1, nb2, sA2), "gemm A");
-    need(X, B, (opB == OP_N ? span2(K, N, ldb, 1) : span2(N, K, ldb, 1)) + spanb(nb1, sB1, nb2, sB2), "gemm B");
-    need(X, Cm, span2(M, N, ldc, 1) + spanb(nb1, sC1, nb2, sC2), "gemm C");
+    need(X, A, (opA == OP_N ? span2(M, K, lda, 1) : span2(K, M, lda, 1)) + spanb(t, 0), "gemm A");
+    need(X, B, (opB == OP_N ? span2(K, N, ldb, 1) : span2(N, K, ldb, 1)) + spanb(t, 1), "gemm B");
+    need(X, Cm, span2(M, N, ldc, 1) + spanb(t, 2), "gemm C");
   }
   if (K == 0) throw std::logic_error("gemm with empty contraction");
+  const double nb = (double)t.nb1 * t.nb2 * t.nb3;
   BufP ws;
-  const int ks = gemm_ksplit(M, N, K, (long)nb1 * nb2);
+  const int ks = gemm_ksplit(M, N, K, (long)nb);
   if (ks > 1) {
     ws = X.buf(gemm_ws_elems(g, ks));
     g.ws = (cplx*)ws->p;
@@ -228,8 +255,19 @@ static void G(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long ld
   }
   hipEvent_t e = X.t0();
   const bool mc = gemm(g, X.s());
-  X.t1(e, mc ? QTT_K_MFMA : QTT_K_GEMM, 8.0 * M * N * K * (double)nb1 * nb2,
-       16.0 * ((double)M * K + (double)K * N + (beta.x != 0.0 || beta.y != 0.0 ? 2.0 : 1.0) * M * N) * nb1 * nb2);
+  X.t1(e, mc ? QTT_K_MFMA : QTT_K_GEMM, 8.0 * M * N * K * nb,
+       16.0 * ((double)M * K + (double)K * N + (beta.x != 0.0 || beta.y != 0.0 ? 2.0 : 1.0) * M * N) * nb);
+}
+
+static void G(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long lda, int opB,
+              const cplx* B, long ldb, cplx* Cm, long ldc, int nb1 = 1, long sA1 = 0,
+              long sB1 = 0, long sC1 = 0, int nb2 = 1, long sA2 = 0, long sB2 = 0,
+              long sC2 = 0, cplx alpha = make_double2(1.0, 0.0),
+              cplx beta = make_double2(0.0, 0.0)) {
+  Bat t;
+  t.nb1 = nb1; t.sA1 = sA1; t.sB1 = sB1; t.sC1 = sC1;
+  t.nb2 = nb2; t.sA2 = sA2; t.sB2 = sB2; t.sC2 = sC2;
+  GB(X, M, N, K, opA, A, lda, opB, B, ldb, Cm, ldc, t, alpha, beta);
 }
 
 static double qr_flops(int m, int n, bool q) {
@@ -264,11 +302,12 @@ static void ck_svd(const Ctx& X, int B, int m, int n, MatView A, MatOut U, doubl
   X.t1(e, QTT_K_JACOBI, B * 4.0 * 22.0 * (double)m * n * n, 16.0 * B * (2.0 * m * n + (double)n * n));
 }
 static void ck_copy2d(const Ctx& X, int B, int rows, int cols, MatView in, MatOut out, cplx a,
-                      hipStream_t s) {
+                      hipStream_t s, const double* bscale = nullptr) {
   if (rows <= 0 || cols <= 0 || B <= 0) return;
   need(X, in.base, span2(rows, cols, in.rs, in.cs) + (B - 1) * in.sb, "copy in");
   need(X, out.base, span2(rows, cols, out.rs, out.cs) + (B - 1) * out.sb, "copy out");
-  copy2d(B, rows, cols, in, out, a, s);
+  if (bscale) need(X, bscale, B - 1, "copy scale", sizeof(double));
+  copy2d(B, rows, cols, in, out, a, s, bscale);
 }
 static void ck_conj_transpose(const Ctx& X, int B, int rows, int keep, MatView in, MatOut out,
                               hipStream_t s) {
@@ -568,7 +607,10 @@ static std::vector<double> tt_norms(const Ctx& X, const TT& x) {
 }
 
 // z = alpha x + beta y (block cores)
-static TTP axpby(const Ctx& X, double alpha, const TT& x, double beta, const TT& y) {
+// z = alpha x + beta y (block concatenation of the cores); alpha_b, beta_b:
+// optional per-batch-element factors (device) multiplying alpha, beta
+static TTP axpby(const Ctx& X, double alpha, const TT& x, double beta, const TT& y,
+                 const double* alpha_b = nullptr, const double* beta_b = nullptr) {
   if (x.L != y.L || x.B != y.B) throw std::invalid_argument("axpby: shape mismatch");
   const int L = x.L, B = x.B;
   std::vector<int> rz(L + 1);
@@ -583,14 +625,16 @@ static TTP axpby(const Ctx& X, double alpha, const TT& x, double beta, const TT&
     const long zsb = (long)R0 * d * R1;
     // x block at (0, 0)
     ck_copy2d(X, B, xr0 * d, xr1, MatView{x.core[k], (long)xr1, 1, (long)xr0 * d * xr1, 0},
-           MatOut{z->core[k], (long)R1, 1, zsb}, CR(k == 0 ? alpha : 1.0), X.s());
+           MatOut{z->core[k], (long)R1, 1, zsb}, CR(k == 0 ? alpha : 1.0), X.s(),
+           k == 0 ? alpha_b : nullptr);
     // y block at row offset (k>0 ? xr0*d : 0), col offset (k<L-1 ? xr1 : 0)
     const long roff = (k > 0) ? (long)xr0 * d : 0;
     const long coff = (k < L - 1) ? xr1 : 0;
     if (k == 0 || k == L - 1) {
       // first core: concatenate columns; last core: stack rows
       ck_copy2d(X, B, yr0 * d, yr1, MatView{y.core[k], (long)yr1, 1, (long)yr0 * d * yr1, 0},
-             MatOut{z->core[k] + roff * R1 + coff, (long)R1, 1, zsb}, CR(k == 0 ? beta : 1.0), X.s());
+             MatOut{z->core[k] + roff * R1 + coff, (long)R1, 1, zsb}, CR(k == 0 ? beta : 1.0), X.s(),
+             k == 0 ? beta_b : nullptr);
       if (k == 0 && L == 1) throw std::invalid_argument("axpby: L == 1");
     } else {
       ck_copy2d(X, B, yr0 * d, yr1, MatView{y.core[k], (long)yr1, 1, (long)yr0 * d * yr1, 0},
@@ -628,14 +672,26 @@ static BufP left_step(const Ctx& X, const TT& A, const TT& x, int k, const cplx*
   G(X, lt * rho, din * r2, r, OP_N, Mc, r, OP_N, x.core[k], (long)din * r2, (cplx*)T1->p,
     (long)din * r2, B, (long)lt * rho * r, (long)r * din * r2, (long)lt * rho * din * r2);
   auto P = X.buf((size_t)B * lt * dout * rho2 * r2);
+  // operator instance per group of g train elements (g = B for one instance)
+  const int ob = A.opb, g = B / ob;
+  if (B % ob) throw std::invalid_argument("train batch not a multiple of the operator instances");
+  const long ia = ob > 1 ? A.celems(k) : 0;
+  Bat t;
+  t.nb1 = ob;
+  t.sA1 = ia;
+  t.nb2 = g * lt;
   if (!A.diag[k]) {
-    G(X, dout * rho2, r2, rho * din, OP_T, A.core[k], (long)dout * rho2, OP_N, (cplx*)T1->p, r2,
-      (cplx*)P->p, r2, B * lt, 0, (long)rho * din * r2, (long)dout * rho2 * r2);
+    t.sB1 = (long)g * lt * rho * din * r2; t.sC1 = (long)g * lt * dout * rho2 * r2;
+    t.sB2 = (long)rho * din * r2; t.sC2 = (long)dout * rho2 * r2;
+    GB(X, dout * rho2, r2, rho * din, OP_T, A.core[k], (long)dout * rho2, OP_N, (cplx*)T1->p, r2,
+       (cplx*)P->p, r2, t);
   } else {
     const int d = dout;
-    G(X, rho2, r2, rho, OP_T, A.core[k], (long)d * rho2, OP_N, (cplx*)T1->p, (long)d * r2,
-      (cplx*)P->p, r2, B * lt, 0, (long)rho * d * r2, (long)d * rho2 * r2, d, rho2, r2,
-      (long)rho2 * r2);
+    t.sB1 = (long)g * lt * rho * d * r2; t.sC1 = (long)g * lt * d * rho2 * r2;
+    t.sB2 = (long)rho * d * r2; t.sC2 = (long)d * rho2 * r2;
+    t.nb3 = d; t.sA3 = rho2; t.sB3 = r2; t.sC3 = (long)rho2 * r2;
+    GB(X, rho2, r2, rho, OP_T, A.core[k], (long)d * rho2, OP_N, (cplx*)T1->p, (long)d * r2,
+       (cplx*)P->p, r2, t);
   }
   return P;
 }
@@ -644,6 +700,7 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
                         RoundStats* st) {
   const int L = x.L, B = x.B;
   if (A.L != L) throw std::invalid_argument("operator and train differ in length");
+  if (B % A.opb) throw std::invalid_argument("train batch not a multiple of the operator instances");
   for (int k = 0; k < L; ++k)
     if (A.din[k] != x.dout[k]) throw std::invalid_argument("operator input dim mismatch");
   // sketch ranks
@@ -700,14 +757,24 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
       (long)r * din * r2, (long)rho2 * r2 * l2, (long)r * din * rho2 * l2, rho2, 0,
       (long)r2 * l2, l2);
     auto X2 = X.buf((size_t)B * r * rho * dout * l2);
+    const int ob = A.opb, g = B / ob;
+    const long ia = ob > 1 ? A.celems(k) : 0;
+    Bat t;
+    t.nb1 = ob;
+    t.sA1 = ia;
+    t.nb2 = g * r;
     if (!A.diag[k]) {
-      G(X, rho * dout, l2, din * rho2, OP_N, A.coreR[k], (long)din * rho2, OP_N, (cplx*)X1->p, l2,
-        (cplx*)X2->p, l2, B * r, 0, (long)din * rho2 * l2, (long)rho * dout * l2);
+      t.sB1 = (long)g * r * din * rho2 * l2; t.sC1 = (long)g * r * rho * dout * l2;
+      t.sB2 = (long)din * rho2 * l2; t.sC2 = (long)rho * dout * l2;
+      GB(X, rho * dout, l2, din * rho2, OP_N, A.coreR[k], (long)din * rho2, OP_N, (cplx*)X1->p, l2,
+         (cplx*)X2->p, l2, t);
     } else {
       const int d = dout;
-      G(X, rho, l2, rho2, OP_N, A.core[k], (long)d * rho2, OP_N, (cplx*)X1->p, l2, (cplx*)X2->p,
-        (long)d * l2, B * r, 0, (long)d * rho2 * l2, (long)rho * d * l2, d, rho2,
-        (long)rho2 * l2, l2);
+      t.sB1 = (long)g * r * d * rho2 * l2; t.sC1 = (long)g * r * rho * d * l2;
+      t.sB2 = (long)d * rho2 * l2; t.sC2 = (long)rho * d * l2;
+      t.nb3 = d; t.sA3 = rho2; t.sB3 = (long)rho2 * l2; t.sC3 = l2;
+      GB(X, rho, l2, rho2, OP_N, A.core[k], (long)d * rho2, OP_N, (cplx*)X1->p, l2, (cplx*)X2->p,
+         (long)d * l2, t);
     }
     W[k] = X.buf((size_t)B * rho * r * l);
     if (dense_w[k]) {
@@ -774,6 +841,7 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
 // Materialised product (ranks multiply).
 static TTP apply_full(const Ctx& X, const TT& A, const TT& x) {
   const int L = x.L, B = x.B;
+  if (B % A.opb) throw std::invalid_argument("train batch not a multiple of the operator instances");
   std::vector<int> rz(L + 1);
   for (int k = 0; k <= L; ++k) rz[k] = A.r[k] * x.r[k];
   auto z = new_tt(X, L, B, A.dout, rz);
@@ -787,10 +855,12 @@ static TTP apply_full(const Ctx& X, const TT& A, const TT& x) {
     const long dx = din > 0 ? din : dout;
     const long total = (long)B * rho * r * dout * rho2 * r2;
     if (total >= (1L << 31)) throw std::invalid_argument("product core too large for one launch");
-    need(X, A.core[k], (long)rho * (din > 0 ? din : 1) * dout * rho2 - 1, "apply A");
+    const long ainst = (long)rho * (din > 0 ? din : 1) * dout * rho2;
+    need(X, A.core[k], ainst * A.opb - 1, "apply A");
     need(X, x.core[k], (long)B * r * dx * r2 - 1, "apply x");
     need(X, z->core[k], total - 1, "apply Z");
-    d[k] = TtoDesc{A.core[k], x.core[k], z->core[k], B, rho, din, dout, rho2, r, r2, total, blocks};
+    d[k] = TtoDesc{A.core[k], x.core[k], z->core[k], B, rho, din, dout, rho2, r, r2, total, blocks,
+                   A.opb > 1 ? ainst : 0, B / A.opb};
     blocks += tto_apply_blocks(total);
     flops += (double)total * 8.0 * (din > 0 ? din : 1);
     bytes += 16.0 * ((double)rho * (din > 0 ? din : 1) * dout * rho2 + (double)B * r * dx * r2 + (double)total);
@@ -838,7 +908,13 @@ static TTP green_chain(const Ctx& X, const TT& G, const TT& x, int flags, const 
   o2.seed = o.seed * 7 + 3;
   auto p = op_apply(X, *G.gP, *s, flags, o2, &s1);
   disc = std::max(disc, s1.rel_max());
-  auto q = axpby(X, G.inv_mu0, *u, -G.c, *p);
+  TTP q;
+  if (G.inv_mu0_b) {
+    if (G.nbatch_scalars != x.B) throw std::invalid_argument("Green scalars do not match the batch");
+    q = axpby(X, 1.0, *u, -1.0, *p, (const double*)G.inv_mu0_b->p, (const double*)G.c_b->p);
+  } else {
+    q = axpby(X, G.inv_mu0, *u, -G.c, *p);
+  }
   if (!(flags & QTT_NO_ROUND)) {
     o2.seed = o.seed * 7 + 5;
     SketchOpts o3 = o2;
@@ -1003,6 +1079,116 @@ static TTP green_op(const Ctx& X, int n, double lam0, double mu0, double delta) 
   return t;
 }
 
+// SFFT of a grid size, built once per (n, delta) in a context
+static TTP sfft_cached(const Ctx& X, int n, double delta) {
+  const auto key = std::make_pair(n, delta);
+  auto it = X.c->sfft_cache.find(key);
+  if (it != X.c->sfft_cache.end()) return it->second;
+  auto t = sfft_op(X, n, delta);
+  X.c->sfft_cache[key] = t;
+  return t;
+}
+
+// Green operator for one reference medium: the factors are built once per
+// (n, delta) and shared, the two medium scalars are set per call
+static TTP green_cached(const Ctx& X, int n, double lam0, double mu0, double delta) {
+  const auto key = std::make_pair(n, delta);
+  auto it = X.c->green_cache.find(key);
+  TTP base;
+  if (it != X.c->green_cache.end()) {
+    base = it->second;
+  } else {
+    base = green_op(X, n, lam0, mu0, delta);
+    X.c->green_cache[key] = base;
+  }
+  auto t = std::make_shared<TT>(*base);
+  host::green_scalars(lam0, mu0, &t->inv_mu0, &t->c);
+  return t;
+}
+
+// Green operator for a batch of structures (train batch = 6 per structure)
+static TTP green_batch(const Ctx& X, int n, double delta, const std::vector<double>& lam0,
+                       const std::vector<double>& mu0, int per) {
+  auto t = green_cached(X, n, lam0[0], mu0[0], delta);
+  const int S = (int)lam0.size(), B = S * per;
+  std::vector<double> a(B), c(B);
+  for (int s2 = 0; s2 < S; ++s2) {
+    double inv, hc;
+    host::green_scalars(lam0[s2], mu0[s2], &inv, &hc);
+    for (int q = 0; q < per; ++q) {
+      a[(size_t)s2 * per + q] = inv;
+      c[(size_t)s2 * per + q] = hc;
+    }
+  }
+  t->inv_mu0_b = X.bufd(B);
+  t->c_b = X.bufd(B);
+  check(hipMemcpyAsync(t->inv_mu0_b->p, a.data(), B * sizeof(double), hipMemcpyHostToDevice, X.s()), "h2d");
+  check(hipMemcpyAsync(t->c_b->p, c.data(), B * sizeof(double), hipMemcpyHostToDevice, X.s()), "h2d");
+  X.sync();
+  t->nbatch_scalars = B;
+  return t;
+}
+
+// Several host operators of one structure pattern stacked as instances of
+// one device operator, each zero-padded to the common ranks (exact).
+static TTP upload_op_batch(const Ctx& X, const std::vector<host::HTT>& hs) {
+  const int S = (int)hs.size();
+  if (S == 1) return upload_op(X, hs[0]);
+  const int L = (int)hs[0].size();
+  auto t = std::make_shared<TT>();
+  t->kind = 1; t->L = L; t->B = 1; t->opb = S; t->pool = X.c->pool;
+  t->dout.resize(L); t->din.resize(L); t->diag.resize(L); t->r.assign(L + 1, 1);
+  t->core.resize(L); t->coreR.assign(L, nullptr);
+  for (int k = 0; k < L; ++k) {
+    const host::HCore& c0 = hs[0][k];
+    t->dout[k] = c0.dout;
+    t->diag[k] = (c0.din == 0);
+    t->din[k] = c0.din == 0 ? c0.dout : c0.din;
+    for (int s2 = 0; s2 < S; ++s2) {
+      const host::HCore& c = hs[s2][k];
+      if ((int)hs[s2].size() != L || c.dout != c0.dout || c.din != c0.din)
+        throw std::invalid_argument("batched operators differ in structure");
+      t->r[k] = std::max(t->r[k], c.r0);
+      t->r[k + 1] = std::max(t->r[k + 1], c.r1);
+    }
+  }
+  for (int k = 0; k < L; ++k) {
+    const int R0 = t->r[k], R1 = t->r[k + 1], d = t->dout[k];
+    const int e = t->diag[k] ? 1 : t->din[k];
+    const size_t inst = (size_t)R0 * d * e * R1;
+    std::vector<std::complex<double>> Lv(inst * S, 0.0), Rv;
+    if (!t->diag[k]) Rv.assign(inst * S, 0.0);
+    for (int s2 = 0; s2 < S; ++s2) {
+      const host::HCore& c = hs[s2][k];
+      std::complex<double>* lo = Lv.data() + inst * s2;
+      for (int a = 0; a < c.r0; ++a)
+        for (int o = 0; o < d; ++o)
+          for (int i = 0; i < e; ++i)
+            for (int b2 = 0; b2 < c.r1; ++b2) {
+              if (t->diag[k]) {
+                lo[((size_t)a * d + o) * R1 + b2] = c.v[((size_t)a * d + o) * c.r1 + b2];
+              } else {
+                const std::complex<double> v = c.v[(((size_t)a * d + o) * e + i) * c.r1 + b2];
+                lo[(((size_t)a * e + i) * d + o) * R1 + b2] = v;                 // layout L
+                Rv[inst * s2 + (((size_t)a * d + o) * e + i) * R1 + b2] = v;     // layout R
+              }
+            }
+    }
+    auto bl = X.buf(Lv.size());
+    check(hipMemcpyAsync(bl->p, Lv.data(), Lv.size() * sizeof(cplx), hipMemcpyHostToDevice, X.s()), "op h2d");
+    t->core[k] = (cplx*)bl->p;
+    t->mem.push_back(bl);
+    if (!t->diag[k]) {
+      auto br = X.buf(Rv.size());
+      check(hipMemcpyAsync(br->p, Rv.data(), Rv.size() * sizeof(cplx), hipMemcpyHostToDevice, X.s()), "op h2d");
+      t->coreR[k] = (cplx*)br->p;
+      t->mem.push_back(br);
+    }
+  }
+  X.sync();
+  return t;
+}
+
 static TTP identity_op(const Ctx& X, int n) {
   auto it = X.c->ident.find(n);
   if (it != X.c->ident.end()) return it->second;
@@ -1076,8 +1262,8 @@ struct Ops {
 static Ops build_ops(const Ctx& X, const qtt_problem* P, double delta) {
   Ops o;
   const int n = P->n;
-  o.S = sfft_op(X, n, delta);
-  o.G = green_op(X, n, P->lame0[0], P->lame0[1], delta);
+  o.S = sfft_cached(X, n, delta);
+  o.G = green_cached(X, n, P->lame0[0], P->lame0[1], delta);
   host::HTT cd = host::stiffness_tto(P->phase, n, P->nphase, P->lame, P->lame0, delta, 0, &o.chi, nullptr);
   o.Cd = upload_op(X, cd);
   o.I = identity_op(X, n);
@@ -1872,13 +2058,130 @@ int ls_adjoint_prepared(qtt_ctx* c, const qtt_prepared* pp, const qtt_solve_opts
 }
 
 
+// structures per batched group: bounds the GEMM batch (6 * group * rank *
+// dim must stay under the 65535 grid limit at rank 80)
+static const size_t kBatchMax = 32;
+
+// One group of structures of the same grid size solved together: the
+// train batch is 6 load cases per structure, the stiffness operator holds
+// one instance per structure, the SFFT and the Green factors are shared and
+// the Green scalars are per structure.  The host stiffness builds (TT-SVD
+// of the voxel arrays) run on parallel host threads.
+static int batch_group(qtt_ctx* c, const std::vector<int>& ids, const qtt_problem* Ps,
+                       const qtt_solve_opts* O, double* Ceff, qtt_report* Rs) {
+  int status = QTT_OK;
+  auto body = [&]() {
+    const int S = (int)ids.size();
+    for (int i : ids) check_problem(&Ps[i], O);
+    const int n = Ps[ids[0]].n;
+    Ctx X{c};
+    const double t0 = now_s();
+    std::vector<host::HTT> cds(S);
+    {
+      std::vector<std::exception_ptr> errs(S);
+      const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+      const int nthr = std::max(1, std::min<int>(S, (int)std::min(16u, hw)));
+      std::atomic<int> next{0};
+      std::vector<std::thread> pool;
+      for (int w = 0; w < nthr; ++w)
+        pool.emplace_back([&]() {
+          for (int s2; (s2 = next.fetch_add(1)) < S;) {
+            try {
+              const qtt_problem& P = Ps[ids[s2]];
+              host::HTT chi;
+              cds[s2] = host::stiffness_tto(P.phase, n, P.nphase, P.lame, P.lame0, O->delta, 0, &chi, nullptr);
+            } catch (...) {
+              errs[s2] = std::current_exception();
+            }
+          }
+        });
+      for (auto& th : pool) th.join();
+      for (auto& e : errs)
+        if (e) std::rethrow_exception(e);
+    }
+    Ops ops;
+    ops.S = sfft_cached(X, n, O->delta);
+    std::vector<double> l0(S), m0(S);
+    for (int s2 = 0; s2 < S; ++s2) {
+      l0[s2] = Ps[ids[s2]].lame0[0];
+      m0[s2] = Ps[ids[s2]].lame0[1];
+    }
+    ops.G = green_batch(X, n, O->delta, l0, m0, 6);
+    ops.Cd = upload_op_batch(X, cds);
+    ops.I = identity_op(X, n);
+    cds.clear();
+    const double t1 = now_s();
+    std::vector<int> ks((size_t)6 * S);
+    for (size_t b = 0; b < ks.size(); ++b) ks[b] = (int)(b % 6);
+    SolveOut so = ls_loop(X, ops, &Ps[ids[0]], O, ks);
+    auto md = mean_apply(X, *ops.Cd, *so.eps);
+    auto me = mean_apply(X, *ops.I, *so.eps);
+    const double t2 = now_s();
+    for (int s2 = 0; s2 < S; ++s2) {
+      const int id = ids[s2];
+      double C0m[36];
+      host::iso_voigt(Ps[id].lame0[0], Ps[id].lame0[1], C0m);
+      double* Ce = Ceff + (size_t)36 * id;
+      bool all = true;
+      for (int k = 0; k < 6; ++k) {
+        const size_t b = (size_t)s2 * 6 + k;
+        for (int i = 0; i < 6; ++i) {
+          std::complex<double> v = md[b * 6 + i];
+          for (int j = 0; j < 6; ++j) v += C0m[i * 6 + j] * me[b * 6 + j];
+          Ce[i * 6 + k] = v.real();
+        }
+        all = all && so.res[b] < O->tol;
+      }
+      if (Rs) {
+        qtt_report& R = Rs[id];
+        std::memset(&R, 0, sizeof(R));
+        for (int k = 0; k < 6; ++k) {
+          R.iterations[k] = so.iters[(size_t)s2 * 6 + k];
+          R.residual[k] = so.res[(size_t)s2 * 6 + k];
+        }
+        R.max_rank = so.max_rank;
+        R.discarded = so.disc;
+        R.seconds_setup = (t1 - t0) / S;
+        R.seconds_solve = (t2 - t1) / S;
+        R.status = all ? QTT_OK : QTT_ENOCONV;
+      }
+    }
+    if (!so.converged) status = QTT_ENOCONV;
+  };
+  int rc = [&]() -> int { QTT_TRY(c, body()); }();
+  if (rc == QTT_OK) rc = status;
+  if (rc != QTT_OK && rc != QTT_ENOCONV && Rs)
+    for (int i : ids) Rs[i].status = rc;
+  return rc;
+}
+
 int qtt_batch_solve(qtt_ctx* c, int count, const qtt_problem* Ps, const qtt_solve_opts* O,
                     double* Ceff, qtt_report* Rs) {
-  if (!c || count < 0 || (count > 0 && (!Ps || !Ceff))) return QTT_EINVAL;
-  int worst = QTT_OK;
+  if (!c || !O || count < 0 || (count > 0 && (!Ps || !Ceff))) return QTT_EINVAL;
+  // structures with all six load cases are solved together, grouped by
+  // grid size, at most kBatchMax per group; the others one by one
+  std::map<int, std::vector<int>> groups;
+  std::vector<int> single;
   for (int i = 0; i < count; ++i) {
+    if (Ps[i].load_mask == 0x3F && Ps[i].n >= 1 && Ps[i].n <= 10) groups[Ps[i].n].push_back(i);
+    else single.push_back(i);
+  }
+  int worst = QTT_OK;
+  auto note = [&](int rc) {
+    if (rc != QTT_OK && (worst == QTT_OK || worst == QTT_ENOCONV)) worst = rc;
+  };
+  for (auto& gr : groups) {
+    const std::vector<int>& ids = gr.second;
+    for (size_t a = 0; a < ids.size(); a += kBatchMax) {
+      std::vector<int> chunk(ids.begin() + a, ids.begin() + std::min(ids.size(), a + kBatchMax));
+      const int rc = batch_group(c, chunk, Ps, O, Ceff, Rs);
+      note(rc);
+      if (rc != QTT_OK && rc != QTT_ENOCONV) return rc;
+    }
+  }
+  for (int i : single) {
     const int rc = ls_solve(c, &Ps[i], O, Ceff + (size_t)36 * i, Rs ? &Rs[i] : nullptr, nullptr);
-    if (rc != QTT_OK && worst == QTT_OK) worst = rc;
+    note(rc);
     if (rc != QTT_OK && rc != QTT_ENOCONV) return rc;
   }
   return worst;

@@ -500,9 +500,13 @@ GreenFactors green_factors(int n, double lam0, double mu0, double delta) {
     }
     G.E = control_op(nt, 6, 6, cf);
   }
-  G.inv_2mu0 = 0.5 / mu0;
-  G.half_c = 0.5 * (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));
+  green_scalars(lam0, mu0, &G.inv_2mu0, &G.half_c);
   return G;
+}
+
+void green_scalars(double lam0, double mu0, double* inv_2mu0, double* half_c) {
+  *inv_2mu0 = 0.5 / mu0;
+  *half_c = 0.5 * (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));
 }
 
 HTT stiffness_tto(const uint8_t* phase, int n, int nphase, const double* lame,

@@ -50,6 +50,10 @@ struct GreenFactors {
   double inv_2mu0 = 0.0, half_c = 0.0;
 };
 GreenFactors green_factors(int n, double lam0, double mu0, double delta);
+// The two scalars of the Green step that depend on the reference medium:
+// 1/(2 mu0) and (lam0 + mu0) / (2 mu0 (lam0 + 2 mu0)) (the factors U, Sd,
+// P, E do not depend on it).
+void green_scalars(double lam0, double mu0, double* inv_2mu0, double* half_c);
 
 // Joint train of the unit directions n^sigma_a in momentum order (core 0
 // of dimension 6 = (sigma, a)).

@@ -84,11 +84,11 @@ __global__ __launch_bounds__((TM / 4) * (TN / 4)) void k_gemm(GemmArgs g) {
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-  const int bz = blockIdx.z;
-  const int b1 = bz / g.nb2, b2 = bz % g.nb2;
-  const cplx* A = g.A + b1 * g.sA1 + b2 * g.sA2;
-  const cplx* B = g.B + b1 * g.sB1 + b2 * g.sB2;
-  cplx* C = g.C + b1 * g.sC1 + b2 * g.sC2;
+  long oa, ob, oc;
+  gemm_batch_offsets(g, blockIdx.z, oa, ob, oc);
+  const cplx* A = g.A + oa;
+  const cplx* B = g.B + ob;
+  cplx* C = g.C + oc;
 
   cplx acc[4][4];
 #pragma unroll
@@ -166,22 +166,22 @@ __global__ __launch_bounds__((TM / 4) * (TN / 4)) void k_gemm(GemmArgs g) {
 
 template <int TM, int TN>
 static void launch_gemm(const GemmArgs& g, hipStream_t s) {
-  dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, g.nb1 * g.nb2);
+  dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, (unsigned)gemm_nbatch(g));
   hipLaunchKernelGGL((k_gemm<TM, TN>), grid, dim3((TM / 4) * (TN / 4)), 0, s, g);
 }
 
 bool gemm(const GemmArgs& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return false;
-  if (g.nb1 * (long)g.nb2 > 65535) throw std::runtime_error("gemm: batch too large");
+  if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0 || g.nb3 <= 0) return false;
+  if (gemm_nbatch(g) > 65535) throw std::runtime_error("gemm: batch too large");
   if (gemm_mfma(g, s)) return true;
   gemm_vector(g, s);
   return false;
 }
 
 void gemm_vector(const GemmArgs& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0) return;
-  if (g.nb1 * (long)g.nb2 > 65535) throw std::runtime_error("gemm: batch too large");
-  const long tiles64 = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * g.nb1 * g.nb2;
+  if (g.M <= 0 || g.N <= 0 || g.nb1 <= 0 || g.nb2 <= 0 || g.nb3 <= 0) return;
+  if (gemm_nbatch(g) > 65535) throw std::runtime_error("gemm: batch too large");
+  const long tiles64 = (long)((g.M + 63) / 64) * ((g.N + 63) / 64) * gemm_nbatch(g);
   if (g.M <= 16 && g.N > 32) launch_gemm<16, 64>(g, s);
   else if (g.N <= 16 && g.M > 32) launch_gemm<64, 16>(g, s);
   else if (g.M <= 32 || g.N <= 32 || tiles64 < 512) launch_gemm<32, 32>(g, s);
@@ -538,13 +538,14 @@ __global__ __launch_bounds__(TTO_NT) void k_tto_apply_all(int ncores, const TtoD
     const int a = t % d.rho;
     const int b = t / d.rho;
     const cplx* xb = d.x + ((long)(b * d.r + c) * dx) * d.r2 + c2;
+    const cplx* Ab = d.A + (long)(b / d.group) * d.a_stride;
     cplx acc;
     if (d.din == 0) {
-      acc = cmul(d.A[((long)a * d.dout + i) * d.rho2 + a2], xb[(long)i * d.r2]);
+      acc = cmul(Ab[((long)a * d.dout + i) * d.rho2 + a2], xb[(long)i * d.r2]);
     } else {
       acc = make_double2(0.0, 0.0);
       for (int j = 0; j < d.din; ++j)
-        acc = cadd(acc, cmul(d.A[(((long)a * d.din + j) * d.dout + i) * d.rho2 + a2], xb[(long)j * d.r2]));
+        acc = cadd(acc, cmul(Ab[(((long)a * d.din + j) * d.dout + i) * d.rho2 + a2], xb[(long)j * d.r2]));
     }
     d.Z[el] = acc;
   }
@@ -601,22 +602,28 @@ void scale_cols(int batch, int rows, int cols, long ld, long sb, cplx* x, const 
   check(hipGetLastError(), "scale_cols launch");
 }
 
-__global__ void k_copy2d(long total, int rows, int cols, MatView in, MatOut out, cplx alpha) {
+__global__ void k_copy2d(long total, int rows, int cols, MatView in, MatOut out, cplx alpha,
+                         const double* bscale) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
   const int j = e % cols;
   const long t = e / cols;
   const int i = t % rows;
   const long b = t / rows;
-  out.base[b * out.sb + i * out.rs + (long)j * out.cs] = cmul(alpha, ldview(in, b, i, j));
+  cplx a = alpha;
+  if (bscale) {
+    a.x *= bscale[b];
+    a.y *= bscale[b];
+  }
+  out.base[b * out.sb + i * out.rs + (long)j * out.cs] = cmul(a, ldview(in, b, i, j));
 }
 
 void copy2d(int batch, int rows, int cols, MatView in, MatOut out, cplx alpha,
-            hipStream_t s) {
+            hipStream_t s, const double* bscale) {
   const long total = (long)batch * rows * cols;
   if (total == 0) return;
   hipLaunchKernelGGL(k_copy2d, dim3((total + 255) / 256), dim3(256), 0, s, total, rows, cols,
-                     in, out, alpha);
+                     in, out, alpha, bscale);
   check(hipGetLastError(), "copy2d launch");
 }
 

@@ -38,9 +38,10 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int
   const int wm = w >> 1, wn = w & 1;   // wave position in the 2 x 2 grid
   const int m0 = blockIdx.y * MT, n0 = blockIdx.x * NT;
   const int bz = blockIdx.z / ksplit, slice = blockIdx.z % ksplit;
-  const int b1 = bz / g.nb2, b2 = bz % g.nb2;
-  const cplx* A = g.A + b1 * g.sA1 + b2 * g.sA2;
-  const cplx* B = g.B + b1 * g.sB1 + b2 * g.sB2;
+  long oa, ob, oc;
+  gemm_batch_offsets(g, bz, oa, ob, oc);
+  const cplx* A = g.A + oa;
+  const cplx* B = g.B + ob;
   const int kbeg = slice * kchunk, kend = min(g.K, kbeg + kchunk);
 
   dv4 cr[2][2], ci[2][2];
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int
 
   if (ksplit > 1) {
     // raw partial sums of this K slice: ws[slice][bz][m][n]
-    cplx* P = g.ws + ((long)slice * g.nb1 * g.nb2 + bz) * (long)g.M * g.N;
+    cplx* P = g.ws + ((long)slice * gemm_nbatch(g) + bz) * (long)g.M * g.N;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int
         }
     return;
   }
-  cplx* C = g.C + b1 * g.sC1 + b2 * g.sC2;
+  cplx* C = g.C + oc;
   const bool zb = (g.beta.x == 0.0 && g.beta.y == 0.0);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int
 
 // C = alpha * sum_s ws[s] + beta * C, slices added in order s = 0, 1, ...
 __global__ __launch_bounds__(256) void k_zgemm_reduce(GemmArgs g, int ksplit) {
-  const long mn = (long)g.M * g.N, nb = (long)g.nb1 * g.nb2;
+  const long mn = (long)g.M * g.N, nb = gemm_nbatch(g);
   const long total = nb * mn;
   for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256L) {
     const long bz = e / mn, r = e % mn;
@@ -196,8 +197,9 @@ __global__ __launch_bounds__(256) void k_zgemm_reduce(GemmArgs g, int ksplit) {
       sx += p.x;
       sy += p.y;
     }
-    const int b1 = (int)(bz / g.nb2), b2 = (int)(bz % g.nb2);
-    cplx* cp = g.C + b1 * g.sC1 + b2 * g.sC2 + (long)m * g.ldc + n;
+    long oa, ob, oc;
+    gemm_batch_offsets(g, bz, oa, ob, oc);
+    cplx* cp = g.C + oc + (long)m * g.ldc + n;
     cplx out = make_double2(g.alpha.x * sx - g.alpha.y * sy, g.alpha.x * sy + g.alpha.y * sx);
     if (g.beta.x != 0.0 || g.beta.y != 0.0) {
       const cplx c0 = *cp;
@@ -224,13 +226,13 @@ int gemm_ksplit(int M, int N, int K, long nbatch) {
 }
 
 size_t gemm_ws_elems(const GemmArgs& g, int ksplit) {
-  return ksplit > 1 ? (size_t)ksplit * g.nb1 * g.nb2 * (size_t)g.M * g.N : 0;
+  return ksplit > 1 ? (size_t)ksplit * gemm_nbatch(g) * (size_t)g.M * g.N : 0;
 }
 
 bool gemm_mfma(const GemmArgs& g, hipStream_t s) {
   if (!gemm_mfma_ok(g.M, g.N, g.K)) return false;
   int ks = g.ksplit > 1 && g.ws ? g.ksplit : 1;
-  const long nb = (long)g.nb1 * g.nb2;
+  const long nb = gemm_nbatch(g);
   if (nb * ks > 65535) ks = 1;
   // slice length: a multiple of the stage depth
   const int per = (g.K + ks - 1) / ks;

@@ -36,11 +36,23 @@ struct GemmArgs {
   cplx* C; long ldc, sC1, sC2;
   int nb1, nb2;
   cplx alpha, beta;
+  // optional third batch level (innermost): element (b1, b2, b3) adds
+  // b3 * s?3; the batch index is z = (b1 * nb2 + b2) * nb3 + b3
+  int nb3 = 1;
+  long sA3 = 0, sB3 = 0, sC3 = 0;
   // split-K workspace of the matrix-core path (gemm_ws_elems entries for
   // ksplit slices); ksplit = 1 or ws = nullptr: no split
   cplx* ws = nullptr;
   int ksplit = 1;
 };
+__host__ __device__ inline long gemm_nbatch(const GemmArgs& g) { return (long)g.nb1 * g.nb2 * g.nb3; }
+__host__ __device__ inline void gemm_batch_offsets(const GemmArgs& g, long z, long& oa, long& ob, long& oc) {
+  const long b3 = z % g.nb3, t = z / g.nb3;
+  const long b2 = t % g.nb2, b1 = t / g.nb2;
+  oa = b1 * g.sA1 + b2 * g.sA2 + b3 * g.sA3;
+  ob = b1 * g.sB1 + b2 * g.sB2 + b3 * g.sB3;
+  oc = b1 * g.sC1 + b2 * g.sC2 + b3 * g.sC3;
+}
 // Returns true when the matrix-core kernel ran, false for the vector kernel.
 bool gemm(const GemmArgs& g, hipStream_t s);
 // Matrix-core path of gemm for M, N >= 32 and K >= 8 (kernels_mfma.hip);
@@ -117,6 +129,8 @@ struct TtoDesc {
   cplx* Z;
   int batch, rho, din, dout, rho2, r, r2;
   long total, start_block;
+  long a_stride;  // operator instance stride (0: one instance for all b)
+  int group;      // train batch elements per operator instance
 };
 long tto_apply_blocks(long total);
 // Every core of a product in one launch; D_dev: ncores descriptors in
@@ -136,9 +150,10 @@ void scale_cols(int batch, int rows, int cols, long ld, long sb, cplx* x,
 void conj_transpose(int batch, int rows, int keep, MatView in, MatOut out,
                     hipStream_t s);
 
-// Generic strided 2D copy with optional scale: out(i,j) = alpha * in(i,j)
+// Generic strided 2D copy with optional scale: out(i,j) = alpha * in(i,j),
+// times bscale[b] per batch element when bscale (device) is given.
 void copy2d(int batch, int rows, int cols, MatView in, MatOut out,
-            cplx alpha, hipStream_t s);
+            cplx alpha, hipStream_t s, const double* bscale = nullptr);
 
 // Fill count complex entries with value v.
 void fill(cplx* p, size_t count, cplx v, hipStream_t s);
