@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (= matrix) peak
 PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 matrix (dense)
 
 
 def log(*a):
@@ -77,6 +78,59 @@ def tto_apply_bandwidth(q, ctx, n, reps=3):
             "sfft_rank": max(S.ranks), "x_rank": max(ranks)}
 
 
+def batched_vs_plain(q, ctx, M, count, n, max_iter):
+    """The batched workload's random-sphere recipe (structures 0.., seed
+    [0, i]: 1-8 spheres, radii U[0.05, 0.2], E_incl U[2, 50]) on the 2^n
+    grid with a cap equal to the grid's largest structural rank (the
+    recipe's own caps bind hard: spheres compress poorly in QTT), delta 1e-7,
+    tol 1e-5: one batched solve of all ``count`` structures with FP32
+    contractions, and with FP64, against one FP64 solve per structure.  Wall
+    time includes the per-structure stiffness build; the grid's SFFT and
+    Green factors are built before the timings."""
+    import torch
+    ps = [M.config_c3_structure(i, grid_n=n) for i in range(count)]
+    cap = ps[0].cap
+    mk = lambda prec: q.SolveOptions(delta=ps[0].delta, tol=ps[0].tol, cap=cap, max_iter=max_iter,
+                                     oversample=16, seed=7, precision=prec)
+    o64, o32 = mk(q.QTT_PREC_FP64), mk(q.QTT_PREC_FP32)
+    q.ls_solve(ctx, ps[0].phase, ps[0].lame, ps[0].lame0,
+               q.SolveOptions(delta=o64.delta, tol=o64.tol, cap=cap, max_iter=1))
+    probs = [(p.phase, p.lame, p.lame0) for p in ps]
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t
+
+    log(f"batched comparison: {count} structures of {1 << n}^3, batched FP32 contractions")
+    (C32, r32), t32 = timed(lambda: q.batch_solve(ctx, probs, o32))
+    log(f"  {t32:.2f} s; batched FP64")
+    (C64, r64), t64 = timed(lambda: q.batch_solve(ctx, probs, o64))
+    log(f"  {t64:.2f} s; one FP64 solve per structure")
+
+    def plain():
+        out = []
+        for p in ps:
+            C, rep, _ = q.ls_solve(ctx, p.phase, p.lame, p.lame0, o64)
+            out.append((C, rep))
+        return out
+
+    pl, tp = timed(plain)
+    Cp = [c for c, _ in pl]
+    rel = lambda A, B: max(float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(A, B))
+    conv = lambda reps: int(sum(1 for r in reps if r.status == 0))
+    log(f"batched {count} x {1 << n}^3 cap {cap}: fp32 {t32:.2f} s, fp64 {t64:.2f} s, plain fp64 {tp:.2f} s")
+    return {"structures": count, "grid": f"{1 << n}^3", "cap": cap, "delta": o64.delta,
+            "tol": o64.tol, "batched_fp32_s": t32, "batched_fp64_s": t64, "plain_fp64_s": tp,
+            "speedup_batched_fp32_vs_plain": tp / t32, "speedup_batched_fp64_vs_plain": tp / t64,
+            "structures_per_s_batched_fp32": count / t32, "structures_per_s_plain_fp64": count / tp,
+            "converged": {"batched_fp32": conv(r32), "batched_fp64": conv(r64),
+                          "plain_fp64": conv([r for _, r in pl])},
+            "max_rel_diff_fp32_vs_plain": rel(C32, Cp), "max_rel_diff_fp64_vs_plain": rel(C64, Cp)}
+
+
 def cpu_baseline(p, target_s=15.0):
     """Oracle (dense basic scheme, FP64, scipy.fft on all host cores): k
     updates of load case 11 on the full 256^3 grid of the same workload, k
@@ -111,6 +165,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gradient", action="store_true",
                     help="skip the adjoint solve (gradient cost ratio)")
+    ap.add_argument("--batch", type=int, default=4,
+                    help="structures in the batched-vs-plain comparison (0: skip)")
     ap.add_argument("--max-iter", type=int, default=110,
                     help="updates per load case (the cap-64 strain plateaus above tol; 110 "
                          "is the dense scheme's count to 1e-6 on this geometry)")
@@ -123,7 +179,7 @@ def main():
     if int(os.environ.get("RANK", "0")) != 0:
         return
 
-    os.environ.setdefault("QTTHOM_VERBOSE", "1")   # one progress line per update (stderr)
+    os.environ.setdefault("QTTHOM_VERBOSE", "1")  # progress lines (stderr); 0 silences them   # one progress line per update (stderr)
     import torch
     import paper_2412_11566_amd as q
     import microstructures as M
@@ -154,7 +210,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
-    fam = [q.stats_get(ctx, f) for f in range(6)]
+    fam = [q.stats_get(ctx, f) for f in range(7)]
     q.stats_enable(ctx, False)
     grad = None
     if not args.no_gradient:
@@ -177,14 +233,18 @@ def main():
             f"flops {f['flops']:.3e} bytes {f['bytes']:.3e}")
     dom = max(fam, key=lambda f: f["seconds"])
     achieved = dom["flops"] / dom["seconds"] / 1e12
-    roofline = {"bound": "mfma" if dom["family"] == "gemm_mfma" else "alu",
+    peak = PEAK_FP32_TFLOPS if dom["family"] == "gemm_mfma_fp32" else PEAK_FP64_TFLOPS
+    roofline = {"bound": "mfma" if dom["family"].startswith("gemm_mfma") else "alu",
                 "kernel": dom["family"], "achieved": achieved,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": None, "launches": dom["launches"],
                 "avg_launch_us": 1e6 * dom["seconds"] / max(dom["launches"], 1),
                 "time_share": dom["seconds"] / elapsed}
     err = golden_error(C, "c2") if args.n == 8 else None
     tto = tto_apply_bandwidth(q, ctx, args.n)
+    batch = None
+    if args.batch > 0:
+        batch = batched_vs_plain(q, ctx, M, args.batch, 4, 300)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p)
@@ -211,6 +271,7 @@ def main():
         "roofline": roofline,
         "tto_apply": tto,
         "gradient": grad,
+        "batched": batch,
         "cpu_baseline": cpu,
     }
     bad = []

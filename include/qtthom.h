@@ -247,7 +247,7 @@ int ls_adjoint_prepared(qtt_ctx* ctx, const qtt_prepared* prep,
 
 /* The strided batched complex FP64 GEMM that every core contraction of
  * the path runs on (the products of App. C and the factorisations of the
- * rounding, Alg. 3 / Sec. 2.2):
+ * rounding, Sec. 3 around eq. rounding_condition_tt):
  *   C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b],   b < batch,
  * op(A) is M x K: op 0 (N) reads A[m*lda + k], op 1 (T) reads A[k*lda + m],
  * op 2 (C) reads conj(A[k*lda + m]); op(B) is K x N likewise.  A, B, C are
@@ -257,15 +257,18 @@ int ls_adjoint_prepared(qtt_ctx* ctx, const qtt_prepared* prep,
  * caller guarantees every addressed element lies in its allocation.
  * path: 0 automatic (matrix cores for M, N >= 32 and K >= 8, else vector
  * ALU), 1 vector ALU, 2 matrix cores (QTT_EINVAL if the shape is outside
- * its range).  Asynchronous on the context's stream.  QTT_EINVAL on null
- * pointers, K < 1, batch outside [1, 65535] or leading dimensions smaller
- * than a row. */
+ * its range), 3 matrix cores with FP32 operands and accumulation (the
+ * contraction precision of QTT_PREC_FP32; results stored as doubles).
+ * Asynchronous on the context's stream.  QTT_EINVAL on null pointers,
+ * K < 1, batch outside [1, 65535] or leading dimensions smaller than a
+ * row. */
 int qtt_zgemm(qtt_ctx* ctx, int opA, int opB, int M, int N, int K,
               const double* alpha, const void* A, long lda, const void* B,
               long ldb, const double* beta, void* C, long ldc, int batch,
               long sA, long sB, long sC, int path);
 
-/* The two small dense factorisations of TT-rounding (Sec. 2.2, Alg. 3),
+/* The two small dense factorisations of TT-rounding (Sec. 3, QR sweep and
+ * truncated SVD around eq. rounding_condition_tt),
  * exposed for direct testing and timing.  Device pointers, interleaved
  * complex doubles, row-major, batch stride = one matrix, caller-owned.
  *
@@ -296,7 +299,8 @@ int qtt_zjacobi(qtt_ctx* ctx, int batch, int n, const void* A, void* U,
 #define QTT_K_APPLY     3   /* materialised TTO x TT core product           */
 #define QTT_K_OTHER     4   /* elementwise helpers, RNG                     */
 #define QTT_K_MFMA      5   /* batched complex GEMM on the matrix cores     */
-#define QTT_K_COUNT     6
+#define QTT_K_MFMA32    6   /* the same in FP32 (QTT_PREC_FP32 contractions) */
+#define QTT_K_COUNT     7
 int qtt_stats_enable(qtt_ctx* ctx, int on);
 int qtt_stats_get(qtt_ctx* ctx, int family, long long* launches,
                   double* seconds, double* flops, double* bytes);

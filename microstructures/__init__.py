@@ -217,21 +217,37 @@ def config_c2(n: int = 8) -> Problem:
 _C3_CAP = {5: 16, 6: 32, 7: 64}
 
 
-def config_c3_structure(i: int, master_seed: int = 0) -> Problem:
+def config_c3_structure(i: int, master_seed: int = 0, grid_n: int | None = None) -> Problem:
     """Structure ``i`` of the batched workload (seed [master, i]).
 
     Draw order: grid n in {5, 6, 7}; sphere count in 1..8; centres; radii in
     [0.05, 0.2]; then inclusion E in [2, 50].  nu = 0.3 for both phases,
     matrix E = 1.  Cap by grid: 32^3 -> 16, 64^3 -> 32, 128^3 -> 64.
+    ``grid_n`` replaces the drawn grid (the draw still happens, so the
+    geometry and moduli of structure i are unchanged); its cap is then the
+    largest structural rank of that grid (no binding).
     """
     rng = np.random.default_rng([master_seed, i])
     n = int(rng.choice([5, 6, 7]))
+    if grid_n is not None:
+        n = grid_n
     count = int(rng.integers(1, 9))
     cs, rs = random_spheres(rng, count, 0.05, 0.2)
     E_incl = float(rng.uniform(2.0, 50.0))
+    cap = _C3_CAP.get(n) if grid_n is None else _structural_cap(n)
     return Problem(f"c3_{i:03d}_n{n}", n, spheres(1 << n, cs, rs),
-                   [(1.0, 0.3), (E_incl, 0.3)], cap=_C3_CAP[n], delta=1e-7,
+                   [(1.0, 0.3), (E_incl, 0.3)], cap=cap, delta=1e-7,
                    tol=1e-5, meta={"count": count, "E_incl": E_incl})
+
+
+def _structural_cap(n: int) -> int:
+    """Largest bond rank of a strain train on a 2^n grid (Voigt core of
+    dimension 6, then 3n binary cores)."""
+    L = 3 * n + 1
+    best = 1
+    for k in range(1, L):
+        best = max(best, min(6 * 2 ** (k - 1), 2 ** (L - k)))
+    return best
 
 
 def config_c3(count: int = 256, master_seed: int = 0) -> list:

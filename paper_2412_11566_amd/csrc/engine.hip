@@ -145,6 +145,9 @@ struct qtt_ctx {
   std::string err;
   std::shared_ptr<qtt::Pool> pool;
   uint64_t sketch_counter = 0;
+  // contractions of a product run in FP32 on the matrix cores while set
+  // (rounding, norms and averages always run in FP64)
+  bool gemm_fp32 = false;
   std::map<int, std::shared_ptr<qtt_tensor>> ident;  // identity operator per n
   // SFFT and Green factors per (n, delta): shared by every problem of that
   // grid size (the factors do not depend on the reference medium)
@@ -253,9 +256,10 @@ static void GB(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long l
     g.ws = (cplx*)ws->p;
     g.ksplit = ks;
   }
+  g.fp32 = X.c->gemm_fp32;
   hipEvent_t e = X.t0();
   const bool mc = gemm(g, X.s());
-  X.t1(e, mc ? QTT_K_MFMA : QTT_K_GEMM, 8.0 * M * N * K * nb,
+  X.t1(e, mc ? (g.fp32 ? QTT_K_MFMA32 : QTT_K_MFMA) : QTT_K_GEMM, 8.0 * M * N * K * nb,
        16.0 * ((double)M * K + (double)K * N + (beta.x != 0.0 || beta.y != 0.0 ? 2.0 : 1.0) * M * N) * nb);
 }
 
@@ -660,6 +664,18 @@ struct SketchOpts {
   // without the final truncated-SVD sweep: used for intermediate products
   // whose result is immediately sketched again
   bool no_truncate = false;
+  // contractions in FP32 (QR, SVD and the truncation stay FP64)
+  bool fp32 = false;
+};
+
+// FP32 contractions for the lifetime of the scope (restores the previous
+// setting; off() ends it early)
+struct Fp32Scope {
+  qtt_ctx* c;
+  bool prev;
+  Fp32Scope(const Ctx& X, bool on) : c(X.c), prev(X.c->gemm_fp32) { c->gemm_fp32 = on; }
+  void off() { c->gemm_fp32 = prev; }
+  ~Fp32Scope() { c->gemm_fp32 = prev; }
 };
 
 // Contract Mc (B, lt, rho, r) with x_k -> T1 (B, lt, rho, din, r2), then with
@@ -703,6 +719,13 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
   if (B % A.opb) throw std::invalid_argument("train batch not a multiple of the operator instances");
   for (int k = 0; k < L; ++k)
     if (A.din[k] != x.dout[k]) throw std::invalid_argument("operator input dim mismatch");
+  // FP32 (o.fp32) is used only for contractions whose operands are well
+  // conditioned: the operator x train step (T1) and the projection onto the
+  // orthonormal QR basis (Q^H P).  The Gaussian tensor-train sketches are
+  // ill-conditioned (their condition numbers multiply along the train), so
+  // the partial sketches W and the sketched unfoldings Y = P W stay FP64.
+  const bool f32 = o.fp32 && !o.exact;
+  Fp32Scope prec(X, false);
   // sketch ranks
   std::vector<int> ell(L + 1, 1);
   std::vector<long> left(L + 1, 1), right(L + 1, 1);
@@ -799,7 +822,9 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
   int lt = 1;
   for (int k = 0; k < L; ++k) {
     const int rho2 = A.r[k + 1], r2 = x.r[k + 1], dout = A.dout[k];
+    X.c->gemm_fp32 = f32;
     auto P = left_step(X, A, x, k, (cplx*)Mc->p, lt);
+    X.c->gemm_fp32 = false;
     if (k == L - 1) {
       set_core(X, *y, k, lt, 1, P);
       break;
@@ -821,12 +846,15 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
        MatOut{(cplx*)R->p, (long)l2, 1, (long)kq * l2}, MatOut{(cplx*)Q->p, (long)kq, 1, (long)m * kq},
        (cplx*)ws->p, X.s());
     auto Mn = X.buf((size_t)B * kq * rho2 * r2);
+    X.c->gemm_fp32 = f32;
     G(X, kq, rho2 * r2, m, OP_C, (cplx*)Q->p, kq, OP_N, (cplx*)P->p, (long)rho2 * r2, (cplx*)Mn->p,
       (long)rho2 * r2, B, (long)m * kq, (long)m * rho2 * r2, (long)kq * rho2 * r2);
+    X.c->gemm_fp32 = false;
     set_core(X, *y, k, lt, kq, Q);
     Mc = Mn;
     lt = kq;
   }
+  prec.off();
   if (o.no_truncate && !o.exact && o.cap > 0) {
     if (st) {
       st->disc2.assign(B, 0.0);
@@ -1279,6 +1307,8 @@ static void check_problem(const qtt_problem* P, const qtt_solve_opts* O) {
   if (!P->phase || !P->lame) throw std::invalid_argument("null phase or lame");
   if (!(O->delta > 0.0) || !(O->tol >= 0.0) || O->max_iter < 0)
     throw std::invalid_argument("bad solve options");
+  if (O->precision != QTT_PREC_FP64 && O->precision != QTT_PREC_FP32)
+    throw std::invalid_argument("precision must be QTT_PREC_FP64 or QTT_PREC_FP32");
 }
 
 struct SolveOut {
@@ -1297,6 +1327,7 @@ static SketchOpts sk(const Ctx& X, const qtt_solve_opts* O) {
   s.cap = O->cap;
   s.oversample = std::max(0, O->oversample);
   s.exact = O->exact != 0;
+  s.fp32 = O->precision == QTT_PREC_FP32;
   s.seed = O->seed * 1000003ULL + (X.c->sketch_counter++);
   return s;
 }
@@ -1829,7 +1860,7 @@ int qtt_zgemm(qtt_ctx* c, int opA, int opB, int M, int N, int K, const double* a
               long ldc, int batch, long sA, long sB, long sC, int path) {
   if (!c || !alpha || !beta || !A || !B || !Cm) return QTT_EINVAL;
   if (M < 0 || N < 0 || K < 1 || batch < 1 || batch > 65535 || opA < 0 || opA > 2 || opB < 0 ||
-      opB > 2 || path < 0 || path > 2)
+      opB > 2 || path < 0 || path > 3)
     return QTT_EINVAL;
   if (lda < (opA == OP_N ? K : M) || ldb < (opB == OP_N ? N : K) || ldc < N) return QTT_EINVAL;
   QTT_TRY(c, {
@@ -1849,6 +1880,7 @@ int qtt_zgemm(qtt_ctx* c, int opA, int opB, int M, int N, int K, const double* a
       g.ws = (cplx*)ws->p;
       g.ksplit = ks;
     }
+    g.fp32 = path == 3;
     if (path == 0) gemm(g, c->stream);
     else if (path == 1) gemm_vector(g, c->stream);
     else if (!gemm_mfma(g, c->stream))

@@ -25,6 +25,7 @@ namespace qtt {
 namespace {
 
 typedef double dv4 __attribute__((ext_vector_type(4)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
 
 constexpr int MT = 64, NT = 64, KT = 16;
 constexpr int PAD = 2;
@@ -184,6 +185,159 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int
       }
 }
 
+// The same tiling with FP32 operands and FP32 accumulation on
+// v_mfma_f32_16x16x4f32 (twice the FP64 matrix rate): operands are rounded
+// to float when staged, results widened to double on store.  Output lane
+// layout of this instruction: lane l, register r holds D[4 (l / 16) + r][l % 16].
+__global__ __launch_bounds__(NTHR) void k_zgemm_mfma32(GemmArgs g, int ksplit, int kchunk) {
+  __shared__ float Ar[KT][MT + 4], Ai[KT][MT + 4];
+  __shared__ float Br[KT][NT + 4], Bi[KT][NT + 4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int m0 = blockIdx.y * MT, n0 = blockIdx.x * NT;
+  const int bz = blockIdx.z / ksplit, slice = blockIdx.z % ksplit;
+  long oa, ob, oc;
+  gemm_batch_offsets(g, bz, oa, ob, oc);
+  const cplx* A = g.A + oa;
+  const cplx* B = g.B + ob;
+  const int kbeg = slice * kchunk, kend = min(g.K, kbeg + kchunk);
+
+  fv4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = fv4{0.f, 0.f, 0.f, 0.f};
+      ci[i][j] = fv4{0.f, 0.f, 0.f, 0.f};
+    }
+  cplx ra[PER_T], rb[PER_T];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int t = 0; t < PER_T; ++t) {
+      const int e = tid + NTHR * t;
+      int mm, kk;
+      if (g.opA == OP_N) { kk = e % KT; mm = e / KT; }
+      else { mm = e % MT; kk = e / MT; }
+      const int m = m0 + mm, k = k0 + kk;
+      cplx v = make_double2(0.0, 0.0);
+      if (m < g.M && k < kend) {
+        if (g.opA == OP_N) v = A[(long)m * g.lda + k];
+        else {
+          v = A[(long)k * g.lda + m];
+          if (g.opA == OP_C) v.y = -v.y;
+        }
+      }
+      ra[t] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < PER_T; ++t) {
+      const int e = tid + NTHR * t;
+      int nn, kk;
+      if (g.opB == OP_N) { nn = e % NT; kk = e / NT; }
+      else { kk = e % KT; nn = e / KT; }
+      const int n = n0 + nn, k = k0 + kk;
+      cplx v = make_double2(0.0, 0.0);
+      if (n < g.N && k < kend) {
+        if (g.opB == OP_N) v = B[(long)k * g.ldb + n];
+        else {
+          v = B[(long)n * g.ldb + k];
+          if (g.opB == OP_C) v.y = -v.y;
+        }
+      }
+      rb[t] = v;
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int t = 0; t < PER_T; ++t) {
+      const int e = tid + NTHR * t;
+      int mm, kk;
+      if (g.opA == OP_N) { kk = e % KT; mm = e / KT; }
+      else { mm = e % MT; kk = e / MT; }
+      Ar[kk][mm] = (float)ra[t].x;
+      Ai[kk][mm] = (float)ra[t].y;
+    }
+#pragma unroll
+    for (int t = 0; t < PER_T; ++t) {
+      const int e = tid + NTHR * t;
+      int nn, kk;
+      if (g.opB == OP_N) { nn = e % NT; kk = e / NT; }
+      else { kk = e % KT; nn = e / KT; }
+      Br[kk][nn] = (float)rb[t].x;
+      Bi[kk][nn] = (float)rb[t].y;
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += KT) {
+    stage();
+    __syncthreads();
+    if (k0 + KT < kend) fetch(k0 + KT);
+#pragma unroll
+    for (int k4 = 0; k4 < KT / 4; ++k4) {
+      const int kk = k4 * 4 + (lane >> 4);
+      float ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int mm = wm * 32 + i * 16 + (lane & 15);
+        ar[i] = Ar[kk][mm];
+        ai[i] = Ai[kk][mm];
+        nai[i] = -ai[i];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int nn = wn * 32 + j * 16 + (lane & 15);
+        br[j] = Br[kk][nn];
+        bi[j] = Bi[kk][nn];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], br[j], cr[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[i], bi[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bi[j], ci[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], br[j], ci[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  if (ksplit > 1) {
+    cplx* P = g.ws + ((long)slice * gemm_nbatch(g) + bz) * (long)g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+          const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+          if (m < g.M && n < g.N) P[(long)m * g.N + n] = make_double2(cr[i][j][r], ci[i][j][r]);
+        }
+    return;
+  }
+  cplx* C = g.C + oc;
+  const bool zb = (g.beta.x == 0.0 && g.beta.y == 0.0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (m >= g.M || n >= g.N) continue;
+        const double re = cr[i][j][r], im = ci[i][j][r];
+        cplx out = make_double2(g.alpha.x * re - g.alpha.y * im, g.alpha.x * im + g.alpha.y * re);
+        cplx* cp = C + (long)m * g.ldc + n;
+        if (!zb) {
+          const cplx c0 = *cp;
+          out.x += g.beta.x * c0.x - g.beta.y * c0.y;
+          out.y += g.beta.x * c0.y + g.beta.y * c0.x;
+        }
+        *cp = out;
+      }
+}
+
 // C = alpha * sum_s ws[s] + beta * C, slices added in order s = 0, 1, ...
 __global__ __launch_bounds__(256) void k_zgemm_reduce(GemmArgs g, int ksplit) {
   const long mn = (long)g.M * g.N, nb = gemm_nbatch(g);
@@ -239,7 +393,8 @@ bool gemm_mfma(const GemmArgs& g, hipStream_t s) {
   const int kchunk = (per + KT - 1) / KT * KT;
   ks = (g.K + kchunk - 1) / kchunk;
   dim3 grid((g.N + NT - 1) / NT, (g.M + MT - 1) / MT, (unsigned)(nb * ks));
-  hipLaunchKernelGGL(k_zgemm_mfma, grid, dim3(NTHR), 0, s, g, ks, kchunk);
+  if (g.fp32) hipLaunchKernelGGL(k_zgemm_mfma32, grid, dim3(NTHR), 0, s, g, ks, kchunk);
+  else hipLaunchKernelGGL(k_zgemm_mfma, grid, dim3(NTHR), 0, s, g, ks, kchunk);
   check(hipGetLastError(), "zgemm_mfma launch");
   if (ks > 1) {
     const long total = nb * g.M * (long)g.N;

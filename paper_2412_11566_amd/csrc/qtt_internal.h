@@ -40,6 +40,9 @@ struct GemmArgs {
   // b3 * s?3; the batch index is z = (b1 * nb2 + b2) * nb3 + b3
   int nb3 = 1;
   long sA3 = 0, sB3 = 0, sC3 = 0;
+  // matrix-core path only: FP32 operands and accumulation (the vector
+  // kernel for thin shapes always computes in FP64)
+  bool fp32 = false;
   // split-K workspace of the matrix-core path (gemm_ws_elems entries for
   // ksplit slices); ksplit = 1 or ws = nullptr: no split
   cplx* ws = nullptr;

@@ -67,3 +67,18 @@ def test_batch_mixed_sizes_and_masks(ctx):
     for (ph, lame, lame0), C in zip(probs, Cb):
         Cs, _, _ = q.ls_solve(ctx, ph, lame, lame0, opts)
         assert rel(C, Cs) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_random_spheres_16(ctx, prec):
+    """The batched workload's random-sphere recipe on 16^3 (cap = largest
+    structural rank, delta 1e-7, tol 1e-5), batched with FP64 or FP32
+    contractions: each C_eff within 1e-5 of the converged dense scheme."""
+    ps = [M.config_c3_structure(i, grid_n=4) for i in range(4)]
+    opts = q.SolveOptions(delta=1e-7, tol=1e-5, cap=ps[0].cap, max_iter=400,
+                          precision=q.QTT_PREC_FP32 if prec == "fp32" else q.QTT_PREC_FP64)
+    Cb, reps = q.batch_solve(ctx, [(p.phase, p.lame, p.lame0) for p in ps], opts)
+    for p, C, rep in zip(ps, Cb, reps):
+        Co, _ = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=1e-10)
+        assert rep.status == 0
+        assert rel(C, Co) < 1e-5

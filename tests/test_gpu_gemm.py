@@ -45,6 +45,28 @@ def test_zgemm(ctx, path, ops):
         assert err < 64 * K * 2.2e-16, (M, N, K, ops, path, err)
 
 
+@pytest.mark.parametrize("ops", ["NN", "CN", "NT"])
+def test_zgemm_fp32_matrix_cores(ctx, ops):
+    """FP32 operands and accumulation (the QTT_PREC_FP32 contractions):
+    error within the FP32 bound sqrt(K)-scaled, against an FP64 reference."""
+    import torch
+    import paper_2412_11566_amd as q
+    rng = np.random.default_rng(9)
+    for (M, N, K) in [(32, 32, 8), (70, 45, 33), (160, 80, 800), (128, 256, 96), (64, 64, 2000)]:
+        a = _rand(rng, 2, *((M, K) if ops[0] == "N" else (K, M)))
+        b = _rand(rng, 2, *((K, N) if ops[1] == "N" else (N, K)))
+        ref = _op(a, ops[0]) @ _op(b, ops[1])
+        A = torch.from_numpy(a).cuda()
+        B = torch.from_numpy(b).cuda()
+        Cm = torch.zeros((2, M, N), dtype=torch.complex128, device="cuda")
+        q.zgemm(ctx, A, B, Cm, ops[0], ops[1], 1.0, 0.0, path=3)
+        out = Cm.cpu().numpy()
+        # entries of a and b are O(1): |error| ~ sqrt(K) * 6e-8 * |a||b| per term
+        err = np.abs(out - ref).max() / np.sqrt(K)
+        assert err < 5e-6, (M, N, K, ops, err)
+        assert np.abs(out - ref).max() > 0.0   # really computed in FP32
+
+
 def test_zgemm_mfma_rejects_small(ctx):
     import torch
     import paper_2412_11566_amd as q

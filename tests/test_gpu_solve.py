@@ -67,3 +67,15 @@ def test_c0_cap32_binding(ctx):
     assert rep.max_rank <= 32
     assert max(rep.residual) < 0.1
     assert rel(C, Cref) < 1e-2
+
+
+def test_c0_fp32_contractions(ctx):
+    """FP32 contractions (FP64 sketches, QR, SVD and residuals): C_eff of the
+    16^3 sphere within 1e-5 of the converged dense scheme at tol 1e-5 (the
+    fixed point stalls near 1e-6 in FP32)."""
+    p = M.config_c0()
+    opts = q.SolveOptions(delta=1e-8, tol=1e-5, cap=128, max_iter=200, precision=q.QTT_PREC_FP32)
+    C, rep, _ = q.ls_solve(ctx, p.phase, p.lame, p.lame0, opts)
+    Cref, _ = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=1e-12)
+    assert rep.status == 0
+    assert rel(C, Cref) < 1e-5
