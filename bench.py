@@ -37,6 +37,26 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (= matrix) peak
 PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 matrix (dense)
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE passes, scaled by
+# the same counters on a plain copy (profiles/zgemm_mfma_256_fibres_hbm_counters.md);
+# valid only while the kernel source is the one that was measured.
+MEASURED_TRAFFIC = {
+    "gemm_mfma": {"bytes_per_launch": 173.0e6,
+                  "source": "paper_2412_11566_amd/csrc/kernels_mfma.hip",
+                  "sha256": "67d3b046409172c090b7fcd27e5a5ca0fe5ce0cd39aafe765d2d635f2d82e232"},
+}
+
+
+def measured_traffic(family):
+    import hashlib
+    m = MEASURED_TRAFFIC.get(family)
+    if not m:
+        return None
+    with open(os.path.join(ROOT, m["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != m["sha256"]:
+            return None   # the kernel changed since the counters were taken
+    return m["bytes_per_launch"]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -170,7 +190,20 @@ def main():
     ap.add_argument("--max-iter", type=int, default=110,
                     help="updates per load case (the cap-64 strain plateaus above tol; 110 "
                          "is the dense scheme's count to 1e-6 on this geometry)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run 5 plain device-to-device copies of BYTES bytes (the "
+                         "reference for the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        import torch
+        n = args.copy_calibration // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the six load cases and independent structures would shard across GPUs with "
@@ -237,7 +270,9 @@ def main():
     roofline = {"bound": "mfma" if dom["family"].startswith("gemm_mfma") else "alu",
                 "kernel": dom["family"], "achieved": achieved,
                 "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "launches": dom["launches"],
+                "traffic": measured_traffic(dom["family"]),
+                "algorithmic_bytes_per_launch": dom["bytes"] / max(dom["launches"], 1),
+                "launches": dom["launches"],
                 "avg_launch_us": 1e6 * dom["seconds"] / max(dom["launches"], 1),
                 "time_share": dom["seconds"] / elapsed}
     err = golden_error(C, "c2") if args.n == 8 else None
