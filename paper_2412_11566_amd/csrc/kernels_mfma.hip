@@ -32,11 +32,18 @@ constexpr int PAD = 2;
 constexpr int NTHR = 256;
 constexpr int PER_T = MT * KT / NTHR;  // staged elements per thread and operand (4)
 
-__global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int kchunk) {
+// FP64 kernel over a WM x WN grid of waves, each wave BM x BN MFMA blocks
+// of 16 x 16: 64 x 64 tiles (2 x 2 waves of 2 x 2 blocks) for large outputs,
+// 32 x 32 tiles (2 x 2 waves of one block) when 64 x 64 tiles would leave
+// compute units idle.
+template <int WM, int WN, int BM, int BN>
+__global__ __launch_bounds__(64 * WM * WN) void k_zgemm_mfma(GemmArgs g, int ksplit, int kchunk) {
+  constexpr int MT = 16 * BM * WM, NT = 16 * BN * WN, NTHR = 64 * WM * WN;
+  constexpr int PER_TA = MT * KT / NTHR, PER_TB = NT * KT / NTHR;
   __shared__ double Ar[KT][MT + PAD], Ai[KT][MT + PAD];
   __shared__ double Br[KT][NT + PAD], Bi[KT][NT + PAD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w >> 1, wn = w & 1;   // wave position in the 2 x 2 grid
+  const int wm = w / WN, wn = w % WN;   // wave position in the grid
   const int m0 = blockIdx.y * MT, n0 = blockIdx.x * NT;
   const int bz = blockIdx.z / ksplit, slice = blockIdx.z % ksplit;
   long oa, ob, oc;
@@ -45,19 +52,19 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int
   const cplx* B = g.B + ob;
   const int kbeg = slice * kchunk, kend = min(g.K, kbeg + kchunk);
 
-  dv4 cr[2][2], ci[2][2];
+  dv4 cr[BM][BN], ci[BM][BN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < BM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < BN; ++j) {
       cr[i][j] = dv4{0.0, 0.0, 0.0, 0.0};
       ci[i][j] = dv4{0.0, 0.0, 0.0, 0.0};
     }
 
-  cplx ra[PER_T], rb[PER_T];
+  cplx ra[PER_TA], rb[PER_TB];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int t = 0; t < PER_T; ++t) {
+    for (int t = 0; t < PER_TA; ++t) {
       const int e = tid + NTHR * t;
       int mm, kk;
       if (g.opA == OP_N) { kk = e % KT; mm = e / KT; }
@@ -74,7 +81,7 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int
       ra[t] = v;
     }
 #pragma unroll
-    for (int t = 0; t < PER_T; ++t) {
+    for (int t = 0; t < PER_TB; ++t) {
       const int e = tid + NTHR * t;
       int nn, kk;
       if (g.opB == OP_N) { nn = e % NT; kk = e / NT; }
@@ -93,7 +100,7 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int
   };
   auto stage = [&]() {
 #pragma unroll
-    for (int t = 0; t < PER_T; ++t) {
+    for (int t = 0; t < PER_TA; ++t) {
       const int e = tid + NTHR * t;
       int mm, kk;
       if (g.opA == OP_N) { kk = e % KT; mm = e / KT; }
@@ -102,7 +109,7 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int
       Ai[kk][mm] = ra[t].y;
     }
 #pragma unroll
-    for (int t = 0; t < PER_T; ++t) {
+    for (int t = 0; t < PER_TB; ++t) {
       const int e = tid + NTHR * t;
       int nn, kk;
       if (g.opB == OP_N) { nn = e % NT; kk = e / NT; }
@@ -120,24 +127,24 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int
 #pragma unroll
     for (int k4 = 0; k4 < KT / 4; ++k4) {
       const int kk = k4 * 4 + (lane >> 4);
-      double ar[2], ai[2], nai[2], br[2], bi[2];
+      double ar[BM], ai[BM], nai[BM], br[BN], bi[BN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int mm = wm * 32 + i * 16 + (lane & 15);
+      for (int i = 0; i < BM; ++i) {
+        const int mm = wm * 16 * BM + i * 16 + (lane & 15);
         ar[i] = Ar[kk][mm];
         ai[i] = Ai[kk][mm];
         nai[i] = -ai[i];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int nn = wn * 32 + j * 16 + (lane & 15);
+      for (int j = 0; j < BN; ++j) {
+        const int nn = wn * 16 * BN + j * 16 + (lane & 15);
         br[j] = Br[kk][nn];
         bi[j] = Bi[kk][nn];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < BM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < BN; ++j) {
           cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
           cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cr[i][j], 0, 0, 0);
           ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
@@ -151,13 +158,13 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int
     // raw partial sums of this K slice: ws[slice][bz][m][n]
     cplx* P = g.ws + ((long)slice * gemm_nbatch(g) + bz) * (long)g.M * g.N;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < BM; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < BN; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wm * 32 + i * 16 + 4 * r + (lane >> 4);
-          const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+          const int m = m0 + wm * 16 * BM + i * 16 + 4 * r + (lane >> 4);
+          const int n = n0 + wn * 16 * BN + j * 16 + (lane & 15);
           if (m < g.M && n < g.N) P[(long)m * g.N + n] = make_double2(cr[i][j][r], ci[i][j][r]);
         }
     return;
@@ -165,13 +172,13 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma(GemmArgs g, int ksplit, int
   cplx* C = g.C + oc;
   const bool zb = (g.beta.x == 0.0 && g.beta.y == 0.0);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < BM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < BN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm * 32 + i * 16 + 4 * r + (lane >> 4);
-        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+        const int m = m0 + wm * 16 * BM + i * 16 + 4 * r + (lane >> 4);
+        const int n = n0 + wn * 16 * BN + j * 16 + (lane & 15);
         if (m >= g.M || n >= g.N) continue;
         const double re = cr[i][j][r], im = ci[i][j][r];
         cplx out = make_double2(g.alpha.x * re - g.alpha.y * im, g.alpha.x * im + g.alpha.y * re);
@@ -366,14 +373,24 @@ __global__ __launch_bounds__(256) void k_zgemm_reduce(GemmArgs g, int ksplit) {
 
 }  // namespace
 
-bool gemm_mfma_ok(int M, int N, int K) { return M >= 32 && N >= 32 && K >= 8 && (M + MT - 1) / MT <= 65535; }
+bool gemm_mfma_ok(int M, int N, int K) { return M >= 32 && N >= 32 && K >= 8 && (M + 31) / 32 <= 65535; }
+
+// tile of the FP64 path: 32 x 32 (one wave) when 64 x 64 tiles would give
+// fewer than two workgroups per compute unit
+static bool small_tiles(int M, int N, long nbatch) {
+  const long tiles64 = (long)((M + 63) / 64) * ((N + 63) / 64) * nbatch;
+  return tiles64 < 512;
+}
 
 int gemm_ksplit(int M, int N, int K, long nbatch) {
   if (!gemm_mfma_ok(M, N, K)) return 1;
-  const long tiles = (long)((M + MT - 1) / MT) * ((N + NT - 1) / NT) * nbatch;
-  if (tiles >= 192 || K < 4 * KT) return 1;
-  // aim at ~512 workgroups, every slice at least 2 stages of K
-  long s = std::min<long>((512 + tiles - 1) / tiles, K / (2 * KT));
+  const bool sm = small_tiles(M, N, nbatch);
+  const int t = sm ? 32 : 64;
+  const long tiles = (long)((M + t - 1) / t) * ((N + t - 1) / t) * nbatch;
+  const long want = sm ? 1024 : 512;   // workgroups to aim at (4 waves each)
+  if (tiles >= want / 2 || K < 4 * KT) return 1;
+  // every slice at least 2 stages of K
+  long s = std::min<long>((want + tiles - 1) / tiles, K / (2 * KT));
   s = std::min<long>(s, 32);
   if (tiles * s > 65535) s = 65535 / tiles;
   return (int)std::max<long>(1, s);
@@ -392,9 +409,17 @@ bool gemm_mfma(const GemmArgs& g, hipStream_t s) {
   const int per = (g.K + ks - 1) / ks;
   const int kchunk = (per + KT - 1) / KT * KT;
   ks = (g.K + kchunk - 1) / kchunk;
-  dim3 grid((g.N + NT - 1) / NT, (g.M + MT - 1) / MT, (unsigned)(nb * ks));
-  if (g.fp32) hipLaunchKernelGGL(k_zgemm_mfma32, grid, dim3(NTHR), 0, s, g, ks, kchunk);
-  else hipLaunchKernelGGL(k_zgemm_mfma, grid, dim3(NTHR), 0, s, g, ks, kchunk);
+  if (g.fp32) {
+    dim3 grid((g.N + NT - 1) / NT, (g.M + MT - 1) / MT, (unsigned)(nb * ks));
+    if (grid.y > 65535u) return false;
+    hipLaunchKernelGGL(k_zgemm_mfma32, grid, dim3(NTHR), 0, s, g, ks, kchunk);
+  } else if (small_tiles(g.M, g.N, nb)) {
+    dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, (unsigned)(nb * ks));
+    hipLaunchKernelGGL((k_zgemm_mfma<2, 2, 1, 1>), grid, dim3(256), 0, s, g, ks, kchunk);
+  } else {
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, (unsigned)(nb * ks));
+    hipLaunchKernelGGL((k_zgemm_mfma<2, 2, 2, 2>), grid, dim3(256), 0, s, g, ks, kchunk);
+  }
   check(hipGetLastError(), "zgemm_mfma launch");
   if (ks > 1) {
     const long total = nb * g.M * (long)g.N;
