@@ -187,6 +187,8 @@ def main():
                     help="skip the adjoint solve (gradient cost ratio)")
     ap.add_argument("--batch", type=int, default=4,
                     help="structures in the batched-vs-plain comparison (0: skip)")
+    ap.add_argument("--oversample", type=int, default=16,
+                    help="sketch rank beyond the cap (randomized rounding)")
     ap.add_argument("--max-iter", type=int, default=110,
                     help="updates per load case (the cap-64 strain plateaus above tol; 110 "
                          "is the dense scheme's count to 1e-6 on this geometry)")
@@ -224,9 +226,10 @@ def main():
     setup_s = time.perf_counter() - t
     log(f"setup (operators) {setup_s:.1f} s")
     opts = q.SolveOptions(delta=p.delta, tol=p.tol, cap=p.cap, max_iter=args.max_iter,
-                          oversample=16, seed=2024)
+                          oversample=args.oversample, seed=2024)
     for w in range(args.warmup):
-        wo = q.SolveOptions(delta=p.delta, tol=p.tol, cap=p.cap, max_iter=2, oversample=16, seed=1)
+        wo = q.SolveOptions(delta=p.delta, tol=p.tol, cap=p.cap, max_iter=2, oversample=args.oversample,
+                            seed=1)
         q.ls_solve_prepared(ctx, prep, wo)
     q.stats_enable(ctx, True)
     q.stats_reset(ctx)
@@ -299,7 +302,7 @@ def main():
         "config": {"workload": f"{p.N}^3 four z-fibres R=0.15, E 20/1, nu 0.25/0.35, "
                                f"6 load cases, cap {p.cap}, delta {p.delta:g}, tol {p.tol:g}",
                    "n": args.n, "cores": 3 * args.n + 1, "cap": p.cap, "delta": p.delta,
-                   "tol": p.tol, "oversample": 16},
+                   "tol": p.tol, "oversample": args.oversample},
         "iterations_per_load_case": reps[-1].iterations,
         "ceff_rel_error_vs_oracle": err,
         "setup_seconds": setup_s,

@@ -675,6 +675,24 @@ __device__ __forceinline__ double dpp_xor2(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x4E, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ double dpp_half_mirror(double v) {   // lane i <- lane 7 - i (per 8)
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x141, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x141, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double dpp_mirror(double v) {        // lane i <- lane 15 - i (per 16)
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x140, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x140, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// sum over the 16 lanes of a DPP row, returned to every lane of the row
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_xor1(v);
+  v += dpp_xor2(v);
+  v += dpp_half_mirror(v);
+  v += dpp_mirror(v);
+  return v;
+}
 __device__ __forceinline__ cplx quad_sum(cplx p) {
   p.x += dpp_xor1(p.x);
   p.y += dpp_xor1(p.y);
@@ -977,11 +995,9 @@ __global__ __launch_bounds__(JNT) void k_jacobi_lds(int n, MatView A, MatOut U, 
           const cplx t = cdotc(xa[i], xb[i]);
           ga = make_double2(ga.x + t.x, ga.y + t.y);
         }
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-          ga.x += __shfl_xor(ga.x, o, 16);
-          ga.y += __shfl_xor(ga.y, o, 16);
-        }
+        // the 16 lanes of a pair are one DPP row
+        ga.x = row16_sum(ga.x);
+        ga.y = row16_sum(ga.y);
         const double al = nrm2[ca], be = nrm2[cb];
         const double gg = sqrt(cabs2(ga));
         if (!(gg > tol * sqrt(al * be)) || al < 1e-300 || be < 1e-300) continue;
