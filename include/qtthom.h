@@ -255,10 +255,13 @@ int ls_adjoint_prepared(qtt_ctx* ctx, const qtt_prepared* prep,
  * batch strides sA/sB/sC in complex elements; alpha, beta are host
  * {re, im}.  The library cannot see the extent of caller memory: the
  * caller guarantees every addressed element lies in its allocation.
- * path: 0 automatic (matrix cores for M, N >= 32 and K >= 8, else vector
+ * path: 0 automatic (matrix cores for M, N >= 16 and K >= 4, else vector
  * ALU), 1 vector ALU, 2 matrix cores (QTT_EINVAL if the shape is outside
  * its range), 3 matrix cores with FP32 operands and accumulation (the
- * contraction precision of QTT_PREC_FP32; results stored as doubles).
+ * contraction precision of QTT_PREC_FP32; results stored as doubles),
+ * 4 + t matrix cores in FP64 with tile variant t forced instead of chosen
+ * per shape (t = 0..6: 16x16, 32x32, 64x64, 80x80, 32x80, 80x32, 64x80;
+ * for tests and tuning).
  * Asynchronous on the context's stream.  QTT_EINVAL on null pointers,
  * K < 1, batch outside [1, 65535] or leading dimensions smaller than a
  * row. */

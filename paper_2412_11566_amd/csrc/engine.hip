@@ -250,13 +250,13 @@ static void GB(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long l
   if (K == 0) throw std::logic_error("gemm with empty contraction");
   const double nb = (double)t.nb1 * t.nb2 * t.nb3;
   BufP ws;
-  const int ks = gemm_ksplit(M, N, K, (long)nb);
+  g.fp32 = X.c->gemm_fp32;
+  const int ks = gemm_ksplit(M, N, K, (long)nb, g.fp32);
   if (ks > 1) {
     ws = X.buf(gemm_ws_elems(g, ks));
     g.ws = (cplx*)ws->p;
     g.ksplit = ks;
   }
-  g.fp32 = X.c->gemm_fp32;
   hipEvent_t e = X.t0();
   const bool mc = gemm(g, X.s());
   X.t1(e, mc ? (g.fp32 ? QTT_K_MFMA32 : QTT_K_MFMA) : QTT_K_GEMM, 8.0 * M * N * K * nb,
@@ -806,10 +806,17 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
       for (int b = 0; b < B; ++b)
         ck_copy2d(X, r, rho, (int)m, MatView{(cplx*)X2->p + (long)b * r * rho * m, m, 1, rho * m, 0},
                   MatOut{(cplx*)W[k]->p + (long)b * rho * r * m, (long)r * m, 1, m}, C1(), X.s());
-    } else {
+    } else if (rho >= r) {
+      // rows a of X2[b][c] against Omega_k: one product per (b, c)
       G(X, rho, l, dout * l2, OP_N, (cplx*)X2->p, (long)dout * l2, OP_T, (cplx*)Om[k]->p,
         (long)dout * l2, (cplx*)W[k]->p, (long)r * l, B, (long)r * rho * dout * l2, 0,
         (long)rho * r * l, r, (long)rho * dout * l2, 0, l);
+    } else {
+      // rows c (stride rho dout l2) against Omega_k: one product per (b, a),
+      // the longer of the two row counts on the matrix-core M side
+      G(X, r, l, dout * l2, OP_N, (cplx*)X2->p, (long)rho * dout * l2, OP_T, (cplx*)Om[k]->p,
+        (long)dout * l2, (cplx*)W[k]->p, (long)l, B, (long)r * rho * dout * l2, 0,
+        (long)rho * r * l, rho, (long)dout * l2, 0, (long)r * l);
     }
   }
   // left-to-right: QR of sketched unfoldings
@@ -1904,7 +1911,7 @@ int qtt_zgemm(qtt_ctx* c, int opA, int opB, int M, int N, int K, const double* a
               long ldc, int batch, long sA, long sB, long sC, int path) {
   if (!c || !alpha || !beta || !A || !B || !Cm) return QTT_EINVAL;
   if (M < 0 || N < 0 || K < 1 || batch < 1 || batch > 65535 || opA < 0 || opA > 2 || opB < 0 ||
-      opB > 2 || path < 0 || path > 3)
+      opB > 2 || path < 0 || path > 3 + gemm_num_tiles())
     return QTT_EINVAL;
   if (lda < (opA == OP_N ? K : M) || ldb < (opB == OP_N ? N : K) || ldc < N) return QTT_EINVAL;
   QTT_TRY(c, {
@@ -1918,17 +1925,18 @@ int qtt_zgemm(qtt_ctx* c, int opA, int opB, int M, int N, int K, const double* a
     g.beta = make_double2(beta[0], beta[1]);
     if (M == 0 || N == 0) return;
     BufP ws;
-    const int ks = path == 1 ? 1 : gemm_ksplit(M, N, K, batch);
+    g.fp32 = path == 3;
+    g.tile = path >= 4 ? path - 4 : -1;
+    const int ks = path == 1 ? 1 : gemm_ksplit(M, N, K, batch, g.fp32, g.tile);
     if (ks > 1) {
       ws = std::make_shared<Buf>(c->pool, gemm_ws_elems(g, ks) * sizeof(cplx));
       g.ws = (cplx*)ws->p;
       g.ksplit = ks;
     }
-    g.fp32 = path == 3;
     if (path == 0) gemm(g, c->stream);
     else if (path == 1) gemm_vector(g, c->stream);
     else if (!gemm_mfma(g, c->stream))
-      throw std::invalid_argument("zgemm: shape not handled by the matrix-core kernel (needs M, N >= 32, K >= 8)");
+      throw std::invalid_argument("zgemm: shape not handled by the matrix-core kernel (needs M, N >= 16, K >= 4)");
   });
 }
 

@@ -1,7 +1,8 @@
 // Complex FP64 GEMM on the CDNA matrix cores (v_mfma_f64_16x16x4f64).
 //
-// One workgroup computes a 64 x 64 complex tile of C with 4 waves (2 x 2),
-// each wave a 32 x 32 sub-tile made of 2 x 2 MFMA blocks of 16 x 16.  The
+// One workgroup computes a complex tile of C with a grid of waves, each
+// wave a sub-tile of 16 x 16 MFMA blocks (tiles from 16 x 16 to 80 x 80,
+// chosen per shape to limit padding and fill the compute units).  The
 // complex product is four real MFMAs per block (re*re, -im*im, re*im,
 // im*re) into separate real and imaginary accumulators.  A and B stage
 // through LDS in split real/imaginary planes, 16 complex values of K per
@@ -12,7 +13,7 @@
 //   D: lane l, register r holds D[4 r + l / 16][l % 16].
 //
 // Shapes with few output tiles and a long contraction (the sketch products
-// of TT-rounding: 160 x 80 outputs over K = 800) split K over workgroups;
+// of TT-rounding: 160 x 80 outputs over K = 12240) split K over workgroups;
 // each slice writes its partial sums to a workspace and a second kernel
 // adds the slices in fixed order (deterministic) and applies alpha, beta.
 #include "qtt_internal.h"
@@ -33,11 +34,9 @@ constexpr int NTHR = 256;
 constexpr int PER_T = MT * KT / NTHR;  // staged elements per thread and operand (4)
 
 // FP64 kernel over a WM x WN grid of waves, each wave BM x BN MFMA blocks
-// of 16 x 16: 64 x 64 tiles (2 x 2 waves of 2 x 2 blocks) for large outputs,
-// 32 x 32 tiles (2 x 2 waves of one block) when 64 x 64 tiles would leave
-// compute units idle.
+// of 16 x 16 (tile variants and their choice: plan_fp64 below).
 template <int WM, int WN, int BM, int BN>
-__global__ __launch_bounds__(64 * WM * WN) void k_zgemm_mfma(GemmArgs g, int ksplit, int kchunk) {
+__global__ __launch_bounds__(64 * WM * WN, 2) void k_zgemm_mfma(GemmArgs g, int ksplit, int kchunk) {
   constexpr int MT = 16 * BM * WM, NT = 16 * BN * WN, NTHR = 64 * WM * WN;
   constexpr int PER_TA = MT * KT / NTHR, PER_TB = NT * KT / NTHR;
   __shared__ double Ar[KT][MT + PAD], Ai[KT][MT + PAD];
@@ -61,8 +60,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_zgemm_mfma(GemmArgs g, int ksp
       ci[i][j] = dv4{0.0, 0.0, 0.0, 0.0};
     }
 
+  // fetch: raw loads only (indices clamped in range, validity kept in a
+  // mask) so no load waits on its data before the stage that stores it;
+  // stage: mask, conjugate and split into the LDS planes
   cplx ra[PER_TA], rb[PER_TB];
+  unsigned oka = 0u, okb = 0u;
   auto fetch = [&](int k0) {
+    oka = 0u;
+    okb = 0u;
 #pragma unroll
     for (int t = 0; t < PER_TA; ++t) {
       const int e = tid + NTHR * t;
@@ -70,15 +75,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_zgemm_mfma(GemmArgs g, int ksp
       if (g.opA == OP_N) { kk = e % KT; mm = e / KT; }
       else { mm = e % MT; kk = e / MT; }
       const int m = m0 + mm, k = k0 + kk;
-      cplx v = make_double2(0.0, 0.0);
-      if (m < g.M && k < kend) {
-        if (g.opA == OP_N) v = A[(long)m * g.lda + k];
-        else {
-          v = A[(long)k * g.lda + m];
-          if (g.opA == OP_C) v.y = -v.y;
-        }
-      }
-      ra[t] = v;
+      const bool ok = m < g.M && k < kend;
+      const long idx = g.opA == OP_N ? (long)m * g.lda + k : (long)k * g.lda + m;
+      ra[t] = A[ok ? idx : 0];
+      oka |= ok ? (1u << t) : 0u;
     }
 #pragma unroll
     for (int t = 0; t < PER_TB; ++t) {
@@ -87,17 +87,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_zgemm_mfma(GemmArgs g, int ksp
       if (g.opB == OP_N) { nn = e % NT; kk = e / NT; }
       else { kk = e % KT; nn = e / KT; }
       const int n = n0 + nn, k = k0 + kk;
-      cplx v = make_double2(0.0, 0.0);
-      if (n < g.N && k < kend) {
-        if (g.opB == OP_N) v = B[(long)k * g.ldb + n];
-        else {
-          v = B[(long)n * g.ldb + k];
-          if (g.opB == OP_C) v.y = -v.y;
-        }
-      }
-      rb[t] = v;
+      const bool ok = n < g.N && k < kend;
+      const long idx = g.opB == OP_N ? (long)k * g.ldb + n : (long)n * g.ldb + k;
+      rb[t] = B[ok ? idx : 0];
+      okb |= ok ? (1u << t) : 0u;
     }
   };
+  const double sa = g.opA == OP_C ? -1.0 : 1.0, sb = g.opB == OP_C ? -1.0 : 1.0;
   auto stage = [&]() {
 #pragma unroll
     for (int t = 0; t < PER_TA; ++t) {
@@ -105,8 +101,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_zgemm_mfma(GemmArgs g, int ksp
       int mm, kk;
       if (g.opA == OP_N) { kk = e % KT; mm = e / KT; }
       else { mm = e % MT; kk = e / MT; }
-      Ar[kk][mm] = ra[t].x;
-      Ai[kk][mm] = ra[t].y;
+      const bool ok = (oka >> t) & 1u;
+      Ar[kk][mm] = ok ? ra[t].x : 0.0;
+      Ai[kk][mm] = ok ? sa * ra[t].y : 0.0;
     }
 #pragma unroll
     for (int t = 0; t < PER_TB; ++t) {
@@ -114,8 +111,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_zgemm_mfma(GemmArgs g, int ksp
       int nn, kk;
       if (g.opB == OP_N) { nn = e % NT; kk = e / NT; }
       else { kk = e % KT; nn = e / KT; }
-      Br[kk][nn] = rb[t].x;
-      Bi[kk][nn] = rb[t].y;
+      const bool ok = (okb >> t) & 1u;
+      Br[kk][nn] = ok ? rb[t].x : 0.0;
+      Bi[kk][nn] = ok ? sb * rb[t].y : 0.0;
     }
   };
 
@@ -217,8 +215,13 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma32(GemmArgs g, int ksplit, i
       cr[i][j] = fv4{0.f, 0.f, 0.f, 0.f};
       ci[i][j] = fv4{0.f, 0.f, 0.f, 0.f};
     }
+  // raw loads at fetch, mask / conjugate / round at stage (as in the FP64
+  // kernel)
   cplx ra[PER_T], rb[PER_T];
+  unsigned oka = 0u, okb = 0u;
   auto fetch = [&](int k0) {
+    oka = 0u;
+    okb = 0u;
 #pragma unroll
     for (int t = 0; t < PER_T; ++t) {
       const int e = tid + NTHR * t;
@@ -226,15 +229,10 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma32(GemmArgs g, int ksplit, i
       if (g.opA == OP_N) { kk = e % KT; mm = e / KT; }
       else { mm = e % MT; kk = e / MT; }
       const int m = m0 + mm, k = k0 + kk;
-      cplx v = make_double2(0.0, 0.0);
-      if (m < g.M && k < kend) {
-        if (g.opA == OP_N) v = A[(long)m * g.lda + k];
-        else {
-          v = A[(long)k * g.lda + m];
-          if (g.opA == OP_C) v.y = -v.y;
-        }
-      }
-      ra[t] = v;
+      const bool ok = m < g.M && k < kend;
+      const long idx = g.opA == OP_N ? (long)m * g.lda + k : (long)k * g.lda + m;
+      ra[t] = A[ok ? idx : 0];
+      oka |= ok ? (1u << t) : 0u;
     }
 #pragma unroll
     for (int t = 0; t < PER_T; ++t) {
@@ -243,17 +241,13 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma32(GemmArgs g, int ksplit, i
       if (g.opB == OP_N) { nn = e % NT; kk = e / NT; }
       else { kk = e % KT; nn = e / KT; }
       const int n = n0 + nn, k = k0 + kk;
-      cplx v = make_double2(0.0, 0.0);
-      if (n < g.N && k < kend) {
-        if (g.opB == OP_N) v = B[(long)k * g.ldb + n];
-        else {
-          v = B[(long)n * g.ldb + k];
-          if (g.opB == OP_C) v.y = -v.y;
-        }
-      }
-      rb[t] = v;
+      const bool ok = n < g.N && k < kend;
+      const long idx = g.opB == OP_N ? (long)k * g.ldb + n : (long)n * g.ldb + k;
+      rb[t] = B[ok ? idx : 0];
+      okb |= ok ? (1u << t) : 0u;
     }
   };
+  const float sa = g.opA == OP_C ? -1.f : 1.f, sb = g.opB == OP_C ? -1.f : 1.f;
   auto stage = [&]() {
 #pragma unroll
     for (int t = 0; t < PER_T; ++t) {
@@ -261,8 +255,9 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma32(GemmArgs g, int ksplit, i
       int mm, kk;
       if (g.opA == OP_N) { kk = e % KT; mm = e / KT; }
       else { mm = e % MT; kk = e / MT; }
-      Ar[kk][mm] = (float)ra[t].x;
-      Ai[kk][mm] = (float)ra[t].y;
+      const bool ok = (oka >> t) & 1u;
+      Ar[kk][mm] = ok ? (float)ra[t].x : 0.f;
+      Ai[kk][mm] = ok ? sa * (float)ra[t].y : 0.f;
     }
 #pragma unroll
     for (int t = 0; t < PER_T; ++t) {
@@ -270,8 +265,9 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma32(GemmArgs g, int ksplit, i
       int nn, kk;
       if (g.opB == OP_N) { nn = e % NT; kk = e / NT; }
       else { kk = e % KT; nn = e / KT; }
-      Br[kk][nn] = (float)rb[t].x;
-      Bi[kk][nn] = (float)rb[t].y;
+      const bool ok = (okb >> t) & 1u;
+      Br[kk][nn] = ok ? (float)rb[t].x : 0.f;
+      Bi[kk][nn] = ok ? sb * (float)rb[t].y : 0.f;
     }
   };
   if (kbeg < kend) fetch(kbeg);
@@ -373,37 +369,110 @@ __global__ __launch_bounds__(256) void k_zgemm_reduce(GemmArgs g, int ksplit) {
 
 }  // namespace
 
-bool gemm_mfma_ok(int M, int N, int K) { return M >= 32 && N >= 32 && K >= 8 && (M + 31) / 32 <= 65535; }
+// FP64 tile variants (WM x WN waves of BM x BN blocks).  Sketch ranks of
+// TT-rounding put 80 (cap 64 + oversampling 16) on one side of most
+// products, which 80-wide tiles cover without padding; a wave then holds a
+// 16 x 80 (or 80 x 16) strip of five blocks.
+struct TileV {
+  int wm, wn, bm, bn;
+  int mt() const { return 16 * bm * wm; }
+  int nt() const { return 16 * bn * wn; }
+  int waves() const { return wm * wn; }
+};
+constexpr TileV kTiles[] = {
+    {1, 1, 1, 1},   // 16 x 16
+    {2, 2, 1, 1},   // 32 x 32
+    {2, 2, 2, 2},   // 64 x 64
+    {5, 1, 1, 5},   // 80 x 80
+    {2, 1, 1, 5},   // 32 x 80
+    {1, 2, 5, 1},   // 80 x 32
+    {4, 1, 1, 5},   // 64 x 80
+};
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+constexpr TileV kTileFp32 = {2, 2, 2, 2};  // the FP32 kernel's fixed tile
 
-// tile of the FP64 path: 32 x 32 (one wave) when 64 x 64 tiles would give
-// fewer than two workgroups per compute unit
-static bool small_tiles(int M, int N, long nbatch) {
-  const long tiles64 = (long)((M + 63) / 64) * ((N + 63) / 64) * nbatch;
-  return tiles64 < 512;
-}
+bool gemm_mfma_ok(int M, int N, int K) { return M >= 16 && N >= 16 && K >= 4 && (M + 15) / 16 <= 65535; }
 
-int gemm_ksplit(int M, int N, int K, long nbatch) {
-  if (!gemm_mfma_ok(M, N, K)) return 1;
-  const bool sm = small_tiles(M, N, nbatch);
-  const int t = sm ? 32 : 64;
-  const long tiles = (long)((M + t - 1) / t) * ((N + t - 1) / t) * nbatch;
-  const long want = sm ? 1024 : 512;   // workgroups to aim at (4 waves each)
-  if (tiles >= want / 2 || K < 4 * KT) return 1;
+// workgroups whose waves fill the chip twice over (1024 SIMDs) need no K split
+constexpr long kWaveTarget = 2048;
+
+static int ksplit_for(const TileV& t, int M, int N, int K, long nbatch) {
+  const long tiles = (long)((M + t.mt() - 1) / t.mt()) * ((N + t.nt() - 1) / t.nt()) * nbatch;
+  const long waves = tiles * t.waves();
+  if (waves >= kWaveTarget / 2 || K < 4 * KT) return 1;
   // every slice at least 2 stages of K
-  long s = std::min<long>((want + tiles - 1) / tiles, K / (2 * KT));
+  long s = std::min<long>((kWaveTarget + waves - 1) / waves, K / (2 * KT));
   s = std::min<long>(s, 32);
-  if (tiles * s > 65535) s = 65535 / tiles;
+  if (nbatch * s > 65535) s = 65535 / nbatch;
   return (int)std::max<long>(1, s);
 }
+
+struct Plan {
+  int v;   // index into kTiles
+  int ks;  // K slices
+};
+
+// The FP64 variant with the least modelled time: padded MFMA work over the
+// waves that run it (up to two per SIMD), with an operand-staging overhead
+// that falls with the tile size (fitted to measured rates: about 50% of the
+// matrix-core peak on padded work for 32 x 32 tiles, 62% for 64 x 64 and
+// 64 x 80), and a penalty for 5-wave workgroups, of which one fits a compute
+// unit at two waves per SIMD (one SIMD then runs two of the five waves).
+static Plan plan_fp64(int M, int N, int K, long nbatch) {
+  Plan best{2, 1};
+  double bestc = 0.0;
+  const double kp = (double)((K + KT - 1) / KT * KT);
+  for (int v = 0; v < kNumTiles; ++v) {
+    const TileV& t = kTiles[v];
+    const long tm = (M + t.mt() - 1) / t.mt(), tn = (N + t.nt() - 1) / t.nt();
+    if (tm > 65535 || tn > 65535) continue;
+    const int ks = ksplit_for(t, M, N, K, nbatch);
+    if (nbatch * ks > 65535) continue;
+    const double work = (double)tm * t.mt() * (double)tn * t.nt() * kp * nbatch;
+    const double waves = (double)tm * tn * nbatch * ks * t.waves();
+    const double par = std::min(waves, (double)kWaveTarget);
+    const double balance = t.waves() == 5 ? 5.0 / 8.0 : 1.0;
+    const double c = work / par * (1.0 + 10.0 / t.mt() + 10.0 / t.nt()) / balance;
+    if (bestc == 0.0 || c < bestc) {
+      bestc = c;
+      best = Plan{v, ks};
+    }
+  }
+  return best;
+}
+
+int gemm_ksplit(int M, int N, int K, long nbatch, bool fp32, int tile) {
+  if (!gemm_mfma_ok(M, N, K)) return 1;
+  if (fp32) return ksplit_for(kTileFp32, M, N, K, nbatch);
+  if (tile >= 0 && tile < kNumTiles) return ksplit_for(kTiles[tile], M, N, K, nbatch);
+  return plan_fp64(M, N, K, nbatch).ks;
+}
+int gemm_num_tiles() { return kNumTiles; }
 
 size_t gemm_ws_elems(const GemmArgs& g, int ksplit) {
   return ksplit > 1 ? (size_t)ksplit * gemm_nbatch(g) * (size_t)g.M * g.N : 0;
 }
 
+template <int WM, int WN, int BM, int BN>
+static void launch_fp64(const GemmArgs& g, int ks, int kchunk, hipStream_t s) {
+  constexpr int MT = 16 * BM * WM, NT = 16 * BN * WN;
+  dim3 grid((g.N + NT - 1) / NT, (g.M + MT - 1) / MT, (unsigned)(gemm_nbatch(g) * ks));
+  hipLaunchKernelGGL((k_zgemm_mfma<WM, WN, BM, BN>), grid, dim3(64 * WM * WN), 0, s, g, ks, kchunk);
+}
+
 bool gemm_mfma(const GemmArgs& g, hipStream_t s) {
   if (!gemm_mfma_ok(g.M, g.N, g.K)) return false;
-  int ks = g.ksplit > 1 && g.ws ? g.ksplit : 1;
   const long nb = gemm_nbatch(g);
+  Plan pl = g.fp32 ? Plan{-1, 1} : plan_fp64(g.M, g.N, g.K, nb);
+  if (!g.fp32 && g.tile >= 0) {
+    if (g.tile >= kNumTiles) return false;
+    const TileV& t = kTiles[g.tile];
+    if ((g.M + t.mt() - 1) / t.mt() > 65535 || (g.N + t.nt() - 1) / t.nt() > 65535) return false;
+    pl.v = g.tile;
+  }
+  if (g.fp32 && (g.M + MT - 1) / MT > 65535) return false;
+  // the split the caller sized the workspace for (gemm_ksplit), else none
+  int ks = g.ksplit > 1 && g.ws ? g.ksplit : 1;
   if (nb * ks > 65535) ks = 1;
   // slice length: a multiple of the stage depth
   const int per = (g.K + ks - 1) / ks;
@@ -411,14 +480,17 @@ bool gemm_mfma(const GemmArgs& g, hipStream_t s) {
   ks = (g.K + kchunk - 1) / kchunk;
   if (g.fp32) {
     dim3 grid((g.N + NT - 1) / NT, (g.M + MT - 1) / MT, (unsigned)(nb * ks));
-    if (grid.y > 65535u) return false;
     hipLaunchKernelGGL(k_zgemm_mfma32, grid, dim3(NTHR), 0, s, g, ks, kchunk);
-  } else if (small_tiles(g.M, g.N, nb)) {
-    dim3 grid((g.N + 31) / 32, (g.M + 31) / 32, (unsigned)(nb * ks));
-    hipLaunchKernelGGL((k_zgemm_mfma<2, 2, 1, 1>), grid, dim3(256), 0, s, g, ks, kchunk);
   } else {
-    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, (unsigned)(nb * ks));
-    hipLaunchKernelGGL((k_zgemm_mfma<2, 2, 2, 2>), grid, dim3(256), 0, s, g, ks, kchunk);
+    switch (pl.v) {
+      case 0: launch_fp64<1, 1, 1, 1>(g, ks, kchunk, s); break;
+      case 1: launch_fp64<2, 2, 1, 1>(g, ks, kchunk, s); break;
+      case 2: launch_fp64<2, 2, 2, 2>(g, ks, kchunk, s); break;
+      case 3: launch_fp64<5, 1, 1, 5>(g, ks, kchunk, s); break;
+      case 4: launch_fp64<2, 1, 1, 5>(g, ks, kchunk, s); break;
+      case 5: launch_fp64<1, 2, 5, 1>(g, ks, kchunk, s); break;
+      default: launch_fp64<4, 1, 1, 5>(g, ks, kchunk, s); break;
+    }
   }
   check(hipGetLastError(), "zgemm_mfma launch");
   if (ks > 1) {

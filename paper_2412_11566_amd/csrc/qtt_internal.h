@@ -47,6 +47,9 @@ struct GemmArgs {
   // ksplit slices); ksplit = 1 or ws = nullptr: no split
   cplx* ws = nullptr;
   int ksplit = 1;
+  // matrix-core FP64 tile variant forced (0 .. gemm_num_tiles() - 1), or -1:
+  // chosen per shape
+  int tile = -1;
 };
 __host__ __device__ inline long gemm_nbatch(const GemmArgs& g) { return (long)g.nb1 * g.nb2 * g.nb3; }
 __host__ __device__ inline void gemm_batch_offsets(const GemmArgs& g, long z, long& oa, long& ob, long& oc) {
@@ -58,12 +61,13 @@ __host__ __device__ inline void gemm_batch_offsets(const GemmArgs& g, long z, lo
 }
 // Returns true when the matrix-core kernel ran, false for the vector kernel.
 bool gemm(const GemmArgs& g, hipStream_t s);
-// Matrix-core path of gemm for M, N >= 32 and K >= 8 (kernels_mfma.hip);
+// Matrix-core path of gemm for M, N >= 16 and K >= 4 (kernels_mfma.hip);
 // returns false when the shape is left to the vector kernel.
 bool gemm_mfma(const GemmArgs& g, hipStream_t s);
-// The K split the matrix-core path wants for this shape (1: none) and the
-// workspace it then needs.
-int gemm_ksplit(int M, int N, int K, long nbatch);
+// The K split the matrix-core path wants for this shape and precision
+// (1: none) and the workspace it then needs.
+int gemm_ksplit(int M, int N, int K, long nbatch, bool fp32, int tile = -1);
+int gemm_num_tiles();
 size_t gemm_ws_elems(const GemmArgs& g, int ksplit);
 // Vector-ALU path of gemm (any shape).
 void gemm_vector(const GemmArgs& g, hipStream_t s);

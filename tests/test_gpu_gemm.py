@@ -7,9 +7,14 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(32, 32, 8), (64, 64, 16), (70, 45, 33), (128, 256, 96), (33, 97, 130),
-          (200, 40, 9), (16, 80, 40), (80, 12, 40), (5, 7, 3),
+          (200, 40, 9), (16, 80, 40), (80, 12, 40), (5, 7, 3), (16, 16, 4), (151, 80, 153),
+          (17, 161, 21),
           # long contractions over few output tiles: the split-K path
-          (160, 80, 800), (96, 40, 517), (64, 64, 2000)]
+          (160, 80, 800), (96, 40, 517), (64, 64, 2000), (16, 16, 1584)]
+
+
+def _mfma_shape(M, N, K):
+    return M >= 16 and N >= 16 and K >= 4
 
 
 def _rand(rng, *shape):
@@ -20,14 +25,16 @@ def _op(x, o):
     return x if o == "N" else (np.swapaxes(x, 1, 2) if o == "T" else np.conj(np.swapaxes(x, 1, 2)))
 
 
-@pytest.mark.parametrize("path", [0, 1, 2])
+@pytest.mark.parametrize("path", [0, 1, 2, 4, 5, 6, 7, 8, 9, 10])
 @pytest.mark.parametrize("ops", ["NN", "TN", "CN", "NT", "NC", "CT"])
 def test_zgemm(ctx, path, ops):
+    """path 0 automatic, 1 vector ALU, 2 matrix cores with the tile chosen
+    per shape, 4..10 matrix cores with each FP64 tile variant forced."""
     import torch
     import paper_2412_11566_amd as q
     rng = np.random.default_rng(7)
     for (M, N, K) in SHAPES:
-        if path == 2 and (M < 32 or N < 32 or K < 8):
+        if path >= 2 and not _mfma_shape(M, N, K):
             continue
         batch = 3
         a = _rand(rng, batch, *((M, K) if ops[0] == "N" else (K, M)))
@@ -70,8 +77,10 @@ def test_zgemm_fp32_matrix_cores(ctx, ops):
 def test_zgemm_mfma_rejects_small(ctx):
     import torch
     import paper_2412_11566_amd as q
-    A = torch.zeros((1, 16, 8), dtype=torch.complex128, device="cuda")
+    A = torch.zeros((1, 15, 8), dtype=torch.complex128, device="cuda")
     B = torch.zeros((1, 8, 64), dtype=torch.complex128, device="cuda")
-    Cm = torch.zeros((1, 16, 64), dtype=torch.complex128, device="cuda")
+    Cm = torch.zeros((1, 15, 64), dtype=torch.complex128, device="cuda")
     with pytest.raises(q.QttError):
         q.zgemm(ctx, A, B, Cm, path=2)
+    with pytest.raises(q.QttError):
+        q.zgemm(ctx, A, B, Cm, path=11)   # no such tile variant
