@@ -278,8 +278,10 @@ int qtt_zgemm(qtt_ctx* ctx, int opA, int opB, int M, int N, int K,
  * qtt_zqr: Householder QR of batch m x n matrices A (k = min(m, n)):
  * R (k x n, upper trapezoidal, real diagonal) and, if Q != NULL, Q (m x k,
  * orthonormal columns) with A = Q R.  path 0: the kernels the library
- * uses (register-resident where the shape fits), 1: the global-memory
- * kernel.  Synchronises the stream before returning.
+ * uses, 1: the global-memory kernel, 2: the blocked matrix-core kernel
+ * (m >= n, 16 < n <= 96, m <= 192), 3: the register-resident unblocked
+ * kernels (m <= 256, n <= 128); QTT_EINVAL when the forced path does not
+ * cover the shape.  Synchronises the stream before returning.
  *
  * qtt_zjacobi: one-sided Jacobi of batch n x n matrices A (n <= 96):
  * A V = U diag(S) with U (n x n) orthonormal columns for the nonzero S

@@ -1941,7 +1941,7 @@ int qtt_zgemm(qtt_ctx* c, int opA, int opB, int M, int N, int K, const double* a
 }
 
 int qtt_zqr(qtt_ctx* c, int batch, int m, int n, const void* A, void* R, void* Qo, int path) {
-  if (!c || !A || !R || batch < 1 || batch > 65535 || m < 1 || n < 1 || path < 0 || path > 1)
+  if (!c || !A || !R || batch < 1 || batch > 65535 || m < 1 || n < 1 || path < 0 || path > 3)
     return QTT_EINVAL;
   QTT_TRY(c, {
     Ctx X{c};
@@ -1951,8 +1951,16 @@ int qtt_zqr(qtt_ctx* c, int batch, int m, int n, const void* A, void* R, void* Q
     MatOut ro{(cplx*)R, (long)n, 1, (long)k * n};
     MatOut qo{(cplx*)Qo, (long)k, 1, (long)m * k};
     if (!Qo) qo = MatOut{nullptr, 0, 0, 0};
-    if (path == 0) qr(batch, m, n, av, ro, qo, (cplx*)ws->p, c->stream);
-    else qr_generic(batch, m, n, av, ro, qo, (cplx*)ws->p, c->stream);
+    if (path == 0) {
+      qr(batch, m, n, av, ro, qo, (cplx*)ws->p, c->stream);
+    } else if (path == 1) {
+      qr_generic(batch, m, n, av, ro, qo, (cplx*)ws->p, c->stream);
+    } else if (path == 2) {
+      if (!qr_blocked(batch, m, n, av, ro, qo, (cplx*)ws->p, c->stream))
+        throw std::invalid_argument("zqr: shape not covered by the blocked matrix-core kernel");
+    } else if (!qr_fast(batch, m, n, av, ro, qo, (cplx*)ws->p, c->stream)) {
+      throw std::invalid_argument("zqr: shape not covered by the register-resident kernels");
+    }
     X.sync();  // the workspace is released on return
   });
 }

@@ -91,6 +91,14 @@ struct MatOut {
 void qr(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
         hipStream_t s);
 size_t qr_ws(int batch, int m, int n);
+// per-matrix slice of that workspace: the generic kernel's copy of A and
+// Q (m n + m k + k entries), or the blocked kernel's V and T of every
+// 16-column panel (np (16 m + 256) entries), whichever is larger
+inline size_t qr_ws_per_matrix(int m, int n) {
+  const long k = m < n ? m : n, np = (k + 15) / 16;
+  const long gen = (long)m * n + (long)m * k + k, blk = np * (16L * m + 256);
+  return (size_t)(gen > blk ? gen : blk);
+}
 // The global-memory kernel behind qr() for shapes the register kernels do
 // not hold (same contract as qr).
 void qr_generic(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
@@ -100,6 +108,10 @@ void qr_generic(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws
 // kernels_fact.hip); returns false when the shape does not fit.  Uses
 // qr_fast_ws(batch, m, n) <= qr_ws(batch, m, n) workspace entries.
 bool qr_fast(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, hipStream_t s);
+// Blocked QR on the matrix cores (kernels_qr_blk.hip) for m >= n,
+// 16 < n <= 96, m <= 192; false when the shape is not covered.  `ws` as
+// for qr().
+bool qr_blocked(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, hipStream_t s);
 size_t qr_fast_ws(int batch, int m, int n);
 
 // One-sided Jacobi of batched square n x n matrices (n <= 96) resident in

@@ -52,6 +52,44 @@ def test_zqr(ctx, shape):
     assert torch.equal(R, R2)
 
 
+# shapes of the blocked matrix-core kernel (m >= n, 16 < n <= 96, m <= 192):
+# full and partial last panels, padded row blocks, every column-group count
+QR_BLOCKED_SHAPES = [(160, 80), (128, 80), (96, 80), (160, 64), (64, 64), (48, 48), (128, 33),
+                     (17, 17), (192, 96), (100, 50), (33, 20), (150, 96), (80, 80), (191, 95),
+                     (160, 40), (24, 18)]
+
+
+@pytest.mark.parametrize("shape", QR_BLOCKED_SHAPES)
+def test_zqr_blocked(ctx, shape):
+    """Blocked Householder QR (panels of 16 columns, compact WY block
+    reflectors on the matrix cores) against the definition and numpy."""
+    import torch
+    import paper_2412_11566_amd as q
+    m, n = shape
+    k = min(m, n)
+    rng = np.random.default_rng(m * 7 + n)
+    a = _rand(rng, 3, m, n)
+    A = torch.from_numpy(a).cuda()
+    R = torch.zeros((3, k, n), dtype=torch.complex128, device="cuda")
+    Q = torch.zeros((3, m, k), dtype=torch.complex128, device="cuda")
+    q.zqr(ctx, A, R, Q, path=2)
+    _check_qr(a, R.cpu().numpy(), Q.cpu().numpy())
+    R2 = torch.zeros_like(R)
+    q.zqr(ctx, A, R2, path=2)
+    assert torch.equal(R, R2)
+
+
+def test_zqr_blocked_rejects_uncovered(ctx):
+    import torch
+    import paper_2412_11566_amd as q
+    for (m, n) in [(40, 64), (200, 64), (100, 16), (100, 100)]:
+        k = min(m, n)
+        A = torch.zeros((1, m, n), dtype=torch.complex128, device="cuda")
+        R = torch.zeros((1, k, n), dtype=torch.complex128, device="cuda")
+        with pytest.raises(q.QttError):
+            q.zqr(ctx, A, R, path=2)
+
+
 @pytest.mark.parametrize("shape", [(160, 80), (64, 40), (128, 128)])
 def test_zqr_rank_deficient_and_generic_path(ctx, shape):
     import torch
@@ -61,7 +99,9 @@ def test_zqr_rank_deficient_and_generic_path(ctx, shape):
     rng = np.random.default_rng(5)
     a = _rand(rng, 2, m, 5) @ _rand(rng, 2, 5, n)
     a[:, :, 3] = 0.0                       # an exactly zero column
-    for path in (0, 1):
+    for path in (0, 1, 2, 3):
+        if path == 2 and not (m >= n and 16 < n <= 96 and m <= 192):
+            continue
         A = torch.from_numpy(a).cuda()
         R = torch.zeros((2, k, n), dtype=torch.complex128, device="cuda")
         Q = torch.zeros((2, m, k), dtype=torch.complex128, device="cuda")
@@ -81,13 +121,16 @@ def test_zqr_tiny_columns(ctx, shape):
     a = _rand(rng, 2, m, n)
     a[:, :, 1] *= 1e-155
     a[:, :, 5] *= 1e-300
-    A = torch.from_numpy(a).cuda()
-    R = torch.zeros((2, k, n), dtype=torch.complex128, device="cuda")
-    Q = torch.zeros((2, m, k), dtype=torch.complex128, device="cuda")
-    q.zqr(ctx, A, R, Q)
-    R, Q = R.cpu().numpy(), Q.cpu().numpy()
-    assert np.all(np.isfinite(R)) and np.all(np.isfinite(Q))
-    _check_qr(a, R, Q, full_rank=False)
+    for path in (0, 2):
+        if path == 2 and not (m >= n and 16 < n <= 96 and m <= 192):
+            continue
+        A = torch.from_numpy(a).cuda()
+        R = torch.zeros((2, k, n), dtype=torch.complex128, device="cuda")
+        Q = torch.zeros((2, m, k), dtype=torch.complex128, device="cuda")
+        q.zqr(ctx, A, R, Q, path=path)
+        R, Q = R.cpu().numpy(), Q.cpu().numpy()
+        assert np.all(np.isfinite(R)) and np.all(np.isfinite(Q))
+        _check_qr(a, R, Q, full_rank=False)
 
 
 @pytest.mark.parametrize("n", [1, 2, 7, 16, 33, 64, 80, 96])
