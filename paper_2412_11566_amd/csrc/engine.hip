@@ -1941,7 +1941,7 @@ int qtt_zgemm(qtt_ctx* c, int opA, int opB, int M, int N, int K, const double* a
 }
 
 int qtt_zqr(qtt_ctx* c, int batch, int m, int n, const void* A, void* R, void* Qo, int path) {
-  if (!c || !A || !R || batch < 1 || batch > 65535 || m < 1 || n < 1 || path < 0 || path > 3)
+  if (!c || !A || !R || batch < 1 || batch > 65535 || m < 1 || n < 1 || path < 0 || path > 4)
     return QTT_EINVAL;
   QTT_TRY(c, {
     Ctx X{c};
@@ -1958,8 +1958,11 @@ int qtt_zqr(qtt_ctx* c, int batch, int m, int n, const void* A, void* R, void* Q
     } else if (path == 2) {
       if (!qr_blocked(batch, m, n, av, ro, qo, (cplx*)ws->p, c->stream))
         throw std::invalid_argument("zqr: shape not covered by the blocked matrix-core kernel");
-    } else if (!qr_fast(batch, m, n, av, ro, qo, (cplx*)ws->p, c->stream)) {
-      throw std::invalid_argument("zqr: shape not covered by the register-resident kernels");
+    } else if (path == 3) {
+      if (!qr_fast(batch, m, n, av, ro, qo, (cplx*)ws->p, c->stream))
+        throw std::invalid_argument("zqr: shape not covered by the register-resident kernels");
+    } else if (!qr_two_col(batch, m, n, av, ro, qo, c->stream)) {
+      throw std::invalid_argument("zqr: shape not covered by the two-column register kernel");
     }
     X.sync();  // the workspace is released on return
   });

@@ -38,5 +38,41 @@ __device__ __forceinline__ cplx ldv(const MatView& v, long b, long i, long j) {
   return a;
 }
 
+// 1 / x from the hardware estimate and one Newton step (x normal)
+__device__ __forceinline__ double rcp_nt(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Householder reflector of a column with leading entry al and squared norm
+// s of the entries below it, H = I - tau v v^H with v = [1; x inv] and
+// H^H [al; x] = [beta; 0]:
+//   beta = -sign(Re al) sqrt(|al|^2 + s),  tau = (beta - al) / beta,
+//   inv = 1 / (al - beta);
+// the identity (tau = 0) for a column already zero below the diagonal or
+// of squared norm below QR_TINY (beta and |al - beta| then stay far from
+// the bottom of the double range).  Square root and reciprocals come from
+// the hardware estimates with one Newton step each: the compiler's
+// correctly rounded expansions form a long dependent chain, and this chain
+// sits on the critical path of every elimination step.
+__device__ __forceinline__ void householder(cplx al, double s, cplx& tau, cplx& inv, double& beta) {
+  const double t = cabs2(al) + s;
+  if ((s == 0.0 && al.y == 0.0) || t < QR_TINY) {
+    tau = make_double2(0.0, 0.0);
+    inv = make_double2(0.0, 0.0);
+    beta = al.x;
+    return;
+  }
+  const double r = __builtin_amdgcn_rsq(t);
+  const double q0 = t * r;
+  const double nrm = fma(fma(-q0, q0, t), 0.5 * r, q0);
+  beta = -copysign(nrm, al.x);
+  const double rb = rcp_nt(beta);
+  const cplx d = make_double2(al.x - beta, al.y);
+  const double rdd = rcp_nt(cabs2(d));
+  tau = make_double2((beta - al.x) * rb, -al.y * rb);
+  inv = make_double2(d.x * rdd, -d.y * rdd);
+}
+
 }  // namespace dev
 }  // namespace qtt

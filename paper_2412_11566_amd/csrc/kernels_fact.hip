@@ -68,18 +68,12 @@ __global__ __launch_bounds__(QNW * 64) void k_qr_reg(int m, int n, MatView A, Ma
 #pragma unroll
       for (int q = 0; q < QNW; ++q) xn2 += pn[q];
       const cplx alpha = sh_alpha;
-      if ((xn2 == 0.0 && alpha.y == 0.0) || cabs2(alpha) + xn2 < QR_TINY) {
-        sh_tau = make_double2(0.0, 0.0);
-        sh_inv = make_double2(0.0, 0.0);
-        sh_beta = alpha.x;
-      } else {
-        const double beta = -copysign(sqrt(cabs2(alpha) + xn2), alpha.x);
-        sh_tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-        const cplx d = make_double2(alpha.x - beta, alpha.y);
-        const double dd = cabs2(d);
-        sh_inv = make_double2(d.x / dd, -d.y / dd);
-        sh_beta = beta;
-      }
+      cplx tau, inv;
+      double beta;
+      householder(alpha, xn2, tau, inv, beta);
+      sh_tau = tau;
+      sh_inv = inv;
+      sh_beta = beta;
       taus[j] = sh_tau;
       V[(long)m * k + j] = sh_tau;
     }
@@ -272,17 +266,7 @@ __global__ __launch_bounds__(512) void k_qr_rows(int m, int n, MatView A, MatOut
         al.y = wsum(al.y);
         cplx tau, inv;
         double beta;
-        if ((s == 0.0 && al.y == 0.0) || cabs2(al) + s < QR_TINY) {
-          tau = make_double2(0.0, 0.0);
-          inv = make_double2(0.0, 0.0);
-          beta = al.x;
-        } else {
-          beta = -copysign(sqrt(cabs2(al) + s), al.x);
-          tau = make_double2((beta - al.x) / beta, -al.y / beta);
-          const cplx d = make_double2(al.x - beta, al.y);
-          const double dd = cabs2(d);
-          inv = make_double2(d.x / dd, -d.y / dd);
-        }
+        householder(al, s, tau, inv, beta);
         const bool zero = (tau.x == 0.0 && tau.y == 0.0);
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
@@ -477,17 +461,7 @@ __global__ __launch_bounds__(NW * 64) void k_qr_lc(int m, int n, MatView A, MatO
     const cplx al = rowj[buf][j];
     cplx tau, inv;
     double beta;
-    if ((s == 0.0 && al.y == 0.0) || cabs2(al) + s < QR_TINY) {
-      tau = make_double2(0.0, 0.0);
-      inv = make_double2(0.0, 0.0);
-      beta = al.x;
-    } else {
-      beta = -copysign(sqrt(cabs2(al) + s), al.x);
-      tau = make_double2((beta - al.x) / beta, -al.y / beta);
-      const cplx d = make_double2(al.x - beta, al.y);
-      const double dd = cabs2(d);
-      inv = make_double2(d.x / dd, -d.y / dd);
-    }
+    householder(al, s, tau, inv, beta);
     if (tid == 0) taus[j] = tau;
     if (!live) continue;
     // f_col = conj(tau) * v^H a_col, with v_j = 1 and v_r = x_r * inv
@@ -672,7 +646,8 @@ __device__ __forceinline__ cplx quad_sum(cplx p) {
 }
 
 template <int RB, int RPL, int CG>
-__global__ __launch_bounds__(RB * CG * 64) void k_qr_2d(int m, int n, MatView A, MatOut R, MatOut Q) {
+__global__ __launch_bounds__(RB * CG * 64) void k_qr_2d(int m, int n, MatView A, MatOut R, MatOut Q,
+                                                        cplx* vout, long vsz) {
   constexpr int NC = 16 * CG, RBS = 4 * RPL, MR = RB * RBS;
   const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -741,17 +716,7 @@ __global__ __launch_bounds__(RB * CG * 64) void k_qr_2d(int m, int n, MatView A,
     const cplx al = rowj[j];
     cplx tau, inv;
     double beta;
-    if ((s == 0.0 && al.y == 0.0) || cabs2(al) + s < QR_TINY) {
-      tau = zero;
-      inv = zero;
-      beta = al.x;
-    } else {
-      beta = -copysign(sqrt(cabs2(al) + s), al.x);
-      const cplx d = make_double2(al.x - beta, al.y);
-      const double dd = cabs2(d);
-      tau = make_double2((beta - al.x) / beta, -al.y / beta);
-      inv = make_double2(d.x / dd, -d.y / dd);
-    }
+    householder(al, s, tau, inv, beta);
     if (tid == 0) {
       taus[j] = tau;
       invs[j] = inv;
@@ -812,6 +777,30 @@ __global__ __launch_bounds__(RB * CG * 64) void k_qr_2d(int m, int n, MatView A,
     if (row < k && col < n)
       R.base[b * R.sb + (long)row * R.rs + (long)col * R.cs] = csel(row <= col, a[i], zero);
     QR2D_WINDOW(i);
+  }
+  if (vout != nullptr) {
+    // Householder vectors of 16-column panels for the matrix-core Q
+    // formation: V[p][row][c] (unit diagonal, zero above), then tau[p][c]
+    // after the T blocks
+    const int np = (k + 15) / 16;
+    cplx* V = vout + (long)b * vsz;
+    if (col < np * 16) {  // columns of the last panel beyond k: zero
+      cplx* vp = V + (long)(col >> 4) * m * 16 + (col & 15);
+      const bool live = col < k;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = base + rs + 4 * i;
+        if (row < m)
+          vp[row * 16] = csel(live && row > col, a[i],
+                              make_double2(live && row == col ? 1.0 : 0.0, 0.0));
+        QR2D_WINDOW(i);
+      }
+    }
+    if (tid < np * 16) {
+      const int c = tid;
+      V[(long)np * m * 16 + (long)np * 256 + c] = csel(c < k, taus[c], zero);
+    }
+    return;
   }
   if (Q.base == nullptr) return;
 #pragma unroll
@@ -894,11 +883,286 @@ __global__ __launch_bounds__(RB * CG * 64) void k_qr_2d(int m, int n, MatView A,
   }
 }
 
+// The same algorithm with CPL columns per lane (lane l of wave (rb, cg)
+// holds columns cg*16*CPL + l/4 + 16 c, c < CPL): every published value of
+// the current column read from LDS serves CPL columns, which divides the
+// LDS traffic of the two row loops (the bound of the one-column form) by
+// CPL for the same register footprint per lane.
+template <int RB, int RPL, int CG, int CPL>
+__global__ __launch_bounds__(RB * CG * 64) void k_qr_2c(int m, int n, MatView A, MatOut R, MatOut Q) {
+  constexpr int GW = 16 * CPL, NC = GW * CG, RBS = 4 * RPL, MR = RB * RBS;
+  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rb = w / CG, cg = w % CG;
+  const int rs = lane & 3, cl = lane >> 2;
+  const int col0 = cg * GW + cl;   // column of c = 0; column c is col0 + 16 c
+  const int base = rb * RBS;
+  const int k = min(m, n);
+  __shared__ cplx part[RB][NC];
+  __shared__ cplx rowj[NC];
+  __shared__ cplx xbuf[2][MR];
+  __shared__ cplx taus[NC], invs[NC];
+  __shared__ double betas[NC];
+  cplx a[CPL][RPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c)
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int row = base + rs + 4 * i, col = col0 + 16 * c;
+      a[c][i] = (row < m && col < n) ? ldv(A, b, row, col) : make_double2(0.0, 0.0);
+      QR2D_WINDOW(i);
+    }
+  const cplx zero = make_double2(0.0, 0.0);
+  if (col0 == 0) {
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int row = base + rs + 4 * i;
+      xbuf[0][row] = csel(row > 0 && row < m, a[0][i], zero);
+    }
+  }
+  for (int j = 0; j < k; ++j) {
+    const int xb = j & 1, jg = j / GW;
+    const bool colsLive = cg >= jg;          // uniform
+    const bool rowsLive = base + RBS > j;    // uniform
+    const bool holdsRowJ = j >= base && j < base + RBS;
+    __syncthreads();
+    if (colsLive) {
+      cplx p[CPL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) p[c] = zero;
+      if (rowsLive) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const cplx x = xbuf[xb][base + rs + 4 * i];
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) cdot_acc(p[c], x, a[c][i]);
+          QR2D_WINDOW(i);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        p[c] = quad_sum(p[c]);
+        if (rs == 0) part[rb][col0 + 16 * c] = p[c];
+      }
+      if (holdsRowJ) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          cplx r = zero;
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const double e = (base + rs + 4 * i == j) ? 1.0 : 0.0;
+            r.x = fma(e, a[c][i].x, r.x);
+            r.y = fma(e, a[c][i].y, r.y);
+          }
+          if (j - base - rs >= 0 && ((j - base - rs) & 3) == 0) rowj[col0 + 16 * c] = r;
+        }
+      }
+    }
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < RB; ++q) s += part[q][j].x;
+    const cplx al = rowj[j];
+    cplx tau, inv;
+    double beta;
+    householder(al, s, tau, inv, beta);
+    if (tid == 0) {
+      taus[j] = tau;
+      invs[j] = inv;
+      betas[j] = beta;
+    }
+    if (colsLive && rowsLive) {
+      cplx f[CPL], g[CPL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int col = col0 + 16 * c;
+        f[c] = zero;
+        g[c] = zero;
+        if (col > j && col < n) {
+          cplx P = zero;
+#pragma unroll
+          for (int q = 0; q < RB; ++q) P = make_double2(P.x + part[q][col].x, P.y + part[q][col].y);
+          const cplx cp = cmul(make_double2(inv.x, -inv.y), P);
+          const cplx rj = rowj[col];
+          f[c] = cmul(make_double2(tau.x, -tau.y), make_double2(cp.x + rj.x, cp.y + rj.y));
+          g[c] = cmul(f[c], inv);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const cplx x = xbuf[xb][base + rs + 4 * i];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) caxpy_sub(a[c][i], g[c], x);
+        QR2D_WINDOW(i);
+      }
+      if (holdsRowJ) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const double e = (base + rs + 4 * i == j) ? 1.0 : 0.0;
+            a[c][i].x = fma(-e, f[c].x, a[c][i].x);
+            a[c][i].y = fma(-e, f[c].y, a[c][i].y);
+          }
+      }
+    }
+    // owners of column j + 1 publish it below its diagonal
+    if (j + 1 < k) {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        if (col0 + 16 * c != j + 1) continue;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int row = base + rs + 4 * i;
+          xbuf[xb ^ 1][row] = csel(row > j + 1 && row < m, a[c][i], zero);
+        }
+      }
+    }
+  }
+  __syncthreads();  // betas, invs complete
+#pragma unroll
+  for (int c = 0; c < CPL; ++c) {
+    const int col = col0 + 16 * c;
+    if (col < k) {
+      const cplx ic = invs[col];
+      const double bc = betas[col];
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int row = base + rs + 4 * i;
+        const cplx v = cmul(a[c][i], ic);
+        a[c][i] = csel(row > col, v, csel(row == col, make_double2(bc, 0.0), a[c][i]));
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c)
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int row = base + rs + 4 * i, col = col0 + 16 * c;
+      if (row < k && col < n)
+        R.base[b * R.sb + (long)row * R.rs + (long)col * R.cs] = csel(row <= col, a[c][i], zero);
+      QR2D_WINDOW(i);
+    }
+  if (Q.base == nullptr) return;
+#pragma unroll
+  for (int c = 0; c < CPL; ++c)
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int row = base + rs + 4 * i, col = col0 + 16 * c;
+      if (row <= col || col >= k) a[c][i] = zero;
+    }
+  for (int j = k - 1; j >= 0; --j) {
+    const int xb = j & 1, jg = j / GW;
+    const bool colsLive = cg >= jg;
+    const bool rowsLive = base + RBS > j;
+    const bool holdsRowJ = j >= base && j < base + RBS;
+    // column j: publish v below the diagonal, then turn it into e_j
+    if (cg == jg) {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const bool isJ = col0 + 16 * c == j;
+        if (isJ) {
+#pragma unroll
+          for (int i = 0; i < RPL; ++i) {
+            const int row = base + rs + 4 * i;
+            xbuf[xb][row] = csel(row > j && row < m, a[c][i], zero);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int row = base + rs + 4 * i;
+          a[c][i] = csel(isJ, make_double2(row == j ? 1.0 : 0.0, 0.0), a[c][i]);
+        }
+      }
+    }
+    __syncthreads();
+    if (colsLive) {
+      cplx p[CPL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) p[c] = zero;
+      if (rowsLive) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const cplx x = xbuf[xb][base + rs + 4 * i];
+#pragma unroll
+          for (int c = 0; c < CPL; ++c) cdot_acc(p[c], x, a[c][i]);
+          QR2D_WINDOW(i);
+        }
+        if (holdsRowJ) {
+#pragma unroll
+          for (int c = 0; c < CPL; ++c)
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+              const double e = (base + rs + 4 * i == j) ? 1.0 : 0.0;
+              p[c].x = fma(e, a[c][i].x, p[c].x);
+              p[c].y = fma(e, a[c][i].y, p[c].y);
+            }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        p[c] = quad_sum(p[c]);
+        if (rs == 0) part[rb][col0 + 16 * c] = p[c];
+      }
+    }
+    __syncthreads();
+    const cplx tj = taus[j];
+    if (!colsLive || !rowsLive || (tj.x == 0.0 && tj.y == 0.0)) continue;
+    cplx f[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+      const int col = col0 + 16 * c;
+      f[c] = zero;
+      if (col >= j && col < k) {
+        cplx P = zero;
+#pragma unroll
+        for (int q = 0; q < RB; ++q) P = make_double2(P.x + part[q][col].x, P.y + part[q][col].y);
+        f[c] = cmul(tj, P);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const cplx x = xbuf[xb][base + rs + 4 * i];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) caxpy_sub(a[c][i], f[c], x);
+      QR2D_WINDOW(i);
+    }
+    if (holdsRowJ) {
+#pragma unroll
+      for (int c = 0; c < CPL; ++c)
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const double e = (base + rs + 4 * i == j) ? 1.0 : 0.0;
+          a[c][i].x = fma(-e, f[c].x, a[c][i].x);
+          a[c][i].y = fma(-e, f[c].y, a[c][i].y);
+        }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < CPL; ++c)
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int row = base + rs + 4 * i, col = col0 + 16 * c;
+      if (row < m && col < k) Q.base[b * Q.sb + (long)row * Q.rs + (long)col * Q.cs] = a[c][i];
+      QR2D_WINDOW(i);
+    }
+}
+
+template <int RB, int RPL, int CG, int CPL>
+bool try_qr_2c(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q,
+               hipStream_t s) {
+  if (m > RB * 4 * RPL || n > 16 * CPL * CG) return false;
+  hipLaunchKernelGGL((k_qr_2c<RB, RPL, CG, CPL>), dim3(batch), dim3(RB * CG * 64), 0, s, m, n, A, R, Q);
+  check(hipGetLastError(), "qr_2c launch");
+  return true;
+}
+
 template <int RB, int RPL, int CG>
 bool try_qr_2d(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q,
-               hipStream_t s) {
+               hipStream_t s, cplx* vout = nullptr) {
   if (m > RB * 4 * RPL || n > 16 * CG) return false;
-  hipLaunchKernelGGL((k_qr_2d<RB, RPL, CG>), dim3(batch), dim3(RB * CG * 64), 0, s, m, n, A, R, Q);
+  hipLaunchKernelGGL((k_qr_2d<RB, RPL, CG>), dim3(batch), dim3(RB * CG * 64), 0, s, m, n, A, R, Q, vout,
+                     (long)qr_ws_per_matrix(m, n));
   check(hipGetLastError(), "qr_2d launch");
   return true;
 }
@@ -1026,9 +1290,24 @@ size_t qr_fast_ws(int batch, int m, int n) {
 }
 
 template <int RB, int CG>
-bool qr2d_any(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q, hipStream_t s) {
-  return try_qr_2d<RB, 4, CG>(batch, m, n, A, R, Q, s) || try_qr_2d<RB, 8, CG>(batch, m, n, A, R, Q, s) ||
-         try_qr_2d<RB, 12, CG>(batch, m, n, A, R, Q, s) || try_qr_2d<RB, 14, CG>(batch, m, n, A, R, Q, s);
+bool qr2d_any(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q, hipStream_t s,
+              cplx* vout = nullptr) {
+  return try_qr_2d<RB, 4, CG>(batch, m, n, A, R, Q, s, vout) ||
+         try_qr_2d<RB, 8, CG>(batch, m, n, A, R, Q, s, vout) ||
+         try_qr_2d<RB, 12, CG>(batch, m, n, A, R, Q, s, vout) ||
+         try_qr_2d<RB, 14, CG>(batch, m, n, A, R, Q, s, vout);
+}
+
+bool qr_2d_vectors(int batch, int m, int n, MatView A, MatOut R, cplx* ws, hipStream_t s) {
+  const MatOut Q{nullptr, 0, 0, 0};
+  switch ((n + 15) / 16) {
+    case 2: return qr2d_any<8, 2>(batch, m, n, A, R, Q, s, ws);
+    case 3: return qr2d_any<5, 3>(batch, m, n, A, R, Q, s, ws);
+    case 4: return qr2d_any<4, 4>(batch, m, n, A, R, Q, s, ws);
+    case 5: return qr2d_any<3, 5>(batch, m, n, A, R, Q, s, ws);
+    case 6: return qr2d_any<2, 6>(batch, m, n, A, R, Q, s, ws);
+    default: return false;
+  }
 }
 
 bool qr_fast(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, hipStream_t s) {
@@ -1057,6 +1336,17 @@ bool qr_fast(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, h
   if (try_qr_lc<8, 16, 2>(batch, m, n, A, R, Q, s) || try_qr_lc<16, 10, 2>(batch, m, n, A, R, Q, s))
     return true;
   return try_qr_rows<2, 16>(batch, m, n, A, R, Q, ws, s) || try_qr_rows<3, 16>(batch, m, n, A, R, Q, ws, s);
+}
+
+bool qr_two_col(int batch, int m, int n, MatView A, MatOut R, MatOut Q, hipStream_t s) {
+  if (batch <= 0 || m <= 0 || n <= 0) return true;
+  switch ((n + 31) / 32) {
+    case 1: return try_qr_2c<8, 4, 1, 2>(batch, m, n, A, R, Q, s) || try_qr_2c<8, 8, 1, 2>(batch, m, n, A, R, Q, s);
+    case 2: return try_qr_2c<8, 4, 2, 2>(batch, m, n, A, R, Q, s) || try_qr_2c<8, 8, 2, 2>(batch, m, n, A, R, Q, s);
+    case 3: return try_qr_2c<5, 4, 3, 2>(batch, m, n, A, R, Q, s) || try_qr_2c<5, 8, 3, 2>(batch, m, n, A, R, Q, s) ||
+                   try_qr_2c<5, 12, 3, 2>(batch, m, n, A, R, Q, s);
+    default: return false;
+  }
 }
 
 bool jacobi_square(int batch, int n, MatView A, MatOut U, double* S, hipStream_t s) {

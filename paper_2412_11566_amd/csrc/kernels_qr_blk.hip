@@ -124,6 +124,71 @@ __device__ __forceinline__ void blk_wsum(const cplx* Wp, int cg, int rq, int cl,
   }
 }
 
+// Q = H_0 ... H_{np-1} [I_k; 0] in reverse panel order from V_p and T_p in
+// global memory: the column groups at or after panel p meet H_p as three
+// block products on the matrix cores (W = V^H Q, W <- T W, Q <- Q - V W);
+// a group before panel p is still a block of the identity, untouched by
+// H_p.  The register arrays hold Q on return (also written to Q.base).
+template <int RB, int RPL, int CG>
+__device__ __forceinline__ void formq_phase(int m, int k, int np, int b, int tid, int rb, int cg,
+                                            int cl0, int rq0, int col, int base, cplx* Vs, cplx* Wp,
+                                            cplx (*Ts)[VST], const cplx* Vg, const cplx* Tg, MatOut Q,
+                                            dv4 (&ar)[RPL / 4], dv4 (&ai)[RPL / 4]) {
+  constexpr int RBS = 4 * RPL, MR = RB * RBS, NT = RB * CG * 64;
+  const int rq = rq0;
+  cplx* Qb = Q.base + b * Q.sb;
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int row = base + rq + 4 * i;
+    AR(i) = (row == col && col < k) ? 1.0 : 0.0;
+    AI(i) = 0.0;
+  }
+  for (int p = np - 1; p >= 0; --p) {
+    const int j0 = 16 * p;
+    int rq, cl;
+    OPAQUE(rq, rq0);
+    OPAQUE(cl, cl0);
+    __syncthreads();  // the previous panel's Vs, Ts, Wp reads are done
+    for (int e = tid; e < MR * 16; e += NT) {
+      const int row = e >> 4, c = e & 15;
+      Vs[row * VST + c] = row < m ? Vg[((long)p * m + row) * 16 + c] : cz();
+    }
+    for (int e = tid; e < 256; e += NT) Ts[e >> 4][e & 15] = Tg[(long)p * 256 + e];
+    __syncthreads();
+    const bool live = cg >= p;
+    if (live) {
+      dv4 wr, wi;
+      blk_vhx<RPL>(Vs, base, rq, cl, j0, ar, ai, wr, wi);
+      cplx* Wq = Wp + ((long)rb * CG + cg) * 256;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Wq[(4 * r + rq) * 16 + cl] = make_double2(wr[r], wi[r]);
+    }
+    __syncthreads();
+    if (live && base + RBS > j0) {
+      dv4 Wr, Wi;
+      blk_wsum<RB, CG>(Wp, cg, rq, cl, Wr, Wi);
+      // W2 = T W: A operand T[cl][4s + rq]
+      dv4 w2r = {0.0, 0.0, 0.0, 0.0}, w2i = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const cplx t = Ts[cl][4 * s + rq];
+        w2r = mfma(t.x, Wr[s], w2r);
+        w2r = mfma(-t.y, Wi[s], w2r);
+        w2i = mfma(t.x, Wi[s], w2i);
+        w2i = mfma(t.y, Wr[s], w2i);
+      }
+      blk_sub_vw<RPL>(Vs, base, rq, cl, j0, w2r, w2i, ar, ai);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int row = base + rq + 4 * i;
+    if (row < m && col < k)
+      Qb[(long)row * Q.rs + (long)col * Q.cs] = make_double2(AR(i), AI(i));
+    QRB_WINDOW(i);
+  }
+}
+
 template <int RB, int RPL, int CG>
 __global__ __launch_bounds__(RB * CG * 64) void k_qr_blk(int m, int n, MatView A, MatOut R,
                                                          MatOut Q, cplx* ws, long wsz) {
@@ -217,19 +282,13 @@ __global__ __launch_bounds__(RB * CG * 64) void k_qr_blk(int m, int n, MatView A
 #pragma unroll
       for (int q = 0; q < RB; ++q) s += part[q][j - j0].x;
       const cplx al = rowj[j - j0];
+      cplx P = cz();
+#pragma unroll
+      for (int q = 0; q < RB; ++q) P = make_double2(P.x + part[q][cl].x, P.y + part[q][cl].y);
+      const cplx rj = rowj[cl];
       cplx tau, inv;
       double beta;
-      if ((s == 0.0 && al.y == 0.0) || cabs2(al) + s < QR_TINY) {
-        tau = cz();
-        inv = cz();
-        beta = al.x;
-      } else {
-        beta = -copysign(sqrt(cabs2(al) + s), al.x);
-        const cplx d = make_double2(al.x - beta, al.y);
-        const double dd = cabs2(d);
-        tau = make_double2((beta - al.x) / beta, -al.y / beta);
-        inv = make_double2(d.x / dd, -d.y / dd);
-      }
+      householder(al, s, tau, inv, beta);
       if (rb == 0 && lane == 0) {
         taus[j - j0] = tau;
         invs[j - j0] = inv;
@@ -240,11 +299,7 @@ __global__ __launch_bounds__(RB * CG * 64) void k_qr_blk(int m, int n, MatView A
         // the diagonal and v_j = 1:  a -= (f inv) x,  a[j] -= f
         cplx f = cz(), g = cz();
         if (col > j && col < n) {
-          cplx P = cz();
-#pragma unroll
-          for (int q = 0; q < RB; ++q) P = make_double2(P.x + part[q][cl].x, P.y + part[q][cl].y);
           const cplx cp = cmul(make_double2(inv.x, -inv.y), P);
-          const cplx rj = rowj[cl];
           f = cmul(make_double2(tau.x, -tau.y), make_double2(cp.x + rj.x, cp.y + rj.y));
           g = cmul(f, inv);
         }
@@ -376,63 +431,108 @@ __global__ __launch_bounds__(RB * CG * 64) void k_qr_blk(int m, int n, MatView A
     QRB_WINDOW(i);
   }
   if (Q.base == nullptr) return;
-  cplx* Qb = Q.base + b * Q.sb;
+  formq_phase<RB, RPL, CG>(m, k, np, b, tid, rb, cg, cl0, rq0, col, base, Vs, Wp, Ts, Vg, Tg, Q, ar, ai);
+}
 
-  // ---- Q = H_0 ... H_{np-1} [I_k; 0] ----
-#pragma unroll
-  for (int i = 0; i < RPL; ++i) {
-    const int row = base + rq + 4 * i;
-    AR(i) = (row == col && col < k) ? 1.0 : 0.0;
-    AI(i) = 0.0;
-  }
-  for (int p = np - 1; p >= 0; --p) {
-    const int j0 = 16 * p;
-    int rq, cl;
-    OPAQUE(rq, rq0);
-    OPAQUE(cl, cl0);
-    __syncthreads();  // the previous panel's Vs, Ts, Wp reads are done
-    for (int e = tid; e < MR * 16; e += NT) {
-      const int row = e >> 4, c = e & 15;
-      Vs[row * VST + c] = row < m ? Vg[((long)p * m + row) * 16 + c] : cz();
-    }
-    for (int e = tid; e < 256; e += NT) Ts[e >> 4][e & 15] = Tg[(long)p * 256 + e];
-    __syncthreads();
-    const bool live = cg >= p;
-    if (live) {
-      dv4 wr, wi;
-      blk_vhx<RPL>(Vs, base, rq, cl, j0, ar, ai, wr, wi);
-      cplx* Wq = Wp + ((long)rb * CG + cg) * 256;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Wq[(4 * r + rq) * 16 + cl] = make_double2(wr[r], wi[r]);
-    }
-    __syncthreads();
-    if (live && base + RBS > j0) {
-      dv4 Wr, Wi;
-      blk_wsum<RB, CG>(Wp, cg, rq, cl, Wr, Wi);
-      // W2 = T W: A operand T[cl][4s + rq]
-      dv4 w2r = {0.0, 0.0, 0.0, 0.0}, w2i = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const cplx t = Ts[cl][4 * s + rq];
-        w2r = mfma(t.x, Wr[s], w2r);
-        w2r = mfma(-t.y, Wi[s], w2r);
-        w2i = mfma(t.x, Wi[s], w2i);
-        w2i = mfma(t.y, Wr[s], w2i);
-      }
-      blk_sub_vw<RPL>(Vs, base, rq, cl, j0, w2r, w2i, ar, ai);
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < RPL; ++i) {
-    const int row = base + rq + 4 * i;
-    if (row < m && col < k)
-      Qb[(long)row * Q.rs + (long)col * Q.cs] = make_double2(AR(i), AI(i));
-    QRB_WINDOW(i);
-  }
+// Q alone from the panel vectors and T blocks in the workspace (the Q
+// phase of k_qr_blk as its own kernel, after the unblocked register
+// kernel has produced R and the vectors).
+template <int RB, int RPL, int CG>
+__global__ __launch_bounds__(RB * CG * 64) void k_qr_formq(int m, int n, MatOut Q, cplx* ws, long wsz) {
+  constexpr int NQ = RPL / 4;
+  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rb = w / CG, cg = w % CG;
+  const int cl0 = lane & 15, rq0 = lane >> 4;
+  const int col = cg * 16 + cl0;
+  const int base = rb * 4 * RPL;
+  const int k = min(m, n), np = (k + 15) / 16;
+  extern __shared__ cplx dyn[];
+  cplx* Vs = dyn;
+  cplx* Wp = dyn + RB * 4 * RPL * VST;
+  __shared__ cplx Ts[16][VST];
+  const cplx* Vg = ws + (long)b * wsz;
+  const cplx* Tg = Vg + (long)np * m * 16;
+  dv4 ar[NQ], ai[NQ];
+  formq_phase<RB, RPL, CG>(m, k, np, b, tid, rb, cg, cl0, rq0, col, base, Vs, Wp, Ts, Vg, Tg, Q, ar, ai);
 }
 
 #undef AR
 #undef AI
+
+// T_p of every panel from V_p (workspace) and tau_p: the Gram V_p^H V_p on
+// the matrix cores (four waves over interleaved 4-row slices, summed in
+// LDS), then the recurrence T[i][j] = -tau_j sum_{c<j} T[i][c] G[c][j],
+// T[i][i] = tau_i, one row of T per lane with the row in registers.
+__global__ __launch_bounds__(256) void k_qr_tbuild(int m, int n, cplx* ws, long wsz) {
+  const int p = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int k = min(m, n), np = (k + 15) / 16;
+  const int cl = lane & 15, rq = lane >> 4;
+  cplx* W = ws + (long)b * wsz;
+  const cplx* V = W + (long)p * m * 16;
+  cplx* T = W + (long)np * m * 16 + (long)p * 256;
+  const cplx* tau = W + (long)np * m * 16 + (long)np * 256 + (long)p * 16;
+  __shared__ cplx Gp[4][256];
+  dv4 gr = {0.0, 0.0, 0.0, 0.0}, gi = {0.0, 0.0, 0.0, 0.0};
+  // V is zero above row 16 p
+  for (int sl = 4 * p + w; 4 * sl < m; sl += 4) {
+    const int row = 4 * sl + rq;
+    const cplx v = row < m ? V[(long)row * 16 + cl] : cz();
+    gr = mfma(v.x, v.x, gr);
+    gr = mfma(v.y, v.y, gr);
+    gi = mfma(v.x, v.y, gi);
+    gi = mfma(-v.y, v.x, gi);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Gp[w][(4 * r + rq) * 16 + cl] = make_double2(gr[r], gi[r]);
+  __syncthreads();
+  if (tid < 16) {
+    const int i = tid;
+    cplx t[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const cplx tj = tau[j];
+      cplx acc = cz();
+#pragma unroll
+      for (int c = 0; c < j; ++c) {
+        const int e = c * 16 + j;
+        const cplx g = make_double2(Gp[0][e].x + Gp[1][e].x + Gp[2][e].x + Gp[3][e].x,
+                                    Gp[0][e].y + Gp[1][e].y + Gp[2][e].y + Gp[3][e].y);
+        acc.x += t[c].x * g.x - t[c].y * g.y;
+        acc.y += t[c].x * g.y + t[c].y * g.x;
+      }
+      const cplx tn = cmul(make_double2(-tj.x, -tj.y), acc);
+      t[j] = i < j ? tn : (i == j ? tj : cz());
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j) T[i * 16 + j] = t[j];
+  }
+}
+
+template <int RB, int RPL, int CG>
+bool try_qr_formq(int batch, int m, int n, const MatOut& Q, cplx* ws, hipStream_t s) {
+  constexpr int MR = RB * 4 * RPL;
+  if (m > MR || n > 16 * CG) return false;
+  const size_t shm = (size_t)(MR * VST + RB * CG * 256) * sizeof(cplx);
+  static bool attr = false;
+  if (!attr) {
+    check(hipFuncSetAttribute((const void*)k_qr_formq<RB, RPL, CG>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm),
+          "qr_formq lds attribute");
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_qr_formq<RB, RPL, CG>), dim3(batch), dim3(RB * CG * 64), shm, s, m, n, Q, ws,
+                     (long)qr_ws_per_matrix(m, n));
+  check(hipGetLastError(), "qr_formq launch");
+  return true;
+}
+
+template <int CG>
+bool qr_formq_cg(int batch, int m, int n, const MatOut& Q, cplx* ws, hipStream_t s) {
+  return try_qr_formq<2, 4, CG>(batch, m, n, Q, ws, s) || try_qr_formq<2, 8, CG>(batch, m, n, Q, ws, s) ||
+         try_qr_formq<2, 12, CG>(batch, m, n, Q, ws, s) || try_qr_formq<2, 16, CG>(batch, m, n, Q, ws, s) ||
+         try_qr_formq<2, 20, CG>(batch, m, n, Q, ws, s) || try_qr_formq<2, 24, CG>(batch, m, n, Q, ws, s);
+}
 
 template <int RB, int RPL, int CG>
 bool try_qr_blk(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q,
@@ -442,7 +542,7 @@ bool try_qr_blk(int batch, int m, int n, const MatView& A, const MatOut& R, cons
   const long k = m < n ? m : n, np = (k + 15) / 16;
   // per-matrix slice of the qr() workspace
   const long wsz = (long)qr_ws_per_matrix(m, n);
-  if (np * (16L * m + 256) > wsz) return false;
+  if (np * (16L * m + 256 + 16) > wsz) return false;
   const size_t shm = (size_t)(MR * VST + RB * CG * 256) * sizeof(cplx);
   static bool attr = false;
   if (!attr) {
@@ -469,6 +569,21 @@ bool qr_blk_cg(int batch, int m, int n, const MatView& A, const MatOut& R, const
 }
 
 }  // namespace
+
+bool qr_form_q(int batch, int m, int n, MatOut Q, cplx* ws, hipStream_t s) {
+  if (batch <= 0 || m <= 0 || n <= 0) return true;
+  if (m < n || n <= 16 || n > 96 || m > 192) return false;
+  const int np = (n + 15) / 16;
+  hipLaunchKernelGGL(k_qr_tbuild, dim3(np, batch), dim3(256), 0, s, m, n, ws, (long)qr_ws_per_matrix(m, n));
+  check(hipGetLastError(), "qr_tbuild launch");
+  switch (np) {
+    case 2: return qr_formq_cg<2>(batch, m, n, Q, ws, s);
+    case 3: return qr_formq_cg<3>(batch, m, n, Q, ws, s);
+    case 4: return qr_formq_cg<4>(batch, m, n, Q, ws, s);
+    case 5: return qr_formq_cg<5>(batch, m, n, Q, ws, s);
+    default: return qr_formq_cg<6>(batch, m, n, Q, ws, s);
+  }
+}
 
 bool qr_blocked(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, hipStream_t s) {
   if (batch <= 0 || m <= 0 || n <= 0) return true;

@@ -92,11 +92,12 @@ void qr(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
         hipStream_t s);
 size_t qr_ws(int batch, int m, int n);
 // per-matrix slice of that workspace: the generic kernel's copy of A and
-// Q (m n + m k + k entries), or the blocked kernel's V and T of every
-// 16-column panel (np (16 m + 256) entries), whichever is larger
+// Q (m n + m k + k entries), or V, T and tau of every 16-column panel
+// (np (16 m + 256 + 16) entries: V[np][m][16], T[np][16][16], tau[np][16]),
+// whichever is larger
 inline size_t qr_ws_per_matrix(int m, int n) {
   const long k = m < n ? m : n, np = (k + 15) / 16;
-  const long gen = (long)m * n + (long)m * k + k, blk = np * (16L * m + 256);
+  const long gen = (long)m * n + (long)m * k + k, blk = np * (16L * m + 256 + 16);
   return (size_t)(gen > blk ? gen : blk);
 }
 // The global-memory kernel behind qr() for shapes the register kernels do
@@ -112,6 +113,17 @@ bool qr_fast(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, h
 // 16 < n <= 96, m <= 192; false when the shape is not covered.  `ws` as
 // for qr().
 bool qr_blocked(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, hipStream_t s);
+// R of the unblocked 2D-wave register kernel, with the Householder
+// vectors and tau per 16-column panel written to the workspace (layout of
+// qr_ws_per_matrix's blocked part) instead of Q; false when no variant
+// holds the shape (16 < n <= 96).
+bool qr_2d_vectors(int batch, int m, int n, MatView A, MatOut R, cplx* ws, hipStream_t s);
+// Q (m x k) from those vectors: T of each panel (compact WY), then the
+// block reflectors applied on the matrix cores in reverse panel order;
+// false when the shape is outside the blocked kernel's range.
+bool qr_form_q(int batch, int m, int n, MatOut Q, cplx* ws, hipStream_t s);
+// Unblocked register kernel with two columns per lane (n <= 96).
+bool qr_two_col(int batch, int m, int n, MatView A, MatOut R, MatOut Q, hipStream_t s);
 size_t qr_fast_ws(int batch, int m, int n);
 
 // One-sided Jacobi of batched square n x n matrices (n <= 96) resident in
