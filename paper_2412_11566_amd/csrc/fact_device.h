@@ -44,6 +44,18 @@ __device__ __forceinline__ double rcp_nt(double x) {
   return fma(r, fma(-x, r, 1.0), r);
 }
 
+// 1 / sqrt(x) and sqrt(x) from the hardware estimate and one Newton step
+// (x normal, positive)
+__device__ __forceinline__ double rsq_nt(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  return fma(0.5 * r, fma(-x * r, r, 1.0), r);
+}
+__device__ __forceinline__ double sqrt_nt(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  const double q0 = x * r;
+  return fma(fma(-q0, q0, x), 0.5 * r, q0);
+}
+
 // Householder reflector of a column with leading entry al and squared norm
 // s of the entries below it, H = I - tau v v^H with v = [1; x inv] and
 // H^H [al; x] = [beta; 0]:
@@ -63,10 +75,7 @@ __device__ __forceinline__ void householder(cplx al, double s, cplx& tau, cplx& 
     beta = al.x;
     return;
   }
-  const double r = __builtin_amdgcn_rsq(t);
-  const double q0 = t * r;
-  const double nrm = fma(fma(-q0, q0, t), 0.5 * r, q0);
-  beta = -copysign(nrm, al.x);
+  beta = -copysign(sqrt_nt(t), al.x);
   const double rb = rcp_nt(beta);
   const cplx d = make_double2(al.x - beta, al.y);
   const double rdd = rcp_nt(cabs2(d));

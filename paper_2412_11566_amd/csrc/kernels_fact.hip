@@ -1233,12 +1233,23 @@ __global__ __launch_bounds__(JNT) void k_jacobi_lds(int n, MatView A, MatOut U, 
         ga.x = row16_sum(ga.x);
         ga.y = row16_sum(ga.y);
         const double al = nrm2[ca], be = nrm2[cb];
-        const double gg = sqrt(cabs2(ga));
-        if (!(gg > tol * sqrt(al * be)) || al < 1e-300 || be < 1e-300) continue;
-        const double zeta = (be - al) / (2.0 * gg);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-        const cplx ph = make_double2(ga.x / gg, -ga.y / gg);
+        const double gg2 = cabs2(ga);
+        if (!(gg2 > tol * tol * (al * be)) || al < 1e-300 || be < 1e-300) continue;
+        // rotation angle: t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+        // zeta = (be - al) / (2 |ga|), written as w / (1 + sqrt(1 + w^2)) with
+        // w = 1 / |zeta| for |zeta| > 1 so no square overflows; reciprocals and
+        // square roots from the hardware estimates with a Newton step (the
+        // chain is on the critical path of every rotation round)
+        const double rg = rsq_nt(gg2), gg = gg2 * rg;
+        const double zeta = (be - al) * (0.5 * rg);
+        const double z = fabs(zeta);
+        const bool big = z > 1.0;
+        const double wz = big ? rcp_nt(z) : z;
+        const double s1 = sqrt_nt(fma(wz, wz, 1.0));
+        const double ta = big ? wz * rcp_nt(1.0 + s1) : rcp_nt(z + s1);
+        const double t = zeta >= 0.0 ? ta : -ta;
+        const double cs = rsq_nt(fma(t, t, 1.0)), sn = cs * t;
+        const cplx ph = make_double2(ga.x * rg, -ga.y * rg);
         for (int i = sub; i < n; i += 16) {
           const cplx u = xa[i], wv = cmul(ph, xb[i]);
           xa[i] = make_double2(cs * u.x - sn * wv.x, cs * u.y - sn * wv.y);
