@@ -3,8 +3,9 @@
 // One workgroup computes a complex tile of C with a grid of waves, each
 // wave a sub-tile of 16 x 16 MFMA blocks (tiles from 16 x 16 to 80 x 80,
 // chosen per shape to limit padding and fill the compute units).  The
-// complex product is four real MFMAs per block (re*re, -im*im, re*im,
-// im*re) into separate real and imaginary accumulators.  A and B stage
+// complex product is three real MFMAs per block where the registers hold a
+// third accumulator (Gauss: re*re, im*im and (re+im)*(re+im), combined
+// after the contraction), four otherwise.  A and B stage
 // through LDS in split real/imaginary planes, 16 complex values of K per
 // stage; the next stage is fetched into registers while the matrix cores
 // work on the current one.  Operand lane layout of the 16x16x4 FP64
@@ -35,7 +36,7 @@ constexpr int PER_T = MT * KT / NTHR;  // staged elements per thread and operand
 
 // FP64 kernel over a WM x WN grid of waves, each wave BM x BN MFMA blocks
 // of 16 x 16 (tile variants and their choice: plan_fp64 below).
-template <int WM, int WN, int BM, int BN>
+template <int WM, int WN, int BM, int BN, bool G3>
 __global__ __launch_bounds__(64 * WM * WN, 2) void k_zgemm_mfma(GemmArgs g, int ksplit, int kchunk) {
   constexpr int MT = 16 * BM * WM, NT = 16 * BN * WN, NTHR = 64 * WM * WN;
   constexpr int PER_TA = MT * KT / NTHR, PER_TB = NT * KT / NTHR;
@@ -51,13 +52,19 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_zgemm_mfma(GemmArgs g, int 
   const cplx* B = g.B + ob;
   const int kbeg = slice * kchunk, kend = min(g.K, kbeg + kchunk);
 
-  dv4 cr[BM][BN], ci[BM][BN];
+  // G3: three real products per complex block (Gauss): cr = Ar Br,
+  // c2 = Ai Bi, ci = (Ar + Ai)(Br + Bi); then Re C = cr - c2,
+  // Im C = ci - cr - c2.  Otherwise four: cr = Ar Br - Ai Bi,
+  // ci = Ar Bi + Ai Br (one accumulator fewer per block, for the variants
+  // whose registers cannot hold a third)
+  dv4 cr[BM][BN], ci[BM][BN], c2[G3 ? BM : 1][G3 ? BN : 1];
 #pragma unroll
   for (int i = 0; i < BM; ++i)
 #pragma unroll
     for (int j = 0; j < BN; ++j) {
       cr[i][j] = dv4{0.0, 0.0, 0.0, 0.0};
       ci[i][j] = dv4{0.0, 0.0, 0.0, 0.0};
+      if (G3) c2[G3 ? i : 0][G3 ? j : 0] = dv4{0.0, 0.0, 0.0, 0.0};
     }
 
   // fetch: raw loads only (indices clamped in range, validity kept in a
@@ -125,31 +132,48 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_zgemm_mfma(GemmArgs g, int 
 #pragma unroll
     for (int k4 = 0; k4 < KT / 4; ++k4) {
       const int kk = k4 * 4 + (lane >> 4);
-      double ar[BM], ai[BM], nai[BM], br[BN], bi[BN];
+      double ar[BM], ai[BM], sa[BM], br[BN], bi[BN], sb[BN];
 #pragma unroll
       for (int i = 0; i < BM; ++i) {
         const int mm = wm * 16 * BM + i * 16 + (lane & 15);
         ar[i] = Ar[kk][mm];
         ai[i] = Ai[kk][mm];
-        nai[i] = -ai[i];
+        sa[i] = G3 ? ar[i] + ai[i] : -ai[i];
       }
 #pragma unroll
       for (int j = 0; j < BN; ++j) {
         const int nn = wn * 16 * BN + j * 16 + (lane & 15);
         br[j] = Br[kk][nn];
         bi[j] = Bi[kk][nn];
+        sb[j] = G3 ? br[j] + bi[j] : 0.0;
       }
 #pragma unroll
       for (int i = 0; i < BM; ++i)
 #pragma unroll
         for (int j = 0; j < BN; ++j) {
           cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
+          if (G3) {
+            c2[G3 ? i : 0][G3 ? j : 0] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                ai[i], bi[j], c2[G3 ? i : 0][G3 ? j : 0], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[i], sb[j], ci[i][j], 0, 0, 0);
+          } else {  // sa = -Ai
+            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(sa[i], bi[j], cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
+          }
         }
     }
     __syncthreads();
+  }
+  if (G3) {
+#pragma unroll
+    for (int i = 0; i < BM; ++i)
+#pragma unroll
+      for (int j = 0; j < BN; ++j) {
+        const dv4 p2 = c2[G3 ? i : 0][G3 ? j : 0];
+        ci[i][j] = ci[i][j] - cr[i][j] - p2;
+        cr[i][j] = cr[i][j] - p2;
+      }
   }
 
   if (ksplit > 1) {
@@ -375,21 +399,23 @@ __global__ __launch_bounds__(256) void k_zgemm_reduce(GemmArgs g, int ksplit) {
 // 16 x 80 (or 80 x 16) strip of five blocks.
 struct TileV {
   int wm, wn, bm, bn;
+  bool g3;     // three real products per complex block (registers permitting)
+  double eff;  // measured rate on padded work, relative units
   int mt() const { return 16 * bm * wm; }
   int nt() const { return 16 * bn * wn; }
   int waves() const { return wm * wn; }
 };
 constexpr TileV kTiles[] = {
-    {1, 1, 1, 1},   // 16 x 16
-    {2, 2, 1, 1},   // 32 x 32
-    {2, 2, 2, 2},   // 64 x 64
-    {5, 1, 1, 5},   // 80 x 80
-    {2, 1, 1, 5},   // 32 x 80
-    {1, 2, 5, 1},   // 80 x 32
-    {4, 1, 1, 5},   // 64 x 80
+    {1, 1, 1, 1, true, 3.0},     // 16 x 16
+    {2, 2, 1, 1, true, 6.4},     // 32 x 32
+    {2, 2, 2, 2, true, 7.0},     // 64 x 64
+    {5, 1, 1, 5, true, 4.6},     // 80 x 80
+    {2, 1, 1, 5, false, 5.3},    // 32 x 80
+    {1, 2, 5, 1, false, 5.25},   // 80 x 32
+    {4, 1, 1, 5, true, 7.7},     // 64 x 80
 };
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
-constexpr TileV kTileFp32 = {2, 2, 2, 2};  // the FP32 kernel's fixed tile
+constexpr TileV kTileFp32 = {2, 2, 2, 2, false, 1.0};  // the FP32 kernel's fixed tile
 
 bool gemm_mfma_ok(int M, int N, int K) { return M >= 16 && N >= 16 && K >= 4 && (M + 15) / 16 <= 65535; }
 
@@ -413,11 +439,13 @@ struct Plan {
 };
 
 // The FP64 variant with the least modelled time: padded MFMA work over the
-// waves that run it (up to two per SIMD), with an operand-staging overhead
-// that falls with the tile size (fitted to measured rates: about 50% of the
-// matrix-core peak on padded work for 32 x 32 tiles, 62% for 64 x 64 and
-// 64 x 80), and a penalty for 5-wave workgroups, of which one fits a compute
-// unit at two waves per SIMD (one SIMD then runs two of the five waves).
+// waves that run it (up to two per SIMD) and over the variant's rate on
+// padded work, measured on the batched products of TT-rounding (rank-80
+// sketches against operator ranks of 60 to 160): 64 x 80 tiles with three
+// products per block lead, 5-wave 80 x 80 tiles trail (one workgroup per
+// compute unit at two waves per SIMD leaves one SIMD with two of its five
+// waves).  Split-K shapes pay their padding twice: the padded slices also
+// write and reduce partial sums.
 static Plan plan_fp64(int M, int N, int K, long nbatch) {
   Plan best{2, 1};
   double bestc = 0.0;
@@ -431,8 +459,8 @@ static Plan plan_fp64(int M, int N, int K, long nbatch) {
     const double work = (double)tm * t.mt() * (double)tn * t.nt() * kp * nbatch;
     const double waves = (double)tm * tn * nbatch * ks * t.waves();
     const double par = std::min(waves, (double)kWaveTarget);
-    const double balance = t.waves() == 5 ? 5.0 / 8.0 : 1.0;
-    const double c = work / par * (1.0 + 10.0 / t.mt() + 10.0 / t.nt()) / balance;
+    const double pad = (double)tm * t.mt() * tn * t.nt() / ((double)M * N);
+    const double c = work / (par * t.eff) * (ks > 1 ? pad * pad : 1.0);
     if (bestc == 0.0 || c < bestc) {
       bestc = c;
       best = Plan{v, ks};
@@ -453,11 +481,11 @@ size_t gemm_ws_elems(const GemmArgs& g, int ksplit) {
   return ksplit > 1 ? (size_t)ksplit * gemm_nbatch(g) * (size_t)g.M * g.N : 0;
 }
 
-template <int WM, int WN, int BM, int BN>
+template <int WM, int WN, int BM, int BN, bool G3>
 static void launch_fp64(const GemmArgs& g, int ks, int kchunk, hipStream_t s) {
   constexpr int MT = 16 * BM * WM, NT = 16 * BN * WN;
   dim3 grid((g.N + NT - 1) / NT, (g.M + MT - 1) / MT, (unsigned)(gemm_nbatch(g) * ks));
-  hipLaunchKernelGGL((k_zgemm_mfma<WM, WN, BM, BN>), grid, dim3(64 * WM * WN), 0, s, g, ks, kchunk);
+  hipLaunchKernelGGL((k_zgemm_mfma<WM, WN, BM, BN, G3>), grid, dim3(64 * WM * WN), 0, s, g, ks, kchunk);
 }
 
 bool gemm_mfma(const GemmArgs& g, hipStream_t s) {
@@ -483,13 +511,13 @@ bool gemm_mfma(const GemmArgs& g, hipStream_t s) {
     hipLaunchKernelGGL(k_zgemm_mfma32, grid, dim3(NTHR), 0, s, g, ks, kchunk);
   } else {
     switch (pl.v) {
-      case 0: launch_fp64<1, 1, 1, 1>(g, ks, kchunk, s); break;
-      case 1: launch_fp64<2, 2, 1, 1>(g, ks, kchunk, s); break;
-      case 2: launch_fp64<2, 2, 2, 2>(g, ks, kchunk, s); break;
-      case 3: launch_fp64<5, 1, 1, 5>(g, ks, kchunk, s); break;
-      case 4: launch_fp64<2, 1, 1, 5>(g, ks, kchunk, s); break;
-      case 5: launch_fp64<1, 2, 5, 1>(g, ks, kchunk, s); break;
-      default: launch_fp64<4, 1, 1, 5>(g, ks, kchunk, s); break;
+      case 0: launch_fp64<1, 1, 1, 1, true>(g, ks, kchunk, s); break;
+      case 1: launch_fp64<2, 2, 1, 1, true>(g, ks, kchunk, s); break;
+      case 2: launch_fp64<2, 2, 2, 2, true>(g, ks, kchunk, s); break;
+      case 3: launch_fp64<5, 1, 1, 5, true>(g, ks, kchunk, s); break;
+      case 4: launch_fp64<2, 1, 1, 5, false>(g, ks, kchunk, s); break;
+      case 5: launch_fp64<1, 2, 5, 1, false>(g, ks, kchunk, s); break;
+      default: launch_fp64<4, 1, 1, 5, true>(g, ks, kchunk, s); break;
     }
   }
   check(hipGetLastError(), "zgemm_mfma launch");
