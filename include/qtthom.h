@@ -292,12 +292,18 @@ int qtt_zqr(qtt_ctx* ctx, int batch, int m, int n, const void* A, void* R,
 int qtt_zjacobi(qtt_ctx* ctx, int batch, int n, const void* A, void* U,
                 double* S);
 
-/* Kernel statistics for roofline accounting.  When enabled, every launch
- * of the library's kernels is bracketed by HIP events on the context's
- * stream; qtt_stats_get synchronises and returns, for one kernel family
- * (QTT_K_*), the number of launches, the summed event time in seconds,
- * and the algorithmic FP64 flops and HBM bytes of those launches (counted
- * from the operand shapes, not measured). */
+/* Kernel statistics for roofline accounting.  qtt_stats_enable(ctx, s)
+ * with s >= 1 brackets every s-th launch of the library's kernels by HIP
+ * events on the context's stream (s = 1: every launch; a larger s keeps
+ * the event records' own cost out of a timed run), 0 turns statistics
+ * off, negative s is QTT_EINVAL.  An event pair measures from the end of
+ * the preceding work on the stream to the end of the launch, dispatch gap
+ * included.  qtt_stats_get synchronises and returns, for one kernel family
+ * (QTT_K_*) and over the timed launches only, their number, the summed
+ * event time in seconds, and their algorithmic FP64 flops and HBM bytes
+ * (counted from the operand shapes, not measured); qtt_stats_get_all
+ * returns the number, flops and bytes of every launch (timed or not).
+ * qtt_stats_reset clears both and restarts the sampling. */
 #define QTT_K_GEMM      0   /* batched complex GEMM, vector ALU kernel      */
 #define QTT_K_QR        1   /* Householder QR                               */
 #define QTT_K_JACOBI    2   /* one-sided Jacobi SVD                         */
@@ -309,6 +315,8 @@ int qtt_zjacobi(qtt_ctx* ctx, int batch, int n, const void* A, void* U,
 int qtt_stats_enable(qtt_ctx* ctx, int on);
 int qtt_stats_get(qtt_ctx* ctx, int family, long long* launches,
                   double* seconds, double* flops, double* bytes);
+int qtt_stats_get_all(qtt_ctx* ctx, int family, long long* launches,
+                      double* flops, double* bytes);
 int qtt_stats_reset(qtt_ctx* ctx);
 
 /* Many problems in one call (the six load cases of each are batched

@@ -341,7 +341,8 @@ def ls_solve_prepared(ctx: Context, prep: Prepared, opts: SolveOptions, keep_eps
     return Ceff.reshape(6, 6), _report(rep), (Tensor(ctx, eps) if keep_eps else None)
 
 
-def stats_enable(ctx: Context, on: bool = True):
+def stats_enable(ctx: Context, on=True):
+    """on: False/0 off, True/1 every launch timed, s > 1 every s-th launch."""
     ctx.check(_c.lib().qtt_stats_enable(ctx.h, int(on)))
 
 
@@ -356,6 +357,16 @@ def stats_get(ctx: Context, family: int) -> dict:
                                      C.byref(by)))
     return {"family": _c.KERNEL_FAMILIES[family], "launches": n.value, "seconds": sec.value,
             "flops": fl.value, "bytes": by.value}
+
+
+def stats_get_all(ctx: Context, family: int) -> dict:
+    """Launch count, flops and bytes over every launch of a family (timed or
+    not)."""
+    n = C.c_longlong()
+    fl, by = C.c_double(), C.c_double()
+    ctx.check(_c.lib().qtt_stats_get_all(ctx.h, family, C.byref(n), C.byref(fl), C.byref(by)))
+    return {"family": _c.KERNEL_FAMILIES[family], "launches": n.value, "flops": fl.value,
+            "bytes": by.value}
 
 
 _OPS = {"N": 0, "T": 1, "C": 2}

@@ -97,6 +97,7 @@ SIGNATURES = {
     "qtt_stats_enable": (I, [P, I]),
     "qtt_stats_get": (I, [P, I, C.POINTER(C.c_longlong), DP, DP, DP]),
     "qtt_stats_reset": (I, [P]),
+    "qtt_stats_get_all": (I, [P, I, C.POINTER(C.c_longlong), DP, DP]),
 }
 
 QTT_K_GEMM = 0

@@ -152,12 +152,17 @@ struct qtt_ctx {
   // SFFT and Green factors per (n, delta): shared by every problem of that
   // grid size (the factors do not depend on the reference medium)
   std::map<std::pair<int, double>, std::shared_ptr<qtt_tensor>> sfft_cache, green_cache;
-  // kernel statistics (HIP events around launches)
+  // kernel statistics (HIP events around every stats_stride-th launch;
+  // flops and bytes of every launch are counted as well)
   bool stats_on = false;
+  int stats_stride = 1;
+  unsigned long long stats_tick = 0;
   std::vector<qtt_stat_rec> pending;
   std::vector<hipEvent_t> evfree;
   long long st_calls[QTT_K_COUNT] = {0};
   double st_secs[QTT_K_COUNT] = {0}, st_flops[QTT_K_COUNT] = {0}, st_bytes[QTT_K_COUNT] = {0};
+  long long st_all_calls[QTT_K_COUNT] = {0};
+  double st_all_flops[QTT_K_COUNT] = {0}, st_all_bytes[QTT_K_COUNT] = {0};
   ~qtt_ctx() {
     for (auto& r : pending) {
       (void)hipEventDestroy(r.a);
@@ -189,14 +194,22 @@ struct Ctx {
     check(hipEventCreate(&e), "event create");
     return e;
   }
+  // t0 before a launch, t1 after it: a null handle when statistics are
+  // off, the untimed marker for launches between samples
+  static hipEvent_t untimed() { static int tag; return reinterpret_cast<hipEvent_t>(&tag); }
   hipEvent_t t0() const {
     if (!c->stats_on) return nullptr;
+    if (c->stats_tick++ % (unsigned long long)c->stats_stride != 0) return untimed();
     hipEvent_t e = ev();
     check(hipEventRecord(e, c->stream), "event record");
     return e;
   }
   void t1(hipEvent_t a, int fam, double flops, double bytes) const {
     if (!a) return;
+    c->st_all_calls[fam] += 1;
+    c->st_all_flops[fam] += flops;
+    c->st_all_bytes[fam] += bytes;
+    if (a == untimed()) return;
     hipEvent_t e = ev();
     check(hipEventRecord(e, c->stream), "event record");
     c->pending.push_back({fam, a, e, flops, bytes});
@@ -257,10 +270,20 @@ static void GB(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long l
     g.ws = (cplx*)ws->p;
     g.ksplit = ks;
   }
+  if (gemm_nbatch(g) > 65535) throw std::runtime_error("gemm: batch too large");
+  // the statistics bracket the product kernel alone; the split-K sum of
+  // slices (an elementwise pass) is counted with the other helpers
   hipEvent_t e = X.t0();
-  const bool mc = gemm(g, X.s());
+  int ks_used = 1;
+  const bool mc = gemm_mfma_main(g, X.s(), ks_used);
+  if (!mc) gemm_vector(g, X.s());
   X.t1(e, mc ? (g.fp32 ? QTT_K_MFMA32 : QTT_K_MFMA) : QTT_K_GEMM, 8.0 * M * N * K * nb,
        16.0 * ((double)M * K + (double)K * N + (beta.x != 0.0 || beta.y != 0.0 ? 2.0 : 1.0) * M * N) * nb);
+  if (ks_used > 1) {
+    hipEvent_t e2 = X.t0();
+    gemm_mfma_reduce(g, ks_used, X.s());
+    X.t1(e2, QTT_K_OTHER, 0.0, 16.0 * ((double)ks_used + 1.0 + (beta.x != 0.0 || beta.y != 0.0 ? 1.0 : 0.0)) * M * N * nb);
+  }
 }
 
 static void G(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long lda, int opB,
@@ -1978,8 +2001,18 @@ int qtt_zjacobi(qtt_ctx* c, int batch, int n, const void* A, void* U, double* S)
 }
 
 int qtt_stats_enable(qtt_ctx* c, int on) {
-  if (!c) return QTT_EINVAL;
+  if (!c || on < 0) return QTT_EINVAL;
   c->stats_on = on != 0;
+  c->stats_stride = on > 0 ? on : 1;
+  c->stats_tick = 0;
+  return QTT_OK;
+}
+
+int qtt_stats_get_all(qtt_ctx* c, int fam, long long* launches, double* flops, double* bytes) {
+  if (!c || fam < 0 || fam >= QTT_K_COUNT) return QTT_EINVAL;
+  if (launches) *launches = c->st_all_calls[fam];
+  if (flops) *flops = c->st_all_flops[fam];
+  if (bytes) *bytes = c->st_all_bytes[fam];
   return QTT_OK;
 }
 
@@ -2000,9 +2033,11 @@ int qtt_stats_reset(qtt_ctx* c) {
   QTT_TRY(c, {
     stats_collect(c);
     for (int f = 0; f < QTT_K_COUNT; ++f) {
-      c->st_calls[f] = 0;
+      c->st_calls[f] = c->st_all_calls[f] = 0;
       c->st_secs[f] = c->st_flops[f] = c->st_bytes[f] = 0.0;
+      c->st_all_flops[f] = c->st_all_bytes[f] = 0.0;
     }
+    c->stats_tick = 0;
   });
 }
 

@@ -489,6 +489,22 @@ static void launch_fp64(const GemmArgs& g, int ks, int kchunk, hipStream_t s) {
 }
 
 bool gemm_mfma(const GemmArgs& g, hipStream_t s) {
+  int ks = 1;
+  if (!gemm_mfma_main(g, s, ks)) return false;
+  gemm_mfma_reduce(g, ks, s);
+  return true;
+}
+
+void gemm_mfma_reduce(const GemmArgs& g, int ks, hipStream_t s) {
+  if (ks <= 1) return;
+  const long total = gemm_nbatch(g) * g.M * (long)g.N;
+  const long blocks = std::min<long>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)blocks), dim3(256), 0, s, g, ks);
+  check(hipGetLastError(), "zgemm_reduce launch");
+}
+
+bool gemm_mfma_main(const GemmArgs& g, hipStream_t s, int& ks_used) {
+  ks_used = 1;
   if (!gemm_mfma_ok(g.M, g.N, g.K)) return false;
   const long nb = gemm_nbatch(g);
   Plan pl = g.fp32 ? Plan{-1, 1} : plan_fp64(g.M, g.N, g.K, nb);
@@ -521,12 +537,7 @@ bool gemm_mfma(const GemmArgs& g, hipStream_t s) {
     }
   }
   check(hipGetLastError(), "zgemm_mfma launch");
-  if (ks > 1) {
-    const long total = nb * g.M * (long)g.N;
-    const long blocks = std::min<long>((total + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_zgemm_reduce, dim3((unsigned)blocks), dim3(256), 0, s, g, ks);
-    check(hipGetLastError(), "zgemm_reduce launch");
-  }
+  ks_used = ks;
   return true;
 }
 

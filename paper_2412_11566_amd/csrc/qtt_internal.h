@@ -64,6 +64,10 @@ bool gemm(const GemmArgs& g, hipStream_t s);
 // Matrix-core path of gemm for M, N >= 16 and K >= 4 (kernels_mfma.hip);
 // returns false when the shape is left to the vector kernel.
 bool gemm_mfma(const GemmArgs& g, hipStream_t s);
+// The two launches of gemm_mfma separately: the product (K slices into the
+// workspace when ks_used > 1) and the ordered sum of the slices.
+bool gemm_mfma_main(const GemmArgs& g, hipStream_t s, int& ks_used);
+void gemm_mfma_reduce(const GemmArgs& g, int ks, hipStream_t s);
 // The K split the matrix-core path wants for this shape and precision
 // (1: none) and the workspace it then needs.
 int gemm_ksplit(int M, int N, int K, long nbatch, bool fp32, int tile = -1);
