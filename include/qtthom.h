@@ -280,8 +280,11 @@ int qtt_zgemm(qtt_ctx* ctx, int opA, int opB, int M, int N, int K,
  * orthonormal columns) with A = Q R.  path 0: the kernels the library
  * uses, 1: the global-memory kernel, 2: the blocked matrix-core kernel
  * (m >= n, 16 < n <= 96, m <= 192), 3: the register-resident unblocked
- * kernels (m <= 256, n <= 128); QTT_EINVAL when the forced path does not
- * cover the shape.  Synchronises the stream before returning.
+ * kernels (m <= 256, n <= 128), 4: the two-columns-per-lane register
+ * kernel (n <= 96), 5: the one-wave-per-column-group kernel for R (m <=
+ * 160, n <= 96) with Q from the matrix-core block reflectors (Q needs
+ * m >= n > 16); QTT_EINVAL when the forced path does not cover the shape.
+ * Synchronises the stream before returning.
  *
  * qtt_zjacobi: one-sided Jacobi of batch n x n matrices A (n <= 96):
  * A V = U diag(S) with U (n x n) orthonormal columns for the nonzero S

@@ -1964,7 +1964,7 @@ int qtt_zgemm(qtt_ctx* c, int opA, int opB, int M, int N, int K, const double* a
 }
 
 int qtt_zqr(qtt_ctx* c, int batch, int m, int n, const void* A, void* R, void* Qo, int path) {
-  if (!c || !A || !R || batch < 1 || batch > 65535 || m < 1 || n < 1 || path < 0 || path > 4)
+  if (!c || !A || !R || batch < 1 || batch > 65535 || m < 1 || n < 1 || path < 0 || path > 5)
     return QTT_EINVAL;
   QTT_TRY(c, {
     Ctx X{c};
@@ -1984,8 +1984,15 @@ int qtt_zqr(qtt_ctx* c, int batch, int m, int n, const void* A, void* R, void* Q
     } else if (path == 3) {
       if (!qr_fast(batch, m, n, av, ro, qo, (cplx*)ws->p, c->stream))
         throw std::invalid_argument("zqr: shape not covered by the register-resident kernels");
-    } else if (!qr_two_col(batch, m, n, av, ro, qo, c->stream)) {
-      throw std::invalid_argument("zqr: shape not covered by the two-column register kernel");
+    } else if (path == 4) {
+      if (!qr_two_col(batch, m, n, av, ro, qo, c->stream))
+        throw std::invalid_argument("zqr: shape not covered by the two-column register kernel");
+    } else {
+      const bool qok = !Qo || (m >= n && n > 16 && n <= 96);
+      if (!qok || !qr_one_rowblock(batch, m, n, av, ro, Qo ? (cplx*)ws->p : nullptr, c->stream))
+        throw std::invalid_argument("zqr: shape not covered by the one-row-block kernel");
+      if (Qo && !qr_form_q(batch, m, n, qo, (cplx*)ws->p, c->stream))
+        throw std::invalid_argument("zqr: shape not covered by the matrix-core Q formation");
     }
     X.sync();  // the workspace is released on return
   });

@@ -298,10 +298,15 @@ void qr(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
   // R from the unblocked register kernel, Q from its Householder vectors
   // as block reflectors on the matrix cores (160 x 80: Q formation 70 us
   // against 157 us in the register kernel)
-  if (Q.base != nullptr && m >= n && n > 16 && n <= 96 && m <= 192 &&
-      qr_2d_vectors(batch, m, n, A, R, ws, s)) {
-    if (!qr_form_q(batch, m, n, Q, ws, s)) throw std::logic_error("qr: Q formation shape");
-    return;
+  if (m >= n && n > 16 && n <= 96 && m <= 192) {
+    if (Q.base != nullptr) {
+      if (qr_2d_vectors(batch, m, n, A, R, ws, s)) {
+        if (!qr_form_q(batch, m, n, Q, ws, s)) throw std::logic_error("qr: Q formation shape");
+        return;
+      }
+    } else if (m <= 32 && qr_one_rowblock(batch, m, n, A, R, nullptr, s)) {
+      return;
+    }
   }
   if (qr_fast(batch, m, n, A, R, Q, ws, s)) return;
   qr_generic(batch, m, n, A, R, Q, ws, s);

@@ -149,11 +149,24 @@ __device__ __forceinline__ void formq_phase(int m, int k, int np, int b, int tid
     OPAQUE(rq, rq0);
     OPAQUE(cl, cl0);
     __syncthreads();  // the previous panel's Vs, Ts, Wp reads are done
-    for (int e = tid; e < MR * 16; e += NT) {
-      const int row = e >> 4, c = e & 15;
-      Vs[row * VST + c] = row < m ? Vg[((long)p * m + row) * 16 + c] : cz();
+    {
+      // every load of the panel issued before the LDS stores
+      constexpr int CNT = (MR * 16 + NT - 1) / NT;
+      cplx t[CNT];
+#pragma unroll
+      for (int q = 0; q < CNT; ++q) {
+        const int e = tid + q * NT, row = min(e >> 4, m - 1);
+        t[q] = Vg[((long)p * m + row) * 16 + (e & 15)];
+      }
+      const cplx tt = Tg[(long)p * 256 + (tid & 255)];
+#pragma unroll
+      for (int q = 0; q < CNT; ++q) {
+        const int e = tid + q * NT, row = e >> 4;
+        if (e < MR * 16)
+          Vs[row * VST + (e & 15)] = make_double2(row < m ? t[q].x : 0.0, row < m ? t[q].y : 0.0);
+      }
+      if (tid < 256) Ts[tid >> 4][tid & 15] = tt;
     }
-    for (int e = tid; e < 256; e += NT) Ts[e >> 4][e & 15] = Tg[(long)p * 256 + e];
     __syncthreads();
     const bool live = cg >= p;
     if (live) {
@@ -474,14 +487,22 @@ __global__ __launch_bounds__(256) void k_qr_tbuild(int m, int n, cplx* ws, long 
   const cplx* tau = W + (long)np * m * 16 + (long)np * 256 + (long)p * 16;
   __shared__ cplx Gp[4][256];
   dv4 gr = {0.0, 0.0, 0.0, 0.0}, gi = {0.0, 0.0, 0.0, 0.0};
-  // V is zero above row 16 p
-  for (int sl = 4 * p + w; 4 * sl < m; sl += 4) {
-    const int row = 4 * sl + rq;
-    const cplx v = row < m ? V[(long)row * 16 + cl] : cz();
-    gr = mfma(v.x, v.x, gr);
-    gr = mfma(v.y, v.y, gr);
-    gi = mfma(v.x, v.y, gi);
-    gi = mfma(-v.y, v.x, gi);
+  // V is zero above row 16 p; this wave's 4-row slices sl = 4 p + w + 4 q
+  // (at most 12 for m <= 192), every load issued before the products
+  constexpr int MAXQ = 12;
+  cplx v[MAXQ];
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+    const int row = 4 * (4 * p + w + 4 * q) + rq;
+    const cplx t = V[(long)min(row, m - 1) * 16 + cl];
+    v[q] = make_double2(row < m ? t.x : 0.0, row < m ? t.y : 0.0);
+  }
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) {
+    gr = mfma(v[q].x, v[q].x, gr);
+    gr = mfma(v[q].y, v[q].y, gr);
+    gi = mfma(v[q].x, v[q].y, gi);
+    gi = mfma(-v[q].y, v[q].x, gi);
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) Gp[w][(4 * r + rq) * 16 + cl] = make_double2(gr[r], gi[r]);

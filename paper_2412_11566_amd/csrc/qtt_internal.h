@@ -122,6 +122,10 @@ bool qr_blocked(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws
 // qr_ws_per_matrix's blocked part) instead of Q; false when no variant
 // holds the shape (16 < n <= 96).
 bool qr_2d_vectors(int batch, int m, int n, MatView A, MatOut R, cplx* ws, hipStream_t s);
+// R (and, with vout, the panel vectors) from the kernel with one wave per
+// 16-column group holding all rows (n <= 96, m <= 160); false otherwise.
+bool qr_one_rowblock(int batch, int m, int n, const MatView& A, const MatOut& R, cplx* vout,
+                     hipStream_t s);
 // Q (m x k) from those vectors: T of each panel (compact WY), then the
 // block reflectors applied on the matrix cores in reverse panel order;
 // false when the shape is outside the blocked kernel's range.

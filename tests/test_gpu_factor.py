@@ -102,6 +102,30 @@ def test_zqr_two_columns_per_lane(ctx, shape):
     assert torch.equal(R, R2)
 
 
+QR_ONE_ROWBLOCK_SHAPES = [(160, 80), (128, 80), (96, 80), (160, 64), (64, 64), (48, 48), (128, 32),
+                          (33, 20), (17, 17), (100, 96), (160, 17), (150, 90)]
+
+
+@pytest.mark.parametrize("shape", QR_ONE_ROWBLOCK_SHAPES)
+def test_zqr_one_rowblock(ctx, shape):
+    """One wave per 16-column group over all rows (one barrier per column),
+    Q from the panel vectors as matrix-core block reflectors."""
+    import torch
+    import paper_2412_11566_amd as q
+    m, n = shape
+    k = min(m, n)
+    rng = np.random.default_rng(m * 17 + n)
+    a = _rand(rng, 3, m, n)
+    A = torch.from_numpy(a).cuda()
+    R = torch.zeros((3, k, n), dtype=torch.complex128, device="cuda")
+    Q = torch.zeros((3, m, k), dtype=torch.complex128, device="cuda")
+    q.zqr(ctx, A, R, Q, path=5)
+    _check_qr(a, R.cpu().numpy(), Q.cpu().numpy())
+    R2 = torch.zeros_like(R)
+    q.zqr(ctx, A, R2, path=5)
+    assert torch.equal(R, R2)
+
+
 def test_zqr_blocked_rejects_uncovered(ctx):
     import torch
     import paper_2412_11566_amd as q
@@ -122,10 +146,12 @@ def test_zqr_rank_deficient_and_generic_path(ctx, shape):
     rng = np.random.default_rng(5)
     a = _rand(rng, 2, m, 5) @ _rand(rng, 2, 5, n)
     a[:, :, 3] = 0.0                       # an exactly zero column
-    for path in (0, 1, 2, 3, 4):
+    for path in (0, 1, 2, 3, 4, 5):
         if path == 2 and not (m >= n and 16 < n <= 96 and m <= 192):
             continue
         if path == 4 and n > 96:
+            continue
+        if path == 5 and not (m >= n and 16 < n <= 96 and m <= 160):
             continue
         A = torch.from_numpy(a).cuda()
         R = torch.zeros((2, k, n), dtype=torch.complex128, device="cuda")
@@ -146,8 +172,10 @@ def test_zqr_tiny_columns(ctx, shape):
     a = _rand(rng, 2, m, n)
     a[:, :, 1] *= 1e-155
     a[:, :, 5] *= 1e-300
-    for path in (0, 2, 4):
+    for path in (0, 2, 4, 5):
         if path == 2 and not (m >= n and 16 < n <= 96 and m <= 192):
+            continue
+        if path == 5 and not (m >= n and 16 < n <= 96 and m <= 160):
             continue
         A = torch.from_numpy(a).cuda()
         R = torch.zeros((2, k, n), dtype=torch.complex128, device="cuda")
