@@ -1381,9 +1381,21 @@ __global__ __launch_bounds__(JNT) void k_jacobi_lds(int n, MatView A, MatOut U, 
         if (ca > cb) { const int t = ca; ca = cb; cb = t; }
         cplx* xa = Wl + ca * n;
         cplx* xb = Wl + cb * n;
+        // the pair's rows of this lane in registers: one LDS round trip for
+        // the loads, the rotation writes back from them
+        constexpr int JR = (JMAXN + 15) / 16;
+        cplx va[JR], vb[JR];
+#pragma unroll
+        for (int q = 0; q < JR; ++q) {
+          const int i = min(sub + 16 * q, n - 1);
+          va[q] = xa[i];
+          vb[q] = xb[i];
+        }
         cplx ga = make_double2(0.0, 0.0);
-        for (int i = sub; i < n; i += 16) {
-          const cplx t = cdotc(xa[i], xb[i]);
+#pragma unroll
+        for (int q = 0; q < JR; ++q) {
+          if (sub + 16 * q >= n) continue;
+          const cplx t = cdotc(va[q], vb[q]);
           ga = make_double2(ga.x + t.x, ga.y + t.y);
         }
         // the 16 lanes of a pair are one DPP row
@@ -1407,8 +1419,11 @@ __global__ __launch_bounds__(JNT) void k_jacobi_lds(int n, MatView A, MatOut U, 
         const double t = zeta >= 0.0 ? ta : -ta;
         const double cs = rsq_nt(fma(t, t, 1.0)), sn = cs * t;
         const cplx ph = make_double2(ga.x * rg, -ga.y * rg);
-        for (int i = sub; i < n; i += 16) {
-          const cplx u = xa[i], wv = cmul(ph, xb[i]);
+#pragma unroll
+        for (int q = 0; q < JR; ++q) {
+          const int i = sub + 16 * q;
+          if (i >= n) continue;
+          const cplx u = va[q], wv = cmul(ph, vb[q]);
           xa[i] = make_double2(cs * u.x - sn * wv.x, cs * u.y - sn * wv.y);
           xb[i] = make_double2(sn * u.x + cs * wv.x, sn * u.y + cs * wv.y);
         }
