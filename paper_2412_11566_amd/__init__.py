@@ -89,8 +89,12 @@ class Tensor:
         self.h = h
 
     def __del__(self):
-        if getattr(self, "h", None):
-            _c.lib().qtt_tensor_destroy(self.h)
+        # at interpreter shutdown the module globals may already be gone
+        if getattr(self, "h", None) and _c is not None:
+            try:
+                _c.lib().qtt_tensor_destroy(self.h)
+            except Exception:
+                pass
             self.h = None
 
     def shape(self):
@@ -318,8 +322,11 @@ class Prepared:
         self._keep = keep
 
     def __del__(self):
-        if getattr(self, "h", None):
-            _c.lib().qtt_prepared_destroy(self.h)
+        if getattr(self, "h", None) and _c is not None:
+            try:
+                _c.lib().qtt_prepared_destroy(self.h)
+            except Exception:
+                pass
             self.h = None
 
 
