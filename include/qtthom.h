@@ -87,6 +87,8 @@ typedef struct qtt_solve_opts {
     int oversample;          /* extra sketch rank beyond cap (>= 0)        */
     int exact;               /* nonzero: sketch at full structural rank    */
     uint64_t seed;           /* seed of the sketching random numbers       */
+    int streams;             /* load-case groups solved concurrently, each
+                                on a stream of its own (<= 1: one stream) */
 } qtt_solve_opts;
 
 typedef struct qtt_report {
@@ -299,9 +301,15 @@ int qtt_zjacobi(qtt_ctx* ctx, int batch, int n, const void* A, void* U,
  * with s >= 1 brackets every s-th launch of the library's kernels by HIP
  * events on the context's stream (s = 1: every launch; a larger s keeps
  * the event records' own cost out of a timed run), 0 turns statistics
- * off, negative s is QTT_EINVAL.  An event pair measures from the end of
- * the preceding work on the stream to the end of the launch, dispatch gap
- * included.  qtt_stats_get synchronises and returns, for one kernel family
+ * off, negative s is QTT_EINVAL.  The matrix-core GEMM (QTT_K_MFMA,
+ * QTT_K_MFMA32) is timed by the kernel itself: the span from its first
+ * workgroup's start to its last workgroup's end on the device's
+ * constant-rate real-time counter (the interval a kernel-trace profiler
+ * reports).  Every other family is timed by a HIP event pair from the end
+ * of the preceding work on the stream to the end of the launch, dispatch
+ * gap included.  With concurrent load-case groups (qtt_solve_opts.streams
+ * > 1) kernels of different groups share the device and each duration
+ * includes that sharing.  qtt_stats_get synchronises and returns, for one kernel family
  * (QTT_K_*) and over the timed launches only, their number, the summed
  * event time in seconds, and their algorithmic FP64 flops and HBM bytes
  * (counted from the operand shapes, not measured); qtt_stats_get_all

@@ -229,10 +229,11 @@ class SolveOptions:
     oversample: int = 16
     exact: bool = False
     seed: int = 0
+    streams: int = 1
 
     def c(self) -> _c.SolveOpts:
         return _c.SolveOpts(self.delta, self.tol, self.cap, self.max_iter, self.precision,
-                            self.oversample, int(self.exact), self.seed)
+                            self.oversample, int(self.exact), self.seed, self.streams)
 
 
 @dataclass

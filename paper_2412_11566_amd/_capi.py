@@ -43,7 +43,7 @@ class Problem(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("delta", C.c_double), ("tol", C.c_double), ("cap", C.c_int),
                 ("max_iter", C.c_int), ("precision", C.c_int), ("oversample", C.c_int),
-                ("exact", C.c_int), ("seed", C.c_uint64)]
+                ("exact", C.c_int), ("seed", C.c_uint64), ("streams", C.c_int)]
 
 
 class Report(C.Structure):

@@ -25,6 +25,7 @@
 #include <cstring>
 #include <map>
 #include <thread>
+#include <array>
 #include <atomic>
 #include <exception>
 #include <memory>
@@ -134,8 +135,9 @@ struct qtt_tensor {
 
 struct qtt_stat_rec {
   int fam;
-  hipEvent_t a, b;
+  hipEvent_t a, b;  // event pair, or null when the launch recorded a span
   double flops, bytes;
+  int slot;         // span slot of the launch (-1: event pair)
 };
 
 struct qtt_ctx {
@@ -159,16 +161,36 @@ struct qtt_ctx {
   unsigned long long stats_tick = 0;
   std::vector<qtt_stat_rec> pending;
   std::vector<hipEvent_t> evfree;
+  // span slots of the timed matrix-core launches (device {start, end}
+  // pairs of real-time counter ticks at span_hz)
+  static constexpr int SPAN_SLOTS = 16384;
+  unsigned long long* span = nullptr;
+  int span_used = 0;
+  double span_hz = 0.0;
   long long st_calls[QTT_K_COUNT] = {0};
   double st_secs[QTT_K_COUNT] = {0}, st_flops[QTT_K_COUNT] = {0}, st_bytes[QTT_K_COUNT] = {0};
   long long st_all_calls[QTT_K_COUNT] = {0};
   double st_all_flops[QTT_K_COUNT] = {0}, st_all_bytes[QTT_K_COUNT] = {0};
+  // contexts of the concurrent load-case groups (own stream and pool); a
+  // sub-context reads the parent's operators
+  const qtt_ctx* parent = nullptr;
+  std::vector<std::unique_ptr<qtt_ctx>> subs;
   ~qtt_ctx() {
+    for (auto& sc : subs) {
+      if (sc->stream) (void)hipStreamSynchronize(sc->stream);
+      if (sc->own_stream && sc->stream) (void)hipStreamDestroy(sc->stream);
+      sc->own_stream = false;
+    }
+    subs.clear();
     for (auto& r : pending) {
-      (void)hipEventDestroy(r.a);
-      (void)hipEventDestroy(r.b);
+      if (r.a) (void)hipEventDestroy(r.a);
+      if (r.b) (void)hipEventDestroy(r.b);
     }
     for (auto e : evfree) (void)hipEventDestroy(e);
+    if (span) {
+      if (stream) (void)hipStreamSynchronize(stream);
+      (void)hipFree(span);
+    }
   }
 };
 
@@ -212,7 +234,19 @@ struct Ctx {
     if (a == untimed()) return;
     hipEvent_t e = ev();
     check(hipEventRecord(e, c->stream), "event record");
-    c->pending.push_back({fam, a, e, flops, bytes});
+    c->pending.push_back({fam, a, e, flops, bytes, -1});
+  }
+  // a matrix-core launch timed by its own span (first workgroup start to
+  // last workgroup end on the real-time counter, written by the kernel):
+  // k0 hands out the span pair of a sampled launch (null between samples,
+  // slot -1) and returns whether statistics are on; k1 books the launch
+  bool k0(unsigned long long*& span, int& slot) const;
+  void k1(bool on, int slot, hipEvent_t a, hipEvent_t b, int fam, double flops, double bytes) const {
+    if (!on) return;
+    c->st_all_calls[fam] += 1;
+    c->st_all_flops[fam] += flops;
+    c->st_all_bytes[fam] += bytes;
+    if (slot >= 0 || a) c->pending.push_back({fam, a, b, flops, bytes, slot});
   }
   hipStream_t s() const { return c->stream; }
   BufP buf(size_t elems) const { return std::make_shared<Buf>(c->pool, std::max<size_t>(elems, 1) * sizeof(cplx)); }
@@ -224,8 +258,14 @@ struct Ctx {
 // bytes) must lie inside one live device allocation of this context.
 static void need(const Ctx& X, const void* base, long last, const char* what, size_t esz = sizeof(cplx)) {
   if (last < 0) return;
-  if (!X.c->pool->contains(base, (size_t)(last + 1) * esz))
-    throw std::logic_error(std::string("device operand out of bounds: ") + what);
+  const size_t bytes = (size_t)(last + 1) * esz;
+  if (X.c->pool->contains(base, bytes)) return;
+  // a sub-context also reads the parent's (idle, read-only) operators, and
+  // the parent reads its (idle) sub-contexts' results when it merges them
+  if (X.c->parent && X.c->parent->pool->contains(base, bytes)) return;
+  for (const auto& sc : X.c->subs)
+    if (sc->pool->contains(base, bytes)) return;
+  throw std::logic_error(std::string("device operand out of bounds: ") + what);
 }
 static long span2(long rows, long cols, long rs, long cs) {
   return (rows - 1) * rs + (cols - 1) * cs;
@@ -273,11 +313,26 @@ static void GB(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long l
   if (gemm_nbatch(g) > 65535) throw std::runtime_error("gemm: batch too large");
   // the statistics bracket the product kernel alone; the split-K sum of
   // slices (an elementwise pass) is counted with the other helpers
-  hipEvent_t e = X.t0();
+  int slot = -1;
+  const bool on = X.k0(g.span, slot);
   int ks_used = 1;
   const bool mc = gemm_mfma_main(g, X.s(), ks_used);
-  if (!mc) gemm_vector(g, X.s());
-  X.t1(e, mc ? (g.fp32 ? QTT_K_MFMA32 : QTT_K_MFMA) : QTT_K_GEMM, 8.0 * M * N * K * nb,
+  hipEvent_t ka = nullptr, kb = nullptr;
+  if (!mc) {
+    // the vector kernel (no span) between stream-position events; the
+    // span slot stays unused
+    if (slot >= 0) {
+      ka = X.ev();
+      check(hipEventRecord(ka, X.s()), "event record");
+    }
+    gemm_vector(g, X.s());
+    if (slot >= 0) {
+      kb = X.ev();
+      check(hipEventRecord(kb, X.s()), "event record");
+    }
+    slot = -1;
+  }
+  X.k1(on, slot, ka, kb, mc ? (g.fp32 ? QTT_K_MFMA32 : QTT_K_MFMA) : QTT_K_GEMM, 8.0 * M * N * K * nb,
        16.0 * ((double)M * K + (double)K * N + (beta.x != 0.0 || beta.y != 0.0 ? 2.0 : 1.0) * M * N) * nb);
   if (ks_used > 1) {
     hipEvent_t e2 = X.t0();
@@ -1338,12 +1393,13 @@ static TTP dC_op(const Ctx& X, const host::HTT& chi, int p, const double D[36]) 
 }
 
 static bool verbose() {
-  static int v = -1;
-  if (v < 0) {
+  // thread-safe static initialisation (load-case groups log from several
+  // host threads)
+  static const bool v = []() {
     const char* e = std::getenv("QTTHOM_VERBOSE");
-    v = (e && *e && *e != '0') ? 1 : 0;
-  }
-  return v == 1;
+    return e && *e && *e != '0';
+  }();
+  return v;
 }
 
 static double now_s() {
@@ -1506,19 +1562,59 @@ struct Prepared {
 };
 
 static void stats_collect(qtt_ctx* c) {
-  if (c->pending.empty()) return;
+  if (c->pending.empty() && c->span_used == 0) return;
   check(hipStreamSynchronize(c->stream), "stats sync");
+  std::vector<unsigned long long> sp;
+  if (c->span_used > 0) {
+    sp.resize(2 * (size_t)c->span_used);
+    check(hipMemcpyAsync(sp.data(), c->span, sp.size() * sizeof(unsigned long long),
+                         hipMemcpyDeviceToHost, c->stream),
+          "span copy");
+    check(hipStreamSynchronize(c->stream), "span copy sync");
+  }
   for (auto& r : c->pending) {
-    float ms = 0.f;
-    check(hipEventElapsedTime(&ms, r.a, r.b), "event elapsed");
+    double sec = 0.0;
+    if (r.slot >= 0) {
+      const unsigned long long t0 = sp[2 * (size_t)r.slot], t1 = sp[2 * (size_t)r.slot + 1];
+      if (t1 < t0) throw std::logic_error("stats: span slot not written by its launch");
+      sec = (double)(t1 - t0) / c->span_hz;
+    } else {
+      float ms = 0.f;
+      check(hipEventElapsedTime(&ms, r.a, r.b), "event elapsed");
+      sec = 1e-3 * ms;
+      c->evfree.push_back(r.a);
+      c->evfree.push_back(r.b);
+    }
     c->st_calls[r.fam] += 1;
-    c->st_secs[r.fam] += 1e-3 * ms;
+    c->st_secs[r.fam] += sec;
     c->st_flops[r.fam] += r.flops;
     c->st_bytes[r.fam] += r.bytes;
-    c->evfree.push_back(r.a);
-    c->evfree.push_back(r.b);
   }
   c->pending.clear();
+  if (c->span_used > 0) {
+    span_arm(c->span, c->span_used, c->stream);
+    c->span_used = 0;
+  }
+}
+
+bool Ctx::k0(unsigned long long*& span, int& slot) const {
+  span = nullptr;
+  slot = -1;
+  if (!c->stats_on) return false;
+  if (c->stats_tick++ % (unsigned long long)c->stats_stride != 0) return true;
+  if (!c->span) {
+    int khz = 0;
+    check(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device), "wall clock rate");
+    if (khz <= 0) throw std::runtime_error("stats: device reports no real-time counter rate");
+    c->span_hz = 1e3 * khz;
+    check(hipMalloc(&c->span, 2 * sizeof(unsigned long long) * qtt_ctx::SPAN_SLOTS), "span alloc");
+    span_arm(c->span, qtt_ctx::SPAN_SLOTS, c->stream);
+    c->span_used = 0;
+  }
+  if (c->span_used == qtt_ctx::SPAN_SLOTS) stats_collect(c);  // books and re-arms the slots
+  slot = c->span_used++;
+  span = c->span + 2 * (size_t)slot;
+  return true;
 }
 
 }  // namespace qtt
@@ -1825,6 +1921,112 @@ int tt_mean_apply(qtt_ctx* c, const qtt_tensor* A, const qtt_tensor* x, double* 
 
 }  // extern "C"
 
+// The load cases of one prepared problem are independent fixed points:
+// with ng > 1 they run as ng groups, each on a sub-context of its own
+// (stream and memory pool, default stream priority) driven by its own host
+// thread, so one group's latency-bound factorisations overlap another's
+// matrix-core products.  The operators stay in the parent context and are
+// only read.  Returns the merged result (strain train with the batch in
+// ks order, ranks padded with zeros to the largest per bond) and fills the
+// groups' C_eff columns.
+static SolveOut solve_groups(qtt_ctx* c, const Prepared& pr, const qtt_problem* P,
+                             const qtt_solve_opts* O, const std::vector<int>& ks, int ng,
+                             double* Ceff) {
+  check(hipStreamSynchronize(c->stream), "sync before groups");  // operators complete
+  while ((int)c->subs.size() < ng) {
+    auto sc = std::make_unique<qtt_ctx>();
+    sc->device = c->device;
+    check(hipStreamCreate(&sc->stream), "stream create");
+    sc->own_stream = true;
+    sc->pool = std::make_shared<Pool>();
+    sc->pool->device = c->device;
+    sc->parent = c;
+    c->subs.push_back(std::move(sc));
+  }
+  std::vector<std::vector<int>> groups(ng);
+  for (size_t i = 0; i < ks.size(); ++i) groups[i * ng / ks.size()].push_back(ks[i]);
+  std::vector<SolveOut> outs(ng);
+  std::vector<std::array<double, 36>> cg(ng);
+  std::vector<std::exception_ptr> errs(ng);
+  std::vector<std::thread> th;
+  for (int g = 0; g < ng; ++g) {
+    qtt_ctx* sc = c->subs[g].get();
+    sc->stats_on = c->stats_on;
+    sc->stats_stride = c->stats_stride;
+    sc->stats_tick = (unsigned long long)g;
+    sc->gemm_fp32 = false;
+    // the sketch seeds follow the parent's counter, one disjoint range per group
+    sc->sketch_counter = c->sketch_counter + ((uint64_t)g << 40);
+    th.emplace_back([&, g, sc]() {
+      try {
+        check(hipSetDevice(sc->device), "set device");
+        Ctx Xs{sc};
+        outs[g] = ls_loop(Xs, pr.ops, P, O, groups[g]);
+        cg[g].fill(0.0);
+        ceff_from(Xs, pr.ops, P, outs[g], cg[g].data());
+        Xs.sync();
+      } catch (...) {
+        errs[g] = std::current_exception();
+      }
+    });
+  }
+  for (auto& t : th) t.join();
+  c->sketch_counter += 1;
+  // statistics of the groups into the parent
+  for (int g = 0; g < ng; ++g) {
+    qtt_ctx* sc = c->subs[g].get();
+    stats_collect(sc);
+    for (int f = 0; f < QTT_K_COUNT; ++f) {
+      c->st_calls[f] += sc->st_calls[f];
+      c->st_secs[f] += sc->st_secs[f];
+      c->st_flops[f] += sc->st_flops[f];
+      c->st_bytes[f] += sc->st_bytes[f];
+      c->st_all_calls[f] += sc->st_all_calls[f];
+      c->st_all_flops[f] += sc->st_all_flops[f];
+      c->st_all_bytes[f] += sc->st_all_bytes[f];
+      sc->st_calls[f] = sc->st_all_calls[f] = 0;
+      sc->st_secs[f] = sc->st_flops[f] = sc->st_bytes[f] = sc->st_all_flops[f] = sc->st_all_bytes[f] = 0.0;
+    }
+  }
+  for (auto& e : errs)
+    if (e) std::rethrow_exception(e);
+  for (int g = 0; g < ng; ++g)
+    for (int k : groups[g])
+      for (int i = 0; i < 6; ++i) Ceff[i * 6 + k] = cg[g][i * 6 + k];
+  // merged report and strain train (parent pool and stream)
+  SolveOut so;
+  so.ks = ks;
+  for (int g = 0; g < ng; ++g) {
+    so.iters.insert(so.iters.end(), outs[g].iters.begin(), outs[g].iters.end());
+    so.res.insert(so.res.end(), outs[g].res.begin(), outs[g].res.end());
+    so.max_rank = std::max(so.max_rank, outs[g].max_rank);
+    so.disc = std::max(so.disc, outs[g].disc);
+    so.converged = so.converged && outs[g].converged;
+  }
+  Ctx X{c};
+  const TT& e0 = *outs[0].eps;
+  const int L = e0.L, B = (int)ks.size();
+  std::vector<int> r(L + 1, 1);
+  for (int k = 0; k <= L; ++k)
+    for (int g = 0; g < ng; ++g) r[k] = std::max(r[k], outs[g].eps->r[k]);
+  auto y = new_tt(X, L, B, e0.dout, r);
+  int boff = 0;
+  for (int g = 0; g < ng; ++g) {
+    const TT& eg = *outs[g].eps;
+    for (int k = 0; k < L; ++k) {
+      const int d = eg.dout[k], ra = eg.r[k], rb = eg.r[k + 1], Ra = r[k], Rb = r[k + 1];
+      cplx* dst = y->core[k] + (long)boff * Ra * d * Rb;
+      if (ra != Ra || rb != Rb) ck_fill(X, dst, (size_t)eg.B * Ra * d * Rb, C0(), X.s());
+      ck_copy2d(X, eg.B, ra * d, rb, MatView{eg.core[k], (long)rb, 1, (long)ra * d * rb, 0},
+                MatOut{dst, (long)Rb, 1, (long)Ra * d * Rb}, C1(), X.s());
+    }
+    boff += eg.B;
+  }
+  X.sync();  // the groups' buffers are released on return
+  so.eps = y;
+  return so;
+}
+
 static int solve_prepared(qtt_ctx* c, const Prepared& pr, const qtt_solve_opts* O, double* Ceff,
                           qtt_report* R, qtt_tensor** eps_out, double setup_seconds) {
   int status = QTT_OK;
@@ -1837,9 +2039,10 @@ static int solve_prepared(qtt_ctx* c, const Prepared& pr, const qtt_solve_opts* 
       if (P.load_mask & (1 << k)) ks.push_back(k);
     if (ks.empty()) throw std::invalid_argument("empty load mask");
     const double t1 = now_s();
-    SolveOut so = ls_loop(X, pr.ops, &P, O, ks);
     for (int i = 0; i < 36; ++i) Ceff[i] = 0.0;
-    ceff_from(X, pr.ops, &P, so, Ceff);
+    const int ng = std::max(1, std::min<int>(O->streams, (int)ks.size()));
+    SolveOut so = ng > 1 ? solve_groups(c, pr, &P, O, ks, ng, Ceff) : ls_loop(X, pr.ops, &P, O, ks);
+    if (ng == 1) ceff_from(X, pr.ops, &P, so, Ceff);
     X.sync();
     const double t2 = now_s();
     if (R) {

@@ -651,6 +651,20 @@ void conj_transpose(int batch, int rows, int keep, MatView in, MatOut out, hipSt
   copy2d(batch, keep, rows, t, out, make_double2(1.0, 0.0), s);
 }
 
+__global__ void k_span_arm(unsigned long long* t, int slots) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < slots) {
+    t[2 * i] = ~0ull;
+    t[2 * i + 1] = 0ull;
+  }
+}
+
+void span_arm(unsigned long long* t, int slots, hipStream_t s) {
+  if (slots <= 0) return;
+  hipLaunchKernelGGL(k_span_arm, dim3((slots + 255) / 256), dim3(256), 0, s, t, slots);
+  check(hipGetLastError(), "span arm launch");
+}
+
 __global__ void k_fill(cplx* p, size_t count, cplx v) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e < count) p[e] = v;

@@ -1543,13 +1543,15 @@ bool qr_two_col(int batch, int m, int n, MatView A, MatOut R, MatOut Q, hipStrea
 bool jacobi_square(int batch, int n, MatView A, MatOut U, double* S, hipStream_t s) {
   if (batch <= 0 || n <= 0) return true;
   if (n > JMAXN) return false;
-  static bool attr = false;
-  if (!attr) {
+  // once per kernel and process (thread-safe static initialisation: the
+  // load-case groups of a solve launch from several host threads)
+  static const bool attr = [&]() {
     check(hipFuncSetAttribute((const void*)k_jacobi_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                               JMAXN * JMAXN * (int)sizeof(cplx)),
           "jacobi lds attribute");
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   const size_t shm = (size_t)n * n * sizeof(cplx);
   hipLaunchKernelGGL(k_jacobi_lds, dim3(batch), dim3(JNT), shm, s, n, A, U, S);
   check(hipGetLastError(), "jacobi_lds launch");

@@ -34,6 +34,20 @@ constexpr int PAD = 2;
 constexpr int NTHR = 256;
 constexpr int PER_T = MT * KT / NTHR;  // staged elements per thread and operand (4)
 
+// span of a timed launch (GemmArgs::span, null otherwise): the earliest
+// workgroup start and the latest workgroup end on the device's
+// constant-rate real-time counter; the end is taken after the whole
+// workgroup has issued its stores
+__device__ __forceinline__ void span_begin(unsigned long long* t) {
+  if (t && threadIdx.x == 0) atomicMin(t, (unsigned long long)wall_clock64());
+}
+__device__ __forceinline__ void span_end(unsigned long long* t) {
+  if (t) {
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(t + 1, (unsigned long long)wall_clock64());
+  }
+}
+
 // FP64 kernel over a WM x WN grid of waves, each wave BM x BN MFMA blocks
 // of 16 x 16 (tile variants and their choice: plan_fp64 below).
 template <int WM, int WN, int BM, int BN, bool G3>
@@ -42,6 +56,7 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_zgemm_mfma(GemmArgs g, int 
   constexpr int PER_TA = MT * KT / NTHR, PER_TB = NT * KT / NTHR;
   __shared__ double Ar[KT][MT + PAD], Ai[KT][MT + PAD];
   __shared__ double Br[KT][NT + PAD], Bi[KT][NT + PAD];
+  span_begin(g.span);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w / WN, wn = w % WN;   // wave position in the grid
   const int m0 = blockIdx.y * MT, n0 = blockIdx.x * NT;
@@ -189,6 +204,7 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_zgemm_mfma(GemmArgs g, int 
           const int n = n0 + wn * 16 * BN + j * 16 + (lane & 15);
           if (m < g.M && n < g.N) P[(long)m * g.N + n] = make_double2(cr[i][j][r], ci[i][j][r]);
         }
+    span_end(g.span);
     return;
   }
   cplx* C = g.C + oc;
@@ -212,6 +228,7 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_zgemm_mfma(GemmArgs g, int 
         }
         *cp = out;
       }
+  span_end(g.span);
 }
 
 // The same tiling with FP32 operands and FP32 accumulation on
@@ -221,6 +238,7 @@ __global__ __launch_bounds__(64 * WM * WN, 2) void k_zgemm_mfma(GemmArgs g, int 
 __global__ __launch_bounds__(NTHR) void k_zgemm_mfma32(GemmArgs g, int ksplit, int kchunk) {
   __shared__ float Ar[KT][MT + 4], Ai[KT][MT + 4];
   __shared__ float Br[KT][NT + 4], Bi[KT][NT + 4];
+  span_begin(g.span);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w >> 1, wn = w & 1;
   const int m0 = blockIdx.y * MT, n0 = blockIdx.x * NT;
@@ -340,6 +358,7 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma32(GemmArgs g, int ksplit, i
           const int n = n0 + wn * 32 + j * 16 + (lane & 15);
           if (m < g.M && n < g.N) P[(long)m * g.N + n] = make_double2(cr[i][j][r], ci[i][j][r]);
         }
+    span_end(g.span);
     return;
   }
   cplx* C = g.C + oc;
@@ -363,6 +382,7 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma32(GemmArgs g, int ksplit, i
         }
         *cp = out;
       }
+  span_end(g.span);
 }
 
 // C = alpha * sum_s ws[s] + beta * C, slices added in order s = 0, 1, ...

@@ -535,13 +535,15 @@ bool try_qr_formq(int batch, int m, int n, const MatOut& Q, cplx* ws, hipStream_
   constexpr int MR = RB * 4 * RPL;
   if (m > MR || n > 16 * CG) return false;
   const size_t shm = (size_t)(MR * VST + RB * CG * 256) * sizeof(cplx);
-  static bool attr = false;
-  if (!attr) {
+  // once per kernel and process (thread-safe static initialisation: the
+  // load-case groups of a solve launch from several host threads)
+  static const bool attr = [&]() {
     check(hipFuncSetAttribute((const void*)k_qr_formq<RB, RPL, CG>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm),
           "qr_formq lds attribute");
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   hipLaunchKernelGGL((k_qr_formq<RB, RPL, CG>), dim3(batch), dim3(RB * CG * 64), shm, s, m, n, Q, ws,
                      (long)qr_ws_per_matrix(m, n));
   check(hipGetLastError(), "qr_formq launch");
@@ -565,13 +567,15 @@ bool try_qr_blk(int batch, int m, int n, const MatView& A, const MatOut& R, cons
   const long wsz = (long)qr_ws_per_matrix(m, n);
   if (np * (16L * m + 256 + 16) > wsz) return false;
   const size_t shm = (size_t)(MR * VST + RB * CG * 256) * sizeof(cplx);
-  static bool attr = false;
-  if (!attr) {
+  // once per kernel and process (thread-safe static initialisation: the
+  // load-case groups of a solve launch from several host threads)
+  static const bool attr = [&]() {
     check(hipFuncSetAttribute((const void*)k_qr_blk<RB, RPL, CG>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm),
           "qr_blk lds attribute");
-    attr = true;
-  }
+    return true;
+  }();
+  (void)attr;
   hipLaunchKernelGGL((k_qr_blk<RB, RPL, CG>), dim3(batch), dim3(RB * CG * 64), shm, s, m, n, A, R, Q,
                      ws, wsz);
   check(hipGetLastError(), "qr_blk launch");

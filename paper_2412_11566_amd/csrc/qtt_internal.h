@@ -50,6 +50,11 @@ struct GemmArgs {
   // matrix-core FP64 tile variant forced (0 .. gemm_num_tiles() - 1), or -1:
   // chosen per shape
   int tile = -1;
+  // matrix-core path only: when set, the product kernel records its span
+  // (earliest workgroup start into span[0] by atomic min, latest workgroup
+  // end into span[1] by atomic max, device real-time counter ticks); the
+  // caller arms the pair as {~0, 0} (span_arm)
+  unsigned long long* span = nullptr;
 };
 __host__ __device__ inline long gemm_nbatch(const GemmArgs& g) { return (long)g.nb1 * g.nb2 * g.nb3; }
 __host__ __device__ inline void gemm_batch_offsets(const GemmArgs& g, long z, long& oa, long& ob, long& oc) {
@@ -193,6 +198,9 @@ void conj_transpose(int batch, int rows, int keep, MatView in, MatOut out,
 // times bscale[b] per batch element when bscale (device) is given.
 void copy2d(int batch, int rows, int cols, MatView in, MatOut out,
             cplx alpha, hipStream_t s, const double* bscale = nullptr);
+
+// Arm `slots` span pairs for timed launches: t[2i] = ~0, t[2i+1] = 0.
+void span_arm(unsigned long long* t, int slots, hipStream_t s);
 
 // Fill count complex entries with value v.
 void fill(cplx* p, size_t count, cplx v, hipStream_t s);

@@ -79,3 +79,63 @@ def test_c0_fp32_contractions(ctx):
     Cref, _ = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=1e-12)
     assert rep.status == 0
     assert rel(C, Cref) < 1e-5
+
+
+def test_concurrent_load_case_groups(ctx):
+    """Load cases solved as 3 concurrent groups (own streams and pools):
+    C_eff, the merged strain train (zero-padded ranks) and the adjoint
+    gradient built on it agree with the one-stream solve."""
+    p = M.config_c0()
+    prep = q.prepare(ctx, p.phase, p.lame, p.lame0, 1e-8)
+    res = {}
+    for ns in (1, 3):
+        opts = q.SolveOptions(delta=1e-8, tol=1e-9, cap=128, max_iter=300, streams=ns, seed=3)
+        C, rep, eps = q.ls_solve_prepared(ctx, prep, opts, keep_eps=True)
+        assert rep.status == 0 and all(it > 0 for it in rep.iterations)
+        g, arep = q.ls_adjoint_prepared(ctx, prep, q.SolveOptions(delta=1e-8, tol=1e-9, cap=128,
+                                                                   max_iter=300, seed=4),
+                                        eps, gbar=np.ones((6, 6)))
+        res[ns] = (C, np.asarray(g))
+    Cref, _ = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=1e-12)
+    assert rel(res[3][0], Cref) < 1e-5
+    assert rel(res[3][0], res[1][0]) < 1e-6
+    assert np.abs(res[3][1] - res[1][1]).max() < 1e-5 * np.abs(res[1][1]).max()
+
+
+def test_kernel_statistics(ctx):
+    """Sampled kernel statistics of a solve: every launch is counted, every
+    s-th is timed (the matrix-core GEMM by its own real-time-counter span,
+    also when the load cases run as concurrent groups), the durations are
+    positive and below the solve's wall time, and reset clears them."""
+    import time
+    p = M.config_c0()
+    prep = q.prepare(ctx, p.phase, p.lame, p.lame0, 1e-8)
+    nfam = len(q._c.KERNEL_FAMILIES)
+    mfma = q._c.QTT_K_MFMA
+    for ns, stride in ((1, 1), (3, 4)):
+        opts = q.SolveOptions(delta=1e-8, tol=1e-9, cap=128, max_iter=20, streams=ns, seed=3)
+        q.stats_enable(ctx, stride)
+        q.stats_reset(ctx)
+        t = time.perf_counter()
+        q.ls_solve_prepared(ctx, prep, opts)
+        wall = time.perf_counter() - t
+        timed = [q.stats_get(ctx, f) for f in range(nfam)]
+        every = [q.stats_get_all(ctx, f) for f in range(nfam)]
+        q.stats_enable(ctx, False)
+        total_all = sum(a["launches"] for a in every)
+        total_timed = sum(s["launches"] for s in timed)
+        assert every[mfma]["launches"] > 0 and timed[mfma]["launches"] > 0
+        assert timed[mfma]["seconds"] > 0.0
+        if stride == 1:
+            assert total_timed == total_all
+        else:
+            # one sampling counter per group, each starting at its group index
+            assert abs(total_timed - total_all / stride) <= ns + 2
+        for s, a in zip(timed, every):
+            if s["launches"]:
+                avg = s["seconds"] / s["launches"]
+                assert 0.0 <= avg < wall, (s["family"], avg, wall)
+                assert s["flops"] <= a["flops"] * (1 + 1e-12)
+        q.stats_reset(ctx)
+        assert q.stats_get(ctx, mfma)["launches"] == 0
+        assert q.stats_get_all(ctx, mfma)["launches"] == 0
