@@ -88,7 +88,10 @@ typedef struct qtt_solve_opts {
     int exact;               /* nonzero: sketch at full structural rank    */
     uint64_t seed;           /* seed of the sketching random numbers       */
     int streams;             /* load-case groups solved concurrently, each
-                                on a stream of its own (<= 1: one stream) */
+                                on a stream of its own (<= 1: one stream);
+                                in ls_adjoint also the number of groups of
+                                the adjoint fixed point and of the gradient
+                                terms; ls_batch_solve ignores it          */
 } qtt_solve_opts;
 
 typedef struct qtt_report {

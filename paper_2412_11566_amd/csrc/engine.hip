@@ -1921,18 +1921,17 @@ int tt_mean_apply(qtt_ctx* c, const qtt_tensor* A, const qtt_tensor* x, double* 
 
 }  // extern "C"
 
-// The load cases of one prepared problem are independent fixed points:
-// with ng > 1 they run as ng groups, each on a sub-context of its own
-// (stream and memory pool, default stream priority) driven by its own host
-// thread, so one group's latency-bound factorisations overlap another's
-// matrix-core products.  The operators stay in the parent context and are
-// only read.  Returns the merged result (strain train with the batch in
-// ks order, ranks padded with zeros to the largest per bond) and fills the
-// groups' C_eff columns.
-static SolveOut solve_groups(qtt_ctx* c, const Prepared& pr, const qtt_problem* P,
-                             const qtt_solve_opts* O, const std::vector<int>& ks, int ng,
-                             double* Ceff) {
-  check(hipStreamSynchronize(c->stream), "sync before groups");  // operators complete
+// Runs fn(X_g, g) for g < ng concurrently, each on a sub-context with its
+// own stream (default priority) and pool driven from its own host thread,
+// so one group's latency-bound factorisations overlap another's
+// matrix-core products.  The sub-contexts
+// read the parent's buffers (operators, trains), which stay unwritten while
+// the groups run, and draw sketches from disjoint counter ranges.  Kernel
+// statistics are merged into the parent; the first group error is
+// rethrown after every group has finished.
+template <class Fn>
+static void run_groups(qtt_ctx* c, int ng, Fn&& fn) {
+  check(hipStreamSynchronize(c->stream), "sync before groups");  // parent work complete
   while ((int)c->subs.size() < ng) {
     auto sc = std::make_unique<qtt_ctx>();
     sc->device = c->device;
@@ -1943,10 +1942,6 @@ static SolveOut solve_groups(qtt_ctx* c, const Prepared& pr, const qtt_problem* 
     sc->parent = c;
     c->subs.push_back(std::move(sc));
   }
-  std::vector<std::vector<int>> groups(ng);
-  for (size_t i = 0; i < ks.size(); ++i) groups[i * ng / ks.size()].push_back(ks[i]);
-  std::vector<SolveOut> outs(ng);
-  std::vector<std::array<double, 36>> cg(ng);
   std::vector<std::exception_ptr> errs(ng);
   std::vector<std::thread> th;
   for (int g = 0; g < ng; ++g) {
@@ -1954,16 +1949,14 @@ static SolveOut solve_groups(qtt_ctx* c, const Prepared& pr, const qtt_problem* 
     sc->stats_on = c->stats_on;
     sc->stats_stride = c->stats_stride;
     sc->stats_tick = (unsigned long long)g;
-    sc->gemm_fp32 = false;
+    sc->gemm_fp32 = false;  // set per contraction by the precision scopes
     // the sketch seeds follow the parent's counter, one disjoint range per group
-    sc->sketch_counter = c->sketch_counter + ((uint64_t)g << 40);
+    sc->sketch_counter = c->sketch_counter + ((uint64_t)(g + 1) << 40);
     th.emplace_back([&, g, sc]() {
       try {
         check(hipSetDevice(sc->device), "set device");
         Ctx Xs{sc};
-        outs[g] = ls_loop(Xs, pr.ops, P, O, groups[g]);
-        cg[g].fill(0.0);
-        ceff_from(Xs, pr.ops, P, outs[g], cg[g].data());
+        fn(Xs, g);
         Xs.sync();
       } catch (...) {
         errs[g] = std::current_exception();
@@ -1972,7 +1965,6 @@ static SolveOut solve_groups(qtt_ctx* c, const Prepared& pr, const qtt_problem* 
   }
   for (auto& t : th) t.join();
   c->sketch_counter += 1;
-  // statistics of the groups into the parent
   for (int g = 0; g < ng; ++g) {
     qtt_ctx* sc = c->subs[g].get();
     stats_collect(sc);
@@ -1990,29 +1982,23 @@ static SolveOut solve_groups(qtt_ctx* c, const Prepared& pr, const qtt_problem* 
   }
   for (auto& e : errs)
     if (e) std::rethrow_exception(e);
-  for (int g = 0; g < ng; ++g)
-    for (int k : groups[g])
-      for (int i = 0; i < 6; ++i) Ceff[i * 6 + k] = cg[g][i * 6 + k];
-  // merged report and strain train (parent pool and stream)
-  SolveOut so;
-  so.ks = ks;
-  for (int g = 0; g < ng; ++g) {
-    so.iters.insert(so.iters.end(), outs[g].iters.begin(), outs[g].iters.end());
-    so.res.insert(so.res.end(), outs[g].res.begin(), outs[g].res.end());
-    so.max_rank = std::max(so.max_rank, outs[g].max_rank);
-    so.disc = std::max(so.disc, outs[g].disc);
-    so.converged = so.converged && outs[g].converged;
-  }
-  Ctx X{c};
-  const TT& e0 = *outs[0].eps;
-  const int L = e0.L, B = (int)ks.size();
+}
+
+// The batch elements of several trains of one shape stacked into one train
+// (parent pool and stream), ranks zero-padded to the largest per bond.
+static TTP stack_trains(const Ctx& X, const std::vector<TTP>& parts) {
+  const TT& e0 = *parts[0];
+  const int L = e0.L;
+  int B = 0;
   std::vector<int> r(L + 1, 1);
-  for (int k = 0; k <= L; ++k)
-    for (int g = 0; g < ng; ++g) r[k] = std::max(r[k], outs[g].eps->r[k]);
+  for (const auto& t : parts) {
+    B += t->B;
+    for (int k = 0; k <= L; ++k) r[k] = std::max(r[k], t->r[k]);
+  }
   auto y = new_tt(X, L, B, e0.dout, r);
   int boff = 0;
-  for (int g = 0; g < ng; ++g) {
-    const TT& eg = *outs[g].eps;
+  for (const auto& tp : parts) {
+    const TT& eg = *tp;
     for (int k = 0; k < L; ++k) {
       const int d = eg.dout[k], ra = eg.r[k], rb = eg.r[k + 1], Ra = r[k], Rb = r[k + 1];
       cplx* dst = y->core[k] + (long)boff * Ra * d * Rb;
@@ -2022,8 +2008,40 @@ static SolveOut solve_groups(qtt_ctx* c, const Prepared& pr, const qtt_problem* 
     }
     boff += eg.B;
   }
-  X.sync();  // the groups' buffers are released on return
-  so.eps = y;
+  X.sync();  // the parts' buffers may be released on return
+  return y;
+}
+
+// The load cases ks split into ng groups solved concurrently (run_groups);
+// C_eff columns are written per group, the reports and strain trains merged
+// in the order of ks.
+static SolveOut solve_groups(qtt_ctx* c, const Prepared& pr, const qtt_problem* P,
+                             const qtt_solve_opts* O, const std::vector<int>& ks, int ng,
+                             double* Ceff) {
+  std::vector<std::vector<int>> groups(ng);
+  for (size_t i = 0; i < ks.size(); ++i) groups[i * ng / ks.size()].push_back(ks[i]);
+  std::vector<SolveOut> outs(ng);
+  std::vector<std::array<double, 36>> cg(ng);
+  run_groups(c, ng, [&](const Ctx& Xs, int g) {
+    outs[g] = ls_loop(Xs, pr.ops, P, O, groups[g]);
+    cg[g].fill(0.0);
+    ceff_from(Xs, pr.ops, P, outs[g], cg[g].data());
+  });
+  for (int g = 0; g < ng; ++g)
+    for (int k : groups[g])
+      for (int i = 0; i < 6; ++i) Ceff[i * 6 + k] = cg[g][i * 6 + k];
+  SolveOut so;
+  so.ks = ks;
+  std::vector<TTP> parts;
+  for (int g = 0; g < ng; ++g) {
+    so.iters.insert(so.iters.end(), outs[g].iters.begin(), outs[g].iters.end());
+    so.res.insert(so.res.end(), outs[g].res.begin(), outs[g].res.end());
+    so.max_rank = std::max(so.max_rank, outs[g].max_rank);
+    so.disc = std::max(so.disc, outs[g].disc);
+    so.converged = so.converged && outs[g].converged;
+    parts.push_back(outs[g].eps);
+  }
+  so.eps = stack_trains(Ctx{c}, parts);
   return so;
 }
 
@@ -2255,6 +2273,77 @@ int qtt_stats_reset(qtt_ctx* c) {
 
 extern "C" {
 
+// The adjoint fixed point for the load cases ks (train batch in ks order):
+// w = C e_k - (C - C0) : G[w] with G = S^H Gamma S, from w = C e_k, stopped
+// per case when ||w_{m+1} - w_m|| / ||C e_k|| < tol.
+struct AdjOut {
+  TTP w;
+  std::vector<int> it;
+  std::vector<double> res;
+  bool conv = true;
+};
+
+static AdjOut adj_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, const qtt_solve_opts* O,
+                       const std::vector<int>& ks) {
+  const int n = P->n, B = (int)ks.size();
+  // C e_k trains: (C - C0) : E + C0 E
+  std::vector<double> E((size_t)B * 6, 0.0), C0E((size_t)B * 6, 0.0);
+  double C0m[36];
+  host::iso_voigt(P->lame0[0], P->lame0[1], C0m);
+  for (int b = 0; b < B; ++b) {
+    E[(size_t)b * 6 + ks[b]] = 1.0;
+    for (int i = 0; i < 6; ++i) C0E[(size_t)b * 6 + i] = C0m[i * 6 + ks[b]];
+  }
+  auto Et = const_strain(X, n, B, E.data());
+  auto C0t = const_strain(X, n, B, C0E.data());
+  SketchOpts so = sk(X, O);
+  so.exact = true;  // rank of (C - C0) E is the stiffness rank: exact
+  auto dE = op_apply(X, *ops.Cd, *Et, 0, so, nullptr);
+  auto Ce = axpby(X, 1.0, *dE, 1.0, *C0t);
+  round_tt(X, *Ce, O->delta, O->cap, nullptr);
+  std::vector<double> nCe = tt_norms(X, *Ce);
+  AdjOut out;
+  auto w = Ce;
+  out.it.assign(B, 0);
+  out.res.assign(B, 0.0);
+  std::vector<char> done(B, 0);
+  int m = 0;
+  while (true) {
+    auto u = op_apply(X, *ops.S, *w, 0, ski(X, O), nullptr);
+    u = op_apply(X, *ops.G, *u, 0, ski(X, O), nullptr);
+    u = op_apply(X, *ops.S->adj, *u, 0, ski(X, O), nullptr);
+    u = op_apply(X, *ops.Cd, *u, 0, ski(X, O), nullptr);
+    auto nw = round_any(X, axpby(X, 1.0, *Ce, -1.0, *u), sk(X, O), nullptr);
+    auto d = axpby(X, 1.0, *nw, -1.0, *w);
+    auto dn = tt_norms(X, *d);
+    w = nw;
+    ++m;
+    bool all = true;
+    for (int b = 0; b < B; ++b) {
+      const double r = dn[b] / std::max(nCe[b], 1e-300);
+      if (!std::isfinite(r)) throw std::runtime_error("NaN in adjoint residual");
+      if (!done[b]) {
+        out.it[b] = m;
+        out.res[b] = r;
+        if (r < O->tol) done[b] = 1;
+      }
+      all = all && done[b];
+    }
+    if (verbose()) {
+      std::fprintf(stderr, "[qtthom] adjoint it %d res", m);
+      for (int b = 0; b < B; ++b) std::fprintf(stderr, " %.3e", out.res[b]);
+      std::fprintf(stderr, "\n");
+    }
+    if (all) break;
+    if (m >= O->max_iter) {
+      out.conv = false;
+      break;
+    }
+  }
+  out.w = w;
+  return out;
+}
+
 // Adjoint fixed point and gradient on built operators (see ls_adjoint).
 static int adjoint_ops(qtt_ctx* c, const Ops& ops, const qtt_problem* P, const qtt_solve_opts* O,
                        const qtt_tensor* eps, const double* gbar, double* grad, qtt_report* R,
@@ -2267,78 +2356,60 @@ static int adjoint_ops(qtt_ctx* c, const Ops& ops, const qtt_problem* P, const q
     const int n = P->n, np = P->nphase;
     if (eps->L != 3 * n + 1) throw std::invalid_argument("eps does not match the problem size");
     const double NN = std::pow(2.0, 3.0 * n);
-    // C e_k trains: (C - C0) : E + C0 E
-    std::vector<double> E(36, 0.0), C0E(36, 0.0);
-    double C0m[36];
-    host::iso_voigt(P->lame0[0], P->lame0[1], C0m);
-    for (int k = 0; k < 6; ++k) {
-      E[k * 6 + k] = 1.0;
-      for (int i = 0; i < 6; ++i) C0E[k * 6 + i] = C0m[i * 6 + k];
-    }
-    auto Et = const_strain(X, n, 6, E.data());
-    auto C0t = const_strain(X, n, 6, C0E.data());
-    SketchOpts so = sk(X, O);
-    so.exact = true;  // rank of (C - C0) E is the stiffness rank: exact
-    auto dE = op_apply(X, *ops.Cd, *Et, 0, so, nullptr);
-    auto Ce = axpby(X, 1.0, *dE, 1.0, *C0t);
-    round_tt(X, *Ce, O->delta, O->cap, nullptr);
-    std::vector<double> nCe = tt_norms(X, *Ce);
-    // adjoint fixed point w = C e_k - (C - C0) : G[w],  G = S^H Gamma S
-    auto w = Ce;
-    std::vector<int> it(6, 0);
-    std::vector<double> res(6, 0.0);
-    std::vector<char> done(6, 0);
-    int m = 0;
-    bool conv = true;
-    while (true) {
-      auto u = op_apply(X, *ops.S, *w, 0, ski(X, O), nullptr);
-      u = op_apply(X, *ops.G, *u, 0, ski(X, O), nullptr);
-      u = op_apply(X, *ops.S->adj, *u, 0, ski(X, O), nullptr);
-      u = op_apply(X, *ops.Cd, *u, 0, ski(X, O), nullptr);
-      auto nw = round_any(X, axpby(X, 1.0, *Ce, -1.0, *u), sk(X, O), nullptr);
-      auto d = axpby(X, 1.0, *nw, -1.0, *w);
-      auto dn = tt_norms(X, *d);
-      w = nw;
-      ++m;
-      bool all = true;
-      for (int b = 0; b < 6; ++b) {
-        const double r = dn[b] / std::max(nCe[b], 1e-300);
-        if (!std::isfinite(r)) throw std::runtime_error("NaN in adjoint residual");
-        if (!done[b]) {
-          it[b] = m;
-          res[b] = r;
-          if (r < O->tol) done[b] = 1;
-        }
-        all = all && done[b];
+    const std::vector<int> all_ks = {0, 1, 2, 3, 4, 5};
+    const int ng = std::max(1, std::min<int>(O->streams, 6));
+    AdjOut ao;
+    if (ng == 1) {
+      ao = adj_loop(X, ops, P, O, all_ks);
+    } else {
+      std::vector<std::vector<int>> groups(ng);
+      for (int i = 0; i < 6; ++i) groups[i * ng / 6].push_back(i);
+      std::vector<AdjOut> outs(ng);
+      run_groups(c, ng, [&](const Ctx& Xs, int g) { outs[g] = adj_loop(Xs, ops, P, O, groups[g]); });
+      std::vector<TTP> parts;
+      ao.conv = true;
+      for (int g = 0; g < ng; ++g) {
+        ao.it.insert(ao.it.end(), outs[g].it.begin(), outs[g].it.end());
+        ao.res.insert(ao.res.end(), outs[g].res.begin(), outs[g].res.end());
+        ao.conv = ao.conv && outs[g].conv;
+        parts.push_back(outs[g].w);
       }
-      if (verbose()) {
-        std::fprintf(stderr, "[qtthom] adjoint it %d res", m);
-        for (int b = 0; b < 6; ++b) std::fprintf(stderr, " %.3e", res[b]);
-        std::fprintf(stderr, "\n");
-      }
-      if (all) break;
-      if (m >= O->max_iter) { conv = false; break; }
+      ao.w = stack_trains(X, parts);
     }
+    const auto& w = ao.w;
+    const auto& it = ao.it;
+    const auto& res = ao.res;
+    const bool conv = ao.conv;
     // gradient: dC_kl/dtheta = <e_k . dC eps^l> - <w_k, G[dC eps^l]>
     const int nt = 2 * np;
     std::vector<double> J((size_t)36 * nt, 0.0);
     double Dl[36], Dm[36];
     host::iso_voigt(1.0, 0.0, Dl);
     host::iso_voigt(0.0, 1.0, Dm);
-    for (int p = 0; p < np; ++p)
-      for (int t = 0; t < 2; ++t) {
-        auto dC = dC_op(X, ops.chi, p, t == 0 ? Dl : Dm);
-        auto v = op_apply(X, *dC, *eps, 0, sk(X, O), nullptr);   // dC : eps^l
-        auto first = mean_apply(X, *ops.I, *v);                 // <e_k . dC eps^l>
-        auto gv = op_apply(X, *ops.S, *v, 0, ski(X, O), nullptr);
-        gv = op_apply(X, *ops.G, *gv, 0, ski(X, O), nullptr);
-        gv = op_apply(X, *ops.S->adj, *gv, 0, sk(X, O), nullptr);
-        auto gram = tt_gram(X, *w, *gv);                        // [k][l] sum conj(w_k) Gv_l
-        for (int k = 0; k < 6; ++k)
-          for (int l = 0; l < 6; ++l)
-            J[((size_t)k * 6 + l) * nt + 2 * p + t] =
-                first[(size_t)l * 6 + k].real() - gram[(size_t)k * 6 + l].real() / NN;
-      }
+    // one (phase, modulus) derivative per task; with ng > 1 the tasks run
+    // on the load-case groups' sub-contexts (w and eps are only read)
+    auto grad_task = [&](const Ctx& Xg, int task) {
+      const int p = task / 2, t = task % 2;
+      auto dC = dC_op(Xg, ops.chi, p, t == 0 ? Dl : Dm);
+      auto v = op_apply(Xg, *dC, *eps, 0, sk(Xg, O), nullptr);   // dC : eps^l
+      auto first = mean_apply(Xg, *ops.I, *v);                  // <e_k . dC eps^l>
+      auto gv = op_apply(Xg, *ops.S, *v, 0, ski(Xg, O), nullptr);
+      gv = op_apply(Xg, *ops.G, *gv, 0, ski(Xg, O), nullptr);
+      gv = op_apply(Xg, *ops.S->adj, *gv, 0, sk(Xg, O), nullptr);
+      auto gram = tt_gram(Xg, *w, *gv);                         // [k][l] sum conj(w_k) Gv_l
+      for (int k = 0; k < 6; ++k)
+        for (int l = 0; l < 6; ++l)
+          J[((size_t)k * 6 + l) * nt + task] =
+              first[(size_t)l * 6 + k].real() - gram[(size_t)k * 6 + l].real() / NN;
+    };
+    if (ng == 1) {
+      for (int task = 0; task < nt; ++task) grad_task(X, task);
+    } else {
+      const int ngr = std::min(ng, nt);
+      run_groups(c, ngr, [&](const Ctx& Xs, int g) {
+        for (int task = g; task < nt; task += ngr) grad_task(Xs, task);
+      });
+    }
     if (gbar) {
       for (int t = 0; t < nt; ++t) {
         double s = 0.0;

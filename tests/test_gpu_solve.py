@@ -82,9 +82,10 @@ def test_c0_fp32_contractions(ctx):
 
 
 def test_concurrent_load_case_groups(ctx):
-    """Load cases solved as 3 concurrent groups (own streams and pools):
-    C_eff, the merged strain train (zero-padded ranks) and the adjoint
-    gradient built on it agree with the one-stream solve."""
+    """Load cases solved as 3 concurrent groups (own streams and pools),
+    forward and adjoint: C_eff, the merged strain train (zero-padded ranks),
+    the merged adjoint train and the gradient agree with the one-stream
+    solve."""
     p = M.config_c0()
     prep = q.prepare(ctx, p.phase, p.lame, p.lame0, 1e-8)
     res = {}
@@ -93,8 +94,10 @@ def test_concurrent_load_case_groups(ctx):
         C, rep, eps = q.ls_solve_prepared(ctx, prep, opts, keep_eps=True)
         assert rep.status == 0 and all(it > 0 for it in rep.iterations)
         g, arep = q.ls_adjoint_prepared(ctx, prep, q.SolveOptions(delta=1e-8, tol=1e-9, cap=128,
-                                                                   max_iter=300, seed=4),
+                                                                   max_iter=300, seed=4,
+                                                                   streams=ns),
                                         eps, gbar=np.ones((6, 6)))
+        assert arep.status == 0 and all(it > 0 for it in arep.iterations)
         res[ns] = (C, np.asarray(g))
     Cref, _ = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=1e-12)
     assert rel(res[3][0], Cref) < 1e-5
