@@ -75,12 +75,9 @@ def tto_apply_bandwidth(q, ctx, n, reps=3):
     """Materialised SFFT x train (ranks multiply) on a synthetic complex
     train: seed 1, L = 3n + 1, every spatial bond min(64, structural),
     SFFT built at delta 1e-10.  Bytes = sum_k |A_k| + |x_k| + |Z_k| (x16)."""
-    rng = np.random.default_rng(1)
-    dims = [6] + [2] * (3 * n)
-    L = len(dims)
-    ranks = [1] + [min(64, int(np.prod(dims[:k])), int(np.prod(dims[k:]))) for k in range(1, L)] + [1]
-    cores = [(rng.standard_normal((1, ranks[k], d, ranks[k + 1]))
-              + 1j * rng.standard_normal((1, ranks[k], d, ranks[k + 1]))) for k, d in enumerate(dims)]
+    import microstructures as M
+    cores = M.synthetic_train(n, 64, seed=1)
+    ranks = [cores[0].shape[1]] + [c.shape[3] for c in cores]
     S = q.sfft_build(ctx, n, 1e-10)
     x = q.tt_from_cores(ctx, cores)
     y = q.sfft_apply(ctx, S, x, flags=q.QTT_NO_ROUND)   # warm-up

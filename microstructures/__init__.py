@@ -32,6 +32,7 @@ __all__ = [
     "sphere", "laminate", "fibres", "spheres", "random_spheres",
     "config_c0", "config_c1_laminate", "config_c1_sphere", "config_c2",
     "config_c3", "config_c3_structure", "config_c4", "homogeneous",
+    "synthetic_train",
 ]
 
 
@@ -261,3 +262,17 @@ def config_c4(n: int = 10, seed: int = 0) -> Problem:
     return Problem(f"c4_spheres{1 << n}", n, spheres(1 << n, cs, rs),
                    [(1.0, 0.3), (10.0, 0.3)], cap=128, delta=1e-6, tol=1e-4,
                    meta={"centres": cs, "radii": rs})
+
+
+def synthetic_train(n: int, rank: int = 64, seed: int = 1) -> list:
+    """Seeded random complex strain train on the 2^n grid: Voigt core of
+    dimension 6, then 3n binary cores, every bond min(rank, structural),
+    entries standard normal in real and imaginary parts.  Cores have shape
+    (1, r_{k-1}, d_k, r_k) (a batch of one train); the TTO-apply
+    measurement and the full-size checks draw the same train."""
+    rng = np.random.default_rng(seed)
+    dims = [6] + [2] * (3 * n)
+    L = len(dims)
+    ranks = [1] + [min(rank, int(np.prod(dims[:k])), int(np.prod(dims[k:]))) for k in range(1, L)] + [1]
+    return [(rng.standard_normal((1, ranks[k], d, ranks[k + 1]))
+             + 1j * rng.standard_normal((1, ranks[k], d, ranks[k + 1]))) for k, d in enumerate(dims)]

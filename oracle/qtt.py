@@ -202,6 +202,33 @@ def bitrev(k: np.ndarray, n: int) -> np.ndarray:
     return out
 
 
+def tt_entry(cores, idx) -> complex:
+    """One entry x[i_1, ..., i_L] of a TT with cores (r_{k-1}, d_k, r_k):
+    the product of the core slices at the indices (Sec. 3, eq. tt_format)."""
+    v = np.ones(1, dtype=np.complex128)
+    for c, i in zip(cores, idx):
+        v = v @ c[:, int(i), :]
+    return complex(v[0])
+
+
+def sfft_entry(cores, n: int, v: int, k) -> complex:
+    """Entry (v, k_x, k_y, k_z) of the SFFT applied to a controlled QTT
+    strain train (Voigt core, then n bits per axis, most significant first),
+    from the plain definition of the reduced QFT on each axis (Sec. 4.1):
+    (S x)[v, k] = N^(-3/2) sum_j x[v, j] exp(+2 pi i j . rev_n(k) / N).
+    The phase factorises over the bits of j, so each bit core is summed
+    over its two values with that bit's phase; no dense field is formed."""
+    N = 1 << n
+    vec = np.asarray(cores[0])[0, int(v), :].astype(np.complex128)
+    for a in range(3):
+        m = int(bitrev(np.array([int(k[a])]), n)[0])
+        for t in range(n):
+            c = np.asarray(cores[1 + a * n + t])
+            w = np.exp(2j * np.pi * (1 << (n - 1 - t)) * m / N)
+            vec = vec @ (c[:, 0, :] + w * c[:, 1, :])
+    return complex(vec[0]) / N ** 1.5
+
+
 def qn_matrix(n: int) -> np.ndarray:
     """Reduced QFT Q_n[k, j] = N^-1/2 exp(2 pi i j rev(k) / N) (Sec. 4.1)."""
     N = 1 << n

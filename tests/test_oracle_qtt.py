@@ -143,3 +143,31 @@ def test_untruncated_alg2_equals_alg1_same_iterations():
     C2, _ = Q.qtt_effective_stiffness(p.phase, p.lame, p.lame0, 1e-14, 1 << 30, 0.0, fixed_iters=3)
     C1, _ = D.effective_stiffness(p.phase, p.lame, p.lame0, 0.0, fixed_iters=3)
     assert np.abs(C2 - C1).max() < 1e-11 * np.abs(C1).max()
+
+
+def test_tt_entry_matches_full():
+    rng = np.random.default_rng(21)
+    dims = [6, 2, 2, 2, 2, 2, 2]
+    x = rand_tt(rng, dims, 5)
+    F = Q.tt_full(x)
+    for _ in range(20):
+        idx = tuple(int(rng.integers(d)) for d in dims)
+        assert abs(Q.tt_entry(x, idx) - F[idx]) < 1e-12 * np.abs(F).max()
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_sfft_entry_matches_library_fft(n):
+    """Entrywise SFFT of a train (used on sampled outputs at full size) equals
+    N^(3/2) ifftn of the dense field read at bit-reversed indices, the
+    library-FFT form of the reduced QFT on each axis."""
+    N = 1 << n
+    rng = np.random.default_rng(22 + n)
+    x = rand_tt(rng, [6] + [2] * (3 * n), 7)
+    f = Q.tt_full(x).reshape(6, N, N, N)
+    ref = N ** 1.5 * np.fft.ifftn(f, axes=(1, 2, 3))
+    r = Q.bitrev(np.arange(N), n)
+    for _ in range(40):
+        v = int(rng.integers(6))
+        k = [int(a) for a in rng.integers(N, size=3)]
+        want = ref[v, r[k[0]], r[k[1]], r[k[2]]]
+        assert abs(Q.sfft_entry(x, n, v, k) - want) < 1e-12 * np.abs(ref).max()
