@@ -131,9 +131,10 @@ __device__ __forceinline__ void blk_wsum(const cplx* Wp, int cg, int rq, int cl,
 // H_p.  The register arrays hold Q on return (also written to Q.base).
 template <int RB, int RPL, int CG>
 __device__ __forceinline__ void formq_phase(int m, int k, int np, int b, int tid, int rb, int cg,
-                                            int cl0, int rq0, int col, int base, cplx* Vs, cplx* Wp,
-                                            cplx (*Ts)[VST], const cplx* Vg, const cplx* Tg, MatOut Q,
-                                            dv4 (&ar)[RPL / 4], dv4 (&ai)[RPL / 4]) {
+                                            int cgl, int pstart, int cl0, int rq0, int col, int base,
+                                            cplx* Vs, cplx* Wp, cplx (*Ts)[VST], const cplx* Vg,
+                                            const cplx* Tg, MatOut Q, dv4 (&ar)[RPL / 4],
+                                            dv4 (&ai)[RPL / 4]) {
   constexpr int RBS = 4 * RPL, MR = RB * RBS, NT = RB * CG * 64;
   const int rq = rq0;
   cplx* Qb = Q.base + b * Q.sb;
@@ -143,7 +144,7 @@ __device__ __forceinline__ void formq_phase(int m, int k, int np, int b, int tid
     AR(i) = (row == col && col < k) ? 1.0 : 0.0;
     AI(i) = 0.0;
   }
-  for (int p = np - 1; p >= 0; --p) {
+  for (int p = pstart; p >= 0; --p) {
     const int j0 = 16 * p;
     int rq, cl;
     OPAQUE(rq, rq0);
@@ -151,35 +152,40 @@ __device__ __forceinline__ void formq_phase(int m, int k, int np, int b, int tid
     __syncthreads();  // the previous panel's Vs, Ts, Wp reads are done
     {
       // every load of the panel issued before the LDS stores
-      constexpr int CNT = (MR * 16 + NT - 1) / NT;
-      cplx t[CNT];
+      constexpr int CNT = (MR * 16 + NT - 1) / NT, TCNT = (256 + NT - 1) / NT;
+      cplx t[CNT], tt[TCNT];
 #pragma unroll
       for (int q = 0; q < CNT; ++q) {
         const int e = tid + q * NT, row = min(e >> 4, m - 1);
         t[q] = Vg[((long)p * m + row) * 16 + (e & 15)];
       }
-      const cplx tt = Tg[(long)p * 256 + (tid & 255)];
+#pragma unroll
+      for (int q = 0; q < TCNT; ++q) tt[q] = Tg[(long)p * 256 + min(tid + q * NT, 255)];
 #pragma unroll
       for (int q = 0; q < CNT; ++q) {
         const int e = tid + q * NT, row = e >> 4;
         if (e < MR * 16)
           Vs[row * VST + (e & 15)] = make_double2(row < m ? t[q].x : 0.0, row < m ? t[q].y : 0.0);
       }
-      if (tid < 256) Ts[tid >> 4][tid & 15] = tt;
+#pragma unroll
+      for (int q = 0; q < TCNT; ++q) {
+        const int e = tid + q * NT;
+        if (e < 256) Ts[e >> 4][e & 15] = tt[q];
+      }
     }
     __syncthreads();
     const bool live = cg >= p;
     if (live) {
       dv4 wr, wi;
       blk_vhx<RPL>(Vs, base, rq, cl, j0, ar, ai, wr, wi);
-      cplx* Wq = Wp + ((long)rb * CG + cg) * 256;
+      cplx* Wq = Wp + ((long)rb * CG + cgl) * 256;
 #pragma unroll
       for (int r = 0; r < 4; ++r) Wq[(4 * r + rq) * 16 + cl] = make_double2(wr[r], wi[r]);
     }
     __syncthreads();
     if (live && base + RBS > j0) {
       dv4 Wr, Wi;
-      blk_wsum<RB, CG>(Wp, cg, rq, cl, Wr, Wi);
+      blk_wsum<RB, CG>(Wp, cgl, rq, cl, Wr, Wi);
       // W2 = T W: A operand T[cl][4s + rq]
       dv4 w2r = {0.0, 0.0, 0.0, 0.0}, w2i = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -444,18 +450,21 @@ __global__ __launch_bounds__(RB * CG * 64) void k_qr_blk(int m, int n, MatView A
     QRB_WINDOW(i);
   }
   if (Q.base == nullptr) return;
-  formq_phase<RB, RPL, CG>(m, k, np, b, tid, rb, cg, cl0, rq0, col, base, Vs, Wp, Ts, Vg, Tg, Q, ar, ai);
+  formq_phase<RB, RPL, CG>(m, k, np, b, tid, rb, cg, cg, np - 1, cl0, rq0, col, base, Vs, Wp, Ts, Vg,
+                           Tg, Q, ar, ai);
 }
 
-// Q alone from the panel vectors and T blocks in the workspace (the Q
-// phase of k_qr_blk as its own kernel, after the unblocked register
-// kernel has produced R and the vectors).
-template <int RB, int RPL, int CG>
-__global__ __launch_bounds__(RB * CG * 64) void k_qr_formq(int m, int n, MatOut Q, cplx* ws, long wsz) {
+// Q alone from the panel vectors and T blocks in the workspace (the Q phase
+// of k_qr_blk as its own kernel, after the unblocked register kernel has
+// produced R and the vectors), with one workgroup per 16-column group of Q
+// (grid (batch, np)): the groups are independent, so each runs on a compute
+// unit of its own and applies only the panels p <= its group (a later panel
+// leaves an identity block untouched); RB waves split the rows.
+template <int RB, int RPL>
+__global__ __launch_bounds__(RB * 64) void k_qr_formq1(int m, int n, MatOut Q, cplx* ws, long wsz) {
   constexpr int NQ = RPL / 4;
-  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int rb = w / CG, cg = w % CG;
+  const int b = blockIdx.x, cg = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
+  const int rb = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int cl0 = lane & 15, rq0 = lane >> 4;
   const int col = cg * 16 + cl0;
   const int base = rb * 4 * RPL;
@@ -467,7 +476,8 @@ __global__ __launch_bounds__(RB * CG * 64) void k_qr_formq(int m, int n, MatOut 
   const cplx* Vg = ws + (long)b * wsz;
   const cplx* Tg = Vg + (long)np * m * 16;
   dv4 ar[NQ], ai[NQ];
-  formq_phase<RB, RPL, CG>(m, k, np, b, tid, rb, cg, cl0, rq0, col, base, Vs, Wp, Ts, Vg, Tg, Q, ar, ai);
+  formq_phase<RB, RPL, 1>(m, k, np, b, tid, rb, cg, 0, min(np - 1, cg), cl0, rq0, col, base, Vs, Wp, Ts,
+                          Vg, Tg, Q, ar, ai);
 }
 
 #undef AR
@@ -530,31 +540,30 @@ __global__ __launch_bounds__(256) void k_qr_tbuild(int m, int n, cplx* ws, long 
   }
 }
 
-template <int RB, int RPL, int CG>
-bool try_qr_formq(int batch, int m, int n, const MatOut& Q, cplx* ws, hipStream_t s) {
+template <int RB, int RPL>
+bool try_qr_formq1(int batch, int m, int n, const MatOut& Q, cplx* ws, hipStream_t s) {
   constexpr int MR = RB * 4 * RPL;
-  if (m > MR || n > 16 * CG) return false;
-  const size_t shm = (size_t)(MR * VST + RB * CG * 256) * sizeof(cplx);
-  // once per kernel and process (thread-safe static initialisation: the
-  // load-case groups of a solve launch from several host threads)
+  const int k = m < n ? m : n, np = (k + 15) / 16;
+  if (m > MR) return false;
+  const size_t shm = (size_t)(MR * VST + RB * 256) * sizeof(cplx);
   static const bool attr = [&]() {
-    check(hipFuncSetAttribute((const void*)k_qr_formq<RB, RPL, CG>,
+    check(hipFuncSetAttribute((const void*)k_qr_formq1<RB, RPL>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm),
-          "qr_formq lds attribute");
+          "qr_formq1 lds attribute");
     return true;
   }();
   (void)attr;
-  hipLaunchKernelGGL((k_qr_formq<RB, RPL, CG>), dim3(batch), dim3(RB * CG * 64), shm, s, m, n, Q, ws,
+  hipLaunchKernelGGL((k_qr_formq1<RB, RPL>), dim3(batch, np), dim3(RB * 64), shm, s, m, n, Q, ws,
                      (long)qr_ws_per_matrix(m, n));
-  check(hipGetLastError(), "qr_formq launch");
+  check(hipGetLastError(), "qr_formq1 launch");
   return true;
 }
 
-template <int CG>
-bool qr_formq_cg(int batch, int m, int n, const MatOut& Q, cplx* ws, hipStream_t s) {
-  return try_qr_formq<2, 4, CG>(batch, m, n, Q, ws, s) || try_qr_formq<2, 8, CG>(batch, m, n, Q, ws, s) ||
-         try_qr_formq<2, 12, CG>(batch, m, n, Q, ws, s) || try_qr_formq<2, 16, CG>(batch, m, n, Q, ws, s) ||
-         try_qr_formq<2, 20, CG>(batch, m, n, Q, ws, s) || try_qr_formq<2, 24, CG>(batch, m, n, Q, ws, s);
+// row blocks of 4 RPL rows: 4 waves up to 128 rows, then 5 or 6 waves of
+// 32 rows (measured at 160 x 80 and 160 x 64 against 2, 4 and 10 waves)
+bool qr_formq_split(int batch, int m, int n, const MatOut& Q, cplx* ws, hipStream_t s) {
+  return try_qr_formq1<4, 4>(batch, m, n, Q, ws, s) || try_qr_formq1<4, 8>(batch, m, n, Q, ws, s) ||
+         try_qr_formq1<5, 8>(batch, m, n, Q, ws, s) || try_qr_formq1<6, 8>(batch, m, n, Q, ws, s);
 }
 
 template <int RB, int RPL, int CG>
@@ -601,13 +610,7 @@ bool qr_form_q(int batch, int m, int n, MatOut Q, cplx* ws, hipStream_t s) {
   const int np = (n + 15) / 16;
   hipLaunchKernelGGL(k_qr_tbuild, dim3(np, batch), dim3(256), 0, s, m, n, ws, (long)qr_ws_per_matrix(m, n));
   check(hipGetLastError(), "qr_tbuild launch");
-  switch (np) {
-    case 2: return qr_formq_cg<2>(batch, m, n, Q, ws, s);
-    case 3: return qr_formq_cg<3>(batch, m, n, Q, ws, s);
-    case 4: return qr_formq_cg<4>(batch, m, n, Q, ws, s);
-    case 5: return qr_formq_cg<5>(batch, m, n, Q, ws, s);
-    default: return qr_formq_cg<6>(batch, m, n, Q, ws, s);
-  }
+  return qr_formq_split(batch, m, n, Q, ws, s);
 }
 
 bool qr_blocked(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, hipStream_t s) {
