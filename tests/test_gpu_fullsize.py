@@ -49,18 +49,28 @@ def test_sfft_apply_256_sampled_entries(ctx):
     assert np.abs(got - want).max() < 1e-8 * rms, np.abs(got - want).max() / rms
 
 
-def test_fibres_256_solve_against_oracle(ctx):
-    """The benchmark's solve (256^3 four fibres, cap 64, delta 1e-8, sketch
-    oversampling 16, 110 updates per load case, three concurrent groups):
-    C_eff within 5e-3 of the oracle's converged dense solution (rank 64
-    leaves 1.2e-2 of the strain field; measured C_eff error 2.0-2.1e-3),
-    symmetric to the same level, and between the Reuss and Voigt bounds of
-    the voxel phase fractions."""
+BENCH_OPTS = dict(max_iter=110, oversample=16, seed=2024, streams=3)
+
+
+@pytest.fixture(scope="module")
+def fibres256(ctx):
+    """The benchmark's solve: 256^3 four fibres, cap 64, delta 1e-8, sketch
+    oversampling 16, 110 updates per load case, three concurrent groups."""
     p = M.config_c2()
     prep = q.prepare(ctx, p.phase, p.lame, p.lame0, p.delta)
-    opts = q.SolveOptions(delta=p.delta, tol=p.tol, cap=p.cap, max_iter=110, oversample=16,
-                          seed=2024, streams=3)
-    C, rep, _ = q.ls_solve_prepared(ctx, prep, opts)
+    opts = q.SolveOptions(delta=p.delta, tol=p.tol, cap=p.cap, **BENCH_OPTS)
+    C, rep, eps = q.ls_solve_prepared(ctx, prep, opts, keep_eps=True)
+    return p, prep, opts, C, rep, eps
+
+
+def test_fibres_256_solve_against_oracle(fibres256):
+    """C_eff within 5e-3 of the oracle's converged dense solution (rank 64
+    leaves 1.2e-2 of the strain field; measured C_eff error 1.9-2.1e-3),
+    symmetric to the same level, and between the Reuss and Voigt bounds of
+    the voxel phase fractions to that level (the geometry attains the Voigt
+    bound in one direction: the oracle's converged C_eff meets it to 1e-15,
+    so truncation may cross it by its own error)."""
+    p, _, _, C, rep, _ = fibres256
     assert rep.max_rank <= p.cap
     assert all(it == 110 for it in rep.iterations)  # the cap-64 residual plateaus above tol
     ref = np.array(json.load(open(os.path.join(HERE, "golden", "ceff_c2.json")))["ceff"]).reshape(6, 6)
@@ -69,5 +79,26 @@ def test_fibres_256_solve_against_oracle(ctx):
     Cs = B.iso_phases(p.lame)
     f = np.array([np.mean(p.phase == i) for i in range(len(p.lame))])
     Csym = 0.5 * (C + C.T)
-    assert np.linalg.eigvalsh(B.voigt_bound(Cs, f) - Csym).min() > 0.0
-    assert np.linalg.eigvalsh(Csym - B.reuss_bound(Cs, f)).min() > 0.0
+    tol = 5e-3 * np.linalg.norm(C)
+    assert np.linalg.eigvalsh(B.voigt_bound(Cs, f) - Csym).min() > -tol
+    assert np.linalg.eigvalsh(Csym - B.reuss_bound(Cs, f)).min() > -tol
+
+
+def test_fibres_256_gradient_euler(ctx, fibres256):
+    """The adjoint Jacobian of the benchmark's solve (same options, three
+    groups): C is linear in each phase's (lambda, mu), so at convergence the
+    energy form gives sum_theta theta dC_eff/dtheta = C_eff (Hill's lemma),
+    and each dC_eff/dtheta is symmetric.  The oracle's exact 16^3 fields of
+    the same geometry meet the first to 1.2e-3 (the Nyquist average is not
+    a projection); the cap-64 truncation adds its 2e-3, so both are checked
+    to 2e-2, far below what a dropped term, a wrong sign or a factor would
+    leave."""
+    p, prep, opts, C, _, eps = fibres256
+    J, arep = q.ls_adjoint_prepared(ctx, prep, opts, eps)
+    J = np.asarray(J)
+    assert J.shape == (6, 6, 2 * len(p.lame))
+    theta = np.asarray(p.lame).ravel()
+    euler = np.einsum("klt,t->kl", J, theta)
+    assert np.linalg.norm(euler - C) < 2e-2 * np.linalg.norm(C)
+    for t in range(J.shape[2]):
+        assert np.linalg.norm(J[:, :, t] - J[:, :, t].T) < 2e-2 * np.linalg.norm(J[:, :, t])
