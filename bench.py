@@ -209,9 +209,9 @@ def main():
         print(json.dumps({"copy_bytes": n * 8, "copies": 5}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the six load cases and independent structures would shard across GPUs with "
-              "no exchange during the solve, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the six load "
+              "cases and independent structures would shard across GPUs with no exchange "
+              "during the solve, only a final gather of C_eff)", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("RANK", "0")) != 0:
         return
