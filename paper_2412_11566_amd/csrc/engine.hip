@@ -428,11 +428,6 @@ static void ck_tto_core_apply(const Ctx& X, int B, int rho, int din, int dout, i
   X.t1(e, QTT_K_APPLY, zel * 8.0 * (din > 0 ? din : 1),
        16.0 * ((double)rho * (din > 0 ? din : 1) * dout * rho2 + (double)B * r * dx * r2 + zel));
 }
-static void ck_gaussian(const Ctx& X, cplx* out, size_t count, uint64_t seed, uint64_t stream,
-                        double scale, hipStream_t s) {
-  need(X, out, (long)count - 1, "gaussian");
-  gaussian(out, count, seed, stream, scale, s);
-}
 static void ck_sum_middle(const Ctx& X, int B, int outer, int np, int inner, const cplx* in,
                           cplx* out, cplx w, hipStream_t s) {
   need(X, in, (long)B * outer * np * inner - 1, "sum in");
@@ -836,13 +831,25 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
     }
   }
   // random test train Omega_k (ell_k, dout_k, ell_{k+1}), k = 1..L-1
+  // (drawn in as few launches as the block limit allows)
   std::vector<BufP> Om(L);
+  GaussBlocks gb;
+  gb.start[0] = 0;
   for (int k = 1; k < L; ++k) {
     if (dense_w[k] || ident_w[k]) continue;
     const size_t cnt = (size_t)ell[k] * A.dout[k] * ell[k + 1];
     Om[k] = X.buf(cnt);
-    ck_gaussian(X, (cplx*)Om[k]->p, cnt, o.seed, (uint64_t)k, 1.0 / std::sqrt((double)A.dout[k] * ell[k + 1]), X.s());
+    need(X, Om[k]->p, (long)cnt - 1, "gaussian");
+    gb.out[gb.n] = (cplx*)Om[k]->p;
+    gb.stream[gb.n] = (uint64_t)k;
+    gb.scale[gb.n] = 1.0 / std::sqrt((double)A.dout[k] * ell[k + 1]);
+    gb.start[gb.n + 1] = gb.start[gb.n] + (long)cnt;
+    if (++gb.n == GAUSS_MULTI_MAX) {
+      gaussian_multi(gb, o.seed, X.s());
+      gb.n = 0;
+    }
   }
+  gaussian_multi(gb, o.seed, X.s());
   // right-to-left partial sketches W_k (B, rho_k, r_k, ell_k)
   std::vector<BufP> W(L + 1);
   W[L] = X.buf(B);

@@ -457,10 +457,10 @@ __device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1, uint32_
   c0 = n0; c1 = l1; c2 = n2; c3 = l0;
 }
 
-__global__ void k_gaussian(cplx* out, size_t count, uint64_t seed, uint64_t stream,
-                           double scale) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= count) return;
+// entry e of the complex standard normal stream (seed, stream), scaled:
+// Philox4x32-10 on the counter (e, stream), then Box-Muller
+__device__ __forceinline__ cplx gaussian_entry(uint64_t e, uint64_t seed, uint64_t stream,
+                                               double scale) {
   uint32_t c0 = (uint32_t)e, c1 = (uint32_t)(e >> 32);
   uint32_t c2 = (uint32_t)stream, c3 = (uint32_t)(stream >> 32);
   uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -475,16 +475,26 @@ __global__ void k_gaussian(cplx* out, size_t count, uint64_t seed, uint64_t stre
   const double rr = sqrt(-2.0 * log(u1)) * scale;
   double sn, cs;
   sincospi(2.0 * u2, &sn, &cs);
-  out[e] = make_double2(rr * cs, rr * sn);
+  return make_double2(rr * cs, rr * sn);
 }
 
-void gaussian(cplx* out, size_t count, uint64_t seed, uint64_t stream, double scale,
-              hipStream_t s) {
-  if (count == 0) return;
+// every block of a GaussBlocks set in one launch: thread e finds its block
+// by the prefix offsets (at most GAUSS_MULTI_MAX compares)
+__global__ void k_gaussian_multi(GaussBlocks g, uint64_t seed) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.start[g.n]) return;
+  int i = 0;
+  while (i + 1 < g.n && e >= g.start[i + 1]) ++i;
+  const long el = e - g.start[i];
+  g.out[i][el] = gaussian_entry((uint64_t)el, seed, g.stream[i], g.scale[i]);
+}
+
+void gaussian_multi(const GaussBlocks& g, uint64_t seed, hipStream_t s) {
+  if (g.n <= 0 || g.start[g.n] == 0) return;
   const int nt = 256;
-  hipLaunchKernelGGL(k_gaussian, dim3((count + nt - 1) / nt), dim3(nt), 0, s, out,
-                     count, seed, stream, scale);
-  check(hipGetLastError(), "gaussian launch");
+  const long total = g.start[g.n];
+  hipLaunchKernelGGL(k_gaussian_multi, dim3((unsigned)((total + nt - 1) / nt)), dim3(nt), 0, s, g, seed);
+  check(hipGetLastError(), "gaussian multi launch");
 }
 
 // ---------------------------------------------------------------------------

@@ -152,9 +152,19 @@ void svd(int batch, int m, int n, MatView A, MatOut U, double* S, MatOut V,
 size_t svd_ws(int batch, int m, int n);
 
 // Complex standard normal numbers (Philox4x32-10 counter generator +
-// Box-Muller), entry e of the stream (seed, stream) at out[e], scaled.
-void gaussian(cplx* out, size_t count, uint64_t seed, uint64_t stream,
-              double scale, hipStream_t s);
+// Box-Muller), several blocks in one launch: block i (i < n) fills
+// out[i][e], e < start[i+1] - start[i], with entry e of the stream
+// (seed, stream[i]) scaled by scale[i].  Passed by value as the kernel
+// argument.
+constexpr int GAUSS_MULTI_MAX = 40;
+struct GaussBlocks {
+  int n = 0;
+  cplx* out[GAUSS_MULTI_MAX];
+  long start[GAUSS_MULTI_MAX + 1];
+  uint64_t stream[GAUSS_MULTI_MAX];
+  double scale[GAUSS_MULTI_MAX];
+};
+void gaussian_multi(const GaussBlocks& g, uint64_t seed, hipStream_t s);
 
 // Materialised TTO x TT core product:
 // Z[b][(a,c)][i][(a2,c2)] = sum_j A[a][j][i][a2] x[b][c][j][c2]
