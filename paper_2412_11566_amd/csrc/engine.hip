@@ -974,13 +974,21 @@ static TTP apply_full(const Ctx& X, const TT& A, const TT& x) {
     const int r = x.r[k], r2 = x.r[k + 1];
     const long dx = din > 0 ? din : dout;
     const long total = (long)B * rho * r * dout * rho2 * r2;
-    if (total >= (1L << 31)) throw std::invalid_argument("product core too large for one launch");
     const long ainst = (long)rho * (din > 0 ? din : 1) * dout * rho2;
+    // 32-bit offsets inside a core's output, input and operator instance
+    if (total >= (1L << 31) || (long)B * r * dx * r2 >= (1L << 31) || ainst >= (1L << 31))
+      throw std::invalid_argument("product core too large for one launch");
     need(X, A.core[k], ainst * A.opb - 1, "apply A");
     need(X, x.core[k], (long)B * r * dx * r2 - 1, "apply x");
     need(X, z->core[k], total - 1, "apply Z");
     d[k] = TtoDesc{A.core[k], x.core[k], z->core[k], B, rho, din, dout, rho2, r, r2, total, blocks,
                    A.opb > 1 ? ainst : 0, B / A.opb};
+    d[k].f_inner = make_fastdiv((uint32_t)(rho2 * r2));
+    d[k].f_r2 = make_fastdiv((uint32_t)r2);
+    d[k].f_dout = make_fastdiv((uint32_t)dout);
+    d[k].f_r = make_fastdiv((uint32_t)r);
+    d[k].f_rho = make_fastdiv((uint32_t)rho);
+    d[k].f_group = make_fastdiv((uint32_t)(B / A.opb));
     blocks += tto_apply_blocks(total);
     flops += (double)total * 8.0 * (din > 0 ? din : 1);
     bytes += 16.0 * ((double)rho * (din > 0 ? din : 1) * dout * rho2 + (double)B * r * dx * r2 + (double)total);

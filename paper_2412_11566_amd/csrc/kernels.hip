@@ -539,7 +539,9 @@ void tto_core_apply(int batch, int rho, int din, int dout, int rho2, int r, int 
 // are assigned to cores by the descriptors' start_block prefix; inside a
 // core the output is walked row-major with the (a2, c2) index innermost, so
 // consecutive lanes write consecutive output entries and read consecutive
-// x entries.  32-bit index arithmetic (every core has < 2^31 entries).
+// x entries.  32-bit indices (every core has < 2^31 entries), split by the
+// descriptors' multiply-high dividers: integer divisions of the index
+// otherwise cost more than the product itself and bound the kernel.
 constexpr int TTO_NT = 256, TTO_EPT = 4;
 
 __global__ __launch_bounds__(TTO_NT) void k_tto_apply_all(int ncores, const TtoDesc* __restrict__ D) {
@@ -547,31 +549,29 @@ __global__ __launch_bounds__(TTO_NT) void k_tto_apply_all(int ncores, const TtoD
   for (int q = 1; q < ncores; ++q)
     if ((long)blockIdx.x >= D[q].start_block) kc = q;
   const TtoDesc d = D[kc];
-  const long blk = (long)blockIdx.x - d.start_block;
-  const int inner = d.rho2 * d.r2;
+  const uint32_t blk = (uint32_t)((long)blockIdx.x - d.start_block);
+  const uint32_t total = (uint32_t)d.total;
   const int dx = d.din > 0 ? d.din : d.dout;
 #pragma unroll
   for (int u = 0; u < TTO_EPT; ++u) {
-    const long el = (blk * TTO_EPT + u) * TTO_NT + threadIdx.x;
-    if (el >= d.total) return;
-    const int row = (int)(el / inner), colx = (int)(el - (long)row * inner);
-    const int a2 = colx / d.r2, c2 = colx - a2 * d.r2;
-    int t = row;
-    const int i = t % d.dout;
-    t /= d.dout;
-    const int c = t % d.r;
-    t /= d.r;
-    const int a = t % d.rho;
-    const int b = t / d.rho;
-    const cplx* xb = d.x + ((long)(b * d.r + c) * dx) * d.r2 + c2;
-    const cplx* Ab = d.A + (long)(b / d.group) * d.a_stride;
+    const uint32_t el = (blk * TTO_EPT + u) * TTO_NT + threadIdx.x;
+    if (el >= total) return;
+    const uint32_t row = fdiv(el, d.f_inner), colx = el - row * (uint32_t)(d.rho2 * d.r2);
+    const uint32_t a2 = fdiv(colx, d.f_r2), c2 = colx - a2 * (uint32_t)d.r2;
+    const uint32_t t1 = fdiv(row, d.f_dout), i = row - t1 * (uint32_t)d.dout;
+    const uint32_t t2 = fdiv(t1, d.f_r), c = t1 - t2 * (uint32_t)d.r;
+    const uint32_t b = fdiv(t2, d.f_rho), a = t2 - b * (uint32_t)d.rho;
+    // offsets inside one core's x and one operator instance fit 32 bits
+    const cplx* xb = d.x + ((b * (uint32_t)d.r + c) * (uint32_t)dx * (uint32_t)d.r2 + c2);
+    const cplx* Ab = d.A + (long)fdiv(b, d.f_group) * d.a_stride;
     cplx acc;
     if (d.din == 0) {
-      acc = cmul(Ab[((long)a * d.dout + i) * d.rho2 + a2], xb[(long)i * d.r2]);
+      acc = cmul(Ab[(a * (uint32_t)d.dout + i) * (uint32_t)d.rho2 + a2], xb[i * (uint32_t)d.r2]);
     } else {
       acc = make_double2(0.0, 0.0);
       for (int j = 0; j < d.din; ++j)
-        acc = cadd(acc, cmul(Ab[(((long)a * d.din + j) * d.dout + i) * d.rho2 + a2], xb[(long)j * d.r2]));
+        acc = cadd(acc, cmul(Ab[((a * (uint32_t)d.din + j) * (uint32_t)d.dout + i) * (uint32_t)d.rho2 + a2],
+                             xb[(uint32_t)j * (uint32_t)d.r2]));
     }
     d.Z[el] = acc;
   }

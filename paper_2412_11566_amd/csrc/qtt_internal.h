@@ -174,6 +174,33 @@ void tto_core_apply(int batch, int rho, int din, int dout, int rho2, int r,
                     int r2, const cplx* A, const cplx* x, cplx* Z,
                     hipStream_t s);
 
+// x / d for 0 <= x < 2^31 and 1 <= d < 2^31 by the high half of a 32-bit
+// multiply and a shift (the round-up method of Granlund and Montgomery,
+// 1994): with s = ceil(log2 d) >= 1 and m = floor(2^(31+s) / d) + 1
+// (< 2^32), floor(x m / 2^(31+s)) = floor(x / d) because
+// x (m d - 2^(31+s)) <= x d < 2^(31+s); d = 1 is marked by m = 0.
+struct FastDiv {
+  uint32_t m = 0, sh = 0, d = 1;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  if (d <= 1) return f;
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  f.m = (uint32_t)(((1ull << (31 + s)) / d) + 1);
+  f.sh = s - 1;
+  return f;
+}
+__host__ __device__ inline uint32_t fdiv(uint32_t x, const FastDiv& f) {
+#ifdef __HIP_DEVICE_COMPILE__
+  const uint32_t hi = __umulhi(x, f.m);
+#else
+  const uint32_t hi = (uint32_t)(((uint64_t)x * f.m) >> 32);
+#endif
+  return f.m == 0 ? x : hi >> f.sh;
+}
+
 // One core of a product for the single-launch form: the same contraction
 // as tto_core_apply, batch folded into the row index, output Z of `total`
 // entries, blocks [start_block, start_block + tto_apply_blocks(total)).
@@ -185,6 +212,8 @@ struct TtoDesc {
   long total, start_block;
   long a_stride;  // operator instance stride (0: one instance for all b)
   int group;      // train batch elements per operator instance
+  // dividers of the output index: rho2 r2, r2, dout, r, rho, group
+  FastDiv f_inner, f_r2, f_dout, f_r, f_rho, f_group;
 };
 long tto_apply_blocks(long total);
 // Every core of a product in one launch; D_dev: ncores descriptors in

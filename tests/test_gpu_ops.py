@@ -118,6 +118,26 @@ def test_sfft_apply(ctx, flags):
         assert rel(dense(yc, b).reshape(6, N, N, N), ref) < 1e-11
 
 
+def test_sfft_materialised_row_walk(ctx):
+    """Materialised SFFT product on ranks up to 128 (product rows of up to
+    256 entries, bond ranks 6, 12, 24, 48, 96 that do not divide the
+    workgroup size: the row walk's carry), batch of two, against the library
+    FFT at bit-reversed indices; rows wider than a workgroup are covered at
+    full size (rank 640)."""
+    n = 4
+    N = 1 << n
+    rng = np.random.default_rng(15)
+    x = rand_strain(rng, n, 128, batch=2)
+    S = q.sfft_build(ctx, n, 1e-14)
+    y = q.sfft_apply(ctx, S, q.tt_from_cores(ctx, x), flags=q.QTT_NO_ROUND)
+    xr = [x[0].shape[1]] + [c.shape[3] for c in x]
+    assert y.ranks == [a * b for a, b in zip(S.ranks, xr)]
+    yc = y.cores()
+    for b in range(2):
+        ref = _sfft_reference(dense(x, b).reshape(6, N, N, N), n)
+        assert rel(dense(yc, b).reshape(6, N, N, N), ref) < 1e-11
+
+
 def test_sfft_inverse_roundtrip(ctx):
     n = 2
     rng = np.random.default_rng(6)
