@@ -983,13 +983,12 @@ static TTP apply_full(const Ctx& X, const TT& A, const TT& x) {
     need(X, z->core[k], total - 1, "apply Z");
     d[k] = TtoDesc{A.core[k], x.core[k], z->core[k], B, rho, din, dout, rho2, r, r2, total, blocks,
                    A.opb > 1 ? ainst : 0, B / A.opb};
-    d[k].f_inner = make_fastdiv((uint32_t)(rho2 * r2));
+    d[k].f_cols = make_fastdiv((uint32_t)(total / ((long)dout * rho2)));
     d[k].f_r2 = make_fastdiv((uint32_t)r2);
-    d[k].f_dout = make_fastdiv((uint32_t)dout);
     d[k].f_r = make_fastdiv((uint32_t)r);
     d[k].f_rho = make_fastdiv((uint32_t)rho);
     d[k].f_group = make_fastdiv((uint32_t)(B / A.opb));
-    blocks += tto_apply_blocks(total);
+    blocks += tto_apply_blocks(total, rho2);
     flops += (double)total * 8.0 * (din > 0 ? din : 1);
     bytes += 16.0 * ((double)rho * (din > 0 ? din : 1) * dout * rho2 + (double)B * r * dx * r2 + (double)total);
   }

@@ -536,48 +536,58 @@ void tto_core_apply(int batch, int rho, int din, int dout, int rho2, int r, int 
 }
 
 // All cores of a materialised TTO x TT product in one launch.  Block ranges
-// are assigned to cores by the descriptors' start_block prefix; inside a
-// core the output is walked row-major with the (a2, c2) index innermost, so
-// consecutive lanes write consecutive output entries and read consecutive
-// x entries.  32-bit indices (every core has < 2^31 entries), split by the
-// descriptors' multiply-high dividers: integer divisions of the index
-// otherwise cost more than the product itself and bound the kernel.
-constexpr int TTO_NT = 256, TTO_EPT = 4;
+// are assigned to cores by the descriptors' start_block prefix.  A thread
+// owns one (i, column (b, a, c, c2)) of its core's output: it loads its x
+// entries once and writes the rho2 outputs a2 of that row segment, so x is
+// read once per rho2 outputs instead of once per output, and the
+// operator entries, the same for every lane of a wave with one (a), are
+// broadcast loads.  Consecutive lanes hold consecutive c2: every store
+// instruction writes consecutive output entries.  32-bit offsets inside a
+// core (the host checks every core has < 2^31 entries); the column index
+// is split by the descriptors' multiply-high dividers.
+constexpr int TTO_NT = 256;
 
 __global__ __launch_bounds__(TTO_NT) void k_tto_apply_all(int ncores, const TtoDesc* __restrict__ D) {
   int kc = 0;
   for (int q = 1; q < ncores; ++q)
     if ((long)blockIdx.x >= D[q].start_block) kc = q;
   const TtoDesc d = D[kc];
-  const uint32_t blk = (uint32_t)((long)blockIdx.x - d.start_block);
-  const uint32_t total = (uint32_t)d.total;
-  const int dx = d.din > 0 ? d.din : d.dout;
-#pragma unroll
-  for (int u = 0; u < TTO_EPT; ++u) {
-    const uint32_t el = (blk * TTO_EPT + u) * TTO_NT + threadIdx.x;
-    if (el >= total) return;
-    const uint32_t row = fdiv(el, d.f_inner), colx = el - row * (uint32_t)(d.rho2 * d.r2);
-    const uint32_t a2 = fdiv(colx, d.f_r2), c2 = colx - a2 * (uint32_t)d.r2;
-    const uint32_t t1 = fdiv(row, d.f_dout), i = row - t1 * (uint32_t)d.dout;
-    const uint32_t t2 = fdiv(t1, d.f_r), c = t1 - t2 * (uint32_t)d.r;
-    const uint32_t b = fdiv(t2, d.f_rho), a = t2 - b * (uint32_t)d.rho;
-    // offsets inside one core's x and one operator instance fit 32 bits
-    const cplx* xb = d.x + ((b * (uint32_t)d.r + c) * (uint32_t)dx * (uint32_t)d.r2 + c2);
-    const cplx* Ab = d.A + (long)fdiv(b, d.f_group) * d.a_stride;
-    cplx acc;
-    if (d.din == 0) {
-      acc = cmul(Ab[(a * (uint32_t)d.dout + i) * (uint32_t)d.rho2 + a2], xb[i * (uint32_t)d.r2]);
-    } else {
-      acc = make_double2(0.0, 0.0);
-      for (int j = 0; j < d.din; ++j)
-        acc = cadd(acc, cmul(Ab[((a * (uint32_t)d.din + j) * (uint32_t)d.dout + i) * (uint32_t)d.rho2 + a2],
-                             xb[(uint32_t)j * (uint32_t)d.r2]));
+  const uint32_t dout = (uint32_t)d.dout, rho2 = (uint32_t)d.rho2, r2 = (uint32_t)d.r2;
+  const uint32_t cols = (uint32_t)(d.total / (dout * rho2));
+  const uint32_t g = (uint32_t)((long)blockIdx.x - d.start_block) * TTO_NT + threadIdx.x;
+  if (g >= cols * dout) return;
+  const uint32_t i = fdiv(g, d.f_cols), col = g - i * cols;
+  const uint32_t t1 = fdiv(col, d.f_r2), c2 = col - t1 * r2;
+  const uint32_t t2 = fdiv(t1, d.f_r), c = t1 - t2 * (uint32_t)d.r;
+  const uint32_t b = fdiv(t2, d.f_rho), a = t2 - b * (uint32_t)d.rho;
+  const uint32_t dx = d.din > 0 ? (uint32_t)d.din : dout;
+  const cplx* xb = d.x + ((b * (uint32_t)d.r + c) * dx * r2 + c2);
+  const cplx* Ab = d.A + (long)fdiv(b, d.f_group) * d.a_stride;
+  cplx* Zb = d.Z + (((t2 * (uint32_t)d.r + c) * dout + i) * rho2 * r2 + c2);
+  if (d.din == 0) {
+    const cplx xi = xb[i * r2];
+    const cplx* Ai = Ab + (a * dout + i) * rho2;
+    for (uint32_t a2 = 0; a2 < rho2; ++a2) Zb[a2 * r2] = cmul(Ai[a2], xi);
+  } else if (d.din == 2) {
+    const cplx x0 = xb[0], x1 = xb[r2];
+    const cplx* A0 = Ab + ((a * 2u) * dout + i) * rho2;
+    const cplx* A1 = Ab + ((a * 2u + 1u) * dout + i) * rho2;
+    for (uint32_t a2 = 0; a2 < rho2; ++a2) Zb[a2 * r2] = cadd(cmul(A0[a2], x0), cmul(A1[a2], x1));
+  } else {
+    const uint32_t din = (uint32_t)d.din;
+    for (uint32_t a2 = 0; a2 < rho2; ++a2) {
+      cplx acc = make_double2(0.0, 0.0);
+      for (uint32_t j = 0; j < din; ++j)
+        acc = cadd(acc, cmul(Ab[((a * din + j) * dout + i) * rho2 + a2], xb[j * r2]));
+      Zb[a2 * r2] = acc;
     }
-    d.Z[el] = acc;
   }
 }
 
-long tto_apply_blocks(long total) { return (total + (long)TTO_NT * TTO_EPT - 1) / ((long)TTO_NT * TTO_EPT); }
+long tto_apply_blocks(long total, int rho2) {
+  const long threads = total / rho2;  // one per (i, column)
+  return (threads + TTO_NT - 1) / TTO_NT;
+}
 
 void tto_apply_all(int ncores, const TtoDesc* D_dev, long nblocks, hipStream_t s) {
   if (ncores <= 0 || nblocks <= 0) return;

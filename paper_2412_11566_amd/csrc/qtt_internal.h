@@ -203,7 +203,8 @@ __host__ __device__ inline uint32_t fdiv(uint32_t x, const FastDiv& f) {
 
 // One core of a product for the single-launch form: the same contraction
 // as tto_core_apply, batch folded into the row index, output Z of `total`
-// entries, blocks [start_block, start_block + tto_apply_blocks(total)).
+// entries, blocks [start_block, start_block + tto_apply_blocks(total,
+// rho2)), one thread per rho2 outputs.
 struct TtoDesc {
   const cplx* A;
   const cplx* x;
@@ -212,10 +213,10 @@ struct TtoDesc {
   long total, start_block;
   long a_stride;  // operator instance stride (0: one instance for all b)
   int group;      // train batch elements per operator instance
-  // dividers of the output index: rho2 r2, r2, dout, r, rho, group
-  FastDiv f_inner, f_r2, f_dout, f_r, f_rho, f_group;
+  // dividers of the thread index (i, column (b, a, c, c2)) and the instance
+  FastDiv f_cols, f_r2, f_r, f_rho, f_group;
 };
-long tto_apply_blocks(long total);
+long tto_apply_blocks(long total, int rho2);
 // Every core of a product in one launch; D_dev: ncores descriptors in
 // device memory, nblocks = sum of the cores' blocks.
 void tto_apply_all(int ncores, const TtoDesc* D_dev, long nblocks, hipStream_t s);
