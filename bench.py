@@ -194,6 +194,9 @@ def main():
                     help="load-case groups solved concurrently on streams of their own")
     ap.add_argument("--stats-stride", type=int, default=8,
                     help="time every s-th library launch with HIP events (1: all)")
+    ap.add_argument("--tto-only", action="store_true",
+                    help="only run the TTO-apply measurement (materialised SFFT product on the "
+                         "seeded rank-64 train) and print its line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run 5 plain device-to-device copies of BYTES bytes (the "
                          "reference for the HBM byte counters) and exit")
@@ -207,6 +210,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n * 8, "copies": 5}), flush=True)
+        return
+    if args.tto_only:
+        import paper_2412_11566_amd as q
+        ctx = q.Context(0)
+        print(json.dumps({"tto_apply": tto_apply_bandwidth(q, ctx, args.n, reps=5)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the six load "

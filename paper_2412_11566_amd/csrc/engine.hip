@@ -416,18 +416,6 @@ static void ck_batch_norm(const Ctx& X, int B, long len, long stride, const cplx
   need(X, out, B - 1, "norm out", sizeof(double));
   batch_norm(B, len, stride, x, out, s);
 }
-static void ck_tto_core_apply(const Ctx& X, int B, int rho, int din, int dout, int rho2, int r,
-                              int r2, const cplx* A, const cplx* x, cplx* Z, hipStream_t s) {
-  const long dx = din > 0 ? din : dout;
-  need(X, A, (long)rho * (din > 0 ? din : 1) * dout * rho2 - 1, "apply A");
-  need(X, x, (long)B * r * dx * r2 - 1, "apply x");
-  need(X, Z, (long)B * rho * r * dout * rho2 * r2 - 1, "apply Z");
-  hipEvent_t e = X.t0();
-  tto_core_apply(B, rho, din, dout, rho2, r, r2, A, x, Z, s);
-  const double zel = (double)B * rho * r * dout * rho2 * r2;
-  X.t1(e, QTT_K_APPLY, zel * 8.0 * (din > 0 ? din : 1),
-       16.0 * ((double)rho * (din > 0 ? din : 1) * dout * rho2 + (double)B * r * dx * r2 + zel));
-}
 static void ck_sum_middle(const Ctx& X, int B, int outer, int np, int inner, const cplx* in,
                           cplx* out, cplx w, hipStream_t s) {
   need(X, in, (long)B * outer * np * inner - 1, "sum in");

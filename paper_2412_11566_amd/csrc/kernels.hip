@@ -500,41 +500,6 @@ void gaussian_multi(const GaussBlocks& g, uint64_t seed, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Materialised TTO x TT core product (Table 2, contract)
 // ---------------------------------------------------------------------------
-__global__ void k_tto_core_apply(long total, int rho, int din, int dout, int rho2, int r,
-                                 int r2, const cplx* __restrict__ A,
-                                 const cplx* __restrict__ x, cplx* __restrict__ Z) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= total) return;
-  long t = e;
-  const int c2 = t % r2; t /= r2;
-  const int a2 = t % rho2; t /= rho2;
-  const int i = t % dout; t /= dout;
-  const int c = t % r; t /= r;
-  const int a = t % rho; t /= rho;
-  const long b = t;
-  const int dx = din > 0 ? din : dout;
-  const cplx* xb = x + ((b * r + c) * dx) * (long)r2 + c2;
-  cplx acc;
-  if (din == 0) {
-    acc = cmul(A[((long)a * dout + i) * rho2 + a2], xb[(long)i * r2]);
-  } else {
-    acc = make_double2(0.0, 0.0);
-    for (int j = 0; j < din; ++j)
-      acc = cadd(acc, cmul(A[(((long)a * din + j) * dout + i) * rho2 + a2], xb[(long)j * r2]));
-  }
-  Z[e] = acc;
-}
-
-void tto_core_apply(int batch, int rho, int din, int dout, int rho2, int r, int r2,
-                    const cplx* A, const cplx* x, cplx* Z, hipStream_t s) {
-  const long total = (long)batch * rho * r * dout * rho2 * r2;
-  if (total == 0) return;
-  const int nt = 256;
-  hipLaunchKernelGGL(k_tto_core_apply, dim3((total + nt - 1) / nt), dim3(nt), 0, s, total,
-                     rho, din, dout, rho2, r, r2, A, x, Z);
-  check(hipGetLastError(), "tto_core_apply launch");
-}
-
 // All cores of a materialised TTO x TT product in one launch.  Block ranges
 // are assigned to cores by the descriptors' start_block prefix.  A thread
 // owns one (i, column (b, a, c, c2)) of its core's output: it loads its x

@@ -166,14 +166,6 @@ struct GaussBlocks {
 };
 void gaussian_multi(const GaussBlocks& g, uint64_t seed, hipStream_t s);
 
-// Materialised TTO x TT core product:
-// Z[b][(a,c)][i][(a2,c2)] = sum_j A[a][j][i][a2] x[b][c][j][c2]
-// (A stored (rho, din, dout, rho2); diag operators pass din = 0 and A
-// stored (rho, d, rho2)).
-void tto_core_apply(int batch, int rho, int din, int dout, int rho2, int r,
-                    int r2, const cplx* A, const cplx* x, cplx* Z,
-                    hipStream_t s);
-
 // x / d for 0 <= x < 2^31 and 1 <= d < 2^31 by the high half of a 32-bit
 // multiply and a shift (the round-up method of Granlund and Montgomery,
 // 1994): with s = ceil(log2 d) >= 1 and m = floor(2^(31+s) / d) + 1
@@ -201,8 +193,10 @@ __host__ __device__ inline uint32_t fdiv(uint32_t x, const FastDiv& f) {
   return f.m == 0 ? x : hi >> f.sh;
 }
 
-// One core of a product for the single-launch form: the same contraction
-// as tto_core_apply, batch folded into the row index, output Z of `total`
+// One core of a materialised TTO x TT product (Table 2, contract):
+// Z[b][(a,c)][i][(a2,c2)] = sum_j A[a][j][i][a2] x[b][c][j][c2] (A stored
+// (rho, din, dout, rho2); diagonal operators pass din = 0 and A stored
+// (rho, d, rho2)), batch folded into the row index, output Z of `total`
 // entries, blocks [start_block, start_block + tto_apply_blocks(total,
 // rho2)), one thread per rho2 outputs.
 struct TtoDesc {
