@@ -469,83 +469,91 @@ __global__ __launch_bounds__(RB * 64) void k_qr_formq1(int m, int n, MatOut Q, c
   const int col = cg * 16 + cl0;
   const int base = rb * 4 * RPL;
   const int k = min(m, n), np = (k + 15) / 16;
+  const int pmax = min(np - 1, cg);
   extern __shared__ cplx dyn[];
   cplx* Vs = dyn;
   cplx* Wp = dyn + RB * 4 * RPL * VST;
+  cplx* Gl = Wp + RB * 256;  // Gram of panel p at Gl[p * 256], p <= pmax
+  cplx* Tl = Gl + np * 256;  // T of panel p at Tl[p * 256]
   __shared__ cplx Ts[16][VST];
   const cplx* Vg = ws + (long)b * wsz;
-  const cplx* Tg = Vg + (long)np * m * 16;
+  const cplx* taug = Vg + (long)np * m * 16 + (long)np * 256;
+  // T of the panels p <= pmax this group meets (compact WY; each group
+  // builds its own, in parallel with the other groups, instead of a launch
+  // of its own): wave rb takes panels rb, rb + RB, ...; the Gram
+  // V_p^H V_p on the matrix cores over 4-row slices from row 16 p (V is
+  // zero above), then the recurrence T[i][j] = -tau_j sum_{c<j} T[i][c]
+  // G[c][j], T[i][i] = tau_i, one row of T per lane
+  {
+    const int cl = lane & 15, rq = lane >> 4;
+    const int nsl = (m + 3) / 4;
+    for (int p = rb; p <= pmax; p += RB) {
+      const cplx* V = Vg + (long)p * m * 16;
+      dv4 gr = {0.0, 0.0, 0.0, 0.0}, gi = {0.0, 0.0, 0.0, 0.0};
+      // up to 24 slices of loads in flight before their products
+      for (int q0 = 4 * p; q0 < nsl; q0 += 24) {
+        cplx v[24];
+#pragma unroll
+        for (int q = 0; q < 24; ++q) {
+          const int row = 4 * (q0 + q) + rq;
+          const cplx t = V[(long)min(row, m - 1) * 16 + cl];
+          v[q] = make_double2(row < m ? t.x : 0.0, row < m ? t.y : 0.0);
+        }
+#pragma unroll
+        for (int q = 0; q < 24; ++q) {
+          gr = mfma(v[q].x, v[q].x, gr);
+          gr = mfma(v[q].y, v[q].y, gr);
+          gi = mfma(v[q].x, v[q].y, gi);
+          gi = mfma(-v[q].y, v[q].x, gi);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Gl[p * 256 + (4 * r + rq) * 16 + cl] = make_double2(gr[r], gi[r]);
+    }
+    __syncthreads();
+    for (int p = rb; p <= pmax; p += RB) {
+      if (lane < 16) {
+        const int i = lane;
+        const cplx* G = Gl + p * 256;
+        const cplx* tau = taug + (long)p * 16;
+        cplx t[16], tv[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) tv[j] = tau[j];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const cplx tj = tv[j];
+          cplx acc = cz();
+#pragma unroll
+          for (int c = 0; c < j; ++c) {
+            const cplx g = G[c * 16 + j];
+            acc.x += t[c].x * g.x - t[c].y * g.y;
+            acc.y += t[c].x * g.y + t[c].y * g.x;
+          }
+          const cplx tn = cmul(make_double2(-tj.x, -tj.y), acc);
+          t[j] = i < j ? tn : (i == j ? tj : cz());
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) Tl[p * 256 + i * 16 + j] = t[j];
+      }
+    }
+    __syncthreads();
+  }
   dv4 ar[NQ], ai[NQ];
-  formq_phase<RB, RPL, 1>(m, k, np, b, tid, rb, cg, 0, min(np - 1, cg), cl0, rq0, col, base, Vs, Wp, Ts,
-                          Vg, Tg, Q, ar, ai);
+  formq_phase<RB, RPL, 1>(m, k, np, b, tid, rb, cg, 0, pmax, cl0, rq0, col, base, Vs, Wp, Ts, Vg, Tl,
+                          Q, ar, ai);
 }
 
 #undef AR
 #undef AI
-
-// T_p of every panel from V_p (workspace) and tau_p: the Gram V_p^H V_p on
-// the matrix cores (four waves over interleaved 4-row slices, summed in
-// LDS), then the recurrence T[i][j] = -tau_j sum_{c<j} T[i][c] G[c][j],
-// T[i][i] = tau_i, one row of T per lane with the row in registers.
-__global__ __launch_bounds__(256) void k_qr_tbuild(int m, int n, cplx* ws, long wsz) {
-  const int p = blockIdx.x, b = blockIdx.y, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int k = min(m, n), np = (k + 15) / 16;
-  const int cl = lane & 15, rq = lane >> 4;
-  cplx* W = ws + (long)b * wsz;
-  const cplx* V = W + (long)p * m * 16;
-  cplx* T = W + (long)np * m * 16 + (long)p * 256;
-  const cplx* tau = W + (long)np * m * 16 + (long)np * 256 + (long)p * 16;
-  __shared__ cplx Gp[4][256];
-  dv4 gr = {0.0, 0.0, 0.0, 0.0}, gi = {0.0, 0.0, 0.0, 0.0};
-  // V is zero above row 16 p; this wave's 4-row slices sl = 4 p + w + 4 q
-  // (at most 12 for m <= 192), every load issued before the products
-  constexpr int MAXQ = 12;
-  cplx v[MAXQ];
-#pragma unroll
-  for (int q = 0; q < MAXQ; ++q) {
-    const int row = 4 * (4 * p + w + 4 * q) + rq;
-    const cplx t = V[(long)min(row, m - 1) * 16 + cl];
-    v[q] = make_double2(row < m ? t.x : 0.0, row < m ? t.y : 0.0);
-  }
-#pragma unroll
-  for (int q = 0; q < MAXQ; ++q) {
-    gr = mfma(v[q].x, v[q].x, gr);
-    gr = mfma(v[q].y, v[q].y, gr);
-    gi = mfma(v[q].x, v[q].y, gi);
-    gi = mfma(-v[q].y, v[q].x, gi);
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r) Gp[w][(4 * r + rq) * 16 + cl] = make_double2(gr[r], gi[r]);
-  __syncthreads();
-  if (tid < 16) {
-    const int i = tid;
-    cplx t[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const cplx tj = tau[j];
-      cplx acc = cz();
-#pragma unroll
-      for (int c = 0; c < j; ++c) {
-        const int e = c * 16 + j;
-        const cplx g = make_double2(Gp[0][e].x + Gp[1][e].x + Gp[2][e].x + Gp[3][e].x,
-                                    Gp[0][e].y + Gp[1][e].y + Gp[2][e].y + Gp[3][e].y);
-        acc.x += t[c].x * g.x - t[c].y * g.y;
-        acc.y += t[c].x * g.y + t[c].y * g.x;
-      }
-      const cplx tn = cmul(make_double2(-tj.x, -tj.y), acc);
-      t[j] = i < j ? tn : (i == j ? tj : cz());
-    }
-#pragma unroll
-    for (int j = 0; j < 16; ++j) T[i * 16 + j] = t[j];
-  }
-}
 
 template <int RB, int RPL>
 bool try_qr_formq1(int batch, int m, int n, const MatOut& Q, cplx* ws, hipStream_t s) {
   constexpr int MR = RB * 4 * RPL;
   const int k = m < n ? m : n, np = (k + 15) / 16;
   if (m > MR) return false;
-  const size_t shm = (size_t)(MR * VST + RB * 256) * sizeof(cplx);
+  // V rows, W partials, and the Gram and T of up to np panels
+  const size_t shm = (size_t)(MR * VST + RB * 256 + 2 * 6 * 256) * sizeof(cplx);
+  if (np > 6) return false;
   static const bool attr = [&]() {
     check(hipFuncSetAttribute((const void*)k_qr_formq1<RB, RPL>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm),
@@ -607,9 +615,6 @@ bool qr_blk_cg(int batch, int m, int n, const MatView& A, const MatOut& R, const
 bool qr_form_q(int batch, int m, int n, MatOut Q, cplx* ws, hipStream_t s) {
   if (batch <= 0 || m <= 0 || n <= 0) return true;
   if (m < n || n <= 16 || n > 96 || m > 192) return false;
-  const int np = (n + 15) / 16;
-  hipLaunchKernelGGL(k_qr_tbuild, dim3(np, batch), dim3(256), 0, s, m, n, ws, (long)qr_ws_per_matrix(m, n));
-  check(hipGetLastError(), "qr_tbuild launch");
   return qr_formq_split(batch, m, n, Q, ws, s);
 }
 
