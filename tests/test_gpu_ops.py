@@ -118,12 +118,12 @@ def test_sfft_apply(ctx, flags):
         assert rel(dense(yc, b).reshape(6, N, N, N), ref) < 1e-11
 
 
-def test_sfft_materialised_row_walk(ctx):
-    """Materialised SFFT product on ranks up to 128 (product rows of up to
-    256 entries, bond ranks 6, 12, 24, 48, 96 that do not divide the
-    workgroup size: the row walk's carry), batch of two, against the library
-    FFT at bit-reversed indices; rows wider than a workgroup are covered at
-    full size (rank 640)."""
+def test_sfft_materialised_ranks_128(ctx):
+    """Materialised SFFT product on ranks up to 128 (product bonds up to
+    256, bond ranks 6, 12, 24, 48, 96 that do not divide the workgroup
+    size, so threads of one workgroup span several output columns), batch
+    of two, against the library FFT at bit-reversed indices; the rank-640
+    product is covered at full size."""
     n = 4
     N = 1 << n
     rng = np.random.default_rng(15)
