@@ -26,7 +26,9 @@
 // Q = H_0 H_1 ... [I; 0] is formed afterwards in reverse panel order with
 // the same block products (W = V^H Q, W <- T W, Q <- Q - V W) from V and T
 // kept in the workspace; a column group of Q only meets the reflectors of
-// panels at or before its own.
+// panels at or before its own.  k_qr_formq1 forms Q alone (one workgroup
+// per column group, T rebuilt in LDS from V and tau) after the unblocked
+// register QR of kernels_fact.hip has written the vectors.
 #include "fact_device.h"
 
 #include <stdexcept>
