@@ -175,22 +175,18 @@ struct qtt_ctx {
   // sub-context reads the parent's operators
   const qtt_ctx* parent = nullptr;
   std::vector<std::unique_ptr<qtt_ctx>> subs;
+  // every context (a group's sub-context too) drains and releases its own
+  // stream last, after its sub-contexts, events and span slots
   ~qtt_ctx() {
-    for (auto& sc : subs) {
-      if (sc->stream) (void)hipStreamSynchronize(sc->stream);
-      if (sc->own_stream && sc->stream) (void)hipStreamDestroy(sc->stream);
-      sc->own_stream = false;
-    }
     subs.clear();
+    if (stream) (void)hipStreamSynchronize(stream);
     for (auto& r : pending) {
       if (r.a) (void)hipEventDestroy(r.a);
       if (r.b) (void)hipEventDestroy(r.b);
     }
     for (auto e : evfree) (void)hipEventDestroy(e);
-    if (span) {
-      if (stream) (void)hipStreamSynchronize(stream);
-      (void)hipFree(span);
-    }
+    if (span) (void)hipFree(span);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };
 
@@ -1669,7 +1665,7 @@ int qtt_create(int device, void* hip_stream, qtt_ctx** out) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return QTT_EINVAL;
     check(hipSetDevice(device), "set device");
-    auto* c = new qtt_ctx();
+    auto c = std::make_unique<qtt_ctx>();
     c->device = device;
     if (hip_stream) {
       c->stream = (hipStream_t)hip_stream;
@@ -1679,7 +1675,7 @@ int qtt_create(int device, void* hip_stream, qtt_ctx** out) {
     }
     c->pool = std::make_shared<Pool>();
     c->pool->device = device;
-    *out = c;
+    *out = c.release();
     return QTT_OK;
   } catch (...) {
     return QTT_EHIP;
@@ -1690,8 +1686,7 @@ int qtt_destroy(qtt_ctx* c) {
   if (!c) return QTT_EINVAL;
   (void)hipStreamSynchronize(c->stream);
   c->ident.clear();
-  if (c->own_stream) (void)hipStreamDestroy(c->stream);
-  delete c;
+  delete c;  // the destructor releases the stream
   return QTT_OK;
 }
 
