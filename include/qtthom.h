@@ -71,11 +71,15 @@ typedef struct qtt_tensor qtt_tensor;
 /* Problem statement: the corrector problem of Sec. 2 on a voxel grid. */
 typedef struct qtt_problem {
     int n;                   /* bits per axis, N = 2^n, 1 <= n <= 10       */
-    const uint8_t* phase;    /* host, N^3 phase ids, C order, x slowest    */
+    const uint8_t* phase;    /* N^3 phase ids, C order, x slowest; host
+                                memory unless phase_on_device              */
     int nphase;              /* number of phases, 1..16                    */
     const double* lame;      /* host, [nphase][2] = (lambda, mu)           */
     double lame0[2];         /* reference medium (lambda0, mu0)            */
     int load_mask;           /* bit k set: solve unit load case e_k        */
+    int phase_on_device;     /* nonzero: `phase` is device memory of the
+                                context's device (read, never written or
+                                kept beyond the call)                      */
 } qtt_problem;
 
 typedef struct qtt_solve_opts {
@@ -92,6 +96,15 @@ typedef struct qtt_solve_opts {
                                 in ls_adjoint also the number of groups of
                                 the adjoint fixed point and of the gradient
                                 terms; ls_batch_solve ignores it          */
+    double* history;         /* host, optional (NULL: none), written by
+                                ls_solve and ls_solve_prepared: entry
+                                [k * history_len + m] receives the relative
+                                update ||eps_{m+1} - eps_m|| / ||E|| of load
+                                case k after update m + 1 (the stopping
+                                test of Alg. 2), NaN where load case k made
+                                no such update; ls_adjoint and
+                                qtt_batch_solve leave it untouched          */
+    int history_len;         /* entries per load case in `history`         */
 } qtt_solve_opts;
 
 typedef struct qtt_report {
@@ -134,6 +147,42 @@ int qtt_tensor_to_host(qtt_ctx* ctx, const qtt_tensor* t, double* data,
                        size_t capacity);
 int qtt_tensor_destroy(qtt_tensor* t);
 
+/* Device-resident trains without a host copy.
+ *
+ * qtt_tensor_create: a batch of `batch` trains (L cores, dims[L], ranks[L+1]
+ * with ranks[0] = ranks[L] = 1) in memory the library allocates on the
+ * context's device, zero-filled; released by qtt_tensor_destroy.
+ *
+ * qtt_tensor_wrap: the same shape over caller-owned DEVICE memory `dev`
+ * of `bytes` bytes holding the cores one after another, each batch-major
+ * (batch, r_{k-1}, d_k, r_k) in interleaved complex doubles (the layout of
+ * qtt_tt_from_host); no copy is made.  QTT_ECAPACITY if `bytes` is smaller
+ * than the cores need, QTT_EINVAL if `dev` is not 16-byte aligned.  The
+ * caller keeps ownership and keeps the memory alive and unmodified while
+ * the handle is used; qtt_tensor_destroy releases the handle only.
+ * Wrapped trains are operands like any other (products, tt_round, ls_*);
+ * an operation that replaces cores (tt_round in place) re-points the
+ * handle to library memory and leaves the caller's buffer as it was.
+ *
+ * qtt_tensor_core: device address and size in bytes of core k of a train
+ * (all batch elements), valid until the handle is destroyed or its cores
+ * are replaced.
+ *
+ * qtt_tensor_export: device-to-device copy of all cores of a train, in the
+ * qtt_tt_from_host layout, into caller DEVICE memory `dev` of `bytes`
+ * bytes (QTT_ECAPACITY if too small); ordered on the context's stream and
+ * complete when the call returns.
+ *
+ * These are how torch-owned device buffers enter and leave the library
+ * (the caller's allocator owns the memory). */
+int qtt_tensor_create(qtt_ctx* ctx, int L, const int* dims, const int* ranks,
+                      int batch, qtt_tensor** out);
+int qtt_tensor_wrap(qtt_ctx* ctx, int L, const int* dims, const int* ranks,
+                    int batch, void* dev, size_t bytes, qtt_tensor** out);
+int qtt_tensor_core(const qtt_tensor* t, int k, void** dev, size_t* bytes);
+int qtt_tensor_export(qtt_ctx* ctx, const qtt_tensor* t, void* dev,
+                      size_t bytes);
+
 /* Constant strain field of each batch element: E[b][6] (host); rank-1
  * train of Sec. 4.3 (constant operands). */
 int qtt_const_strain(qtt_ctx* ctx, int n, int batch, const double* E,
@@ -141,18 +190,26 @@ int qtt_const_strain(qtt_ctx* ctx, int n, int batch, const double* E,
 
 /* ---- operators (Sec. 4) ------------------------------------------------ */
 /* SFFT operator: the reduced QFT Q_n of Sec. 4.1 (QFT circuit without the
- * final SWAPs) on each spatial axis, identity on the Voigt core, built by
- * contracting the circuit's gates into a TTO with SVD truncation at
- * `delta` (Zip-Up, Sec. 4.2).  On one axis, S maps the voxel index j to
- * the momentum index k with weight N^-1/2 exp(+2 pi i j rev_n(k) / N). */
+ * final SWAPs) on each spatial axis, identity on the Voigt core.  Built on
+ * the host by contracting the circuit layer by layer (the Hadamard gate,
+ * then the controlled phases carried on a bond of dimension 2) with SVD
+ * truncation at `delta` after each layer; the paper's Zip-Up (Sec. 4.2)
+ * yields the same operator.  On one axis, S maps the voxel index j to the
+ * momentum index k with weight N^-1/2 exp(+2 pi i j rev_n(k) / N). */
 int qtt_sfft_build(qtt_ctx* ctx, int n, double delta, qtt_tensor** S);
 
 /* Green operator Gamma_0 of App. A (direct scheme, k = i q) for the
  * isotropic reference medium (lam0, mu0), Nyquist-symmetrised, in the SFFT
  * momentum convention of Sec. 4.3 (indices reversed per axis, then complex
- * conjugated).  It is held in the separable form of App. D
- * (eq. green_separability): Gamma = (1/mu0) h A - c h^2 B with
- * h = 1/|xi|^2 and polynomial Voigt operators A, B, each a raised TTO. */
+ * conjugated).  It is held as four raised operators that share the spatial
+ * cores of the unit direction n = xi/|xi| (n = 0 at xi = 0), each bounded by
+ * one pointwise, so truncation errors are not amplified between them:
+ * u_j = tau_jk n_k, s = n . u, q = u / (2 mu0) - (c/2) n s and
+ * eps = sym(n (x) q) with c = (lam0 + mu0) / (mu0 (lam0 + 2 mu0)), which
+ * is the closed form of eq. orig_green_eshelby for isotropic C0 (the
+ * separable split of App. D with its 1/|xi|^2 factors cancelled).  The two
+ * Nyquist representatives of a frequency carry a direction each (joint
+ * control index), averaged in the last map. */
 int qtt_green_build(qtt_ctx* ctx, int n, double lam0, double mu0,
                     double delta, qtt_tensor** G);
 
@@ -288,13 +345,18 @@ int qtt_zgemm(qtt_ctx* ctx, int opA, int opB, int M, int N, int K,
  * kernels (m <= 256, n <= 128), 4: the two-columns-per-lane register
  * kernel (n <= 96), 5: the one-wave-per-column-group kernel for R (m <=
  * 160, n <= 96) with Q from the matrix-core block reflectors (Q needs
- * m >= n > 16); QTT_EINVAL when the forced path does not cover the shape.
+ * m >= n > 16), 6: the workspace-resident blocked kernel with trailing
+ * updates and Q formation on the matrix cores (m >= n, m <= 320, n <= 160;
+ * the library's choice beyond 192 rows or 96 columns); QTT_EINVAL when the
+ * forced path does not cover the shape.
  * Synchronises the stream before returning.
  *
- * qtt_zjacobi: one-sided Jacobi of batch n x n matrices A (n <= 96):
+ * qtt_zjacobi: one-sided Jacobi of batch n x n matrices A (n <= 160):
  * A V = U diag(S) with U (n x n) orthonormal columns for the nonzero S
  * (zero columns otherwise) and S (batch x n) descending; V is not formed.
- * QTT_EINVAL for n > 96. */
+ * Up to n = 96 the matrix is held in LDS; beyond, its first columns stay
+ * in LDS and the rest live in a library workspace.  QTT_EINVAL for
+ * n > 160. */
 int qtt_zqr(qtt_ctx* ctx, int batch, int m, int n, const void* A, void* R,
             void* Q, int path);
 int qtt_zjacobi(qtt_ctx* ctx, int batch, int n, const void* A, void* U,

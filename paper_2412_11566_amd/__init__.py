@@ -26,7 +26,8 @@ __all__ = [
     "tt_from_cores", "const_strain", "sfft_build", "green_build", "from_voxels",
     "sfft_apply", "tt_hadamard", "green_apply", "tt_round", "tt_norm", "tt_axpby",
     "tt_mean_apply", "ls_solve", "ls_adjoint", "batch_solve", "Prepared", "prepare",
-    "ls_solve_prepared", "stats_enable", "stats_get", "stats_reset",
+    "ls_solve_prepared", "stats_enable", "stats_get", "stats_reset", "tensor_create",
+    "tensor_wrap", "tensor_export", "NotConvergedWarning",
     "QTT_EXACT", "QTT_INVERSE", "QTT_NO_ROUND", "QTT_PREC_FP32", "QTT_PREC_FP64",
 ]
 
@@ -35,6 +36,10 @@ class QttError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"qtthom error {_c.ERR_NAMES.get(code, code)}: {msg}")
         self.code = code
+
+
+class NotConvergedWarning(RuntimeWarning):
+    """A fixed point (forward or adjoint) stopped at max_iter."""
 
 
 def _dp(a: np.ndarray):
@@ -112,6 +117,10 @@ class Tensor:
     def ranks(self):
         return self.shape()["ranks"]
 
+    def nbytes(self) -> int:
+        """Bytes of all cores (the qtt_tt_from_host layout)."""
+        return 16 * int(_c.lib().qtt_tensor_size(self.h))
+
     def cores(self):
         """Host copies: trains -> list of (B, r0, d, r1); operators -> (r0, dout, din, r1)."""
         s = self.shape()
@@ -146,6 +155,48 @@ def tt_from_cores(ctx: Context, cores) -> Tensor:
     ranks = np.array([cores[0].shape[1]] + [c.shape[3] for c in cores], np.int32)
     data = np.concatenate([c.ravel() for c in cores]).view(np.float64)
     return _new(ctx, _c.lib().qtt_tt_from_host, len(cores), _ip(dims), _ip(ranks), B, _dp(data))
+
+
+def _train_shape(dims, ranks):
+    dims = np.ascontiguousarray(dims, dtype=np.int32)
+    ranks = np.ascontiguousarray(ranks, dtype=np.int32)
+    if ranks.shape[0] != dims.shape[0] + 1:
+        raise ValueError("ranks must have len(dims) + 1 entries")
+    return dims, ranks
+
+
+def tensor_create(ctx: Context, dims, ranks, batch: int = 1) -> Tensor:
+    """Zero-filled trains in library device memory (qtt_tensor_create)."""
+    d, r = _train_shape(dims, ranks)
+    return _new(ctx, _c.lib().qtt_tensor_create, len(d), _ip(d), _ip(r), int(batch))
+
+
+def tensor_wrap(ctx: Context, buf, dims, ranks, batch: int = 1) -> Tensor:
+    """Trains over a caller-owned device buffer (qtt_tensor_wrap): ``buf`` is
+    a contiguous complex128 torch device tensor holding the cores one after
+    another, each (batch, r_{k-1}, d_k, r_k).  No copy; the returned handle
+    keeps a reference to ``buf``."""
+    import torch
+    if buf.dtype != torch.complex128 or not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("tensor_wrap: a contiguous complex128 device tensor")
+    d, r = _train_shape(dims, ranks)
+    t = _new(ctx, _c.lib().qtt_tensor_wrap, len(d), _ip(d), _ip(r), int(batch),
+             C.c_void_p(buf.data_ptr()), buf.numel() * 16)
+    t._owner = buf
+    return t
+
+
+def tensor_export(ctx: Context, t: Tensor, out=None):
+    """All cores of a train copied device-to-device into a complex128 torch
+    tensor (qtt_tensor_export); returns that tensor (flat)."""
+    import torch
+    n = int(_c.lib().qtt_tensor_size(t.h))
+    if out is None:
+        out = torch.empty(n, dtype=torch.complex128, device="cuda")
+    if out.dtype != torch.complex128 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("tensor_export: a contiguous complex128 device tensor")
+    ctx.check(_c.lib().qtt_tensor_export(ctx.h, t.h, C.c_void_p(out.data_ptr()), out.numel() * 16))
+    return out
 
 
 def const_strain(ctx: Context, n: int, E) -> Tensor:
@@ -230,10 +281,18 @@ class SolveOptions:
     exact: bool = False
     seed: int = 0
     streams: int = 1
+    # entries of the per-load-case residual history to record (0: none)
+    history: int = 0
 
     def c(self) -> _c.SolveOpts:
-        return _c.SolveOpts(self.delta, self.tol, self.cap, self.max_iter, self.precision,
-                            self.oversample, int(self.exact), self.seed, self.streams)
+        o = _c.SolveOpts(self.delta, self.tol, self.cap, self.max_iter, self.precision,
+                         self.oversample, int(self.exact), self.seed, self.streams)
+        if self.history > 0:
+            buf = np.zeros(6 * self.history)
+            o.history = _dp(buf)
+            o.history_len = self.history
+            o._hist = buf  # kept alive with the struct
+        return o
 
 
 @dataclass
@@ -245,22 +304,40 @@ class SolveReport:
     status: int
     seconds_setup: float
     seconds_solve: float
+    # (6, history) relative updates per load case, NaN past the last
+    # update (SolveOptions.history > 0 only)
+    history: np.ndarray | None = None
 
 
 def _problem(phase, lame, lame0, load_mask):
-    phase = np.ascontiguousarray(phase, dtype=np.uint8)
-    n = int(round(np.log2(phase.shape[0])))
-    if phase.shape != (1 << n,) * 3:
+    """qtt_problem from a host array or a torch uint8 device tensor (then
+    the library reads the voxels from device memory)."""
+    on_dev = not isinstance(phase, np.ndarray) and getattr(phase, "is_cuda", False)
+    if on_dev:
+        import torch
+        if phase.dtype != torch.uint8 or not phase.is_contiguous():
+            raise ValueError("device phase: a contiguous uint8 tensor")
+        shape = tuple(phase.shape)
+        ptr = C.cast(C.c_void_p(phase.data_ptr()), C.POINTER(C.c_uint8))
+    else:
+        phase = np.ascontiguousarray(phase, dtype=np.uint8)
+        shape = phase.shape
+        ptr = phase.ctypes.data_as(C.POINTER(C.c_uint8))
+    n = int(round(np.log2(shape[0])))
+    if shape != (1 << n,) * 3:
         raise ValueError("phase must be a cubic array with side 2**n")
     lame = np.ascontiguousarray(lame, dtype=np.float64)
-    p = _c.Problem(n, phase.ctypes.data_as(C.POINTER(C.c_uint8)), lame.shape[0], _dp(lame),
-                   (C.c_double * 2)(*lame0), load_mask)
+    p = _c.Problem(n, ptr, lame.shape[0], _dp(lame), (C.c_double * 2)(*lame0), load_mask,
+                   int(on_dev))
     return p, (phase, lame)
 
 
-def _report(r: _c.Report) -> SolveReport:
+def _report(r: _c.Report, o: _c.SolveOpts | None = None) -> SolveReport:
+    h = None
+    if o is not None and getattr(o, "_hist", None) is not None:
+        h = o._hist.reshape(6, -1).copy()
     return SolveReport(list(r.iterations), list(r.residual), r.max_rank, r.discarded, r.status,
-                       r.seconds_setup, r.seconds_solve)
+                       r.seconds_setup, r.seconds_solve, h)
 
 
 def ls_solve(ctx: Context, phase, lame, lame0, opts: SolveOptions, load_mask: int = 0x3F,
@@ -275,7 +352,7 @@ def ls_solve(ctx: Context, phase, lame, lame0, opts: SolveOptions, load_mask: in
                            C.byref(eps) if keep_eps else None)
     ctx.check(rc, allow=(QTT_ENOCONV,))
     del keep
-    return Ceff.reshape(6, 6), _report(rep), (Tensor(ctx, eps) if keep_eps else None)
+    return Ceff.reshape(6, 6), _report(rep, o), (Tensor(ctx, eps) if keep_eps else None)
 
 
 def ls_adjoint(ctx: Context, phase, lame, lame0, opts: SolveOptions, eps: Tensor, gbar=None):
@@ -346,7 +423,7 @@ def ls_solve_prepared(ctx: Context, prep: Prepared, opts: SolveOptions, keep_eps
     rc = _c.lib().ls_solve_prepared(ctx.h, prep.h, C.byref(o), _dp(Ceff), C.byref(rep),
                                     C.byref(eps) if keep_eps else None)
     ctx.check(rc, allow=(QTT_ENOCONV,))
-    return Ceff.reshape(6, 6), _report(rep), (Tensor(ctx, eps) if keep_eps else None)
+    return Ceff.reshape(6, 6), _report(rep, o), (Tensor(ctx, eps) if keep_eps else None)
 
 
 def stats_enable(ctx: Context, on=True):
@@ -466,34 +543,55 @@ def ls_adjoint_prepared(ctx: Context, prep: Prepared, opts: SolveOptions, eps: T
     return out, _report(rep)
 
 
+def _not_converged(what: str, rep: SolveReport, policy: str):
+    if rep.status == QTT_OK or policy == "ignore":
+        return
+    msg = (f"{what} fixed point stopped at max_iter (status {rep.status}); "
+           f"iterations {rep.iterations}, last relative updates {rep.residual}")
+    if policy == "raise":
+        raise QttError(rep.status, msg)
+    import warnings
+    warnings.warn(msg, NotConvergedWarning, stacklevel=3)
+
+
 def _autograd_function():
     import torch
 
     class CeffFn(torch.autograd.Function):
         """C_eff as a differentiable function of the phase Lame parameters.
 
-        forward(lame (nphase, 2) float64 tensor, phase, lame0, ctx, opts)
-        -> C_eff (6, 6) float64.  The forward solve keeps its strain
-        trains; backward runs the adjoint LS solve (ls_adjoint_prepared)
-        with the incoming cotangent and returns dL/dlame.  The reference
-        medium lame0 is held fixed (not differentiated)."""
+        forward(lame (nphase, 2) float64 tensor, phase, lame0, ctx, opts,
+        policy, reports) -> C_eff (6, 6) float64.  The forward solve keeps
+        its strain trains; backward runs the adjoint LS solve
+        (ls_adjoint_prepared) with the incoming cotangent and returns
+        dL/dlame.  The reference medium lame0 is held fixed (not
+        differentiated).  The gradient is that of the converged fixed point
+        (energy/adjoint form), so a forward or adjoint solve that stopped
+        at max_iter is reported by ``policy``: "raise" (QttError),
+        "warn" (NotConvergedWarning) or "ignore".  ``reports`` (a dict) receives
+        the forward report under "forward" and the adjoint one under
+        "adjoint"."""
 
         @staticmethod
-        def forward(actx, lame, phase, lame0, qctx, opts):
+        def forward(actx, lame, phase, lame0, qctx, opts, policy, reports):
             lam = lame.detach().cpu().numpy().astype(np.float64)
             prep = prepare(qctx, phase, lam, lame0, opts.delta)
             Ceff, rep, eps = ls_solve_prepared(qctx, prep, opts, keep_eps=True)
-            actx.saved = (qctx, prep, opts, eps, lame.shape, lame.dtype, lame.device)
-            actx.report = rep
+            reports["forward"] = rep
+            _not_converged("forward", rep, policy)
+            actx.saved = (qctx, prep, opts, eps, lame.shape, lame.dtype, lame.device, policy,
+                          reports)
             return torch.as_tensor(Ceff, dtype=torch.float64, device=lame.device)
 
         @staticmethod
         def backward(actx, gC):
-            qctx, prep, opts, eps, shape, dtype, device = actx.saved
+            qctx, prep, opts, eps, shape, dtype, device, policy, reports = actx.saved
             g = gC.detach().cpu().numpy().astype(np.float64)
-            grad, _ = ls_adjoint_prepared(qctx, prep, opts, eps, gbar=g)
+            grad, arep = ls_adjoint_prepared(qctx, prep, opts, eps, gbar=g)
+            reports["adjoint"] = arep
+            _not_converged("adjoint", arep, policy)
             return (torch.as_tensor(grad.reshape(shape), dtype=dtype, device=device),
-                    None, None, None, None)
+                    None, None, None, None, None, None)
 
     return CeffFn
 
@@ -501,10 +599,19 @@ def _autograd_function():
 _CeffFn = None
 
 
-def ceff(lame, phase, lame0, ctx: Context, opts: SolveOptions):
+def ceff(lame, phase, lame0, ctx: Context, opts: SolveOptions, on_noconv: str = "raise"):
     """Differentiable C_eff: ``ceff(lame_tensor, ...)`` returns a (6, 6)
-    torch tensor whose backward is the adjoint solve."""
+    torch tensor whose backward is the adjoint solve.  ``on_noconv``:
+    "raise", "warn" or "ignore" when the forward or adjoint fixed point
+    stops at max_iter.  The returned tensor carries ``qtt_reports``, a dict
+    with the forward report ("forward") and, after backward, the adjoint
+    report ("adjoint")."""
     global _CeffFn
+    if on_noconv not in ("raise", "warn", "ignore"):
+        raise ValueError("on_noconv: 'raise', 'warn' or 'ignore'")
     if _CeffFn is None:
         _CeffFn = _autograd_function()
-    return _CeffFn.apply(lame, phase, lame0, ctx, opts)
+    reports = {"forward": None, "adjoint": None}
+    out = _CeffFn.apply(lame, phase, lame0, ctx, opts, on_noconv, reports)
+    out.qtt_reports = reports
+    return out

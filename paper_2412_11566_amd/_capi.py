@@ -37,13 +37,14 @@ ERR_NAMES = {QTT_EINVAL: "EINVAL", QTT_ENOMEM: "ENOMEM", QTT_ECAPACITY: "ECAPACI
 class Problem(C.Structure):
     _fields_ = [("n", C.c_int), ("phase", C.POINTER(C.c_uint8)), ("nphase", C.c_int),
                 ("lame", C.POINTER(C.c_double)), ("lame0", C.c_double * 2),
-                ("load_mask", C.c_int)]
+                ("load_mask", C.c_int), ("phase_on_device", C.c_int)]
 
 
 class SolveOpts(C.Structure):
     _fields_ = [("delta", C.c_double), ("tol", C.c_double), ("cap", C.c_int),
                 ("max_iter", C.c_int), ("precision", C.c_int), ("oversample", C.c_int),
-                ("exact", C.c_int), ("seed", C.c_uint64), ("streams", C.c_int)]
+                ("exact", C.c_int), ("seed", C.c_uint64), ("streams", C.c_int),
+                ("history", C.POINTER(C.c_double)), ("history_len", C.c_int)]
 
 
 class Report(C.Structure):
@@ -70,6 +71,10 @@ SIGNATURES = {
     "qtt_tensor_size": (C.c_size_t, [P]),
     "qtt_tensor_to_host": (I, [P, P, DP, C.c_size_t]),
     "qtt_tensor_destroy": (I, [P]),
+    "qtt_tensor_create": (I, [P, I, IP, IP, I, PP]),
+    "qtt_tensor_wrap": (I, [P, I, IP, IP, I, P, C.c_size_t, PP]),
+    "qtt_tensor_core": (I, [P, I, PP, C.POINTER(C.c_size_t)]),
+    "qtt_tensor_export": (I, [P, P, P, C.c_size_t]),
     "qtt_const_strain": (I, [P, I, I, DP, PP]),
     "qtt_sfft_build": (I, [P, I, D, PP]),
     "qtt_green_build": (I, [P, I, D, D, D, PP]),

@@ -74,12 +74,19 @@ struct Pool {
   void put(void* p, size_t c) { freel.emplace(c, p); }
   // live allocations (start -> requested bytes), for host-side bounds checks
   std::map<uintptr_t, size_t> live;
+  // caller-owned device ranges wrapped as tensors (qtt_tensor_wrap); the
+  // same range may be wrapped more than once
+  std::multimap<uintptr_t, size_t> ext;
   bool contains(const void* p, size_t bytes) const {
     const uintptr_t a = (uintptr_t)p;
     auto it = live.upper_bound(a);
-    if (it == live.begin()) return false;
-    --it;
-    return a >= it->first && a + bytes <= it->first + it->second;
+    if (it != live.begin()) {
+      --it;
+      if (a >= it->first && a + bytes <= it->first + it->second) return true;
+    }
+    for (const auto& kv : ext)
+      if (a >= kv.first && a + bytes <= kv.first + kv.second) return true;
+    return false;
   }
 };
 
@@ -87,12 +94,23 @@ struct Buf {
   std::shared_ptr<Pool> pool;
   void* p = nullptr;
   size_t c = 0;
+  bool ext = false;  // caller-owned range: registered, never freed
   Buf(std::shared_ptr<Pool> pl, size_t bytes) : pool(std::move(pl)) {
     p = pool->get(bytes, c);
     pool->live[(uintptr_t)p] = bytes;
   }
+  Buf(std::shared_ptr<Pool> pl, void* extp, size_t bytes) : pool(std::move(pl)), p(extp), c(bytes), ext(true) {
+    pool->ext.emplace((uintptr_t)p, bytes);
+  }
   ~Buf() {
-    if (p) {
+    if (ext) {
+      auto r = pool->ext.equal_range((uintptr_t)p);
+      for (auto it = r.first; it != r.second; ++it)
+        if (it->second == c) {
+          pool->ext.erase(it);
+          break;
+        }
+    } else if (p) {
       pool->live.erase((uintptr_t)p);
       pool->put(p, c);
     }
@@ -105,6 +123,13 @@ using BufP = std::shared_ptr<Buf>;
 }  // namespace qtt
 
 using qtt::cplx;
+
+namespace qtt {
+// a NaN or Inf met in a norm or residual (QTT_ENAN at the ABI)
+struct nan_error : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+}  // namespace qtt
 
 struct qtt_tensor {
   int kind = 0;  // 0 train, 1 operator, 2 Green operator (factored)
@@ -490,6 +515,24 @@ static int choose_rank(std::vector<double>& S, int B, int kk, const std::vector<
   return rmax;
 }
 
+// One-sided Jacobi of B square n x n matrices (n <= 160): the LDS kernel
+// up to 96, the LDS + workspace kernel beyond.
+static void jacobi_any(const Ctx& X, int B, int n, MatView A, MatOut U, double* S) {
+  need(X, A.base, span2(n, n, A.rs, A.cs) + (long)(B - 1) * A.sb, "jac in");
+  need(X, U.base, span2(n, n, U.rs, U.cs) + (long)(B - 1) * U.sb, "jac U");
+  need(X, S, (long)B * n - 1, "jac S", sizeof(double));
+  hipEvent_t e = X.t0();
+  bool ok;
+  if (n <= 96) {
+    ok = jacobi_square(B, n, A, U, S, X.s());
+  } else {
+    auto ws = X.buf(jacobi_ws(B, n));
+    ok = jacobi_big(B, n, A, U, S, (cplx*)ws->p, X.s());
+  }
+  if (!ok) throw std::logic_error("jacobi size");
+  X.t1(e, QTT_K_JACOBI, B * 4.0 * 22.0 * (double)n * n * n, 16.0 * B * 2.0 * n * n);
+}
+
 static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* st) {
   const int L = y.L, B = y.B;
   std::vector<double> nrm(B);
@@ -499,6 +542,8 @@ static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* 
     check(hipMemcpyAsync(nrm.data(), nb->p, B * sizeof(double), hipMemcpyDeviceToHost, X.s()), "norm d2h");
     X.sync();
   }
+  for (int b = 0; b < B; ++b)
+    if (!std::isfinite(nrm[b])) throw nan_error("NaN/Inf in the norm of a train being rounded");
   std::vector<double> thr(B), disc2(B, 0.0);
   for (int b = 0; b < B; ++b) thr[b] = delta / std::sqrt((double)std::max(L - 1, 1)) * nrm[b];
   for (int k = L - 1; k >= 1; --k) {
@@ -506,7 +551,7 @@ static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* 
     const int kk = std::min(p, q);
     const int rows = y.r[k - 1] * y.dout[k - 1];
     const long msz = (long)p * q;
-    if (kk <= 96 && std::max(p, q) <= 192) {
+    if (kk <= 160 && std::max(p, q) <= 320) {
       // small square factor: R of the tall orientation, Jacobi on it in LDS
       auto R = X.buf((size_t)B * kk * kk);
       auto U = X.buf((size_t)B * kk * kk);
@@ -517,28 +562,16 @@ static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* 
         ck_qr(X, B, q, p, MatView{y.core[k], 1, (long)q, msz, 1},
               MatOut{(cplx*)R->p, (long)kk, 1, (long)kk * kk}, MatOut{nullptr, 0, 0, 0}, (cplx*)ws->p, X.s());
         // Jacobi on R^H: left singular vectors of M
-        need(X, R->p, (long)B * kk * kk - 1, "jac in");
-        need(X, U->p, (long)B * kk * kk - 1, "jac U");
-        need(X, Sd->p, (long)B * kk - 1, "jac S", sizeof(double));
-        hipEvent_t e = X.t0();
-        if (!jacobi_square(B, kk, MatView{(cplx*)R->p, 1, (long)kk, (long)kk * kk, 1},
-                           MatOut{(cplx*)U->p, (long)kk, 1, (long)kk * kk}, (double*)Sd->p, X.s()))
-          throw std::logic_error("jacobi size");
-        X.t1(e, QTT_K_JACOBI, B * 4.0 * 22.0 * (double)kk * kk * kk, 16.0 * B * 2.0 * kk * kk);
+        jacobi_any(X, B, kk, MatView{(cplx*)R->p, 1, (long)kk, (long)kk * kk, 1},
+                   MatOut{(cplx*)U->p, (long)kk, 1, (long)kk * kk}, (double*)Sd->p);
       } else {
         Qb = X.buf((size_t)B * p * q);
         auto ws = X.buf(qr_ws(B, p, q));
         ck_qr(X, B, p, q, MatView{y.core[k], (long)q, 1, msz, 0},
               MatOut{(cplx*)R->p, (long)kk, 1, (long)kk * kk}, MatOut{(cplx*)Qb->p, (long)q, 1, msz},
               (cplx*)ws->p, X.s());
-        need(X, R->p, (long)B * kk * kk - 1, "jac in");
-        need(X, U->p, (long)B * kk * kk - 1, "jac U");
-        need(X, Sd->p, (long)B * kk - 1, "jac S", sizeof(double));
-        hipEvent_t e = X.t0();
-        if (!jacobi_square(B, kk, MatView{(cplx*)R->p, (long)kk, 1, (long)kk * kk, 0},
-                           MatOut{(cplx*)U->p, (long)kk, 1, (long)kk * kk}, (double*)Sd->p, X.s()))
-          throw std::logic_error("jacobi size");
-        X.t1(e, QTT_K_JACOBI, B * 4.0 * 22.0 * (double)kk * kk * kk, 16.0 * B * 2.0 * kk * kk);
+        jacobi_any(X, B, kk, MatView{(cplx*)R->p, (long)kk, 1, (long)kk * kk, 0},
+                   MatOut{(cplx*)U->p, (long)kk, 1, (long)kk * kk}, (double*)Sd->p);
       }
       std::vector<double> S((size_t)B * kk);
       check(hipMemcpyAsync(S.data(), Sd->p, S.size() * sizeof(double), hipMemcpyDeviceToHost, X.s()), "S d2h");
@@ -572,6 +605,35 @@ static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* 
           (long)kk * kk, (long)p * rmax);
         G(X, rows, rmax, p, OP_N, y.core[k - 1], p, OP_N, (cplx*)T->p, rmax, (cplx*)nk1->p, rmax, B,
           (long)rows * p, (long)p * rmax, (long)rows * rmax);
+      }
+      // Row j of W = (U S^-1)^H M carries an error of about
+      // eps * sigma_0 / sigma_j, so with kept singular values far apart the
+      // rows of the new core are no longer orthonormal (the later bonds'
+      // thresholds and the discarded mass assume they are).  Then W is
+      // split as W = R^H Q^H (QR of W^H): the core becomes Q^H, exactly
+      // orthonormal, and R^H moves into the absorbed factor, so the
+      // product (U S) W is unchanged.
+      double spread = 1.0;
+      for (int b = 0; b < B; ++b) {
+        const double s0 = S[(size_t)b * kk];
+        for (int j = 0; j < rmax; ++j) {
+          const double sj = S[(size_t)b * kk + j];
+          if (sj > 0.0) spread = std::max(spread, s0 / sj);
+        }
+      }
+      if (spread > 1e6) {
+        auto Qw = X.buf((size_t)B * q * rmax);
+        auto Rw = X.buf((size_t)B * rmax * rmax);
+        auto ws = X.buf(qr_ws(B, q, rmax));
+        ck_qr(X, B, q, rmax, MatView{(cplx*)nk->p, 1, (long)q, (long)rmax * q, 1},
+              MatOut{(cplx*)Rw->p, (long)rmax, 1, (long)rmax * rmax},
+              MatOut{(cplx*)Qw->p, (long)rmax, 1, (long)q * rmax}, (cplx*)ws->p, X.s());
+        ck_conj_transpose(X, B, q, rmax, MatView{(cplx*)Qw->p, (long)rmax, 1, (long)q * rmax, 0},
+                          MatOut{(cplx*)nk->p, (long)q, 1, (long)rmax * q}, X.s());
+        auto nk2 = X.buf((size_t)B * rows * rmax);
+        G(X, rows, rmax, rmax, OP_N, (cplx*)nk1->p, rmax, OP_C, (cplx*)Rw->p, rmax, (cplx*)nk2->p, rmax,
+          B, (long)rows * rmax, (long)rmax * rmax, (long)rows * rmax);
+        nk1 = nk2;
       }
       X.sync();  // host S buffers are reused next step
       set_core(X, y, k, rmax, y.r[k + 1], nk);
@@ -664,6 +726,8 @@ static std::vector<double> tt_norms(const Ctx& X, const TT& x) {
   std::vector<double> out(B);
   check(hipMemcpyAsync(out.data(), nb->p, B * sizeof(double), hipMemcpyDeviceToHost, X.s()), "norm d2h");
   X.sync();
+  for (int b = 0; b < B; ++b)
+    if (!std::isfinite(out[b])) throw nan_error("NaN/Inf in a train norm");
   return out;
 }
 
@@ -1413,12 +1477,23 @@ struct Ops {
   double lam0 = 0, mu0 = 0;
 };
 
+// The phase array of a problem in host memory (copied from the device when
+// phase_on_device is set; tmp holds the copy).
+static const uint8_t* host_phase(const qtt_problem* P, std::vector<uint8_t>& tmp) {
+  if (!P->phase_on_device) return P->phase;
+  tmp.resize((size_t)1 << (3 * P->n));
+  check(hipMemcpy(tmp.data(), P->phase, tmp.size(), hipMemcpyDeviceToHost), "phase d2h");
+  return tmp.data();
+}
+
 static Ops build_ops(const Ctx& X, const qtt_problem* P, double delta) {
   Ops o;
   const int n = P->n;
   o.S = sfft_cached(X, n, delta);
   o.G = green_cached(X, n, P->lame0[0], P->lame0[1], delta);
-  host::HTT cd = host::stiffness_tto(P->phase, n, P->nphase, P->lame, P->lame0, delta, 0, &o.chi, nullptr);
+  std::vector<uint8_t> tmp;
+  const uint8_t* ph = host_phase(P, tmp);
+  host::HTT cd = host::stiffness_tto(ph, n, P->nphase, P->lame, P->lame0, delta, 0, &o.chi, nullptr);
   o.Cd = upload_op(X, cd);
   o.I = identity_op(X, n);
   o.lam0 = P->lame0[0];
@@ -1435,6 +1510,11 @@ static void check_problem(const qtt_problem* P, const qtt_solve_opts* O) {
     throw std::invalid_argument("bad solve options");
   if (O->precision != QTT_PREC_FP64 && O->precision != QTT_PREC_FP32)
     throw std::invalid_argument("precision must be QTT_PREC_FP64 or QTT_PREC_FP32");
+  if (O->history && O->history_len < 1) throw std::invalid_argument("history without a length");
+  for (int i = 0; i < 2 * P->nphase; ++i)
+    if (!std::isfinite(P->lame[i])) throw std::invalid_argument("non-finite phase modulus");
+  if (!std::isfinite(P->lame0[0]) || !(P->lame0[1] > 0.0) || !(P->lame0[0] + 2.0 * P->lame0[1] > 0.0))
+    throw std::invalid_argument("reference medium must be finite with mu0 > 0, lam0 + 2 mu0 > 0");
 }
 
 struct SolveOut {
@@ -1470,8 +1550,10 @@ static SketchOpts ski(const Ctx& X, const qtt_solve_opts* O) {
   return s;
 }
 
+// hist (host, optional): hist[k * hlen + m] = relative update of load case
+// k after update m + 1 (rows of the load cases in ks only)
 static SolveOut ls_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, const qtt_solve_opts* O,
-                        const std::vector<int>& ks) {
+                        const std::vector<int>& ks, double* hist = nullptr, int hlen = 0) {
   SolveOut out;
   const int n = P->n, B = (int)ks.size();
   out.ks = ks;
@@ -1507,10 +1589,11 @@ static SolveOut ls_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, cons
     bool all = true;
     for (int b = 0; b < B; ++b) {
       const double r = dn[b] / normE;
-      if (!std::isfinite(r)) throw std::runtime_error("NaN/Inf in residual");
+      if (!std::isfinite(r)) throw nan_error("NaN/Inf in the fixed-point residual");
       if (!done[b]) {
         out.iters[b] = m;
         out.res[b] = r;
+        if (hist && m <= hlen) hist[(size_t)ks[b] * hlen + (m - 1)] = r;
         if (r < O->tol) done[b] = 1;
       }
       all = all && done[b];
@@ -1555,6 +1638,7 @@ struct Prepared {
     qtt_problem P;
     P.n = n; P.phase = phase.data(); P.nphase = nphase; P.lame = lame.data();
     P.lame0[0] = lame0[0]; P.lame0[1] = lame0[1]; P.load_mask = load_mask;
+    P.phase_on_device = 0;
     return P;
   }
 };
@@ -1646,9 +1730,12 @@ static int guarded(qtt_ctx* ctx, F&& f) {
   } catch (const std::overflow_error& e) {
     if (ctx) ctx->err = e.what();
     return QTT_EDIVERGED;
+  } catch (const nan_error& e) {
+    if (ctx) ctx->err = e.what();
+    return QTT_ENAN;
   } catch (const std::runtime_error& e) {
     if (ctx) ctx->err = e.what();
-    return std::string(e.what()).find("NaN") != std::string::npos ? QTT_ENAN : QTT_EHIP;
+    return QTT_EHIP;
   } catch (...) {
     if (ctx) ctx->err = "unknown error";
     return QTT_EHIP;
@@ -1785,6 +1872,82 @@ int qtt_tensor_to_host(qtt_ctx* c, const qtt_tensor* t, double* data, size_t cap
 int qtt_tensor_destroy(qtt_tensor* t) {
   delete t;
   return QTT_OK;
+}
+
+// shape of a train from the ABI arrays (ranks[0] = ranks[L] = 1)
+static void tt_spec(int L, const int* dims, const int* ranks, int batch, std::vector<int>& d,
+                    std::vector<int>& r) {
+  if (L < 1 || !dims || !ranks || batch < 1) throw std::invalid_argument("bad train shape");
+  if (ranks[0] != 1 || ranks[L] != 1) throw std::invalid_argument("boundary ranks must be 1");
+  d.assign(dims, dims + L);
+  r.assign(ranks, ranks + L + 1);
+  for (int k = 0; k < L; ++k)
+    if (d[k] < 1 || r[k + 1] < 1) throw std::invalid_argument("bad dims or ranks");
+}
+
+int qtt_tensor_create(qtt_ctx* c, int L, const int* dims, const int* ranks, int batch,
+                      qtt_tensor** out) {
+  if (!c || !out) return QTT_EINVAL;
+  QTT_TRY(c, {
+    Ctx X{c};
+    std::vector<int> d, r;
+    tt_spec(L, dims, ranks, batch, d, r);
+    auto t = new_tt(X, L, batch, d, r);
+    for (int k = 0; k < L; ++k) ck_fill(X, t->core[k], (size_t)batch * t->celems(k), C0(), X.s());
+    X.sync();
+    *out = new qtt_tensor(*t);
+  });
+}
+
+int qtt_tensor_wrap(qtt_ctx* c, int L, const int* dims, const int* ranks, int batch, void* dev,
+                    size_t bytes, qtt_tensor** out) {
+  if (!c || !out || !dev) return QTT_EINVAL;
+  QTT_TRY(c, {
+    std::vector<int> d, r;
+    tt_spec(L, dims, ranks, batch, d, r);
+    if ((uintptr_t)dev % alignof(cplx) != 0) throw std::invalid_argument("wrapped memory not 16-byte aligned");
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, dev) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+        attr.device != c->device)
+      throw std::invalid_argument("wrapped memory is not device memory of the context's device");
+    auto t = std::make_shared<qtt_tensor>();
+    t->kind = 0; t->L = L; t->B = batch; t->dout = d; t->din = d; t->r = r;
+    t->diag.assign(L, 0);
+    t->pool = c->pool;
+    t->core.resize(L);
+    size_t need_b = 0;
+    for (int k = 0; k < L; ++k) need_b += (size_t)batch * t->celems(k) * sizeof(cplx);
+    if (need_b > bytes) throw std::length_error("wrapped memory smaller than the cores");
+    auto reg = std::make_shared<Buf>(c->pool, dev, need_b);
+    size_t off = 0;
+    for (int k = 0; k < L; ++k) {
+      t->core[k] = (cplx*)((char*)dev + off);
+      off += (size_t)batch * t->celems(k) * sizeof(cplx);
+    }
+    t->mem.push_back(reg);
+    *out = new qtt_tensor(*t);
+  });
+}
+
+int qtt_tensor_core(const qtt_tensor* t, int k, void** dev, size_t* bytes) {
+  if (!t || !dev || t->kind != 0 || k < 0 || k >= t->L) return QTT_EINVAL;
+  *dev = t->core[k];
+  if (bytes) *bytes = (size_t)t->B * t->celems(k) * sizeof(cplx);
+  return QTT_OK;
+}
+
+int qtt_tensor_export(qtt_ctx* c, const qtt_tensor* t, void* dev, size_t bytes) {
+  if (!c || !t || !dev || t->kind != 0) return QTT_EINVAL;
+  if (bytes < qtt_tensor_size(t) * sizeof(cplx)) return QTT_ECAPACITY;
+  QTT_TRY(c, {
+    size_t off = 0;
+    for (int k = 0; k < t->L; ++k) {
+      const size_t b = (size_t)t->B * t->celems(k) * sizeof(cplx);
+      check(hipMemcpyAsync((char*)dev + off, t->core[k], b, hipMemcpyDeviceToDevice, c->stream), "export d2d");
+      off += b;
+    }
+    check(hipStreamSynchronize(c->stream), "export sync");
+  });
 }
 
 int qtt_const_strain(qtt_ctx* c, int n, int batch, const double* E, qtt_tensor** out) {
@@ -2020,7 +2183,7 @@ static SolveOut solve_groups(qtt_ctx* c, const Prepared& pr, const qtt_problem* 
   std::vector<SolveOut> outs(ng);
   std::vector<std::array<double, 36>> cg(ng);
   run_groups(c, ng, [&](const Ctx& Xs, int g) {
-    outs[g] = ls_loop(Xs, pr.ops, P, O, groups[g]);
+    outs[g] = ls_loop(Xs, pr.ops, P, O, groups[g], O->history, O->history_len);
     cg[g].fill(0.0);
     ceff_from(Xs, pr.ops, P, outs[g], cg[g].data());
   });
@@ -2056,7 +2219,10 @@ static int solve_prepared(qtt_ctx* c, const Prepared& pr, const qtt_solve_opts* 
     const double t1 = now_s();
     for (int i = 0; i < 36; ++i) Ceff[i] = 0.0;
     const int ng = std::max(1, std::min<int>(O->streams, (int)ks.size()));
-    SolveOut so = ng > 1 ? solve_groups(c, pr, &P, O, ks, ng, Ceff) : ls_loop(X, pr.ops, &P, O, ks);
+    if (O->history)
+      for (size_t e = 0; e < (size_t)6 * O->history_len; ++e) O->history[e] = std::nan("");
+    SolveOut so = ng > 1 ? solve_groups(c, pr, &P, O, ks, ng, Ceff)
+                         : ls_loop(X, pr.ops, &P, O, ks, O->history, O->history_len);
     if (ng == 1) ceff_from(X, pr.ops, &P, so, Ceff);
     X.sync();
     const double t2 = now_s();
@@ -2084,7 +2250,12 @@ static Prepared make_prepared(qtt_ctx* c, const qtt_problem* P, double delta) {
   Prepared pr;
   pr.n = P->n; pr.nphase = P->nphase; pr.load_mask = P->load_mask;
   const size_t NN = (size_t)1 << (3 * P->n);
-  pr.phase.assign(P->phase, P->phase + NN);
+  if (P->phase_on_device) {
+    pr.phase.resize(NN);
+    check(hipMemcpy(pr.phase.data(), P->phase, NN, hipMemcpyDeviceToHost), "phase d2h");
+  } else {
+    pr.phase.assign(P->phase, P->phase + NN);
+  }
   pr.lame.assign(P->lame, P->lame + 2 * P->nphase);
   pr.lame0[0] = P->lame0[0];
   pr.lame0[1] = P->lame0[1];
@@ -2182,7 +2353,7 @@ int qtt_zgemm(qtt_ctx* c, int opA, int opB, int M, int N, int K, const double* a
 }
 
 int qtt_zqr(qtt_ctx* c, int batch, int m, int n, const void* A, void* R, void* Qo, int path) {
-  if (!c || !A || !R || batch < 1 || batch > 65535 || m < 1 || n < 1 || path < 0 || path > 5)
+  if (!c || !A || !R || batch < 1 || batch > 65535 || m < 1 || n < 1 || path < 0 || path > 6)
     return QTT_EINVAL;
   QTT_TRY(c, {
     Ctx X{c};
@@ -2205,6 +2376,9 @@ int qtt_zqr(qtt_ctx* c, int batch, int m, int n, const void* A, void* R, void* Q
     } else if (path == 4) {
       if (!qr_two_col(batch, m, n, av, ro, qo, c->stream))
         throw std::invalid_argument("zqr: shape not covered by the two-column register kernel");
+    } else if (path == 6) {
+      if (!qr_big(batch, m, n, av, ro, qo, (cplx*)ws->p, c->stream))
+        throw std::invalid_argument("zqr: shape not covered by the workspace-resident blocked kernel");
     } else {
       const bool qok = !Qo || (m >= n && n > 16 && n <= 96);
       if (!qok || !qr_one_rowblock(batch, m, n, av, ro, Qo ? (cplx*)ws->p : nullptr, c->stream))
@@ -2219,9 +2393,17 @@ int qtt_zqr(qtt_ctx* c, int batch, int m, int n, const void* A, void* R, void* Q
 int qtt_zjacobi(qtt_ctx* c, int batch, int n, const void* A, void* U, double* S) {
   if (!c || !A || !U || !S || batch < 1 || batch > 65535 || n < 1) return QTT_EINVAL;
   QTT_TRY(c, {
-    if (!jacobi_square(batch, n, MatView{(const cplx*)A, (long)n, 1, (long)n * n, 0},
-                       MatOut{(cplx*)U, (long)n, 1, (long)n * n}, S, c->stream))
-      throw std::invalid_argument("zjacobi: n exceeds the LDS-resident kernel (n <= 96)");
+    const MatView av{(const cplx*)A, (long)n, 1, (long)n * n, 0};
+    const MatOut uo{(cplx*)U, (long)n, 1, (long)n * n};
+    if (n <= 96) {
+      if (!jacobi_square(batch, n, av, uo, S, c->stream)) throw std::logic_error("zjacobi size");
+    } else {
+      if (n > 160) throw std::invalid_argument("zjacobi: n exceeds 160");
+      Ctx X{c};
+      auto ws = X.buf(jacobi_ws(batch, n));
+      if (!jacobi_big(batch, n, av, uo, S, (cplx*)ws->p, c->stream)) throw std::logic_error("zjacobi size");
+      X.sync();  // the workspace is released on return
+    }
   });
 }
 
@@ -2318,7 +2500,7 @@ static AdjOut adj_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, const
     bool all = true;
     for (int b = 0; b < B; ++b) {
       const double r = dn[b] / std::max(nCe[b], 1e-300);
-      if (!std::isfinite(r)) throw std::runtime_error("NaN in adjoint residual");
+      if (!std::isfinite(r)) throw nan_error("NaN/Inf in the adjoint residual");
       if (!done[b]) {
         out.it[b] = m;
         out.res[b] = r;
@@ -2497,7 +2679,9 @@ static int batch_group(qtt_ctx* c, const std::vector<int>& ids, const qtt_proble
             try {
               const qtt_problem& P = Ps[ids[s2]];
               host::HTT chi;
-              cds[s2] = host::stiffness_tto(P.phase, n, P.nphase, P.lame, P.lame0, O->delta, 0, &chi, nullptr);
+              std::vector<uint8_t> tmp;
+              const uint8_t* ph = host_phase(&P, tmp);
+              cds[s2] = host::stiffness_tto(ph, n, P.nphase, P.lame, P.lame0, O->delta, 0, &chi, nullptr);
             } catch (...) {
               errs[s2] = std::current_exception();
             }

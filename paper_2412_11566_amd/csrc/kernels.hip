@@ -291,6 +291,10 @@ size_t qr_ws(int batch, int m, int n) {
 void qr(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
         hipStream_t s) {
   if (batch <= 0 || m <= 0 || n <= 0) return;
+  // beyond what one compute unit holds (more than 192 rows or 96 columns):
+  // the workspace-resident blocked kernel (288 x 144 with Q: 5.2 ms in the
+  // global-memory kernel)
+  if ((m > 192 || n > 96) && qr_big(batch, m, n, A, R, Q, ws, s)) return;
   // the blocked matrix-core kernel beats the unblocked register kernels
   // only beyond 80 columns (192 x 96: 0.72 ms against 1.46 ms with Q;
   // 160 x 80: 0.52 ms against 0.39 ms)

@@ -1465,6 +1465,138 @@ __global__ __launch_bounds__(JNT) void k_jacobi_lds(int n, MatView A, MatOut U, 
   }
 }
 
+// The same one-sided Jacobi for 96 < n <= 160, where the square matrix
+// (up to 400 KB) outgrows the 160 KB of LDS: the first nA columns stay in
+// LDS, the others live in a per-matrix workspace slice (global memory,
+// L2-resident); a column is addressed through a flat pointer to either, so
+// the rotation loop is the LDS kernel's.
+constexpr int JBIGN = 160;
+
+__device__ __forceinline__ cplx* jcol(cplx* Wl, cplx* Wg, int nA, int n, int c) {
+  return c < nA ? Wl + (long)c * n : Wg + (long)(c - nA) * n;
+}
+
+__global__ __launch_bounds__(JNT) void k_jacobi_hyb(int n, int nA, MatView A, MatOut U, double* S,
+                                                    cplx* gws, long gsz) {
+  extern __shared__ cplx Wl[];  // columns [0, nA), column-major
+  __shared__ double nrm2[JBIGN];
+  __shared__ double sig[JBIGN];
+  __shared__ int rankpos[JBIGN];
+  __shared__ int rotated;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int g = tid >> 4, sub = tid & 15;
+  constexpr int NG = JNT / 16;
+  cplx* Wg = gws + (long)b * gsz;  // columns [nA, n)
+  for (int e = tid; e < n * n; e += JNT) {
+    const int i = e % n, j = e / n;
+    jcol(Wl, Wg, nA, n, j)[i] = ldv(A, b, i, j);
+  }
+  __syncthreads();
+  const int npad = n + (n & 1);
+  const int npairs = npad / 2;
+  const double tol = 8.0 * 2.220446049250313e-16 * sqrt((double)n);
+  for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
+    for (int c = tid; c < n; c += JNT) {
+      const cplx* xc = jcol(Wl, Wg, nA, n, c);
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) s += cabs2(xc[i]);
+      nrm2[c] = s;
+    }
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < npad - 1; ++r) {
+      for (int p = g; p < npairs; p += NG) {
+        const int pa = p, pb = npad - 1 - p;
+        int ca = pa == 0 ? 0 : ((pa - 1 + r) % (npad - 1)) + 1;
+        int cb = ((pb - 1 + r) % (npad - 1)) + 1;
+        if (ca >= n || cb >= n) continue;
+        if (ca > cb) { const int t = ca; ca = cb; cb = t; }
+        cplx* xa = jcol(Wl, Wg, nA, n, ca);
+        cplx* xb = jcol(Wl, Wg, nA, n, cb);
+        constexpr int JR = (JBIGN + 15) / 16;
+        cplx va[JR], vb[JR];
+#pragma unroll
+        for (int q = 0; q < JR; ++q) {
+          const int i = min(sub + 16 * q, n - 1);
+          va[q] = xa[i];
+          vb[q] = xb[i];
+        }
+        cplx ga = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < JR; ++q) {
+          if (sub + 16 * q >= n) continue;
+          const cplx t = cdotc(va[q], vb[q]);
+          ga = make_double2(ga.x + t.x, ga.y + t.y);
+        }
+        ga.x = row16_sum(ga.x);
+        ga.y = row16_sum(ga.y);
+        const double al = nrm2[ca], be = nrm2[cb];
+        const double gg2 = cabs2(ga);
+        if (!(gg2 > tol * tol * (al * be)) || al < 1e-300 || be < 1e-300) continue;
+        const double rg = rsq_nt(gg2), gg = gg2 * rg;
+        const double zeta = (be - al) * (0.5 * rg);
+        const double z = fabs(zeta);
+        const bool big = z > 1.0;
+        const double wz = big ? rcp_nt(z) : z;
+        const double s1 = sqrt_nt(fma(wz, wz, 1.0));
+        const double ta = big ? wz * rcp_nt(1.0 + s1) : rcp_nt(z + s1);
+        const double t = zeta >= 0.0 ? ta : -ta;
+        const double cs = rsq_nt(fma(t, t, 1.0)), sn = cs * t;
+        const cplx ph = make_double2(ga.x * rg, -ga.y * rg);
+#pragma unroll
+        for (int q = 0; q < JR; ++q) {
+          const int i = sub + 16 * q;
+          if (i >= n) continue;
+          const cplx u = va[q], wv = cmul(ph, vb[q]);
+          xa[i] = make_double2(cs * u.x - sn * wv.x, cs * u.y - sn * wv.y);
+          xb[i] = make_double2(sn * u.x + cs * wv.x, sn * u.y + cs * wv.y);
+        }
+        if (sub == 0) {
+          nrm2[ca] = al - t * gg;
+          nrm2[cb] = be + t * gg;
+          rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  for (int c = tid; c < n; c += JNT) {
+    const cplx* xc = jcol(Wl, Wg, nA, n, c);
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += cabs2(xc[i]);
+    sig[c] = sqrt(s);
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += JNT) {
+    const double sj = sig[j];
+    int pos = 0;
+    for (int i = 0; i < n; ++i) {
+      const double si = sig[i];
+      pos += (si > sj) || (si == sj && i < j);
+    }
+    rankpos[j] = pos;
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += JNT) S[(long)b * n + rankpos[j]] = sig[j];
+  for (int e = tid; e < n * n; e += JNT) {
+    const int i = e / n, j = e % n;
+    const double sj = sig[j];
+    cplx u = jcol(Wl, Wg, nA, n, j)[i];
+    if (sj > 0.0) { u.x /= sj; u.y /= sj; }
+    else u = make_double2(0.0, 0.0);
+    U.base[b * U.sb + (long)i * U.rs + (long)rankpos[j] * U.cs] = u;
+  }
+}
+
+// columns of an n x n Jacobi matrix that stay in LDS (the rest go to the
+// workspace): as many as 156 KB of dynamic LDS hold
+static int jacobi_lds_cols(int n) {
+  const int c = (int)((156L * 1024) / (16L * n));
+  return c < n ? c : n;
+}
+
 }  // namespace
 
 size_t qr_fast_ws(int batch, int m, int n) {
@@ -1538,6 +1670,29 @@ bool qr_two_col(int batch, int m, int n, MatView A, MatOut R, MatOut Q, hipStrea
                    try_qr_2c<5, 12, 3, 2>(batch, m, n, A, R, Q, s);
     default: return false;
   }
+}
+
+size_t jacobi_ws(int batch, int n) {
+  if (n <= JMAXN) return 0;
+  return (size_t)batch * (size_t)(n - jacobi_lds_cols(n)) * n;
+}
+
+bool jacobi_big(int batch, int n, MatView A, MatOut U, double* S, cplx* ws, hipStream_t s) {
+  if (batch <= 0 || n <= 0) return true;
+  if (n <= JMAXN || n > JBIGN || ws == nullptr) return false;
+  static const bool attr = [&]() {
+    check(hipFuncSetAttribute((const void*)k_jacobi_hyb, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              156 * 1024),
+          "jacobi_hyb lds attribute");
+    return true;
+  }();
+  (void)attr;
+  const int nA = jacobi_lds_cols(n);
+  const size_t shm = (size_t)nA * n * sizeof(cplx);
+  hipLaunchKernelGGL(k_jacobi_hyb, dim3(batch), dim3(JNT), shm, s, n, nA, A, U, S, ws,
+                     (long)(n - nA) * n);
+  check(hipGetLastError(), "jacobi_hyb launch");
+  return true;
 }
 
 bool jacobi_square(int batch, int n, MatView A, MatOut U, double* S, hipStream_t s) {

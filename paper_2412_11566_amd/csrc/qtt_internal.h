@@ -102,11 +102,12 @@ void qr(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
 size_t qr_ws(int batch, int m, int n);
 // per-matrix slice of that workspace: the generic kernel's copy of A and
 // Q (m n + m k + k entries), or V, T and tau of every 16-column panel
-// (np (16 m + 256 + 16) entries: V[np][m][16], T[np][16][16], tau[np][16]),
-// whichever is larger
+// (np (16 m + 256 + 16) entries: V[np][m][16], T[np][16][16], tau[np][16])
+// followed by the large-shape kernel's working copy of A in panel-major
+// order (nc 16 m entries, nc = ceil(n / 16)), whichever is larger
 inline size_t qr_ws_per_matrix(int m, int n) {
-  const long k = m < n ? m : n, np = (k + 15) / 16;
-  const long gen = (long)m * n + (long)m * k + k, blk = np * (16L * m + 256 + 16);
+  const long k = m < n ? m : n, np = (k + 15) / 16, nc = (n + 15) / 16;
+  const long gen = (long)m * n + (long)m * k + k, blk = np * (16L * m + 256 + 16) + nc * 16L * m;
   return (size_t)(gen > blk ? gen : blk);
 }
 // The global-memory kernel behind qr() for shapes the register kernels do
@@ -135,6 +136,12 @@ bool qr_one_rowblock(int batch, int m, int n, const MatView& A, const MatOut& R,
 // block reflectors applied on the matrix cores in reverse panel order;
 // false when the shape is outside the blocked kernel's range.
 bool qr_form_q(int batch, int m, int n, MatOut Q, cplx* ws, hipStream_t s);
+// Blocked QR for large shapes (m >= n, m <= 320, n <= 160): the matrix in
+// the workspace, one workgroup walking over 16-column panels with the
+// trailing updates on the matrix cores, Q formed afterwards from the
+// panels' block reflectors (kernels_qr_big.hip); false when the shape is
+// not covered.  `ws` as for qr().
+bool qr_big(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, hipStream_t s);
 // Unblocked register kernel with two columns per lane (n <= 96).
 bool qr_two_col(int batch, int m, int n, MatView A, MatOut R, MatOut Q, hipStream_t s);
 size_t qr_fast_ws(int batch, int m, int n);
@@ -143,6 +150,11 @@ size_t qr_fast_ws(int batch, int m, int n);
 // LDS: A V = U diag(S) with U orthonormal columns and S descending (V is not
 // formed).  Returns false when n is too large.
 bool jacobi_square(int batch, int n, MatView A, MatOut U, double* S, hipStream_t s);
+
+// The same for 96 < n <= 160: the first columns in LDS, the others in `ws`
+// (jacobi_ws(batch, n) entries); false when n is outside that range.
+bool jacobi_big(int batch, int n, MatView A, MatOut U, double* S, cplx* ws, hipStream_t s);
+size_t jacobi_ws(int batch, int n);
 
 // One-sided Jacobi SVD of batched m x n matrices with m >= n:
 // A = U diag(S) V^H with U (m x n) orthonormal columns, V (n x n) unitary,

@@ -79,6 +79,57 @@ def test_zqr_blocked(ctx, shape):
     assert torch.equal(R, R2)
 
 
+# shapes of the workspace-resident blocked kernel (m >= n, m <= 320,
+# n <= 160): the sketched unfoldings of rank caps up to 144 + 16, ragged
+# last panels and row blocks
+QR_BIG_SHAPES = [(288, 144), (272, 136), (320, 160), (256, 128), (290, 130), (200, 100),
+                 (144, 144), (97, 97), (193, 17), (320, 1), (161, 160), (230, 150)]
+
+
+@pytest.mark.parametrize("shape", QR_BIG_SHAPES)
+def test_zqr_big(ctx, shape):
+    """Blocked QR with the matrix in the workspace: against the definition
+    and numpy; R alone equals the R of the Q-forming call; a rank-deficient
+    matrix with a zero and a tiny column keeps Q orthonormal and finite."""
+    import torch
+    import paper_2412_11566_amd as q
+    m, n = shape
+    k = min(m, n)
+    rng = np.random.default_rng(m * 31 + n)
+    a = _rand(rng, 2, m, n)
+    A = torch.from_numpy(a).cuda()
+    # outputs start as NaN: every entry of R (zeros below the diagonal
+    # included) and of Q must be written
+    nan = complex(float("nan"), float("nan"))
+    R = torch.full((2, k, n), nan, dtype=torch.complex128, device="cuda")
+    Q = torch.full((2, m, k), nan, dtype=torch.complex128, device="cuda")
+    q.zqr(ctx, A, R, Q, path=6)
+    _check_qr(a, R.cpu().numpy(), Q.cpu().numpy())
+    R2 = torch.full_like(R, nan)
+    q.zqr(ctx, A, R2, path=6)
+    assert torch.equal(R, R2)
+    if n >= 8:
+        d = _rand(rng, 2, m, 5) @ _rand(rng, 2, 5, n)
+        d[:, :, 3] = 0.0
+        d[:, :, 6] *= 1e-300
+        A = torch.from_numpy(d).cuda()
+        q.zqr(ctx, A, R, Q, path=6)
+        Rn, Qn = R.cpu().numpy(), Q.cpu().numpy()
+        assert np.all(np.isfinite(Rn)) and np.all(np.isfinite(Qn))
+        _check_qr(d, Rn, Qn, full_rank=False)
+
+
+def test_zqr_big_rejects_uncovered(ctx):
+    import torch
+    import paper_2412_11566_amd as q
+    for (m, n) in [(321, 64), (200, 161), (100, 120)]:
+        k = min(m, n)
+        A = torch.zeros((1, m, n), dtype=torch.complex128, device="cuda")
+        R = torch.zeros((1, k, n), dtype=torch.complex128, device="cuda")
+        with pytest.raises(q.QttError):
+            q.zqr(ctx, A, R, path=6)
+
+
 QR_TWO_COL_SHAPES = [(160, 80), (128, 80), (96, 80), (160, 64), (64, 64), (48, 48), (128, 32),
                      (200, 64), (33, 20), (17, 17), (250, 40), (100, 96), (16, 90), (5, 70)]
 
@@ -186,7 +237,7 @@ def test_zqr_tiny_columns(ctx, shape):
         _check_qr(a, R, Q, full_rank=False)
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 16, 33, 64, 80, 96])
+@pytest.mark.parametrize("n", [1, 2, 7, 16, 33, 64, 80, 96, 97, 128, 144, 160])
 def test_zjacobi(ctx, n):
     import torch
     import paper_2412_11566_amd as q
@@ -213,6 +264,6 @@ def test_zjacobi(ctx, n):
 def test_zjacobi_rejects_large(ctx):
     import torch
     import paper_2412_11566_amd as q
-    A = torch.zeros((1, 97, 97), dtype=torch.complex128, device="cuda")
+    A = torch.zeros((1, 161, 161), dtype=torch.complex128, device="cuda")
     with pytest.raises(q.QttError):
-        q.zjacobi(ctx, A, torch.zeros_like(A), torch.zeros((1, 97), dtype=torch.float64, device="cuda"))
+        q.zjacobi(ctx, A, torch.zeros_like(A), torch.zeros((1, 161), dtype=torch.float64, device="cuda"))
