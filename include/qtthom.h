@@ -362,6 +362,23 @@ int qtt_zqr(qtt_ctx* ctx, int batch, int m, int n, const void* A, void* R,
 int qtt_zjacobi(qtt_ctx* ctx, int batch, int n, const void* A, void* U,
                 double* S);
 
+/* qtt_zqr without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same factorisation as qtt_zqr with path 0 (same
+ * arguments, layouts and results), but its workspace is a fixed device
+ * array of QTT_ZQR_NOALLOC_MAX_ELEMS complex doubles (16 MiB) that the
+ * library holds on every GPU it runs on until the process ends, and the
+ * call neither allocates, frees nor synchronises: it is enqueued on the
+ * context's stream and complete when that stream reaches it.
+ * QTT_ECAPACITY (with a message) when batch * (workspace of one m x n
+ * matrix) exceeds the array: 288 x 144 takes 85,392 entries per matrix, so
+ * up to 12 such matrices per call.  Every call on one GPU shares that GPU's
+ * array: calls whose execution overlaps on one GPU (other contexts or
+ * streams) race on it and must be serialised by the caller. */
+#define QTT_ZQR_NOALLOC_MAX_ELEMS 1048576
+int qtt_zqr_noalloc(qtt_ctx* ctx, int batch, int m, int n, const void* A,
+                    void* R, void* Q);
+
 /* Kernel statistics for roofline accounting.  qtt_stats_enable(ctx, s)
  * with s >= 1 brackets every s-th launch of the library's kernels by HIP
  * events on the context's stream (s = 1: every launch; a larger s keeps

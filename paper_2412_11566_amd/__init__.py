@@ -508,6 +508,26 @@ def zqr(ctx: Context, A, R, Q=None, path: int = 0):
                                C.c_void_p(R.data_ptr()), qp, path))
 
 
+def zqr_noalloc(ctx: Context, A, R, Q=None):
+    """qtt_zqr_noalloc: the QR of ``zqr`` (path 0) on the library's fixed
+    device workspace; asynchronous on the context's stream, allocates
+    nothing."""
+    _dev3(A, "A")
+    _dev3(R, "R")
+    batch, m, n = A.shape
+    k = min(m, n)
+    if tuple(R.shape) != (batch, k, n):
+        raise ValueError("zqr_noalloc: R must be (batch, min(m, n), n)")
+    qp = None
+    if Q is not None:
+        _dev3(Q, "Q")
+        if tuple(Q.shape) != (batch, m, k):
+            raise ValueError("zqr_noalloc: Q must be (batch, m, min(m, n))")
+        qp = C.c_void_p(Q.data_ptr())
+    ctx.check(_c.lib().qtt_zqr_noalloc(ctx.h, batch, m, n, C.c_void_p(A.data_ptr()),
+                                       C.c_void_p(R.data_ptr()), qp))
+
+
 def zjacobi(ctx: Context, A, U, S):
     """One-sided Jacobi of square matrices: A (batch, n, n) -> U (batch, n,
     n), S (batch, n) float64 descending, with A V = U diag(S)."""

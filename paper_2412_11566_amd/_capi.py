@@ -29,6 +29,8 @@ QTT_EXACT = 4
 QTT_PREC_FP64 = 0
 QTT_PREC_FP32 = 1
 
+QTT_ZQR_NOALLOC_MAX_ELEMS = 1048576
+
 ERR_NAMES = {QTT_EINVAL: "EINVAL", QTT_ENOMEM: "ENOMEM", QTT_ECAPACITY: "ECAPACITY",
              QTT_EHIP: "EHIP", QTT_ENOCONV: "ENOCONV", QTT_ENAN: "ENAN",
              QTT_EDIVERGED: "EDIVERGED"}
@@ -98,6 +100,7 @@ SIGNATURES = {
                       C.c_long, C.c_long, C.c_long, I]),
     "qtt_zqr": (I, [P, I, I, I, P, P, P, I]),
     "qtt_zjacobi": (I, [P, I, I, P, P, P]),
+    "qtt_zqr_noalloc": (I, [P, I, I, I, P, P, P]),
     "ls_adjoint_prepared": (I, [P, P, C.POINTER(SolveOpts), P, DP, DP, C.POINTER(Report)]),
     "qtt_stats_enable": (I, [P, I]),
     "qtt_stats_get": (I, [P, I, C.POINTER(C.c_longlong), DP, DP, DP]),

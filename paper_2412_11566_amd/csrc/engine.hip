@@ -24,6 +24,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <thread>
 #include <array>
 #include <atomic>
@@ -1705,6 +1706,40 @@ struct qtt_prepared {
   qtt::Prepared p;
 };
 
+// ---------------------------------------------------------------------------
+// Fixed device workspace of the entry point that allocates nothing
+// (qtt_zqr_noalloc): one array per GPU for the life of the process.  In host
+// code `scratch` names a host-side stand-in, not a device address, so host
+// code only ever uses the address hipGetSymbolAddress returned for the
+// device at context creation (scratch_ptr).
+// ---------------------------------------------------------------------------
+namespace qtt {
+constexpr size_t NOALLOC_ELEMS = (size_t)QTT_ZQR_NOALLOC_MAX_ELEMS;
+static __device__ __align__(256) cplx scratch[NOALLOC_ELEMS];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_addr;
+
+// Looks up (once per device, with that device current) the device address
+// of `scratch`; returns nullptr until then.
+static void* scratch_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr)
+    throw std::runtime_error(std::string("scratch symbol address: ") + hipGetErrorString(e));
+  g_scratch_addr[device] = p;
+  return p;
+}
+static void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(device);
+  return it == g_scratch_addr.end() ? nullptr : it->second;
+}
+}  // namespace qtt
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1752,6 +1787,7 @@ int qtt_create(int device, void* hip_stream, qtt_ctx** out) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return QTT_EINVAL;
     check(hipSetDevice(device), "set device");
+    (void)scratch_setup(device);  // the device's fixed workspace, once per device
     auto c = std::make_unique<qtt_ctx>();
     c->device = device;
     if (hip_stream) {
@@ -2387,6 +2423,32 @@ int qtt_zqr(qtt_ctx* c, int batch, int m, int n, const void* A, void* R, void* Q
         throw std::invalid_argument("zqr: shape not covered by the matrix-core Q formation");
     }
     X.sync();  // the workspace is released on return
+  });
+}
+
+int qtt_zqr_noalloc(qtt_ctx* c, int batch, int m, int n, const void* A, void* R, void* Qo) {
+  if (!c || !A || !R || batch < 1 || batch > 65535 || m < 1 || n < 1) return QTT_EINVAL;
+  const size_t need_ws = qr_ws(batch, m, n);
+  if (need_ws > NOALLOC_ELEMS) {
+    c->err = "qtt_zqr_noalloc: batch " + std::to_string(batch) + " of " + std::to_string(m) + " x " +
+             std::to_string(n) + " needs " + std::to_string(need_ws) +
+             " workspace entries, more than the fixed " + std::to_string(NOALLOC_ELEMS);
+    return QTT_ECAPACITY;
+  }
+  void* ws = scratch_ptr(c->device);
+  if (!ws) {
+    c->err = "qtt_zqr_noalloc: no workspace address for this device";
+    return QTT_EHIP;
+  }
+  QTT_TRY(c, {
+    const int k = std::min(m, n);
+    MatView av{(const cplx*)A, (long)n, 1, (long)m * n, 0};
+    MatOut ro{(cplx*)R, (long)n, 1, (long)k * n};
+    MatOut qo{(cplx*)Qo, (long)k, 1, (long)m * k};
+    if (!Qo) qo = MatOut{nullptr, 0, 0, 0};
+    // the library's own choice of kernels (qtt_zqr path 0) on the fixed
+    // workspace; no synchronisation, so the call can be captured
+    qr(batch, m, n, av, ro, qo, (cplx*)ws, c->stream);
   });
 }
 
