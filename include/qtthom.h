@@ -65,6 +65,7 @@ extern "C" {
 #define QTT_PREC_FP64   0
 #define QTT_PREC_FP32   1
 
+
 typedef struct qtt_ctx qtt_ctx;
 typedef struct qtt_tensor qtt_tensor;
 
@@ -351,12 +352,12 @@ int qtt_zgemm(qtt_ctx* ctx, int opA, int opB, int M, int N, int K,
  * forced path does not cover the shape.
  * Synchronises the stream before returning.
  *
- * qtt_zjacobi: one-sided Jacobi of batch n x n matrices A (n <= 160):
+ * qtt_zjacobi: one-sided Jacobi of batch n x n matrices A (n <= 320):
  * A V = U diag(S) with U (n x n) orthonormal columns for the nonzero S
  * (zero columns otherwise) and S (batch x n) descending; V is not formed.
  * Up to n = 96 the matrix is held in LDS; beyond, its first columns stay
  * in LDS and the rest live in a library workspace.  QTT_EINVAL for
- * n > 160. */
+ * n > 320. */
 int qtt_zqr(qtt_ctx* ctx, int batch, int m, int n, const void* A, void* R,
             void* Q, int path);
 int qtt_zjacobi(qtt_ctx* ctx, int batch, int n, const void* A, void* U,
@@ -404,7 +405,11 @@ int qtt_zqr_noalloc(qtt_ctx* ctx, int batch, int m, int n, const void* A,
 #define QTT_K_OTHER     4   /* elementwise helpers, RNG                     */
 #define QTT_K_MFMA      5   /* batched complex GEMM on the matrix cores     */
 #define QTT_K_MFMA32    6   /* the same in FP32 (QTT_PREC_FP32 contractions) */
-#define QTT_K_COUNT     7
+#define QTT_K_CONTRACT  7   /* the operator x train core contractions inside
+                               products (TTO apply as the rounding runs it:
+                               operator core times partial contraction), any
+                               GEMM path */
+#define QTT_K_COUNT     8
 int qtt_stats_enable(qtt_ctx* ctx, int on);
 int qtt_stats_get(qtt_ctx* ctx, int family, long long* launches,
                   double* seconds, double* flops, double* bytes);

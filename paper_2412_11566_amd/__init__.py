@@ -212,16 +212,16 @@ def green_build(ctx: Context, n: int, lam0: float, mu0: float, delta: float) -> 
     return _new(ctx, _c.lib().qtt_green_build, n, lam0, mu0, delta)
 
 
-def from_voxels(ctx: Context, phase: np.ndarray, lame, lame0, delta: float, cap: int = 0):
-    """(C - C0) raised operator and the one-hot phase train."""
-    phase = np.ascontiguousarray(phase, dtype=np.uint8)
-    n = int(round(np.log2(phase.shape[0])))
-    lame = np.ascontiguousarray(lame, dtype=np.float64)
+def from_voxels(ctx: Context, phase, lame, lame0, delta: float, cap: int = 0):
+    """(C - C0) raised operator and the one-hot phase train; ``phase`` is a
+    host array or a torch uint8 device tensor (read in place)."""
+    p, keep = _problem(phase, lame, lame0, 0)
     l0 = np.ascontiguousarray(lame0, dtype=np.float64)
     h, chi = C.c_void_p(), C.c_void_p()
     ctx.check(_c.lib().qtt_from_voxels(
-        ctx.h, phase.ctypes.data_as(C.POINTER(C.c_uint8)), 0, n, lame.shape[0], _dp(lame),
-        _dp(l0), delta, cap, C.byref(h), C.byref(chi)))
+        ctx.h, p.phase, p.phase_on_device, p.n, p.nphase, p.lame, _dp(l0), delta, cap,
+        C.byref(h), C.byref(chi)))
+    del keep
     return Tensor(ctx, h), Tensor(ctx, chi)
 
 

@@ -115,9 +115,10 @@ QTT_K_APPLY = 3
 QTT_K_OTHER = 4
 QTT_K_MFMA = 5
 QTT_K_MFMA32 = 6
+QTT_K_CONTRACT = 7
 KERNEL_FAMILIES = {QTT_K_GEMM: "gemm", QTT_K_QR: "qr", QTT_K_JACOBI: "jacobi",
                    QTT_K_APPLY: "tto_apply", QTT_K_OTHER: "other", QTT_K_MFMA: "gemm_mfma",
-                   QTT_K_MFMA32: "gemm_mfma_fp32"}
+                   QTT_K_MFMA32: "gemm_mfma_fp32", QTT_K_CONTRACT: "tto_contract"}
 
 HOST_SIGNATURES = {
     "qtt_host_qn_tto": (I, [I, D, IP, DP, C.c_size_t]),

@@ -176,6 +176,9 @@ struct qtt_ctx {
   // contractions of a product run in FP32 on the matrix cores while set
   // (rounding, norms and averages always run in FP64)
   bool gemm_fp32 = false;
+  // statistics family of the next GEMMs when >= 0 (QTT_K_CONTRACT for the
+  // operator x train contractions), else by kernel path
+  int gemm_family = -1;
   std::map<int, std::shared_ptr<qtt_tensor>> ident;  // identity operator per n
   // SFFT and Green factors per (n, delta): shared by every problem of that
   // grid size (the factors do not depend on the reference medium)
@@ -354,7 +357,9 @@ static void GB(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long l
     }
     slot = -1;
   }
-  X.k1(on, slot, ka, kb, mc ? (g.fp32 ? QTT_K_MFMA32 : QTT_K_MFMA) : QTT_K_GEMM, 8.0 * M * N * K * nb,
+  const int fam = X.c->gemm_family >= 0 ? X.c->gemm_family
+                                         : (mc ? (g.fp32 ? QTT_K_MFMA32 : QTT_K_MFMA) : QTT_K_GEMM);
+  X.k1(on, slot, ka, kb, fam, 8.0 * M * N * K * nb,
        16.0 * ((double)M * K + (double)K * N + (beta.x != 0.0 || beta.y != 0.0 ? 2.0 : 1.0) * M * N) * nb);
   if (ks_used > 1) {
     hipEvent_t e2 = X.t0();
@@ -516,7 +521,7 @@ static int choose_rank(std::vector<double>& S, int B, int kk, const std::vector<
   return rmax;
 }
 
-// One-sided Jacobi of B square n x n matrices (n <= 160): the LDS kernel
+// One-sided Jacobi of B square n x n matrices (n <= 320): the LDS kernel
 // up to 96, the LDS + workspace kernel beyond.
 static void jacobi_any(const Ctx& X, int B, int n, MatView A, MatOut U, double* S) {
   need(X, A.base, span2(n, n, A.rs, A.cs) + (long)(B - 1) * A.sb, "jac in");
@@ -818,6 +823,7 @@ static BufP left_step(const Ctx& X, const TT& A, const TT& x, int k, const cplx*
   t.nb1 = ob;
   t.sA1 = ia;
   t.nb2 = g * lt;
+  X.c->gemm_family = QTT_K_CONTRACT;
   if (!A.diag[k]) {
     t.sB1 = (long)g * lt * rho * din * r2; t.sC1 = (long)g * lt * dout * rho2 * r2;
     t.sB2 = (long)rho * din * r2; t.sC2 = (long)dout * rho2 * r2;
@@ -831,6 +837,7 @@ static BufP left_step(const Ctx& X, const TT& A, const TT& x, int k, const cplx*
     GB(X, rho2, r2, rho, OP_T, A.core[k], (long)d * rho2, OP_N, (cplx*)T1->p, (long)d * r2,
        (cplx*)P->p, r2, t);
   }
+  X.c->gemm_family = -1;
   return P;
 }
 
@@ -920,6 +927,7 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
     t.nb1 = ob;
     t.sA1 = ia;
     t.nb2 = g * r;
+    X.c->gemm_family = QTT_K_CONTRACT;
     if (!A.diag[k]) {
       t.sB1 = (long)g * r * din * rho2 * l2; t.sC1 = (long)g * r * rho * dout * l2;
       t.sB2 = (long)din * rho2 * l2; t.sC2 = (long)rho * dout * l2;
@@ -933,6 +941,7 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
       GB(X, rho, l2, rho2, OP_N, A.core[k], (long)d * rho2, OP_N, (cplx*)X1->p, l2, (cplx*)X2->p,
          (long)d * l2, t);
     }
+    X.c->gemm_family = -1;
     W[k] = X.buf((size_t)B * rho * r * l);
     if (dense_w[k]) {
       // W_k[b][a][c][(i t)] = X2[b][c][a][(i t)]  (l = dout * l2)
@@ -1478,6 +1487,150 @@ struct Ops {
   double lam0 = 0, mu0 = 0;
 };
 
+// ---------------------------------------------------------------------------
+// One-hot phase train on the device (the binary discretisation of Sec. 4.3
+// followed by TT-SVD, recomputed per geometry as App. D notes)
+// ---------------------------------------------------------------------------
+// R (c x c) of the QR of a tall m x c matrix (row-major, contiguous) by a
+// tree of batched QRs: blocks of b rows are factored, their R factors
+// stacked and factored again until one block remains.  Orthogonal
+// transformations throughout, so the singular values of R are those of the
+// matrix to working accuracy.
+static BufP tsqr_r(const Ctx& X, BufP M, long m, int c) {
+  const int b = c <= 96 ? 256 : 2 * ((c + 15) / 16) * 16;  // rows per block (m >= c per block)
+  while (m > b) {
+    const long nb = (m + b - 1) / b;
+    BufP src = M;
+    if (nb * b != m) {
+      // zero-pad the last block
+      src = X.buf((size_t)nb * b * c);
+      ck_fill(X, (cplx*)src->p + (size_t)m * c, (size_t)(nb * b - m) * c, C0(), X.s());
+      ck_copy2d(X, 1, (int)m, c, MatView{(cplx*)M->p, c, 1, (long)m * c, 0},
+                MatOut{(cplx*)src->p, c, 1, (long)nb * b * c}, C1(), X.s());
+    }
+    auto Rs = X.buf((size_t)nb * c * c);
+    // workspace bounded to ~256 MB per launch
+    const size_t per = qr_ws_per_matrix(b, c);
+    const long chunk = std::max<long>(1, std::min<long>(nb, (long)((256UL << 20) / (16 * per))));
+    auto ws = X.buf(qr_ws(chunk, b, c));
+    for (long b0 = 0; b0 < nb; b0 += chunk) {
+      const int cnt = (int)std::min(chunk, nb - b0);
+      ck_qr(X, cnt, b, c, MatView{(cplx*)src->p + (size_t)b0 * b * c, c, 1, (long)b * c, 0},
+            MatOut{(cplx*)Rs->p + (size_t)b0 * c * c, c, 1, (long)c * c}, MatOut{nullptr, 0, 0, 0},
+            (cplx*)ws->p, X.s());
+    }
+    M = Rs;
+    m = nb * c;
+  }
+  const int k = (int)std::min<long>(m, c);
+  auto R = X.buf((size_t)c * c);
+  ck_fill(X, (cplx*)R->p, (size_t)c * c, C0(), X.s());
+  auto ws = X.buf(qr_ws(1, (int)m, c));
+  ck_qr(X, 1, (int)m, c, MatView{(cplx*)M->p, c, 1, m * c, 0}, MatOut{(cplx*)R->p, c, 1, (long)c * c},
+        MatOut{nullptr, 0, 0, 0}, (cplx*)ws->p, X.s());
+  (void)k;
+  return R;
+}
+
+// TT-SVD of the one-hot tensor chi[p, x] = (phase(x) == p) with dims
+// (nphase, 2, ..., 2), right to left: the unfolding M (nphase 2^(k-1) x
+// 2 r_k) is reduced to R by tsqr_r, R^H goes through the one-sided Jacobi
+// (its left singular vectors are M's right singular vectors V, sorted by
+// singular value), the rank follows the per-bond rule delta / sqrt(L-1)
+// ||chi||, core k = V_r^H and M <- M V_r continues with the next bit.
+// Returns the cores on the host (r_{k-1}, d_k, r_k), real; false when a
+// bond would need more than 160 (the Jacobi's 320 columns).
+static bool device_chi(const Ctx& X, const uint8_t* phase, bool on_device, int n, int P, double delta,
+                       host::HTT& out) {
+  const long NN = 1L << (3 * n);
+  const int L = 3 * n + 1;
+  const uint8_t* dph = phase;
+  BufP phb;
+  if (!on_device) {
+    phb = X.buf((size_t)(NN + 15) / 16);
+    check(hipMemcpyAsync(phb->p, phase, NN, hipMemcpyHostToDevice, X.s()), "phase h2d");
+    dph = (const uint8_t*)phb->p;
+  }
+  auto T = X.buf((size_t)P * NN);
+  auto flag = X.bufd(1);
+  check(hipMemsetAsync(flag->p, 0, sizeof(int), X.s()), "flag clear");
+  need(X, T->p, (long)P * NN - 1, "onehot out");
+  onehot(dph, NN, P, (cplx*)T->p, (int*)flag->p, X.s());
+  int bad = 0;
+  check(hipMemcpyAsync(&bad, flag->p, sizeof(int), hipMemcpyDeviceToHost, X.s()), "flag d2h");
+  X.sync();
+  if (bad) throw std::invalid_argument("phase id out of range");
+  const double thr = delta / std::sqrt((double)(L - 1)) * std::sqrt((double)NN);
+  host::HTT cores(L);
+  BufP M = T;
+  long rows = (long)P * NN / 2;
+  int rk = 1;  // rank to the right of the current core
+  for (int k = L - 1; k >= 1; --k) {
+    const int c = 2 * rk;
+    if (c > 320) return false;
+    auto R = tsqr_r(X, M, rows, c);
+    auto U = X.buf((size_t)c * c);
+    auto Sd = X.bufd(c);
+    jacobi_any(X, 1, c, MatView{(cplx*)R->p, 1, (long)c, (long)c * c, 1},
+               MatOut{(cplx*)U->p, (long)c, 1, (long)c * c}, (double*)Sd->p);
+    std::vector<double> S(c);
+    std::vector<cplx> Uh((size_t)c * c);
+    check(hipMemcpyAsync(S.data(), Sd->p, c * sizeof(double), hipMemcpyDeviceToHost, X.s()), "S d2h");
+    check(hipMemcpyAsync(Uh.data(), U->p, Uh.size() * sizeof(cplx), hipMemcpyDeviceToHost, X.s()), "U d2h");
+    X.sync();
+    const int r = keep_rank(S.data(), c, thr, 0);
+    host::HCore& hc = cores[k];
+    hc.r0 = r; hc.dout = 2; hc.din = 0; hc.r1 = rk;
+    hc.v.resize((size_t)r * c);
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < c; ++j) {
+        const cplx u = Uh[(size_t)j * c + i];  // V_r^H[i][j] = conj(U[j][i])
+        hc.v[(size_t)i * c + j] = std::complex<double>(u.x, -u.y);
+      }
+    // M <- M V_r in row chunks (the GEMM grid bounds the rows per product)
+    auto Mn = X.buf((size_t)rows * r);
+    // rows is P times a power of two: halve the chunk while it stays at
+    // least max(4096, rows / 32768) rows and divides rows
+    const long target = std::max<long>(4096, rows / 32768);
+    long nbt = 1;
+    while (rows % (2 * nbt) == 0 && rows / (2 * nbt) >= target) nbt *= 2;
+    const long ch = rows / nbt;
+    G(X, (int)ch, r, c, OP_N, (cplx*)M->p, c, OP_N, (cplx*)U->p, c, (cplx*)Mn->p, r, (int)nbt,
+      ch * c, 0, ch * r);
+    M = Mn;
+    rk = r;
+    rows /= 2;
+  }
+  // core 0: M is (P x r_0)
+  host::HCore& h0 = cores[0];
+  h0.r0 = 1; h0.dout = P; h0.din = 0; h0.r1 = rk;
+  std::vector<cplx> m0((size_t)P * rk);
+  check(hipMemcpyAsync(m0.data(), M->p, m0.size() * sizeof(cplx), hipMemcpyDeviceToHost, X.s()), "core0 d2h");
+  X.sync();
+  h0.v.resize(m0.size());
+  for (size_t e = 0; e < m0.size(); ++e) h0.v[e] = std::complex<double>(m0[e].x, m0[e].y);
+  out = std::move(cores);
+  return true;
+}
+
+// Raised stiffness operator (and the one-hot train) of a problem: the
+// device TT-SVD, or the host one when a bond rank exceeds the device path.
+static host::HTT stiffness_op(const Ctx& X, const uint8_t* phase, bool on_device, int n, int P,
+                              const double* lame, const double* lame0, double delta, int cap,
+                              host::HTT* chi) {
+  host::HTT t;
+  if (device_chi(X, phase, on_device, n, P, delta, t))
+    return host::stiffness_from_chi(std::move(t), P, lame, lame0, cap, chi, nullptr);
+  std::vector<uint8_t> tmp;
+  const uint8_t* ph = phase;
+  if (on_device) {
+    tmp.resize((size_t)1 << (3 * n));
+    check(hipMemcpy(tmp.data(), phase, tmp.size(), hipMemcpyDeviceToHost), "phase d2h");
+    ph = tmp.data();
+  }
+  return host::stiffness_tto(ph, n, P, lame, lame0, delta, cap, chi, nullptr);
+}
+
 // The phase array of a problem in host memory (copied from the device when
 // phase_on_device is set; tmp holds the copy).
 static const uint8_t* host_phase(const qtt_problem* P, std::vector<uint8_t>& tmp) {
@@ -1492,9 +1645,8 @@ static Ops build_ops(const Ctx& X, const qtt_problem* P, double delta) {
   const int n = P->n;
   o.S = sfft_cached(X, n, delta);
   o.G = green_cached(X, n, P->lame0[0], P->lame0[1], delta);
-  std::vector<uint8_t> tmp;
-  const uint8_t* ph = host_phase(P, tmp);
-  host::HTT cd = host::stiffness_tto(ph, n, P->nphase, P->lame, P->lame0, delta, 0, &o.chi, nullptr);
+  host::HTT cd = stiffness_op(X, P->phase, P->phase_on_device != 0, n, P->nphase, P->lame, P->lame0,
+                              delta, 0, &o.chi);
   o.Cd = upload_op(X, cd);
   o.I = identity_op(X, n);
   o.lam0 = P->lame0[0];
@@ -1569,6 +1721,10 @@ static SolveOut ls_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, cons
   int m = 0;
   while (true) {
     RoundStats st;
+    // fresh sketches in every update: with the same test matrices in every
+    // update the truncated map is no contraction (measured: the relative
+    // update grew at 64^3 cap 64 and at 256^3 cap 64, and stalled 2.5 times
+    // higher at 256^3 cap 128); fresh draws decorrelate the rounding errors
     auto tau = op_apply(X, *ops.Cd, *eps, 0, ski(X, O), &st);
     auto th = op_apply(X, *ops.S, *tau, 0, ski(X, O), &st);
     auto eh = op_apply(X, *ops.G, *th, 0, ski(X, O), &st);
@@ -2017,16 +2173,8 @@ int qtt_from_voxels(qtt_ctx* c, const uint8_t* phase, int phase_on_device, int n
     return QTT_EINVAL;
   QTT_TRY(c, {
     Ctx X{c};
-    const size_t NN = (size_t)1 << (3 * n);
-    std::vector<uint8_t> hp;
-    const uint8_t* ph = phase;
-    if (phase_on_device) {
-      hp.resize(NN);
-      check(hipMemcpy(hp.data(), phase, NN, hipMemcpyDeviceToHost), "phase d2h");
-      ph = hp.data();
-    }
     host::HTT chih;
-    host::HTT cd = host::stiffness_tto(ph, n, nphase, lame, lame0, delta, cap, &chih, nullptr);
+    host::HTT cd = stiffness_op(X, phase, phase_on_device != 0, n, nphase, lame, lame0, delta, cap, &chih);
     *Cm = new qtt_tensor(*upload_op(X, cd));
     if (chi) {
       // the one-hot train as a train (kind 0, batch 1)
@@ -2460,7 +2608,7 @@ int qtt_zjacobi(qtt_ctx* c, int batch, int n, const void* A, void* U, double* S)
     if (n <= 96) {
       if (!jacobi_square(batch, n, av, uo, S, c->stream)) throw std::logic_error("zjacobi size");
     } else {
-      if (n > 160) throw std::invalid_argument("zjacobi: n exceeds 160");
+      if (n > 320) throw std::invalid_argument("zjacobi: n exceeds 320");
       Ctx X{c};
       auto ws = X.buf(jacobi_ws(batch, n));
       if (!jacobi_big(batch, n, av, uo, S, (cplx*)ws->p, c->stream)) throw std::logic_error("zjacobi size");
@@ -2728,30 +2876,14 @@ static int batch_group(qtt_ctx* c, const std::vector<int>& ids, const qtt_proble
     const int n = Ps[ids[0]].n;
     Ctx X{c};
     const double t0 = now_s();
+    // per-structure stiffness operators from the device TT-SVD of each
+    // voxel array (one after another on the context's stream)
     std::vector<host::HTT> cds(S);
-    {
-      std::vector<std::exception_ptr> errs(S);
-      const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-      const int nthr = std::max(1, std::min<int>(S, (int)std::min(16u, hw)));
-      std::atomic<int> next{0};
-      std::vector<std::thread> pool;
-      for (int w = 0; w < nthr; ++w)
-        pool.emplace_back([&]() {
-          for (int s2; (s2 = next.fetch_add(1)) < S;) {
-            try {
-              const qtt_problem& P = Ps[ids[s2]];
-              host::HTT chi;
-              std::vector<uint8_t> tmp;
-              const uint8_t* ph = host_phase(&P, tmp);
-              cds[s2] = host::stiffness_tto(ph, n, P.nphase, P.lame, P.lame0, O->delta, 0, &chi, nullptr);
-            } catch (...) {
-              errs[s2] = std::current_exception();
-            }
-          }
-        });
-      for (auto& th : pool) th.join();
-      for (auto& e : errs)
-        if (e) std::rethrow_exception(e);
+    for (int s2 = 0; s2 < S; ++s2) {
+      const qtt_problem& P = Ps[ids[s2]];
+      host::HTT chi;
+      cds[s2] = stiffness_op(X, P.phase, P.phase_on_device != 0, n, P.nphase, P.lame, P.lame0, O->delta,
+                             0, &chi);
     }
     Ops ops;
     ops.S = sfft_cached(X, n, O->delta);

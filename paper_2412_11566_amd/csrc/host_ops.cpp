@@ -521,6 +521,11 @@ HTT stiffness_tto(const uint8_t* phase, int n, int nphase, const double* lame,
   std::vector<int> dims(3 * n + 1, 2);
   dims[0] = nphase;
   HTT t = tt_svd_real(oh, dims, delta, 0);
+  return stiffness_from_chi(std::move(t), nphase, lame, lame0, cap, chi, max_rank);
+}
+
+HTT stiffness_from_chi(HTT t, int nphase, const double* lame, const double* lame0, int cap, HTT* chi,
+                       int* max_rank) {
   int mr = 1;
   for (auto& c : t) mr = std::max(mr, c.r1);
   if (max_rank) *max_rank = mr;

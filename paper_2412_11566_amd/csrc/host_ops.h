@@ -65,6 +65,11 @@ HTT stiffness_tto(const uint8_t* phase, int n, int nphase, const double* lame,
                   const double* lame0, double delta, int cap, HTT* chi,
                   int* max_rank);
 
+// The same operator from an already computed one-hot phase train (core 0
+// of dimension nphase, then the 3n binary cores); chi receives the train.
+HTT stiffness_from_chi(HTT t, int nphase, const double* lame, const double* lame0, int cap, HTT* chi,
+                       int* max_rank);
+
 // Isotropic Voigt stiffness (order 11, 22, 33, 23, 13, 12).
 void iso_voigt(double lam, double mu, double C[36]);
 

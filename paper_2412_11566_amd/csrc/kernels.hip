@@ -665,6 +665,25 @@ void fill(cplx* p, size_t count, cplx v, hipStream_t s) {
   check(hipGetLastError(), "fill launch");
 }
 
+// One-hot expansion of a voxel phase array: out[p * NN + v] = 1 if
+// phase[v] == p else 0, p < nphase; *bad is set when a phase id is out of
+// range.
+__global__ void k_onehot(const uint8_t* __restrict__ phase, long NN, int nphase, cplx* __restrict__ out,
+                         int* bad) {
+  const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= NN) return;
+  const int ph = phase[v];
+  if (ph >= nphase) *bad = 1;
+  for (int p = 0; p < nphase; ++p) out[(long)p * NN + v] = make_double2(ph == p ? 1.0 : 0.0, 0.0);
+}
+
+void onehot(const uint8_t* phase, long NN, int nphase, cplx* out, int* bad, hipStream_t s) {
+  if (NN <= 0) return;
+  hipLaunchKernelGGL(k_onehot, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, s, phase, NN, nphase,
+                     out, bad);
+  check(hipGetLastError(), "onehot launch");
+}
+
 __global__ void k_sum_middle(long total, int outer, int np, int inner, const cplx* in,
                              cplx* out, cplx w) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;

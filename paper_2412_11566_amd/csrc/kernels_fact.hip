@@ -1465,17 +1465,19 @@ __global__ __launch_bounds__(JNT) void k_jacobi_lds(int n, MatView A, MatOut U, 
   }
 }
 
-// The same one-sided Jacobi for 96 < n <= 160, where the square matrix
-// (up to 400 KB) outgrows the 160 KB of LDS: the first nA columns stay in
+// The same one-sided Jacobi for 96 < n <= 320, where the square matrix
+// (up to 1.6 MB) outgrows the 160 KB of LDS: the first nA columns stay in
 // LDS, the others live in a per-matrix workspace slice (global memory,
 // L2-resident); a column is addressed through a flat pointer to either, so
-// the rotation loop is the LDS kernel's.
-constexpr int JBIGN = 160;
+// the rotation loop is the LDS kernel's.  LP lanes cooperate on a column
+// pair: 16 up to n = 160, 32 beyond (ten rows per lane either way).
+constexpr int JBIGN = 320;
 
 __device__ __forceinline__ cplx* jcol(cplx* Wl, cplx* Wg, int nA, int n, int c) {
   return c < nA ? Wl + (long)c * n : Wg + (long)(c - nA) * n;
 }
 
+template <int LP>
 __global__ __launch_bounds__(JNT) void k_jacobi_hyb(int n, int nA, MatView A, MatOut U, double* S,
                                                     cplx* gws, long gsz) {
   extern __shared__ cplx Wl[];  // columns [0, nA), column-major
@@ -1484,8 +1486,8 @@ __global__ __launch_bounds__(JNT) void k_jacobi_hyb(int n, int nA, MatView A, Ma
   __shared__ int rankpos[JBIGN];
   __shared__ int rotated;
   const int b = blockIdx.x, tid = threadIdx.x;
-  const int g = tid >> 4, sub = tid & 15;
-  constexpr int NG = JNT / 16;
+  const int g = tid / LP, sub = tid % LP;
+  constexpr int NG = JNT / LP;
   cplx* Wg = gws + (long)b * gsz;  // columns [nA, n)
   for (int e = tid; e < n * n; e += JNT) {
     const int i = e % n, j = e / n;
@@ -1513,23 +1515,27 @@ __global__ __launch_bounds__(JNT) void k_jacobi_hyb(int n, int nA, MatView A, Ma
         if (ca > cb) { const int t = ca; ca = cb; cb = t; }
         cplx* xa = jcol(Wl, Wg, nA, n, ca);
         cplx* xb = jcol(Wl, Wg, nA, n, cb);
-        constexpr int JR = (JBIGN + 15) / 16;
+        constexpr int JR = 10;  // rows per lane: n <= LP * JR (160 or 320)
         cplx va[JR], vb[JR];
 #pragma unroll
         for (int q = 0; q < JR; ++q) {
-          const int i = min(sub + 16 * q, n - 1);
+          const int i = min(sub + LP * q, n - 1);
           va[q] = xa[i];
           vb[q] = xb[i];
         }
         cplx ga = make_double2(0.0, 0.0);
 #pragma unroll
         for (int q = 0; q < JR; ++q) {
-          if (sub + 16 * q >= n) continue;
+          if (sub + LP * q >= n) continue;
           const cplx t = cdotc(va[q], vb[q]);
           ga = make_double2(ga.x + t.x, ga.y + t.y);
         }
         ga.x = row16_sum(ga.x);
         ga.y = row16_sum(ga.y);
+        if (LP == 32) {
+          ga.x += __shfl_xor(ga.x, 16);
+          ga.y += __shfl_xor(ga.y, 16);
+        }
         const double al = nrm2[ca], be = nrm2[cb];
         const double gg2 = cabs2(ga);
         if (!(gg2 > tol * tol * (al * be)) || al < 1e-300 || be < 1e-300) continue;
@@ -1545,7 +1551,7 @@ __global__ __launch_bounds__(JNT) void k_jacobi_hyb(int n, int nA, MatView A, Ma
         const cplx ph = make_double2(ga.x * rg, -ga.y * rg);
 #pragma unroll
         for (int q = 0; q < JR; ++q) {
-          const int i = sub + 16 * q;
+          const int i = sub + LP * q;
           if (i >= n) continue;
           const cplx u = va[q], wv = cmul(ph, vb[q]);
           xa[i] = make_double2(cs * u.x - sn * wv.x, cs * u.y - sn * wv.y);
@@ -1591,9 +1597,10 @@ __global__ __launch_bounds__(JNT) void k_jacobi_hyb(int n, int nA, MatView A, Ma
 }
 
 // columns of an n x n Jacobi matrix that stay in LDS (the rest go to the
-// workspace): as many as 156 KB of dynamic LDS hold
+// workspace): as many as 150 KB of dynamic LDS hold (the static arrays of
+// n = 320 take another 6.4 KB of the 160 KB)
 static int jacobi_lds_cols(int n) {
-  const int c = (int)((156L * 1024) / (16L * n));
+  const int c = (int)((150L * 1024) / (16L * n));
   return c < n ? c : n;
 }
 
@@ -1681,16 +1688,23 @@ bool jacobi_big(int batch, int n, MatView A, MatOut U, double* S, cplx* ws, hipS
   if (batch <= 0 || n <= 0) return true;
   if (n <= JMAXN || n > JBIGN || ws == nullptr) return false;
   static const bool attr = [&]() {
-    check(hipFuncSetAttribute((const void*)k_jacobi_hyb, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              156 * 1024),
+    check(hipFuncSetAttribute((const void*)k_jacobi_hyb<16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              150 * 1024),
+          "jacobi_hyb lds attribute");
+    check(hipFuncSetAttribute((const void*)k_jacobi_hyb<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              150 * 1024),
           "jacobi_hyb lds attribute");
     return true;
   }();
   (void)attr;
   const int nA = jacobi_lds_cols(n);
   const size_t shm = (size_t)nA * n * sizeof(cplx);
-  hipLaunchKernelGGL(k_jacobi_hyb, dim3(batch), dim3(JNT), shm, s, n, nA, A, U, S, ws,
-                     (long)(n - nA) * n);
+  if (n <= 160)
+    hipLaunchKernelGGL(k_jacobi_hyb<16>, dim3(batch), dim3(JNT), shm, s, n, nA, A, U, S, ws,
+                       (long)(n - nA) * n);
+  else
+    hipLaunchKernelGGL(k_jacobi_hyb<32>, dim3(batch), dim3(JNT), shm, s, n, nA, A, U, S, ws,
+                       (long)(n - nA) * n);
   check(hipGetLastError(), "jacobi_hyb launch");
   return true;
 }

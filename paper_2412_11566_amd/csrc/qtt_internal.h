@@ -256,6 +256,10 @@ void fill(cplx* p, size_t count, cplx v, hipStream_t s);
 void sum_middle(int batch, int outer, int np, int inner, const cplx* in,
                 cplx* out, cplx w, hipStream_t s);
 
+// out[p * NN + v] = (phase[v] == p) for p < nphase (device arrays); sets
+// *bad (device int) when a phase id is >= nphase.
+void onehot(const uint8_t* phase, long NN, int nphase, cplx* out, int* bad, hipStream_t s);
+
 void check(hipError_t e, const char* what);
 
 }  // namespace qtt

@@ -237,7 +237,7 @@ def test_zqr_tiny_columns(ctx, shape):
         _check_qr(a, R, Q, full_rank=False)
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 16, 33, 64, 80, 96, 97, 128, 144, 160])
+@pytest.mark.parametrize("n", [1, 2, 7, 16, 33, 64, 80, 96, 97, 128, 144, 160, 161, 230, 320])
 def test_zjacobi(ctx, n):
     import torch
     import paper_2412_11566_amd as q
@@ -264,6 +264,6 @@ def test_zjacobi(ctx, n):
 def test_zjacobi_rejects_large(ctx):
     import torch
     import paper_2412_11566_amd as q
-    A = torch.zeros((1, 161, 161), dtype=torch.complex128, device="cuda")
+    A = torch.zeros((1, 321, 321), dtype=torch.complex128, device="cuda")
     with pytest.raises(q.QttError):
-        q.zjacobi(ctx, A, torch.zeros_like(A), torch.zeros((1, 161), dtype=torch.float64, device="cuda"))
+        q.zjacobi(ctx, A, torch.zeros_like(A), torch.zeros((1, 321), dtype=torch.float64, device="cuda"))

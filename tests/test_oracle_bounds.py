@@ -124,3 +124,22 @@ def test_hs_planted_coefficient_error_is_caught():
     k1, m1, f1, k2, m2, f2 = next(iter(_phase_pairs()))
     _, G = _walpole(k1, m1, [(k1, m1, f1), (k2, m2, f2)])
     assert abs(bad_mbound(k1, m1, f1, k2, m2, f2) - G) > 1e-6 * abs(G)
+
+
+def test_voigt_reuss_matrices_of_isotropic_phases():
+    """The matrix bounds of oracle.bounds on isotropic phases are isotropic
+    with the arithmetic (Voigt) and harmonic (Reuss) means of the bulk and
+    shear moduli taken separately (the isotropic stiffness acts as 3 kappa
+    and 2 mu on its two eigenspaces)."""
+    from oracle.voigt import iso_voigt
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        lam = rng.uniform(0.1, 5.0, 3)
+        mu = rng.uniform(0.1, 5.0, 3)
+        f = rng.dirichlet(np.ones(3))
+        Cs = np.stack([iso_voigt(l, m) for l, m in zip(lam, mu)])
+        k = lam + 2 * mu / 3
+        kV, mV = f @ k, f @ mu
+        kR, mR = 1 / (f @ (1 / k)), 1 / (f @ (1 / mu))
+        assert np.allclose(B.voigt_bound(Cs, f), iso_voigt(kV - 2 * mV / 3, mV), rtol=1e-12, atol=1e-12)
+        assert np.allclose(B.reuss_bound(Cs, f), iso_voigt(kR - 2 * mR / 3, mR), rtol=1e-12, atol=1e-12)

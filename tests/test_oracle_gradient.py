@@ -59,3 +59,19 @@ def test_euler_identity_fibres_shrinks_with_grid():
         dev.append(np.linalg.norm(E - C) / np.linalg.norm(C))
         assert np.abs(J - J.transpose(1, 0, 2)).max() < 1e-12 * np.abs(J).max()
     assert dev[0] < 5e-3 and dev[1] < 2e-3 and dev[1] < dev[0]
+
+
+def test_references_agree_on_the_64_fibres():
+    """The gradient references on the four-fibre workload at 64^3 (the
+    (64, 64, 1) slice of the z-invariant geometry): energy identity,
+    central differences with the workload's step 1e-6, dense adjoint."""
+    p = M.config_c2(6)
+    ph = p.phase[:, :, :1].copy()
+    C, it, fields = D.effective_stiffness(ph, p.lame, p.lame0, tol=1e-13, keep_fields=True)
+    ge = D.gradient_energy(ph, fields)
+    gf = D.gradient_fd(ph, p.lame, p.lame0, tol=1e-13, rel_step=1e-6)
+    adj = D.adjoint_fields(ph, p.lame, p.lame0, tol=1e-13)
+    ga = D.gradient_adjoint(ph, p.lame, p.lame0, fields, adj)
+    scale = np.abs(ge).max()
+    assert np.abs(gf - ge).max() < 1e-6 * scale
+    assert np.abs(ga - ge).max() < 1e-9 * scale
