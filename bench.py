@@ -42,13 +42,14 @@ PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 matrix (dense)
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE passes, scaled by
-# the same counters on a plain copy (profiles/zgemm_mfma_256_fibres_hbm_counters.md),
-# per kernel family and number of concurrent load-case groups (which sets the
-# GEMM batch); valid only while the kernel source is the one that was measured.
+# the same counters on a plain copy, per kernel family and number of
+# concurrent load-case groups (which sets the batches); valid only while the
+# kernel sources are the ones that were measured
+# (profiles/qr_family_256_fibres_hbm_counters.md).
 MEASURED_TRAFFIC = {
-    ("gemm_mfma", 3): {"bytes_per_launch": 51.46e6,
-                       "source": "paper_2412_11566_amd/csrc/kernels_mfma.hip",
-                       "sha256": "830dbc627e39fd1927bc649505417bbc2148db3add9269ee21b8c1ee9f690175"},
+    ("qr", 3): {"bytes_per_launch": 1.380e6,
+                "sources": {"paper_2412_11566_amd/csrc/kernels_fact.hip": "a21946655c633bd888ed6c0f5de687b71afd4da1af9727d3135a9f64376e7ed5",
+                            "paper_2412_11566_amd/csrc/kernels_qr_blk.hip": "b1c5622f451c62339712078db1a68a59894a8739c06eafdb20a5afdf7fbc3c19"}},
 }
 
 
@@ -57,9 +58,10 @@ def measured_traffic(family, streams):
     m = MEASURED_TRAFFIC.get((family, streams))
     if not m:
         return None
-    with open(os.path.join(ROOT, m["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != m["sha256"]:
-            return None   # the kernel changed since the counters were taken
+    for src, sha in m["sources"].items():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != sha:
+                return None   # a kernel changed since the counters were taken
     return m["bytes_per_launch"]
 
 
@@ -277,6 +279,8 @@ def main():
                          "is the dense scheme's count to 1e-6 on this geometry)")
     ap.add_argument("--streams", type=int, default=3,
                     help="load-case groups solved concurrently on streams of their own")
+    ap.add_argument("--orth", choices=["householder", "cholqr"], default="householder",
+                    help="orthonormalisation of the range finder's sketched unfoldings")
     ap.add_argument("--stats-stride", type=int, default=8,
                     help="time every s-th library launch with HIP events (1: all)")
     ap.add_argument("--tto-only", action="store_true",
@@ -315,13 +319,28 @@ def main():
 
     p = M.config_c2(args.n)
     ctx = q.Context(0)
+    # the stiffness operator alone (device TT-SVD of the voxels, a0), then
+    # every operator of the problem (SFFT and Green factors from their
+    # closed forms on the host, stiffness again)
+    t = time.perf_counter()
+    A0, chi0 = q.from_voxels(ctx, p.phase, p.lame, p.lame0, p.delta)
+    torch.cuda.synchronize()
+    stiff_s = time.perf_counter() - t
+    del A0, chi0
+    t = time.perf_counter()
+    S0 = q.sfft_build(ctx, args.n, p.delta)
+    torch.cuda.synchronize()
+    sfft_s = time.perf_counter() - t
+    del S0
     t = time.perf_counter()
     prep = q.prepare(ctx, p.phase, p.lame, p.lame0, p.delta)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t
-    log(f"setup (operators, device TT-SVD of the voxels) {setup_s:.2f} s")
+    log(f"setup: stiffness from voxels (device TT-SVD) {stiff_s:.2f} s, SFFT {sfft_s:.2f} s, "
+        f"qtt_prepare (all operators) {setup_s:.2f} s")
+    orth = q.QTT_ORTH_CHOLQR if args.orth == "cholqr" else q.QTT_ORTH_HOUSEHOLDER
     opts = q.SolveOptions(delta=p.delta, tol=p.tol, cap=p.cap, max_iter=args.max_iter,
-                          oversample=args.oversample, seed=2024, streams=args.streams)
+                          oversample=args.oversample, seed=2024, streams=args.streams, orth=orth)
     for w in range(args.warmup):
         wo = q.SolveOptions(delta=p.delta, tol=p.tol, cap=p.cap, max_iter=2, oversample=args.oversample,
                             seed=1, streams=args.streams)
@@ -389,7 +408,7 @@ def main():
     grad = None
     if not args.no_cap128:
         o128 = q.SolveOptions(delta=p.delta, tol=p.tol, cap=128, max_iter=args.max_iter,
-                              oversample=args.oversample, seed=2024, streams=args.streams)
+                              oversample=args.oversample, seed=2024, streams=args.streams, orth=orth)
         C128, r128, eps128, t128, _ = timed_solve(q, ctx, prep, o128, keep_eps=not args.no_gradient)
         e128 = golden_error(C128, "c2") if args.n == 8 else None
         cap128 = {"cap": 128, "iterations_per_s": sum(r128.iterations) / t128, "solve_s": t128,
@@ -435,13 +454,15 @@ def main():
                                f"6 load cases, cap {p.cap}, delta {p.delta:g}, tol {p.tol:g}",
                    "n": args.n, "cores": 3 * args.n + 1, "cap": p.cap, "delta": p.delta,
                    "tol": p.tol, "oversample": args.oversample, "streams": args.streams,
-                   "max_iter": args.max_iter},
+                   "max_iter": args.max_iter, "orth": args.orth},
         "iterations_per_load_case": reps[-1].iterations,
         "ceff_rel_error_vs_oracle": err,
         "ceff_note": "cap 64 cannot hold the converged strain (rank 64 leaves 1.2e-2); the "
                      "1e-5 line is cap128",
         "cap128": cap128,
         "setup_seconds": setup_s,
+        "setup_breakdown": {"stiffness_from_voxels_s": stiff_s, "sfft_build_s": sfft_s,
+                            "prepare_all_operators_s": setup_s},
         "roofline": roofline,
         "roofline_families": rl,
         "tt_rounding": tt_rounding,

@@ -64,7 +64,20 @@ extern "C" {
 /* precision of the core contractions (rounding is always FP64) */
 #define QTT_PREC_FP64   0
 #define QTT_PREC_FP32   1
+/* split-BF16: each operand of the operator x train contractions is rounded
+ * to hi + lo (two bf16 values, 16 significant bits) and every real product
+ * is formed from three bf16 products on the matrix cores with FP32
+ * accumulation (Table 2's contractions); sketches, QR, SVD and residuals
+ * stay FP64 */
+#define QTT_PREC_BF16X3 2
 
+/* orthonormalisation of the range finder's sketched unfoldings (Sec. 3:
+ * only the basis is kept, not R).  QTT_ORTH_HOUSEHOLDER (default):
+ * Householder QR; QTT_ORTH_CHOLQR: CholeskyQR2 on the FP64 matrix cores
+ * where the Gram matrix is well enough conditioned, Householder QR for the
+ * rest (qtt_zorth).  The exact sketch always uses Householder. */
+#define QTT_ORTH_HOUSEHOLDER 0
+#define QTT_ORTH_CHOLQR      1
 
 typedef struct qtt_ctx qtt_ctx;
 typedef struct qtt_tensor qtt_tensor;
@@ -106,6 +119,9 @@ typedef struct qtt_solve_opts {
                                 no such update; ls_adjoint and
                                 qtt_batch_solve leave it untouched          */
     int history_len;         /* entries per load case in `history`         */
+    int orth;                /* QTT_ORTH_*: how the range finder of each
+                                rounding orthonormalises its sketched
+                                unfoldings (Sec. 3)                         */
 } qtt_solve_opts;
 
 typedef struct qtt_report {
@@ -324,10 +340,13 @@ int ls_adjoint_prepared(qtt_ctx* ctx, const qtt_prepared* prep,
  * contraction precision of QTT_PREC_FP32; results stored as doubles),
  * 4 + t matrix cores in FP64 with tile variant t forced instead of chosen
  * per shape (t = 0..6: 16x16, 32x32, 64x64, 80x80, 32x80, 80x32, 64x80;
- * for tests and tuning).
+ * for tests and tuning), QTT_GEMM_PATH_BF16X3 matrix cores with split-BF16
+ * operands and FP32 accumulation (the contraction precision of
+ * QTT_PREC_BF16X3; results stored as doubles).
  * Asynchronous on the context's stream.  QTT_EINVAL on null pointers,
  * K < 1, batch outside [1, 65535] or leading dimensions smaller than a
  * row. */
+#define QTT_GEMM_PATH_BF16X3 16
 int qtt_zgemm(qtt_ctx* ctx, int opA, int opB, int M, int N, int K,
               const double* alpha, const void* A, long lda, const void* B,
               long ldb, const double* beta, void* C, long ldc, int batch,
@@ -362,6 +381,21 @@ int qtt_zqr(qtt_ctx* ctx, int batch, int m, int n, const void* A, void* R,
             void* Q, int path);
 int qtt_zjacobi(qtt_ctx* ctx, int batch, int n, const void* A, void* U,
                 double* S);
+
+/* qtt_zorth: orthonormal basis of the column space of batch m x n
+ * matrices A (m >= n, 32 < m <= 192 for 16 < n <= 64, 32 < m <= 168 for
+ * 64 < n <= 80): Q (m x n) with
+ * Q^H Q = I and range(Q) = range(A) -- the factor the range finder of
+ * TT-rounding keeps (Sec. 3).  CholeskyQR2 on the FP64 matrix cores, one
+ * workgroup per matrix; a matrix whose first Cholesky breaks down (a pivot
+ * at or below 1e-12 of the largest diagonal entry of A^H A) or whose
+ * first-pass columns are farther than 0.5 (Frobenius) from orthonormal is
+ * factored by Householder QR instead.  fallback (host array of batch ints,
+ * may be NULL) receives 1 for each matrix that took Householder, else 0.
+ * Same layouts as qtt_zqr; QTT_EINVAL outside the covered shapes.
+ * Synchronises the stream before returning. */
+int qtt_zorth(qtt_ctx* ctx, int batch, int m, int n, const void* A, void* Q,
+              int* fallback);
 
 /* qtt_zqr without any allocation, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
@@ -409,7 +443,10 @@ int qtt_zqr_noalloc(qtt_ctx* ctx, int batch, int m, int n, const void* A,
                                products (TTO apply as the rounding runs it:
                                operator core times partial contraction), any
                                GEMM path */
-#define QTT_K_COUNT     8
+#define QTT_K_MFMA_BF16 8   /* matrix-core GEMM with split-BF16 operands
+                               (QTT_PREC_BF16X3 products outside the
+                               contraction family)                         */
+#define QTT_K_COUNT     9
 int qtt_stats_enable(qtt_ctx* ctx, int on);
 int qtt_stats_get(qtt_ctx* ctx, int family, long long* launches,
                   double* seconds, double* flops, double* bytes);

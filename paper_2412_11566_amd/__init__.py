@@ -19,7 +19,8 @@ import numpy as np
 
 from . import _capi as _c
 from ._capi import (QTT_EXACT, QTT_INVERSE, QTT_NO_ROUND, QTT_OK, QTT_ENOCONV,
-                    QTT_PREC_FP32, QTT_PREC_FP64)
+                    QTT_ORTH_CHOLQR, QTT_ORTH_HOUSEHOLDER, QTT_PREC_BF16X3, QTT_PREC_FP32,
+                    QTT_PREC_FP64)
 
 __all__ = [
     "QttError", "Context", "Tensor", "SolveOptions", "SolveReport",
@@ -28,7 +29,8 @@ __all__ = [
     "tt_mean_apply", "ls_solve", "ls_adjoint", "batch_solve", "Prepared", "prepare",
     "ls_solve_prepared", "stats_enable", "stats_get", "stats_reset", "tensor_create",
     "tensor_wrap", "tensor_export", "NotConvergedWarning",
-    "QTT_EXACT", "QTT_INVERSE", "QTT_NO_ROUND", "QTT_PREC_FP32", "QTT_PREC_FP64",
+    "QTT_EXACT", "QTT_INVERSE", "QTT_NO_ROUND", "QTT_ORTH_CHOLQR", "QTT_ORTH_HOUSEHOLDER",
+    "QTT_PREC_BF16X3", "QTT_PREC_FP32", "QTT_PREC_FP64",
 ]
 
 
@@ -283,10 +285,13 @@ class SolveOptions:
     streams: int = 1
     # entries of the per-load-case residual history to record (0: none)
     history: int = 0
+    # range-finder orthonormalisation: QTT_ORTH_HOUSEHOLDER or QTT_ORTH_CHOLQR
+    orth: int = 0
 
     def c(self) -> _c.SolveOpts:
         o = _c.SolveOpts(self.delta, self.tol, self.cap, self.max_iter, self.precision,
                          self.oversample, int(self.exact), self.seed, self.streams)
+        o.orth = self.orth
         if self.history > 0:
             buf = np.zeros(6 * self.history)
             o.history = _dp(buf)
@@ -506,6 +511,20 @@ def zqr(ctx: Context, A, R, Q=None, path: int = 0):
         qp = C.c_void_p(Q.data_ptr())
     ctx.check(_c.lib().qtt_zqr(ctx.h, batch, m, n, C.c_void_p(A.data_ptr()),
                                C.c_void_p(R.data_ptr()), qp, path))
+
+
+def zorth(ctx: Context, A, Q):
+    """qtt_zorth: orthonormal basis Q (batch, m, n) of the columns of A
+    (batch, m, n); returns the per-matrix fallback flags (1: Householder)."""
+    _dev3(A, "A")
+    _dev3(Q, "Q")
+    if tuple(Q.shape) != tuple(A.shape):
+        raise ValueError("zorth: Q must have the shape of A")
+    batch, m, n = A.shape
+    flags = (C.c_int * batch)()
+    ctx.check(_c.lib().qtt_zorth(ctx.h, batch, m, n, C.c_void_p(A.data_ptr()),
+                                 C.c_void_p(Q.data_ptr()), flags))
+    return list(flags)
 
 
 def zqr_noalloc(ctx: Context, A, R, Q=None):

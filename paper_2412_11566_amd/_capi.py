@@ -28,6 +28,11 @@ QTT_EXACT = 4
 
 QTT_PREC_FP64 = 0
 QTT_PREC_FP32 = 1
+QTT_PREC_BF16X3 = 2
+QTT_GEMM_PATH_BF16X3 = 16
+
+QTT_ORTH_HOUSEHOLDER = 0
+QTT_ORTH_CHOLQR = 1
 
 QTT_ZQR_NOALLOC_MAX_ELEMS = 1048576
 
@@ -46,7 +51,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("delta", C.c_double), ("tol", C.c_double), ("cap", C.c_int),
                 ("max_iter", C.c_int), ("precision", C.c_int), ("oversample", C.c_int),
                 ("exact", C.c_int), ("seed", C.c_uint64), ("streams", C.c_int),
-                ("history", C.POINTER(C.c_double)), ("history_len", C.c_int)]
+                ("history", C.POINTER(C.c_double)), ("history_len", C.c_int), ("orth", C.c_int)]
 
 
 class Report(C.Structure):
@@ -101,6 +106,7 @@ SIGNATURES = {
     "qtt_zqr": (I, [P, I, I, I, P, P, P, I]),
     "qtt_zjacobi": (I, [P, I, I, P, P, P]),
     "qtt_zqr_noalloc": (I, [P, I, I, I, P, P, P]),
+    "qtt_zorth": (I, [P, I, I, I, P, P, C.POINTER(C.c_int)]),
     "ls_adjoint_prepared": (I, [P, P, C.POINTER(SolveOpts), P, DP, DP, C.POINTER(Report)]),
     "qtt_stats_enable": (I, [P, I]),
     "qtt_stats_get": (I, [P, I, C.POINTER(C.c_longlong), DP, DP, DP]),
@@ -116,9 +122,11 @@ QTT_K_OTHER = 4
 QTT_K_MFMA = 5
 QTT_K_MFMA32 = 6
 QTT_K_CONTRACT = 7
+QTT_K_MFMA_BF16 = 8
 KERNEL_FAMILIES = {QTT_K_GEMM: "gemm", QTT_K_QR: "qr", QTT_K_JACOBI: "jacobi",
                    QTT_K_APPLY: "tto_apply", QTT_K_OTHER: "other", QTT_K_MFMA: "gemm_mfma",
-                   QTT_K_MFMA32: "gemm_mfma_fp32", QTT_K_CONTRACT: "tto_contract"}
+                   QTT_K_MFMA32: "gemm_mfma_fp32", QTT_K_CONTRACT: "tto_contract",
+                   QTT_K_MFMA_BF16: "gemm_mfma_bf16x3"}
 
 HOST_SIGNATURES = {
     "qtt_host_qn_tto": (I, [I, D, IP, DP, C.c_size_t]),

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libqtthom.so")
 HOSTLIB = os.path.join(HERE, "libqtthom_host.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "kernels_fact.hip", "kernels_qr_blk.hip", "kernels_qr_big.hip", "kernels_mfma.hip", "engine.hip", "host_ops.cpp", "host_capi.cpp"]
+SOURCES = ["kernels.hip", "kernels_fact.hip", "kernels_qr_blk.hip", "kernels_qr_big.hip", "kernels_cholqr.hip", "kernels_mfma.hip", "engine.hip", "host_ops.cpp", "host_capi.cpp"]
 ARCH = os.environ.get("QTTHOM_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"-I{INCLUDE}", f"-I{CSRC}"]

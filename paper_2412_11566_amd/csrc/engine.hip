@@ -176,6 +176,8 @@ struct qtt_ctx {
   // contractions of a product run in FP32 on the matrix cores while set
   // (rounding, norms and averages always run in FP64)
   bool gemm_fp32 = false;
+  // the same with split-BF16 operands and FP32 accumulation
+  bool gemm_bf16 = false;
   // statistics family of the next GEMMs when >= 0 (QTT_K_CONTRACT for the
   // operator x train contractions), else by kernel path
   int gemm_family = -1;
@@ -329,7 +331,8 @@ static void GB(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long l
   const double nb = (double)t.nb1 * t.nb2 * t.nb3;
   BufP ws;
   g.fp32 = X.c->gemm_fp32;
-  const int ks = gemm_ksplit(M, N, K, (long)nb, g.fp32);
+  g.bf16x3 = X.c->gemm_bf16;
+  const int ks = gemm_ksplit(M, N, K, (long)nb, g.fp32 || g.bf16x3);
   if (ks > 1) {
     ws = X.buf(gemm_ws_elems(g, ks));
     g.ws = (cplx*)ws->p;
@@ -358,7 +361,8 @@ static void GB(const Ctx& X, int M, int N, int K, int opA, const cplx* A, long l
     slot = -1;
   }
   const int fam = X.c->gemm_family >= 0 ? X.c->gemm_family
-                                         : (mc ? (g.fp32 ? QTT_K_MFMA32 : QTT_K_MFMA) : QTT_K_GEMM);
+                                         : (mc ? (g.bf16x3 ? QTT_K_MFMA_BF16 : (g.fp32 ? QTT_K_MFMA32 : QTT_K_MFMA))
+                                               : QTT_K_GEMM);
   X.k1(on, slot, ka, kb, fam, 8.0 * M * N * K * nb,
        16.0 * ((double)M * K + (double)K * N + (beta.x != 0.0 || beta.y != 0.0 ? 2.0 : 1.0) * M * N) * nb);
   if (ks_used > 1) {
@@ -388,6 +392,15 @@ static double qr_flops(int m, int n, bool q) {
 
 // checked launchers: every device range a kernel touches is verified on the
 // host against the live allocations before the launch
+static void ck_orth(const Ctx& X, int B, int m, int n, MatView A, MatOut Q, cplx* ws, hipStream_t s) {
+  need(X, A.base, span2(m, n, A.rs, A.cs) + (B - 1) * A.sb, "orth A");
+  need(X, Q.base, span2(m, n, Q.rs, Q.cs) + (B - 1) * Q.sb, "orth Q");
+  need(X, ws, (long)orth_ws(B, m, n) - 1, "orth ws");
+  hipEvent_t e = X.t0();
+  if (!orth(B, m, n, A, Q, ws, s)) throw std::logic_error("orth: shape not covered");
+  // counted as the Householder QR with Q that produces the same basis
+  X.t1(e, QTT_K_QR, B * qr_flops(m, n, true), 16.0 * B * 2.0 * m * n);
+}
 static void ck_qr(const Ctx& X, int B, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws,
                   hipStream_t s) {
   const int k = std::min(m, n);
@@ -793,16 +806,27 @@ struct SketchOpts {
   bool no_truncate = false;
   // contractions in FP32 (QR, SVD and the truncation stay FP64)
   bool fp32 = false;
+  // contractions with split-BF16 operands and FP32 accumulation
+  bool bf16 = false;
+  // range-finder bases by CholeskyQR2 (Householder fallback) instead of
+  // Householder QR
+  bool cholqr = false;
 };
 
-// FP32 contractions for the lifetime of the scope (restores the previous
-// setting; off() ends it early)
+// reduced-precision contractions (FP32, split-BF16) for the lifetime of
+// the scope (restores the previous setting; off() ends it early)
 struct Fp32Scope {
   qtt_ctx* c;
-  bool prev;
-  Fp32Scope(const Ctx& X, bool on) : c(X.c), prev(X.c->gemm_fp32) { c->gemm_fp32 = on; }
-  void off() { c->gemm_fp32 = prev; }
-  ~Fp32Scope() { c->gemm_fp32 = prev; }
+  bool prev, prevb;
+  Fp32Scope(const Ctx& X, bool on) : c(X.c), prev(X.c->gemm_fp32), prevb(X.c->gemm_bf16) {
+    c->gemm_fp32 = on;
+    c->gemm_bf16 = false;
+  }
+  void off() {
+    c->gemm_fp32 = prev;
+    c->gemm_bf16 = prevb;
+  }
+  ~Fp32Scope() { off(); }
 };
 
 // Contract Mc (B, lt, rho, r) with x_k -> T1 (B, lt, rho, din, r2), then with
@@ -853,7 +877,7 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
   // orthonormal QR basis (Q^H P).  The Gaussian tensor-train sketches are
   // ill-conditioned (their condition numbers multiply along the train), so
   // the partial sketches W and the sketched unfoldings Y = P W stay FP64.
-  const bool f32 = o.fp32 && !o.exact;
+  const bool f32 = o.fp32 && !o.exact, b16 = o.bf16 && !o.exact;
   Fp32Scope prec(X, false);
   // sketch ranks
   std::vector<int> ell(L + 1, 1);
@@ -973,8 +997,10 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
   for (int k = 0; k < L; ++k) {
     const int rho2 = A.r[k + 1], r2 = x.r[k + 1], dout = A.dout[k];
     X.c->gemm_fp32 = f32;
+    X.c->gemm_bf16 = b16;
     auto P = left_step(X, A, x, k, (cplx*)Mc->p, lt);
     X.c->gemm_fp32 = false;
+    X.c->gemm_bf16 = false;
     if (k == L - 1) {
       set_core(X, *y, k, lt, 1, P);
       break;
@@ -990,16 +1016,25 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
         (cplx*)Y->p, l2, B, (long)m * rho2 * r2, (long)rho2 * r2 * l2, (long)m * l2);
     }
     auto Q = X.buf((size_t)B * m * kq);
-    auto R = X.buf((size_t)B * kq * l2);
-    auto ws = X.buf(qr_ws(B, m, l2));
-    ck_qr(X, B, m, l2, MatView{(cplx*)Y->p, (long)l2, 1, (long)m * l2, 0},
-       MatOut{(cplx*)R->p, (long)l2, 1, (long)kq * l2}, MatOut{(cplx*)Q->p, (long)kq, 1, (long)m * kq},
-       (cplx*)ws->p, X.s());
+    const MatView yv{(cplx*)Y->p, (long)l2, 1, (long)m * l2, 0};
+    const MatOut qv{(cplx*)Q->p, (long)kq, 1, (long)m * kq};
+    if (o.cholqr && !o.exact && orth_ok(m, l2)) {
+      // only the basis is kept (R is not needed): CholeskyQR2 on the matrix
+      // cores, Householder for the matrices it cannot take
+      auto ws = X.buf(orth_ws(B, m, l2));
+      ck_orth(X, B, m, l2, yv, qv, (cplx*)ws->p, X.s());
+    } else {
+      auto R = X.buf((size_t)B * kq * l2);
+      auto ws = X.buf(qr_ws(B, m, l2));
+      ck_qr(X, B, m, l2, yv, MatOut{(cplx*)R->p, (long)l2, 1, (long)kq * l2}, qv, (cplx*)ws->p, X.s());
+    }
     auto Mn = X.buf((size_t)B * kq * rho2 * r2);
     X.c->gemm_fp32 = f32;
+    X.c->gemm_bf16 = b16;
     G(X, kq, rho2 * r2, m, OP_C, (cplx*)Q->p, kq, OP_N, (cplx*)P->p, (long)rho2 * r2, (cplx*)Mn->p,
       (long)rho2 * r2, B, (long)m * kq, (long)m * rho2 * r2, (long)kq * rho2 * r2);
     X.c->gemm_fp32 = false;
+    X.c->gemm_bf16 = false;
     set_core(X, *y, k, lt, kq, Q);
     Mc = Mn;
     lt = kq;
@@ -1291,8 +1326,14 @@ static TTP sfft_op(const Ctx& X, int n, double delta) {
   return t;
 }
 
+static bool device_direction(const Ctx& X, int n, double delta, host::HTT& out);
+
+// The Green factors from the direction train: its TT-SVD on the device, or
+// on the host when a bond rank exceeds the device path
 static TTP green_op(const Ctx& X, int n, double lam0, double mu0, double delta) {
-  host::GreenFactors gf = host::green_factors(n, lam0, mu0, delta);
+  host::HTT nt;
+  host::GreenFactors gf = device_direction(X, n, delta, nt) ? host::green_factors_from(nt, lam0, mu0)
+                                                            : host::green_factors(n, lam0, mu0, delta);
   auto t = std::make_shared<TT>();
   t->kind = 2; t->L = 3 * n + 1; t->B = 1; t->pool = X.c->pool;
   t->gU = upload_op(X, gf.U);
@@ -1532,14 +1573,10 @@ static BufP tsqr_r(const Ctx& X, BufP M, long m, int c) {
   return R;
 }
 
-// TT-SVD of the one-hot tensor chi[p, x] = (phase(x) == p) with dims
-// (nphase, 2, ..., 2), right to left: the unfolding M (nphase 2^(k-1) x
-// 2 r_k) is reduced to R by tsqr_r, R^H goes through the one-sided Jacobi
-// (its left singular vectors are M's right singular vectors V, sorted by
-// singular value), the rank follows the per-bond rule delta / sqrt(L-1)
-// ||chi||, core k = V_r^H and M <- M V_r continues with the next bit.
-// Returns the cores on the host (r_{k-1}, d_k, r_k), real; false when a
-// bond would need more than 160 (the Jacobi's 320 columns).
+// TT-SVD of the one-hot tensor chi[p, x] = (phase(x) == p) (Sec. 4.3
+// binary discretisation) on the device; ||chi|| = sqrt(2^(3n)).
+static bool device_ttsvd(const Ctx& X, BufP T, int n, int P, double thr, host::HTT& out);
+
 static bool device_chi(const Ctx& X, const uint8_t* phase, bool on_device, int n, int P, double delta,
                        host::HTT& out) {
   const long NN = 1L << (3 * n);
@@ -1560,7 +1597,41 @@ static bool device_chi(const Ctx& X, const uint8_t* phase, bool on_device, int n
   check(hipMemcpyAsync(&bad, flag->p, sizeof(int), hipMemcpyDeviceToHost, X.s()), "flag d2h");
   X.sync();
   if (bad) throw std::invalid_argument("phase id out of range");
-  const double thr = delta / std::sqrt((double)(L - 1)) * std::sqrt((double)NN);
+  return device_ttsvd(X, T, n, P, delta / std::sqrt((double)(L - 1)) * std::sqrt((double)NN), out);
+}
+
+// TT-SVD of the unit momentum directions n^sigma_a (App. A, the Green
+// factors' shared train) on the device: every nonzero frequency contributes
+// |n^0|^2 + |n^1|^2 = 2, so ||T|| = sqrt(2 (2^(3n) - 1)).
+static bool device_direction(const Ctx& X, int n, double delta, host::HTT& out) {
+  const long NN = 1L << (3 * n);
+  const int L = 3 * n + 1, N = 1 << n;
+  std::vector<double> f, f2;
+  host::momentum_freqs(n, f, f2);
+  auto fd = X.bufd(2 * (size_t)N);
+  check(hipMemcpyAsync(fd->p, f.data(), N * sizeof(double), hipMemcpyHostToDevice, X.s()), "freq h2d");
+  check(hipMemcpyAsync((double*)fd->p + N, f2.data(), N * sizeof(double), hipMemcpyHostToDevice, X.s()),
+        "freq h2d");
+  auto T = X.buf((size_t)6 * NN);
+  need(X, T->p, 6 * NN - 1, "direction out");
+  direction((const double*)fd->p, (const double*)fd->p + N, n, (cplx*)T->p, X.s());
+  X.sync();  // the host frequency arrays are released on return
+  return device_ttsvd(X, T, n, 6, delta / std::sqrt((double)(L - 1)) * std::sqrt(2.0 * (double)(NN - 1)),
+                      out);
+}
+
+// TT-SVD of a dense device tensor T with dims (P, 2, ..., 2) (3n binary
+// indices, P slowest; complex storage, P 2^(3n) entries), right to left: the
+// unfolding M (P 2^(k-1) x 2 r_k) is reduced to R by tsqr_r, R^H goes
+// through the one-sided Jacobi (its left singular vectors are M's right
+// singular vectors V, sorted by singular value), the rank follows the
+// per-bond rule (singular values beyond rank r carry at most thr in 2-norm,
+// thr = delta / sqrt(L - 1) ||T||), core k = V_r^H and M <- M V_r continues
+// with the next bit.  Returns the cores on the host (r_{k-1}, d_k, r_k);
+// false when a bond would need more than 160 (the Jacobi's 320 columns).
+static bool device_ttsvd(const Ctx& X, BufP T, int n, int P, double thr, host::HTT& out) {
+  const long NN = 1L << (3 * n);
+  const int L = 3 * n + 1;
   host::HTT cores(L);
   BufP M = T;
   long rows = (long)P * NN / 2;
@@ -1661,9 +1732,11 @@ static void check_problem(const qtt_problem* P, const qtt_solve_opts* O) {
   if (!P->phase || !P->lame) throw std::invalid_argument("null phase or lame");
   if (!(O->delta > 0.0) || !(O->tol >= 0.0) || O->max_iter < 0)
     throw std::invalid_argument("bad solve options");
-  if (O->precision != QTT_PREC_FP64 && O->precision != QTT_PREC_FP32)
-    throw std::invalid_argument("precision must be QTT_PREC_FP64 or QTT_PREC_FP32");
+  if (O->precision != QTT_PREC_FP64 && O->precision != QTT_PREC_FP32 && O->precision != QTT_PREC_BF16X3)
+    throw std::invalid_argument("precision must be QTT_PREC_FP64, QTT_PREC_FP32 or QTT_PREC_BF16X3");
   if (O->history && O->history_len < 1) throw std::invalid_argument("history without a length");
+  if (O->orth != QTT_ORTH_HOUSEHOLDER && O->orth != QTT_ORTH_CHOLQR)
+    throw std::invalid_argument("orth must be QTT_ORTH_HOUSEHOLDER or QTT_ORTH_CHOLQR");
   for (int i = 0; i < 2 * P->nphase; ++i)
     if (!std::isfinite(P->lame[i])) throw std::invalid_argument("non-finite phase modulus");
   if (!std::isfinite(P->lame0[0]) || !(P->lame0[1] > 0.0) || !(P->lame0[0] + 2.0 * P->lame0[1] > 0.0))
@@ -1687,6 +1760,8 @@ static SketchOpts sk(const Ctx& X, const qtt_solve_opts* O) {
   s.oversample = std::max(0, O->oversample);
   s.exact = O->exact != 0;
   s.fp32 = O->precision == QTT_PREC_FP32;
+  s.bf16 = O->precision == QTT_PREC_BF16X3;
+  s.cholqr = O->orth == QTT_ORTH_CHOLQR;
   s.seed = O->seed * 1000003ULL + (X.c->sketch_counter++);
   return s;
 }
@@ -2294,6 +2369,7 @@ static void run_groups(qtt_ctx* c, int ng, Fn&& fn) {
     sc->stats_stride = c->stats_stride;
     sc->stats_tick = (unsigned long long)g;
     sc->gemm_fp32 = false;  // set per contraction by the precision scopes
+    sc->gemm_bf16 = false;
     // the sketch seeds follow the parent's counter, one disjoint range per group
     sc->sketch_counter = c->sketch_counter + ((uint64_t)(g + 1) << 40);
     th.emplace_back([&, g, sc]() {
@@ -2507,7 +2583,7 @@ int qtt_zgemm(qtt_ctx* c, int opA, int opB, int M, int N, int K, const double* a
               long ldc, int batch, long sA, long sB, long sC, int path) {
   if (!c || !alpha || !beta || !A || !B || !Cm) return QTT_EINVAL;
   if (M < 0 || N < 0 || K < 1 || batch < 1 || batch > 65535 || opA < 0 || opA > 2 || opB < 0 ||
-      opB > 2 || path < 0 || path > 3 + gemm_num_tiles())
+      opB > 2 || path < 0 || (path > 3 + gemm_num_tiles() && path != QTT_GEMM_PATH_BF16X3))
     return QTT_EINVAL;
   if (lda < (opA == OP_N ? K : M) || ldb < (opB == OP_N ? N : K) || ldc < N) return QTT_EINVAL;
   QTT_TRY(c, {
@@ -2522,8 +2598,9 @@ int qtt_zgemm(qtt_ctx* c, int opA, int opB, int M, int N, int K, const double* a
     if (M == 0 || N == 0) return;
     BufP ws;
     g.fp32 = path == 3;
-    g.tile = path >= 4 ? path - 4 : -1;
-    const int ks = path == 1 ? 1 : gemm_ksplit(M, N, K, batch, g.fp32, g.tile);
+    g.bf16x3 = path == QTT_GEMM_PATH_BF16X3;
+    g.tile = path >= 4 && !g.bf16x3 ? path - 4 : -1;
+    const int ks = path == 1 ? 1 : gemm_ksplit(M, N, K, batch, g.fp32 || g.bf16x3, g.tile);
     if (ks > 1) {
       ws = std::make_shared<Buf>(c->pool, gemm_ws_elems(g, ks) * sizeof(cplx));
       g.ws = (cplx*)ws->p;
@@ -2570,6 +2647,26 @@ int qtt_zqr(qtt_ctx* c, int batch, int m, int n, const void* A, void* R, void* Q
       if (Qo && !qr_form_q(batch, m, n, qo, (cplx*)ws->p, c->stream))
         throw std::invalid_argument("zqr: shape not covered by the matrix-core Q formation");
     }
+    X.sync();  // the workspace is released on return
+  });
+}
+
+int qtt_zorth(qtt_ctx* c, int batch, int m, int n, const void* A, void* Qo, int* fallback) {
+  if (!c || !A || !Qo || batch < 1 || batch > 65535 || m < 1 || n < 1) return QTT_EINVAL;
+  if (!orth_ok(m, n)) {
+    c->err = "qtt_zorth: " + std::to_string(m) + " x " + std::to_string(n) +
+             " outside m >= n, 32 < m <= 192 for 16 < n <= 64, 32 < m <= 168 for 64 < n <= 80";
+    return QTT_EINVAL;
+  }
+  QTT_TRY(c, {
+    Ctx X{c};
+    auto ws = X.buf(orth_ws(batch, m, n));
+    // caller-owned operands (not in the context's pool): launched directly
+    orth(batch, m, n, MatView{(const cplx*)A, (long)n, 1, (long)m * n, 0},
+         MatOut{(cplx*)Qo, (long)n, 1, (long)m * n}, (cplx*)ws->p, c->stream);
+    if (fallback)
+      check(hipMemcpyAsync(fallback, ws->p, batch * sizeof(int), hipMemcpyDeviceToHost, c->stream),
+            "orth flags d2h");
     X.sync();  // the workspace is released on return
   });
 }

@@ -389,6 +389,8 @@ int bitrev(int k, int n) {
 // 1D momentum-order frequency tables: entry k holds the frequency of DFT
 // index (-rev(k)) mod N (Nyquist represented as -N/2) and the same with the
 // Nyquist sign flipped.
+}  // namespace
+
 void momentum_freqs(int n, std::vector<double>& f, std::vector<double>& f2) {
   const int N = 1 << n;
   f.resize(N);
@@ -401,7 +403,6 @@ void momentum_freqs(int n, std::vector<double>& f, std::vector<double>& f2) {
   }
 }
 
-}  // namespace
 
 HTT direction_train(int n, double delta) {
   const int N = 1 << n;
@@ -461,7 +462,10 @@ HTT control_op(const HTT& nt, int dout, int din, const std::vector<double>& coef
 }  // namespace
 
 GreenFactors green_factors(int n, double lam0, double mu0, double delta) {
-  const HTT nt = direction_train(n, delta);
+  return green_factors_from(direction_train(n, delta), lam0, mu0);
+}
+
+GreenFactors green_factors_from(const HTT& nt, double lam0, double mu0) {
   GreenFactors G;
   // U: u^s_j = sum_k tau_{V(j,k)} n^s_k  ; out (s, j), in Voigt J
   {

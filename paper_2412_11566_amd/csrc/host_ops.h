@@ -58,6 +58,11 @@ void green_scalars(double lam0, double mu0, double* inv_2mu0, double* half_c);
 // Joint train of the unit directions n^sigma_a in momentum order (core 0
 // of dimension 6 = (sigma, a)).
 HTT direction_train(int n, double delta);
+// The four factors from an already computed direction train.
+GreenFactors green_factors_from(const HTT& nt, double lam0, double mu0);
+// Momentum frequencies of one axis (SFFT order) and their other Nyquist
+// representative: f[k] in (-N/2, N/2], f2[k] = f[k] except -f[k] at N/2.
+void momentum_freqs(int n, std::vector<double>& f, std::vector<double>& f2);
 
 // Raised stiffness operator C(x) - C0 (or one-hot phase train chi) from a
 // voxel phase array; returns the operator, and the one-hot train in chi.

@@ -684,6 +684,33 @@ void onehot(const uint8_t* phase, long NN, int nphase, cplx* out, int* bad, hipS
   check(hipGetLastError(), "onehot launch");
 }
 
+// Unit momentum directions of the Green factors: out[c * NN + e], e =
+// (x N + y) N + z, c = (sigma, a) with a < 3: f_a / |f| for f = (f[x],
+// f[y], f[z]) (sigma = 0) and the same with the other Nyquist
+// representative f2 (sigma = 1, same |f|); 0 at the zero frequency.  f and
+// f2 hold one axis's momentum frequencies.
+__global__ void k_direction(const double* __restrict__ f, const double* __restrict__ f2, int n, long NN,
+                            cplx* __restrict__ out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NN) return;
+  const int N = 1 << n;
+  const int x = (int)(e >> (2 * n)), y = (int)((e >> n) & (N - 1)), z = (int)(e & (N - 1));
+  const double r2 = f[x] * f[x] + f[y] * f[y] + f[z] * f[z];
+  const double inv = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
+  out[0 * NN + e] = make_double2(f[x] * inv, 0.0);
+  out[1 * NN + e] = make_double2(f[y] * inv, 0.0);
+  out[2 * NN + e] = make_double2(f[z] * inv, 0.0);
+  out[3 * NN + e] = make_double2(f2[x] * inv, 0.0);
+  out[4 * NN + e] = make_double2(f2[y] * inv, 0.0);
+  out[5 * NN + e] = make_double2(f2[z] * inv, 0.0);
+}
+
+void direction(const double* f, const double* f2, int n, cplx* out, hipStream_t s) {
+  const long NN = 1L << (3 * n);
+  hipLaunchKernelGGL(k_direction, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, s, f, f2, n, NN, out);
+  check(hipGetLastError(), "direction launch");
+}
+
 __global__ void k_sum_middle(long total, int outer, int np, int inner, const cplx* in,
                              cplx* out, cplx w) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -647,9 +647,11 @@ __device__ __forceinline__ cplx quad_sum(cplx p) {
 
 template <int RB, int RPL, int CG>
 __global__ __launch_bounds__(RB * CG * 64) void k_qr_2d(int m, int n, MatView A, MatOut R, MatOut Q,
-                                                        cplx* vout, long vsz) {
+                                                        cplx* vout, long vsz, const int* only) {
   constexpr int NC = 16 * CG, RBS = 4 * RPL, MR = RB * RBS;
   const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  // only the matrices whose flag is set (the CholeskyQR kernel's fallbacks)
+  if (only != nullptr && only[b] == 0) return;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int rb = w / CG, cg = w % CG;
   const int rs = lane & 3, cl = lane >> 2;
@@ -1316,10 +1318,10 @@ bool qr_1r_dispatch(int batch, int m, int n, const MatView& A, const MatOut& R, 
 
 template <int RB, int RPL, int CG>
 bool try_qr_2d(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q,
-               hipStream_t s, cplx* vout = nullptr) {
+               hipStream_t s, cplx* vout = nullptr, const int* only = nullptr) {
   if (m > RB * 4 * RPL || n > 16 * CG) return false;
   hipLaunchKernelGGL((k_qr_2d<RB, RPL, CG>), dim3(batch), dim3(RB * CG * 64), 0, s, m, n, A, R, Q, vout,
-                     (long)qr_ws_per_matrix(m, n));
+                     (long)qr_ws_per_matrix(m, n), only);
   check(hipGetLastError(), "qr_2d launch");
   return true;
 }
@@ -1613,11 +1615,11 @@ size_t qr_fast_ws(int batch, int m, int n) {
 
 template <int RB, int CG>
 bool qr2d_any(int batch, int m, int n, const MatView& A, const MatOut& R, const MatOut& Q, hipStream_t s,
-              cplx* vout = nullptr) {
-  return try_qr_2d<RB, 4, CG>(batch, m, n, A, R, Q, s, vout) ||
-         try_qr_2d<RB, 8, CG>(batch, m, n, A, R, Q, s, vout) ||
-         try_qr_2d<RB, 12, CG>(batch, m, n, A, R, Q, s, vout) ||
-         try_qr_2d<RB, 14, CG>(batch, m, n, A, R, Q, s, vout);
+              cplx* vout = nullptr, const int* only = nullptr) {
+  return try_qr_2d<RB, 4, CG>(batch, m, n, A, R, Q, s, vout, only) ||
+         try_qr_2d<RB, 8, CG>(batch, m, n, A, R, Q, s, vout, only) ||
+         try_qr_2d<RB, 12, CG>(batch, m, n, A, R, Q, s, vout, only) ||
+         try_qr_2d<RB, 14, CG>(batch, m, n, A, R, Q, s, vout, only);
 }
 
 bool qr_one_rowblock(int batch, int m, int n, const MatView& A, const MatOut& R, cplx* vout,
@@ -1625,17 +1627,17 @@ bool qr_one_rowblock(int batch, int m, int n, const MatView& A, const MatOut& R,
   return qr_1r_dispatch(batch, m, n, A, R, vout, s);
 }
 
-bool qr_2d_vectors(int batch, int m, int n, MatView A, MatOut R, cplx* ws, hipStream_t s) {
+bool qr_2d_vectors(int batch, int m, int n, MatView A, MatOut R, cplx* ws, hipStream_t s, const int* only) {
   // one wave per column group wins only for short columns (24 x 24: 42 us
   // against 59 us; 160 x 80: 373 us against 189 us for R)
-  if (m <= 32 && qr_one_rowblock(batch, m, n, A, R, ws, s)) return true;
+  if (only == nullptr && m <= 32 && qr_one_rowblock(batch, m, n, A, R, ws, s)) return true;
   const MatOut Q{nullptr, 0, 0, 0};
   switch ((n + 15) / 16) {
-    case 2: return qr2d_any<8, 2>(batch, m, n, A, R, Q, s, ws);
-    case 3: return qr2d_any<5, 3>(batch, m, n, A, R, Q, s, ws);
-    case 4: return qr2d_any<4, 4>(batch, m, n, A, R, Q, s, ws);
-    case 5: return qr2d_any<3, 5>(batch, m, n, A, R, Q, s, ws);
-    case 6: return qr2d_any<2, 6>(batch, m, n, A, R, Q, s, ws);
+    case 2: return qr2d_any<8, 2>(batch, m, n, A, R, Q, s, ws, only);
+    case 3: return qr2d_any<5, 3>(batch, m, n, A, R, Q, s, ws, only);
+    case 4: return qr2d_any<4, 4>(batch, m, n, A, R, Q, s, ws, only);
+    case 5: return qr2d_any<3, 5>(batch, m, n, A, R, Q, s, ws, only);
+    case 6: return qr2d_any<2, 6>(batch, m, n, A, R, Q, s, ws, only);
     default: return false;
   }
 }

@@ -385,6 +385,208 @@ __global__ __launch_bounds__(NTHR) void k_zgemm_mfma32(GemmArgs g, int ksplit, i
   span_end(g.span);
 }
 
+// Split-BF16 operands on v_mfma_f32_16x16x32_bf16 with FP32 accumulation
+// (the contraction precision of QTT_PREC_BF16X3): every operand x is
+// rounded to float and split as x = hi + lo, hi = bf16(x), lo =
+// bf16(x - hi), so hi + lo carries 16 significant bits; each real product
+// a b is formed as hi_a hi_b + hi_a lo_b + lo_a hi_b (the lo lo term, of
+// relative size 2^-16, is dropped), three bf16 products per real product
+// and twelve per complex block.  Same 64 x 64 tile and wave grid as the
+// FP32 kernel, with K staged 32 at a time (one instruction's depth).
+// Operands sit in LDS k-contiguous, one row of 32 (+ 8 pad) bf16 per tile
+// row, so a lane's eight K values are one 16-byte read and the sixteen rows
+// a quarter-wave reads fall in distinct banks (80-byte stride).  Lane
+// layout of the instruction:
+//   A: lane l holds A[l % 16][8 (l / 16) .. 8 (l / 16) + 7];
+//   B: lane l holds B[8 (l / 16) .. 8 (l / 16) + 7][l % 16];
+//   D: lane l, register r holds D[4 (l / 16) + r][l % 16].
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+constexpr int KB = 32, KBP = KB + 8;
+constexpr int PER_B = MT * KB / NTHR;  // staged complex elements per thread and operand (8)
+
+__device__ __forceinline__ void split_bf16(double x, __bf16& hi, __bf16& lo) {
+  const float f = (float)x;
+  hi = (__bf16)f;
+  lo = (__bf16)(f - (float)hi);
+}
+__device__ __forceinline__ bf8 neg8(bf8 v) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  u4 b = __builtin_bit_cast(u4, v);
+  b ^= 0x80008000u;
+  return __builtin_bit_cast(bf8, b);
+}
+
+__global__ __launch_bounds__(NTHR) void k_zgemm_bf16x3(GemmArgs g, int ksplit, int kchunk) {
+  // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo
+  __shared__ __attribute__((aligned(16))) __bf16 As[4][MT][KBP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[4][NT][KBP];
+  span_begin(g.span);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int m0 = blockIdx.y * MT, n0 = blockIdx.x * NT;
+  const int bz = blockIdx.z / ksplit, slice = blockIdx.z % ksplit;
+  long oa, ob, oc;
+  gemm_batch_offsets(g, bz, oa, ob, oc);
+  const cplx* A = g.A + oa;
+  const cplx* B = g.B + ob;
+  const int kbeg = slice * kchunk, kend = min(g.K, kbeg + kchunk);
+
+  fv4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = fv4{0.f, 0.f, 0.f, 0.f};
+      ci[i][j] = fv4{0.f, 0.f, 0.f, 0.f};
+    }
+  cplx ra[PER_B], rb[PER_B];
+  unsigned oka = 0u, okb = 0u;
+  // element e of a stage: A row mm / K index kk, B column nn / K index kk;
+  // the K index runs fastest where the operand is K-contiguous in memory
+  auto fetch = [&](int k0) {
+    oka = 0u;
+    okb = 0u;
+#pragma unroll
+    for (int t = 0; t < PER_B; ++t) {
+      const int e = tid + NTHR * t;
+      int mm, kk;
+      if (g.opA == OP_N) { kk = e % KB; mm = e / KB; }
+      else { mm = e % MT; kk = e / MT; }
+      const int m = m0 + mm, k = k0 + kk;
+      const bool ok = m < g.M && k < kend;
+      const long idx = g.opA == OP_N ? (long)m * g.lda + k : (long)k * g.lda + m;
+      ra[t] = A[ok ? idx : 0];
+      oka |= ok ? (1u << t) : 0u;
+    }
+#pragma unroll
+    for (int t = 0; t < PER_B; ++t) {
+      const int e = tid + NTHR * t;
+      int nn, kk;
+      if (g.opB == OP_N) { nn = e % NT; kk = e / NT; }
+      else { kk = e % KB; nn = e / KB; }
+      const int n = n0 + nn, k = k0 + kk;
+      const bool ok = n < g.N && k < kend;
+      const long idx = g.opB == OP_N ? (long)k * g.ldb + n : (long)n * g.ldb + k;
+      rb[t] = B[ok ? idx : 0];
+      okb |= ok ? (1u << t) : 0u;
+    }
+  };
+  const double sa = g.opA == OP_C ? -1.0 : 1.0, sb = g.opB == OP_C ? -1.0 : 1.0;
+  auto stage = [&]() {
+#pragma unroll
+    for (int t = 0; t < PER_B; ++t) {
+      const int e = tid + NTHR * t;
+      int mm, kk;
+      if (g.opA == OP_N) { kk = e % KB; mm = e / KB; }
+      else { mm = e % MT; kk = e / MT; }
+      const bool ok = (oka >> t) & 1u;
+      __bf16 h, l;
+      split_bf16(ok ? ra[t].x : 0.0, h, l);
+      As[0][mm][kk] = h;
+      As[1][mm][kk] = l;
+      split_bf16(ok ? sa * ra[t].y : 0.0, h, l);
+      As[2][mm][kk] = h;
+      As[3][mm][kk] = l;
+    }
+#pragma unroll
+    for (int t = 0; t < PER_B; ++t) {
+      const int e = tid + NTHR * t;
+      int nn, kk;
+      if (g.opB == OP_N) { nn = e % NT; kk = e / NT; }
+      else { kk = e % KB; nn = e / KB; }
+      const bool ok = (okb >> t) & 1u;
+      __bf16 h, l;
+      split_bf16(ok ? rb[t].x : 0.0, h, l);
+      Bs[0][nn][kk] = h;
+      Bs[1][nn][kk] = l;
+      split_bf16(ok ? sb * rb[t].y : 0.0, h, l);
+      Bs[2][nn][kk] = h;
+      Bs[3][nn][kk] = l;
+    }
+  };
+  const int kq = 8 * (lane >> 4);
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += KB) {
+    stage();
+    __syncthreads();
+    if (k0 + KB < kend) fetch(k0 + KB);
+    bf8 a[2][4], b[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int mm = wm * 32 + i * 16 + (lane & 15);
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) a[i][pl] = *(const bf8*)&As[pl][mm][kq];
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int nn = wn * 32 + j * 16 + (lane & 15);
+#pragma unroll
+      for (int pl = 0; pl < 4; ++pl) b[j][pl] = *(const bf8*)&Bs[pl][nn][kq];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bf8 nih = neg8(a[i][2]), nil = neg8(a[i][3]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        // re += Ar Br - Ai Bi;  im += Ar Bi + Ai Br  (hi hi, hi lo, lo hi each)
+        fv4 r = cr[i][j], m = ci[i][j];
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][0], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][1], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][0], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[j][2], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, b[j][3], r, 0, 0, 0);
+        r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nil, b[j][2], r, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][2], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][3], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][2], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][0], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][1], m, 0, 0, 0);
+        m = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][3], b[j][0], m, 0, 0, 0);
+        cr[i][j] = r;
+        ci[i][j] = m;
+      }
+    }
+    __syncthreads();
+  }
+  if (ksplit > 1) {
+    cplx* P = g.ws + ((long)slice * gemm_nbatch(g) + bz) * (long)g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+          const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+          if (m < g.M && n < g.N) P[(long)m * g.N + n] = make_double2(cr[i][j][r], ci[i][j][r]);
+        }
+    span_end(g.span);
+    return;
+  }
+  cplx* C = g.C + oc;
+  const bool zb = (g.beta.x == 0.0 && g.beta.y == 0.0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (m >= g.M || n >= g.N) continue;
+        const double re = cr[i][j][r], im = ci[i][j][r];
+        cplx out = make_double2(g.alpha.x * re - g.alpha.y * im, g.alpha.x * im + g.alpha.y * re);
+        cplx* cp = C + (long)m * g.ldc + n;
+        if (!zb) {
+          const cplx c0 = *cp;
+          out.x += g.beta.x * c0.x - g.beta.y * c0.y;
+          out.y += g.beta.x * c0.y + g.beta.y * c0.x;
+        }
+        *cp = out;
+      }
+  span_end(g.span);
+}
+
 // C = alpha * sum_s ws[s] + beta * C, slices added in order s = 0, 1, ...
 __global__ __launch_bounds__(256) void k_zgemm_reduce(GemmArgs g, int ksplit) {
   const long mn = (long)g.M * g.N, nb = gemm_nbatch(g);
@@ -527,22 +729,27 @@ bool gemm_mfma_main(const GemmArgs& g, hipStream_t s, int& ks_used) {
   ks_used = 1;
   if (!gemm_mfma_ok(g.M, g.N, g.K)) return false;
   const long nb = gemm_nbatch(g);
-  Plan pl = g.fp32 ? Plan{-1, 1} : plan_fp64(g.M, g.N, g.K, nb);
-  if (!g.fp32 && g.tile >= 0) {
+  const bool low = g.fp32 || g.bf16x3;
+  Plan pl = low ? Plan{-1, 1} : plan_fp64(g.M, g.N, g.K, nb);
+  if (!low && g.tile >= 0) {
     if (g.tile >= kNumTiles) return false;
     const TileV& t = kTiles[g.tile];
     if ((g.M + t.mt() - 1) / t.mt() > 65535 || (g.N + t.nt() - 1) / t.nt() > 65535) return false;
     pl.v = g.tile;
   }
-  if (g.fp32 && (g.M + MT - 1) / MT > 65535) return false;
+  if ((g.fp32 || g.bf16x3) && (g.M + MT - 1) / MT > 65535) return false;
   // the split the caller sized the workspace for (gemm_ksplit), else none
   int ks = g.ksplit > 1 && g.ws ? g.ksplit : 1;
   if (nb * ks > 65535) ks = 1;
   // slice length: a multiple of the stage depth
   const int per = (g.K + ks - 1) / ks;
-  const int kchunk = (per + KT - 1) / KT * KT;
+  const int kst = g.bf16x3 ? KB : KT;
+  const int kchunk = (per + kst - 1) / kst * kst;
   ks = (g.K + kchunk - 1) / kchunk;
-  if (g.fp32) {
+  if (g.bf16x3) {
+    dim3 grid((g.N + NT - 1) / NT, (g.M + MT - 1) / MT, (unsigned)(nb * ks));
+    hipLaunchKernelGGL(k_zgemm_bf16x3, grid, dim3(NTHR), 0, s, g, ks, kchunk);
+  } else if (g.fp32) {
     dim3 grid((g.N + NT - 1) / NT, (g.M + MT - 1) / MT, (unsigned)(nb * ks));
     hipLaunchKernelGGL(k_zgemm_mfma32, grid, dim3(NTHR), 0, s, g, ks, kchunk);
   } else {

@@ -463,9 +463,11 @@ __global__ __launch_bounds__(RB * CG * 64) void k_qr_blk(int m, int n, MatView A
 // unit of its own and applies only the panels p <= its group (a later panel
 // leaves an identity block untouched); RB waves split the rows.
 template <int RB, int RPL>
-__global__ __launch_bounds__(RB * 64) void k_qr_formq1(int m, int n, MatOut Q, cplx* ws, long wsz) {
+__global__ __launch_bounds__(RB * 64) void k_qr_formq1(int m, int n, MatOut Q, cplx* ws, long wsz,
+                                                      const int* only) {
   constexpr int NQ = RPL / 4;
   const int b = blockIdx.x, cg = blockIdx.y, tid = threadIdx.x, lane = tid & 63;
+  if (only != nullptr && only[b] == 0) return;
   const int rb = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int cl0 = lane & 15, rq0 = lane >> 4;
   const int col = cg * 16 + cl0;
@@ -549,7 +551,7 @@ __global__ __launch_bounds__(RB * 64) void k_qr_formq1(int m, int n, MatOut Q, c
 #undef AI
 
 template <int RB, int RPL>
-bool try_qr_formq1(int batch, int m, int n, const MatOut& Q, cplx* ws, hipStream_t s) {
+bool try_qr_formq1(int batch, int m, int n, const MatOut& Q, cplx* ws, hipStream_t s, const int* only) {
   constexpr int MR = RB * 4 * RPL;
   const int k = m < n ? m : n, np = (k + 15) / 16;
   if (m > MR) return false;
@@ -564,16 +566,16 @@ bool try_qr_formq1(int batch, int m, int n, const MatOut& Q, cplx* ws, hipStream
   }();
   (void)attr;
   hipLaunchKernelGGL((k_qr_formq1<RB, RPL>), dim3(batch, np), dim3(RB * 64), shm, s, m, n, Q, ws,
-                     (long)qr_ws_per_matrix(m, n));
+                     (long)qr_ws_per_matrix(m, n), only);
   check(hipGetLastError(), "qr_formq1 launch");
   return true;
 }
 
 // row blocks of 4 RPL rows: 4 waves up to 128 rows, then 5 or 6 waves of
 // 32 rows (measured at 160 x 80 and 160 x 64 against 2, 4 and 10 waves)
-bool qr_formq_split(int batch, int m, int n, const MatOut& Q, cplx* ws, hipStream_t s) {
-  return try_qr_formq1<4, 4>(batch, m, n, Q, ws, s) || try_qr_formq1<4, 8>(batch, m, n, Q, ws, s) ||
-         try_qr_formq1<5, 8>(batch, m, n, Q, ws, s) || try_qr_formq1<6, 8>(batch, m, n, Q, ws, s);
+bool qr_formq_split(int batch, int m, int n, const MatOut& Q, cplx* ws, hipStream_t s, const int* only) {
+  return try_qr_formq1<4, 4>(batch, m, n, Q, ws, s, only) || try_qr_formq1<4, 8>(batch, m, n, Q, ws, s, only) ||
+         try_qr_formq1<5, 8>(batch, m, n, Q, ws, s, only) || try_qr_formq1<6, 8>(batch, m, n, Q, ws, s, only);
 }
 
 template <int RB, int RPL, int CG>
@@ -614,10 +616,10 @@ bool qr_blk_cg(int batch, int m, int n, const MatView& A, const MatOut& R, const
 
 }  // namespace
 
-bool qr_form_q(int batch, int m, int n, MatOut Q, cplx* ws, hipStream_t s) {
+bool qr_form_q(int batch, int m, int n, MatOut Q, cplx* ws, hipStream_t s, const int* only) {
   if (batch <= 0 || m <= 0 || n <= 0) return true;
   if (m < n || n <= 16 || n > 96 || m > 192) return false;
-  return qr_formq_split(batch, m, n, Q, ws, s);
+  return qr_formq_split(batch, m, n, Q, ws, s, only);
 }
 
 bool qr_blocked(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws, hipStream_t s) {

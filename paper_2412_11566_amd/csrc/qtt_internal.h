@@ -43,6 +43,9 @@ struct GemmArgs {
   // matrix-core path only: FP32 operands and accumulation (the vector
   // kernel for thin shapes always computes in FP64)
   bool fp32 = false;
+  // matrix-core path only: split-BF16 operands (hi + lo, three bf16
+  // products per real product) with FP32 accumulation
+  bool bf16x3 = false;
   // split-K workspace of the matrix-core path (gemm_ws_elems entries for
   // ksplit slices); ksplit = 1 or ws = nullptr: no split
   cplx* ws = nullptr;
@@ -126,16 +129,32 @@ bool qr_blocked(int batch, int m, int n, MatView A, MatOut R, MatOut Q, cplx* ws
 // R of the unblocked 2D-wave register kernel, with the Householder
 // vectors and tau per 16-column panel written to the workspace (layout of
 // qr_ws_per_matrix's blocked part) instead of Q; false when no variant
-// holds the shape (16 < n <= 96).
-bool qr_2d_vectors(int batch, int m, int n, MatView A, MatOut R, cplx* ws, hipStream_t s);
+// holds the shape (16 < n <= 96).  With `only` (a device array of batch
+// flags) the matrices whose flag is zero are skipped.
+bool qr_2d_vectors(int batch, int m, int n, MatView A, MatOut R, cplx* ws, hipStream_t s,
+                   const int* only = nullptr);
 // R (and, with vout, the panel vectors) from the kernel with one wave per
 // 16-column group holding all rows (n <= 96, m <= 160); false otherwise.
 bool qr_one_rowblock(int batch, int m, int n, const MatView& A, const MatOut& R, cplx* vout,
                      hipStream_t s);
 // Q (m x k) from those vectors: T of each panel (compact WY), then the
 // block reflectors applied on the matrix cores in reverse panel order;
-// false when the shape is outside the blocked kernel's range.
-bool qr_form_q(int batch, int m, int n, MatOut Q, cplx* ws, hipStream_t s);
+// false when the shape is outside the blocked kernel's range.  `only` as
+// for qr_2d_vectors.
+bool qr_form_q(int batch, int m, int n, MatOut Q, cplx* ws, hipStream_t s, const int* only = nullptr);
+// Orthonormal basis of the column space of batched m x n matrices (m >= n):
+// Q (m x n) with Q^H Q = I and range(Q) = range(A), no R.  CholeskyQR2 on
+// the FP64 matrix cores (kernels_cholqr.hip), one workgroup per matrix;
+// a matrix whose Gram is too ill-conditioned for it (the first Cholesky
+// breaks down, or the columns after the first pass are not within 0.5 of
+// orthonormal in Frobenius norm) is flagged and factored by the Householder
+// kernels instead, in the same stream order.  Covers 32 < m <= 192 for
+// 16 < n <= 64 and 32 < m <= 168 for 64 < n <= 80 (m >= n); false
+// otherwise.  `ws` holds orth_ws(batch, m, n) entries;
+// on return its first batch ints hold the flags (1 = Householder).
+bool orth(int batch, int m, int n, MatView A, MatOut Q, cplx* ws, hipStream_t s);
+size_t orth_ws(int batch, int m, int n);
+bool orth_ok(int m, int n);
 // Blocked QR for large shapes (m >= n, m <= 320, n <= 160): the matrix in
 // the workspace, one workgroup walking over 16-column panels with the
 // trailing updates on the matrix cores, Q formed afterwards from the
@@ -259,6 +278,10 @@ void sum_middle(int batch, int outer, int np, int inner, const cplx* in,
 // out[p * NN + v] = (phase[v] == p) for p < nphase (device arrays); sets
 // *bad (device int) when a phase id is >= nphase.
 void onehot(const uint8_t* phase, long NN, int nphase, cplx* out, int* bad, hipStream_t s);
+// Unit momentum directions n^sigma_a of the Green factors on the 2^n grid
+// (6 x 2^(3n) entries, control index (sigma, a) slowest, then x, y, z
+// bits); f, f2: device arrays of one axis's frequencies (2^n each).
+void direction(const double* f, const double* f2, int n, cplx* out, hipStream_t s);
 
 void check(hipError_t e, const char* what);
 

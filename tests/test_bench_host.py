@@ -20,8 +20,10 @@ def test_more_than_one_gpu_is_refused():
 
 def test_traffic_reported_only_for_the_measured_source_and_groups():
     for (family, streams), m in bench.MEASURED_TRAFFIC.items():
-        with open(os.path.join(ROOT, m["source"]), "rb") as f:
-            same = hashlib.sha256(f.read()).hexdigest() == m["sha256"]
+        same = True
+        for src, sha in m["sources"].items():
+            with open(os.path.join(ROOT, src), "rb") as f:
+                same = same and hashlib.sha256(f.read()).hexdigest() == sha
         assert bench.measured_traffic(family, streams) == (m["bytes_per_launch"] if same else None)
         assert bench.measured_traffic(family, streams + 1) is None
-    assert bench.measured_traffic("qr", 3) is None
+    assert bench.measured_traffic("jacobi", 3) is None

@@ -1,6 +1,6 @@
 """The 64^3 workloads of the precision comparison (FP64 cores against FP32
-contractions with FP64 rounding), cap 64, rounding accuracy 1e-8, contrast
-100 (matrix E = 1, nu = 0.3; inclusion E = 100, nu = 0.2).
+and split-BF16 contractions with FP64 rounding), cap 64, rounding accuracy
+1e-8, contrast 100 (matrix E = 1, nu = 0.3; inclusion E = 100, nu = 0.2).
 
 * Laminate (layers normal to x, volume fraction 0.5): the strain depends on
   x only, so the cap never binds; C_eff must match the converged dense
@@ -51,8 +51,26 @@ def test_c1_laminate_64(ctx, prec):
     assert rel(C, ref) < bar
 
 
+def test_c1_laminate_64_split_bf16(ctx):
+    """Split-BF16 contractions: each real product carries up to ~3 * 2^-16 =
+    4.6e-5 relative error, which the contrast-100 fixed point turns into a
+    relative-update floor of a few 1e-4, so the solve stops at max_iter
+    (QTT_ENOCONV) with bounded updates, and C_eff stays within 2e-4 of the
+    closed form (2e-5 to 6e-5 measured)."""
+    p = M.config_c1_laminate()
+    opts = q.SolveOptions(delta=1e-8, tol=1e-5, cap=64, max_iter=30, precision=q.QTT_PREC_BF16X3,
+                          streams=3)
+    C, rep, _ = q.ls_solve(ctx, p.phase, p.lame, p.lame0, opts)
+    assert rep.status in (0, q._c.QTT_ENOCONV)
+    assert max(rep.residual) < 1e-3
+    ref = B.laminate_x(B.iso_phases(p.lame), [p.volume_fraction(0), p.volume_fraction(1)])
+    assert rel(C, ref) < 2e-4
+    assert rel(C, _golden("c1lam")) < 2e-4
+
+
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("prec", [q.QTT_PREC_FP64, q.QTT_PREC_FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("prec", [q.QTT_PREC_FP64, q.QTT_PREC_FP32, q.QTT_PREC_BF16X3],
+                         ids=["fp64", "fp32", "bf16x3"])
 def test_c1_sphere_64_cap_bound(ctx, prec):
     p = M.config_c1_sphere()
     opts = q.SolveOptions(delta=1e-8, tol=1e-6, cap=64, max_iter=60, precision=prec, streams=3)

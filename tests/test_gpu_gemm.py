@@ -74,6 +74,39 @@ def test_zgemm_fp32_matrix_cores(ctx, ops):
         assert np.abs(out - ref).max() > 0.0   # really computed in FP32
 
 
+@pytest.mark.parametrize("ops", ["NN", "CN", "NT", "TC"])
+def test_zgemm_split_bf16(ctx, ops):
+    """Split-BF16 operands with FP32 accumulation (the QTT_PREC_BF16X3
+    contractions).  Each operand is hi + lo in bf16 (relative error 2^-16
+    after the split) and the dropped lo*lo term is of the same order, so a
+    real product carries ~3 * 2^-16 relative error at worst and the K-sum
+    grows like sqrt(K) for random signs: |error| / sqrt(K) < 2e-4 for O(1)
+    entries.  Beside that bound: plain bf16 (2^-8) would miss it by far, and
+    the result must be less accurate than FP32 contractions (it is really
+    the split-BF16 path)."""
+    import torch
+    import paper_2412_11566_amd as q
+    rng = np.random.default_rng(11)
+    for (M, N, K) in [(32, 32, 8), (70, 45, 33), (160, 80, 800), (128, 256, 96), (64, 64, 2000),
+                      (17, 161, 31), (96, 40, 517)]:
+        a = _rand(rng, 2, *((M, K) if ops[0] == "N" else (K, M)))
+        b = _rand(rng, 2, *((K, N) if ops[1] == "N" else (N, K)))
+        ref = _op(a, ops[0]) @ _op(b, ops[1])
+        A = torch.from_numpy(a).cuda()
+        B = torch.from_numpy(b).cuda()
+        Cm = torch.full((2, M, N), 0.5 + 0.25j, dtype=torch.complex128, device="cuda")
+        c0 = Cm.cpu().numpy()
+        q.zgemm(ctx, A, B, Cm, ops[0], ops[1], 0.5 - 1.0j, 2.0, path=q._c.QTT_GEMM_PATH_BF16X3)
+        out = Cm.cpu().numpy()
+        want = (0.5 - 1.0j) * ref + 2.0 * c0
+        err = np.abs(out - want).max() / np.sqrt(K)
+        assert err < 2e-4, (M, N, K, ops, err)
+        C32 = torch.zeros((2, M, N), dtype=torch.complex128, device="cuda")
+        q.zgemm(ctx, A, B, C32, ops[0], ops[1], 1.0, 0.0, path=3)
+        e32 = np.abs(C32.cpu().numpy() - ref).max()
+        assert np.abs(out - want).max() > e32
+
+
 def test_zgemm_mfma_rejects_small(ctx):
     import torch
     import paper_2412_11566_amd as q

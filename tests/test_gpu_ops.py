@@ -175,8 +175,11 @@ def test_hadamard(ctx):
             assert rel(dense(y.cores(), b).reshape(6, N, N, N), ref) < 1e-11
 
 
-def test_green_apply(ctx):
-    n = 2
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_green_apply(ctx, n):
+    """The Green operator, its four factors assembled from the direction
+    train that the device TT-SVD builds, against the oracle's Green table
+    (direct scheme, Nyquist rule) on every voxel."""
     N = 1 << n
     lam0, mu0 = 2.3, 1.4
     rng = np.random.default_rng(8)

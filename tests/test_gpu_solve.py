@@ -42,18 +42,37 @@ def test_c0_exact_same_iterations(ctx):
     assert rel(C, Cref) < 1e-10
 
 
-def test_c0_delta_1e8(ctx):
+@pytest.mark.parametrize("orth", ["cholqr", "householder"])
+def test_c0_delta_1e8(ctx, orth):
     """16^3 sphere at rounding tolerance 1e-8 with a cap that does not bind
     (128 = largest structural rank): C_eff within 1e-5 of the converged
-    dense basic scheme; symmetric."""
+    dense basic scheme; symmetric.  Both orthonormalisations of the range
+    finder (CholeskyQR2 with Householder fallback, Householder only)."""
     p = M.config_c0()
-    opts = q.SolveOptions(delta=1e-8, tol=1e-8, cap=128, max_iter=300)
+    mode = q.QTT_ORTH_CHOLQR if orth == "cholqr" else q.QTT_ORTH_HOUSEHOLDER
+    opts = q.SolveOptions(delta=1e-8, tol=1e-8, cap=128, max_iter=300, orth=mode)
     C, rep, _ = q.ls_solve(ctx, p.phase, p.lame, p.lame0, opts)
     Cref, it = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=1e-12)
     assert rep.status == 0
     assert max(rep.iterations) <= 80
     assert rel(C, Cref) < 1e-5
     assert np.abs(C - C.T).max() < 1e-5 * np.abs(C).max()
+
+
+def test_c0_split_bf16_contractions(ctx):
+    """Split-BF16 contractions (hi + lo bf16 operands, FP32 accumulation;
+    sketches, QR, SVD and residuals FP64) on the 16^3 sphere with a cap that
+    does not bind.  A split-BF16 real product carries up to ~3 * 2^-16 =
+    4.6e-5 relative error, so the relative update cannot fall much below
+    1e-5 (the FP64 solve reaches 1e-8) and the solve runs to tol 1e-4; C_eff
+    within 1e-4 of the converged dense scheme (about 1e-5 measured)."""
+    p = M.config_c0()
+    opts = q.SolveOptions(delta=1e-8, tol=1e-4, cap=128, max_iter=200, precision=q.QTT_PREC_BF16X3)
+    C, rep, _ = q.ls_solve(ctx, p.phase, p.lame, p.lame0, opts)
+    Cref, _ = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=1e-12)
+    assert rep.status == 0
+    assert rel(C, Cref) < 1e-4
+    assert np.abs(C - C.T).max() < 1e-4 * np.abs(C).max()
 
 
 def test_c0_cap32_binding(ctx):
