@@ -72,12 +72,20 @@ extern "C" {
 #define QTT_PREC_BF16X3 2
 
 /* orthonormalisation of the range finder's sketched unfoldings (Sec. 3:
- * only the basis is kept, not R).  QTT_ORTH_HOUSEHOLDER (default):
- * Householder QR; QTT_ORTH_CHOLQR: CholeskyQR2 on the FP64 matrix cores
- * where the Gram matrix is well enough conditioned, Householder QR for the
- * rest (qtt_zorth).  The exact sketch always uses Householder. */
-#define QTT_ORTH_HOUSEHOLDER 0
-#define QTT_ORTH_CHOLQR      1
+ * only the basis is kept, not R).  The exact sketch always uses
+ * Householder.
+ * QTT_ORTH_AUTO (default): CholeskyQR2 on the FP64 matrix cores (qtt_zorth
+ *   path 2) in the fixed-point updates whose iterate is cap-bound (a bond
+ *   rank at a cap below that bond's structural rank, and the previous
+ *   update's truncation discarded at least 1e-5 of it), where a column of the
+ *   sketch that depends on the earlier ones to rounding is dropped (zero
+ *   column of the basis) instead of refactored; Householder elsewhere.
+ * QTT_ORTH_HOUSEHOLDER: Householder QR throughout.
+ * QTT_ORTH_CHOLQR: CholeskyQR2 throughout, Householder QR for the matrices
+ *   whose Gram is too ill-conditioned for it (qtt_zorth path 0). */
+#define QTT_ORTH_AUTO        0
+#define QTT_ORTH_HOUSEHOLDER 1
+#define QTT_ORTH_CHOLQR      2
 
 typedef struct qtt_ctx qtt_ctx;
 typedef struct qtt_tensor qtt_tensor;
@@ -393,9 +401,16 @@ int qtt_zjacobi(qtt_ctx* ctx, int batch, int n, const void* A, void* U,
  * factored by Householder QR instead.  fallback (host array of batch ints,
  * may be NULL) receives 1 for each matrix that took Householder, else 0.
  * Same layouts as qtt_zqr; QTT_EINVAL outside the covered shapes.
- * Synchronises the stream before returning. */
+ * path 0: each pass spread over the device (partial Grams per 32-row
+ * slice, one workgroup per matrix for the Cholesky and R^-1, the products
+ * on the matrix-core GEMM; the library's choice); 1: one fused workgroup
+ * per matrix; 2: as 0, but a column dependent on the earlier ones to
+ * rounding (pivot at most 1e-13 of the largest) gives an exactly zero
+ * column of Q instead of a fallback (Q^H Q is I on the kept columns, zero
+ * on the dropped ones; the form the range finder uses).  Synchronises the
+ * stream before returning. */
 int qtt_zorth(qtt_ctx* ctx, int batch, int m, int n, const void* A, void* Q,
-              int* fallback);
+              int* fallback, int path);
 
 /* qtt_zqr without any allocation, for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that

@@ -19,7 +19,7 @@ import numpy as np
 
 from . import _capi as _c
 from ._capi import (QTT_EXACT, QTT_INVERSE, QTT_NO_ROUND, QTT_OK, QTT_ENOCONV,
-                    QTT_ORTH_CHOLQR, QTT_ORTH_HOUSEHOLDER, QTT_PREC_BF16X3, QTT_PREC_FP32,
+                    QTT_ORTH_AUTO, QTT_ORTH_CHOLQR, QTT_ORTH_HOUSEHOLDER, QTT_PREC_BF16X3, QTT_PREC_FP32,
                     QTT_PREC_FP64)
 
 __all__ = [
@@ -29,7 +29,7 @@ __all__ = [
     "tt_mean_apply", "ls_solve", "ls_adjoint", "batch_solve", "Prepared", "prepare",
     "ls_solve_prepared", "stats_enable", "stats_get", "stats_reset", "tensor_create",
     "tensor_wrap", "tensor_export", "NotConvergedWarning",
-    "QTT_EXACT", "QTT_INVERSE", "QTT_NO_ROUND", "QTT_ORTH_CHOLQR", "QTT_ORTH_HOUSEHOLDER",
+    "QTT_EXACT", "QTT_INVERSE", "QTT_NO_ROUND", "QTT_ORTH_AUTO", "QTT_ORTH_CHOLQR", "QTT_ORTH_HOUSEHOLDER",
     "QTT_PREC_BF16X3", "QTT_PREC_FP32", "QTT_PREC_FP64",
 ]
 
@@ -285,7 +285,8 @@ class SolveOptions:
     streams: int = 1
     # entries of the per-load-case residual history to record (0: none)
     history: int = 0
-    # range-finder orthonormalisation: QTT_ORTH_HOUSEHOLDER or QTT_ORTH_CHOLQR
+    # range-finder orthonormalisation: QTT_ORTH_AUTO (default),
+    # QTT_ORTH_HOUSEHOLDER or QTT_ORTH_CHOLQR
     orth: int = 0
 
     def c(self) -> _c.SolveOpts:
@@ -513,9 +514,10 @@ def zqr(ctx: Context, A, R, Q=None, path: int = 0):
                                C.c_void_p(R.data_ptr()), qp, path))
 
 
-def zorth(ctx: Context, A, Q):
+def zorth(ctx: Context, A, Q, path: int = 0):
     """qtt_zorth: orthonormal basis Q (batch, m, n) of the columns of A
-    (batch, m, n); returns the per-matrix fallback flags (1: Householder)."""
+    (batch, m, n); returns the per-matrix fallback flags (1: Householder).
+    path 0: spread over the device, 1: one fused workgroup per matrix."""
     _dev3(A, "A")
     _dev3(Q, "Q")
     if tuple(Q.shape) != tuple(A.shape):
@@ -523,7 +525,7 @@ def zorth(ctx: Context, A, Q):
     batch, m, n = A.shape
     flags = (C.c_int * batch)()
     ctx.check(_c.lib().qtt_zorth(ctx.h, batch, m, n, C.c_void_p(A.data_ptr()),
-                                 C.c_void_p(Q.data_ptr()), flags))
+                                 C.c_void_p(Q.data_ptr()), flags, path))
     return list(flags)
 
 

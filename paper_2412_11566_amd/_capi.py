@@ -31,8 +31,9 @@ QTT_PREC_FP32 = 1
 QTT_PREC_BF16X3 = 2
 QTT_GEMM_PATH_BF16X3 = 16
 
-QTT_ORTH_HOUSEHOLDER = 0
-QTT_ORTH_CHOLQR = 1
+QTT_ORTH_AUTO = 0
+QTT_ORTH_HOUSEHOLDER = 1
+QTT_ORTH_CHOLQR = 2
 
 QTT_ZQR_NOALLOC_MAX_ELEMS = 1048576
 
@@ -106,7 +107,7 @@ SIGNATURES = {
     "qtt_zqr": (I, [P, I, I, I, P, P, P, I]),
     "qtt_zjacobi": (I, [P, I, I, P, P, P]),
     "qtt_zqr_noalloc": (I, [P, I, I, I, P, P, P]),
-    "qtt_zorth": (I, [P, I, I, I, P, P, C.POINTER(C.c_int)]),
+    "qtt_zorth": (I, [P, I, I, I, P, P, C.POINTER(C.c_int), I]),
     "ls_adjoint_prepared": (I, [P, P, C.POINTER(SolveOpts), P, DP, DP, C.POINTER(Report)]),
     "qtt_stats_enable": (I, [P, I]),
     "qtt_stats_get": (I, [P, I, C.POINTER(C.c_longlong), DP, DP, DP]),

@@ -392,12 +392,13 @@ static double qr_flops(int m, int n, bool q) {
 
 // checked launchers: every device range a kernel touches is verified on the
 // host against the live allocations before the launch
-static void ck_orth(const Ctx& X, int B, int m, int n, MatView A, MatOut Q, cplx* ws, hipStream_t s) {
+static void ck_orth(const Ctx& X, int B, int m, int n, MatView A, MatOut Q, cplx* ws, hipStream_t s,
+                    bool drop) {
   need(X, A.base, span2(m, n, A.rs, A.cs) + (B - 1) * A.sb, "orth A");
   need(X, Q.base, span2(m, n, Q.rs, Q.cs) + (B - 1) * Q.sb, "orth Q");
-  need(X, ws, (long)orth_ws(B, m, n) - 1, "orth ws");
+  need(X, ws, (long)orth_split_ws(B, m, n) - 1, "orth ws");
   hipEvent_t e = X.t0();
-  if (!orth(B, m, n, A, Q, ws, s)) throw std::logic_error("orth: shape not covered");
+  if (!orth_split(B, m, n, A, Q, ws, s, drop)) throw std::logic_error("orth: shape not covered");
   // counted as the Householder QR with Q that produces the same basis
   X.t1(e, QTT_K_QR, B * qr_flops(m, n, true), 16.0 * B * 2.0 * m * n);
 }
@@ -808,9 +809,11 @@ struct SketchOpts {
   bool fp32 = false;
   // contractions with split-BF16 operands and FP32 accumulation
   bool bf16 = false;
-  // range-finder bases by CholeskyQR2 (Householder fallback) instead of
-  // Householder QR
-  bool cholqr = false;
+  // range-finder bases: QTT_ORTH_HOUSEHOLDER, _CHOLQR or _AUTO
+  int orth = QTT_ORTH_HOUSEHOLDER;
+  // the fixed-point iterate entering this product has a bond rank at the
+  // cap (QTT_ORTH_AUTO then takes CholeskyQR2: the sketches are full rank)
+  bool saturated = false;
 };
 
 // reduced-precision contractions (FP32, split-BF16) for the lifetime of
@@ -1018,11 +1021,16 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
     auto Q = X.buf((size_t)B * m * kq);
     const MatView yv{(cplx*)Y->p, (long)l2, 1, (long)m * l2, 0};
     const MatOut qv{(cplx*)Q->p, (long)kq, 1, (long)m * kq};
-    if (o.cholqr && !o.exact && orth_ok(m, l2)) {
+    const bool cq = o.orth == QTT_ORTH_CHOLQR || (o.orth == QTT_ORTH_AUTO && o.saturated);
+    if (cq && !o.exact && orth_ok(m, l2)) {
       // only the basis is kept (R is not needed): CholeskyQR2 on the matrix
       // cores, Householder for the matrices it cannot take
-      auto ws = X.buf(orth_ws(B, m, l2));
-      ck_orth(X, B, m, l2, yv, qv, (cplx*)ws->p, X.s());
+      auto ws = X.buf(orth_split_ws(B, m, l2));
+      // cap-bound updates (QTT_ORTH_AUTO): dependent columns of the sketch
+      // become zero columns of the basis instead of a fallback; the rounding
+      // only needs an isometry on the range, and the dropped directions
+      // (below 3e-7 relative) lie far under the cap's truncation
+      ck_orth(X, B, m, l2, yv, qv, (cplx*)ws->p, X.s(), o.orth == QTT_ORTH_AUTO);
     } else {
       auto R = X.buf((size_t)B * kq * l2);
       auto ws = X.buf(qr_ws(B, m, l2));
@@ -1735,8 +1743,8 @@ static void check_problem(const qtt_problem* P, const qtt_solve_opts* O) {
   if (O->precision != QTT_PREC_FP64 && O->precision != QTT_PREC_FP32 && O->precision != QTT_PREC_BF16X3)
     throw std::invalid_argument("precision must be QTT_PREC_FP64, QTT_PREC_FP32 or QTT_PREC_BF16X3");
   if (O->history && O->history_len < 1) throw std::invalid_argument("history without a length");
-  if (O->orth != QTT_ORTH_HOUSEHOLDER && O->orth != QTT_ORTH_CHOLQR)
-    throw std::invalid_argument("orth must be QTT_ORTH_HOUSEHOLDER or QTT_ORTH_CHOLQR");
+  if (O->orth != QTT_ORTH_HOUSEHOLDER && O->orth != QTT_ORTH_CHOLQR && O->orth != QTT_ORTH_AUTO)
+    throw std::invalid_argument("orth must be QTT_ORTH_HOUSEHOLDER, QTT_ORTH_CHOLQR or QTT_ORTH_AUTO");
   for (int i = 0; i < 2 * P->nphase; ++i)
     if (!std::isfinite(P->lame[i])) throw std::invalid_argument("non-finite phase modulus");
   if (!std::isfinite(P->lame0[0]) || !(P->lame0[1] > 0.0) || !(P->lame0[0] + 2.0 * P->lame0[1] > 0.0))
@@ -1761,12 +1769,32 @@ static SketchOpts sk(const Ctx& X, const qtt_solve_opts* O) {
   s.exact = O->exact != 0;
   s.fp32 = O->precision == QTT_PREC_FP32;
   s.bf16 = O->precision == QTT_PREC_BF16X3;
-  s.cholqr = O->orth == QTT_ORTH_CHOLQR;
+  s.orth = O->orth;
   s.seed = O->seed * 1000003ULL + (X.c->sketch_counter++);
   return s;
 }
 
 // options for an intermediate product of the fixed-point update
+// The iterate is cap-bound: a bond rank at a cap that truncates there
+// (below the bond's structural rank), and the last truncation of the
+// iterate discarded at least 1e-5 of it (30 times what a dropped direction
+// of the range finder can carry), so the cap, not delta, sets the error.
+static bool saturated(const TT& x, int cap, double last_disc) {
+  if (cap <= 0 || !(last_disc >= 1e-5)) return false;
+  double left = 1.0;
+  for (int k = 1; k < x.L; ++k) {
+    left *= x.dout[k - 1];
+    double right = 1.0;
+    for (int i = k; i < x.L; ++i) right *= x.dout[i];
+    if (x.r[k] >= cap && std::min(left, right) > cap) return true;
+  }
+  return false;
+}
+static SketchOpts satur(SketchOpts s, bool sat) {
+  s.saturated = sat;
+  return s;
+}
+
 static SketchOpts ski(const Ctx& X, const qtt_solve_opts* O) {
   SketchOpts s = sk(X, O);
   // Products whose result is sketched again at once keep the sketch rank
@@ -1794,18 +1822,24 @@ static SolveOut ls_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, cons
   out.res.assign(B, INFINITY);
   std::vector<char> done(B, 0);
   int m = 0;
+  double last_disc = 0.0;
   while (true) {
     RoundStats st;
     // fresh sketches in every update: with the same test matrices in every
     // update the truncated map is no contraction (measured: the relative
     // update grew at 64^3 cap 64 and at 256^3 cap 64, and stalled 2.5 times
     // higher at 256^3 cap 128); fresh draws decorrelate the rounding errors
-    auto tau = op_apply(X, *ops.Cd, *eps, 0, ski(X, O), &st);
-    auto th = op_apply(X, *ops.S, *tau, 0, ski(X, O), &st);
-    auto eh = op_apply(X, *ops.G, *th, 0, ski(X, O), &st);
-    auto y = op_apply(X, *ops.S->adj, *eh, 0, ski(X, O), &st);
-    auto nw = round_any(X, axpby(X, 1.0, *Et, -1.0, *y), sk(X, O), &st);
+    // the products of an update whose iterate sits at the cap sketch full-rank
+    // unfoldings (QTT_ORTH_AUTO); the intermediate products carry the sketch
+    // rank whatever their numerical rank, so their own ranks do not tell
+    const bool sat = saturated(*eps, O->cap, last_disc);
+    auto tau = op_apply(X, *ops.Cd, *eps, 0, satur(ski(X, O), sat), &st);
+    auto th = op_apply(X, *ops.S, *tau, 0, satur(ski(X, O), sat), &st);
+    auto eh = op_apply(X, *ops.G, *th, 0, satur(ski(X, O), sat), &st);
+    auto y = op_apply(X, *ops.S->adj, *eh, 0, satur(ski(X, O), sat), &st);
+    auto nw = round_any(X, axpby(X, 1.0, *Et, -1.0, *y), satur(sk(X, O), sat), &st);
     out.disc = std::max(out.disc, st.rel_max());
+    last_disc = st.rel_max();  // the iterate's truncation (the last rounding)
     for (int k = 1; k < nw->L; ++k) out.max_rank = std::max(out.max_rank, nw->r[k]);
     double prev = 0.0;
     for (int b = 0; b < B; ++b)
@@ -2651,8 +2685,9 @@ int qtt_zqr(qtt_ctx* c, int batch, int m, int n, const void* A, void* R, void* Q
   });
 }
 
-int qtt_zorth(qtt_ctx* c, int batch, int m, int n, const void* A, void* Qo, int* fallback) {
-  if (!c || !A || !Qo || batch < 1 || batch > 65535 || m < 1 || n < 1) return QTT_EINVAL;
+int qtt_zorth(qtt_ctx* c, int batch, int m, int n, const void* A, void* Qo, int* fallback, int path) {
+  if (!c || !A || !Qo || batch < 1 || batch > 65535 || m < 1 || n < 1 || path < 0 || path > 2)
+    return QTT_EINVAL;
   if (!orth_ok(m, n)) {
     c->err = "qtt_zorth: " + std::to_string(m) + " x " + std::to_string(n) +
              " outside m >= n, 32 < m <= 192 for 16 < n <= 64, 32 < m <= 168 for 64 < n <= 80";
@@ -2660,10 +2695,12 @@ int qtt_zorth(qtt_ctx* c, int batch, int m, int n, const void* A, void* Qo, int*
   }
   QTT_TRY(c, {
     Ctx X{c};
-    auto ws = X.buf(orth_ws(batch, m, n));
+    auto ws = X.buf(path != 1 ? orth_split_ws(batch, m, n) : orth_ws(batch, m, n));
     // caller-owned operands (not in the context's pool): launched directly
-    orth(batch, m, n, MatView{(const cplx*)A, (long)n, 1, (long)m * n, 0},
-         MatOut{(cplx*)Qo, (long)n, 1, (long)m * n}, (cplx*)ws->p, c->stream);
+    const MatView av{(const cplx*)A, (long)n, 1, (long)m * n, 0};
+    const MatOut qo{(cplx*)Qo, (long)n, 1, (long)m * n};
+    if (path == 1) orth(batch, m, n, av, qo, (cplx*)ws->p, c->stream);
+    else orth_split(batch, m, n, av, qo, (cplx*)ws->p, c->stream, path == 2);
     if (fallback)
       check(hipMemcpyAsync(fallback, ws->p, batch * sizeof(int), hipMemcpyDeviceToHost, c->stream),
             "orth flags d2h");
@@ -2790,16 +2827,20 @@ static AdjOut adj_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, const
   std::vector<double> nCe = tt_norms(X, *Ce);
   AdjOut out;
   auto w = Ce;
+  double last_disc = 0.0;
   out.it.assign(B, 0);
   out.res.assign(B, 0.0);
   std::vector<char> done(B, 0);
   int m = 0;
   while (true) {
-    auto u = op_apply(X, *ops.S, *w, 0, ski(X, O), nullptr);
-    u = op_apply(X, *ops.G, *u, 0, ski(X, O), nullptr);
-    u = op_apply(X, *ops.S->adj, *u, 0, ski(X, O), nullptr);
-    u = op_apply(X, *ops.Cd, *u, 0, ski(X, O), nullptr);
-    auto nw = round_any(X, axpby(X, 1.0, *Ce, -1.0, *u), sk(X, O), nullptr);
+    const bool sat = saturated(*w, O->cap, last_disc);
+    RoundStats st;
+    auto u = op_apply(X, *ops.S, *w, 0, satur(ski(X, O), sat), nullptr);
+    u = op_apply(X, *ops.G, *u, 0, satur(ski(X, O), sat), nullptr);
+    u = op_apply(X, *ops.S->adj, *u, 0, satur(ski(X, O), sat), nullptr);
+    u = op_apply(X, *ops.Cd, *u, 0, satur(ski(X, O), sat), nullptr);
+    auto nw = round_any(X, axpby(X, 1.0, *Ce, -1.0, *u), satur(sk(X, O), sat), &st);
+    last_disc = st.rel_max();
     auto d = axpby(X, 1.0, *nw, -1.0, *w);
     auto dn = tt_norms(X, *d);
     w = nw;

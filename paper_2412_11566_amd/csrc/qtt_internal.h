@@ -152,8 +152,20 @@ bool qr_form_q(int batch, int m, int n, MatOut Q, cplx* ws, hipStream_t s, const
 // 16 < n <= 64 and 32 < m <= 168 for 64 < n <= 80 (m >= n); false
 // otherwise.  `ws` holds orth_ws(batch, m, n) entries;
 // on return its first batch ints hold the flags (1 = Householder).
-bool orth(int batch, int m, int n, MatView A, MatOut Q, cplx* ws, hipStream_t s);
+// With drop, a column dependent on the earlier ones to rounding (Cholesky
+// pivot at most 1e-13 of the largest) is not handed to Householder but
+// gives an exactly zero column of Q: Q^H Q is then I on the kept columns
+// and zero on the dropped ones, still an isometry on range(A) up to the
+// dropped directions (relative size below 3e-7).
+bool orth(int batch, int m, int n, MatView A, MatOut Q, cplx* ws, hipStream_t s, bool drop = false);
 size_t orth_ws(int batch, int m, int n);
+// The same basis with each pass spread over the device: partial Grams per
+// 32-row slice, one workgroup per matrix for the Cholesky and R^-1, the
+// products on the library's GEMM.  Needs unit column strides and no
+// conjugation; false otherwise or outside orth_ok.  `ws` holds
+// orth_split_ws(batch, m, n) entries, flags first as for orth.
+bool orth_split(int batch, int m, int n, MatView A, MatOut Q, cplx* ws, hipStream_t s, bool drop = false);
+size_t orth_split_ws(int batch, int m, int n);
 bool orth_ok(int m, int n);
 // Blocked QR for large shapes (m >= n, m <= 320, n <= 160): the matrix in
 // the workspace, one workgroup walking over 16-column panels with the

@@ -36,10 +36,10 @@ def _cond(rng, batch, m, n, kappa):
     return (U * s[None, None, :]) @ _ah(V)
 
 
-def _run(ctx, a):
+def _run(ctx, a, path=0):
     A = torch.from_numpy(np.ascontiguousarray(a)).cuda()
     Q = torch.full(a.shape, float("nan"), dtype=torch.complex128, device="cuda")
-    flags = q.zorth(ctx, A, Q)
+    flags = q.zorth(ctx, A, Q, path)
     return Q, flags
 
 
@@ -55,12 +55,16 @@ def _check(a, Qm, tol=1e-13):
         assert np.abs(res).max() / nrm < tol * np.sqrt(m)
 
 
+PATHS = [0, 1]   # spread over the device; one fused workgroup per matrix
+
+
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("shape", SHAPES)
-def test_zorth_random(ctx, shape):
+def test_zorth_random(ctx, shape, path):
     m, n = shape
     rng = np.random.default_rng(7 * m + n)
     a = _rand(rng, 3, m, n)
-    Q, flags = _run(ctx, a)
+    Q, flags = _run(ctx, a, path)
     Qm = Q.cpu().numpy()
     assert flags == [0, 0, 0]
     _check(a, Qm)
@@ -68,31 +72,38 @@ def test_zorth_random(ctx, shape):
     assert np.abs(Qm @ _ah(Qm) - Qn @ _ah(Qn)).max() < 1e-12
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("kappa", [1e2, 1e4, 1e5])
-def test_zorth_conditioned(ctx, kappa):
+def test_zorth_conditioned(ctx, kappa, path):
     rng = np.random.default_rng(int(np.log10(kappa)))
     a = _cond(rng, 2, 160, 80, kappa)
-    Q, flags = _run(ctx, a)
+    Q, flags = _run(ctx, a, path)
     assert flags == [0, 0]
     _check(a, Q.cpu().numpy())
 
 
-def test_zorth_falls_back_where_cholesky_cannot(ctx):
+@pytest.mark.parametrize("path", PATHS)
+def test_zorth_falls_back_where_cholesky_cannot(ctx, path):
     """Rank 10 of 80, condition 1e9 and the zero matrix go to Householder;
     the well-conditioned matrices beside them in the batch keep the
-    CholeskyQR2 result, bit for bit the same as alone."""
+    CholeskyQR2 result: bit for bit the same as alone in the fused kernel,
+    to rounding on the split path (whose GEMM may split K differently for
+    another batch size)."""
     rng = np.random.default_rng(3)
     m, n = 160, 80
     good = _rand(rng, 2, m, n)
     low = _rand(rng, m, 10) @ _rand(rng, 10, n)
     ill = _cond(rng, 1, m, n, 1e9)[0]
     a = np.stack([good[0], low, ill, np.zeros((m, n), complex), good[1]])
-    Q, flags = _run(ctx, a)
+    Q, flags = _run(ctx, a, path)
     assert flags == [0, 1, 1, 1, 0]
     _check(a, Q.cpu().numpy())
-    Q0, f0 = _run(ctx, good)
+    Q0, f0 = _run(ctx, good, path)
     assert f0 == [0, 0]
-    assert torch.equal(Q[0], Q0[0]) and torch.equal(Q[4], Q0[1])
+    if path == 1:
+        assert torch.equal(Q[0], Q0[0]) and torch.equal(Q[4], Q0[1])
+    else:
+        assert (Q[0] - Q0[0]).abs().max().item() < 1e-13 and (Q[4] - Q0[1]).abs().max().item() < 1e-13
 
 
 def test_zorth_rejects_uncovered(ctx):
@@ -101,3 +112,29 @@ def test_zorth_rejects_uncovered(ctx):
         with pytest.raises(q.QttError) as e:
             q.zorth(ctx, A, torch.zeros_like(A))
         assert e.value.code == q._c.QTT_EINVAL
+
+
+def test_zorth_drop_gives_zero_columns_for_dependent_ones(ctx):
+    """Path 2 (the range finder's form): rank-10 and rank-40 matrices of
+    160 x 80 are not flagged; every column of Q is exactly zero or of unit
+    norm, Q^H Q is a projector (eigenvalues 0 or 1 to 1e-12), at least the
+    true rank is kept, range(Q) contains range(A) (1e-12 relative), and a
+    full-rank neighbour in the batch still gets a full orthonormal Q."""
+    rng = np.random.default_rng(21)
+    m, n = 160, 80
+    a = np.stack([_rand(rng, m, 10) @ _rand(rng, 10, n), _rand(rng, m, 40) @ _rand(rng, 40, n),
+                  _rand(rng, m, n)])
+    Q, flags = _run(ctx, a, 2)
+    Qm = Q.cpu().numpy()
+    assert flags == [0, 0, 0]
+    assert np.isfinite(Qm).all()
+    for b, rank in enumerate([10, 40, 80]):
+        norms = np.linalg.norm(Qm[b], axis=0)
+        zero = norms == 0.0
+        assert np.all(zero | (np.abs(norms - 1.0) < 1e-12))
+        assert (~zero).sum() >= rank
+        G = _ah(Qm[b]) @ Qm[b]
+        assert np.abs(G @ G - G).max() < 1e-12
+        res = a[b] - Qm[b] @ (_ah(Qm[b]) @ a[b])
+        assert np.abs(res).max() / np.linalg.norm(a[b]) < 1e-12
+    assert (np.linalg.norm(Qm[2], axis=0) > 0).all()

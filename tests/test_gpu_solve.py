@@ -42,14 +42,14 @@ def test_c0_exact_same_iterations(ctx):
     assert rel(C, Cref) < 1e-10
 
 
-@pytest.mark.parametrize("orth", ["cholqr", "householder"])
+@pytest.mark.parametrize("orth", ["cholqr", "householder", "auto"])
 def test_c0_delta_1e8(ctx, orth):
     """16^3 sphere at rounding tolerance 1e-8 with a cap that does not bind
     (128 = largest structural rank): C_eff within 1e-5 of the converged
     dense basic scheme; symmetric.  Both orthonormalisations of the range
     finder (CholeskyQR2 with Householder fallback, Householder only)."""
     p = M.config_c0()
-    mode = q.QTT_ORTH_CHOLQR if orth == "cholqr" else q.QTT_ORTH_HOUSEHOLDER
+    mode = {"cholqr": q.QTT_ORTH_CHOLQR, "householder": q.QTT_ORTH_HOUSEHOLDER, "auto": q.QTT_ORTH_AUTO}[orth]
     opts = q.SolveOptions(delta=1e-8, tol=1e-8, cap=128, max_iter=300, orth=mode)
     C, rep, _ = q.ls_solve(ctx, p.phase, p.lame, p.lame0, opts)
     Cref, it = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=1e-12)
