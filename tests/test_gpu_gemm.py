@@ -107,6 +107,46 @@ def test_zgemm_split_bf16(ctx, ops):
         assert np.abs(out - want).max() > e32
 
 
+@pytest.mark.parametrize("path", [2, 3, 16])
+def test_zgemm_split_k_back_to_back(ctx, path):
+    """Split-K products issued back to back on one stream, with no host
+    synchronisation between them (different grids, batches, beta; each
+    reuses workspace the previous one released), and the same product twice
+    giving bit-identical results (slices summed in fixed order)."""
+    import torch
+    import paper_2412_11566_amd as q
+    rng = np.random.default_rng(13)
+    cases = [(160, 80, 800, 1), (96, 40, 517, 5), (64, 64, 2000, 2), (16, 16, 1584, 40),
+             (160, 80, 800, 3), (33, 20, 1200, 7)]
+    outs = []
+    for (M, N, K, nb) in cases + cases[:2]:
+        a = _rand(rng, nb, M, K)
+        b = _rand(rng, nb, K, N)
+        c = _rand(rng, nb, M, N)
+        beta = 0.0 if nb % 2 else -0.5 + 0.25j
+        A = torch.from_numpy(a).cuda()
+        B = torch.from_numpy(b).cuda()
+        Cm = torch.from_numpy(c).cuda()
+        q.zgemm(ctx, A, B, Cm, "N", "N", 1.5, beta, path)
+        outs.append((Cm, (a @ b) * 1.5 + beta * c, K))
+    for Cm, ref, K in outs:
+        d = np.abs(Cm.cpu().numpy() - ref).max()
+        if path == 2:    # FP64: the K u bound of test_zgemm
+            assert d / np.abs(ref).max() < 64 * K * 2.2e-16, (path, K, d)
+        else:            # FP32 and split-BF16: the sqrt(K) bounds above (alpha 1.5)
+            assert d / 1.5 / np.sqrt(K) < (5e-6 if path == 3 else 2e-4), (path, K, d)
+    # repeat one product on the same inputs: identical bits
+    a = _rand(rng, 2, 160, 4000)
+    b = _rand(rng, 2, 4000, 80)
+    A = torch.from_numpy(a).cuda()
+    B = torch.from_numpy(b).cuda()
+    C1 = torch.zeros((2, 160, 80), dtype=torch.complex128, device="cuda")
+    C2 = torch.zeros_like(C1)
+    q.zgemm(ctx, A, B, C1, "N", "N", 1.0, 0.0, path)
+    q.zgemm(ctx, A, B, C2, "N", "N", 1.0, 0.0, path)
+    assert torch.equal(C1, C2)
+
+
 def test_zgemm_mfma_rejects_small(ctx):
     import torch
     import paper_2412_11566_amd as q
