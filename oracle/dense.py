@@ -7,7 +7,8 @@ Follows the paper:
   strain E = e_k, Sec. 2 (text after Alg. 1).
 * Green operator in Fourier space, App. A, eq. orig_green_eshelby with the
   direct scheme k_j = i q_j (Table 3), and the Hermitian symmetrisation at
-  the Nyquist frequencies given in App. A.
+  the Nyquist frequencies given in App. A; the staggered-grid scheme of
+  Table 3 from its discrete gradient (``gamma_table_staggered``).
 
 Readings (where the paper is silent or garbled):
 * Stopping test of Alg. 1: ||eps_{m+1} - eps_m||_F / ||E||_F with both
@@ -137,6 +138,83 @@ def gamma_table(N, lam0: float, mu0: float) -> np.ndarray:
     return out
 
 
+# ---------------------------------------------------------------------------
+# Discrete Green operators from a discrete gradient (App. A, Table 3)
+# ---------------------------------------------------------------------------
+
+def staggered_symbols(q: np.ndarray):
+    """Fourier symbols of the staggered grid (App. A, Table 3): the forward
+    difference k+ = exp(+i q) - 1 and the backward difference
+    k- = 1 - exp(-i q), per axis, for q in radians (any shape)."""
+    q = np.asarray(q, dtype=np.float64)
+    return np.exp(1j * q) - 1.0, 1.0 - np.exp(-1j * q)
+
+
+def strain_symbol(k_normal: np.ndarray, k_shear: np.ndarray) -> np.ndarray:
+    """Symbol B (..., 6, 3) of a discrete symmetric gradient: the
+    engineering-Voigt strain of the displacement mode u exp(i q . x) is B u,
+    with normal strains eps_ii = k_normal_i u_i and shears
+    gamma_ij = k_shear_j u_i + k_shear_i u_j (i != j).  Arguments (..., 3).
+    The staggered grid takes k+ for the normal and k- for the shear strains
+    (its Green operator in App. A pairs k+ with i = j and k- otherwise); the
+    direct scheme takes k = i q for both."""
+    kn = np.asarray(k_normal, dtype=np.complex128)
+    ks = np.asarray(k_shear, dtype=np.complex128)
+    B = np.zeros(kn.shape[:-1] + (6, 3), dtype=np.complex128)
+    for I, (i, j) in enumerate(PAIRS):
+        if i == j:
+            B[..., I, i] = kn[..., i]
+        else:
+            B[..., I, i] = ks[..., j]
+            B[..., I, j] = ks[..., i]
+    return B
+
+
+def gamma_voigt_symbol(B: np.ndarray, C0: np.ndarray) -> np.ndarray:
+    """Green operator of a discrete gradient with symbol B (P, 6, 3) for the
+    Voigt stiffness C0 (6, 6): the displacement solving the discrete
+    equilibrium B^H (C0 B u + tau) = 0 gives the strain B u = -G tau with
+    G = B (B^H C0 B)^-1 B^H (App. A eq. orig_green_eshelby with the
+    acoustic tensor B^H C0 B inverted numerically per frequency; 0 where
+    B = 0).  It maps a plain-Voigt polarization to an engineering-Voigt
+    strain, like ``gamma_voigt``.  Returns (P, 6, 6) complex."""
+    B = np.asarray(B, dtype=np.complex128)
+    out = np.zeros((B.shape[0], 6, 6), dtype=np.complex128)
+    live = np.abs(B).reshape(B.shape[0], -1).max(axis=1) > 0
+    Bl = B[live]
+    K = np.conj(Bl).transpose(0, 2, 1) @ C0[None] @ Bl
+    out[live] = Bl @ np.linalg.inv(K) @ np.conj(Bl).transpose(0, 2, 1)
+    return out
+
+
+def gamma_table_staggered(N, lam0: float, mu0: float) -> np.ndarray:
+    """Staggered-grid Voigt Green table on the DFT grid (App. A, Table 3),
+    complex (6, 6, Nx, Ny, Nz) in numpy ``fftn`` order.  DFT index m of an
+    axis of length N is the frequency q = 2 pi m / N; the symbols are
+    2 pi-periodic, so no Nyquist representative has to be chosen and the
+    table is Hermitian in the DFT sense by construction."""
+    shape = (N, N, N) if np.isscalar(N) else tuple(N)
+    C0 = iso_voigt(lam0, mu0)
+    qs = [2.0 * np.pi * np.arange(n) / n for n in shape]
+    Q = np.stack(np.meshgrid(*qs, indexing="ij"), axis=-1).reshape(-1, 3)
+    kp, km = staggered_symbols(Q)
+    G = gamma_voigt_symbol(strain_symbol(kp, km), C0)
+    return G.reshape(shape + (6, 6)).transpose(3, 4, 0, 1, 2).copy()
+
+
+SCHEMES = ("direct", "staggered")
+
+
+def green_table(shape, lam0: float, mu0: float, scheme: str = "direct") -> np.ndarray:
+    """Voigt Green table of a discretisation scheme (App. A, Table 3):
+    ``direct`` (k = i q, Nyquist-symmetrised) or ``staggered``."""
+    if scheme == "direct":
+        return gamma_table(shape, lam0, mu0)
+    if scheme == "staggered":
+        return gamma_table_staggered(shape, lam0, mu0)
+    raise ValueError(f"unknown scheme {scheme!r}")
+
+
 def stiffness_per_phase(lame: np.ndarray) -> np.ndarray:
     return np.stack([iso_voigt(l, m) for l, m in np.asarray(lame)])
 
@@ -206,12 +284,13 @@ def mean_stress(phase: np.ndarray, lame: np.ndarray, eps: np.ndarray) -> np.ndar
 
 def effective_stiffness(phase: np.ndarray, lame: np.ndarray, lame0, tol: float,
                         max_iter: int = 2000, keep_fields: bool = False,
-                        fixed_iters: int | None = None):
-    """C_eff (6x6, columns = unit load cases e_k) from Alg. 1.
+                        fixed_iters: int | None = None, scheme: str = "direct"):
+    """C_eff (6x6, columns = unit load cases e_k) from Alg. 1 with the Green
+    operator of ``scheme`` (see ``green_table``).
 
     Returns (C_eff, iterations per load case[, fields]).
     """
-    G = gamma_table(phase.shape, *lame0)
+    G = green_table(phase.shape, *lame0, scheme)
     C = np.zeros((6, 6))
     iters = []
     fields = []

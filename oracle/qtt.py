@@ -259,22 +259,24 @@ def sfft_3d(n: int, delta: float, cap: int = 1 << 30):
     return [identity_voigt_core()] + [c.copy() for _ in range(3) for c in q]
 
 
-def green_tensor(n: int, lam0: float, mu0: float) -> np.ndarray:
+def green_tensor(n: int, lam0: float, mu0: float, scheme: str = "direct") -> np.ndarray:
     """Dense Green operator in the SFFT momentum order, shape (6,6,N,N,N).
 
     Entry at momentum index (kx, ky, kz) is G_h at DFT index
     (-rev(kx), -rev(ky), -rev(kz)) mod N, which equals conj G_h(rev(k)):
-    indices reversed per axis, then conjugated (Sec. 4.3).
+    indices reversed per axis, then conjugated (Sec. 4.3).  ``scheme``:
+    the discretisation of App. A, Table 3 (``direct`` or ``staggered``).
     """
     N = 1 << n
-    G = D.gamma_table(N, lam0, mu0)
+    G = D.green_table(N, lam0, mu0, scheme)
     m = (-bitrev(np.arange(N), n)) % N
     return G[:, :, m][:, :, :, m][:, :, :, :, m]
 
 
-def green_tto(n: int, lam0: float, mu0: float, delta: float, cap: int = 1 << 30):
+def green_tto(n: int, lam0: float, mu0: float, delta: float, cap: int = 1 << 30,
+              scheme: str = "direct"):
     """Raised Green TTO with a 6x6 Voigt control core."""
-    T = green_tensor(n, lam0, mu0).reshape([36] + [2] * (3 * n))
+    T = green_tensor(n, lam0, mu0, scheme).reshape([36] + [2] * (3 * n))
     cores = tt_svd(T, delta, cap)
     c0 = cores[0].reshape(1, 6, 6, cores[0].shape[2])
     return [c0] + raise_tt(cores[1:])
@@ -356,17 +358,18 @@ def qtt_ls(phase: np.ndarray, lame, lame0, E, delta: float, cap: int, tol: float
     return eps, m, hist, rmax
 
 
-def build_operators(phase, lame, lame0, delta):
+def build_operators(phase, lame, lame0, delta, scheme: str = "direct"):
     n = int(round(math.log2(phase.shape[0])))
     S = sfft_3d(n, delta)
-    return S, tto_adjoint(S), green_tto(n, *lame0, delta), stiffness_tto(phase, lame, lame0, delta)
+    return (S, tto_adjoint(S), green_tto(n, *lame0, delta, scheme=scheme),
+            stiffness_tto(phase, lame, lame0, delta))
 
 
 def qtt_effective_stiffness(phase, lame, lame0, delta, cap, tol, max_iter=2000,
-                            fixed_iters=None):
+                            fixed_iters=None, scheme: str = "direct"):
     """C_eff from Alg. 2; the mean stress is taken on the densified strain."""
     n = int(round(math.log2(phase.shape[0])))
-    ops = build_operators(phase, lame, lame0, delta)
+    ops = build_operators(phase, lame, lame0, delta, scheme)
     C = np.zeros((6, 6))
     iters = []
     for k in range(6):

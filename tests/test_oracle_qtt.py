@@ -124,8 +124,10 @@ def test_green_tt_densifies_to_table():
     assert np.abs(off).max() < 1e-12
 
 
-def test_green_momentum_convention():
-    """S^H (G_TT . S x) = ifftn(G_h . fftn(x)) (the SFFT convention)."""
+@pytest.mark.parametrize("scheme", ["direct", "staggered"])
+def test_green_momentum_convention(scheme):
+    """S^H (G_TT . S x) = ifftn(G_h . fftn(x)) (the SFFT convention), for
+    both discretisations of App. A."""
     n = 2
     N = 1 << n
     lam0, mu0 = 2.3, 1.4
@@ -133,15 +135,21 @@ def test_green_momentum_convention():
     x = rng.normal(size=(6, N, N, N))
     S = Q.sfft_3d(n, 1e-14)
     xt = Q.tt_from_field(x.astype(complex), n, 1e-14)
-    y = Q.tto_apply(Q.tto_adjoint(S), Q.tto_apply(Q.green_tto(n, lam0, mu0, 1e-14), Q.tto_apply(S, xt)))
-    ref = D.apply_gamma(D.gamma_table(N, lam0, mu0), x.astype(complex))
+    G = Q.green_tto(n, lam0, mu0, 1e-14, scheme=scheme)
+    y = Q.tto_apply(Q.tto_adjoint(S), Q.tto_apply(G, Q.tto_apply(S, xt)))
+    ref = D.apply_gamma(D.green_table(N, lam0, mu0, scheme), x.astype(complex))
     assert np.abs(Q.field_from_tt(y, n) - ref).max() < 1e-11 * np.abs(ref).max()
+    if scheme == "staggered":
+        # a real field stays real: the staggered operator is real in space
+        assert np.abs(ref.imag).max() < 1e-12 * np.abs(ref).max()
 
 
-def test_untruncated_alg2_equals_alg1_same_iterations():
+@pytest.mark.parametrize("scheme", ["direct", "staggered"])
+def test_untruncated_alg2_equals_alg1_same_iterations(scheme):
     p = M.Problem("s4", 2, M.sphere(4, 0.3), [(1.0, 0.3), (10.0, 0.3)], cap=0, delta=1e-14, tol=0)
-    C2, _ = Q.qtt_effective_stiffness(p.phase, p.lame, p.lame0, 1e-14, 1 << 30, 0.0, fixed_iters=3)
-    C1, _ = D.effective_stiffness(p.phase, p.lame, p.lame0, 0.0, fixed_iters=3)
+    C2, _ = Q.qtt_effective_stiffness(p.phase, p.lame, p.lame0, 1e-14, 1 << 30, 0.0, fixed_iters=3,
+                                      scheme=scheme)
+    C1, _ = D.effective_stiffness(p.phase, p.lame, p.lame0, 0.0, fixed_iters=3, scheme=scheme)
     assert np.abs(C2 - C1).max() < 1e-11 * np.abs(C1).max()
 
 

@@ -82,12 +82,14 @@ def test_hs_bounds_formula_limits():
     assert mlo == pytest.approx(1.0) and mhi == pytest.approx(1.0)
 
 
-def test_z_invariant_geometry_reduces_to_one_slice():
+@pytest.mark.parametrize("scheme", ["direct", "staggered"])
+def test_z_invariant_geometry_reduces_to_one_slice(scheme):
     """For a z-invariant microstructure only the xi_z = 0 modes carry energy,
     so Alg. 1 on the (N, N, 1) grid reproduces the (N, N, N) iterates and
-    C_eff (used to compute the 256^3 fibre reference)."""
+    C_eff (used to compute the 256^3 fibre references)."""
     p = M.config_c2(3)
-    C3, it3 = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=1e-10)
-    C1, it1 = D.effective_stiffness(p.phase[:, :, :1].copy(), p.lame, p.lame0, tol=1e-10)
+    C3, it3 = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=1e-10, scheme=scheme)
+    C1, it1 = D.effective_stiffness(p.phase[:, :, :1].copy(), p.lame, p.lame0, tol=1e-10,
+                                    scheme=scheme)
     assert it3 == it1
     assert np.abs(C3 - C1).max() < 1e-12 * np.abs(C3).max()
