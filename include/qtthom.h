@@ -87,6 +87,15 @@ extern "C" {
 #define QTT_ORTH_HOUSEHOLDER 1
 #define QTT_ORTH_CHOLQR      2
 
+/* discretisation of the Green operator (App. A, Table 3):
+ * QTT_SCHEME_DIRECT: k = i q (Moulinec-Suquet), Nyquist-symmetrised.
+ * QTT_SCHEME_STAGGERED: the staggered grid, forward differences
+ *   k+ = exp(i q) - 1 on the normal strains and backward differences
+ *   k- = 1 - exp(-i q) on the shears; the constitutive law stays pointwise
+ *   per voxel, as in Alg. 2. */
+#define QTT_SCHEME_DIRECT    0
+#define QTT_SCHEME_STAGGERED 1
+
 typedef struct qtt_ctx qtt_ctx;
 typedef struct qtt_tensor qtt_tensor;
 
@@ -102,6 +111,8 @@ typedef struct qtt_problem {
     int phase_on_device;     /* nonzero: `phase` is device memory of the
                                 context's device (read, never written or
                                 kept beyond the call)                      */
+    int scheme;              /* QTT_SCHEME_*: the Green operator's
+                                discretisation (App. A, Table 3)           */
 } qtt_problem;
 
 typedef struct qtt_solve_opts {
@@ -237,6 +248,22 @@ int qtt_sfft_build(qtt_ctx* ctx, int n, double delta, qtt_tensor** S);
  * control index), averaged in the last map. */
 int qtt_green_build(qtt_ctx* ctx, int n, double lam0, double mu0,
                     double delta, qtt_tensor** G);
+
+/* The Green operator of a discretisation scheme (QTT_SCHEME_*; App. A,
+ * Table 3); QTT_SCHEME_DIRECT is qtt_green_build.  The staggered-grid
+ * operator is B (B^H C0 B)^-1 B^H with B the strain symbol of its gradient
+ * (the discrete form of eq. orig_green_eshelby).  For isotropic C0 its
+ * acoustic tensor is mu0 |k+|^2 I + (lam0 + mu0) conj(k+) (k+)^T, so with
+ * the unit vectors n = k+ / |k+| and m = k- / |k+| it is held, like the
+ * direct one, as four factors over one train of (n_a, m_a):
+ * u_k = -m_k tau_kk - sum_{j != k} n_j tau_kj, s = n . u,
+ * q = u / mu0 + (lam0 + mu0) / (mu0 (lam0 + 2 mu0)) m s and
+ * eps_kk = n_k q_k, gamma_ij = m_j q_i + m_i q_j.  The symbols are
+ * 2 pi-periodic, so no Nyquist representative is chosen.  The train of
+ * (n_a, m_a) is built by the device TT-SVD; QTT_ECAPACITY if a bond needs
+ * more than 160.  QTT_EINVAL for an unknown scheme. */
+int qtt_green_build_scheme(qtt_ctx* ctx, int n, double lam0, double mu0,
+                           double delta, int scheme, qtt_tensor** G);
 
 /* Raised stiffness operator C(x) - C0 (Sec. 4.3; App. D: recomputed per
  * geometry) from a voxel phase array (binary discretisation of Sec. 4.3

@@ -20,7 +20,7 @@ import numpy as np
 from . import _capi as _c
 from ._capi import (QTT_EXACT, QTT_INVERSE, QTT_NO_ROUND, QTT_OK, QTT_ENOCONV,
                     QTT_ORTH_AUTO, QTT_ORTH_CHOLQR, QTT_ORTH_HOUSEHOLDER, QTT_PREC_BF16X3, QTT_PREC_FP32,
-                    QTT_PREC_FP64)
+                    QTT_PREC_FP64, QTT_SCHEME_DIRECT, QTT_SCHEME_STAGGERED)
 
 __all__ = [
     "QttError", "Context", "Tensor", "SolveOptions", "SolveReport",
@@ -30,7 +30,8 @@ __all__ = [
     "ls_solve_prepared", "stats_enable", "stats_get", "stats_reset", "tensor_create",
     "tensor_wrap", "tensor_export", "NotConvergedWarning",
     "QTT_EXACT", "QTT_INVERSE", "QTT_NO_ROUND", "QTT_ORTH_AUTO", "QTT_ORTH_CHOLQR", "QTT_ORTH_HOUSEHOLDER",
-    "QTT_PREC_BF16X3", "QTT_PREC_FP32", "QTT_PREC_FP64",
+    "QTT_PREC_BF16X3", "QTT_PREC_FP32", "QTT_PREC_FP64", "QTT_SCHEME_DIRECT", "QTT_SCHEME_STAGGERED",
+    "SCHEMES",
 ]
 
 
@@ -210,8 +211,21 @@ def sfft_build(ctx: Context, n: int, delta: float) -> Tensor:
     return _new(ctx, _c.lib().qtt_sfft_build, n, delta)
 
 
-def green_build(ctx: Context, n: int, lam0: float, mu0: float, delta: float) -> Tensor:
-    return _new(ctx, _c.lib().qtt_green_build, n, lam0, mu0, delta)
+# Green-operator discretisations (App. A, Table 3)
+SCHEMES = {"direct": 0, "staggered": 1}
+
+
+def _scheme(scheme) -> int:
+    if isinstance(scheme, str):
+        if scheme not in SCHEMES:
+            raise ValueError(f"scheme: one of {sorted(SCHEMES)}")
+        return SCHEMES[scheme]
+    return int(scheme)
+
+
+def green_build(ctx: Context, n: int, lam0: float, mu0: float, delta: float,
+                scheme="direct") -> Tensor:
+    return _new(ctx, _c.lib().qtt_green_build_scheme, n, lam0, mu0, delta, _scheme(scheme))
 
 
 def from_voxels(ctx: Context, phase, lame, lame0, delta: float, cap: int = 0):
@@ -315,7 +329,7 @@ class SolveReport:
     history: np.ndarray | None = None
 
 
-def _problem(phase, lame, lame0, load_mask):
+def _problem(phase, lame, lame0, load_mask, scheme="direct"):
     """qtt_problem from a host array or a torch uint8 device tensor (then
     the library reads the voxels from device memory)."""
     on_dev = not isinstance(phase, np.ndarray) and getattr(phase, "is_cuda", False)
@@ -334,7 +348,7 @@ def _problem(phase, lame, lame0, load_mask):
         raise ValueError("phase must be a cubic array with side 2**n")
     lame = np.ascontiguousarray(lame, dtype=np.float64)
     p = _c.Problem(n, ptr, lame.shape[0], _dp(lame), (C.c_double * 2)(*lame0), load_mask,
-                   int(on_dev))
+                   int(on_dev), _scheme(scheme))
     return p, (phase, lame)
 
 
@@ -347,9 +361,10 @@ def _report(r: _c.Report, o: _c.SolveOpts | None = None) -> SolveReport:
 
 
 def ls_solve(ctx: Context, phase, lame, lame0, opts: SolveOptions, load_mask: int = 0x3F,
-             keep_eps: bool = False):
-    """Alg. 2 for the selected unit load cases; returns (C_eff, report, eps)."""
-    p, keep = _problem(phase, lame, lame0, load_mask)
+             keep_eps: bool = False, scheme="direct"):
+    """Alg. 2 for the selected unit load cases with the Green operator of
+    ``scheme`` (``SCHEMES``); returns (C_eff, report, eps)."""
+    p, keep = _problem(phase, lame, lame0, load_mask, scheme)
     o = opts.c()
     Ceff = np.zeros(36)
     rep = _c.Report()
@@ -361,10 +376,11 @@ def ls_solve(ctx: Context, phase, lame, lame0, opts: SolveOptions, load_mask: in
     return Ceff.reshape(6, 6), _report(rep, o), (Tensor(ctx, eps) if keep_eps else None)
 
 
-def ls_adjoint(ctx: Context, phase, lame, lame0, opts: SolveOptions, eps: Tensor, gbar=None):
+def ls_adjoint(ctx: Context, phase, lame, lame0, opts: SolveOptions, eps: Tensor, gbar=None,
+               scheme="direct"):
     """Adjoint LS solve; returns the Jacobian (6, 6, 2*nphase) or the
     gradient (2*nphase,) when the cotangent ``gbar`` (6, 6) is given."""
-    p, keep = _problem(phase, lame, lame0, 0x3F)
+    p, keep = _problem(phase, lame, lame0, 0x3F, scheme)
     o = opts.c()
     nt = 2 * np.asarray(lame).shape[0]
     rep = _c.Report()
@@ -381,11 +397,11 @@ def ls_adjoint(ctx: Context, phase, lame, lame0, opts: SolveOptions, eps: Tensor
     return out, _report(rep)
 
 
-def batch_solve(ctx: Context, problems, opts: SolveOptions):
+def batch_solve(ctx: Context, problems, opts: SolveOptions, scheme="direct"):
     """Many structures: problems = [(phase, lame, lame0)]; returns (C_eff[count], reports)."""
     ps, keeps = [], []
     for phase, lame, lame0 in problems:
-        p, k = _problem(phase, lame, lame0, 0x3F)
+        p, k = _problem(phase, lame, lame0, 0x3F, scheme)
         ps.append(p)
         keeps.append(k)
     arr = (_c.Problem * len(ps))(*ps)
@@ -414,8 +430,9 @@ class Prepared:
             self.h = None
 
 
-def prepare(ctx: Context, phase, lame, lame0, delta: float, load_mask: int = 0x3F) -> Prepared:
-    p, keep = _problem(phase, lame, lame0, load_mask)
+def prepare(ctx: Context, phase, lame, lame0, delta: float, load_mask: int = 0x3F,
+            scheme="direct") -> Prepared:
+    p, keep = _problem(phase, lame, lame0, load_mask, scheme)
     h = C.c_void_p()
     ctx.check(_c.lib().qtt_prepare(ctx.h, C.byref(p), delta, C.byref(h)))
     return Prepared(ctx, h, keep)

@@ -34,6 +34,8 @@ QTT_GEMM_PATH_BF16X3 = 16
 QTT_ORTH_AUTO = 0
 QTT_ORTH_HOUSEHOLDER = 1
 QTT_ORTH_CHOLQR = 2
+QTT_SCHEME_DIRECT = 0
+QTT_SCHEME_STAGGERED = 1
 
 QTT_ZQR_NOALLOC_MAX_ELEMS = 1048576
 
@@ -45,7 +47,7 @@ ERR_NAMES = {QTT_EINVAL: "EINVAL", QTT_ENOMEM: "ENOMEM", QTT_ECAPACITY: "ECAPACI
 class Problem(C.Structure):
     _fields_ = [("n", C.c_int), ("phase", C.POINTER(C.c_uint8)), ("nphase", C.c_int),
                 ("lame", C.POINTER(C.c_double)), ("lame0", C.c_double * 2),
-                ("load_mask", C.c_int), ("phase_on_device", C.c_int)]
+                ("load_mask", C.c_int), ("phase_on_device", C.c_int), ("scheme", C.c_int)]
 
 
 class SolveOpts(C.Structure):
@@ -86,6 +88,7 @@ SIGNATURES = {
     "qtt_const_strain": (I, [P, I, I, DP, PP]),
     "qtt_sfft_build": (I, [P, I, D, PP]),
     "qtt_green_build": (I, [P, I, D, D, D, PP]),
+    "qtt_green_build_scheme": (I, [P, I, D, D, D, I, PP]),
     "qtt_from_voxels": (I, [P, C.POINTER(C.c_uint8), I, I, I, DP, DP, D, I, PP, PP]),
     "sfft_apply": (I, [P, P, P, PP, I, D, I, U64]),
     "tt_hadamard": (I, [P, P, P, PP, I, D, I, U64]),

@@ -24,6 +24,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <thread>
 #include <array>
@@ -143,9 +144,11 @@ struct qtt_tensor {
   // structures), each padded to the common ranks; train batch element b
   // uses instance b / (B / opb)
   int opb = 1;
-  // Green operator factors
+  // Green operator factors (scheme: QTT_SCHEME_*); the Green step combines
+  // q = inv_mu0 u - c p
   std::shared_ptr<qtt_tensor> gU, gS, gP, gE, adj;
   double inv_mu0 = 0.0, c = 0.0;
+  int scheme = 0;
   // per-structure Green scalars (device arrays over the train batch) when
   // one factor set serves several reference media
   std::shared_ptr<qtt::Buf> inv_mu0_b, c_b;
@@ -181,10 +184,11 @@ struct qtt_ctx {
   // statistics family of the next GEMMs when >= 0 (QTT_K_CONTRACT for the
   // operator x train contractions), else by kernel path
   int gemm_family = -1;
-  std::map<int, std::shared_ptr<qtt_tensor>> ident;  // identity operator per n
+  std::map<std::pair<int, int>, std::shared_ptr<qtt_tensor>> ident;  // identity operator per (n, control dim)
   // SFFT and Green factors per (n, delta): shared by every problem of that
   // grid size (the factors do not depend on the reference medium)
-  std::map<std::pair<int, double>, std::shared_ptr<qtt_tensor>> sfft_cache, green_cache;
+  std::map<std::pair<int, double>, std::shared_ptr<qtt_tensor>> sfft_cache;
+  std::map<std::tuple<int, double, int>, std::shared_ptr<qtt_tensor>> green_cache;  // (n, delta, scheme)
   // kernel statistics (HIP events around every stats_stride-th launch;
   // flops and bytes of every launch are counted as well)
   bool stats_on = false;
@@ -1105,15 +1109,15 @@ static TTP apply_full(const Ctx& X, const TT& A, const TT& x) {
 
 static TTP op_apply(const Ctx& X, const TT& A, const TT& x, int flags, const SketchOpts& o,
                     RoundStats* st);
-static TTP identity_op(const Ctx& X, int n);
+static TTP identity_op(const Ctx& X, int n, int d0 = 6);
 
 // Rounding of an explicit train (e.g. a sum of two trains): with a rank cap
 // the randomized sketch (identity operator) keeps every factorisation at the
 // sketch size; without a cap (or in exact mode) the deterministic
 // QR + SVD rounding is used.
 static TTP round_any(const Ctx& X, const TTP& x, const SketchOpts& o, RoundStats* st) {
-  if (o.cap > 0 && !o.exact && x->dout[0] == 6 && (x->L - 1) % 3 == 0) {
-    auto I = identity_op(X, (x->L - 1) / 3);
+  if (o.cap > 0 && !o.exact && (x->dout[0] == 6 || x->dout[0] == 3) && (x->L - 1) % 3 == 0) {
+    auto I = identity_op(X, (x->L - 1) / 3, x->dout[0]);
     return sketch_apply(X, *I, *x, o, st);
   }
   round_tt(X, *x, o.delta, o.cap, st);
@@ -1335,14 +1339,23 @@ static TTP sfft_op(const Ctx& X, int n, double delta) {
 }
 
 static bool device_direction(const Ctx& X, int n, double delta, host::HTT& out);
+static bool device_direction_staggered(const Ctx& X, int n, double delta, host::HTT& out);
 
 // The Green factors from the direction train: its TT-SVD on the device, or
-// on the host when a bond rank exceeds the device path
-static TTP green_op(const Ctx& X, int n, double lam0, double mu0, double delta) {
+// (direct scheme) on the host when a bond rank exceeds the device path
+static TTP green_op(const Ctx& X, int n, double lam0, double mu0, double delta, int scheme) {
   host::HTT nt;
-  host::GreenFactors gf = device_direction(X, n, delta, nt) ? host::green_factors_from(nt, lam0, mu0)
-                                                            : host::green_factors(n, lam0, mu0, delta);
+  host::GreenFactors gf;
+  if (scheme == QTT_SCHEME_STAGGERED) {
+    if (!device_direction_staggered(X, n, delta, nt))
+      throw std::length_error("staggered Green operator: direction-train rank beyond the device TT-SVD");
+    gf = host::green_factors_staggered_from(nt, lam0, mu0);
+  } else {
+    gf = device_direction(X, n, delta, nt) ? host::green_factors_from(nt, lam0, mu0)
+                                           : host::green_factors(n, lam0, mu0, delta);
+  }
   auto t = std::make_shared<TT>();
+  t->scheme = scheme;
   t->kind = 2; t->L = 3 * n + 1; t->B = 1; t->pool = X.c->pool;
   t->gU = upload_op(X, gf.U);
   t->gS = upload_op(X, gf.Sd);
@@ -1366,31 +1379,31 @@ static TTP sfft_cached(const Ctx& X, int n, double delta) {
 }
 
 // Green operator for one reference medium: the factors are built once per
-// (n, delta) and shared, the two medium scalars are set per call
-static TTP green_cached(const Ctx& X, int n, double lam0, double mu0, double delta) {
-  const auto key = std::make_pair(n, delta);
+// (n, delta, scheme) and shared, the two medium scalars are set per call
+static TTP green_cached(const Ctx& X, int n, double lam0, double mu0, double delta, int scheme) {
+  const auto key = std::make_tuple(n, delta, scheme);
   auto it = X.c->green_cache.find(key);
   TTP base;
   if (it != X.c->green_cache.end()) {
     base = it->second;
   } else {
-    base = green_op(X, n, lam0, mu0, delta);
+    base = green_op(X, n, lam0, mu0, delta, scheme);
     X.c->green_cache[key] = base;
   }
   auto t = std::make_shared<TT>(*base);
-  host::green_scalars(lam0, mu0, &t->inv_mu0, &t->c);
+  host::green_scalars_scheme(scheme, lam0, mu0, &t->inv_mu0, &t->c);
   return t;
 }
 
 // Green operator for a batch of structures (train batch = 6 per structure)
 static TTP green_batch(const Ctx& X, int n, double delta, const std::vector<double>& lam0,
-                       const std::vector<double>& mu0, int per) {
-  auto t = green_cached(X, n, lam0[0], mu0[0], delta);
+                       const std::vector<double>& mu0, int per, int scheme) {
+  auto t = green_cached(X, n, lam0[0], mu0[0], delta, scheme);
   const int S = (int)lam0.size(), B = S * per;
   std::vector<double> a(B), c(B);
   for (int s2 = 0; s2 < S; ++s2) {
     double inv, hc;
-    host::green_scalars(lam0[s2], mu0[s2], &inv, &hc);
+    host::green_scalars_scheme(scheme, lam0[s2], mu0[s2], &inv, &hc);
     for (int q = 0; q < per; ++q) {
       a[(size_t)s2 * per + q] = inv;
       c[(size_t)s2 * per + q] = hc;
@@ -1465,14 +1478,15 @@ static TTP upload_op_batch(const Ctx& X, const std::vector<host::HTT>& hs) {
   return t;
 }
 
-static TTP identity_op(const Ctx& X, int n) {
-  auto it = X.c->ident.find(n);
+static TTP identity_op(const Ctx& X, int n, int d0) {
+  const auto key = std::make_pair(n, d0);
+  auto it = X.c->ident.find(key);
   if (it != X.c->ident.end()) return it->second;
   host::HTT h;
   host::HCore id;
-  id.r0 = 1; id.dout = 6; id.din = 6; id.r1 = 1;
-  id.v.assign(36, 0.0);
-  for (int i = 0; i < 6; ++i) id.v[i * 6 + i] = 1.0;
+  id.r0 = 1; id.dout = d0; id.din = d0; id.r1 = 1;
+  id.v.assign((size_t)d0 * d0, 0.0);
+  for (int i = 0; i < d0; ++i) id.v[i * d0 + i] = 1.0;
   h.push_back(id);
   for (int k = 0; k < 3 * n; ++k) {
     host::HCore c;
@@ -1481,7 +1495,7 @@ static TTP identity_op(const Ctx& X, int n) {
     h.push_back(c);
   }
   auto t = upload_op(X, h);
-  X.c->ident[n] = t;
+  X.c->ident[key] = t;
   return t;
 }
 
@@ -1628,6 +1642,26 @@ static bool device_direction(const Ctx& X, int n, double delta, host::HTT& out) 
                       out);
 }
 
+// The train of the staggered-grid directions (n_a, m_a) (App. A, Table 3):
+// the field on the device from one axis's difference symbols, then the
+// device TT-SVD (|T|^2 = 2 per nonzero frequency)
+static bool device_direction_staggered(const Ctx& X, int n, double delta, host::HTT& out) {
+  const long NN = 1L << (3 * n);
+  const int L = 3 * n + 1, N = 1 << n;
+  std::vector<double> kp, km;
+  host::staggered_symbols(n, kp, km);
+  auto sd = X.buf(2 * (size_t)N);
+  check(hipMemcpyAsync(sd->p, kp.data(), N * sizeof(cplx), hipMemcpyHostToDevice, X.s()), "symbols h2d");
+  check(hipMemcpyAsync((cplx*)sd->p + N, km.data(), N * sizeof(cplx), hipMemcpyHostToDevice, X.s()),
+        "symbols h2d");
+  auto T = X.buf((size_t)6 * NN);
+  need(X, T->p, 6 * NN - 1, "direction out");
+  direction_staggered((const cplx*)sd->p, (const cplx*)sd->p + N, n, (cplx*)T->p, X.s());
+  X.sync();  // the host symbol arrays are released on return
+  return device_ttsvd(X, T, n, 6, delta / std::sqrt((double)(L - 1)) * std::sqrt(2.0 * (double)(NN - 1)),
+                      out);
+}
+
 // TT-SVD of a dense device tensor T with dims (P, 2, ..., 2) (3n binary
 // indices, P slowest; complex storage, P 2^(3n) entries), right to left: the
 // unfolding M (P 2^(k-1) x 2 r_k) is reduced to R by tsqr_r, R^H goes
@@ -1723,7 +1757,7 @@ static Ops build_ops(const Ctx& X, const qtt_problem* P, double delta) {
   Ops o;
   const int n = P->n;
   o.S = sfft_cached(X, n, delta);
-  o.G = green_cached(X, n, P->lame0[0], P->lame0[1], delta);
+  o.G = green_cached(X, n, P->lame0[0], P->lame0[1], delta, P->scheme);
   host::HTT cd = stiffness_op(X, P->phase, P->phase_on_device != 0, n, P->nphase, P->lame, P->lame0,
                               delta, 0, &o.chi);
   o.Cd = upload_op(X, cd);
@@ -1738,6 +1772,8 @@ static void check_problem(const qtt_problem* P, const qtt_solve_opts* O) {
   if (P->n < 1 || P->n > 10) throw std::invalid_argument("n out of range (1..10)");
   if (P->nphase < 1 || P->nphase > 16) throw std::invalid_argument("nphase out of range");
   if (!P->phase || !P->lame) throw std::invalid_argument("null phase or lame");
+  if (P->scheme != QTT_SCHEME_DIRECT && P->scheme != QTT_SCHEME_STAGGERED)
+    throw std::invalid_argument("scheme must be QTT_SCHEME_DIRECT or QTT_SCHEME_STAGGERED");
   if (!(O->delta > 0.0) || !(O->tol >= 0.0) || O->max_iter < 0)
     throw std::invalid_argument("bad solve options");
   if (O->precision != QTT_PREC_FP64 && O->precision != QTT_PREC_FP32 && O->precision != QTT_PREC_BF16X3)
@@ -1893,7 +1929,7 @@ static void ceff_from(const Ctx& X, const Ops& ops, const qtt_problem* P, const 
 }
 
 struct Prepared {
-  int n = 0, nphase = 0, load_mask = 0;
+  int n = 0, nphase = 0, load_mask = 0, scheme = 0;
   std::vector<uint8_t> phase;
   std::vector<double> lame;
   double lame0[2] = {0, 0};
@@ -1901,10 +1937,11 @@ struct Prepared {
   Ops ops;
   double seconds_setup = 0;
   qtt_problem problem() const {
-    qtt_problem P;
+    qtt_problem P{};
     P.n = n; P.phase = phase.data(); P.nphase = nphase; P.lame = lame.data();
     P.lame0[0] = lame0[0]; P.lame0[1] = lame0[1]; P.load_mask = load_mask;
     P.phase_on_device = 0;
+    P.scheme = scheme;
     return P;
   }
 };
@@ -2268,10 +2305,17 @@ int qtt_sfft_build(qtt_ctx* c, int n, double delta, qtt_tensor** S) {
 }
 
 int qtt_green_build(qtt_ctx* c, int n, double lam0, double mu0, double delta, qtt_tensor** Gp) {
-  if (!c || !Gp || n < 1 || n > 9 || !(mu0 > 0) || !(lam0 + 2 * mu0 > 0) || !(delta > 0)) return QTT_EINVAL;
+  return qtt_green_build_scheme(c, n, lam0, mu0, delta, QTT_SCHEME_DIRECT, Gp);
+}
+
+int qtt_green_build_scheme(qtt_ctx* c, int n, double lam0, double mu0, double delta, int scheme,
+                           qtt_tensor** Gp) {
+  if (!c || !Gp || n < 1 || n > 9 || !(mu0 > 0) || !(lam0 + 2 * mu0 > 0) || !(delta > 0) ||
+      (scheme != QTT_SCHEME_DIRECT && scheme != QTT_SCHEME_STAGGERED))
+    return QTT_EINVAL;
   QTT_TRY(c, {
     Ctx X{c};
-    *Gp = new qtt_tensor(*green_op(X, n, lam0, mu0, delta));
+    *Gp = new qtt_tensor(*green_op(X, n, lam0, mu0, delta, scheme));
   });
 }
 
@@ -2542,7 +2586,7 @@ static int solve_prepared(qtt_ctx* c, const Prepared& pr, const qtt_solve_opts* 
 
 static Prepared make_prepared(qtt_ctx* c, const qtt_problem* P, double delta) {
   Prepared pr;
-  pr.n = P->n; pr.nphase = P->nphase; pr.load_mask = P->load_mask;
+  pr.n = P->n; pr.nphase = P->nphase; pr.load_mask = P->load_mask; pr.scheme = P->scheme;
   const size_t NN = (size_t)1 << (3 * P->n);
   if (P->phase_on_device) {
     pr.phase.resize(NN);
@@ -3030,7 +3074,7 @@ static int batch_group(qtt_ctx* c, const std::vector<int>& ids, const qtt_proble
       l0[s2] = Ps[ids[s2]].lame0[0];
       m0[s2] = Ps[ids[s2]].lame0[1];
     }
-    ops.G = green_batch(X, n, O->delta, l0, m0, 6);
+    ops.G = green_batch(X, n, O->delta, l0, m0, 6, Ps[ids[0]].scheme);
     ops.Cd = upload_op_batch(X, cds);
     ops.I = identity_op(X, n);
     cds.clear();
@@ -3083,12 +3127,15 @@ int qtt_batch_solve(qtt_ctx* c, int count, const qtt_problem* Ps, const qtt_solv
                     double* Ceff, qtt_report* Rs) {
   if (!c || !O || count < 0 || (count > 0 && (!Ps || !Ceff))) return QTT_EINVAL;
   // structures with all six load cases are solved together, grouped by
-  // grid size, at most kBatchMax per group; the others one by one
-  std::map<int, std::vector<int>> groups;
+  // grid size and Green scheme, at most kBatchMax per group; the others one
+  // by one
+  std::map<std::pair<int, int>, std::vector<int>> groups;
   std::vector<int> single;
   for (int i = 0; i < count; ++i) {
-    if (Ps[i].load_mask == 0x3F && Ps[i].n >= 1 && Ps[i].n <= 10) groups[Ps[i].n].push_back(i);
-    else single.push_back(i);
+    if (Ps[i].load_mask == 0x3F && Ps[i].n >= 1 && Ps[i].n <= 10)
+      groups[std::make_pair(Ps[i].n, Ps[i].scheme)].push_back(i);
+    else
+      single.push_back(i);
   }
   int worst = QTT_OK;
   auto note = [&](int rc) {

@@ -508,6 +508,77 @@ GreenFactors green_factors_from(const HTT& nt, double lam0, double mu0) {
   return G;
 }
 
+void staggered_symbols(int n, std::vector<double>& kp, std::vector<double>& km) {
+  const int N = 1 << n;
+  kp.resize(2 * (size_t)N);
+  km.resize(2 * (size_t)N);
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < N; ++k) {
+    const int m = (N - bitrev(k, n)) % N;
+    const double h = pi * m / N;  // q / 2
+    // exp(i q) - 1 = 2 i sin(q/2) exp(i q/2) = (-2 sin^2(q/2), sin q);
+    // 1 - exp(-i q) = 2 i sin(q/2) exp(-i q/2) = (2 sin^2(q/2), sin q)
+    const double s2 = 2.0 * std::sin(h) * std::sin(h), sq = std::sin(2.0 * h);
+    kp[2 * k] = -s2;
+    kp[2 * k + 1] = sq;
+    km[2 * k] = s2;
+    km[2 * k + 1] = sq;
+  }
+}
+
+GreenFactors green_factors_staggered_from(const HTT& nt, double lam0, double mu0) {
+  GreenFactors G;
+  // control index c: a (0..2) -> n_a, 3 + a -> m_a
+  // U: u_k = -m_k tau_kk - sum_{j != k} n_j tau_{V(k,j)} ; out k (3), in Voigt (6)
+  {
+    std::vector<double> cf(3 * 6 * 6, 0.0);
+    for (int k = 0; k < 3; ++k) {
+      cf[((size_t)k * 6 + k) * 6 + 3 + k] = -1.0;
+      for (int j = 0; j < 3; ++j)
+        if (j != k) cf[((size_t)k * 6 + voigt_index(k, j)) * 6 + j] = -1.0;
+    }
+    G.U = control_op(nt, 3, 6, cf);
+  }
+  // Sd: s = sum_k n_k u_k ; out 1, in 3
+  {
+    std::vector<double> cf(1 * 3 * 6, 0.0);
+    for (int k = 0; k < 3; ++k) cf[(size_t)k * 6 + k] = 1.0;
+    G.Sd = control_op(nt, 1, 3, cf);
+  }
+  // P: p_k = m_k s ; out 3, in 1
+  {
+    std::vector<double> cf(3 * 1 * 6, 0.0);
+    for (int k = 0; k < 3; ++k) cf[(size_t)k * 6 + 3 + k] = 1.0;
+    G.P = control_op(nt, 3, 1, cf);
+  }
+  // E: eps_kk = n_k q_k, gamma_ij = m_j q_i + m_i q_j ; out Voigt (6), in 3
+  {
+    const int VP[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
+    std::vector<double> cf(6 * 3 * 6, 0.0);
+    for (int I = 0; I < 6; ++I) {
+      const int i = VP[I][0], j = VP[I][1];
+      if (i == j) {
+        cf[((size_t)I * 3 + i) * 6 + i] = 1.0;
+      } else {
+        cf[((size_t)I * 3 + i) * 6 + 3 + j] += 1.0;
+        cf[((size_t)I * 3 + j) * 6 + 3 + i] += 1.0;
+      }
+    }
+    G.E = control_op(nt, 6, 3, cf);
+  }
+  green_scalars_scheme(1, lam0, mu0, &G.inv_2mu0, &G.half_c);
+  return G;
+}
+
+void green_scalars_scheme(int scheme, double lam0, double mu0, double* a, double* c) {
+  if (scheme == 0) {
+    green_scalars(lam0, mu0, a, c);
+    return;
+  }
+  *a = 1.0 / mu0;
+  *c = -(lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));
+}
+
 void green_scalars(double lam0, double mu0, double* inv_2mu0, double* half_c) {
   *inv_2mu0 = 0.5 / mu0;
   *half_c = 0.5 * (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));

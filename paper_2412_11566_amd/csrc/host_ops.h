@@ -64,6 +64,27 @@ GreenFactors green_factors_from(const HTT& nt, double lam0, double mu0);
 // representative: f[k] in (-N/2, N/2], f2[k] = f[k] except -f[k] at N/2.
 void momentum_freqs(int n, std::vector<double>& f, std::vector<double>& f2);
 
+// Staggered-grid Green operator (App. A, Table 3: forward differences
+// kp = exp(i q) - 1 on the normal strains, backward km = 1 - exp(-i q) on
+// the shears, q = 2 pi m / N at DFT index m = -rev(k) mod N of momentum
+// index k).  With B the strain symbol of this gradient the operator is
+// B (B^H C0 B)^-1 B^H; for isotropic C0 the acoustic tensor is
+// mu0 |kp|^2 I + (lam0 + mu0) conj(kp) kp^T (|km_a| = |kp_a| and
+// conj(km) = -kp), so with the unit vectors n = kp / |kp|, m = km / |kp|
+// the operator acts as
+//   u_k = -m_k tau_kk - sum_{j != k} n_j tau_kj,   s = n . u,   p = m s,
+//   q = u / mu0 + c' p / mu0,   c' = (lam0 + mu0) / (lam0 + 2 mu0),
+//   eps_kk = n_k q_k,   gamma_ij = m_j q_i + m_i q_j.
+// The factors share the train of (n_a, m_a) (control index (t, a), 6
+// values): U: 6 -> 3, Sd: 3 -> 1, P: 1 -> 3, E: 3 -> 6; in GreenFactors
+// inv_2mu0 holds the weight of u (1/mu0) and half_c minus that of p.
+// One axis's symbols in momentum order (kp, km as (re, im) pairs).
+void staggered_symbols(int n, std::vector<double>& kp, std::vector<double>& km);
+GreenFactors green_factors_staggered_from(const HTT& nt, double lam0, double mu0);
+// The Green step's two medium scalars for a scheme (0 direct, 1 staggered):
+// q = a u - c p.
+void green_scalars_scheme(int scheme, double lam0, double mu0, double* a, double* c);
+
 // Raised stiffness operator C(x) - C0 (or one-hot phase train chi) from a
 // voxel phase array; returns the operator, and the one-hot train in chi.
 HTT stiffness_tto(const uint8_t* phase, int n, int nphase, const double* lame,

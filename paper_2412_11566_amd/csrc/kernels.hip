@@ -711,6 +711,34 @@ void direction(const double* f, const double* f2, int n, cplx* out, hipStream_t 
   check(hipGetLastError(), "direction launch");
 }
 
+// Staggered-grid directions (App. A, Table 3): per axis the forward and
+// backward difference symbols kp, km of the momentum index; out[a] =
+// kp_a / |kp|, out[3 + a] = km_a / |kp| (|km| = |kp| per axis), 0 at the
+// zero frequency
+__global__ void k_direction_staggered(const cplx* __restrict__ kp, const cplx* __restrict__ km, int n, long NN,
+                                      cplx* __restrict__ out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NN) return;
+  const int N = 1 << n;
+  const int ix[3] = {(int)(e >> (2 * n)), (int)((e >> n) & (N - 1)), (int)(e & (N - 1))};
+  double r2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) r2 += kp[ix[a]].x * kp[ix[a]].x + kp[ix[a]].y * kp[ix[a]].y;
+  const double inv = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    out[a * NN + e] = make_double2(kp[ix[a]].x * inv, kp[ix[a]].y * inv);
+    out[(3 + a) * NN + e] = make_double2(km[ix[a]].x * inv, km[ix[a]].y * inv);
+  }
+}
+
+void direction_staggered(const cplx* kp, const cplx* km, int n, cplx* out, hipStream_t s) {
+  const long NN = 1L << (3 * n);
+  hipLaunchKernelGGL(k_direction_staggered, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, s, kp, km, n, NN,
+                     out);
+  check(hipGetLastError(), "direction_staggered launch");
+}
+
 __global__ void k_sum_middle(long total, int outer, int np, int inner, const cplx* in,
                              cplx* out, cplx w) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -294,6 +294,10 @@ void onehot(const uint8_t* phase, long NN, int nphase, cplx* out, int* bad, hipS
 // (6 x 2^(3n) entries, control index (sigma, a) slowest, then x, y, z
 // bits); f, f2: device arrays of one axis's frequencies (2^n each).
 void direction(const double* f, const double* f2, int n, cplx* out, hipStream_t s);
+// Staggered-grid directions (6 x 2^(3n) entries, control index (t, a): t = 0
+// the forward symbols kp_a / |kp|, t = 1 the backward ones km_a / |kp|);
+// kp, km: device arrays of one axis's symbols in momentum order (2^n each).
+void direction_staggered(const cplx* kp, const cplx* km, int n, cplx* out, hipStream_t s);
 
 void check(hipError_t e, const char* what);
 
