@@ -5,7 +5,8 @@ computes, written from the paper (Hauck, Kabel, Ali, Gauger, "SFFT-based
 homogenization", arXiv 2412.11566):
 
 * ``oracle.dense``  -- the FFT-based basic scheme (Sec. 2, Alg. 1) on dense
-  voxel fields, the Green operator table (App. A, direct scheme), the
+  voxel fields, the Green operator tables (App. A: direct and staggered
+  grid schemes of Table 3), the
   effective stiffness from unit load cases (Sec. 2), and gradient references
   (energy identity, central finite differences, dense adjoint).
 * ``oracle.qtt``    -- a dense-vector quantized-tensor-train reference:
@@ -13,6 +14,8 @@ homogenization", arXiv 2412.11566):
   eq. rounding_condition_tt), the SFFT operator from the reduced QFT
   (Sec. 4.1), the Green TT in the SFFT momentum convention (Sec. 4.3) and the
   SFFT-based homogenization loop (Alg. 2).
+* ``oracle.amen``   -- the AMEn-adapted approximate TTO x TT product
+  (App. B): Galerkin core updates, residual enrichment, QR.
 * ``oracle.bounds`` -- closed forms: isotropic stiffness, laminate effective
   stiffness, Voigt/Reuss and Hashin-Shtrikman bounds.
 
