@@ -318,6 +318,8 @@ def main():
     ap.add_argument("--no-cap128", action="store_true", help="skip the cap-128 leg")
     ap.add_argument("--no-staggered", action="store_true",
                     help="skip the staggered-grid Green operator leg (cap 128)")
+    ap.add_argument("--amen-iters", type=int, default=20,
+                    help="updates per load case of the AMEn Green-product leg (0: skip)")
     ap.add_argument("--batch", type=int, default=4,
                     help="structures in the batched-vs-plain comparison (0: skip)")
     ap.add_argument("--oversample", type=int, default=16,
@@ -497,6 +499,23 @@ def main():
         log(f"staggered cap 128: setup {stag_setup:.2f} s, {tsol:.1f} s, "
             f"{sum(rs.iterations) / tsol:.2f} updates/s, C_eff error {es}")
         del prep_s
+    # the Green step's products by the AMEn-adapted product (App. B) against
+    # the randomized sketch, same workload at cap 128 and the same number of
+    # updates per load case
+    amen = None
+    if args.amen_iters > 0:
+        legs = {}
+        for name, mv in (("amen", q.QTT_MV_AMEN), ("sketch", q.QTT_MV_SKETCH)):
+            oa = q.SolveOptions(delta=p.delta, tol=0.0, cap=128, max_iter=args.amen_iters,
+                                oversample=args.oversample, seed=2024, streams=args.streams, orth=orth,
+                                matvec=mv)
+            Ca, ra, _, ta, _ = timed_solve(q, ctx, prep, oa)
+            legs[name] = {"iterations_per_s": sum(ra.iterations) / ta, "solve_s": ta,
+                          "max_rank": ra.max_rank, "residual": ra.residual,
+                          "ceff_rel_error_vs_oracle": golden_error(Ca, "c2") if args.n == 8 else None}
+            log(f"{name} Green products, cap 128, {args.amen_iters} updates per case: {ta:.1f} s, "
+                f"{sum(ra.iterations) / ta:.2f} updates/s, C_eff error {legs[name]['ceff_rel_error_vs_oracle']}")
+        amen = {"cap": 128, "updates_per_load_case": args.amen_iters, **legs}
     tto = tto_apply_bandwidth(q, ctx, args.n)
     if "tto_contract" in rl:
         tto["in_solve_contractions"] = rl["tto_contract"]
@@ -533,6 +552,7 @@ def main():
                      "1e-5 line is cap128",
         "cap128": cap128,
         "staggered": stag,
+        "amen_green_products": amen,
         "setup_seconds": setup_s,
         "setup_breakdown": {"stiffness_from_voxels_s": stiff_s, "sfft_build_s": sfft_s,
                             "prepare_all_operators_s": setup_s},

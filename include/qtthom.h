@@ -93,6 +93,19 @@ extern "C" {
  *   k+ = exp(i q) - 1 on the normal strains and backward differences
  *   k- = 1 - exp(-i q) on the shears; the constitutive law stays pointwise
  *   per voxel, as in Alg. 2. */
+/* the Green step's products in Alg. 2 (truncated solves with a cap; exact
+ * and untruncated solves always use the sketch):
+ * QTT_MV_SKETCH (default): each factor product rounded by the randomized
+ *   range finder of Sec. 3 (Gaussian TT sketch, QR sweep, truncated SVD).
+ * QTT_MV_AMEN: each factor product by the AMEn-adapted product of App. B
+ *   (tt_amen_apply), warm-started from the same product of the previous
+ *   update (the first update from a random train at the cap's ranks; at
+ *   most 3 sweeps warm, 6 cold; residual train of rank 8), its sweeps
+ *   stopped when the product changes by less than a twentieth of the last
+ *   relative update of the fixed point (at most 1e-3, at least delta). */
+#define QTT_MV_SKETCH 0
+#define QTT_MV_AMEN   1
+
 #define QTT_SCHEME_DIRECT    0
 #define QTT_SCHEME_STAGGERED 1
 
@@ -141,6 +154,8 @@ typedef struct qtt_solve_opts {
     int orth;                /* QTT_ORTH_*: how the range finder of each
                                 rounding orthonormalises its sketched
                                 unfoldings (Sec. 3)                         */
+    int matvec;              /* QTT_MV_*: how the Green step's products are
+                                approximated (Alg. 2, App. B)               */
 } qtt_solve_opts;
 
 typedef struct qtt_report {
@@ -296,6 +311,30 @@ int tt_hadamard(qtt_ctx* ctx, const qtt_tensor* A, const qtt_tensor* x,
 int green_apply(qtt_ctx* ctx, const qtt_tensor* G, const qtt_tensor* x,
                 qtt_tensor** y, int flags, double delta, int cap,
                 uint64_t seed);
+
+/* y ~ A x by the AMEn-adapted product of App. B: instead of forming A x
+ * (ranks multiply, Table 2) and rounding it, ||y - A x|| is minimised core
+ * by core.  A sweep runs left to right; at core k the local solution is the
+ * projection of A x onto the frame of y's other cores (the Galerkin
+ * condition, eq. galerkin_condition), truncated by SVD at
+ * delta / sqrt(L - 1) of its norm and at `cap` (<= 0: none); the residual
+ * A x - y is carried as a train z of its own (its cores the residual's
+ * projections onto z's frame), and its core enriches the kept singular
+ * vectors before the QR that makes y's core orthonormal.  Before every
+ * sweep y and z are made right-orthonormal.  The sweeps stop when the
+ * product changes by less than `tol` (relative, largest over the batch)
+ * between two sweeps, or after `sweeps`.  The returned product keeps the
+ * truncated ranks (the enrichment only steers the next sweep's frames).
+ * A: an operator (kind 1; QTT_EINVAL for the factored Green operator);
+ * x: a train; y0, z0: initial guesses (trains with A's output dims and x's
+ * batch, any ranks; the caller draws them, typically at random), left
+ * unchanged.  Optional outputs: the sweeps run and the last relative
+ * change.  QTT_ECAPACITY when a local core exceeds 320 in its smaller
+ * dimension. */
+int tt_amen_apply(qtt_ctx* ctx, const qtt_tensor* A, const qtt_tensor* x,
+                  const qtt_tensor* y0, const qtt_tensor* z0, double delta,
+                  int cap, int sweeps, double tol, qtt_tensor** y,
+                  int* sweeps_run, double* change);
 
 /* In-place TT-rounding (Sec. 3): QR orthogonalisation sweep, then
  * truncated SVDs keeping per bond the smallest rank whose discarded

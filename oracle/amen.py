@@ -112,6 +112,9 @@ def amen_sweep(A, x, y, z, delta, cap):
         yk = _local(PyL, A[k], x[k], PyR[k + 1])       # Galerkin solution
         if k == L - 1:
             y[k] = yk
+            # the residual's last core in its frame
+            z[k] = (_local(PzL, A[k], x[k], PzR[k + 1])
+                    - np.einsum("ab,bic->aic", SL, yk, optimize=True))
             break
         ry, d, ry2 = yk.shape
         M = yk.reshape(ry * d, ry2)

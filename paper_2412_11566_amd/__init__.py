@@ -20,18 +20,19 @@ import numpy as np
 from . import _capi as _c
 from ._capi import (QTT_EXACT, QTT_INVERSE, QTT_NO_ROUND, QTT_OK, QTT_ENOCONV,
                     QTT_ORTH_AUTO, QTT_ORTH_CHOLQR, QTT_ORTH_HOUSEHOLDER, QTT_PREC_BF16X3, QTT_PREC_FP32,
-                    QTT_PREC_FP64, QTT_SCHEME_DIRECT, QTT_SCHEME_STAGGERED)
+                    QTT_PREC_FP64, QTT_SCHEME_DIRECT, QTT_SCHEME_STAGGERED, QTT_MV_SKETCH,
+                    QTT_MV_AMEN)
 
 __all__ = [
     "QttError", "Context", "Tensor", "SolveOptions", "SolveReport",
     "tt_from_cores", "const_strain", "sfft_build", "green_build", "from_voxels",
-    "sfft_apply", "tt_hadamard", "green_apply", "tt_round", "tt_norm", "tt_axpby",
+    "sfft_apply", "tt_hadamard", "green_apply", "amen_apply", "tt_round", "tt_norm", "tt_axpby",
     "tt_mean_apply", "ls_solve", "ls_adjoint", "batch_solve", "Prepared", "prepare",
     "ls_solve_prepared", "stats_enable", "stats_get", "stats_reset", "tensor_create",
     "tensor_wrap", "tensor_export", "NotConvergedWarning",
     "QTT_EXACT", "QTT_INVERSE", "QTT_NO_ROUND", "QTT_ORTH_AUTO", "QTT_ORTH_CHOLQR", "QTT_ORTH_HOUSEHOLDER",
     "QTT_PREC_BF16X3", "QTT_PREC_FP32", "QTT_PREC_FP64", "QTT_SCHEME_DIRECT", "QTT_SCHEME_STAGGERED",
-    "SCHEMES",
+    "SCHEMES", "QTT_MV_SKETCH", "QTT_MV_AMEN",
 ]
 
 
@@ -260,6 +261,18 @@ def green_apply(ctx, G, x, delta=1e-10, cap=0, seed=0, flags=0) -> Tensor:
     return _prod(_c.lib().green_apply, ctx, G, x, flags, delta, cap, seed)
 
 
+def amen_apply(ctx, A, x, y0, z0, delta: float, cap: int = 0, sweeps: int = 4, tol=None):
+    """y ~ A x by the AMEn-adapted product (App. B) from the initial guesses
+    y0, z0 (trains); returns (y, sweeps run, last relative change)."""
+    h = C.c_void_p()
+    m = C.c_int(0)
+    ch = C.c_double(0.0)
+    ctx.check(_c.lib().tt_amen_apply(ctx.h, A.h, x.h, y0.h, z0.h, delta, cap, sweeps,
+                                     delta if tol is None else tol, C.byref(h), C.byref(m),
+                                     C.byref(ch)))
+    return Tensor(ctx, h), m.value, ch.value
+
+
 def tt_round(ctx, x: Tensor, delta: float, cap: int = 0) -> np.ndarray:
     B = x.shape()["batch"]
     disc = np.zeros(B)
@@ -302,11 +315,14 @@ class SolveOptions:
     # range-finder orthonormalisation: QTT_ORTH_AUTO (default),
     # QTT_ORTH_HOUSEHOLDER or QTT_ORTH_CHOLQR
     orth: int = 0
+    # the Green step's products: QTT_MV_SKETCH (default) or QTT_MV_AMEN
+    matvec: int = 0
 
     def c(self) -> _c.SolveOpts:
         o = _c.SolveOpts(self.delta, self.tol, self.cap, self.max_iter, self.precision,
                          self.oversample, int(self.exact), self.seed, self.streams)
         o.orth = self.orth
+        o.matvec = self.matvec
         if self.history > 0:
             buf = np.zeros(6 * self.history)
             o.history = _dp(buf)

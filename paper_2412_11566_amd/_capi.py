@@ -34,6 +34,8 @@ QTT_GEMM_PATH_BF16X3 = 16
 QTT_ORTH_AUTO = 0
 QTT_ORTH_HOUSEHOLDER = 1
 QTT_ORTH_CHOLQR = 2
+QTT_MV_SKETCH = 0
+QTT_MV_AMEN = 1
 QTT_SCHEME_DIRECT = 0
 QTT_SCHEME_STAGGERED = 1
 
@@ -54,7 +56,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("delta", C.c_double), ("tol", C.c_double), ("cap", C.c_int),
                 ("max_iter", C.c_int), ("precision", C.c_int), ("oversample", C.c_int),
                 ("exact", C.c_int), ("seed", C.c_uint64), ("streams", C.c_int),
-                ("history", C.POINTER(C.c_double)), ("history_len", C.c_int), ("orth", C.c_int)]
+                ("history", C.POINTER(C.c_double)), ("history_len", C.c_int), ("orth", C.c_int),
+                ("matvec", C.c_int)]
 
 
 class Report(C.Structure):
@@ -93,6 +96,7 @@ SIGNATURES = {
     "sfft_apply": (I, [P, P, P, PP, I, D, I, U64]),
     "tt_hadamard": (I, [P, P, P, PP, I, D, I, U64]),
     "green_apply": (I, [P, P, P, PP, I, D, I, U64]),
+    "tt_amen_apply": (I, [P, P, P, P, P, D, I, I, D, PP, IP, DP]),
     "tt_round": (I, [P, P, D, I, DP]),
     "tt_norm": (I, [P, P, DP]),
     "tt_axpby": (I, [P, D, P, D, P, PP]),

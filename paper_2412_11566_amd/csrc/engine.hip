@@ -818,6 +818,10 @@ struct SketchOpts {
   // the fixed-point iterate entering this product has a bond rank at the
   // cap (QTT_ORTH_AUTO then takes CholeskyQR2: the sketches are full rank)
   bool saturated = false;
+  // QTT_MV_AMEN: the Green step's factor products by the AMEn-adapted
+  // product, warm-started from the previous update's results in `amen`
+  int matvec = 0;
+  struct AmenSlots* amen = nullptr;
 };
 
 // reduced-precision contractions (FP32, split-BF16) for the lifetime of
@@ -870,6 +874,60 @@ static BufP left_step(const Ctx& X, const TT& A, const TT& x, int k, const cplx*
   }
   X.c->gemm_family = -1;
   return P;
+}
+
+// Right-to-left step of the sketch (and of the frame interfaces of the
+// AMEn product): X1 = x_k W_{k+1} (B, r, din, rho2, l2), then the operator
+// core -> X2 (B, r, rho, dout, l2); W2 is (B, rho_{k+1}, r_{k+1}, l2).
+static BufP right_contract(const Ctx& X, const TT& A, const TT& x, int k, const cplx* W2, int l2) {
+  const int B = x.B;
+  const int rho = A.r[k], rho2 = A.r[k + 1], r = x.r[k], r2 = x.r[k + 1];
+  const int din = x.dout[k], dout = A.dout[k];
+  auto X1 = X.buf((size_t)B * r * din * rho2 * l2);
+  G(X, r * din, l2, r2, OP_N, x.core[k], r2, OP_N, W2, l2, (cplx*)X1->p, (long)rho2 * l2, B,
+    (long)r * din * r2, (long)rho2 * r2 * l2, (long)r * din * rho2 * l2, rho2, 0,
+    (long)r2 * l2, l2);
+  auto X2 = X.buf((size_t)B * r * rho * dout * l2);
+  const int ob = A.opb, g = B / ob;
+  const long ia = ob > 1 ? A.celems(k) : 0;
+  Bat t;
+  t.nb1 = ob;
+  t.sA1 = ia;
+  t.nb2 = g * r;
+  X.c->gemm_family = QTT_K_CONTRACT;
+  if (!A.diag[k]) {
+    t.sB1 = (long)g * r * din * rho2 * l2; t.sC1 = (long)g * r * rho * dout * l2;
+    t.sB2 = (long)din * rho2 * l2; t.sC2 = (long)rho * dout * l2;
+    GB(X, rho * dout, l2, din * rho2, OP_N, A.coreR[k], (long)din * rho2, OP_N, (cplx*)X1->p, l2,
+       (cplx*)X2->p, l2, t);
+  } else {
+    const int d = dout;
+    t.sB1 = (long)g * r * d * rho2 * l2; t.sC1 = (long)g * r * rho * d * l2;
+    t.sB2 = (long)d * rho2 * l2; t.sC2 = (long)rho * d * l2;
+    t.nb3 = d; t.sA3 = rho2; t.sB3 = (long)rho2 * l2; t.sC3 = l2;
+    GB(X, rho, l2, rho2, OP_N, A.core[k], (long)d * rho2, OP_N, (cplx*)X1->p, l2, (cplx*)X2->p,
+       (long)d * l2, t);
+  }
+  X.c->gemm_family = -1;
+  return X2;
+}
+
+// W (B, rho, r, l) = X2 (B, r, rho, dout, l2) contracted over (dout, l2)
+// with a core Om (l, dout, l2): op OP_T takes Om itself (a Gaussian test
+// core, shared by the batch: oms = 0), OP_C its conjugate (a frame core,
+// one per batch element: oms = its size).
+static void right_project(const Ctx& X, int B, int rho, int r, int dout, int l2, const cplx* X2, int op,
+                          const cplx* Om, long oms, int l, cplx* W) {
+  if (rho >= r) {
+    // rows a of X2[b][c] against Om: one product per (b, c)
+    G(X, rho, l, dout * l2, OP_N, X2, (long)dout * l2, op, Om, (long)dout * l2, W, (long)r * l, B,
+      (long)r * rho * dout * l2, oms, (long)rho * r * l, r, (long)rho * dout * l2, 0, l);
+  } else {
+    // rows c (stride rho dout l2) against Om: one product per (b, a), the
+    // longer of the two row counts on the matrix-core M side
+    G(X, r, l, dout * l2, OP_N, X2, (long)rho * dout * l2, op, Om, (long)dout * l2, W, (long)l, B,
+      (long)r * rho * dout * l2, oms, (long)rho * r * l, rho, (long)dout * l2, 0, (long)r * l);
+  }
 }
 
 static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts& o,
@@ -943,36 +1001,9 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
   ck_fill(X, (cplx*)W[L]->p, B, C1(), X.s());
   for (int k = L - 1; k >= 1; --k) {
     if (ident_w[k]) break;  // every bond further left is an identity bond
-    const int rho = A.r[k], rho2 = A.r[k + 1], r = x.r[k], r2 = x.r[k + 1];
-    const int din = x.dout[k], dout = A.dout[k];
+    const int rho = A.r[k], r = x.r[k], dout = A.dout[k];
     const int l2 = ell[k + 1], l = ell[k];
-    const cplx* W2 = (cplx*)W[k + 1]->p;
-    auto X1 = X.buf((size_t)B * r * din * rho2 * l2);
-    G(X, r * din, l2, r2, OP_N, x.core[k], r2, OP_N, W2, l2, (cplx*)X1->p, (long)rho2 * l2, B,
-      (long)r * din * r2, (long)rho2 * r2 * l2, (long)r * din * rho2 * l2, rho2, 0,
-      (long)r2 * l2, l2);
-    auto X2 = X.buf((size_t)B * r * rho * dout * l2);
-    const int ob = A.opb, g = B / ob;
-    const long ia = ob > 1 ? A.celems(k) : 0;
-    Bat t;
-    t.nb1 = ob;
-    t.sA1 = ia;
-    t.nb2 = g * r;
-    X.c->gemm_family = QTT_K_CONTRACT;
-    if (!A.diag[k]) {
-      t.sB1 = (long)g * r * din * rho2 * l2; t.sC1 = (long)g * r * rho * dout * l2;
-      t.sB2 = (long)din * rho2 * l2; t.sC2 = (long)rho * dout * l2;
-      GB(X, rho * dout, l2, din * rho2, OP_N, A.coreR[k], (long)din * rho2, OP_N, (cplx*)X1->p, l2,
-         (cplx*)X2->p, l2, t);
-    } else {
-      const int d = dout;
-      t.sB1 = (long)g * r * d * rho2 * l2; t.sC1 = (long)g * r * rho * d * l2;
-      t.sB2 = (long)d * rho2 * l2; t.sC2 = (long)rho * d * l2;
-      t.nb3 = d; t.sA3 = rho2; t.sB3 = (long)rho2 * l2; t.sC3 = l2;
-      GB(X, rho, l2, rho2, OP_N, A.core[k], (long)d * rho2, OP_N, (cplx*)X1->p, l2, (cplx*)X2->p,
-         (long)d * l2, t);
-    }
-    X.c->gemm_family = -1;
+    auto X2 = right_contract(X, A, x, k, (const cplx*)W[k + 1]->p, l2);
     W[k] = X.buf((size_t)B * rho * r * l);
     if (dense_w[k]) {
       // W_k[b][a][c][(i t)] = X2[b][c][a][(i t)]  (l = dout * l2)
@@ -980,17 +1011,9 @@ static TTP sketch_apply(const Ctx& X, const TT& A, const TT& x, const SketchOpts
       for (int b = 0; b < B; ++b)
         ck_copy2d(X, r, rho, (int)m, MatView{(cplx*)X2->p + (long)b * r * rho * m, m, 1, rho * m, 0},
                   MatOut{(cplx*)W[k]->p + (long)b * rho * r * m, (long)r * m, 1, m}, C1(), X.s());
-    } else if (rho >= r) {
-      // rows a of X2[b][c] against Omega_k: one product per (b, c)
-      G(X, rho, l, dout * l2, OP_N, (cplx*)X2->p, (long)dout * l2, OP_T, (cplx*)Om[k]->p,
-        (long)dout * l2, (cplx*)W[k]->p, (long)r * l, B, (long)r * rho * dout * l2, 0,
-        (long)rho * r * l, r, (long)rho * dout * l2, 0, l);
     } else {
-      // rows c (stride rho dout l2) against Omega_k: one product per (b, a),
-      // the longer of the two row counts on the matrix-core M side
-      G(X, r, l, dout * l2, OP_N, (cplx*)X2->p, (long)rho * dout * l2, OP_T, (cplx*)Om[k]->p,
-        (long)dout * l2, (cplx*)W[k]->p, (long)l, B, (long)r * rho * dout * l2, 0,
-        (long)rho * r * l, rho, (long)dout * l2, 0, (long)r * l);
+      right_project(X, B, rho, r, dout, l2, (const cplx*)X2->p, OP_T, (const cplx*)Om[k]->p, 0, l,
+                    (cplx*)W[k]->p);
     }
   }
   // left-to-right: QR of sketched unfoldings
@@ -1126,19 +1149,27 @@ static TTP round_any(const Ctx& X, const TTP& x, const SketchOpts& o, RoundStats
 
 // Green step of Alg. 2 in bounded factors (see qtt_green_build):
 // u = U x, s = Sd u, p = P s, q = u/(2 mu0) - (c/2) p, eps = E q.
+static TTP amen_product(const Ctx& X, const TT& A, const TT& x, const SketchOpts& o, int slot, RoundStats* st);
+
 static TTP green_chain(const Ctx& X, const TT& G, const TT& x, int flags, const SketchOpts& o,
                        RoundStats* st) {
   SketchOpts o2 = o;
   RoundStats s1;
   double disc = 0.0;
+  // QTT_MV_AMEN: the four factor products by AMEn (rounded products of
+  // Alg. 2's Green step, App. B), warm-started per factor
+  const bool am = o.matvec == QTT_MV_AMEN && o.amen && !o.exact && o.cap > 0 && !(flags & (QTT_EXACT | QTT_NO_ROUND));
+  auto prod = [&](const TT& A, const TT& v, int slot, RoundStats* sp) {
+    return am ? amen_product(X, A, v, o2, slot, sp) : op_apply(X, A, v, flags, o2, sp);
+  };
   o2.seed = o.seed * 7 + 1;
-  auto u = op_apply(X, *G.gU, x, flags, o2, &s1);
+  auto u = prod(*G.gU, x, 0, &s1);
   disc = std::max(disc, s1.rel_max());
   o2.seed = o.seed * 7 + 2;
-  auto s = op_apply(X, *G.gS, *u, flags, o2, &s1);
+  auto s = prod(*G.gS, *u, 1, &s1);
   disc = std::max(disc, s1.rel_max());
   o2.seed = o.seed * 7 + 3;
-  auto p = op_apply(X, *G.gP, *s, flags, o2, &s1);
+  auto p = prod(*G.gP, *s, 2, &s1);
   disc = std::max(disc, s1.rel_max());
   TTP q;
   if (G.inv_mu0_b) {
@@ -1156,7 +1187,7 @@ static TTP green_chain(const Ctx& X, const TT& G, const TT& x, int flags, const 
   }
   o2.seed = o.seed * 7 + 4;
   o2.no_truncate = o.no_truncate;
-  auto e = op_apply(X, *G.gE, *q, flags, o2, st);
+  auto e = prod(*G.gE, *q, 3, st);
   if (st) {
     // fold the intermediate roundings into the reported maximum
     for (size_t b = 0; b < st->disc2.size(); ++b)
@@ -1173,6 +1204,363 @@ static TTP op_apply(const Ctx& X, const TT& A, const TT& x, int flags, const Ske
   SketchOpts o2 = o;
   if (flags & QTT_EXACT) o2.exact = true;
   return sketch_apply(X, A, x, o2, st);
+}
+
+// ---------------------------------------------------------------------------
+// AMEn-adapted product y ~ A x (App. B)
+// ---------------------------------------------------------------------------
+static std::vector<double> diff_norms(const Ctx& X, const TT& a, const TT& b, double prev_rel);
+
+// QR sweep right to left: cores 1..L-1 become right-orthonormal (orthonormal
+// rows of the r_k x (d r_{k+1}) unfolding), the R factors move left; the
+// tensor is unchanged.
+static void orth_rl(const Ctx& X, TT& y) {
+  const int L = y.L, B = y.B;
+  for (int k = L - 1; k >= 1; --k) {
+    const int p = y.r[k], q = y.dout[k] * y.r[k + 1];
+    const int kk = std::min(p, q);
+    const long msz = (long)p * q;
+    // M^H (q x p) = Q R, so M = R^H Q^H
+    auto Qb = X.buf((size_t)B * q * kk);
+    auto R = X.buf((size_t)B * kk * p);
+    auto ws = X.buf(qr_ws(B, q, p));
+    ck_qr(X, B, q, p, MatView{y.core[k], 1, (long)q, msz, 1}, MatOut{(cplx*)R->p, (long)p, 1, (long)kk * p},
+          MatOut{(cplx*)Qb->p, (long)kk, 1, (long)q * kk}, (cplx*)ws->p, X.s());
+    auto nk = X.buf((size_t)B * kk * q);
+    ck_conj_transpose(X, B, q, kk, MatView{(cplx*)Qb->p, (long)kk, 1, (long)q * kk, 0},
+                      MatOut{(cplx*)nk->p, (long)q, 1, (long)kk * q}, X.s());
+    const int rows = y.r[k - 1] * y.dout[k - 1];
+    auto nk1 = X.buf((size_t)B * rows * kk);
+    G(X, rows, kk, p, OP_N, y.core[k - 1], p, OP_C, (cplx*)R->p, p, (cplx*)nk1->p, kk, B, (long)rows * p,
+      (long)kk * p, (long)rows * kk);
+    set_core(X, y, k, kk, y.r[k + 1], nk);
+    set_core(X, y, k - 1, y.r[k - 1], kk, nk1);
+  }
+}
+
+// Left singular vectors U (B, m, kk) and singular values (host, B x kk,
+// descending) of B matrices Y (m x n, row-major), kk = min(m, n): QR of the
+// tall orientation, one-sided Jacobi of its square factor.
+static BufP left_singular(const Ctx& X, int B, int m, int n, const cplx* Y, std::vector<double>& S) {
+  const int kk = std::min(m, n);
+  if (kk > 320) throw std::length_error("AMEn local core beyond the Jacobi size");
+  auto R = X.buf((size_t)B * kk * kk);
+  auto Sd = X.bufd((size_t)B * kk);
+  auto U = X.buf((size_t)B * m * kk);
+  const long ysz = (long)m * n;
+  if (m >= n) {
+    auto Q = X.buf((size_t)B * m * kk);
+    auto ws = X.buf(qr_ws(B, m, n));
+    ck_qr(X, B, m, n, MatView{Y, (long)n, 1, ysz, 0}, MatOut{(cplx*)R->p, (long)kk, 1, (long)kk * kk},
+          MatOut{(cplx*)Q->p, (long)kk, 1, (long)m * kk}, (cplx*)ws->p, X.s());
+    auto UR = X.buf((size_t)B * kk * kk);
+    jacobi_any(X, B, kk, MatView{(cplx*)R->p, (long)kk, 1, (long)kk * kk, 0},
+               MatOut{(cplx*)UR->p, (long)kk, 1, (long)kk * kk}, (double*)Sd->p);
+    G(X, m, kk, kk, OP_N, (cplx*)Q->p, kk, OP_N, (cplx*)UR->p, kk, (cplx*)U->p, kk, B, (long)m * kk,
+      (long)kk * kk, (long)m * kk);
+  } else {
+    // Y^H (n x m) = Q R, Y = R^H Q^H: the left singular vectors of R^H
+    auto ws = X.buf(qr_ws(B, n, m));
+    ck_qr(X, B, n, m, MatView{Y, 1, (long)n, ysz, 1}, MatOut{(cplx*)R->p, (long)kk, 1, (long)kk * kk},
+          MatOut{nullptr, 0, 0, 0}, (cplx*)ws->p, X.s());
+    jacobi_any(X, B, kk, MatView{(cplx*)R->p, 1, (long)kk, (long)kk * kk, 1},
+               MatOut{(cplx*)U->p, (long)kk, 1, (long)kk * kk}, (double*)Sd->p);
+  }
+  S.resize((size_t)B * kk);
+  check(hipMemcpyAsync(S.data(), Sd->p, S.size() * sizeof(double), hipMemcpyDeviceToHost, X.s()), "S d2h");
+  X.sync();
+  return U;
+}
+
+// One left-to-right AMEn sweep.  y and z are right-orthonormal (cores
+// 1..L-1) on entry.  At core k the local solution is the projection of
+// A x onto y's frame (the Galerkin condition: left interface Ly, right
+// interface Wy), truncated by SVD at delta / sqrt(L - 1) of its norm and
+// the cap; the residual A x - y is projected onto z's frame (its new core)
+// and, with y's left and z's right frame, enriches the kept singular
+// vectors before the QR that gives y's core.  On return y holds the
+// enriched cores (left-orthonormal but the last), z the residual train,
+// and kept the truncated rank of every bond.
+static void amen_sweep(const Ctx& X, const TT& A, const TT& x, TT& y, TT& z, double delta, int cap,
+                       std::vector<int>& kept, RoundStats* st = nullptr) {
+  const int L = x.L, B = x.B;
+  // right interfaces Wy[k] (B, rho_k, r_k, ry_k) and Wz[k] (B, rho_k, r_k,
+  // rz_k) of A x against conj(y), conj(z) over the cores k..L-1; SRc[k]
+  // (B, rz_k, ry_k) the conjugate of sum conj(z) y over the same cores
+  std::vector<BufP> Wy(L + 1), Wz(L + 1), SRc(L + 1);
+  for (auto* v : {&Wy, &Wz, &SRc}) {
+    (*v)[L] = X.buf(B);
+    ck_fill(X, (cplx*)(*v)[L]->p, B, C1(), X.s());
+  }
+  for (int k = L - 1; k >= 1; --k) {
+    const int rho = A.r[k], r = x.r[k], d = A.dout[k];
+    const int ry = y.r[k], ry2 = y.r[k + 1], rz = z.r[k], rz2 = z.r[k + 1];
+    auto Xy = right_contract(X, A, x, k, (const cplx*)Wy[k + 1]->p, ry2);
+    Wy[k] = X.buf((size_t)B * rho * r * ry);
+    right_project(X, B, rho, r, d, ry2, (const cplx*)Xy->p, OP_C, y.core[k], y.celems(k), ry, (cplx*)Wy[k]->p);
+    auto Xz = right_contract(X, A, x, k, (const cplx*)Wz[k + 1]->p, rz2);
+    Wz[k] = X.buf((size_t)B * rho * r * rz);
+    right_project(X, B, rho, r, d, rz2, (const cplx*)Xz->p, OP_C, z.core[k], z.celems(k), rz, (cplx*)Wz[k]->p);
+    // T = y_k SR[k+1]^T (ry d x rz2); SRc[k] = z_k T^H
+    auto T = X.buf((size_t)B * ry * d * rz2);
+    G(X, ry * d, rz2, ry2, OP_N, y.core[k], ry2, OP_C, (cplx*)SRc[k + 1]->p, ry2, (cplx*)T->p, rz2, B,
+      y.celems(k), (long)rz2 * ry2, (long)ry * d * rz2);
+    SRc[k] = X.buf((size_t)B * rz * ry);
+    G(X, rz, ry, d * rz2, OP_N, z.core[k], (long)d * rz2, OP_C, (cplx*)T->p, (long)d * rz2, (cplx*)SRc[k]->p, ry,
+      B, z.celems(k), (long)ry * d * rz2, (long)rz * ry);
+  }
+  BufP Ly = X.buf(B), Lz = X.buf(B), SL = X.buf(B);
+  for (auto* v : {&Ly, &Lz, &SL}) ck_fill(X, (cplx*)(*v)->p, B, C1(), X.s());
+  kept.assign(L + 1, 1);
+  const double tscale = delta / std::sqrt((double)std::max(L - 1, 1));
+  std::vector<double> disc2(B, 0.0), norm(B, 0.0);
+  for (int k = 0; k < L; ++k) {
+    const int d = A.dout[k], rho2 = A.r[k + 1], r2 = x.r[k + 1];
+    const int ry = y.r[k], ry2 = y.r[k + 1], rz = z.r[k], rz2 = z.r[k + 1];
+    const int m = ry * d, mz = rz * d;
+    const long pr = (long)rho2 * r2;
+    auto Py = left_step(X, A, x, k, (const cplx*)Ly->p, ry);  // (B, ry, d, rho2, r2)
+    auto Pz = left_step(X, A, x, k, (const cplx*)Lz->p, rz);
+    // Galerkin solution (B, m, ry2) and the residual in z's frame (B, mz, rz2)
+    auto Yk = X.buf((size_t)B * m * ry2);
+    G(X, m, ry2, (int)pr, OP_N, (cplx*)Py->p, pr, OP_N, (cplx*)Wy[k + 1]->p, ry2, (cplx*)Yk->p, ry2, B,
+      (long)m * pr, pr * ry2, (long)m * ry2);
+    auto Zk = X.buf((size_t)B * mz * rz2);
+    G(X, mz, rz2, (int)pr, OP_N, (cplx*)Pz->p, pr, OP_N, (cplx*)Wz[k + 1]->p, rz2, (cplx*)Zk->p, rz2, B,
+      (long)mz * pr, pr * rz2, (long)mz * rz2);
+    if (k == L - 1) {
+      // Zk -= SL Yk (the right interfaces are 1 here)
+      G(X, rz, d, ry, OP_N, (cplx*)SL->p, ry, OP_N, (cplx*)Yk->p, d, (cplx*)Zk->p, d, B, (long)rz * ry,
+        (long)m, (long)mz, 1, 0, 0, 0, CR(-1.0), C1());
+      set_core(X, y, k, ry, 1, Yk);
+      set_core(X, z, k, rz, 1, Zk);
+      if (st) {
+        st->disc2 = disc2;
+        st->norm = norm;
+      }
+      break;
+    }
+    // truncation of the local solution (its norm is that of the singular
+    // values: one host transfer per core)
+    std::vector<double> S;
+    auto U = left_singular(X, B, m, ry2, (const cplx*)Yk->p, S);
+    const int kk = std::min(m, ry2);
+    std::vector<double> nrm(B, 0.0);
+    for (int b = 0; b < B; ++b) {
+      for (int j = 0; j < kk; ++j) nrm[b] += S[(size_t)b * kk + j] * S[(size_t)b * kk + j];
+      nrm[b] = std::sqrt(nrm[b]);
+      if (!std::isfinite(nrm[b])) throw nan_error("NaN/Inf in an AMEn local core");
+    }
+    std::vector<double> thr(B);
+    for (int b = 0; b < B; ++b) {
+      thr[b] = tscale * nrm[b];
+      norm[b] = nrm[b];
+    }
+    const int r = choose_rank(S, B, kk, thr, cap, disc2);
+    kept[k + 1] = r;
+    // Yt = U_r U_r^H Yk, the truncated local core
+    auto Cc = X.buf((size_t)B * r * ry2);
+    G(X, r, ry2, m, OP_C, (cplx*)U->p, kk, OP_N, (cplx*)Yk->p, ry2, (cplx*)Cc->p, ry2, B, (long)m * kk,
+      (long)m * ry2, (long)r * ry2);
+    auto Yt = X.buf((size_t)B * m * ry2);
+    G(X, m, ry2, r, OP_N, (cplx*)U->p, kk, OP_N, (cplx*)Cc->p, ry2, (cplx*)Yt->p, ry2, B, (long)m * kk,
+      (long)r * ry2, (long)m * ry2);
+    // Zk -= (SL Yt) SR[k+1]^T
+    auto T1 = X.buf((size_t)B * rz * d * ry2);
+    G(X, rz, d * ry2, ry, OP_N, (cplx*)SL->p, ry, OP_N, (cplx*)Yt->p, (long)d * ry2, (cplx*)T1->p,
+      (long)d * ry2, B, (long)rz * ry, (long)m * ry2, (long)rz * d * ry2);
+    G(X, mz, rz2, ry2, OP_N, (cplx*)T1->p, ry2, OP_C, (cplx*)SRc[k + 1]->p, ry2, (cplx*)Zk->p, rz2, B,
+      (long)mz * ry2, (long)rz2 * ry2, (long)mz * rz2, 1, 0, 0, 0, CR(-1.0), C1());
+    // enrichment [U_r, Py Wz[k+1] - Yt SR[k+1]^T] (B, m, r + rz2)
+    const int ke = r + rz2;
+    auto UE = X.buf((size_t)B * m * ke);
+    ck_copy2d(X, B, m, r, MatView{(cplx*)U->p, (long)kk, 1, (long)m * kk, 0},
+              MatOut{(cplx*)UE->p, (long)ke, 1, (long)m * ke}, C1(), X.s());
+    G(X, m, rz2, (int)pr, OP_N, (cplx*)Py->p, pr, OP_N, (cplx*)Wz[k + 1]->p, rz2, (cplx*)UE->p + r, ke, B,
+      (long)m * pr, pr * rz2, (long)m * ke);
+    G(X, m, rz2, ry2, OP_N, (cplx*)Yt->p, ry2, OP_C, (cplx*)SRc[k + 1]->p, ry2, (cplx*)UE->p + r, ke, B,
+      (long)m * ry2, (long)rz2 * ry2, (long)m * ke, 1, 0, 0, 0, CR(-1.0), C1());
+    const int kq = std::min(m, ke);
+    auto Q = X.buf((size_t)B * m * kq);
+    {
+      auto R = X.buf((size_t)B * kq * ke);
+      auto ws = X.buf(qr_ws(B, m, ke));
+      ck_qr(X, B, m, ke, MatView{(cplx*)UE->p, (long)ke, 1, (long)m * ke, 0},
+            MatOut{(cplx*)R->p, (long)ke, 1, (long)kq * ke}, MatOut{(cplx*)Q->p, (long)kq, 1, (long)m * kq},
+            (cplx*)ws->p, X.s());
+    }
+    const int kz = std::min(mz, rz2);
+    auto Qz = X.buf((size_t)B * mz * kz);
+    {
+      auto R = X.buf((size_t)B * kz * rz2);
+      auto ws = X.buf(qr_ws(B, mz, rz2));
+      ck_qr(X, B, mz, rz2, MatView{(cplx*)Zk->p, (long)rz2, 1, (long)mz * rz2, 0},
+            MatOut{(cplx*)R->p, (long)rz2, 1, (long)kz * rz2}, MatOut{(cplx*)Qz->p, (long)kz, 1, (long)mz * kz},
+            (cplx*)ws->p, X.s());
+    }
+    // left interfaces through core k
+    auto Ly2 = X.buf((size_t)B * kq * pr);
+    G(X, kq, (int)pr, m, OP_C, (cplx*)Q->p, kq, OP_N, (cplx*)Py->p, pr, (cplx*)Ly2->p, pr, B, (long)m * kq,
+      (long)m * pr, (long)kq * pr);
+    auto Lz2 = X.buf((size_t)B * kz * pr);
+    G(X, kz, (int)pr, mz, OP_C, (cplx*)Qz->p, kz, OP_N, (cplx*)Pz->p, pr, (cplx*)Lz2->p, pr, B, (long)mz * kz,
+      (long)mz * pr, (long)kz * pr);
+    auto T2 = X.buf((size_t)B * rz * d * kq);
+    G(X, rz, d * kq, ry, OP_N, (cplx*)SL->p, ry, OP_N, (cplx*)Q->p, (long)d * kq, (cplx*)T2->p, (long)d * kq, B,
+      (long)rz * ry, (long)m * kq, (long)rz * d * kq);
+    auto SL2 = X.buf((size_t)B * kz * kq);
+    G(X, kz, kq, mz, OP_C, (cplx*)Qz->p, kz, OP_N, (cplx*)T2->p, kq, (cplx*)SL2->p, kq, B, (long)mz * kz,
+      (long)mz * kq, (long)kz * kq);
+    // core k of y and z; core k + 1 keeps its old left rank until its
+    // own step replaces it
+    set_core(X, y, k, ry, kq, Q);
+    set_core(X, z, k, rz, kz, Qz);
+    Ly = Ly2;
+    Lz = Lz2;
+    SL = SL2;
+  }
+}
+
+// Deep copy of a train (cores into new buffers).
+static TTP copy_tt(const Ctx& X, const TT& x) {
+  auto t = new_tt(X, x.L, x.B, x.dout, x.r);
+  for (int k = 0; k < x.L; ++k)
+    check(hipMemcpyAsync(t->core[k], x.core[k], (size_t)x.B * x.celems(k) * sizeof(cplx), hipMemcpyDeviceToDevice,
+                         X.s()),
+          "train copy");
+  return t;
+}
+
+// The product without its enrichment: on every bond the first kept[k]
+// columns of the enriched basis (they span the kept singular vectors) and
+// the matching rows of the next core.
+static TTP amen_compact(const Ctx& X, const TT& y, const std::vector<int>& kept) {
+  auto t = new_tt(X, y.L, y.B, y.dout, kept);
+  for (int k = 0; k < y.L; ++k) {
+    const int r0 = y.r[k], d = y.dout[k], r1 = y.r[k + 1];
+    ck_copy2d(X, y.B, kept[k] * d, kept[k + 1], MatView{y.core[k], (long)r1, 1, (long)r0 * d * r1, 0},
+              MatOut{t->core[k], (long)kept[k + 1], 1, (long)kept[k] * d * kept[k + 1]}, C1(), X.s());
+  }
+  return t;
+}
+
+struct AmenInfo {
+  int sweeps = 0;
+  double change = INFINITY;
+};
+
+// y ~ A x by AMEn sweeps from the initial guesses y0 and z0 (same batch and
+// dimensions as the product), truncation delta and cap, at most `sweeps`
+// sweeps, stopped when the product changes by less than tol (relative,
+// largest over the batch) between two sweeps.
+static TTP amen_apply(const Ctx& X, const TT& A, const TT& x, const TT& y0, const TT& z0, double delta, int cap,
+                      int sweeps, double tol, AmenInfo* info, TTP* z_out = nullptr, RoundStats* st = nullptr) {
+  const int L = x.L, B = x.B;
+  if (A.kind != 1 || A.L != L) throw std::invalid_argument("AMEn: operator and train differ");
+  if (B % A.opb) throw std::invalid_argument("train batch not a multiple of the operator instances");
+  for (const TT* t : {&y0, &z0}) {
+    if (t->kind != 0 || t->L != L || t->B != B) throw std::invalid_argument("AMEn: initial guess shape");
+    for (int k = 0; k < L; ++k)
+      if (t->dout[k] != A.dout[k]) throw std::invalid_argument("AMEn: initial guess dims");
+  }
+  for (int k = 0; k < L; ++k)
+    if (A.din[k] != x.dout[k]) throw std::invalid_argument("operator input dim mismatch");
+  auto y = copy_tt(X, y0), z = copy_tt(X, z0);
+  orth_rl(X, *y);
+  orth_rl(X, *z);
+  TTP out, prev;
+  AmenInfo inf;
+  for (int m = 1; m <= std::max(1, sweeps); ++m) {
+    std::vector<int> kept;
+    amen_sweep(X, A, x, *y, *z, delta, cap, kept, st);
+    out = amen_compact(X, *y, kept);
+    inf.sweeps = m;
+    if (prev) {
+      auto dn = diff_norms(X, *out, *prev, 0.0);
+      auto nn = tt_norms(X, *out);
+      double ch = 0.0;
+      for (int b = 0; b < B; ++b) ch = std::max(ch, dn[b] / std::max(nn[b], 1e-300));
+      inf.change = ch;
+      if (ch < tol) break;
+    }
+    prev = out;
+    if (m < sweeps) {
+      // fresh trains (the sweep's set_core calls keep every replaced core)
+      y = copy_tt(X, *y);
+      z = copy_tt(X, *z);
+      orth_rl(X, *y);
+      orth_rl(X, *z);
+    }
+  }
+  if (info) *info = inf;
+  if (z_out) *z_out = z;
+  return out;
+}
+
+// Warm starts of the AMEn products of a fixed-point loop: the last result
+// and residual train of every product slot.
+struct AmenSlots {
+  std::map<int, std::pair<TTP, TTP>> yz;
+  int sweeps = 6;       // cold start: at most this many sweeps
+  int warm_sweeps = 3;  // warm start: at most this many sweeps
+  int kick = 8;         // rank of the residual train
+  // the sweeps stop when the product changes by less than this (relative)
+  // between two sweeps; the loop ties it to its last relative update
+  double tol = 1e-3;
+};
+
+// Random complex Gaussian train (cores scaled by 1 / sqrt(d r_{k+1})) with
+// the given ranks, from the sketch generator's stream.
+static TTP random_train(const Ctx& X, int L, int B, const std::vector<int>& dims, const std::vector<int>& ranks,
+                        uint64_t seed) {
+  auto t = new_tt(X, L, B, dims, ranks);
+  GaussBlocks gb;
+  gb.start[0] = 0;
+  for (int k = 0; k < L; ++k) {
+    const long cnt = (long)B * t->celems(k);
+    gb.out[gb.n] = t->core[k];
+    gb.stream[gb.n] = (uint64_t)k;
+    gb.scale[gb.n] = 1.0 / std::sqrt((double)dims[k] * ranks[k + 1]);
+    gb.start[gb.n + 1] = gb.start[gb.n] + cnt;
+    if (++gb.n == GAUSS_MULTI_MAX) {
+      gaussian_multi(gb, seed, X.s());
+      gb.n = 0;
+    }
+  }
+  gaussian_multi(gb, seed, X.s());
+  return t;
+}
+
+static std::vector<int> capped_ranks(const std::vector<int>& dims, int r) {
+  const int L = (int)dims.size();
+  std::vector<int> rk(L + 1, 1);
+  long left = 1;
+  for (int k = 1; k < L; ++k) {
+    left = std::min<long>(left * dims[k - 1], 1L << 30);
+    long right = 1;
+    for (int j = k; j < L && right < (1L << 30); ++j) right *= dims[j];
+    rk[k] = (int)std::max<long>(1, std::min<long>(r, std::min(left, right)));
+  }
+  return rk;
+}
+
+// One product of the Green step by AMEn: the previous result in this slot
+// (same batch) is the initial guess, else a random train at the cap's
+// ranks; sweeps run until the product settles to the loop's tolerance.
+// The residual train is carried the same way.
+static TTP amen_product(const Ctx& X, const TT& A, const TT& x, const SketchOpts& o, int slot, RoundStats* st) {
+  AmenSlots& am = *o.amen;
+  auto& prev = am.yz[slot];
+  const int L = x.L, B = x.B;
+  const bool warm = prev.first && prev.second && prev.first->B == B && prev.first->dout == A.dout;
+  TTP y0 = warm ? prev.first : random_train(X, L, B, A.dout, capped_ranks(A.dout, o.cap), o.seed * 31 + 7);
+  TTP z0 = warm ? prev.second : random_train(X, L, B, A.dout, capped_ranks(A.dout, am.kick), o.seed * 31 + 11);
+  AmenInfo inf;
+  TTP z;
+  auto y = amen_apply(X, A, x, *y0, *z0, o.delta, o.cap, warm ? am.warm_sweeps : am.sweeps,
+                      std::max(o.delta, am.tol), &inf, &z, st);
+  prev = std::make_pair(y, z);
+  return y;
 }
 
 // Volume average of A(x) : x -> host (B x 6) complex; A's core 0 is 6x6.
@@ -1781,6 +2169,8 @@ static void check_problem(const qtt_problem* P, const qtt_solve_opts* O) {
   if (O->history && O->history_len < 1) throw std::invalid_argument("history without a length");
   if (O->orth != QTT_ORTH_HOUSEHOLDER && O->orth != QTT_ORTH_CHOLQR && O->orth != QTT_ORTH_AUTO)
     throw std::invalid_argument("orth must be QTT_ORTH_HOUSEHOLDER, QTT_ORTH_CHOLQR or QTT_ORTH_AUTO");
+  if (O->matvec != QTT_MV_SKETCH && O->matvec != QTT_MV_AMEN)
+    throw std::invalid_argument("matvec must be QTT_MV_SKETCH or QTT_MV_AMEN");
   for (int i = 0; i < 2 * P->nphase; ++i)
     if (!std::isfinite(P->lame[i])) throw std::invalid_argument("non-finite phase modulus");
   if (!std::isfinite(P->lame0[0]) || !(P->lame0[1] > 0.0) || !(P->lame0[0] + 2.0 * P->lame0[1] > 0.0))
@@ -1806,6 +2196,7 @@ static SketchOpts sk(const Ctx& X, const qtt_solve_opts* O) {
   s.fp32 = O->precision == QTT_PREC_FP32;
   s.bf16 = O->precision == QTT_PREC_BF16X3;
   s.orth = O->orth;
+  s.matvec = O->matvec;
   s.seed = O->seed * 1000003ULL + (X.c->sketch_counter++);
   return s;
 }
@@ -1859,6 +2250,7 @@ static SolveOut ls_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, cons
   std::vector<char> done(B, 0);
   int m = 0;
   double last_disc = 0.0;
+  AmenSlots amen;  // warm starts of the AMEn Green products (QTT_MV_AMEN)
   while (true) {
     RoundStats st;
     // fresh sketches in every update: with the same test matrices in every
@@ -1871,7 +2263,16 @@ static SolveOut ls_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, cons
     const bool sat = saturated(*eps, O->cap, last_disc);
     auto tau = op_apply(X, *ops.Cd, *eps, 0, satur(ski(X, O), sat), &st);
     auto th = op_apply(X, *ops.S, *tau, 0, satur(ski(X, O), sat), &st);
-    auto eh = op_apply(X, *ops.G, *th, 0, satur(ski(X, O), sat), &st);
+    SketchOpts og = satur(ski(X, O), sat);
+    og.amen = &amen;
+    {
+      // inexact inner products: a twentieth of the last relative update
+      double last = 0.0;
+      for (int b = 0; b < B; ++b)
+        if (!done[b] && std::isfinite(out.res[b])) last = std::max(last, out.res[b]);
+      amen.tol = m == 0 ? 1e-3 : std::min(1e-3, 0.05 * last);
+    }
+    auto eh = op_apply(X, *ops.G, *th, 0, og, &st);
     auto y = op_apply(X, *ops.S->adj, *eh, 0, satur(ski(X, O), sat), &st);
     auto nw = round_any(X, axpby(X, 1.0, *Et, -1.0, *y), satur(sk(X, O), sat), &st);
     out.disc = std::max(out.disc, st.rel_max());
@@ -2378,6 +2779,21 @@ int green_apply(qtt_ctx* c, const qtt_tensor* Gm, const qtt_tensor* x, qtt_tenso
   return product(c, Gm, x, y, flags, delta, cap, seed, false);
 }
 
+int tt_amen_apply(qtt_ctx* c, const qtt_tensor* A, const qtt_tensor* x, const qtt_tensor* y0,
+                  const qtt_tensor* z0, double delta, int cap, int sweeps, double tol, qtt_tensor** y,
+                  int* sweeps_run, double* change) {
+  if (!c || !A || !x || !y0 || !z0 || !y || A->kind != 1 || x->kind != 0 || !(delta > 0) || sweeps < 1 ||
+      !(tol >= 0))
+    return QTT_EINVAL;
+  QTT_TRY(c, {
+    Ctx X{c};
+    AmenInfo inf;
+    *y = new qtt_tensor(*amen_apply(X, *A, *x, *y0, *z0, delta, cap, sweeps, tol, &inf));
+    if (sweeps_run) *sweeps_run = inf.sweeps;
+    if (change) *change = inf.change;
+  });
+}
+
 int tt_round(qtt_ctx* c, qtt_tensor* x, double delta, int cap, double* discarded) {
   if (!c || !x || x->kind != 0 || !(delta >= 0)) return QTT_EINVAL;
   QTT_TRY(c, {
@@ -2876,11 +3292,20 @@ static AdjOut adj_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, const
   out.res.assign(B, 0.0);
   std::vector<char> done(B, 0);
   int m = 0;
+  AmenSlots amen;  // warm starts of the AMEn Green products (QTT_MV_AMEN)
   while (true) {
     const bool sat = saturated(*w, O->cap, last_disc);
     RoundStats st;
     auto u = op_apply(X, *ops.S, *w, 0, satur(ski(X, O), sat), nullptr);
-    u = op_apply(X, *ops.G, *u, 0, satur(ski(X, O), sat), nullptr);
+    SketchOpts og = satur(ski(X, O), sat);
+    og.amen = &amen;
+    {
+      double last = 0.0;
+      for (int b = 0; b < B; ++b)
+        if (!done[b]) last = std::max(last, out.res[b]);
+      amen.tol = m == 0 ? 1e-3 : std::min(1e-3, 0.05 * last);
+    }
+    u = op_apply(X, *ops.G, *u, 0, og, nullptr);
     u = op_apply(X, *ops.S->adj, *u, 0, satur(ski(X, O), sat), nullptr);
     u = op_apply(X, *ops.Cd, *u, 0, satur(ski(X, O), sat), nullptr);
     auto nw = round_any(X, axpby(X, 1.0, *Ce, -1.0, *u), satur(sk(X, O), sat), &st);
