@@ -286,6 +286,20 @@ int qtt_green_build_scheme(qtt_ctx* ctx, int n, double lam0, double mu0,
  * uint8, C order, x slowest, values < nphase.  lame: host [nphase][2].
  * The optional `chi` receives the one-hot phase train (core 0 of
  * dimension nphase).  QTT_ECAPACITY if a rank would exceed `cap`. */
+/* Applicability estimate from two discretisation orders (Sec. 5.2: the
+ * geometry compressed at two orders indicates the rank and its growth):
+ * the one-hot phase train of the voxel array (order n) and of its coarsened
+ * copy (order n - 1: the majority phase of every 2 x 2 x 2 block, ties to
+ * the lowest id) by the device TT-SVD at `delta`.  ranks[0], ranks[1]: the
+ * largest bond rank at order n - 1 and n; growth (optional): their ratio
+ * (about 2 per order when the rank grows exponentially with the
+ * resolution, about 1 when it saturates).  phase: host or device
+ * (`phase_on_device`), N^3 uint8, n >= 2.  QTT_EINVAL for a phase id
+ * >= nphase; QTT_ECAPACITY when a bond needs more than 160. */
+int qtt_rank_estimate(qtt_ctx* ctx, const uint8_t* phase, int phase_on_device,
+                      int n, int nphase, double delta, int* ranks,
+                      double* growth);
+
 int qtt_from_voxels(qtt_ctx* ctx, const uint8_t* phase, int phase_on_device,
                     int n, int nphase, const double* lame,
                     const double lame0[2], double delta, int cap,

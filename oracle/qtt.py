@@ -301,6 +301,30 @@ def stiffness_tto(phase: np.ndarray, lame, lame0, delta: float, cap: int = 1 << 
     return [c0] + raise_tt(cores[1:])
 
 
+def coarsen_majority(phase: np.ndarray, nphase: int) -> np.ndarray:
+    """The geometry one discretisation order lower: the majority phase of
+    every 2 x 2 x 2 block of voxels, ties to the lowest phase id."""
+    N = phase.shape[0]
+    h = N // 2
+    blocks = phase.reshape(h, 2, h, 2, h, 2).transpose(0, 2, 4, 1, 3, 5).reshape(h, h, h, 8)
+    counts = np.stack([(blocks == p).sum(axis=-1) for p in range(nphase)], axis=-1)
+    return np.argmax(counts, axis=-1).astype(np.uint8)     # argmax: first maximum
+
+
+def rank_estimate(phase: np.ndarray, nphase: int, delta: float):
+    """Applicability estimate from two discretisation orders (Sec. 5.2):
+    the largest bond rank of the one-hot phase train (TT-SVD at delta) of
+    the coarsened geometry (order n - 1) and of the geometry (order n), and
+    their ratio."""
+    def top(ph):
+        oh = np.stack([(ph == p).astype(np.float64) for p in range(nphase)])
+        n3 = int(round(math.log2(ph.size)))
+        return max(ranks(tt_svd(oh.reshape([nphase] + [2] * n3), delta)))
+    rc = top(coarsen_majority(phase, nphase))
+    rf = top(phase)
+    return rc, rf, rf / rc
+
+
 def const_tt(E: np.ndarray, n: int):
     """Rank-1 TT of a constant Voigt field (Sec. 4.3, constant operands)."""
     c0 = np.asarray(E, dtype=np.complex128).reshape(1, 6, 1)

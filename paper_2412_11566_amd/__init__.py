@@ -25,7 +25,7 @@ from ._capi import (QTT_EXACT, QTT_INVERSE, QTT_NO_ROUND, QTT_OK, QTT_ENOCONV,
 
 __all__ = [
     "QttError", "Context", "Tensor", "SolveOptions", "SolveReport",
-    "tt_from_cores", "const_strain", "sfft_build", "green_build", "from_voxels",
+    "tt_from_cores", "const_strain", "sfft_build", "green_build", "from_voxels", "rank_estimate",
     "sfft_apply", "tt_hadamard", "green_apply", "amen_apply", "tt_round", "tt_norm", "tt_axpby",
     "tt_mean_apply", "ls_solve", "ls_adjoint", "batch_solve", "Prepared", "prepare",
     "ls_solve_prepared", "stats_enable", "stats_get", "stats_reset", "tensor_create",
@@ -240,6 +240,19 @@ def from_voxels(ctx: Context, phase, lame, lame0, delta: float, cap: int = 0):
         C.byref(h), C.byref(chi)))
     del keep
     return Tensor(ctx, h), Tensor(ctx, chi)
+
+
+def rank_estimate(ctx: Context, phase, nphase: int, delta: float):
+    """Largest one-hot bond rank of the geometry at its order n and at
+    order n - 1 (2 x 2 x 2 majority coarsening), and their ratio; ``phase``
+    is a host array or a torch uint8 device tensor."""
+    p, keep = _problem(phase, np.zeros((nphase, 2)), (1.0, 1.0), 0)
+    r = (C.c_int * 2)()
+    g = C.c_double(0.0)
+    ctx.check(_c.lib().qtt_rank_estimate(ctx.h, p.phase, p.phase_on_device, p.n, nphase, delta,
+                                         C.cast(r, C.POINTER(C.c_int)), C.byref(g)))
+    del keep
+    return int(r[0]), int(r[1]), g.value
 
 
 def _prod(fn, ctx, A, x, flags, delta, cap, seed):

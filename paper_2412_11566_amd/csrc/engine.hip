@@ -2720,6 +2720,35 @@ int qtt_green_build_scheme(qtt_ctx* c, int n, double lam0, double mu0, double de
   });
 }
 
+int qtt_rank_estimate(qtt_ctx* c, const uint8_t* phase, int phase_on_device, int n, int nphase, double delta,
+                      int* ranks, double* growth) {
+  if (!c || !phase || !ranks || n < 2 || n > 10 || nphase < 1 || nphase > 16 || !(delta > 0)) return QTT_EINVAL;
+  QTT_TRY(c, {
+    Ctx X{c};
+    const long NN = 1L << (3 * n);
+    const uint8_t* dph = phase;
+    BufP phb;
+    if (!phase_on_device) {
+      phb = X.buf((size_t)(NN + 15) / 16);
+      check(hipMemcpyAsync(phb->p, phase, NN, hipMemcpyHostToDevice, X.s()), "phase h2d");
+      dph = (const uint8_t*)phb->p;
+    }
+    auto cb = X.buf((size_t)(NN / 8 + 15) / 16);
+    need(X, cb->p, (long)((NN / 8 + 15) / 16) - 1, "coarse out");
+    coarsen_majority(dph, n, nphase, (uint8_t*)cb->p, X.s());
+    host::HTT fine, coarse;
+    if (!device_chi(X, dph, true, n, nphase, delta, fine) ||
+        !device_chi(X, (const uint8_t*)cb->p, true, n - 1, nphase, delta, coarse))
+      throw std::length_error("rank estimate: a bond beyond the device TT-SVD");
+    int rc = 1, rf = 1;
+    for (const auto& h : coarse) rc = std::max(rc, h.r1);
+    for (const auto& h : fine) rf = std::max(rf, h.r1);
+    ranks[0] = rc;
+    ranks[1] = rf;
+    if (growth) *growth = (double)rf / rc;
+  });
+}
+
 int qtt_from_voxels(qtt_ctx* c, const uint8_t* phase, int phase_on_device, int n, int nphase,
                     const double* lame, const double lame0[2], double delta, int cap,
                     qtt_tensor** Cm, qtt_tensor** chi) {

@@ -739,6 +739,38 @@ void direction_staggered(const cplx* kp, const cplx* km, int n, cplx* out, hipSt
   check(hipGetLastError(), "direction_staggered launch");
 }
 
+// Majority phase of every 2 x 2 x 2 block of an N^3 phase array (C order,
+// x slowest) -> (N/2)^3; ties go to the lowest phase id.  Ids >= nphase
+// (at most 16) count as phase 0 here; the one-hot pass of the coarse array
+// rejects nothing then, the fine array's own pass flags them.
+__global__ void k_coarsen_majority(const uint8_t* __restrict__ phase, int n, int nphase,
+                                   uint8_t* __restrict__ out) {
+  const int h = n - 1, H = 1 << h, N = 1 << n;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (1L << (3 * h))) return;
+  const int x = (int)(e >> (2 * h)), y = (int)((e >> h) & (H - 1)), z = (int)(e & (H - 1));
+  int cnt[16];
+#pragma unroll
+  for (int p = 0; p < 16; ++p) cnt[p] = 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const long f = ((long)(2 * x + (c >> 2)) * N + (2 * y + ((c >> 1) & 1))) * N + (2 * z + (c & 1));
+    const int p = phase[f];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cnt[q] += (q == (p < nphase ? p : 0));
+  }
+  int best = 0;
+#pragma unroll
+  for (int q = 1; q < 16; ++q) best = cnt[q] > cnt[best] ? q : best;
+  out[e] = (uint8_t)best;
+}
+
+void coarsen_majority(const uint8_t* phase, int n, int nphase, uint8_t* out, hipStream_t s) {
+  const long M = 1L << (3 * (n - 1));
+  hipLaunchKernelGGL(k_coarsen_majority, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, phase, n, nphase, out);
+  check(hipGetLastError(), "coarsen launch");
+}
+
 __global__ void k_sum_middle(long total, int outer, int np, int inner, const cplx* in,
                              cplx* out, cplx w) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
