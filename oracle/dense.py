@@ -177,9 +177,10 @@ def gamma_voigt_symbol(B: np.ndarray, C0: np.ndarray) -> np.ndarray:
     G = B (B^H C0 B)^-1 B^H (App. A eq. orig_green_eshelby with the
     acoustic tensor B^H C0 B inverted numerically per frequency; 0 where
     B = 0).  It maps a plain-Voigt polarization to an engineering-Voigt
-    strain, like ``gamma_voigt``.  Returns (P, 6, 6) complex."""
+    strain, like ``gamma_voigt``.  Returns (P, V, V) complex for a Voigt
+    dimension V (6 in 3D, 3 for plane strain)."""
     B = np.asarray(B, dtype=np.complex128)
-    out = np.zeros((B.shape[0], 6, 6), dtype=np.complex128)
+    out = np.zeros((B.shape[0], B.shape[1], B.shape[1]), dtype=np.complex128)
     live = np.abs(B).reshape(B.shape[0], -1).max(axis=1) > 0
     Bl = B[live]
     K = np.conj(Bl).transpose(0, 2, 1) @ C0[None] @ Bl

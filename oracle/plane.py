@@ -1,0 +1,110 @@
+"""Dense-pixel FFT-based homogenization in two dimensions (oracle; test
+infrastructure): plane strain, Voigt dimension 3, the same Alg. 1 as
+``oracle.dense`` on N x N pixel grids.
+
+* Voigt order (11, 22, 12), engineering shear for strain, plain stress.
+  The isotropic plane-strain stiffness keeps lambda and mu:
+  C = [[lam + 2 mu, lam, 0], [lam, lam + 2 mu, 0], [0, 0, mu]].
+* Green operator: the direct scheme k = i q of App. A, Table 3, from its
+  discrete gradient (B (B^H C0 B)^-1 B^H with the strain symbol B), with the
+  Nyquist rule of the three-dimensional oracle.
+* The paper's 2D problems (Sec. 5, Figs. of the 2D geometries) use this
+  Voigt dimension; a z-invariant three-dimensional problem whose load keeps
+  eps_33 = gamma_13 = gamma_23 = 0 is the same plane-strain problem, which
+  the pins use.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.fft as sfft
+
+from .dense import frequencies, gamma_voigt_symbol
+
+PAIRS2 = [(0, 0), (1, 1), (0, 1)]
+
+
+def iso_voigt2(lam: float, mu: float) -> np.ndarray:
+    """Plane-strain isotropic Voigt stiffness (11, 22, 12)."""
+    return np.array([[lam + 2 * mu, lam, 0.0], [lam, lam + 2 * mu, 0.0], [0.0, 0.0, mu]])
+
+
+def strain_symbol2(k: np.ndarray) -> np.ndarray:
+    """B (P, 3, 2): eps_11 = k_1 u_1, eps_22 = k_2 u_2, gamma_12 = k_2 u_1 + k_1 u_2."""
+    k = np.asarray(k, dtype=np.complex128)
+    B = np.zeros(k.shape[:-1] + (3, 2), dtype=np.complex128)
+    B[..., 0, 0] = k[..., 0]
+    B[..., 1, 1] = k[..., 1]
+    B[..., 2, 0] = k[..., 1]
+    B[..., 2, 1] = k[..., 0]
+    return B
+
+
+def gamma_table2(N, lam0: float, mu0: float) -> np.ndarray:
+    """Nyquist-symmetrised plane-strain Green table (3, 3, Nx, Ny) in DFT
+    order (direct scheme): G_h(idx) = (G(xi(idx)) + conj G(xi(-idx))) / 2."""
+    shape = (N, N) if np.isscalar(N) else tuple(N)
+    C0 = iso_voigt2(lam0, mu0)
+    f = [frequencies(n) for n in shape]
+    neg = [fa[(-np.arange(n)) % n] for fa, n in zip(f, shape)]
+
+    def table(fx, fy):
+        X, Y = np.meshgrid(fx, fy, indexing="ij")
+        xi = np.stack([X, Y], axis=-1).reshape(-1, 2)
+        return gamma_voigt_symbol(strain_symbol2(1j * xi), C0).reshape(shape + (3, 3))
+
+    G = 0.5 * (table(*f) + np.conj(table(*neg)))
+    return G.transpose(2, 3, 0, 1).copy()
+
+
+def basic_scheme2(phase: np.ndarray, lame, lame0, E, tol: float, max_iter: int = 2000,
+                  G: np.ndarray | None = None, fixed_iters: int | None = None):
+    """Alg. 1 on an N x N pixel grid (plane strain); returns (eps (3, N, N),
+    iterations, residual history)."""
+    lam0, mu0 = lame0
+    if G is None:
+        G = gamma_table2(phase.shape, lam0, mu0)
+    dC = np.stack([iso_voigt2(l, m) for l, m in np.asarray(lame)]) - iso_voigt2(lam0, mu0)[None]
+    E = np.asarray(E, dtype=np.float64)
+    eps = np.broadcast_to(E[:, None, None], (3,) + phase.shape).astype(np.complex128)
+    normE = np.linalg.norm(E) * np.sqrt(phase.size)
+    hist = []
+    m = 0
+    while True:
+        tau = np.zeros_like(eps)
+        for p in range(dC.shape[0]):
+            msk = phase == p
+            tau[:, msk] = dC[p] @ eps[:, msk]
+        th = sfft.fft2(tau, axes=(1, 2))
+        eh = np.einsum("vwxy,wxy->vxy", G, th)
+        new = E[:, None, None] - sfft.ifft2(eh, axes=(1, 2))
+        res = np.linalg.norm(new - eps) / normE
+        hist.append(res)
+        eps = new
+        m += 1
+        if fixed_iters is not None:
+            if m >= fixed_iters:
+                break
+        elif res < tol or m >= max_iter:
+            break
+    return eps, m, hist
+
+
+def effective_stiffness2(phase: np.ndarray, lame, lame0, tol: float, max_iter: int = 2000,
+                         fixed_iters: int | None = None):
+    """Plane-strain C_eff (3 x 3, columns = unit load cases) from Alg. 1."""
+    G = gamma_table2(phase.shape, *lame0)
+    Cp = np.stack([iso_voigt2(l, m) for l, m in np.asarray(lame)])
+    C = np.zeros((3, 3))
+    its = []
+    for k in range(3):
+        E = np.zeros(3)
+        E[k] = 1.0
+        eps, m, _ = basic_scheme2(phase, lame, lame0, E, tol, max_iter, G=G, fixed_iters=fixed_iters)
+        s = np.zeros(3, dtype=np.complex128)
+        for p in range(Cp.shape[0]):
+            msk = phase == p
+            if msk.any():
+                s += Cp[p] @ eps[:, msk].sum(axis=1)
+        C[:, k] = (s / phase.size).real
+        its.append(m)
+    return C, its
