@@ -285,6 +285,43 @@ def family_rooflines(fam):
     return out
 
 
+def geometry_suite(q, ctx, M, orders2d=(6, 8, 10), orders3d=(5, 6), updates=3, cap=128):
+    """The paper's geometry suite (Sec. 5, App. F) in 2D (plane strain) and
+    3D: per geometry and order n, the setup time, the time per update, the
+    largest strain rank and the strain train's bytes (all load cases)
+    against the dense field's, at delta 1e-8 and the given cap, a fixed
+    number of updates per load case."""
+    import torch
+    lame = M.suite_lame()
+    l0 = M.reference_medium(lame)
+    out = []
+    plan = [(2, g, n) for g in ("square", "circle", "checkerboard", "voronoi") for n in orders2d]
+    plan += [(3, g, n) for g in ("box", "sphere", "checkerboard3", "voronoi3") for n in orders3d]
+    for dim, g, n in plan:
+        ph = M.geometry(g, 1 << n, dim, seed=1)
+        V = 3 if dim == 2 else 6
+        mask = (1 << V) - 1
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prep = q.prepare(ctx, ph, lame, l0, 1e-8, load_mask=mask)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        o = q.SolveOptions(delta=1e-8, tol=0.0, cap=cap, max_iter=updates, seed=7, streams=3)
+        C, rep, eps = q.ls_solve_prepared(ctx, prep, o, keep_eps=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r = eps.ranks
+        dims = [V] + [2] * (dim * n)
+        strain_bytes = 16 * V * sum(r[k] * dims[k] * r[k + 1] for k in range(len(dims)))
+        out.append({"dim": dim, "geometry": g, "n": n, "setup_s": t1 - t0,
+                    "ms_per_update": 1000.0 * (t2 - t1) / (updates * V), "max_strain_rank": rep.max_rank,
+                    "strain_train_bytes": strain_bytes, "dense_field_bytes": 16 * V * V * (1 << (dim * n))})
+        log(f"suite {dim}D {g} n={n}: setup {t1 - t0:.2f} s, {out[-1]['ms_per_update']:.1f} ms/update, "
+            f"rank {rep.max_rank}, strain {strain_bytes / 1e6:.2f} MB vs dense {out[-1]['dense_field_bytes'] / 1e6:.1f} MB")
+        del prep, eps
+    return {"delta": 1e-8, "cap": cap, "updates_per_load_case": updates, "runs": out}
+
+
 def timed_solve(q, ctx, prep, opts, stats_stride=0, keep_eps=False):
     import torch
     if stats_stride:
@@ -318,6 +355,7 @@ def main():
     ap.add_argument("--no-cap128", action="store_true", help="skip the cap-128 leg")
     ap.add_argument("--no-staggered", action="store_true",
                     help="skip the staggered-grid Green operator leg (cap 128)")
+    ap.add_argument("--no-suite", action="store_true", help="skip the geometry-suite leg")
     ap.add_argument("--amen-iters", type=int, default=20,
                     help="updates per load case of the AMEn Green-product leg (0: skip)")
     ap.add_argument("--batch", type=int, default=4,
@@ -516,6 +554,7 @@ def main():
             log(f"{name} Green products, cap 128, {args.amen_iters} updates per case: {ta:.1f} s, "
                 f"{sum(ra.iterations) / ta:.2f} updates/s, C_eff error {legs[name]['ceff_rel_error_vs_oracle']}")
         amen = {"cap": 128, "updates_per_load_case": args.amen_iters, **legs}
+    suite = None if args.no_suite else geometry_suite(q, ctx, M)
     tto = tto_apply_bandwidth(q, ctx, args.n)
     if "tto_contract" in rl:
         tto["in_solve_contractions"] = rl["tto_contract"]
@@ -553,6 +592,7 @@ def main():
         "cap128": cap128,
         "staggered": stag,
         "amen_green_products": amen,
+        "geometry_suite": suite,
         "setup_seconds": setup_s,
         "setup_breakdown": {"stiffness_from_voxels_s": stiff_s, "sfft_build_s": sfft_s,
                             "prepare_all_operators_s": setup_s},

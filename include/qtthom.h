@@ -126,6 +126,13 @@ typedef struct qtt_problem {
                                 kept beyond the call)                      */
     int scheme;              /* QTT_SCHEME_*: the Green operator's
                                 discretisation (App. A, Table 3)           */
+    int dim;                 /* 0 or 3: voxels N^3, Voigt 6; 2: plane
+                                strain on N^2 pixels (C order, x slowest),
+                                Voigt 3 (11, 22, 12), load cases bits 0..2,
+                                C_eff in rows and columns 0..2 of the 6 x 6
+                                output, n <= 12, direct scheme only (the
+                                paper's 2D problems, Sec. 5); ls_solve,
+                                qtt_prepare and ls_solve_prepared         */
 } qtt_problem;
 
 typedef struct qtt_solve_opts {

@@ -32,7 +32,7 @@ __all__ = [
     "sphere", "laminate", "fibres", "spheres", "random_spheres",
     "config_c0", "config_c1_laminate", "config_c1_sphere", "config_c2",
     "config_c3", "config_c3_structure", "config_c4", "homogeneous",
-    "synthetic_train",
+    "synthetic_train", "geometry", "SUITE_2D", "SUITE_3D", "SUITE_YOUNG_NU", "suite_lame",
 ]
 
 
@@ -276,3 +276,108 @@ def synthetic_train(n: int, rank: int = 64, seed: int = 1) -> list:
     ranks = [1] + [min(rank, int(np.prod(dims[:k])), int(np.prod(dims[k:]))) for k in range(1, L)] + [1]
     return [(rng.standard_normal((1, ranks[k], d, ranks[k + 1]))
              + 1j * rng.standard_normal((1, ranks[k], d, ranks[k + 1]))) for k, d in enumerate(dims)]
+
+
+# ---------------------------------------------------------------------------
+# The paper's geometry suite (Sec. 5 and App. F): the 2D geometries and
+# their two 3D generalisations (a non-varying z component; the same view
+# from every direction).  Phase 1 (grey) E = 29/3, phase 0 (white) E = 4/3,
+# both nu = 1/3.
+# ---------------------------------------------------------------------------
+SUITE_YOUNG_NU = [(4.0 / 3.0, 1.0 / 3.0), (29.0 / 3.0, 1.0 / 3.0)]
+
+
+def _grid(N: int, dim: int):
+    x = centres(N)
+    return np.meshgrid(*([x] * dim), indexing="ij")
+
+
+def _spots_centres(rng: np.random.Generator, count: int, radius: float, dim: int,
+                   max_tries: int = 10000) -> np.ndarray:
+    """Centres of `count` equal non-overlapping discs / balls (the whole
+    set redrawn on any overlap, App. F)."""
+    for _ in range(max_tries):
+        cs = rng.uniform(0.0, 1.0, size=(count, dim))
+        if all(_periodic_dist(cs[i], cs[j]) > 2 * radius
+               for i in range(count) for j in range(i + 1, count)):
+            return cs
+    raise RuntimeError("spots: no non-overlapping set found")
+
+
+def _voronoi(N: int, dim: int, seeds: int, fraction: float, rng: np.random.Generator) -> np.ndarray:
+    """Periodic Voronoi cells of `seeds` uniform points; cells are taken as
+    inclusions in a random order until their volume reaches `fraction`
+    (App. F: a fraction of the cells, Phi_vol = 0.9)."""
+    pts = rng.uniform(0.0, 1.0, size=(seeds, dim))
+    g = _grid(N, dim)
+    best = np.full(g[0].shape, np.inf)
+    cell = np.zeros(g[0].shape, dtype=np.int64)
+    for s, p in enumerate(pts):
+        d2 = sum(_periodic_delta(g[a], p[a]) ** 2 for a in range(dim))
+        closer = d2 < best
+        best[closer] = d2[closer]
+        cell[closer] = s
+    out = np.zeros(g[0].shape, dtype=np.uint8)
+    vol = np.bincount(cell.ravel(), minlength=seeds) / cell.size
+    acc = 0.0
+    for s in rng.permutation(seeds):
+        if acc >= fraction:
+            break
+        out[cell == s] = 1
+        acc += vol[s]
+    return out
+
+
+def geometry(name: str, N: int, dim: int = 2, seed: int = 0) -> np.ndarray:
+    """uint8 phase array (N,)*dim of a suite geometry.
+
+    2D: laminate, square (side 1/2), circle (radius 0.3), checkerboard
+    (4 x 4 tiles), spots (10 discs of radius 0.08), voronoi (32 cells,
+    Phi_vol 0.9).  3D: the z-extrusions pillar, circular_pillar, fibres,
+    reduced_checkerboard, laminate3; the same-from-every-direction box,
+    sphere, checkerboard3, voronoi3.
+    """
+    rng = np.random.default_rng(seed)
+    if dim == 2:
+        X, Y = _grid(N, 2)
+        if name == "laminate":
+            return (X >= 0.5).astype(np.uint8)
+        if name == "square":
+            return ((np.abs(X - 0.5) < 0.25) & (np.abs(Y - 0.5) < 0.25)).astype(np.uint8)
+        if name == "circle":
+            return ((X - 0.5) ** 2 + (Y - 0.5) ** 2 < 0.09).astype(np.uint8)
+        if name == "checkerboard":
+            return ((np.floor(4 * X) + np.floor(4 * Y)) % 2).astype(np.uint8)
+        if name == "spots":
+            cs = _spots_centres(rng, 10, 0.08, 2)
+            out = np.zeros((N, N), dtype=bool)
+            for c in cs:
+                out |= _periodic_delta(X, c[0]) ** 2 + _periodic_delta(Y, c[1]) ** 2 < 0.08 ** 2
+            return out.astype(np.uint8)
+        if name == "voronoi":
+            return _voronoi(N, 2, 32, 0.9, rng)
+        raise ValueError(f"unknown 2D geometry {name!r}")
+    extrude = {"laminate3": "laminate", "pillar": "square", "circular_pillar": "circle",
+               "fibres": "spots", "reduced_checkerboard": "checkerboard"}
+    if name in extrude:
+        g2 = geometry(extrude[name], N, 2, seed)
+        return np.broadcast_to(g2[:, :, None], (N, N, N)).copy()
+    X, Y, Z = _grid(N, 3)
+    if name == "box":
+        return ((np.abs(X - 0.5) < 0.25) & (np.abs(Y - 0.5) < 0.25) & (np.abs(Z - 0.5) < 0.25)).astype(np.uint8)
+    if name == "sphere":
+        return sphere(N, 0.3)
+    if name == "checkerboard3":
+        return ((np.floor(4 * X) + np.floor(4 * Y) + np.floor(4 * Z)) % 2).astype(np.uint8)
+    if name == "voronoi3":
+        return _voronoi(N, 3, 32, 0.9, rng)
+    raise ValueError(f"unknown 3D geometry {name!r}")
+
+
+SUITE_2D = ["laminate", "square", "circle", "checkerboard", "spots", "voronoi"]
+SUITE_3D = ["laminate3", "pillar", "circular_pillar", "box", "sphere", "fibres",
+            "reduced_checkerboard", "checkerboard3", "voronoi3"]
+
+
+def suite_lame() -> np.ndarray:
+    return np.array([lame_from_young(E, nu) for E, nu in SUITE_YOUNG_NU], dtype=np.float64)

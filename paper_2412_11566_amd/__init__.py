@@ -373,11 +373,12 @@ def _problem(phase, lame, lame0, load_mask, scheme="direct"):
         shape = phase.shape
         ptr = phase.ctypes.data_as(C.POINTER(C.c_uint8))
     n = int(round(np.log2(shape[0])))
-    if shape != (1 << n,) * 3:
-        raise ValueError("phase must be a cubic array with side 2**n")
+    dim = len(shape)
+    if dim not in (2, 3) or shape != (1 << n,) * dim:
+        raise ValueError("phase must be a cubic (or, for plane strain, square) array with side 2**n")
     lame = np.ascontiguousarray(lame, dtype=np.float64)
     p = _c.Problem(n, ptr, lame.shape[0], _dp(lame), (C.c_double * 2)(*lame0), load_mask,
-                   int(on_dev), _scheme(scheme))
+                   int(on_dev), _scheme(scheme), dim)
     return p, (phase, lame)
 
 
@@ -392,7 +393,9 @@ def _report(r: _c.Report, o: _c.SolveOpts | None = None) -> SolveReport:
 def ls_solve(ctx: Context, phase, lame, lame0, opts: SolveOptions, load_mask: int = 0x3F,
              keep_eps: bool = False, scheme="direct"):
     """Alg. 2 for the selected unit load cases with the Green operator of
-    ``scheme`` (``SCHEMES``); returns (C_eff, report, eps)."""
+    ``scheme`` (``SCHEMES``); returns (C_eff, report, eps).  A square
+    (N, N) ``phase`` is a plane-strain problem: C_eff is then 3 x 3 (Voigt
+    11, 22, 12) and load_mask bits 0..2 select its load cases."""
     p, keep = _problem(phase, lame, lame0, load_mask, scheme)
     o = opts.c()
     Ceff = np.zeros(36)
@@ -402,7 +405,8 @@ def ls_solve(ctx: Context, phase, lame, lame0, opts: SolveOptions, load_mask: in
                            C.byref(eps) if keep_eps else None)
     ctx.check(rc, allow=(QTT_ENOCONV,))
     del keep
-    return Ceff.reshape(6, 6), _report(rep, o), (Tensor(ctx, eps) if keep_eps else None)
+    C6 = Ceff.reshape(6, 6)
+    return (C6[:3, :3].copy() if p.dim == 2 else C6), _report(rep, o), (Tensor(ctx, eps) if keep_eps else None)
 
 
 def ls_adjoint(ctx: Context, phase, lame, lame0, opts: SolveOptions, eps: Tensor, gbar=None,
@@ -464,7 +468,9 @@ def prepare(ctx: Context, phase, lame, lame0, delta: float, load_mask: int = 0x3
     p, keep = _problem(phase, lame, lame0, load_mask, scheme)
     h = C.c_void_p()
     ctx.check(_c.lib().qtt_prepare(ctx.h, C.byref(p), delta, C.byref(h)))
-    return Prepared(ctx, h, keep)
+    pr = Prepared(ctx, h, keep)
+    pr.dim = p.dim
+    return pr
 
 
 def ls_solve_prepared(ctx: Context, prep: Prepared, opts: SolveOptions, keep_eps: bool = False):
@@ -475,7 +481,9 @@ def ls_solve_prepared(ctx: Context, prep: Prepared, opts: SolveOptions, keep_eps
     rc = _c.lib().ls_solve_prepared(ctx.h, prep.h, C.byref(o), _dp(Ceff), C.byref(rep),
                                     C.byref(eps) if keep_eps else None)
     ctx.check(rc, allow=(QTT_ENOCONV,))
-    return Ceff.reshape(6, 6), _report(rep, o), (Tensor(ctx, eps) if keep_eps else None)
+    C6 = Ceff.reshape(6, 6)
+    return (C6[:3, :3].copy() if getattr(prep, "dim", 3) == 2 else C6), _report(rep, o), \
+        (Tensor(ctx, eps) if keep_eps else None)
 
 
 def stats_enable(ctx: Context, on=True):

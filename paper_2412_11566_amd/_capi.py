@@ -49,7 +49,8 @@ ERR_NAMES = {QTT_EINVAL: "EINVAL", QTT_ENOMEM: "ENOMEM", QTT_ECAPACITY: "ECAPACI
 class Problem(C.Structure):
     _fields_ = [("n", C.c_int), ("phase", C.POINTER(C.c_uint8)), ("nphase", C.c_int),
                 ("lame", C.POINTER(C.c_double)), ("lame0", C.c_double * 2),
-                ("load_mask", C.c_int), ("phase_on_device", C.c_int), ("scheme", C.c_int)]
+                ("load_mask", C.c_int), ("phase_on_device", C.c_int), ("scheme", C.c_int),
+                ("dim", C.c_int)]
 
 
 class SolveOpts(C.Structure):

@@ -1132,15 +1132,15 @@ static TTP apply_full(const Ctx& X, const TT& A, const TT& x) {
 
 static TTP op_apply(const Ctx& X, const TT& A, const TT& x, int flags, const SketchOpts& o,
                     RoundStats* st);
-static TTP identity_op(const Ctx& X, int n, int d0 = 6);
+static TTP identity_op(const Ctx& X, int bits, int d0 = 6);
 
 // Rounding of an explicit train (e.g. a sum of two trains): with a rank cap
 // the randomized sketch (identity operator) keeps every factorisation at the
 // sketch size; without a cap (or in exact mode) the deterministic
 // QR + SVD rounding is used.
 static TTP round_any(const Ctx& X, const TTP& x, const SketchOpts& o, RoundStats* st) {
-  if (o.cap > 0 && !o.exact && (x->dout[0] == 6 || x->dout[0] == 3) && (x->L - 1) % 3 == 0) {
-    auto I = identity_op(X, (x->L - 1) / 3, x->dout[0]);
+  if (o.cap > 0 && !o.exact && x->dout[0] <= 6) {
+    auto I = identity_op(X, x->L - 1, x->dout[0]);
     return sketch_apply(X, *I, *x, o, st);
   }
   round_tt(X, *x, o.delta, o.cap, st);
@@ -1566,12 +1566,13 @@ static TTP amen_product(const Ctx& X, const TT& A, const TT& x, const SketchOpts
 // Volume average of A(x) : x -> host (B x 6) complex; A's core 0 is 6x6.
 static std::vector<std::complex<double>> mean_apply(const Ctx& X, const TT& A, const TT& x) {
   const int L = x.L, B = x.B;
-  if (A.dout[0] != 6 || A.kind != 1) throw std::invalid_argument("mean_apply: needs a Voigt operator");
+  const int V = A.dout[0];
+  if ((V != 6 && V != 3) || A.kind != 1) throw std::invalid_argument("mean_apply: needs a Voigt operator");
   auto one = X.buf(B);
   ck_fill(X, (cplx*)one->p, B, C1(), X.s());
-  // core 0: P (B, 1, 6, rho1, r1) -> Mc (B, 6, rho1, r1)
+  // core 0: P (B, 1, V, rho1, r1) -> Mc (B, V, rho1, r1)
   BufP Mc = left_step(X, A, x, 0, (cplx*)one->p, 1);
-  const int lt = 6;
+  const int lt = V;
   for (int k = 1; k < L; ++k) {
     // treat the Voigt output index as the sketch index (lt = 6)
     const int rho2 = A.r[k + 1], r2 = x.r[k + 1], d = A.dout[k];
@@ -1580,7 +1581,7 @@ static std::vector<std::complex<double>> mean_apply(const Ctx& X, const TT& A, c
     ck_sum_middle(X, B, lt, d, rho2 * r2, (cplx*)P->p, (cplx*)Mn->p, CR(1.0 / d), X.s());
     Mc = Mn;
   }
-  std::vector<std::complex<double>> out((size_t)B * 6);
+  std::vector<std::complex<double>> out((size_t)B * V);
   check(hipMemcpyAsync(out.data(), Mc->p, out.size() * sizeof(cplx), hipMemcpyDeviceToHost, X.s()), "mean d2h");
   X.sync();
   return out;
@@ -1711,15 +1712,18 @@ static host::HTT adjoint_host(const host::HTT& h) {
   return out;
 }
 
-static TTP sfft_op(const Ctx& X, int n, double delta) {
+// SFFT on `dim` axes (3, or 2 for plane problems) with the Voigt identity
+// (6 or 3 components) on the control core
+static TTP sfft_op(const Ctx& X, int n, double delta, int dim = 3) {
   host::HTT q = host::qn_tto(n, delta);
   host::HTT S;
   host::HCore id;
-  id.r0 = 1; id.dout = 6; id.din = 6; id.r1 = 1;
-  id.v.assign(36, 0.0);
-  for (int i = 0; i < 6; ++i) id.v[i * 6 + i] = 1.0;
+  const int V = dim == 2 ? 3 : 6;
+  id.r0 = 1; id.dout = V; id.din = V; id.r1 = 1;
+  id.v.assign((size_t)V * V, 0.0);
+  for (int i = 0; i < V; ++i) id.v[i * V + i] = 1.0;
   S.push_back(id);
-  for (int a = 0; a < 3; ++a)
+  for (int a = 0; a < dim; ++a)
     for (auto& c : q) S.push_back(c);
   auto t = upload_op(X, S);
   t->adj = upload_op(X, adjoint_host(S));
@@ -1731,10 +1735,17 @@ static bool device_direction_staggered(const Ctx& X, int n, double delta, host::
 
 // The Green factors from the direction train: its TT-SVD on the device, or
 // (direct scheme) on the host when a bond rank exceeds the device path
-static TTP green_op(const Ctx& X, int n, double lam0, double mu0, double delta, int scheme) {
+static bool device_direction2d(const Ctx& X, int n, double delta, host::HTT& out);
+
+static TTP green_op(const Ctx& X, int n, double lam0, double mu0, double delta, int scheme, int dim = 3) {
   host::HTT nt;
   host::GreenFactors gf;
-  if (scheme == QTT_SCHEME_STAGGERED) {
+  if (dim == 2) {
+    if (scheme != QTT_SCHEME_DIRECT) throw std::invalid_argument("plane problems use the direct scheme");
+    if (!device_direction2d(X, n, delta, nt))
+      throw std::length_error("plane Green operator: direction-train rank beyond the device TT-SVD");
+    gf = host::green_factors2d_from(nt, lam0, mu0);
+  } else if (scheme == QTT_SCHEME_STAGGERED) {
     if (!device_direction_staggered(X, n, delta, nt))
       throw std::length_error("staggered Green operator: direction-train rank beyond the device TT-SVD");
     gf = host::green_factors_staggered_from(nt, lam0, mu0);
@@ -1744,7 +1755,7 @@ static TTP green_op(const Ctx& X, int n, double lam0, double mu0, double delta, 
   }
   auto t = std::make_shared<TT>();
   t->scheme = scheme;
-  t->kind = 2; t->L = 3 * n + 1; t->B = 1; t->pool = X.c->pool;
+  t->kind = 2; t->L = dim * n + 1; t->B = 1; t->pool = X.c->pool;
   t->gU = upload_op(X, gf.U);
   t->gS = upload_op(X, gf.Sd);
   t->gP = upload_op(X, gf.P);
@@ -1756,26 +1767,26 @@ static TTP green_op(const Ctx& X, int n, double lam0, double mu0, double delta, 
   return t;
 }
 
-// SFFT of a grid size, built once per (n, delta) in a context
-static TTP sfft_cached(const Ctx& X, int n, double delta) {
-  const auto key = std::make_pair(n, delta);
+// SFFT of a grid size, built once per (n, dim, delta) in a context
+static TTP sfft_cached(const Ctx& X, int n, double delta, int dim = 3) {
+  const auto key = std::make_pair(4 * n + dim, delta);
   auto it = X.c->sfft_cache.find(key);
   if (it != X.c->sfft_cache.end()) return it->second;
-  auto t = sfft_op(X, n, delta);
+  auto t = sfft_op(X, n, delta, dim);
   X.c->sfft_cache[key] = t;
   return t;
 }
 
 // Green operator for one reference medium: the factors are built once per
 // (n, delta, scheme) and shared, the two medium scalars are set per call
-static TTP green_cached(const Ctx& X, int n, double lam0, double mu0, double delta, int scheme) {
-  const auto key = std::make_tuple(n, delta, scheme);
+static TTP green_cached(const Ctx& X, int n, double lam0, double mu0, double delta, int scheme, int dim = 3) {
+  const auto key = std::make_tuple(4 * n + dim, delta, scheme);
   auto it = X.c->green_cache.find(key);
   TTP base;
   if (it != X.c->green_cache.end()) {
     base = it->second;
   } else {
-    base = green_op(X, n, lam0, mu0, delta, scheme);
+    base = green_op(X, n, lam0, mu0, delta, scheme, dim);
     X.c->green_cache[key] = base;
   }
   auto t = std::make_shared<TT>(*base);
@@ -1866,8 +1877,10 @@ static TTP upload_op_batch(const Ctx& X, const std::vector<host::HTT>& hs) {
   return t;
 }
 
-static TTP identity_op(const Ctx& X, int n, int d0) {
-  const auto key = std::make_pair(n, d0);
+// identity operator on a train of `bits` binary cores after a control core
+// of d0 values
+static TTP identity_op(const Ctx& X, int bits, int d0) {
+  const auto key = std::make_pair(bits, d0);
   auto it = X.c->ident.find(key);
   if (it != X.c->ident.end()) return it->second;
   host::HTT h;
@@ -1876,7 +1889,7 @@ static TTP identity_op(const Ctx& X, int n, int d0) {
   id.v.assign((size_t)d0 * d0, 0.0);
   for (int i = 0; i < d0; ++i) id.v[i * d0 + i] = 1.0;
   h.push_back(id);
-  for (int k = 0; k < 3 * n; ++k) {
+  for (int k = 0; k < bits; ++k) {
     host::HCore c;
     c.r0 = 1; c.dout = 2; c.din = 0; c.r1 = 1;
     c.v.assign(2, 1.0);
@@ -1887,13 +1900,14 @@ static TTP identity_op(const Ctx& X, int n, int d0) {
   return t;
 }
 
-static TTP const_strain(const Ctx& X, int n, int B, const double* E) {
-  const int L = 3 * n + 1;
+// constant strain train: control core E (B x V), then `bits` cores of ones
+static TTP const_strain(const Ctx& X, int n, int B, const double* E, int V = 6, int dim = 3) {
+  const int L = dim * n + 1;
   std::vector<int> dims(L, 2), rk(L + 1, 1);
-  dims[0] = 6;
+  dims[0] = V;
   auto t = new_tt(X, L, B, dims, rk);
-  std::vector<std::complex<double>> e((size_t)B * 6);
-  for (int i = 0; i < B * 6; ++i) e[i] = E[i];
+  std::vector<std::complex<double>> e((size_t)B * V);
+  for (int i = 0; i < B * V; ++i) e[i] = E[i];
   check(hipMemcpyAsync(t->core[0], e.data(), e.size() * sizeof(cplx), hipMemcpyHostToDevice, X.s()), "E h2d");
   for (int k = 1; k < L; ++k) ck_fill(X, t->core[k], (size_t)B * 2, C1(), X.s());
   X.sync();
@@ -1985,12 +1999,13 @@ static BufP tsqr_r(const Ctx& X, BufP M, long m, int c) {
 
 // TT-SVD of the one-hot tensor chi[p, x] = (phase(x) == p) (Sec. 4.3
 // binary discretisation) on the device; ||chi|| = sqrt(2^(3n)).
-static bool device_ttsvd(const Ctx& X, BufP T, int n, int P, double thr, host::HTT& out);
+static bool device_ttsvd(const Ctx& X, BufP T, int bits, int P, double thr, host::HTT& out);
 
-static bool device_chi(const Ctx& X, const uint8_t* phase, bool on_device, int n, int P, double delta,
+// one-hot phase train of a voxel (or pixel) array of 2^bits entries
+static bool device_chi(const Ctx& X, const uint8_t* phase, bool on_device, int bits, int P, double delta,
                        host::HTT& out) {
-  const long NN = 1L << (3 * n);
-  const int L = 3 * n + 1;
+  const long NN = 1L << bits;
+  const int L = bits + 1;
   const uint8_t* dph = phase;
   BufP phb;
   if (!on_device) {
@@ -2007,7 +2022,7 @@ static bool device_chi(const Ctx& X, const uint8_t* phase, bool on_device, int n
   check(hipMemcpyAsync(&bad, flag->p, sizeof(int), hipMemcpyDeviceToHost, X.s()), "flag d2h");
   X.sync();
   if (bad) throw std::invalid_argument("phase id out of range");
-  return device_ttsvd(X, T, n, P, delta / std::sqrt((double)(L - 1)) * std::sqrt((double)NN), out);
+  return device_ttsvd(X, T, bits, P, delta / std::sqrt((double)(L - 1)) * std::sqrt((double)NN), out);
 }
 
 // TT-SVD of the unit momentum directions n^sigma_a (App. A, the Green
@@ -2026,7 +2041,25 @@ static bool device_direction(const Ctx& X, int n, double delta, host::HTT& out) 
   need(X, T->p, 6 * NN - 1, "direction out");
   direction((const double*)fd->p, (const double*)fd->p + N, n, (cplx*)T->p, X.s());
   X.sync();  // the host frequency arrays are released on return
-  return device_ttsvd(X, T, n, 6, delta / std::sqrt((double)(L - 1)) * std::sqrt(2.0 * (double)(NN - 1)),
+  return device_ttsvd(X, T, 3 * n, 6, delta / std::sqrt((double)(L - 1)) * std::sqrt(2.0 * (double)(NN - 1)),
+                      out);
+}
+
+// The plane version: 4 x 2^(2n) directions (sigma, a), a in {x, y}
+static bool device_direction2d(const Ctx& X, int n, double delta, host::HTT& out) {
+  const long NN = 1L << (2 * n);
+  const int L = 2 * n + 1, N = 1 << n;
+  std::vector<double> f, f2;
+  host::momentum_freqs(n, f, f2);
+  auto fd = X.bufd(2 * (size_t)N);
+  check(hipMemcpyAsync(fd->p, f.data(), N * sizeof(double), hipMemcpyHostToDevice, X.s()), "freq h2d");
+  check(hipMemcpyAsync((double*)fd->p + N, f2.data(), N * sizeof(double), hipMemcpyHostToDevice, X.s()),
+        "freq h2d");
+  auto T = X.buf((size_t)4 * NN);
+  need(X, T->p, 4 * NN - 1, "direction out");
+  direction2d((const double*)fd->p, (const double*)fd->p + N, n, (cplx*)T->p, X.s());
+  X.sync();
+  return device_ttsvd(X, T, 2 * n, 4, delta / std::sqrt((double)(L - 1)) * std::sqrt(2.0 * (double)(NN - 1)),
                       out);
 }
 
@@ -2046,7 +2079,7 @@ static bool device_direction_staggered(const Ctx& X, int n, double delta, host::
   need(X, T->p, 6 * NN - 1, "direction out");
   direction_staggered((const cplx*)sd->p, (const cplx*)sd->p + N, n, (cplx*)T->p, X.s());
   X.sync();  // the host symbol arrays are released on return
-  return device_ttsvd(X, T, n, 6, delta / std::sqrt((double)(L - 1)) * std::sqrt(2.0 * (double)(NN - 1)),
+  return device_ttsvd(X, T, 3 * n, 6, delta / std::sqrt((double)(L - 1)) * std::sqrt(2.0 * (double)(NN - 1)),
                       out);
 }
 
@@ -2059,9 +2092,9 @@ static bool device_direction_staggered(const Ctx& X, int n, double delta, host::
 // thr = delta / sqrt(L - 1) ||T||), core k = V_r^H and M <- M V_r continues
 // with the next bit.  Returns the cores on the host (r_{k-1}, d_k, r_k);
 // false when a bond would need more than 160 (the Jacobi's 320 columns).
-static bool device_ttsvd(const Ctx& X, BufP T, int n, int P, double thr, host::HTT& out) {
-  const long NN = 1L << (3 * n);
-  const int L = 3 * n + 1;
+static bool device_ttsvd(const Ctx& X, BufP T, int bits, int P, double thr, host::HTT& out) {
+  const long NN = 1L << bits;
+  const int L = bits + 1;
   host::HTT cores(L);
   BufP M = T;
   long rows = (long)P * NN / 2;
@@ -2118,10 +2151,11 @@ static bool device_ttsvd(const Ctx& X, BufP T, int n, int P, double thr, host::H
 // device TT-SVD, or the host one when a bond rank exceeds the device path.
 static host::HTT stiffness_op(const Ctx& X, const uint8_t* phase, bool on_device, int n, int P,
                               const double* lame, const double* lame0, double delta, int cap,
-                              host::HTT* chi) {
+                              host::HTT* chi, int dim = 3) {
   host::HTT t;
-  if (device_chi(X, phase, on_device, n, P, delta, t))
-    return host::stiffness_from_chi(std::move(t), P, lame, lame0, cap, chi, nullptr);
+  if (device_chi(X, phase, on_device, dim * n, P, delta, t))
+    return host::stiffness_from_chi(std::move(t), P, lame, lame0, cap, chi, nullptr, dim == 2 ? 3 : 6);
+  if (dim == 2) throw std::length_error("plane stiffness: a bond beyond the device TT-SVD");
   std::vector<uint8_t> tmp;
   const uint8_t* ph = phase;
   if (on_device) {
@@ -2136,20 +2170,20 @@ static host::HTT stiffness_op(const Ctx& X, const uint8_t* phase, bool on_device
 // phase_on_device is set; tmp holds the copy).
 static const uint8_t* host_phase(const qtt_problem* P, std::vector<uint8_t>& tmp) {
   if (!P->phase_on_device) return P->phase;
-  tmp.resize((size_t)1 << (3 * P->n));
+  tmp.resize((size_t)1 << ((P->dim == 2 ? 2 : 3) * P->n));
   check(hipMemcpy(tmp.data(), P->phase, tmp.size(), hipMemcpyDeviceToHost), "phase d2h");
   return tmp.data();
 }
 
 static Ops build_ops(const Ctx& X, const qtt_problem* P, double delta) {
   Ops o;
-  const int n = P->n;
-  o.S = sfft_cached(X, n, delta);
-  o.G = green_cached(X, n, P->lame0[0], P->lame0[1], delta, P->scheme);
+  const int n = P->n, dim = P->dim == 2 ? 2 : 3, V = dim == 2 ? 3 : 6;
+  o.S = sfft_cached(X, n, delta, dim);
+  o.G = green_cached(X, n, P->lame0[0], P->lame0[1], delta, P->scheme, dim);
   host::HTT cd = stiffness_op(X, P->phase, P->phase_on_device != 0, n, P->nphase, P->lame, P->lame0,
-                              delta, 0, &o.chi);
+                              delta, 0, &o.chi, dim);
   o.Cd = upload_op(X, cd);
-  o.I = identity_op(X, n);
+  o.I = identity_op(X, dim * n, V);
   o.lam0 = P->lame0[0];
   o.mu0 = P->lame0[1];
   return o;
@@ -2157,7 +2191,11 @@ static Ops build_ops(const Ctx& X, const qtt_problem* P, double delta) {
 
 static void check_problem(const qtt_problem* P, const qtt_solve_opts* O) {
   if (!P || !O) throw std::invalid_argument("null problem or options");
-  if (P->n < 1 || P->n > 10) throw std::invalid_argument("n out of range (1..10)");
+  if (P->dim != 0 && P->dim != 2 && P->dim != 3) throw std::invalid_argument("dim must be 0, 2 or 3");
+  if (P->n < 1 || P->n > (P->dim == 2 ? 12 : 10))
+    throw std::invalid_argument("n out of range (1..10, plane problems 1..12)");
+  if (P->dim == 2 && P->scheme != QTT_SCHEME_DIRECT)
+    throw std::invalid_argument("plane problems use the direct scheme");
   if (P->nphase < 1 || P->nphase > 16) throw std::invalid_argument("nphase out of range");
   if (!P->phase || !P->lame) throw std::invalid_argument("null phase or lame");
   if (P->scheme != QTT_SCHEME_DIRECT && P->scheme != QTT_SCHEME_STAGGERED)
@@ -2239,12 +2277,13 @@ static SolveOut ls_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, cons
                         const std::vector<int>& ks, double* hist = nullptr, int hlen = 0) {
   SolveOut out;
   const int n = P->n, B = (int)ks.size();
+  const int dim = P->dim == 2 ? 2 : 3, V = dim == 2 ? 3 : 6;
   out.ks = ks;
-  std::vector<double> E((size_t)B * 6, 0.0);
-  for (int b = 0; b < B; ++b) E[(size_t)b * 6 + ks[b]] = 1.0;
-  auto Et = const_strain(X, n, B, E.data());
+  std::vector<double> E((size_t)B * V, 0.0);
+  for (int b = 0; b < B; ++b) E[(size_t)b * V + ks[b]] = 1.0;
+  auto Et = const_strain(X, n, B, E.data(), V, dim);
   auto eps = Et;
-  const double normE = std::pow(2.0, 1.5 * n);
+  const double normE = std::pow(2.0, 0.5 * dim * n);
   out.iters.assign(B, 0);
   out.res.assign(B, INFINITY);
   std::vector<char> done(B, 0);
@@ -2315,22 +2354,24 @@ static SolveOut ls_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, cons
 
 static void ceff_from(const Ctx& X, const Ops& ops, const qtt_problem* P, const SolveOut& so,
                       double* Ceff) {
+  // plane problems (3 Voigt components) fill rows and columns 0..2
+  const int V = P->dim == 2 ? 3 : 6;
   auto md = mean_apply(X, *ops.Cd, *so.eps);
   auto me = mean_apply(X, *ops.I, *so.eps);
   double C0m[36];
-  host::iso_voigt(P->lame0[0], P->lame0[1], C0m);
+  host::iso_voigt_dim(V, P->lame0[0], P->lame0[1], C0m);
   for (size_t b = 0; b < so.ks.size(); ++b) {
     const int k = so.ks[b];
-    for (int i = 0; i < 6; ++i) {
-      std::complex<double> s = md[b * 6 + i];
-      for (int j = 0; j < 6; ++j) s += C0m[i * 6 + j] * me[b * 6 + j];
+    for (int i = 0; i < V; ++i) {
+      std::complex<double> s = md[b * V + i];
+      for (int j = 0; j < V; ++j) s += C0m[i * V + j] * me[b * V + j];
       Ceff[i * 6 + k] = s.real();
     }
   }
 }
 
 struct Prepared {
-  int n = 0, nphase = 0, load_mask = 0, scheme = 0;
+  int n = 0, nphase = 0, load_mask = 0, scheme = 0, dim = 0;
   std::vector<uint8_t> phase;
   std::vector<double> lame;
   double lame0[2] = {0, 0};
@@ -2343,6 +2384,7 @@ struct Prepared {
     P.lame0[0] = lame0[0]; P.lame0[1] = lame0[1]; P.load_mask = load_mask;
     P.phase_on_device = 0;
     P.scheme = scheme;
+    P.dim = dim;
     return P;
   }
 };
@@ -2737,8 +2779,8 @@ int qtt_rank_estimate(qtt_ctx* c, const uint8_t* phase, int phase_on_device, int
     need(X, cb->p, (long)((NN / 8 + 15) / 16) - 1, "coarse out");
     coarsen_majority(dph, n, nphase, (uint8_t*)cb->p, X.s());
     host::HTT fine, coarse;
-    if (!device_chi(X, dph, true, n, nphase, delta, fine) ||
-        !device_chi(X, (const uint8_t*)cb->p, true, n - 1, nphase, delta, coarse))
+    if (!device_chi(X, dph, true, 3 * n, nphase, delta, fine) ||
+        !device_chi(X, (const uint8_t*)cb->p, true, 3 * (n - 1), nphase, delta, coarse))
       throw std::length_error("rank estimate: a bond beyond the device TT-SVD");
     int rc = 1, rf = 1;
     for (const auto& h : coarse) rc = std::max(rc, h.r1);
@@ -2972,7 +3014,7 @@ static SolveOut solve_groups(qtt_ctx* c, const Prepared& pr, const qtt_problem* 
   });
   for (int g = 0; g < ng; ++g)
     for (int k : groups[g])
-      for (int i = 0; i < 6; ++i) Ceff[i * 6 + k] = cg[g][i * 6 + k];
+      for (int i = 0; i < 6; ++i) Ceff[i * 6 + k] = cg[g][i * 6 + k];  // rows beyond V stay 0
   SolveOut so;
   so.ks = ks;
   std::vector<TTP> parts;
@@ -2996,7 +3038,7 @@ static int solve_prepared(qtt_ctx* c, const Prepared& pr, const qtt_solve_opts* 
     check_problem(&P, O);
     Ctx X{c};
     std::vector<int> ks;
-    for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < (P.dim == 2 ? 3 : 6); ++k)
       if (P.load_mask & (1 << k)) ks.push_back(k);
     if (ks.empty()) throw std::invalid_argument("empty load mask");
     const double t1 = now_s();
@@ -3031,8 +3073,8 @@ static int solve_prepared(qtt_ctx* c, const Prepared& pr, const qtt_solve_opts* 
 
 static Prepared make_prepared(qtt_ctx* c, const qtt_problem* P, double delta) {
   Prepared pr;
-  pr.n = P->n; pr.nphase = P->nphase; pr.load_mask = P->load_mask; pr.scheme = P->scheme;
-  const size_t NN = (size_t)1 << (3 * P->n);
+  pr.n = P->n; pr.nphase = P->nphase; pr.load_mask = P->load_mask; pr.scheme = P->scheme; pr.dim = P->dim;
+  const size_t NN = (size_t)1 << ((P->dim == 2 ? 2 : 3) * P->n);
   if (P->phase_on_device) {
     pr.phase.resize(NN);
     check(hipMemcpy(pr.phase.data(), P->phase, NN, hipMemcpyDeviceToHost), "phase d2h");
@@ -3376,6 +3418,7 @@ static int adjoint_ops(qtt_ctx* c, const Ops& ops, const qtt_problem* P, const q
   int status = QTT_OK;
   auto body = [&]() {
     check_problem(P, O);
+    if (P->dim == 2) throw std::invalid_argument("the adjoint solve is three-dimensional");
     Ctx X{c};
     const double t1 = now_s();
     const int n = P->n, np = P->nphase;
@@ -3530,7 +3573,7 @@ static int batch_group(qtt_ctx* c, const std::vector<int>& ids, const qtt_proble
     }
     ops.G = green_batch(X, n, O->delta, l0, m0, 6, Ps[ids[0]].scheme);
     ops.Cd = upload_op_batch(X, cds);
-    ops.I = identity_op(X, n);
+    ops.I = identity_op(X, 3 * n);
     cds.clear();
     const double t1 = now_s();
     std::vector<int> ks((size_t)6 * S);
@@ -3586,7 +3629,7 @@ int qtt_batch_solve(qtt_ctx* c, int count, const qtt_problem* Ps, const qtt_solv
   std::map<std::pair<int, int>, std::vector<int>> groups;
   std::vector<int> single;
   for (int i = 0; i < count; ++i) {
-    if (Ps[i].load_mask == 0x3F && Ps[i].n >= 1 && Ps[i].n <= 10)
+    if (Ps[i].load_mask == 0x3F && Ps[i].n >= 1 && Ps[i].n <= 10 && Ps[i].dim != 2)
       groups[std::make_pair(Ps[i].n, Ps[i].scheme)].push_back(i);
     else
       single.push_back(i);

@@ -378,6 +378,16 @@ void iso_voigt(double lam, double mu, double C[36]) {
   for (int i = 3; i < 6; ++i) C[i * 6 + i] = mu;
 }
 
+void iso_voigt_dim(int voigt, double lam, double mu, double* C) {
+  if (voigt == 6) {
+    iso_voigt(lam, mu, C);
+    return;
+  }
+  // plane strain (11, 22, 12)
+  const double v[9] = {lam + 2 * mu, lam, 0.0, lam, lam + 2 * mu, 0.0, 0.0, 0.0, mu};
+  for (int i = 0; i < 9; ++i) C[i] = v[i];
+}
+
 namespace {
 
 int bitrev(int k, int n) {
@@ -440,7 +450,7 @@ int voigt_index(int i, int j) {
 
 // operator whose control core is coef[out][in][c] contracted with the
 // direction train's first core (c = (sigma, a)), spatial cores shared.
-HTT control_op(const HTT& nt, int dout, int din, const std::vector<double>& coef) {
+HTT control_op(const HTT& nt, int dout, int din, const std::vector<double>& coef, int nc = 6) {
   HTT op;
   HCore c0;
   const int r1 = nt[0].r1;
@@ -448,8 +458,8 @@ HTT control_op(const HTT& nt, int dout, int din, const std::vector<double>& coef
   c0.v.assign((size_t)dout * din * r1, zc(0));
   for (int o = 0; o < dout; ++o)
     for (int i = 0; i < din; ++i)
-      for (int c = 0; c < 6; ++c) {
-        const double w = coef[((size_t)o * din + i) * 6 + c];
+      for (int c = 0; c < nc; ++c) {
+        const double w = coef[((size_t)o * din + i) * nc + c];
         if (w == 0.0) continue;
         for (int a = 0; a < r1; ++a)
           c0.v[((size_t)o * din + i) * r1 + a] += w * nt[0].v[(size_t)c * r1 + a];
@@ -570,6 +580,51 @@ GreenFactors green_factors_staggered_from(const HTT& nt, double lam0, double mu0
   return G;
 }
 
+GreenFactors green_factors2d_from(const HTT& nt, double lam0, double mu0) {
+  GreenFactors G;
+  // control c = 2 sigma + a (the two Nyquist representatives, axes x, y);
+  // plane-strain Voigt (11, 22, 12)
+  const int V2[2][2] = {{0, 2}, {2, 1}};
+  // U: u^s_j = sum_k tau_{V(j,k)} n^s_k ; out (s, j) 4, in Voigt 3
+  {
+    std::vector<double> cf(4 * 3 * 4, 0.0);
+    for (int s = 0; s < 2; ++s)
+      for (int j = 0; j < 2; ++j)
+        for (int k = 0; k < 2; ++k) cf[((size_t)(s * 2 + j) * 3 + V2[j][k]) * 4 + s * 2 + k] += 1.0;
+    G.U = control_op(nt, 4, 3, cf, 4);
+  }
+  // Sd: s^s = sum_j u^s_j n^s_j ; out s (2), in (s, j) 4
+  {
+    std::vector<double> cf(2 * 4 * 4, 0.0);
+    for (int s = 0; s < 2; ++s)
+      for (int j = 0; j < 2; ++j) cf[((size_t)s * 4 + s * 2 + j) * 4 + s * 2 + j] = 1.0;
+    G.Sd = control_op(nt, 2, 4, cf, 4);
+  }
+  // P: p^s_j = n^s_j s^s ; out (s, j) 4, in s 2
+  {
+    std::vector<double> cf(4 * 2 * 4, 0.0);
+    for (int s = 0; s < 2; ++s)
+      for (int j = 0; j < 2; ++j) cf[((size_t)(s * 2 + j) * 2 + s) * 4 + s * 2 + j] = 1.0;
+    G.P = control_op(nt, 4, 2, cf, 4);
+  }
+  // E: eps_I = w_I 1/2 sum_s (n^s_i q^s_j + n^s_j q^s_i), (i, j) = pair(I)
+  {
+    const int VP[3][2] = {{0, 0}, {1, 1}, {0, 1}};
+    const double W[3] = {1, 1, 2};
+    std::vector<double> cf(3 * 4 * 4, 0.0);
+    for (int I = 0; I < 3; ++I) {
+      const int i = VP[I][0], j = VP[I][1];
+      for (int s = 0; s < 2; ++s) {
+        cf[((size_t)I * 4 + s * 2 + j) * 4 + s * 2 + i] += 0.5 * W[I];
+        cf[((size_t)I * 4 + s * 2 + i) * 4 + s * 2 + j] += 0.5 * W[I];
+      }
+    }
+    G.E = control_op(nt, 3, 4, cf, 4);
+  }
+  green_scalars(lam0, mu0, &G.inv_2mu0, &G.half_c);
+  return G;
+}
+
 void green_scalars_scheme(int scheme, double lam0, double mu0, double* a, double* c) {
   if (scheme == 0) {
     green_scalars(lam0, mu0, a, c);
@@ -596,26 +651,27 @@ HTT stiffness_tto(const uint8_t* phase, int n, int nphase, const double* lame,
   std::vector<int> dims(3 * n + 1, 2);
   dims[0] = nphase;
   HTT t = tt_svd_real(oh, dims, delta, 0);
-  return stiffness_from_chi(std::move(t), nphase, lame, lame0, cap, chi, max_rank);
+  return stiffness_from_chi(std::move(t), nphase, lame, lame0, cap, chi, max_rank, 6);
 }
 
 HTT stiffness_from_chi(HTT t, int nphase, const double* lame, const double* lame0, int cap, HTT* chi,
-                       int* max_rank) {
+                       int* max_rank, int voigt) {
   int mr = 1;
   for (auto& c : t) mr = std::max(mr, c.r1);
   if (max_rank) *max_rank = mr;
   if (cap > 0 && mr > cap) throw std::length_error("stiffness rank exceeds cap");
+  const int V = voigt, VV = V * V;
   double C0[36];
-  iso_voigt(lame0[0], lame0[1], C0);
+  iso_voigt_dim(V, lame0[0], lame0[1], C0);
   HTT op;
   HCore c0;
   const int r1 = t[0].r1;
-  c0.r0 = 1; c0.dout = 6; c0.din = 6; c0.r1 = r1;
-  c0.v.assign(36 * (size_t)r1, zc(0));
+  c0.r0 = 1; c0.dout = V; c0.din = V; c0.r1 = r1;
+  c0.v.assign(VV * (size_t)r1, zc(0));
   for (int p = 0; p < nphase; ++p) {
     double Cp[36];
-    iso_voigt(lame[2 * p], lame[2 * p + 1], Cp);
-    for (int I = 0; I < 36; ++I) {
+    iso_voigt_dim(V, lame[2 * p], lame[2 * p + 1], Cp);
+    for (int I = 0; I < VV; ++I) {
       const double d = Cp[I] - C0[I];
       if (d == 0.0) continue;
       for (int a = 0; a < r1; ++a) c0.v[(size_t)I * r1 + a] += d * t[0].v[(size_t)p * r1 + a];

@@ -81,6 +81,12 @@ void momentum_freqs(int n, std::vector<double>& f, std::vector<double>& f2);
 // One axis's symbols in momentum order (kp, km as (re, im) pairs).
 void staggered_symbols(int n, std::vector<double>& kp, std::vector<double>& km);
 GreenFactors green_factors_staggered_from(const HTT& nt, double lam0, double mu0);
+// Plane-strain direct Green operator (2D, Voigt 11, 22, 12) from the train
+// of the unit directions n^sigma_a, a in {x, y} (control 2 sigma + a, 4
+// values): the same four maps as the 3D factors, U: 3 -> 4, Sd: 4 -> 2,
+// P: 2 -> 4, E: 4 -> 3, with the same two scalars (the plane-strain
+// acoustic tensor is mu0 |xi|^2 I + (lam0 + mu0) xi xi^T on the plane).
+GreenFactors green_factors2d_from(const HTT& nt, double lam0, double mu0);
 // The Green step's two medium scalars for a scheme (0 direct, 1 staggered):
 // q = a u - c p.
 void green_scalars_scheme(int scheme, double lam0, double mu0, double* a, double* c);
@@ -94,10 +100,13 @@ HTT stiffness_tto(const uint8_t* phase, int n, int nphase, const double* lame,
 // The same operator from an already computed one-hot phase train (core 0
 // of dimension nphase, then the 3n binary cores); chi receives the train.
 HTT stiffness_from_chi(HTT t, int nphase, const double* lame, const double* lame0, int cap, HTT* chi,
-                       int* max_rank);
+                       int* max_rank, int voigt = 6);
 
 // Isotropic Voigt stiffness (order 11, 22, 33, 23, 13, 12).
 void iso_voigt(double lam, double mu, double C[36]);
+// The same for a Voigt dimension: 6, or 3 for plane strain (11, 22, 12:
+// [[lam + 2 mu, lam, 0], [lam, lam + 2 mu, 0], [0, 0, mu]]), row-major.
+void iso_voigt_dim(int voigt, double lam, double mu, double* C);
 
 }  // namespace host
 }  // namespace qtt

@@ -705,6 +705,28 @@ __global__ void k_direction(const double* __restrict__ f, const double* __restri
   out[5 * NN + e] = make_double2(f2[z] * inv, 0.0);
 }
 
+// The same on the 2^n x 2^n grid (plane problems): 4 x 2^(2n) entries,
+// control (sigma, a), a in {x, y}
+__global__ void k_direction2d(const double* __restrict__ f, const double* __restrict__ f2, int n, long NN,
+                              cplx* __restrict__ out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NN) return;
+  const int N = 1 << n;
+  const int x = (int)(e >> n), y = (int)(e & (N - 1));
+  const double r2 = f[x] * f[x] + f[y] * f[y];
+  const double inv = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
+  out[0 * NN + e] = make_double2(f[x] * inv, 0.0);
+  out[1 * NN + e] = make_double2(f[y] * inv, 0.0);
+  out[2 * NN + e] = make_double2(f2[x] * inv, 0.0);
+  out[3 * NN + e] = make_double2(f2[y] * inv, 0.0);
+}
+
+void direction2d(const double* f, const double* f2, int n, cplx* out, hipStream_t s) {
+  const long NN = 1L << (2 * n);
+  hipLaunchKernelGGL(k_direction2d, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, s, f, f2, n, NN, out);
+  check(hipGetLastError(), "direction2d launch");
+}
+
 void direction(const double* f, const double* f2, int n, cplx* out, hipStream_t s) {
   const long NN = 1L << (3 * n);
   hipLaunchKernelGGL(k_direction, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, s, f, f2, n, NN, out);

@@ -297,6 +297,8 @@ void coarsen_majority(const uint8_t* phase, int n, int nphase, uint8_t* out, hip
 // (6 x 2^(3n) entries, control index (sigma, a) slowest, then x, y, z
 // bits); f, f2: device arrays of one axis's frequencies (2^n each).
 void direction(const double* f, const double* f2, int n, cplx* out, hipStream_t s);
+// The plane version (4 x 2^(2n) entries, control (sigma, a), a in {x, y}).
+void direction2d(const double* f, const double* f2, int n, cplx* out, hipStream_t s);
 // Staggered-grid directions (6 x 2^(3n) entries, control index (t, a): t = 0
 // the forward symbols kp_a / |kp|, t = 1 the backward ones km_a / |kp|);
 // kp, km: device arrays of one axis's symbols in momentum order (2^n each).

@@ -1,0 +1,76 @@
+"""Plane-strain problems (the paper's 2D geometries, Sec. 5; Voigt
+dimension 3) on the device: 2n-bit trains with a 3-valued control core,
+the plane SFFT, the plane Green factors from the device TT-SVD of the 2D
+direction field, and the plane-strain stiffness, against the plane-strain
+oracle (pinned to the 3D oracle on z-invariant grids)."""
+import numpy as np
+import pytest
+
+from oracle import plane as P2
+import microstructures as M
+from tests.helpers import rel
+
+pytestmark = pytest.mark.gpu
+
+q = pytest.importorskip("paper_2412_11566_amd")
+
+
+def _suite(name, n):
+    lame = M.suite_lame()
+    return M.geometry(name, 1 << n, 2, seed=1), lame, M.reference_medium(lame)
+
+
+@pytest.mark.parametrize("name", ["circle", "square", "voronoi"])
+def test_plane_exact_same_iterations(ctx, name):
+    """Untruncated, 8 updates: C_eff within 1e-10 of Alg. 1 (plane strain)
+    after the same number of updates."""
+    ph, lame, l0 = _suite(name, 5)
+    m = 8
+    opts = q.SolveOptions(delta=1e-14, tol=0.0, cap=0, max_iter=m, exact=True)
+    C, rep, _ = q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7)
+    Cref, _ = P2.effective_stiffness2(ph, lame, l0, tol=0.0, fixed_iters=m)
+    assert C.shape == (3, 3)
+    assert rel(C, Cref) < 1e-10
+    assert rep.iterations[:3] == [m] * 3
+
+
+@pytest.mark.parametrize("name", ["laminate", "square", "circle", "checkerboard", "spots", "voronoi"])
+def test_plane_suite_delta_1e8(ctx, name):
+    """The 2D suite at 64^2, delta 1e-8, cap 128 (not binding: the largest
+    structural rank of a 12-bit train is 64): C_eff within 1e-5 of the
+    converged plane-strain oracle, symmetric."""
+    ph, lame, l0 = _suite(name, 6)
+    opts = q.SolveOptions(delta=1e-8, tol=1e-8, cap=128, max_iter=400)
+    C, rep, _ = q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7)
+    Cref, _ = P2.effective_stiffness2(ph, lame, l0, tol=1e-12, max_iter=5000)
+    assert rep.status == 0
+    assert rel(C, Cref) < 1e-5
+    assert np.abs(C - C.T).max() < 1e-5 * np.abs(C).max()
+
+
+def test_plane_equals_z_invariant_3d(ctx):
+    """A plane problem and the z-extruded 3D problem give the same in-plane
+    C_eff on the device (the 3D solve on 16^3, the plane one on 16^2)."""
+    ph, lame, l0 = _suite("spots", 4)
+    opts = q.SolveOptions(delta=1e-14, tol=1e-12, cap=0, max_iter=400, exact=True)
+    C2, _, _ = q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7)
+    ph3 = np.broadcast_to(ph[:, :, None], ph.shape + (ph.shape[0],)).copy()
+    C3, _, _ = q.ls_solve(ctx, ph3, lame, l0, opts, load_mask=0x23)
+    IN = [0, 1, 5]
+    assert rel(C2, C3[np.ix_(IN, IN)]) < 1e-10
+
+
+def test_plane_prepared_and_rejects(ctx):
+    ph, lame, l0 = _suite("circle", 5)
+    opts = q.SolveOptions(delta=1e-8, tol=1e-6, cap=64, max_iter=200)
+    prep = q.prepare(ctx, ph, lame, l0, opts.delta, load_mask=0x7)
+    C, rep, _ = q.ls_solve_prepared(ctx, prep, opts)
+    C1, _, _ = q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7)
+    assert C.shape == (3, 3) and rel(C, C1) < 1e-6
+    with pytest.raises(q.QttError) as e:
+        q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7, scheme="staggered")
+    assert e.value.code == q._c.QTT_EINVAL
+    _, _, eps = q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7, keep_eps=True)
+    with pytest.raises(q.QttError) as e:
+        q.ls_adjoint(ctx, ph, lame, l0, opts, eps)
+    assert e.value.code == q._c.QTT_EINVAL
