@@ -1742,8 +1742,28 @@ static TTP green_op(const Ctx& X, int n, double lam0, double mu0, double delta, 
   host::GreenFactors gf;
   if (dim == 2) {
     if (scheme != QTT_SCHEME_DIRECT) throw std::invalid_argument("plane problems use the direct scheme");
-    if (!device_direction2d(X, n, delta, nt))
-      throw std::length_error("plane Green operator: direction-train rank beyond the device TT-SVD");
+    if (!device_direction2d(X, n, delta, nt)) {
+      // host TT-SVD of the 4 x 2^(2n) direction field (bonds beyond the
+      // device path)
+      const int N = 1 << n;
+      const size_t NN = (size_t)N * N;
+      std::vector<double> f, f2;
+      host::momentum_freqs(n, f, f2);
+      std::vector<double> T(4 * NN);
+      for (int x = 0; x < N; ++x)
+        for (int y = 0; y < N; ++y) {
+          const size_t e = (size_t)x * N + y;
+          const double r2 = f[x] * f[x] + f[y] * f[y];
+          const double inv = r2 > 0 ? 1.0 / std::sqrt(r2) : 0.0;
+          T[0 * NN + e] = f[x] * inv;
+          T[1 * NN + e] = f[y] * inv;
+          T[2 * NN + e] = f2[x] * inv;
+          T[3 * NN + e] = f2[y] * inv;
+        }
+      std::vector<int> dims(2 * n + 1, 2);
+      dims[0] = 4;
+      nt = host::tt_svd_real(T, dims, delta, 0);
+    }
     gf = host::green_factors2d_from(nt, lam0, mu0);
   } else if (scheme == QTT_SCHEME_STAGGERED) {
     if (!device_direction_staggered(X, n, delta, nt))
@@ -2155,13 +2175,25 @@ static host::HTT stiffness_op(const Ctx& X, const uint8_t* phase, bool on_device
   host::HTT t;
   if (device_chi(X, phase, on_device, dim * n, P, delta, t))
     return host::stiffness_from_chi(std::move(t), P, lame, lame0, cap, chi, nullptr, dim == 2 ? 3 : 6);
-  if (dim == 2) throw std::length_error("plane stiffness: a bond beyond the device TT-SVD");
   std::vector<uint8_t> tmp;
   const uint8_t* ph = phase;
   if (on_device) {
-    tmp.resize((size_t)1 << (3 * n));
+    tmp.resize((size_t)1 << (dim * n));
     check(hipMemcpy(tmp.data(), phase, tmp.size(), hipMemcpyDeviceToHost), "phase d2h");
     ph = tmp.data();
+  }
+  if (dim == 2) {
+    // host TT-SVD of the one-hot pixel train (bonds beyond the device path)
+    const size_t NN = (size_t)1 << (2 * n);
+    std::vector<double> oh((size_t)P * NN, 0.0);
+    for (size_t e = 0; e < NN; ++e) {
+      if (ph[e] >= P) throw std::invalid_argument("phase id out of range");
+      oh[(size_t)ph[e] * NN + e] = 1.0;
+    }
+    std::vector<int> dims(2 * n + 1, 2);
+    dims[0] = P;
+    host::HTT t2 = host::tt_svd_real(oh, dims, delta, 0);
+    return host::stiffness_from_chi(std::move(t2), P, lame, lame0, cap, chi, nullptr, 3);
   }
   return host::stiffness_tto(ph, n, P, lame, lame0, delta, cap, chi, nullptr);
 }
