@@ -190,11 +190,23 @@ def c3_subset(q, ctx, M, max_iter=30):
         Cp = [q.ls_solve(ctx, p.phase, p.lame, p.lame0, o)[0] for p in ps]
         torch.cuda.synchronize()
         tp = time.perf_counter() - t
+        # batches split by the geometry-rank bucket, and the two-order
+        # applicability estimate of every structure (Sec. 5.2)
+        ok = q.SolveOptions(delta=o.delta, tol=o.tol, cap=cap, max_iter=max_iter, oversample=16, seed=7,
+                            precision=q.QTT_PREC_FP32, rank_buckets=True)
+        t = time.perf_counter()
+        Ck, _ = q.batch_solve(ctx, probs, ok)
+        torch.cuda.synchronize()
+        tk = time.perf_counter() - t
+        est = [q.rank_estimate(ctx, p.phase, 2, o.delta) for p in ps]
         ref = [np.array(g["ceff"]).reshape(6, 6) for g in gs]
         err = lambda A: [float(np.abs(a - r).max() / np.abs(r).max()) for a, r in zip(A, ref)]
-        log(f"c3 subset {grid}^3 x {len(ps)}, cap {cap}: batched {tb:.2f} s, plain {tp:.2f} s")
+        log(f"c3 subset {grid}^3 x {len(ps)}, cap {cap}: batched {tb:.2f} s, plain {tp:.2f} s, "
+            f"rank-bucketed {tk:.2f} s; geometry ranks (n-1, n) {[e[:2] for e in est]}")
         out.append({"grid": f"{grid}^3", "structures": [g["structure"] for g in gs], "cap": cap,
                     "max_iter": max_iter, "precision": "fp32 contractions", "batched_s": tb, "plain_s": tp,
+                    "batched_rank_buckets_s": tk, "ceff_err_rank_buckets": err(Ck),
+                    "rank_estimate": [{"rank_coarse": e[0], "rank": e[1], "growth": e[2]} for e in est],
                     "speedup": tp / tb, "ceff_err_batched": err(Cb), "ceff_err_plain": err(Cp),
                     "converged_batched": int(sum(1 for r in rb if r.status == 0)),
                     "oracle_rank_error_at_cap": [g["rank_error_lower"][str(cap)] for g in gs]})
@@ -547,10 +559,15 @@ def main():
             oa = q.SolveOptions(delta=p.delta, tol=0.0, cap=128, max_iter=args.amen_iters,
                                 oversample=args.oversample, seed=2024, streams=args.streams, orth=orth,
                                 matvec=mv)
-            Ca, ra, _, ta, _ = timed_solve(q, ctx, prep, oa)
+            # statistics on in both legs (every stats_stride-th launch timed,
+            # as in the headline step): launches and time per kernel family
+            Ca, ra, _, ta, fa = timed_solve(q, ctx, prep, oa, stats_stride=args.stats_stride)
             legs[name] = {"iterations_per_s": sum(ra.iterations) / ta, "solve_s": ta,
                           "max_rank": ra.max_rank, "residual": ra.residual,
-                          "ceff_rel_error_vs_oracle": golden_error(Ca, "c2") if args.n == 8 else None}
+                          "ceff_rel_error_vs_oracle": golden_error(Ca, "c2") if args.n == 8 else None,
+                          "families": {f["family"]: {"launches_per_update": f["all_launches"] / sum(ra.iterations),
+                                                     "event_seconds": f["est_seconds"]}
+                                       for f in fa if f["all_launches"]}}
             log(f"{name} Green products, cap 128, {args.amen_iters} updates per case: {ta:.1f} s, "
                 f"{sum(ra.iterations) / ta:.2f} updates/s, C_eff error {legs[name]['ceff_rel_error_vs_oracle']}")
         amen = {"cap": 128, "updates_per_load_case": args.amen_iters, **legs}

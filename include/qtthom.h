@@ -163,6 +163,12 @@ typedef struct qtt_solve_opts {
                                 unfoldings (Sec. 3)                         */
     int matvec;              /* QTT_MV_*: how the Green step's products are
                                 approximated (Alg. 2, App. B)               */
+    int rank_buckets;        /* qtt_batch_solve: nonzero splits the
+                                structures of one grid size by the
+                                power-of-two bucket of their largest
+                                one-hot bond rank (the geometry rank of
+                                Sec. 5.2), so each batch pads to alike
+                                ranks; others ignore it                    */
 } qtt_solve_opts;
 
 typedef struct qtt_report {
@@ -301,8 +307,9 @@ int qtt_green_build_scheme(qtt_ctx* ctx, int n, double lam0, double mu0,
  * largest bond rank at order n - 1 and n; growth (optional): their ratio
  * (about 2 per order when the rank grows exponentially with the
  * resolution, about 1 when it saturates).  phase: host or device
- * (`phase_on_device`), N^3 uint8, n >= 2.  QTT_EINVAL for a phase id
- * >= nphase; QTT_ECAPACITY when a bond needs more than 160. */
+ * (`phase_on_device`), N^3 uint8, 2 <= n <= 8; trains whose bonds exceed
+ * the device TT-SVD's 160 are decomposed on the host.  QTT_EINVAL for a
+ * phase id >= nphase. */
 int qtt_rank_estimate(qtt_ctx* ctx, const uint8_t* phase, int phase_on_device,
                       int n, int nphase, double delta, int* ranks,
                       double* growth);

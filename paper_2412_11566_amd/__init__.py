@@ -330,12 +330,15 @@ class SolveOptions:
     orth: int = 0
     # the Green step's products: QTT_MV_SKETCH (default) or QTT_MV_AMEN
     matvec: int = 0
+    # batch_solve: split grid-size groups by the geometry-rank bucket
+    rank_buckets: bool = False
 
     def c(self) -> _c.SolveOpts:
         o = _c.SolveOpts(self.delta, self.tol, self.cap, self.max_iter, self.precision,
                          self.oversample, int(self.exact), self.seed, self.streams)
         o.orth = self.orth
         o.matvec = self.matvec
+        o.rank_buckets = int(self.rank_buckets)
         if self.history > 0:
             buf = np.zeros(6 * self.history)
             o.history = _dp(buf)

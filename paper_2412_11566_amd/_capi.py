@@ -58,7 +58,7 @@ class SolveOpts(C.Structure):
                 ("max_iter", C.c_int), ("precision", C.c_int), ("oversample", C.c_int),
                 ("exact", C.c_int), ("seed", C.c_uint64), ("streams", C.c_int),
                 ("history", C.POINTER(C.c_double)), ("history_len", C.c_int), ("orth", C.c_int),
-                ("matvec", C.c_int)]
+                ("matvec", C.c_int), ("rank_buckets", C.c_int)]
 
 
 class Report(C.Structure):

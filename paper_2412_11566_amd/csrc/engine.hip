@@ -2796,7 +2796,7 @@ int qtt_green_build_scheme(qtt_ctx* c, int n, double lam0, double mu0, double de
 
 int qtt_rank_estimate(qtt_ctx* c, const uint8_t* phase, int phase_on_device, int n, int nphase, double delta,
                       int* ranks, double* growth) {
-  if (!c || !phase || !ranks || n < 2 || n > 10 || nphase < 1 || nphase > 16 || !(delta > 0)) return QTT_EINVAL;
+  if (!c || !phase || !ranks || n < 2 || n > 8 || nphase < 1 || nphase > 16 || !(delta > 0)) return QTT_EINVAL;
   QTT_TRY(c, {
     Ctx X{c};
     const long NN = 1L << (3 * n);
@@ -2811,9 +2811,23 @@ int qtt_rank_estimate(qtt_ctx* c, const uint8_t* phase, int phase_on_device, int
     need(X, cb->p, (long)((NN / 8 + 15) / 16) - 1, "coarse out");
     coarsen_majority(dph, n, nphase, (uint8_t*)cb->p, X.s());
     host::HTT fine, coarse;
-    if (!device_chi(X, dph, true, 3 * n, nphase, delta, fine) ||
-        !device_chi(X, (const uint8_t*)cb->p, true, 3 * (n - 1), nphase, delta, coarse))
-      throw std::length_error("rank estimate: a bond beyond the device TT-SVD");
+    // the device TT-SVD, or the host one where a bond exceeds its 160
+    auto chi_of = [&](const uint8_t* d, int bits, host::HTT& out) {
+      if (device_chi(X, d, true, bits, nphase, delta, out)) return;
+      const size_t M = (size_t)1 << bits;
+      std::vector<uint8_t> h(M);
+      check(hipMemcpy(h.data(), d, M, hipMemcpyDeviceToHost), "phase d2h");
+      std::vector<double> oh((size_t)nphase * M, 0.0);
+      for (size_t e = 0; e < M; ++e) {
+        if (h[e] >= nphase) throw std::invalid_argument("phase id out of range");
+        oh[(size_t)h[e] * M + e] = 1.0;
+      }
+      std::vector<int> dims(bits + 1, 2);
+      dims[0] = nphase;
+      out = host::tt_svd_real(oh, dims, delta, 0);
+    };
+    chi_of(dph, 3 * n, fine);
+    chi_of((const uint8_t*)cb->p, 3 * (n - 1), coarse);
     int rc = 1, rf = 1;
     for (const auto& h : coarse) rc = std::max(rc, h.r1);
     for (const auto& h : fine) rf = std::max(rf, h.r1);
@@ -3579,7 +3593,8 @@ static const size_t kBatchMax = 32;
 // the Green scalars are per structure.  The host stiffness builds (TT-SVD
 // of the voxel arrays) run on parallel host threads.
 static int batch_group(qtt_ctx* c, const std::vector<int>& ids, const qtt_problem* Ps,
-                       const qtt_solve_opts* O, double* Ceff, qtt_report* Rs) {
+                       const qtt_solve_opts* O, double* Ceff, qtt_report* Rs,
+                       std::map<int, host::HTT>* pre = nullptr) {
   int status = QTT_OK;
   auto body = [&]() {
     const int S = (int)ids.size();
@@ -3592,6 +3607,10 @@ static int batch_group(qtt_ctx* c, const std::vector<int>& ids, const qtt_proble
     std::vector<host::HTT> cds(S);
     for (int s2 = 0; s2 < S; ++s2) {
       const qtt_problem& P = Ps[ids[s2]];
+      if (pre && pre->count(ids[s2])) {
+        cds[s2] = std::move((*pre)[ids[s2]]);
+        continue;
+      }
       host::HTT chi;
       cds[s2] = stiffness_op(X, P.phase, P.phase_on_device != 0, n, P.nphase, P.lame, P.lame0, O->delta,
                              0, &chi);
@@ -3670,11 +3689,41 @@ int qtt_batch_solve(qtt_ctx* c, int count, const qtt_problem* Ps, const qtt_solv
   auto note = [&](int rc) {
     if (rc != QTT_OK && (worst == QTT_OK || worst == QTT_ENOCONV)) worst = rc;
   };
+  // rank buckets: the stiffness operators are built first and each group
+  // splits by the power-of-two bucket of its structures' largest one-hot
+  // bond rank (the geometry rank of Sec. 5.2), so the padded ranks of a
+  // batch are alike
+  std::map<int, host::HTT> pre;
+  if (O->rank_buckets) {
+    std::map<std::pair<int, int>, std::vector<int>> split;
+    int rc = [&]() -> int {
+      QTT_TRY(c, {
+        Ctx X{c};
+        for (auto& gr : groups)
+          for (int i : gr.second) {
+            const qtt_problem& P = Ps[i];
+            check_problem(&P, O);
+            host::HTT chi;
+            pre[i] = stiffness_op(X, P.phase, P.phase_on_device != 0, P.n, P.nphase, P.lame, P.lame0, O->delta,
+                                  0, &chi);
+            int r = 1;
+            for (const auto& h : pre[i]) r = std::max(r, h.r1);
+            int b = 0;
+            while ((1 << b) < r) ++b;
+            // key: grid size and scheme in the first entry, bucket second
+            split[std::make_pair(gr.first.first * 4 + gr.first.second, b)].push_back(i);
+          }
+      });
+    }();
+    if (rc != QTT_OK) return rc;
+    groups.clear();
+    for (auto& sp : split) groups[sp.first] = sp.second;
+  }
   for (auto& gr : groups) {
     const std::vector<int>& ids = gr.second;
     for (size_t a = 0; a < ids.size(); a += kBatchMax) {
       std::vector<int> chunk(ids.begin() + a, ids.begin() + std::min(ids.size(), a + kBatchMax));
-      const int rc = batch_group(c, chunk, Ps, O, Ceff, Rs);
+      const int rc = batch_group(c, chunk, Ps, O, Ceff, Rs, &pre);
       note(rc);
       if (rc != QTT_OK && rc != QTT_ENOCONV) return rc;
     }

@@ -82,3 +82,24 @@ def test_batch_random_spheres_16(ctx, prec):
         Co, _ = D.effective_stiffness(p.phase, p.lame, p.lame0, tol=1e-10)
         assert rep.status == 0
         assert rel(C, Co) < 1e-5
+
+
+def test_batch_rank_buckets(ctx):
+    """Rank buckets (the geometry rank of Sec. 5.2) split the 16^3 and 8^3
+    structures into batches of alike ranks: every C_eff equals the
+    unbucketed batch's and the oracle's (exact sketch, fixed updates)."""
+    m = 4
+    opts = q.SolveOptions(delta=1e-14, tol=0.0, cap=0, max_iter=m, exact=True)
+    probs = list(_structures8())
+    p0 = M.config_c0()
+    probs.append((p0.phase, p0.lame, p0.lame0))
+    lam = M.laminate(16).astype(np.uint8)
+    probs.append((lam, p0.lame, p0.lame0))
+    Cb, _ = q.batch_solve(ctx, probs, opts)
+    ob = q.SolveOptions(delta=1e-14, tol=0.0, cap=0, max_iter=m, exact=True, rank_buckets=True)
+    Ck, reps = q.batch_solve(ctx, probs, ob)
+    for (ph, lame, lame0), C1, C2, rep in zip(probs, Cb, Ck, reps):
+        Co, _ = D.effective_stiffness(ph, lame, lame0, tol=0.0, fixed_iters=m)
+        assert rep.iterations == [m] * 6
+        assert rel(C2, C1) < 1e-10
+        assert rel(C2, Co) < 1e-10

@@ -57,3 +57,15 @@ def test_rank_estimate_rejects(ctx):
     with pytest.raises(q.QttError) as e:
         q.rank_estimate(ctx, np.zeros((2, 2, 2), np.uint8), 1, 1e-8)
     assert e.value.code == q._c.QTT_EINVAL
+
+
+def test_rank_estimate_beyond_the_device_path(ctx):
+    """64^3 random spheres: the one-hot bonds exceed the device TT-SVD's
+    160, so the host decomposes them; the ranks equal the oracle's."""
+    p = M.config_c3_structure(1)
+    if p.n != 6:
+        pytest.skip("structure 1 is not on the 64^3 grid")
+    got = q.rank_estimate(ctx, p.phase, 2, 1e-10)
+    want = Q.rank_estimate(p.phase, 2, 1e-10)
+    assert got[:2] == want[:2]
+    assert got[1] > 160
