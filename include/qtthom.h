@@ -15,6 +15,9 @@
  *   dimension 6 (Voigt order 11, 22, 33, 23, 13, 12; strains with
  *   engineering shear, stresses plain); cores 1..n hold the bits of x, most
  *   significant first (Sec. 4.3, binary discretisation), then y, then z.
+ *   Plane-strain problems (qtt_problem.dim = 2, the paper's 2D geometries)
+ *   use N^2 pixels, a control core of dimension 3 (Voigt 11, 22, 12) and
+ *   L = 2n + 1 cores.
  * - Tensor-train cores are stored row-major as (r_{k-1}, d_k, r_k) with r_k
  *   fastest; complex numbers are interleaved (re, im) doubles.  A tensor
  *   handle may hold a batch of B trains with common ranks (for instance the
