@@ -157,3 +157,25 @@ def test_solve_rejects_unknown_matvec(ctx):
         q.ls_solve(ctx, p.phase, p.lame, p.lame0,
                    q.SolveOptions(delta=1e-8, tol=1e-4, cap=32, max_iter=5, matvec=9))
     assert e.value.code == q._c.QTT_EINVAL
+
+
+def test_solve_amen_with_staggered_and_plane(ctx):
+    """The AMEn Green products with the staggered-grid factors (16^3
+    sphere against the oracle's staggered golden) and with the plane-strain
+    factors (64^2 circle against the plane-strain oracle), delta 1e-8."""
+    import json
+    import os
+    from oracle import plane as P2
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "ceff_c0stag.json")))
+    p = M.config_c0()
+    opts = q.SolveOptions(delta=1e-8, tol=1e-8, cap=128, max_iter=300, matvec=q.QTT_MV_AMEN)
+    C, rep, _ = q.ls_solve(ctx, p.phase, p.lame, p.lame0, opts, scheme="staggered")
+    assert rep.status == 0
+    assert rel(C, np.array(g["ceff"]).reshape(6, 6)) < 1e-5
+    lame = M.suite_lame()
+    l0 = M.reference_medium(lame)
+    ph = M.geometry("circle", 64, 2)
+    C2, rep2, _ = q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7)
+    Cref, _ = P2.effective_stiffness2(ph, lame, l0, tol=1e-12, max_iter=5000)
+    assert rep2.status == 0
+    assert rel(C2, Cref) < 1e-5
