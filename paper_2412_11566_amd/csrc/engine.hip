@@ -570,6 +570,14 @@ static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* 
     if (!std::isfinite(nrm[b])) throw nan_error("NaN/Inf in the norm of a train being rounded");
   std::vector<double> thr(B), disc2(B, 0.0);
   for (int b = 0; b < B; ++b) thr[b] = delta / std::sqrt((double)std::max(L - 1, 1)) * nrm[b];
+  // host arrays of the per-bond uploads stay alive until the sweep's
+  // single final synchronisation (no wait at the end of every bond); the
+  // guard, destroyed first, drains the stream on every exit
+  std::vector<std::vector<double>> hold;
+  struct Drain {
+    hipStream_t s;
+    ~Drain() { (void)hipStreamSynchronize(s); }
+  } drain{X.s()};
   for (int k = L - 1; k >= 1; --k) {
     const int p = y.r[k], q = y.dout[k] * y.r[k + 1];
     const int kk = std::min(p, q);
@@ -659,7 +667,8 @@ static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* 
           B, (long)rows * rmax, (long)rmax * rmax, (long)rows * rmax);
         nk1 = nk2;
       }
-      X.sync();  // host S buffers are reused next step
+      hold.push_back(std::move(S));
+      hold.push_back(std::move(SI));
       set_core(X, y, k, rmax, y.r[k + 1], nk);
       set_core(X, y, k - 1, y.r[k - 1], rmax, nk1);
       continue;
@@ -691,10 +700,11 @@ static void truncate_rl(const Ctx& X, TT& y, double delta, int cap, RoundStats* 
     auto nk1 = X.buf((size_t)B * rows * rmax);
     G(X, rows, rmax, p, OP_N, y.core[k - 1], p, OP_N, lv, kk, (cplx*)nk1->p, rmax, B,
       (long)rows * p, (long)p * kk, (long)rows * rmax);
-    X.sync();
+    hold.push_back(std::move(S));
     set_core(X, y, k, rmax, y.r[k + 1], nk);
     set_core(X, y, k - 1, y.r[k - 1], rmax, nk1);
   }
+  X.sync();  // the uploads of `hold` have been consumed
   if (st) {
     st->disc2 = disc2;
     st->norm = nrm;
