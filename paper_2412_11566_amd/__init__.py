@@ -233,6 +233,8 @@ def from_voxels(ctx: Context, phase, lame, lame0, delta: float, cap: int = 0):
     """(C - C0) raised operator and the one-hot phase train; ``phase`` is a
     host array or a torch uint8 device tensor (read in place)."""
     p, keep = _problem(phase, lame, lame0, 0)
+    if p.dim != 3:
+        raise ValueError("from_voxels: a cubic (N, N, N) voxel array")
     l0 = np.ascontiguousarray(lame0, dtype=np.float64)
     h, chi = C.c_void_p(), C.c_void_p()
     ctx.check(_c.lib().qtt_from_voxels(
@@ -247,6 +249,8 @@ def rank_estimate(ctx: Context, phase, nphase: int, delta: float):
     order n - 1 (2 x 2 x 2 majority coarsening), and their ratio; ``phase``
     is a host array or a torch uint8 device tensor."""
     p, keep = _problem(phase, np.zeros((nphase, 2)), (1.0, 1.0), 0)
+    if p.dim != 3:
+        raise ValueError("rank_estimate: a cubic (N, N, N) voxel array")
     r = (C.c_int * 2)()
     g = C.c_double(0.0)
     ctx.check(_c.lib().qtt_rank_estimate(ctx.h, p.phase, p.phase_on_device, p.n, nphase, delta,
