@@ -103,7 +103,7 @@ extern "C" {
  * QTT_MV_AMEN: each factor product by the AMEn-adapted product of App. B
  *   (tt_amen_apply), warm-started from the same product of the previous
  *   update (the first update from a random train at the cap's ranks; at
- *   most 3 sweeps warm, 6 cold; residual train of rank 8), its sweeps
+ *   most 3 sweeps warm, 6 cold; residual train of rank 16), its sweeps
  *   stopped when the product changes by less than a twentieth of the last
  *   relative update of the fixed point (at most 1e-3, at least delta). */
 #define QTT_MV_SKETCH 0

@@ -1220,6 +1220,7 @@ static TTP op_apply(const Ctx& X, const TT& A, const TT& x, int flags, const Ske
 // AMEn-adapted product y ~ A x (App. B)
 // ---------------------------------------------------------------------------
 static std::vector<double> diff_norms(const Ctx& X, const TT& a, const TT& b, double prev_rel);
+static std::vector<std::complex<double>> tt_dot_diag(const Ctx& X, const TT& x, const TT& y);
 
 // QR sweep right to left: cores 1..L-1 become right-orthonormal (orthonormal
 // rows of the r_k x (d r_{k+1}) unfolding), the R factors move left; the
@@ -1486,12 +1487,31 @@ static TTP amen_apply(const Ctx& X, const TT& A, const TT& x, const TT& y0, cons
     out = amen_compact(X, *y, kept);
     inf.sweeps = m;
     if (prev) {
-      auto dn = diff_norms(X, *out, *prev, 0.0);
-      auto nn = tt_norms(X, *out);
+      // while the change is large, inner products (no QR sweep) measure it;
+      // near the tolerance the difference train's norm does (no
+      // cancellation)
+      const bool gram = std::isfinite(inf.change) ? inf.change > 1e-4 : true;
+      auto dn = diff_norms(X, *out, *prev, gram ? 1.0 : 0.0);
+      std::vector<double> nn(B);
+      if (gram) {
+        auto d = tt_dot_diag(X, *out, *out);
+        for (int b = 0; b < B; ++b) nn[b] = std::sqrt(std::max(0.0, d[b].real()));
+      } else {
+        nn = tt_norms(X, *out);
+      }
       double ch = 0.0;
       for (int b = 0; b < B; ++b) ch = std::max(ch, dn[b] / std::max(nn[b], 1e-300));
       inf.change = ch;
-      if (ch < tol) break;
+      if (ch < tol && !(gram && ch < 1e-4)) break;
+      if (gram && ch < tol) {
+        // confirm a small change without cancellation
+        auto de = diff_norms(X, *out, *prev, 0.0);
+        auto ne = tt_norms(X, *out);
+        ch = 0.0;
+        for (int b = 0; b < B; ++b) ch = std::max(ch, de[b] / std::max(ne[b], 1e-300));
+        inf.change = ch;
+        if (ch < tol) break;
+      }
     }
     prev = out;
     if (m < sweeps) {
@@ -1513,7 +1533,7 @@ struct AmenSlots {
   std::map<int, std::pair<TTP, TTP>> yz;
   int sweeps = 6;       // cold start: at most this many sweeps
   int warm_sweeps = 3;  // warm start: at most this many sweeps
-  int kick = 8;         // rank of the residual train
+  int kick = 16;        // rank of the residual train (16: its products reach the matrix cores)
   // the sweeps stop when the product changes by less than this (relative)
   // between two sweeps; the loop ties it to its last relative update
   double tol = 1e-3;
