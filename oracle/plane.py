@@ -5,9 +5,10 @@ infrastructure): plane strain, Voigt dimension 3, the same Alg. 1 as
 * Voigt order (11, 22, 12), engineering shear for strain, plain stress.
   The isotropic plane-strain stiffness keeps lambda and mu:
   C = [[lam + 2 mu, lam, 0], [lam, lam + 2 mu, 0], [0, 0, mu]].
-* Green operator: the direct scheme k = i q of App. A, Table 3, from its
-  discrete gradient (B (B^H C0 B)^-1 B^H with the strain symbol B), with the
-  Nyquist rule of the three-dimensional oracle.
+* Green operators from their discrete gradients (B (B^H C0 B)^-1 B^H with
+  the strain symbol B): the direct scheme k = i q of App. A, Table 3, with
+  the Nyquist rule of the three-dimensional oracle, and the staggered grid
+  (forward differences on the normal strains, backward on the shear).
 * The paper's 2D problems (Sec. 5, Figs. of the 2D geometries) use this
   Voigt dimension; a z-invariant three-dimensional problem whose load keeps
   eps_33 = gamma_13 = gamma_23 = 0 is the same plane-strain problem, which
@@ -18,7 +19,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.fft as sfft
 
-from .dense import frequencies, gamma_voigt_symbol
+from .dense import frequencies, gamma_voigt_symbol, staggered_symbols
 
 PAIRS2 = [(0, 0), (1, 1), (0, 1)]
 
@@ -28,14 +29,16 @@ def iso_voigt2(lam: float, mu: float) -> np.ndarray:
     return np.array([[lam + 2 * mu, lam, 0.0], [lam, lam + 2 * mu, 0.0], [0.0, 0.0, mu]])
 
 
-def strain_symbol2(k: np.ndarray) -> np.ndarray:
-    """B (P, 3, 2): eps_11 = k_1 u_1, eps_22 = k_2 u_2, gamma_12 = k_2 u_1 + k_1 u_2."""
+def strain_symbol2(k: np.ndarray, k_shear: np.ndarray | None = None) -> np.ndarray:
+    """B (P, 3, 2): eps_11 = k_1 u_1, eps_22 = k_2 u_2,
+    gamma_12 = s_2 u_1 + s_1 u_2 with s = k_shear (default k)."""
     k = np.asarray(k, dtype=np.complex128)
+    s = k if k_shear is None else np.asarray(k_shear, dtype=np.complex128)
     B = np.zeros(k.shape[:-1] + (3, 2), dtype=np.complex128)
     B[..., 0, 0] = k[..., 0]
     B[..., 1, 1] = k[..., 1]
-    B[..., 2, 0] = k[..., 1]
-    B[..., 2, 1] = k[..., 0]
+    B[..., 2, 0] = s[..., 1]
+    B[..., 2, 1] = s[..., 0]
     return B
 
 
@@ -54,6 +57,27 @@ def gamma_table2(N, lam0: float, mu0: float) -> np.ndarray:
 
     G = 0.5 * (table(*f) + np.conj(table(*neg)))
     return G.transpose(2, 3, 0, 1).copy()
+
+
+def gamma_table2_staggered(N, lam0: float, mu0: float) -> np.ndarray:
+    """Plane-strain staggered-grid Green table (App. A, Table 3: forward
+    differences on the normal strains, backward on the shear), (3, 3, Nx,
+    Ny) in DFT order; the symbols are 2 pi-periodic (no Nyquist rule)."""
+    shape = (N, N) if np.isscalar(N) else tuple(N)
+    C0 = iso_voigt2(lam0, mu0)
+    qs = [2.0 * np.pi * np.arange(n) / n for n in shape]
+    Q = np.stack(np.meshgrid(*qs, indexing="ij"), axis=-1).reshape(-1, 2)
+    kp, km = staggered_symbols(Q)
+    G = gamma_voigt_symbol(strain_symbol2(kp, km), C0)
+    return G.reshape(shape + (3, 3)).transpose(2, 3, 0, 1).copy()
+
+
+def green_table2(shape, lam0: float, mu0: float, scheme: str = "direct") -> np.ndarray:
+    if scheme == "direct":
+        return gamma_table2(shape, lam0, mu0)
+    if scheme == "staggered":
+        return gamma_table2_staggered(shape, lam0, mu0)
+    raise ValueError(f"unknown scheme {scheme!r}")
 
 
 def basic_scheme2(phase: np.ndarray, lame, lame0, E, tol: float, max_iter: int = 2000,
@@ -90,9 +114,10 @@ def basic_scheme2(phase: np.ndarray, lame, lame0, E, tol: float, max_iter: int =
 
 
 def effective_stiffness2(phase: np.ndarray, lame, lame0, tol: float, max_iter: int = 2000,
-                         fixed_iters: int | None = None):
-    """Plane-strain C_eff (3 x 3, columns = unit load cases) from Alg. 1."""
-    G = gamma_table2(phase.shape, *lame0)
+                         fixed_iters: int | None = None, scheme: str = "direct"):
+    """Plane-strain C_eff (3 x 3, columns = unit load cases) from Alg. 1
+    with the Green operator of ``scheme``."""
+    G = green_table2(phase.shape, *lame0, scheme)
     Cp = np.stack([iso_voigt2(l, m) for l, m in np.asarray(lame)])
     C = np.zeros((3, 3))
     its = []

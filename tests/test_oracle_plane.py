@@ -49,3 +49,21 @@ def test_homogeneous_after_one_update():
     ph = np.zeros((8, 8), np.uint8)
     C, it = P2.effective_stiffness2(ph, np.array([[2.0, 1.0]]), (1.0, 0.8), tol=1e-13)
     assert np.abs(C - P2.iso_voigt2(2.0, 1.0)).max() < 1e-13 and it == [1, 1, 1]
+
+
+def test_staggered_plane_is_the_3d_in_plane_block():
+    """The plane staggered table and C_eff equal the 3D staggered ones'
+    in-plane blocks on an (N, N, 1) grid (q_z = 0: both difference symbols
+    of z vanish and u_3 decouples)."""
+    N = 8
+    G2 = P2.gamma_table2_staggered(N, 1.3, 0.7)
+    G3 = D.gamma_table_staggered((N, N, 1), 1.3, 0.7)[:, :, :, :, 0]
+    assert np.abs(G2 - G3[np.ix_(IN, IN)]).max() < 1e-14
+    rng = np.random.default_rng(4)
+    ph = (M.spheres(16, rng.uniform(0, 1, (2, 3)), np.array([0.2, 0.15]))[:, :, 0]).astype(np.uint8)
+    lame = np.array([[1.0, 0.5], [6.0, 2.5]])
+    l0 = M.reference_medium(lame)
+    C2, it2 = P2.effective_stiffness2(ph, lame, l0, tol=1e-12, scheme="staggered")
+    C3, it3 = D.effective_stiffness(ph[:, :, None].copy(), lame, l0, tol=1e-12, scheme="staggered")
+    assert np.abs(C2 - C3[np.ix_(IN, IN)]).max() < 1e-11 * np.abs(C2).max()
+    assert it2 == [it3[i] for i in IN]
