@@ -133,9 +133,9 @@ typedef struct qtt_problem {
                                 strain on N^2 pixels (C order, x slowest),
                                 Voigt 3 (11, 22, 12), load cases bits 0..2,
                                 C_eff in rows and columns 0..2 of the 6 x 6
-                                output, n <= 12, direct scheme only (the
-                                paper's 2D problems, Sec. 5); ls_solve,
-                                qtt_prepare and ls_solve_prepared         */
+                                output, n <= 12 (the paper's 2D problems,
+                                Sec. 5); ls_solve, qtt_prepare and
+                                ls_solve_prepared                          */
 } qtt_problem;
 
 typedef struct qtt_solve_opts {

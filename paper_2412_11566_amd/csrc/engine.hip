@@ -1766,12 +1766,16 @@ static bool device_direction_staggered(const Ctx& X, int n, double delta, host::
 // The Green factors from the direction train: its TT-SVD on the device, or
 // (direct scheme) on the host when a bond rank exceeds the device path
 static bool device_direction2d(const Ctx& X, int n, double delta, host::HTT& out);
+static bool device_direction_staggered2d(const Ctx& X, int n, double delta, host::HTT& out);
 
 static TTP green_op(const Ctx& X, int n, double lam0, double mu0, double delta, int scheme, int dim = 3) {
   host::HTT nt;
   host::GreenFactors gf;
-  if (dim == 2) {
-    if (scheme != QTT_SCHEME_DIRECT) throw std::invalid_argument("plane problems use the direct scheme");
+  if (dim == 2 && scheme == QTT_SCHEME_STAGGERED) {
+    if (!device_direction_staggered2d(X, n, delta, nt))
+      throw std::length_error("plane staggered Green operator: direction-train rank beyond the device TT-SVD");
+    gf = host::green_factors_staggered2d_from(nt, lam0, mu0);
+  } else if (dim == 2) {
     if (!device_direction2d(X, n, delta, nt)) {
       // host TT-SVD of the 4 x 2^(2n) direction field (bonds beyond the
       // device path)
@@ -2133,6 +2137,24 @@ static bool device_direction_staggered(const Ctx& X, int n, double delta, host::
                       out);
 }
 
+// The plane staggered directions (n_a, m_a), a in {x, y}: 4 x 2^(2n)
+static bool device_direction_staggered2d(const Ctx& X, int n, double delta, host::HTT& out) {
+  const long NN = 1L << (2 * n);
+  const int L = 2 * n + 1, N = 1 << n;
+  std::vector<double> kp, km;
+  host::staggered_symbols(n, kp, km);
+  auto sd = X.buf(2 * (size_t)N);
+  check(hipMemcpyAsync(sd->p, kp.data(), N * sizeof(cplx), hipMemcpyHostToDevice, X.s()), "symbols h2d");
+  check(hipMemcpyAsync((cplx*)sd->p + N, km.data(), N * sizeof(cplx), hipMemcpyHostToDevice, X.s()),
+        "symbols h2d");
+  auto T = X.buf((size_t)4 * NN);
+  need(X, T->p, 4 * NN - 1, "direction out");
+  direction_staggered2d((const cplx*)sd->p, (const cplx*)sd->p + N, n, (cplx*)T->p, X.s());
+  X.sync();
+  return device_ttsvd(X, T, 2 * n, 4, delta / std::sqrt((double)(L - 1)) * std::sqrt(2.0 * (double)(NN - 1)),
+                      out);
+}
+
 // TT-SVD of a dense device tensor T with dims (P, 2, ..., 2) (3n binary
 // indices, P slowest; complex storage, P 2^(3n) entries), right to left: the
 // unfolding M (P 2^(k-1) x 2 r_k) is reduced to R by tsqr_r, R^H goes
@@ -2256,8 +2278,6 @@ static void check_problem(const qtt_problem* P, const qtt_solve_opts* O) {
   if (P->dim != 0 && P->dim != 2 && P->dim != 3) throw std::invalid_argument("dim must be 0, 2 or 3");
   if (P->n < 1 || P->n > (P->dim == 2 ? 12 : 10))
     throw std::invalid_argument("n out of range (1..10, plane problems 1..12)");
-  if (P->dim == 2 && P->scheme != QTT_SCHEME_DIRECT)
-    throw std::invalid_argument("plane problems use the direct scheme");
   if (P->nphase < 1 || P->nphase > 16) throw std::invalid_argument("nphase out of range");
   if (!P->phase || !P->lame) throw std::invalid_argument("null phase or lame");
   if (P->scheme != QTT_SCHEME_DIRECT && P->scheme != QTT_SCHEME_STAGGERED)

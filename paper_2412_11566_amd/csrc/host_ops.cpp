@@ -580,6 +580,42 @@ GreenFactors green_factors_staggered_from(const HTT& nt, double lam0, double mu0
   return G;
 }
 
+GreenFactors green_factors_staggered2d_from(const HTT& nt, double lam0, double mu0) {
+  GreenFactors G;
+  // control c: a (0, 1) -> n_a, 2 + a -> m_a; plane Voigt (11, 22, 12)
+  // U: u_k = -m_k tau_kk - n_j tau_12 (j != k) ; out 2, in 3
+  {
+    std::vector<double> cf(2 * 3 * 4, 0.0);
+    for (int k = 0; k < 2; ++k) {
+      cf[((size_t)k * 3 + k) * 4 + 2 + k] = -1.0;
+      cf[((size_t)k * 3 + 2) * 4 + (1 - k)] = -1.0;
+    }
+    G.U = control_op(nt, 2, 3, cf, 4);
+  }
+  // Sd: s = sum_k n_k u_k ; out 1, in 2
+  {
+    std::vector<double> cf(1 * 2 * 4, 0.0);
+    for (int k = 0; k < 2; ++k) cf[(size_t)k * 4 + k] = 1.0;
+    G.Sd = control_op(nt, 1, 2, cf, 4);
+  }
+  // P: p_k = m_k s ; out 2, in 1
+  {
+    std::vector<double> cf(2 * 1 * 4, 0.0);
+    for (int k = 0; k < 2; ++k) cf[(size_t)k * 4 + 2 + k] = 1.0;
+    G.P = control_op(nt, 2, 1, cf, 4);
+  }
+  // E: eps_kk = n_k q_k, gamma_12 = m_2 q_1 + m_1 q_2 ; out 3, in 2
+  {
+    std::vector<double> cf(3 * 2 * 4, 0.0);
+    for (int k = 0; k < 2; ++k) cf[((size_t)k * 2 + k) * 4 + k] = 1.0;
+    cf[((size_t)2 * 2 + 0) * 4 + 2 + 1] += 1.0;
+    cf[((size_t)2 * 2 + 1) * 4 + 2 + 0] += 1.0;
+    G.E = control_op(nt, 3, 2, cf, 4);
+  }
+  green_scalars_scheme(1, lam0, mu0, &G.inv_2mu0, &G.half_c);
+  return G;
+}
+
 GreenFactors green_factors2d_from(const HTT& nt, double lam0, double mu0) {
   GreenFactors G;
   // control c = 2 sigma + a (the two Nyquist representatives, axes x, y);

@@ -87,6 +87,10 @@ GreenFactors green_factors_staggered_from(const HTT& nt, double lam0, double mu0
 // P: 2 -> 4, E: 4 -> 3, with the same two scalars (the plane-strain
 // acoustic tensor is mu0 |xi|^2 I + (lam0 + mu0) xi xi^T on the plane).
 GreenFactors green_factors2d_from(const HTT& nt, double lam0, double mu0);
+// The plane staggered-grid factors (the 3D derivation restricted to the
+// plane) from the train of (n_a, m_a), a in {x, y} (control 2 t + a):
+// U: 3 -> 2, Sd: 2 -> 1, P: 1 -> 2, E: 2 -> 3, the staggered scalars.
+GreenFactors green_factors_staggered2d_from(const HTT& nt, double lam0, double mu0);
 // The Green step's two medium scalars for a scheme (0 direct, 1 staggered):
 // q = a u - c p.
 void green_scalars_scheme(int scheme, double lam0, double mu0, double* a, double* c);

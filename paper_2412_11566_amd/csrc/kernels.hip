@@ -754,6 +754,31 @@ __global__ void k_direction_staggered(const cplx* __restrict__ kp, const cplx* _
   }
 }
 
+// The plane version: 4 x 2^(2n) entries, control (t, a), a in {x, y}
+__global__ void k_direction_staggered2d(const cplx* __restrict__ kp, const cplx* __restrict__ km, int n, long NN,
+                                        cplx* __restrict__ out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NN) return;
+  const int N = 1 << n;
+  const int ix[2] = {(int)(e >> n), (int)(e & (N - 1))};
+  double r2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) r2 += kp[ix[a]].x * kp[ix[a]].x + kp[ix[a]].y * kp[ix[a]].y;
+  const double inv = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    out[a * NN + e] = make_double2(kp[ix[a]].x * inv, kp[ix[a]].y * inv);
+    out[(2 + a) * NN + e] = make_double2(km[ix[a]].x * inv, km[ix[a]].y * inv);
+  }
+}
+
+void direction_staggered2d(const cplx* kp, const cplx* km, int n, cplx* out, hipStream_t s) {
+  const long NN = 1L << (2 * n);
+  hipLaunchKernelGGL(k_direction_staggered2d, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, s, kp, km, n, NN,
+                     out);
+  check(hipGetLastError(), "direction_staggered2d launch");
+}
+
 void direction_staggered(const cplx* kp, const cplx* km, int n, cplx* out, hipStream_t s) {
   const long NN = 1L << (3 * n);
   hipLaunchKernelGGL(k_direction_staggered, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, s, kp, km, n, NN,

@@ -303,6 +303,8 @@ void direction2d(const double* f, const double* f2, int n, cplx* out, hipStream_
 // the forward symbols kp_a / |kp|, t = 1 the backward ones km_a / |kp|);
 // kp, km: device arrays of one axis's symbols in momentum order (2^n each).
 void direction_staggered(const cplx* kp, const cplx* km, int n, cplx* out, hipStream_t s);
+// The plane version (4 x 2^(2n) entries, control (t, a), a in {x, y}).
+void direction_staggered2d(const cplx* kp, const cplx* km, int n, cplx* out, hipStream_t s);
 
 void check(hipError_t e, const char* what);
 

@@ -67,9 +67,6 @@ def test_plane_prepared_and_rejects(ctx):
     C, rep, _ = q.ls_solve_prepared(ctx, prep, opts)
     C1, _, _ = q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7)
     assert C.shape == (3, 3) and rel(C, C1) < 1e-6
-    with pytest.raises(q.QttError) as e:
-        q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7, scheme="staggered")
-    assert e.value.code == q._c.QTT_EINVAL
     _, _, eps = q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7, keep_eps=True)
     with pytest.raises(q.QttError) as e:
         q.ls_adjoint(ctx, ph, lame, l0, opts, eps)
@@ -92,3 +89,25 @@ def test_plane_reduced_precision_contractions(ctx, prec):
     Cref, _ = P2.effective_stiffness2(ph, lame, l0, tol=1e-12, max_iter=5000)
     assert rep.status == 0
     assert rel(C, Cref) < (1e-5 if prec == "fp32" else 2e-4)
+
+
+@pytest.mark.parametrize("name", ["circle", "voronoi"])
+def test_plane_staggered(ctx, name):
+    """The plane staggered-grid Green operator: untruncated against Alg. 1
+    with the plane staggered table after 8 updates (1e-10), and at delta
+    1e-8 against the converged oracle (1e-5); it differs from the direct
+    scheme."""
+    ph, lame, l0 = _suite(name, 5)
+    m = 8
+    ex = q.SolveOptions(delta=1e-14, tol=0.0, cap=0, max_iter=m, exact=True)
+    C, _, _ = q.ls_solve(ctx, ph, lame, l0, ex, load_mask=0x7, scheme="staggered")
+    Cref, _ = P2.effective_stiffness2(ph, lame, l0, tol=0.0, fixed_iters=m, scheme="staggered")
+    assert rel(C, Cref) < 1e-10
+    Cd, _ = P2.effective_stiffness2(ph, lame, l0, tol=0.0, fixed_iters=m)
+    assert rel(C, Cd) > 1e-4
+    ph6, _, _ = _suite(name, 6)
+    opts = q.SolveOptions(delta=1e-8, tol=1e-8, cap=128, max_iter=400)
+    C6, rep, _ = q.ls_solve(ctx, ph6, lame, l0, opts, load_mask=0x7, scheme="staggered")
+    C6ref, _ = P2.effective_stiffness2(ph6, lame, l0, tol=1e-12, max_iter=5000, scheme="staggered")
+    assert rep.status == 0
+    assert rel(C6, C6ref) < 1e-5
