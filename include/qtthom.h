@@ -134,8 +134,8 @@ typedef struct qtt_problem {
                                 Voigt 3 (11, 22, 12), load cases bits 0..2,
                                 C_eff in rows and columns 0..2 of the 6 x 6
                                 output, n <= 12 (the paper's 2D problems,
-                                Sec. 5); ls_solve, qtt_prepare and
-                                ls_solve_prepared                          */
+                                Sec. 5); every solve entry point but
+                                ls_adjoint                                 */
 } qtt_problem;
 
 typedef struct qtt_solve_opts {

@@ -1850,8 +1850,8 @@ static TTP green_cached(const Ctx& X, int n, double lam0, double mu0, double del
 
 // Green operator for a batch of structures (train batch = 6 per structure)
 static TTP green_batch(const Ctx& X, int n, double delta, const std::vector<double>& lam0,
-                       const std::vector<double>& mu0, int per, int scheme) {
-  auto t = green_cached(X, n, lam0[0], mu0[0], delta, scheme);
+                       const std::vector<double>& mu0, int per, int scheme, int dim = 3) {
+  auto t = green_cached(X, n, lam0[0], mu0[0], delta, scheme, dim);
   const int S = (int)lam0.size(), B = S * per;
   std::vector<double> a(B), c(B);
   for (int s2 = 0; s2 < S; ++s2) {
@@ -3650,6 +3650,7 @@ static int batch_group(qtt_ctx* c, const std::vector<int>& ids, const qtt_proble
     const int S = (int)ids.size();
     for (int i : ids) check_problem(&Ps[i], O);
     const int n = Ps[ids[0]].n;
+    const int dim = Ps[ids[0]].dim == 2 ? 2 : 3, V = dim == 2 ? 3 : 6;
     Ctx X{c};
     const double t0 = now_s();
     // per-structure stiffness operators from the device TT-SVD of each
@@ -3663,22 +3664,22 @@ static int batch_group(qtt_ctx* c, const std::vector<int>& ids, const qtt_proble
       }
       host::HTT chi;
       cds[s2] = stiffness_op(X, P.phase, P.phase_on_device != 0, n, P.nphase, P.lame, P.lame0, O->delta,
-                             0, &chi);
+                             0, &chi, dim);
     }
     Ops ops;
-    ops.S = sfft_cached(X, n, O->delta);
+    ops.S = sfft_cached(X, n, O->delta, dim);
     std::vector<double> l0(S), m0(S);
     for (int s2 = 0; s2 < S; ++s2) {
       l0[s2] = Ps[ids[s2]].lame0[0];
       m0[s2] = Ps[ids[s2]].lame0[1];
     }
-    ops.G = green_batch(X, n, O->delta, l0, m0, 6, Ps[ids[0]].scheme);
+    ops.G = green_batch(X, n, O->delta, l0, m0, V, Ps[ids[0]].scheme, dim);
     ops.Cd = upload_op_batch(X, cds);
-    ops.I = identity_op(X, 3 * n);
+    ops.I = identity_op(X, dim * n, V);
     cds.clear();
     const double t1 = now_s();
-    std::vector<int> ks((size_t)6 * S);
-    for (size_t b = 0; b < ks.size(); ++b) ks[b] = (int)(b % 6);
+    std::vector<int> ks((size_t)V * S);
+    for (size_t b = 0; b < ks.size(); ++b) ks[b] = (int)(b % V);
     SolveOut so = ls_loop(X, ops, &Ps[ids[0]], O, ks);
     auto md = mean_apply(X, *ops.Cd, *so.eps);
     auto me = mean_apply(X, *ops.I, *so.eps);
@@ -3686,14 +3687,15 @@ static int batch_group(qtt_ctx* c, const std::vector<int>& ids, const qtt_proble
     for (int s2 = 0; s2 < S; ++s2) {
       const int id = ids[s2];
       double C0m[36];
-      host::iso_voigt(Ps[id].lame0[0], Ps[id].lame0[1], C0m);
+      host::iso_voigt_dim(V, Ps[id].lame0[0], Ps[id].lame0[1], C0m);
       double* Ce = Ceff + (size_t)36 * id;
+      for (int i = 0; i < 36; ++i) Ce[i] = 0.0;
       bool all = true;
-      for (int k = 0; k < 6; ++k) {
-        const size_t b = (size_t)s2 * 6 + k;
-        for (int i = 0; i < 6; ++i) {
-          std::complex<double> v = md[b * 6 + i];
-          for (int j = 0; j < 6; ++j) v += C0m[i * 6 + j] * me[b * 6 + j];
+      for (int k = 0; k < V; ++k) {
+        const size_t b = (size_t)s2 * V + k;
+        for (int i = 0; i < V; ++i) {
+          std::complex<double> v = md[b * V + i];
+          for (int j = 0; j < V; ++j) v += C0m[i * V + j] * me[b * V + j];
           Ce[i * 6 + k] = v.real();
         }
         all = all && so.res[b] < O->tol;
@@ -3701,9 +3703,9 @@ static int batch_group(qtt_ctx* c, const std::vector<int>& ids, const qtt_proble
       if (Rs) {
         qtt_report& R = Rs[id];
         std::memset(&R, 0, sizeof(R));
-        for (int k = 0; k < 6; ++k) {
-          R.iterations[k] = so.iters[(size_t)s2 * 6 + k];
-          R.residual[k] = so.res[(size_t)s2 * 6 + k];
+        for (int k = 0; k < V; ++k) {
+          R.iterations[k] = so.iters[(size_t)s2 * V + k];
+          R.residual[k] = so.res[(size_t)s2 * V + k];
         }
         R.max_rank = so.max_rank;
         R.discarded = so.disc;
@@ -3727,11 +3729,15 @@ int qtt_batch_solve(qtt_ctx* c, int count, const qtt_problem* Ps, const qtt_solv
   // structures with all six load cases are solved together, grouped by
   // grid size and Green scheme, at most kBatchMax per group; the others one
   // by one
+  // (key: grid size, dimension and scheme; plane problems need all three
+  // of their load cases, 3D ones all six)
   std::map<std::pair<int, int>, std::vector<int>> groups;
   std::vector<int> single;
   for (int i = 0; i < count; ++i) {
-    if (Ps[i].load_mask == 0x3F && Ps[i].n >= 1 && Ps[i].n <= 10 && Ps[i].dim != 2)
-      groups[std::make_pair(Ps[i].n, Ps[i].scheme)].push_back(i);
+    const bool plane = Ps[i].dim == 2;
+    const int full = plane ? 0x7 : 0x3F;
+    if ((Ps[i].load_mask & full) == full && Ps[i].n >= 1 && Ps[i].n <= (plane ? 12 : 10))
+      groups[std::make_pair(Ps[i].n * 4 + (plane ? 2 : 3), Ps[i].scheme)].push_back(i);
     else
       single.push_back(i);
   }
@@ -3755,12 +3761,13 @@ int qtt_batch_solve(qtt_ctx* c, int count, const qtt_problem* Ps, const qtt_solv
             check_problem(&P, O);
             host::HTT chi;
             pre[i] = stiffness_op(X, P.phase, P.phase_on_device != 0, P.n, P.nphase, P.lame, P.lame0, O->delta,
-                                  0, &chi);
+                                  0, &chi, P.dim == 2 ? 2 : 3);
             int r = 1;
             for (const auto& h : pre[i]) r = std::max(r, h.r1);
             int b = 0;
             while ((1 << b) < r) ++b;
-            // key: grid size and scheme in the first entry, bucket second
+            // key: grid size, dimension and scheme in the first entry,
+            // bucket second
             split[std::make_pair(gr.first.first * 4 + gr.first.second, b)].push_back(i);
           }
       });

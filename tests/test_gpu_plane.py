@@ -111,3 +111,29 @@ def test_plane_staggered(ctx, name):
     C6ref, _ = P2.effective_stiffness2(ph6, lame, l0, tol=1e-12, max_iter=5000, scheme="staggered")
     assert rep.status == 0
     assert rel(C6, C6ref) < 1e-5
+
+
+def test_plane_batch_matches_single(ctx):
+    """Three plane structures of one grid in one batch (per-structure
+    stiffness instances and reference media, shared plane factors): each
+    C_eff block equals its own solve and the oracle (exact sketch, fixed
+    updates); a 3D structure in the same call is grouped apart."""
+    m = 5
+    opts = q.SolveOptions(delta=1e-14, tol=0.0, cap=0, max_iter=m, exact=True)
+    lame = M.suite_lame()
+    probs = []
+    for g, s in (("circle", 1.0), ("square", 1.5), ("spots", 2.0)):
+        lm = lame * np.array([[1.0, 1.0], [s, s]])
+        probs.append((M.geometry(g, 16, 2, seed=1), lm, M.reference_medium(lm)))
+    p0 = M.config_c0()
+    probs.append((p0.phase[::2, ::2, ::2].copy(), p0.lame, p0.lame0))
+    Cb, reps = q.batch_solve(ctx, probs, opts)
+    for i, (ph, lm, l0) in enumerate(probs[:3]):
+        Cs, _, _ = q.ls_solve(ctx, ph, lm, l0, opts, load_mask=0x7)
+        Co, _ = P2.effective_stiffness2(ph, lm, l0, tol=0.0, fixed_iters=m)
+        assert rel(Cb[i][:3, :3], Cs) < 1e-10
+        assert rel(Cb[i][:3, :3], Co) < 1e-10
+        assert reps[i].iterations[:3] == [m] * 3
+    from oracle import dense as D
+    C3, _ = D.effective_stiffness(probs[3][0], p0.lame, p0.lame0, tol=0.0, fixed_iters=m)
+    assert rel(Cb[3], C3) < 1e-10
