@@ -114,17 +114,22 @@ def basic_scheme2(phase: np.ndarray, lame, lame0, E, tol: float, max_iter: int =
 
 
 def effective_stiffness2(phase: np.ndarray, lame, lame0, tol: float, max_iter: int = 2000,
-                         fixed_iters: int | None = None, scheme: str = "direct"):
+                         fixed_iters: int | None = None, scheme: str = "direct",
+                         keep_fields: bool = False):
     """Plane-strain C_eff (3 x 3, columns = unit load cases) from Alg. 1
-    with the Green operator of ``scheme``."""
+    with the Green operator of ``scheme``; with ``keep_fields`` also the
+    three strain fields (3, N, N)."""
     G = green_table2(phase.shape, *lame0, scheme)
     Cp = np.stack([iso_voigt2(l, m) for l, m in np.asarray(lame)])
     C = np.zeros((3, 3))
     its = []
+    fields = []
     for k in range(3):
         E = np.zeros(3)
         E[k] = 1.0
         eps, m, _ = basic_scheme2(phase, lame, lame0, E, tol, max_iter, G=G, fixed_iters=fixed_iters)
+        if keep_fields:
+            fields.append(eps)
         s = np.zeros(3, dtype=np.complex128)
         for p in range(Cp.shape[0]):
             msk = phase == p
@@ -132,4 +137,49 @@ def effective_stiffness2(phase: np.ndarray, lame, lame0, tol: float, max_iter: i
                 s += Cp[p] @ eps[:, msk].sum(axis=1)
         C[:, k] = (s / phase.size).real
         its.append(m)
+    if keep_fields:
+        return C, its, fields
     return C, its
+
+
+# ---------------------------------------------------------------------------
+# Gradients of the plane-strain C_eff with respect to the phase Lame
+# parameters, C0 held fixed; theta = (lam_0, mu_0, lam_1, mu_1, ...).
+# ---------------------------------------------------------------------------
+
+def gradient_energy2(phase: np.ndarray, fields: list) -> np.ndarray:
+    """dC_kl/dtheta = < eps^k : dC/dtheta : eps^l > over the pixels (the
+    energy identity of the converged fixed point, C0 fixed), (3, 3,
+    2 * nphase)."""
+    nphase = int(phase.max()) + 1
+    basis = (iso_voigt2(1.0, 0.0), iso_voigt2(0.0, 1.0))
+    out = np.zeros((3, 3, 2 * nphase))
+    re = [f.real for f in fields]
+    for p in range(nphase):
+        m = phase == p
+        if not m.any():
+            continue
+        for t, dC in enumerate(basis):
+            for k in range(3):
+                for l in range(3):
+                    out[k, l, 2 * p + t] = np.einsum("vx,vw,wx->", re[k][:, m], dC,
+                                                     re[l][:, m]) / phase.size
+    return out
+
+
+def gradient_fd2(phase: np.ndarray, lame, lame0, tol: float, rel_step: float = 1e-6,
+                 max_iter: int = 5000, scheme: str = "direct") -> np.ndarray:
+    """Central finite differences of the plane-strain C_eff in each phase
+    (lam, mu), C0 fixed."""
+    lame = np.asarray(lame, dtype=np.float64)
+    out = np.zeros((3, 3, 2 * lame.shape[0]))
+    for p in range(lame.shape[0]):
+        for t in range(2):
+            h = rel_step * max(abs(lame[p, t]), 1e-3)
+            lp, lm = lame.copy(), lame.copy()
+            lp[p, t] += h
+            lm[p, t] -= h
+            Cp, _ = effective_stiffness2(phase, lp, lame0, tol, max_iter, scheme=scheme)
+            Cm, _ = effective_stiffness2(phase, lm, lame0, tol, max_iter, scheme=scheme)
+            out[:, :, 2 * p + t] = (Cp - Cm) / (2.0 * h)
+    return out

@@ -67,3 +67,37 @@ def test_staggered_plane_is_the_3d_in_plane_block():
     C3, it3 = D.effective_stiffness(ph[:, :, None].copy(), lame, l0, tol=1e-12, scheme="staggered")
     assert np.abs(C2 - C3[np.ix_(IN, IN)]).max() < 1e-11 * np.abs(C2).max()
     assert it2 == [it3[i] for i in IN]
+
+
+def _two_phase_square(N, seed):
+    rng = np.random.default_rng(seed)
+    return (M.spheres(N, rng.uniform(0, 1, (3, 3)), np.array([0.22, 0.15, 0.1]))[:, :, 0]).astype(np.uint8)
+
+
+def test_plane_gradient_energy_identity_matches_finite_differences():
+    """The energy identity of the plane-strain C_eff against central
+    differences of forward solves (both schemes)."""
+    ph = _two_phase_square(16, 5)
+    lame = np.array([[1.0, 0.5], [6.0, 2.5]])
+    l0 = M.reference_medium(lame)
+    for scheme in ("direct", "staggered"):
+        C, _, f = P2.effective_stiffness2(ph, lame, l0, tol=1e-13, max_iter=5000, scheme=scheme,
+                                          keep_fields=True)
+        ge = P2.gradient_energy2(ph, f)
+        gf = P2.gradient_fd2(ph, lame, l0, tol=1e-13, rel_step=1e-5, scheme=scheme)
+        assert np.abs(ge - gf).max() < 1e-6 * np.abs(ge).max()
+        # symmetric in (k, l)
+        assert np.abs(ge - np.swapaxes(ge, 0, 1)).max() < 1e-12 * np.abs(ge).max()
+
+
+def test_plane_gradient_is_the_3d_in_plane_block():
+    """On an (N, N, 1) grid the plane gradient is the in-plane block of the
+    three-dimensional energy identity."""
+    ph = _two_phase_square(16, 9)
+    lame = np.array([[1.0, 0.5], [6.0, 2.5]])
+    l0 = M.reference_medium(lame)
+    _, _, f2 = P2.effective_stiffness2(ph, lame, l0, tol=1e-13, keep_fields=True)
+    _, _, f3 = D.effective_stiffness(ph[:, :, None].copy(), lame, l0, tol=1e-13, keep_fields=True)
+    g2 = P2.gradient_energy2(ph, f2)
+    g3 = D.gradient_energy(ph[:, :, None].copy(), f3)
+    assert np.abs(g2 - g3[np.ix_(IN, IN)]).max() < 1e-11 * np.abs(g2).max()
