@@ -134,8 +134,8 @@ typedef struct qtt_problem {
                                 Voigt 3 (11, 22, 12), load cases bits 0..2,
                                 C_eff in rows and columns 0..2 of the 6 x 6
                                 output, n <= 12 (the paper's 2D problems,
-                                Sec. 5); every solve entry point but
-                                ls_adjoint                                 */
+                                Sec. 5); every solve entry point, the
+                                adjoint included (there V = 3)             */
 } qtt_problem;
 
 typedef struct qtt_solve_opts {
@@ -402,9 +402,11 @@ int ls_solve(qtt_ctx* ctx, const qtt_problem* P, const qtt_solve_opts* O,
  * held fixed.  For each load case k the adjoint fixed point
  * w_k = C e_k - (C - C0) G[w_k] (G = S^H Gamma S) is iterated with the
  * adjoint operators, then dC_kl/dtheta = <e_k, dC eps^l> - <w_k, G dC eps^l>.
- * eps: the six converged forward trains (from ls_solve, all six load
- * cases).  gbar: host [36] cotangent of C_eff or NULL; grad: host,
- * [2 nphase] if gbar is given, else the full Jacobian [36][2 nphase]. */
+ * V is the Voigt dimension of the problem: 6, or 3 for plane strain
+ * (P->dim = 2).  eps: the V converged forward trains (from ls_solve with
+ * every load case), else QTT_EINVAL.  gbar: host [V][V] row-major
+ * cotangent of C_eff or NULL; grad: host, [2 nphase] if gbar is given,
+ * else the full Jacobian [V][V][2 nphase]. */
 int ls_adjoint(qtt_ctx* ctx, const qtt_problem* P, const qtt_solve_opts* O,
                const qtt_tensor* eps, const double* gbar, double* grad,
                qtt_report* R);

@@ -418,18 +418,20 @@ def ls_solve(ctx: Context, phase, lame, lame0, opts: SolveOptions, load_mask: in
 
 def ls_adjoint(ctx: Context, phase, lame, lame0, opts: SolveOptions, eps: Tensor, gbar=None,
                scheme="direct"):
-    """Adjoint LS solve; returns the Jacobian (6, 6, 2*nphase) or the
-    gradient (2*nphase,) when the cotangent ``gbar`` (6, 6) is given."""
+    """Adjoint LS solve; returns the Jacobian (V, V, 2*nphase) or the
+    gradient (2*nphase,) when the cotangent ``gbar`` (V, V) is given; V = 6,
+    or 3 for a plane-strain (square) phase array."""
     p, keep = _problem(phase, lame, lame0, 0x3F, scheme)
     o = opts.c()
     nt = 2 * np.asarray(lame).shape[0]
+    V = 3 if p.dim == 2 else 6
     rep = _c.Report()
     if gbar is None:
-        out = np.zeros(36 * nt)
+        out = np.zeros(V * V * nt)
         rc = _c.lib().ls_adjoint(ctx.h, C.byref(p), C.byref(o), eps.h, None, _dp(out), C.byref(rep))
         ctx.check(rc, allow=(QTT_ENOCONV,))
-        return out.reshape(6, 6, nt), _report(rep)
-    g = np.ascontiguousarray(gbar, dtype=np.float64).reshape(36)
+        return out.reshape(V, V, nt), _report(rep)
+    g = np.ascontiguousarray(gbar, dtype=np.float64).reshape(V * V)
     out = np.zeros(nt)
     rc = _c.lib().ls_adjoint(ctx.h, C.byref(p), C.byref(o), eps.h, _dp(g), _dp(out), C.byref(rep))
     ctx.check(rc, allow=(QTT_ENOCONV,))
@@ -630,14 +632,15 @@ def ls_adjoint_prepared(ctx: Context, prep: Prepared, opts: SolveOptions, eps: T
     ls_solve_prepared(..., keep_eps=True) of the same prepared object."""
     o = opts.c()
     nt = 2 * prep._keep[1].shape[0]
+    V = 3 if getattr(prep, "dim", 3) == 2 else 6
     rep = _c.Report()
     if gbar is None:
-        out = np.zeros(36 * nt)
+        out = np.zeros(V * V * nt)
         rc = _c.lib().ls_adjoint_prepared(ctx.h, prep.h, C.byref(o), eps.h, None, _dp(out),
                                           C.byref(rep))
         ctx.check(rc, allow=(QTT_ENOCONV,))
-        return out.reshape(6, 6, nt), _report(rep)
-    g = np.ascontiguousarray(gbar, dtype=np.float64).reshape(36)
+        return out.reshape(V, V, nt), _report(rep)
+    g = np.ascontiguousarray(gbar, dtype=np.float64).reshape(V * V)
     out = np.zeros(nt)
     rc = _c.lib().ls_adjoint_prepared(ctx.h, prep.h, C.byref(o), eps.h, _dp(g), _dp(out),
                                       C.byref(rep))
@@ -663,7 +666,8 @@ def _autograd_function():
         """C_eff as a differentiable function of the phase Lame parameters.
 
         forward(lame (nphase, 2) float64 tensor, phase, lame0, ctx, opts,
-        policy, reports) -> C_eff (6, 6) float64.  The forward solve keeps
+        policy, reports) -> C_eff (6, 6) float64, (3, 3) for a plane-strain
+        (square) phase array.  The forward solve keeps
         its strain trains; backward runs the adjoint LS solve
         (ls_adjoint_prepared) with the incoming cotangent and returns
         dL/dlame.  The reference medium lame0 is held fixed (not
@@ -703,7 +707,8 @@ _CeffFn = None
 
 def ceff(lame, phase, lame0, ctx: Context, opts: SolveOptions, on_noconv: str = "raise"):
     """Differentiable C_eff: ``ceff(lame_tensor, ...)`` returns a (6, 6)
-    torch tensor whose backward is the adjoint solve.  ``on_noconv``:
+    torch tensor ((3, 3) for plane strain) whose backward is the adjoint
+    solve.  ``on_noconv``:
     "raise", "warn" or "ignore" when the forward or adjoint fixed point
     stops at max_iter.  The returned tensor carries ``qtt_reports``, a dict
     with the forward report ("forward") and, after backward, the adjoint

@@ -1970,13 +1970,13 @@ static TTP const_strain(const Ctx& X, int n, int B, const double* E, int V = 6, 
 
 // d(C)/d(theta) as raised operator from the one-hot train: Voigt core
 // D[I][J] * chi_0[p][alpha], spatial cores of chi.
-static TTP dC_op(const Ctx& X, const host::HTT& chi, int p, const double D[36]) {
+static TTP dC_op(const Ctx& X, const host::HTT& chi, int p, const double* D, int V) {
   host::HTT h;
   host::HCore c0;
   const int r1 = chi[0].r1;
-  c0.r0 = 1; c0.dout = 6; c0.din = 6; c0.r1 = r1;
-  c0.v.assign(36 * (size_t)r1, 0.0);
-  for (int I = 0; I < 36; ++I)
+  c0.r0 = 1; c0.dout = V; c0.din = V; c0.r1 = r1;
+  c0.v.assign((size_t)V * V * r1, 0.0);
+  for (int I = 0; I < V * V; ++I)
     for (int a = 0; a < r1; ++a) c0.v[(size_t)I * r1 + a] = D[I] * chi[0].v[(size_t)p * r1 + a];
   h.push_back(c0);
   for (size_t k = 1; k < chi.size(); ++k) h.push_back(chi[k]);
@@ -3436,16 +3436,17 @@ struct AdjOut {
 static AdjOut adj_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, const qtt_solve_opts* O,
                        const std::vector<int>& ks) {
   const int n = P->n, B = (int)ks.size();
+  const int dim = P->dim == 2 ? 2 : 3, V = dim == 2 ? 3 : 6;
   // C e_k trains: (C - C0) : E + C0 E
-  std::vector<double> E((size_t)B * 6, 0.0), C0E((size_t)B * 6, 0.0);
+  std::vector<double> E((size_t)B * V, 0.0), C0E((size_t)B * V, 0.0);
   double C0m[36];
-  host::iso_voigt(P->lame0[0], P->lame0[1], C0m);
+  host::iso_voigt_dim(V, P->lame0[0], P->lame0[1], C0m);
   for (int b = 0; b < B; ++b) {
-    E[(size_t)b * 6 + ks[b]] = 1.0;
-    for (int i = 0; i < 6; ++i) C0E[(size_t)b * 6 + i] = C0m[i * 6 + ks[b]];
+    E[(size_t)b * V + ks[b]] = 1.0;
+    for (int i = 0; i < V; ++i) C0E[(size_t)b * V + i] = C0m[i * V + ks[b]];
   }
-  auto Et = const_strain(X, n, B, E.data());
-  auto C0t = const_strain(X, n, B, C0E.data());
+  auto Et = const_strain(X, n, B, E.data(), V, dim);
+  auto C0t = const_strain(X, n, B, C0E.data(), V, dim);
   SketchOpts so = sk(X, O);
   so.exact = true;  // rank of (C - C0) E is the stiffness rank: exact
   auto dE = op_apply(X, *ops.Cd, *Et, 0, so, nullptr);
@@ -3514,20 +3515,23 @@ static int adjoint_ops(qtt_ctx* c, const Ops& ops, const qtt_problem* P, const q
   int status = QTT_OK;
   auto body = [&]() {
     check_problem(P, O);
-    if (P->dim == 2) throw std::invalid_argument("the adjoint solve is three-dimensional");
     Ctx X{c};
     const double t1 = now_s();
     const int n = P->n, np = P->nphase;
-    if (eps->L != 3 * n + 1) throw std::invalid_argument("eps does not match the problem size");
-    const double NN = std::pow(2.0, 3.0 * n);
-    const std::vector<int> all_ks = {0, 1, 2, 3, 4, 5};
-    const int ng = std::max(1, std::min<int>(O->streams, 6));
+    const int dim = P->dim == 2 ? 2 : 3, V = dim == 2 ? 3 : 6;
+    if (eps->kind != 0 || eps->B != V || eps->L != dim * n + 1 || eps->dout.empty() ||
+        eps->dout[0] != V)
+      throw std::invalid_argument("eps does not match the problem (V load cases of its grid)");
+    const double NN = std::pow(2.0, (double)dim * n);
+    std::vector<int> all_ks(V);
+    for (int k = 0; k < V; ++k) all_ks[k] = k;
+    const int ng = std::max(1, std::min<int>(O->streams, V));
     AdjOut ao;
     if (ng == 1) {
       ao = adj_loop(X, ops, P, O, all_ks);
     } else {
       std::vector<std::vector<int>> groups(ng);
-      for (int i = 0; i < 6; ++i) groups[i * ng / 6].push_back(i);
+      for (int i = 0; i < V; ++i) groups[i * ng / V].push_back(i);
       std::vector<AdjOut> outs(ng);
       run_groups(c, ng, [&](const Ctx& Xs, int g) { outs[g] = adj_loop(Xs, ops, P, O, groups[g]); });
       std::vector<TTP> parts;
@@ -3546,25 +3550,25 @@ static int adjoint_ops(qtt_ctx* c, const Ops& ops, const qtt_problem* P, const q
     const bool conv = ao.conv;
     // gradient: dC_kl/dtheta = <e_k . dC eps^l> - <w_k, G[dC eps^l]>
     const int nt = 2 * np;
-    std::vector<double> J((size_t)36 * nt, 0.0);
+    std::vector<double> J((size_t)V * V * nt, 0.0);
     double Dl[36], Dm[36];
-    host::iso_voigt(1.0, 0.0, Dl);
-    host::iso_voigt(0.0, 1.0, Dm);
+    host::iso_voigt_dim(V, 1.0, 0.0, Dl);
+    host::iso_voigt_dim(V, 0.0, 1.0, Dm);
     // one (phase, modulus) derivative per task; with ng > 1 the tasks run
     // on the load-case groups' sub-contexts (w and eps are only read)
     auto grad_task = [&](const Ctx& Xg, int task) {
       const int p = task / 2, t = task % 2;
-      auto dC = dC_op(Xg, ops.chi, p, t == 0 ? Dl : Dm);
+      auto dC = dC_op(Xg, ops.chi, p, t == 0 ? Dl : Dm, V);
       auto v = op_apply(Xg, *dC, *eps, 0, sk(Xg, O), nullptr);   // dC : eps^l
       auto first = mean_apply(Xg, *ops.I, *v);                  // <e_k . dC eps^l>
       auto gv = op_apply(Xg, *ops.S, *v, 0, ski(Xg, O), nullptr);
       gv = op_apply(Xg, *ops.G, *gv, 0, ski(Xg, O), nullptr);
       gv = op_apply(Xg, *ops.S->adj, *gv, 0, sk(Xg, O), nullptr);
       auto gram = tt_gram(Xg, *w, *gv);                         // [k][l] sum conj(w_k) Gv_l
-      for (int k = 0; k < 6; ++k)
-        for (int l = 0; l < 6; ++l)
-          J[((size_t)k * 6 + l) * nt + task] =
-              first[(size_t)l * 6 + k].real() - gram[(size_t)k * 6 + l].real() / NN;
+      for (int k = 0; k < V; ++k)
+        for (int l = 0; l < V; ++l)
+          J[((size_t)k * V + l) * nt + task] =
+              first[(size_t)l * V + k].real() - gram[(size_t)k * V + l].real() / NN;
     };
     if (ng == 1) {
       for (int task = 0; task < nt; ++task) grad_task(X, task);
@@ -3577,7 +3581,7 @@ static int adjoint_ops(qtt_ctx* c, const Ops& ops, const qtt_problem* P, const q
     if (gbar) {
       for (int t = 0; t < nt; ++t) {
         double s = 0.0;
-        for (int i = 0; i < 36; ++i) s += gbar[i] * J[(size_t)i * nt + t];
+        for (int i = 0; i < V * V; ++i) s += gbar[i] * J[(size_t)i * nt + t];
         grad[t] = s;
       }
     } else {
@@ -3587,7 +3591,7 @@ static int adjoint_ops(qtt_ctx* c, const Ops& ops, const qtt_problem* P, const q
     const double t2 = now_s();
     if (R) {
       std::memset(R, 0, sizeof(*R));
-      for (int k = 0; k < 6; ++k) {
+      for (int k = 0; k < V; ++k) {
         R->iterations[k] = it[k];
         R->residual[k] = res[k];
       }
@@ -3604,7 +3608,7 @@ static int adjoint_ops(qtt_ctx* c, const Ops& ops, const qtt_problem* P, const q
 
 int ls_adjoint(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, const qtt_tensor* eps,
                const double* gbar, double* grad, qtt_report* R) {
-  if (!c || !P || !O || !eps || !grad || eps->kind != 0 || eps->B != 6) return QTT_EINVAL;
+  if (!c || !P || !O || !eps || !grad) return QTT_EINVAL;
   Ops ops;
   double setup = 0.0;
   int rc = [&]() -> int {
@@ -3626,7 +3630,7 @@ int ls_adjoint(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, const 
 
 int ls_adjoint_prepared(qtt_ctx* c, const qtt_prepared* pp, const qtt_solve_opts* O,
                         const qtt_tensor* eps, const double* gbar, double* grad, qtt_report* R) {
-  if (!c || !pp || !O || !eps || !grad || eps->kind != 0 || eps->B != 6) return QTT_EINVAL;
+  if (!c || !pp || !O || !eps || !grad) return QTT_EINVAL;
   const Prepared& pr = pp->p;
   qtt_problem P = pr.problem();
   return adjoint_ops(c, pr.ops, &P, O, eps, gbar, grad, R, pr.seconds_setup);

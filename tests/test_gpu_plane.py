@@ -68,8 +68,12 @@ def test_plane_prepared_and_rejects(ctx):
     C1, _, _ = q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7)
     assert C.shape == (3, 3) and rel(C, C1) < 1e-6
     _, _, eps = q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7, keep_eps=True)
+    J, arep = q.ls_adjoint(ctx, ph, lame, l0, opts, eps)
+    assert arep.status == 0 and J.shape == (3, 3, 2 * lame.shape[0])
+    # the adjoint needs the three load cases' trains
+    _, _, eps2 = q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x3, keep_eps=True)
     with pytest.raises(q.QttError) as e:
-        q.ls_adjoint(ctx, ph, lame, l0, opts, eps)
+        q.ls_adjoint(ctx, ph, lame, l0, opts, eps2)
     assert e.value.code == q._c.QTT_EINVAL
 
 
