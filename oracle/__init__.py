@@ -16,6 +16,10 @@ homogenization", arXiv 2412.11566):
   SFFT-based homogenization loop (Alg. 2).
 * ``oracle.amen``   -- the AMEn-adapted approximate TTO x TT product
   (App. B): Galerkin core updates, residual enrichment, QR.
+* ``oracle.plane``  -- the basic scheme in plane strain (Voigt 3) on N x N
+  pixels, both Green schemes, and its C_eff gradients.
+* ``oracle.unrolled`` -- the exact derivative of the C_eff returned after a
+  fixed number of updates (reverse mode of Alg. 1), 3D and plane strain.
 * ``oracle.bounds`` -- closed forms: isotropic stiffness, laminate effective
   stiffness, Voigt/Reuss and Hashin-Shtrikman bounds.
 
