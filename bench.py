@@ -364,6 +364,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gradient", action="store_true",
                     help="skip the adjoint solve (gradient cost ratio)")
+    ap.add_argument("--unrolled-steps", type=int, default=10,
+                    help="updates of the unrolled-gradient leg (0: skip)")
     ap.add_argument("--no-cap128", action="store_true", help="skip the cap-128 leg")
     ap.add_argument("--no-staggered", action="store_true",
                     help="skip the staggered-grid Green operator leg (cap 128)")
@@ -528,6 +530,28 @@ def main():
             grad = {"cap": 128, "fwd_s": t128, "adj_s": adj_s, "grad_over_fwd": (t128 + adj_s) / t128,
                     "adjoint_iterations": arep.iterations, "dsumC_dlame": g.tolist()}
             log(f"adjoint {adj_s:.2f} s, (fwd + adj) / fwd = {(t128 + adj_s) / t128:.3f}")
+            if args.unrolled_steps > 0:
+                # the derivative of the C_eff after a fixed number of updates
+                # (reverse mode, iterates kept or checkpointed), against the
+                # same fixed-count forward without the gradient
+                M_ = args.unrolled_steps
+                ou = q.SolveOptions(delta=p.delta, tol=0.0, cap=128, max_iter=1,
+                                    oversample=args.oversample, seed=2024, orth=orth)
+                unr = {"steps": M_}
+                for tag, every, wg in (("fwd", 0, False), ("all_kept", 0, True),
+                                       ("every_5", 5, True)):
+                    torch.cuda.synchronize()
+                    tu = time.perf_counter()
+                    _, gu, _ = q.ls_unrolled_prepared(ctx, prep, ou, M_, every=every,
+                                                      gbar=np.ones((6, 6)), want_grad=wg)
+                    torch.cuda.synchronize()
+                    unr[tag + "_s"] = time.perf_counter() - tu
+                for tag in ("all_kept", "every_5"):
+                    unr[tag + "_over_fwd"] = unr[tag + "_s"] / unr["fwd_s"]
+                unr["dsumC_dlame"] = gu.tolist()
+                grad["unrolled"] = unr
+                log(f"unrolled {M_} updates: fwd {unr['fwd_s']:.2f} s, with gradient "
+                    f"{unr['all_kept_s']:.2f} s (all kept), {unr['every_5_s']:.2f} s (every 5)")
         del eps128
     # the staggered-grid Green operator (App. A, Table 3) on the same
     # workload at cap 128: its own setup (direction train by the device

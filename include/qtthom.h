@@ -431,6 +431,30 @@ int ls_adjoint_prepared(qtt_ctx* ctx, const qtt_prepared* prep,
                         const qtt_solve_opts* O, const qtt_tensor* eps,
                         const double* gbar, double* grad, qtt_report* R);
 
+/* The C_eff returned by exactly `steps` updates of Alg. 2 for all V unit
+ * load cases (no stopping test; O->tol and O->max_iter are not used) and,
+ * if grad is not NULL, its exact derivative with respect to the phase Lame
+ * parameters (C0 fixed): the reverse mode of those updates (Sec. 2's
+ * fixed point, Alg. 2's update), the rounding of each update held fixed.
+ * It is the derivative of what a truncated solve returns, where
+ * ls_adjoint gives that of the converged fixed point.  Every `every`-th
+ * iterate is kept on the device (every = 0 or 1: all of them, nothing is
+ * recomputed); the reverse sweep recomputes the others from them with the
+ * forward pass's own sketches, one segment of `every` updates at a time. 
+ * Ceff: host [36] (plane problems: rows and columns 0..2).  gbar, grad:
+ * as in ls_adjoint ([V][V] cotangent or NULL; [2 nphase] or the Jacobian
+ * [V][V][2 nphase]).  R->iterations = steps, R->residual = the last
+ * update's relative change.  QTT_EINVAL: steps outside 1..100000,
+ * every < 0, or O->matvec other than QTT_MV_SKETCH. */
+int ls_unrolled(qtt_ctx* ctx, const qtt_problem* P, const qtt_solve_opts* O,
+                int steps, int every, const double* gbar, double* Ceff,
+                double* grad, qtt_report* R);
+/* ls_unrolled on a prepared problem (the operators are not rebuilt). */
+int ls_unrolled_prepared(qtt_ctx* ctx, const qtt_prepared* prep,
+                         const qtt_solve_opts* O, int steps, int every,
+                         const double* gbar, double* Ceff, double* grad,
+                         qtt_report* R);
+
 /* The strided batched complex FP64 GEMM that every core contraction of
  * the path runs on (the products of App. C and the factorisations of the
  * rounding, Sec. 3 around eq. rounding_condition_tt):

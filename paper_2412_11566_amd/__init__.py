@@ -27,7 +27,7 @@ __all__ = [
     "QttError", "Context", "Tensor", "SolveOptions", "SolveReport",
     "tt_from_cores", "const_strain", "sfft_build", "green_build", "from_voxels", "rank_estimate",
     "sfft_apply", "tt_hadamard", "green_apply", "amen_apply", "tt_round", "tt_norm", "tt_axpby",
-    "tt_mean_apply", "ls_solve", "ls_adjoint", "batch_solve", "Prepared", "prepare",
+    "tt_mean_apply", "ls_solve", "ls_adjoint", "ls_unrolled", "ls_unrolled_prepared", "batch_solve", "Prepared", "prepare",
     "ls_solve_prepared", "stats_enable", "stats_get", "stats_reset", "tensor_create",
     "tensor_wrap", "tensor_export", "NotConvergedWarning",
     "QTT_EXACT", "QTT_INVERSE", "QTT_NO_ROUND", "QTT_ORTH_AUTO", "QTT_ORTH_CHOLQR", "QTT_ORTH_HOUSEHOLDER",
@@ -648,6 +648,56 @@ def ls_adjoint_prepared(ctx: Context, prep: Prepared, opts: SolveOptions, eps: T
     return out, _report(rep)
 
 
+def _unrolled_out(rc_fn, V, nt, gbar, want_grad):
+    Ceff = np.zeros(36)
+    rep = _c.Report()
+    if not want_grad:
+        rc = rc_fn(None, _dp(Ceff), None, C.byref(rep))
+        out = None
+    elif gbar is None:
+        J = np.zeros(V * V * nt)
+        rc = rc_fn(None, _dp(Ceff), _dp(J), C.byref(rep))
+        out = J.reshape(V, V, nt)
+    else:
+        g = np.ascontiguousarray(gbar, dtype=np.float64).reshape(V * V)
+        out = np.zeros(nt)
+        rc = rc_fn(_dp(g), _dp(Ceff), _dp(out), C.byref(rep))
+    return rc, Ceff.reshape(6, 6)[:V, :V].copy(), out, rep
+
+
+def ls_unrolled(ctx: Context, phase, lame, lame0, opts: SolveOptions, steps: int, every: int = 0,
+                gbar=None, want_grad: bool = True, scheme="direct"):
+    """C_eff after exactly ``steps`` updates and its derivative with respect
+    to the phase Lame parameters (reverse mode of the updates, every
+    ``every``-th iterate kept, 0 or 1: all); returns (C_eff (V, V), Jacobian
+    (V, V, 2*nphase) or gradient (2*nphase,) for a cotangent ``gbar`` or
+    None without ``want_grad``, report)."""
+    p, keep = _problem(phase, lame, lame0, 0x3F, scheme)
+    o = opts.c()
+    V = 3 if p.dim == 2 else 6
+    nt = 2 * np.asarray(lame).shape[0]
+    rc, Cv, out, rep = _unrolled_out(
+        lambda g, Ce, gr, r: _c.lib().ls_unrolled(ctx.h, C.byref(p), C.byref(o), int(steps),
+                                                  int(every), g, Ce, gr, r), V, nt, gbar, want_grad)
+    ctx.check(rc)
+    del keep
+    return Cv, out, _report(rep)
+
+
+def ls_unrolled_prepared(ctx: Context, prep: Prepared, opts: SolveOptions, steps: int,
+                         every: int = 0, gbar=None, want_grad: bool = True):
+    """ls_unrolled on a prepared problem."""
+    o = opts.c()
+    V = 3 if getattr(prep, "dim", 3) == 2 else 6
+    nt = 2 * prep._keep[1].shape[0]
+    rc, Cv, out, rep = _unrolled_out(
+        lambda g, Ce, gr, r: _c.lib().ls_unrolled_prepared(ctx.h, prep.h, C.byref(o), int(steps),
+                                                           int(every), g, Ce, gr, r),
+        V, nt, gbar, want_grad)
+    ctx.check(rc)
+    return Cv, out, _report(rep)
+
+
 def _not_converged(what: str, rep: SolveReport, policy: str):
     if rep.status == QTT_OK or policy == "ignore":
         return
@@ -676,28 +726,39 @@ def _autograd_function():
         at max_iter is reported by ``policy``: "raise" (QttError),
         "warn" (NotConvergedWarning) or "ignore".  ``reports`` (a dict) receives
         the forward report under "forward" and the adjoint one under
-        "adjoint"."""
+        "adjoint".  ``unrolled`` = (steps, every) or None: then C_eff is that
+        of exactly ``steps`` updates and backward its exact derivative
+        (ls_unrolled_prepared)."""
 
         @staticmethod
-        def forward(actx, lame, phase, lame0, qctx, opts, policy, reports):
+        def forward(actx, lame, phase, lame0, qctx, opts, policy, reports, unrolled):
             lam = lame.detach().cpu().numpy().astype(np.float64)
             prep = prepare(qctx, phase, lam, lame0, opts.delta)
-            Ceff, rep, eps = ls_solve_prepared(qctx, prep, opts, keep_eps=True)
+            if unrolled is not None:
+                Ceff, _, rep = ls_unrolled_prepared(qctx, prep, opts, unrolled[0], unrolled[1],
+                                                    want_grad=False)
+                eps = None
+            else:
+                Ceff, rep, eps = ls_solve_prepared(qctx, prep, opts, keep_eps=True)
+                _not_converged("forward", rep, policy)
             reports["forward"] = rep
-            _not_converged("forward", rep, policy)
             actx.saved = (qctx, prep, opts, eps, lame.shape, lame.dtype, lame.device, policy,
-                          reports)
+                          reports, unrolled)
             return torch.as_tensor(Ceff, dtype=torch.float64, device=lame.device)
 
         @staticmethod
         def backward(actx, gC):
-            qctx, prep, opts, eps, shape, dtype, device, policy, reports = actx.saved
+            qctx, prep, opts, eps, shape, dtype, device, policy, reports, unrolled = actx.saved
             g = gC.detach().cpu().numpy().astype(np.float64)
-            grad, arep = ls_adjoint_prepared(qctx, prep, opts, eps, gbar=g)
+            if unrolled is not None:
+                _, grad, arep = ls_unrolled_prepared(qctx, prep, opts, unrolled[0], unrolled[1],
+                                                     gbar=g)
+            else:
+                grad, arep = ls_adjoint_prepared(qctx, prep, opts, eps, gbar=g)
+                _not_converged("adjoint", arep, policy)
             reports["adjoint"] = arep
-            _not_converged("adjoint", arep, policy)
             return (torch.as_tensor(grad.reshape(shape), dtype=dtype, device=device),
-                    None, None, None, None, None, None)
+                    None, None, None, None, None, None, None)
 
     return CeffFn
 
@@ -705,20 +766,24 @@ def _autograd_function():
 _CeffFn = None
 
 
-def ceff(lame, phase, lame0, ctx: Context, opts: SolveOptions, on_noconv: str = "raise"):
+def ceff(lame, phase, lame0, ctx: Context, opts: SolveOptions, on_noconv: str = "raise",
+         steps: int | None = None, every: int = 0):
     """Differentiable C_eff: ``ceff(lame_tensor, ...)`` returns a (6, 6)
     torch tensor ((3, 3) for plane strain) whose backward is the adjoint
     solve.  ``on_noconv``:
     "raise", "warn" or "ignore" when the forward or adjoint fixed point
     stops at max_iter.  The returned tensor carries ``qtt_reports``, a dict
     with the forward report ("forward") and, after backward, the adjoint
-    report ("adjoint")."""
+    report ("adjoint").  With ``steps``, C_eff is that of exactly ``steps``
+    updates and backward is its exact derivative (ls_unrolled, every
+    ``every``-th iterate kept); ``on_noconv`` does not apply then."""
     global _CeffFn
     if on_noconv not in ("raise", "warn", "ignore"):
         raise ValueError("on_noconv: 'raise', 'warn' or 'ignore'")
     if _CeffFn is None:
         _CeffFn = _autograd_function()
     reports = {"forward": None, "adjoint": None}
-    out = _CeffFn.apply(lame, phase, lame0, ctx, opts, on_noconv, reports)
+    unrolled = None if steps is None else (int(steps), int(every))
+    out = _CeffFn.apply(lame, phase, lame0, ctx, opts, on_noconv, reports, unrolled)
     out.qtt_reports = reports
     return out

@@ -118,6 +118,10 @@ SIGNATURES = {
     "qtt_zqr_noalloc": (I, [P, I, I, I, P, P, P]),
     "qtt_zorth": (I, [P, I, I, I, P, P, C.POINTER(C.c_int), I]),
     "ls_adjoint_prepared": (I, [P, P, C.POINTER(SolveOpts), P, DP, DP, C.POINTER(Report)]),
+    "ls_unrolled": (I, [P, C.POINTER(Problem), C.POINTER(SolveOpts), I, I, DP, DP, DP,
+                        C.POINTER(Report)]),
+    "ls_unrolled_prepared": (I, [P, P, C.POINTER(SolveOpts), I, I, DP, DP, DP,
+                                 C.POINTER(Report)]),
     "qtt_stats_enable": (I, [P, I]),
     "qtt_stats_get": (I, [P, I, C.POINTER(C.c_longlong), DP, DP, DP]),
     "qtt_stats_reset": (I, [P]),

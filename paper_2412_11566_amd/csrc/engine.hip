@@ -3433,11 +3433,12 @@ struct AdjOut {
   bool conv = true;
 };
 
-static AdjOut adj_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, const qtt_solve_opts* O,
-                       const std::vector<int>& ks) {
+// The stress fields C(x) e_k of the unit strains e_k, k in ks (batch
+// element b = ks[b]): (C - C0) e_k + C0 e_k, rounded at delta / cap.
+static TTP ce_trains(const Ctx& X, const Ops& ops, const qtt_problem* P, const qtt_solve_opts* O,
+                     const std::vector<int>& ks) {
   const int n = P->n, B = (int)ks.size();
   const int dim = P->dim == 2 ? 2 : 3, V = dim == 2 ? 3 : 6;
-  // C e_k trains: (C - C0) : E + C0 E
   std::vector<double> E((size_t)B * V, 0.0), C0E((size_t)B * V, 0.0);
   double C0m[36];
   host::iso_voigt_dim(V, P->lame0[0], P->lame0[1], C0m);
@@ -3452,6 +3453,14 @@ static AdjOut adj_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, const
   auto dE = op_apply(X, *ops.Cd, *Et, 0, so, nullptr);
   auto Ce = axpby(X, 1.0, *dE, 1.0, *C0t);
   round_tt(X, *Ce, O->delta, O->cap, nullptr);
+  return Ce;
+}
+
+static AdjOut adj_loop(const Ctx& X, const Ops& ops, const qtt_problem* P, const qtt_solve_opts* O,
+                       const std::vector<int>& ks) {
+  const int B = (int)ks.size();
+  // C e_k trains: (C - C0) : E + C0 E
+  auto Ce = ce_trains(X, ops, P, O, ks);
   std::vector<double> nCe = tt_norms(X, *Ce);
   AdjOut out;
   auto w = Ce;
@@ -3636,6 +3645,192 @@ int ls_adjoint_prepared(qtt_ctx* c, const qtt_prepared* pp, const qtt_solve_opts
   return adjoint_ops(c, pr.ops, &P, O, eps, gbar, grad, R, pr.seconds_setup);
 }
 
+
+// Derivative of the C_eff that exactly `steps` updates of Alg. 2 return
+// (no stopping test), by the reverse mode of those updates with the
+// rounding held fixed:
+//   eps_0 = E, eps_{m+1} = round(E - G (C - C0) eps_m),
+//   C_M[k][l] = < e_k . C eps^l_M >,
+//   a_M = C e_k, a_m = -(C - C0) G a_{m+1},
+//   dC_M[k][l]/dtheta = < e_k . dC eps^l_M > - sum_{m < M} < G a^k_{m+1}, dC eps^l_m >.
+// Every `every`-th iterate is kept (a checkpoint); the reverse sweep runs
+// segment by segment from the last, recomputing a segment's iterates from
+// its checkpoint with the sketches of the forward pass (seeds per update
+// and product; the saturation flag of each update is kept), so that the
+// recomputed iterates are the forward's.  The adjoint trains carry a sign
+// that flips per update: b_M = C e_k, b_m = (C - C0) G b_{m+1}, a_m =
+// (-1)^(M-m) b_m.
+static int unrolled_ops(qtt_ctx* c, const Ops& ops, const qtt_problem* P, const qtt_solve_opts* O,
+                        int steps, int every, const double* gbar, double* Ceff, double* grad,
+                        qtt_report* R, double seconds_setup) {
+  int status = QTT_OK;
+  auto body = [&]() {
+    check_problem(P, O);
+    if (steps < 1 || steps > 100000) throw std::invalid_argument("steps must be in 1..100000");
+    if (every < 0) throw std::invalid_argument("every must be >= 0 (0: keep every iterate)");
+    if (O->matvec != QTT_MV_SKETCH)
+      throw std::invalid_argument("the unrolled gradient takes QTT_MV_SKETCH products");
+    if (!Ceff) throw std::invalid_argument("null Ceff");
+    if (every == 0) every = 1;  // every iterate kept: nothing recomputed
+    if (every > steps) every = steps;
+    Ctx X{c};
+    const double t1 = now_s();
+    const int n = P->n, np = P->nphase, nt = 2 * np;
+    const int dim = P->dim == 2 ? 2 : 3, V = dim == 2 ? 3 : 6;
+    const double NN = std::pow(2.0, (double)dim * n);
+    const double normE = std::pow(2.0, 0.5 * dim * n);
+    std::vector<int> all_ks(V);
+    for (int k = 0; k < V; ++k) all_ks[k] = k;
+    std::vector<double> E((size_t)V * V, 0.0);
+    for (int k = 0; k < V; ++k) E[(size_t)k * V + k] = 1.0;
+    auto Et = const_strain(X, n, V, E.data(), V, dim);
+    const unsigned long long base = O->seed * 1000003ULL + 0x5eedULL * 0x100000000ULL;
+    // one update with the sketches of update m (product j: seed base + 8 m + j)
+    std::vector<char> sat_at(steps, 0);
+    auto opts_at = [&](int m, int j, bool inter) {
+      SketchOpts so = inter ? ski(X, O) : sk(X, O);
+      so.seed = base + 8ULL * (unsigned long long)m + (unsigned long long)j;
+      return satur(so, sat_at[m] != 0);
+    };
+    auto update = [&](const TTP& eps, int m, RoundStats* st) {
+      auto tau = op_apply(X, *ops.Cd, *eps, 0, opts_at(m, 0, true), st);
+      auto th = op_apply(X, *ops.S, *tau, 0, opts_at(m, 1, true), st);
+      auto eh = op_apply(X, *ops.G, *th, 0, opts_at(m, 2, true), st);
+      auto y = op_apply(X, *ops.S->adj, *eh, 0, opts_at(m, 3, true), st);
+      return round_any(X, axpby(X, 1.0, *Et, -1.0, *y), opts_at(m, 4, false), st);
+    };
+    // forward pass, checkpoints at m = 0, every, 2 every, ...
+    std::vector<TTP> ck;
+    TTP eps = Et;
+    double last_disc = 0.0;
+    int max_rank = 1;
+    double disc = 0.0;
+    std::vector<double> last_res(V, 0.0);
+    for (int m = 0; m < steps; ++m) {
+      if (m % every == 0) ck.push_back(eps);
+      sat_at[m] = saturated(*eps, O->cap, last_disc) ? 1 : 0;
+      RoundStats st;
+      auto nw = update(eps, m, &st);
+      last_disc = st.rel_max();
+      disc = std::max(disc, last_disc);
+      for (int k = 1; k < nw->L; ++k) max_rank = std::max(max_rank, nw->r[k]);
+      if (m == steps - 1) {
+        auto dn = tt_norms(X, *axpby(X, 1.0, *nw, -1.0, *eps));
+        for (int k = 0; k < V; ++k) {
+          last_res[k] = dn[k] / normE;
+          if (!std::isfinite(last_res[k])) throw nan_error("NaN/Inf in the unrolled iterate");
+        }
+      }
+      eps = nw;
+    }
+    for (int i = 0; i < 36; ++i) Ceff[i] = 0.0;
+    {
+      SolveOut so;
+      so.ks = all_ks;
+      so.eps = eps;
+      ceff_from(X, ops, P, so, Ceff);
+    }
+    if (grad) {
+      std::vector<double> J((size_t)V * V * nt, 0.0);
+      double Dl[36], Dm[36];
+      host::iso_voigt_dim(V, 1.0, 0.0, Dl);
+      host::iso_voigt_dim(V, 0.0, 1.0, Dm);
+      std::vector<TTP> dCs(nt);
+      for (int task = 0; task < nt; ++task)
+        dCs[task] = dC_op(X, ops.chi, task / 2, task % 2 == 0 ? Dl : Dm, V);
+      // explicit term at the last iterate: < e_k . dC eps^l_M >
+      for (int task = 0; task < nt; ++task) {
+        auto v = op_apply(X, *dCs[task], *eps, 0, sk(X, O), nullptr);
+        auto first = mean_apply(X, *ops.I, *v);
+        for (int k = 0; k < V; ++k)
+          for (int l = 0; l < V; ++l)
+            J[((size_t)k * V + l) * nt + task] += first[(size_t)l * V + k].real();
+      }
+      auto b = ce_trains(X, ops, P, O, all_ks);
+      double sgn = 1.0;
+      const int nseg = (steps + every - 1) / every;
+      for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int m0 = sg * every, m1 = std::min(steps, m0 + every);
+        std::vector<TTP> seg(m1 - m0);
+        seg[0] = ck[sg];
+        for (int m = m0; m + 1 < m1; ++m) seg[m - m0 + 1] = update(seg[m - m0], m, nullptr);
+        for (int m = m1 - 1; m >= m0; --m) {
+          // g = G b_{m+1}
+          auto g = op_apply(X, *ops.S, *b, 0, ski(X, O), nullptr);
+          g = op_apply(X, *ops.G, *g, 0, ski(X, O), nullptr);
+          g = op_apply(X, *ops.S->adj, *g, 0, sk(X, O), nullptr);
+          for (int task = 0; task < nt; ++task) {
+            auto v = op_apply(X, *dCs[task], *seg[m - m0], 0, sk(X, O), nullptr);
+            auto gram = tt_gram(X, *g, *v);   // [k][l] sum conj(G b_k) dC eps_l
+            for (int k = 0; k < V; ++k)
+              for (int l = 0; l < V; ++l)
+                J[((size_t)k * V + l) * nt + task] -= sgn * gram[(size_t)k * V + l].real() / NN;
+          }
+          if (m > 0) {
+            b = op_apply(X, *ops.Cd, *g, 0, sk(X, O), nullptr);
+            sgn = -sgn;
+          }
+        }
+      }
+      if (gbar) {
+        for (int t = 0; t < nt; ++t) {
+          double sum = 0.0;
+          for (int i = 0; i < V * V; ++i) sum += gbar[i] * J[(size_t)i * nt + t];
+          grad[t] = sum;
+        }
+      } else {
+        std::memcpy(grad, J.data(), J.size() * sizeof(double));
+      }
+    }
+    X.sync();
+    const double t2 = now_s();
+    if (R) {
+      std::memset(R, 0, sizeof(*R));
+      for (int k = 0; k < V; ++k) {
+        R->iterations[k] = steps;
+        R->residual[k] = last_res[k];
+      }
+      R->max_rank = max_rank;
+      R->discarded = disc;
+      R->seconds_setup = seconds_setup;
+      R->seconds_solve = t2 - t1;
+    }
+  };
+  int rc = [&]() -> int { QTT_TRY(c, body()); }();
+  if (rc == QTT_OK) rc = status;
+  if (R) R->status = rc;
+  return rc;
+}
+
+int ls_unrolled(qtt_ctx* c, const qtt_problem* P, const qtt_solve_opts* O, int steps, int every,
+                const double* gbar, double* Ceff, double* grad, qtt_report* R) {
+  if (!c || !P || !O || !Ceff) return QTT_EINVAL;
+  Ops ops;
+  double setup = 0.0;
+  int rc = [&]() -> int {
+    QTT_TRY(c, {
+      check_problem(P, O);
+      Ctx X{c};
+      const double t0 = now_s();
+      ops = build_ops(X, P, O->delta);
+      X.sync();
+      setup = now_s() - t0;
+    });
+  }();
+  if (rc != QTT_OK) {
+    if (R) R->status = rc;
+    return rc;
+  }
+  return unrolled_ops(c, ops, P, O, steps, every, gbar, Ceff, grad, R, setup);
+}
+
+int ls_unrolled_prepared(qtt_ctx* c, const qtt_prepared* pp, const qtt_solve_opts* O, int steps,
+                         int every, const double* gbar, double* Ceff, double* grad, qtt_report* R) {
+  if (!c || !pp || !O || !Ceff) return QTT_EINVAL;
+  const Prepared& pr = pp->p;
+  qtt_problem P = pr.problem();
+  return unrolled_ops(c, pr.ops, &P, O, steps, every, gbar, Ceff, grad, R, pr.seconds_setup);
+}
 
 // structures per batched group: bounds the GEMM batch (6 * group * rank *
 // dim must stay under the 65535 grid limit at rank 80)
