@@ -96,9 +96,8 @@ __device__ __forceinline__ double rl(double v, int src) {
 // of a row.  The pivot comes from lane (P % 4, P) as a scalar (readlane);
 // row P reaches the lanes of each 16-lane row by a DPP row broadcast from
 // its lane P, which holds exactly that row's columns; the multipliers G[i][P]
-// (column P, held by the lanes of group P % 4) pass through a 16-entry LDS
-// buffer, alternating between two buffers so that one wave sync per step
-// orders them.  All rows and columns beyond P are updated (both triangles:
+// (column P, held by the lanes of group P % 4) reach every group by a lane
+// permute.  All rows and columns beyond P are updated (both triangles:
 // the lower one holds the multipliers of the later steps); row P becomes row
 // P of R.
 template <int P>
@@ -113,14 +112,11 @@ struct CqStep {
     bad = bad || (drop ? d != d : !ok);
     const double r = ok ? dev::rsq_nt(d) : (drop ? 0.0 : 1.0);
     rd[P] = r;
-    double* buf = mc + (P & 1) * 32;
-    if (g == gp) {
-      buf[2 * i] = a[tp].x;
-      buf[2 * i + 1] = a[tp].y;
-    }
-    wave_sync();
+    (void)mc;
+    // G[i][P] from lane (P % 4, i) by a lane permute (no LDS round trip)
+    const double gx = __shfl(a[tp].x, 16 * gp + i, 64), gy = __shfl(a[tp].y, 16 * gp + i, 64);
     const double r2 = i > P ? r * r : 0.0;
-    const cplx f = make_double2(buf[2 * i] * r2, buf[2 * i + 1] * r2);  // G[i][P] / d below P, else 0
+    const cplx f = make_double2(gx * r2, gy * r2);  // G[i][P] / d below P, else 0
     const double sc = i == P ? r : 1.0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -540,8 +536,48 @@ __global__ __launch_bounds__(CQ_WAVES * 64) void k_chol_inv(int n, const cplx* G
   const int lc = lane & 15, lg = lane >> 4;
   if (pass == 1 && flag[b] != 0) return;
   if (tid == 0) s_fail = 0;
+  // the partial Grams summed in slice order; each thread's EPT elements are
+  // loaded together per slice (two slices per round), so the dependent
+  // chain is one load round trip per two slices, not one per element and
+  // slice
+  constexpr int NE = NT * 256, EPT = (NE + CQ_WAVES * 64 - 1) / (CQ_WAVES * 64);
+  double ar[EPT], ai[EPT];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) ar[u] = ai[u] = 0.0;
+  {
+    const cplx* gb = Gp + (long)b * nparts * NE;
+    int p = 0;
+    for (; p + 2 <= nparts; p += 2) {
+      cplx v0[EPT], v1[EPT];
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        const int e = tid + u * CQ_WAVES * 64;
+        v0[u] = e < NE ? gb[(long)p * NE + e] : make_double2(0.0, 0.0);
+        v1[u] = e < NE ? gb[(long)(p + 1) * NE + e] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        ar[u] += v0[u].x;
+        ai[u] += v0[u].y;
+        ar[u] += v1[u].x;
+        ai[u] += v1[u].y;
+      }
+    }
+    if (p < nparts) {
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) {
+        const int e = tid + u * CQ_WAVES * 64;
+        const cplx v = e < NE ? gb[(long)p * NE + e] : make_double2(0.0, 0.0);
+        ar[u] += v.x;
+        ai[u] += v.y;
+      }
+    }
+  }
   double e2 = 0.0;
-  for (int e = tid; e < NT * 256; e += CQ_WAVES * 64) {
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = tid + u * CQ_WAVES * 64;
+    if (e >= NE) break;
     const int t = e >> 8, q = e & 255;
     int I = 0, tt = t;
     while (tt >= NB - I) {
@@ -549,12 +585,7 @@ __global__ __launch_bounds__(CQ_WAVES * 64) void k_chol_inv(int n, const cplx* G
       ++I;
     }
     const int J = I + tt;
-    double vr = 0.0, vi = 0.0;
-    for (int p = 0; p < nparts; ++p) {
-      const cplx v = Gp[(((long)b * nparts + p) * NT + t) * 256 + q];
-      vr += v.x;
-      vi += v.y;
-    }
+    double vr = ar[u], vi = ai[u];
     const int gi = 16 * I + (q >> 4), gj = 16 * J + (q & 15);
     if (gi >= n || gj >= n || (drop && pass == 1 && gi == gj && vr == 0.0)) {
       vr = gi == gj ? 1.0 : 0.0;

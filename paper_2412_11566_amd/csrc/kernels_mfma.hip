@@ -594,9 +594,25 @@ __global__ __launch_bounds__(256) void k_zgemm_reduce(GemmArgs g, int ksplit) {
   for (long e = blockIdx.x * 256L + threadIdx.x; e < total; e += (long)gridDim.x * 256L) {
     const long bz = e / mn, r = e % mn;
     const int m = (int)(r / g.N), n = (int)(r % g.N);
+    // partials summed in split order; four loads in flight per round
     double sx = 0.0, sy = 0.0;
-    for (int s = 0; s < ksplit; ++s) {
-      const cplx p = g.ws[((long)s * nb + bz) * mn + r];
+    const cplx* wp = g.ws + bz * mn + r;
+    const long step = nb * mn;
+    int s = 0;
+    for (; s + 4 <= ksplit; s += 4) {
+      const cplx p0 = wp[(long)s * step], p1 = wp[(long)(s + 1) * step];
+      const cplx p2 = wp[(long)(s + 2) * step], p3 = wp[(long)(s + 3) * step];
+      sx += p0.x;
+      sy += p0.y;
+      sx += p1.x;
+      sy += p1.y;
+      sx += p2.x;
+      sy += p2.y;
+      sx += p3.x;
+      sy += p3.y;
+    }
+    for (; s < ksplit; ++s) {
+      const cplx p = wp[(long)s * step];
       sx += p.x;
       sy += p.y;
     }
