@@ -1349,31 +1349,109 @@ bool try_qr_rows(int batch, int m, int n, const MatView& A, const MatOut& R, con
 constexpr int JNT = 1024;
 constexpr int JMAXN = 96;
 
+typedef double jdv4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ jdv4 jmf(double a, double b, jdv4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Whether any column pair of the n x n column-major LDS matrix W (column
+// stride ld) still needs a rotation: |x_a^H x_b|^2 > tol^2 |x_a|^2 |x_b|^2
+// with both norms above 1e-300, the test of the rotation loop, for all
+// pairs at once.  The Gram blocks (I <= J) come from the matrix cores, one
+// 16 x 16 block per wave at a time, three real products per complex K-step
+// of 4 rows.  A sweep that would find no such pair changes nothing, so this
+// replaces the last, rotation-free sweep (79 rounds at n = 80, each
+// streaming the whole matrix through LDS) by one pass over it.  Every wave
+// must call it.
+__device__ __forceinline__ bool jac_pairs_left(int n, int ld, const cplx* Wl, const double* nrm2,
+                                               double tol) {
+  const int tid = threadIdx.x, lane = tid & 63, lc = lane & 15, lg = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nb = (n + 15) >> 4, nt = nb * (nb + 1) / 2;
+  bool hit = false;
+  for (int t = w; t < nt; t += JNT / 64) {
+    int I = 0, tt = t;
+    while (tt >= nb - I) {
+      tt -= nb - I;
+      ++I;
+    }
+    const int J = I + tt;
+    const int cI = 16 * I + lc, cJ = 16 * J + lc;
+    jdv4 p1 = {0.0, 0.0, 0.0, 0.0}, p2 = p1, p3 = p1;
+    for (int k0 = 0; k0 < n; k0 += 4) {
+      const int row = k0 + lg;
+      const cplx a = (row < n && cI < n) ? Wl[cI * ld + row] : make_double2(0.0, 0.0);
+      const cplx c = (row < n && cJ < n) ? Wl[cJ * ld + row] : make_double2(0.0, 0.0);
+      p1 = jmf(a.x, c.x, p1);
+      p2 = jmf(-a.y, c.y, p2);
+      p3 = jmf(a.x - a.y, c.x + c.y, p3);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ca = 16 * I + 4 * r + lg, cb = 16 * J + lc;
+      if (ca < cb && cb < n) {
+        const double gr = p1[r] - p2[r], gi = p3[r] - p1[r] - p2[r];
+        const double al = nrm2[ca], be = nrm2[cb];
+        if (gr * gr + gi * gi > tol * tol * (al * be) && al >= 1e-300 && be >= 1e-300) hit = true;
+      }
+    }
+  }
+  return hit;
+}
+
 __global__ __launch_bounds__(JNT) void k_jacobi_lds(int n, MatView A, MatOut U, double* S) {
-  extern __shared__ cplx Wl[];  // n x n, column-major
+  // n x n, column-major with column stride n + 1: the check of all pairs
+  // reads 16 columns at one row per lane group, which a stride of n would
+  // put in one LDS bank (n = 80: 1280 B)
+  extern __shared__ cplx Wl[];
   __shared__ double nrm2[JMAXN];
   __shared__ double sig[JMAXN];
   __shared__ int rankpos[JMAXN];
   __shared__ int rotated;
+  __shared__ int pairs_left;
+  __shared__ int wrot[JNT / 64];  // rotations of the last sweep per wave
   const int b = blockIdx.x, tid = threadIdx.x;
   const int g = tid >> 4, sub = tid & 15;  // 64 groups of 16 lanes
   constexpr int NG = JNT / 16;
+  const int ld = n + 1;
   for (int e = tid; e < n * n; e += JNT) {
     const int i = e % n, j = e / n;
-    Wl[e] = ldv(A, b, i, j);
+    Wl[j * ld + i] = ldv(A, b, i, j);
   }
   __syncthreads();
+  int myrot = 0;  // rotations of this lane's pairs in the current sweep
   const int npad = n + (n & 1);
   const int npairs = npad / 2;
   const double tol = 8.0 * 2.220446049250313e-16 * sqrt((double)n);
   for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
     for (int c = tid; c < n; c += JNT) {
       double s = 0.0;
-      for (int i = 0; i < n; ++i) s += cabs2(Wl[c * n + i]);
+      for (int i = 0; i < n; ++i) s += cabs2(Wl[c * ld + i]);
       nrm2[c] = s;
     }
-    if (tid == 0) rotated = 0;
+    {
+      int cnt = myrot;
+      myrot = 0;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+      if ((tid & 63) == 0) wrot[tid >> 6] = cnt;
+    }
+    if (tid == 0) {
+      rotated = 0;
+      pairs_left = 0;
+    }
     __syncthreads();
+    int last_rot = 0;
+#pragma unroll
+    for (int i = 0; i < JNT / 64; ++i) last_rot += wrot[i];
+    // once a sweep rotated at most n^2 / 8 pairs (a quarter of them:
+    // convergence is near), all pairs are tested at once before the next: a
+    // sweep that would find none to rotate is not run
+    if (sweep > 0 && 8 * last_rot <= n * n) {
+      if (jac_pairs_left(n, ld, Wl, nrm2, tol)) pairs_left = 1;
+      __syncthreads();
+      if (!pairs_left) break;
+    }
     for (int r = 0; r < npad - 1; ++r) {
       for (int p = g; p < npairs; p += NG) {
         const int pa = p, pb = npad - 1 - p;
@@ -1381,8 +1459,8 @@ __global__ __launch_bounds__(JNT) void k_jacobi_lds(int n, MatView A, MatOut U, 
         int cb = ((pb - 1 + r) % (npad - 1)) + 1;
         if (ca >= n || cb >= n) continue;
         if (ca > cb) { const int t = ca; ca = cb; cb = t; }
-        cplx* xa = Wl + ca * n;
-        cplx* xb = Wl + cb * n;
+        cplx* xa = Wl + ca * ld;
+        cplx* xb = Wl + cb * ld;
         // the pair's rows of this lane in registers: one LDS round trip for
         // the loads, the rotation writes back from them
         constexpr int JR = (JMAXN + 15) / 16;
@@ -1433,6 +1511,7 @@ __global__ __launch_bounds__(JNT) void k_jacobi_lds(int n, MatView A, MatOut U, 
           nrm2[ca] = al - t * gg;
           nrm2[cb] = be + t * gg;
           rotated = 1;
+          ++myrot;
         }
       }
       __syncthreads();
@@ -1442,7 +1521,7 @@ __global__ __launch_bounds__(JNT) void k_jacobi_lds(int n, MatView A, MatOut U, 
   }
   for (int c = tid; c < n; c += JNT) {
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += cabs2(Wl[c * n + i]);
+    for (int i = 0; i < n; ++i) s += cabs2(Wl[c * ld + i]);
     sig[c] = sqrt(s);
   }
   __syncthreads();
@@ -1460,7 +1539,7 @@ __global__ __launch_bounds__(JNT) void k_jacobi_lds(int n, MatView A, MatOut U, 
   for (int e = tid; e < n * n; e += JNT) {
     const int i = e / n, j = e % n;
     const double sj = sig[j];
-    cplx u = Wl[j * n + i];
+    cplx u = Wl[j * ld + i];
     if (sj > 0.0) { u.x /= sj; u.y /= sj; }
     else u = make_double2(0.0, 0.0);
     U.base[b * U.sb + (long)i * U.rs + (long)rankpos[j] * U.cs] = u;
@@ -1718,12 +1797,12 @@ bool jacobi_square(int batch, int n, MatView A, MatOut U, double* S, hipStream_t
   // load-case groups of a solve launch from several host threads)
   static const bool attr = [&]() {
     check(hipFuncSetAttribute((const void*)k_jacobi_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              JMAXN * JMAXN * (int)sizeof(cplx)),
+                              JMAXN * (JMAXN + 1) * (int)sizeof(cplx)),
           "jacobi lds attribute");
     return true;
   }();
   (void)attr;
-  const size_t shm = (size_t)n * n * sizeof(cplx);
+  const size_t shm = (size_t)n * (n + 1) * sizeof(cplx);
   hipLaunchKernelGGL(k_jacobi_lds, dim3(batch), dim3(JNT), shm, s, n, A, U, S);
   check(hipGetLastError(), "jacobi_lds launch");
   return true;
