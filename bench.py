@@ -47,8 +47,8 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 matrix (dense)
 # kernel sources are the ones that were measured
 # (profiles/qr_family_256_fibres_hbm_counters.md).
 MEASURED_TRAFFIC = {
-    ("qr", 3): {"bytes_per_launch": 1.856e6,
-                "sources": {"paper_2412_11566_amd/csrc/kernels_fact.hip": "a21946655c633bd888ed6c0f5de687b71afd4da1af9727d3135a9f64376e7ed5",
+    ("qr", 3): {"bytes_per_launch": 1.857e6,
+                "sources": {"paper_2412_11566_amd/csrc/kernels_fact.hip": "0cd7de3a2e7eb6850db6e6e814f6a6df2f63c2ed4d935c79e97d40bc5fba4474",
                             "paper_2412_11566_amd/csrc/kernels_qr_blk.hip": "b1c5622f451c62339712078db1a68a59894a8739c06eafdb20a5afdf7fbc3c19",
                             "paper_2412_11566_amd/csrc/kernels_cholqr.hip": "e9b73b176f60e511befc387809ded9fafccfd577714eeea725d63906a66edfde"}},
 }
