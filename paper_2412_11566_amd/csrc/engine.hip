@@ -3663,7 +3663,6 @@ int ls_adjoint_prepared(qtt_ctx* c, const qtt_prepared* pp, const qtt_solve_opts
 static int unrolled_ops(qtt_ctx* c, const Ops& ops, const qtt_problem* P, const qtt_solve_opts* O,
                         int steps, int every, const double* gbar, double* Ceff, double* grad,
                         qtt_report* R, double seconds_setup) {
-  int status = QTT_OK;
   auto body = [&]() {
     check_problem(P, O);
     if (steps < 1 || steps > 100000) throw std::invalid_argument("steps must be in 1..100000");
@@ -3796,8 +3795,7 @@ static int unrolled_ops(qtt_ctx* c, const Ops& ops, const qtt_problem* P, const 
       R->seconds_solve = t2 - t1;
     }
   };
-  int rc = [&]() -> int { QTT_TRY(c, body()); }();
-  if (rc == QTT_OK) rc = status;
+  const int rc = [&]() -> int { QTT_TRY(c, body()); }();
   if (R) R->status = rc;
   return rc;
 }
