@@ -143,14 +143,15 @@ def test_plane_batch_matches_single(ctx):
     assert rel(Cb[3], C3) < 1e-10
 
 
-@pytest.mark.parametrize("n", [10, 11])
-def test_plane_laminate_large_grids(ctx, n):
+@pytest.mark.parametrize("n,scheme", [(10, "direct"), (11, "direct"), (10, "staggered")])
+def test_plane_laminate_large_grids(ctx, n, scheme):
     """The largest plane grids (1024^2 and 2048^2: the n >= 10 SFFT and
-    Green builds): a laminate, whose strain stays low-rank, after 3 updates
-    at delta 1e-8 against the dense plane-strain scheme after 3 updates."""
+    Green builds of both schemes): a laminate, whose strain stays low-rank,
+    after 3 updates at delta 1e-8 against the dense plane-strain scheme
+    after 3 updates."""
     ph, lame, l0 = _suite("laminate", n)
     opts = q.SolveOptions(delta=1e-8, tol=0.0, cap=128, max_iter=3)
-    C, rep, _ = q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7)
-    Cref, _ = P2.effective_stiffness2(ph, lame, l0, tol=0.0, fixed_iters=3)
+    C, rep, _ = q.ls_solve(ctx, ph, lame, l0, opts, load_mask=0x7, scheme=scheme)
+    Cref, _ = P2.effective_stiffness2(ph, lame, l0, tol=0.0, fixed_iters=3, scheme=scheme)
     assert rep.iterations[:3] == [3, 3, 3]
     assert rel(C, Cref) < 1e-6
