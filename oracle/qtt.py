@@ -303,10 +303,12 @@ def stiffness_tto(phase: np.ndarray, lame, lame0, delta: float, cap: int = 1 << 
 
 def coarsen_majority(phase: np.ndarray, nphase: int) -> np.ndarray:
     """The geometry one discretisation order lower: the majority phase of
-    every 2 x 2 x 2 block of voxels, ties to the lowest phase id."""
-    N = phase.shape[0]
-    h = N // 2
-    blocks = phase.reshape(h, 2, h, 2, h, 2).transpose(0, 2, 4, 1, 3, 5).reshape(h, h, h, 8)
+    every 2 x 2 x 2 block of voxels (2 x 2 block of pixels for a plane
+    geometry), ties to the lowest phase id."""
+    d = phase.ndim
+    h = phase.shape[0] // 2
+    blocks = phase.reshape((h, 2) * d).transpose(tuple(range(0, 2 * d, 2)) + tuple(range(1, 2 * d, 2)))
+    blocks = blocks.reshape((h,) * d + (2 ** d,))
     counts = np.stack([(blocks == p).sum(axis=-1) for p in range(nphase)], axis=-1)
     return np.argmax(counts, axis=-1).astype(np.uint8)     # argmax: first maximum
 
@@ -315,7 +317,8 @@ def rank_estimate(phase: np.ndarray, nphase: int, delta: float):
     """Applicability estimate from two discretisation orders (Sec. 5.2):
     the largest bond rank of the one-hot phase train (TT-SVD at delta) of
     the coarsened geometry (order n - 1) and of the geometry (order n), and
-    their ratio."""
+    their ratio; 3D voxels or plane pixels (the bits of x, then y, then z,
+    most significant first)."""
     def top(ph):
         oh = np.stack([(ph == p).astype(np.float64) for p in range(nphase)])
         n3 = int(round(math.log2(ph.size)))

@@ -48,3 +48,32 @@ def test_random_phases_reach_the_structural_rank():
     rc, rf, _ = Q.rank_estimate(ph, 2, 1e-12)
     assert rf == max(min(2 ** k + 1, 2 ** (9 - k)) for k in range(1, 9))
     assert rc <= max(min(2 ** k + 1, 2 ** (6 - k)) for k in range(1, 6))
+
+
+def test_majority_coarsening_brute_force_plane():
+    rng = np.random.default_rng(14)
+    ph = rng.integers(0, 3, (16, 16)).astype(np.uint8)
+    c = Q.coarsen_majority(ph, 3)
+    assert c.shape == (8, 8)
+    for x in range(8):
+        for y in range(8):
+            cnt = np.bincount(ph[2 * x:2 * x + 2, 2 * y:2 * y + 2].ravel(), minlength=3)
+            assert c[x, y] == int(np.flatnonzero(cnt == cnt.max())[0])   # ties: lowest id
+
+
+def test_plane_estimate_structural_facts():
+    """Plane geometries: an upsampled geometry keeps its rank, a laminate
+    stays at rank 2, and independent random pixels reach the structural
+    rank min(2^k + 1, 2^(2n - k))."""
+    rng = np.random.default_rng(15)
+    base = (rng.uniform(size=(16, 16)) < 0.3).astype(np.uint8)
+    up = base.repeat(2, 0).repeat(2, 1)
+    assert np.array_equal(Q.coarsen_majority(up, 2), base)
+    rc, rf, g = Q.rank_estimate(up, 2, 1e-10)
+    assert rc == rf and g == 1.0
+    lam = M.geometry("laminate", 32, 2)
+    assert Q.rank_estimate(lam, 2, 1e-10) == (2, 2, 1.0)
+    ph = rng.integers(0, 2, (16, 16)).astype(np.uint8)
+    rc, rf, _ = Q.rank_estimate(ph, 2, 1e-12)
+    assert rf == max(min(2 ** k + 1, 2 ** (8 - k)) for k in range(1, 8))
+    assert rc <= max(min(2 ** k + 1, 2 ** (6 - k)) for k in range(1, 6))
