@@ -316,6 +316,14 @@ int qtt_green_build_scheme(qtt_ctx* ctx, int n, double lam0, double mu0,
 int qtt_rank_estimate(qtt_ctx* ctx, const uint8_t* phase, int phase_on_device,
                       int n, int nphase, double delta, int* ranks,
                       double* growth);
+/* qtt_rank_estimate for a grid of dimension `dim`: 3 as above, or 2 for a
+ * plane geometry (N^2 pixels, C order, x slowest, 2 <= n <= 12; the
+ * coarsened copy takes the majority phase of every 2 x 2 block).  Same
+ * outputs and codes; QTT_EINVAL for another `dim`. */
+int qtt_rank_estimate_dim(qtt_ctx* ctx, const uint8_t* phase,
+                          int phase_on_device, int n, int nphase,
+                          double delta, int dim, int* ranks,
+                          double* growth);
 
 int qtt_from_voxels(qtt_ctx* ctx, const uint8_t* phase, int phase_on_device,
                     int n, int nphase, const double* lame,

@@ -246,15 +246,14 @@ def from_voxels(ctx: Context, phase, lame, lame0, delta: float, cap: int = 0):
 
 def rank_estimate(ctx: Context, phase, nphase: int, delta: float):
     """Largest one-hot bond rank of the geometry at its order n and at
-    order n - 1 (2 x 2 x 2 majority coarsening), and their ratio; ``phase``
-    is a host array or a torch uint8 device tensor."""
+    order n - 1 (2 x 2 x 2 majority coarsening of a cubic voxel array, 2 x 2
+    of a square pixel array), and their ratio; ``phase`` is a host array or
+    a torch uint8 device tensor."""
     p, keep = _problem(phase, np.zeros((nphase, 2)), (1.0, 1.0), 0)
-    if p.dim != 3:
-        raise ValueError("rank_estimate: a cubic (N, N, N) voxel array")
     r = (C.c_int * 2)()
     g = C.c_double(0.0)
-    ctx.check(_c.lib().qtt_rank_estimate(ctx.h, p.phase, p.phase_on_device, p.n, nphase, delta,
-                                         C.cast(r, C.POINTER(C.c_int)), C.byref(g)))
+    ctx.check(_c.lib().qtt_rank_estimate_dim(ctx.h, p.phase, p.phase_on_device, p.n, nphase, delta,
+                                             p.dim, C.cast(r, C.POINTER(C.c_int)), C.byref(g)))
     del keep
     return int(r[0]), int(r[1]), g.value
 

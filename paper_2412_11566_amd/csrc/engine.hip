@@ -2846,10 +2846,17 @@ int qtt_green_build_scheme(qtt_ctx* c, int n, double lam0, double mu0, double de
 
 int qtt_rank_estimate(qtt_ctx* c, const uint8_t* phase, int phase_on_device, int n, int nphase, double delta,
                       int* ranks, double* growth) {
-  if (!c || !phase || !ranks || n < 2 || n > 8 || nphase < 1 || nphase > 16 || !(delta > 0)) return QTT_EINVAL;
+  return qtt_rank_estimate_dim(c, phase, phase_on_device, n, nphase, delta, 3, ranks, growth);
+}
+
+int qtt_rank_estimate_dim(qtt_ctx* c, const uint8_t* phase, int phase_on_device, int n, int nphase,
+                          double delta, int dim, int* ranks, double* growth) {
+  if (!c || !phase || !ranks || (dim != 2 && dim != 3) || n < 2 || n > (dim == 2 ? 12 : 8) || nphase < 1 ||
+      nphase > 16 || !(delta > 0))
+    return QTT_EINVAL;
   QTT_TRY(c, {
     Ctx X{c};
-    const long NN = 1L << (3 * n);
+    const long NN = 1L << (dim * n);
     const uint8_t* dph = phase;
     BufP phb;
     if (!phase_on_device) {
@@ -2857,9 +2864,10 @@ int qtt_rank_estimate(qtt_ctx* c, const uint8_t* phase, int phase_on_device, int
       check(hipMemcpyAsync(phb->p, phase, NN, hipMemcpyHostToDevice, X.s()), "phase h2d");
       dph = (const uint8_t*)phb->p;
     }
-    auto cb = X.buf((size_t)(NN / 8 + 15) / 16);
-    need(X, cb->p, (long)((NN / 8 + 15) / 16) - 1, "coarse out");
-    coarsen_majority(dph, n, nphase, (uint8_t*)cb->p, X.s());
+    const long NC = NN >> dim;  // pixels or voxels one order lower
+    auto cb = X.buf((size_t)(NC + 15) / 16);
+    need(X, cb->p, (long)((NC + 15) / 16) - 1, "coarse out");
+    coarsen_majority(dph, n, nphase, (uint8_t*)cb->p, X.s(), dim);
     host::HTT fine, coarse;
     // the device TT-SVD, or the host one where a bond exceeds its 160
     auto chi_of = [&](const uint8_t* d, int bits, host::HTT& out) {
@@ -2876,8 +2884,8 @@ int qtt_rank_estimate(qtt_ctx* c, const uint8_t* phase, int phase_on_device, int
       dims[0] = nphase;
       out = host::tt_svd_real(oh, dims, delta, 0);
     };
-    chi_of(dph, 3 * n, fine);
-    chi_of((const uint8_t*)cb->p, 3 * (n - 1), coarse);
+    chi_of(dph, dim * n, fine);
+    chi_of((const uint8_t*)cb->p, dim * (n - 1), coarse);
     int rc = 1, rf = 1;
     for (const auto& h : coarse) rc = std::max(rc, h.r1);
     for (const auto& h : fine) rf = std::max(rf, h.r1);

@@ -812,9 +812,37 @@ __global__ void k_coarsen_majority(const uint8_t* __restrict__ phase, int n, int
   out[e] = (uint8_t)best;
 }
 
-void coarsen_majority(const uint8_t* phase, int n, int nphase, uint8_t* out, hipStream_t s) {
-  const long M = 1L << (3 * (n - 1));
-  hipLaunchKernelGGL(k_coarsen_majority, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, phase, n, nphase, out);
+// The same on an N x N pixel grid (plane geometries): 2 x 2 blocks.
+__global__ void k_coarsen_majority2d(const uint8_t* __restrict__ phase, int n, int nphase,
+                                     uint8_t* __restrict__ out) {
+  const int h = n - 1, H = 1 << h, N = 1 << n;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (1L << (2 * h))) return;
+  const int x = (int)(e >> h), y = (int)(e & (H - 1));
+  int cnt[16];
+#pragma unroll
+  for (int p = 0; p < 16; ++p) cnt[p] = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const long f = (long)(2 * x + (c >> 1)) * N + (2 * y + (c & 1));
+    const int p = phase[f];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cnt[q] += (q == (p < nphase ? p : 0));
+  }
+  int best = 0;
+#pragma unroll
+  for (int q = 1; q < 16; ++q) best = cnt[q] > cnt[best] ? q : best;
+  out[e] = (uint8_t)best;
+}
+
+void coarsen_majority(const uint8_t* phase, int n, int nphase, uint8_t* out, hipStream_t s, int dim) {
+  const long M = 1L << (dim * (n - 1));
+  if (dim == 2)
+    hipLaunchKernelGGL(k_coarsen_majority2d, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, phase, n, nphase,
+                       out);
+  else
+    hipLaunchKernelGGL(k_coarsen_majority, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, phase, n, nphase,
+                       out);
   check(hipGetLastError(), "coarsen launch");
 }
 

@@ -290,9 +290,10 @@ void sum_middle(int batch, int outer, int np, int inner, const cplx* in,
 // out[p * NN + v] = (phase[v] == p) for p < nphase (device arrays); sets
 // *bad (device int) when a phase id is >= nphase.
 void onehot(const uint8_t* phase, long NN, int nphase, cplx* out, int* bad, hipStream_t s);
-// Majority phase of every 2 x 2 x 2 block of the 2^n grid (ties: lowest id)
-// into the 2^(n-1) grid; n >= 1, nphase <= 16.
-void coarsen_majority(const uint8_t* phase, int n, int nphase, uint8_t* out, hipStream_t s);
+// Majority phase of every 2 x 2 x 2 block of the 2^n grid (2 x 2 blocks of a
+// plane grid for dim 2; ties: lowest id) into the 2^(n-1) grid; n >= 1,
+// nphase <= 16.
+void coarsen_majority(const uint8_t* phase, int n, int nphase, uint8_t* out, hipStream_t s, int dim = 3);
 // Unit momentum directions n^sigma_a of the Green factors on the 2^n grid
 // (6 x 2^(3n) entries, control index (sigma, a) slowest, then x, y, z
 // bits); f, f2: device arrays of one axis's frequencies (2^n each).

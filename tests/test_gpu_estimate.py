@@ -69,3 +69,25 @@ def test_rank_estimate_beyond_the_device_path(ctx):
     want = Q.rank_estimate(p.phase, 2, 1e-10)
     assert got[:2] == want[:2]
     assert got[1] > 160
+
+
+PLANE = ["laminate", "square", "circle", "checkerboard", "spots", "voronoi"]
+
+
+@pytest.mark.parametrize("name", PLANE)
+@pytest.mark.parametrize("n", [5, 7])
+def test_plane_rank_estimate_matches_oracle(ctx, name, n):
+    """Plane geometries of the paper's suite (2 x 2 majority coarsening,
+    2n-bit one-hot trains): the oracle's ranks, exactly."""
+    ph = M.geometry(name, 1 << n, 2, seed=1)
+    got = q.rank_estimate(ctx, ph, 2, 1e-10)
+    want = Q.rank_estimate(ph, 2, 1e-10)
+    assert got[:2] == want[:2]
+    assert got[2] == pytest.approx(want[2])
+
+
+def test_plane_rank_estimate_device_array(ctx):
+    ph = M.geometry("voronoi", 64, 2, seed=1)
+    a = q.rank_estimate(ctx, ph, 2, 1e-8)
+    b = q.rank_estimate(ctx, torch.from_numpy(np.ascontiguousarray(ph)).cuda(), 2, 1e-8)
+    assert a == b
