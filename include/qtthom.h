@@ -452,8 +452,9 @@ int ls_adjoint_prepared(qtt_ctx* ctx, const qtt_prepared* prep,
  * Ceff: host [36] (plane problems: rows and columns 0..2).  gbar, grad:
  * as in ls_adjoint ([V][V] cotangent or NULL; [2 nphase] or the Jacobian
  * [V][V][2 nphase]).  R->iterations = steps, R->residual = the last
- * update's relative change.  QTT_EINVAL: steps outside 1..100000,
- * every < 0, or O->matvec other than QTT_MV_SKETCH. */
+ * update's relative change.  The V load cases run as one train batch on
+ * the context's stream (O->streams is not used).  QTT_EINVAL: steps
+ * outside 1..100000, every < 0, or O->matvec other than QTT_MV_SKETCH. */
 int ls_unrolled(qtt_ctx* ctx, const qtt_problem* P, const qtt_solve_opts* O,
                 int steps, int every, const double* gbar, double* Ceff,
                 double* grad, qtt_report* R);
