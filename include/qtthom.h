@@ -329,6 +329,16 @@ int qtt_from_voxels(qtt_ctx* ctx, const uint8_t* phase, int phase_on_device,
                     int n, int nphase, const double* lame,
                     const double lame0[2], double delta, int cap,
                     qtt_tensor** C_minus_C0, qtt_tensor** chi);
+/* qtt_from_voxels for a grid of dimension `dim`: 3 as above, or 2 for a
+ * plane-strain geometry (N^2 pixels, C order, x slowest, 1 <= n <= 12):
+ * core 0 of the operator is 3 x 3 (Voigt 11, 22, 12, the plane-strain
+ * stiffness of each phase minus C0's), then 2n binary cores.  Same
+ * outputs and codes; QTT_EINVAL for another `dim`. */
+int qtt_from_voxels_dim(qtt_ctx* ctx, const uint8_t* phase,
+                        int phase_on_device, int n, int nphase,
+                        const double* lame, const double lame0[2],
+                        double delta, int cap, int dim,
+                        qtt_tensor** C_minus_C0, qtt_tensor** chi);
 
 /* ---- products, each followed by TT-rounding --------------------------- */
 /* y = S x (or S^H x with QTT_INVERSE), Sec. 4.3 Alg. 2 lines for the SFFT

@@ -231,14 +231,13 @@ def green_build(ctx: Context, n: int, lam0: float, mu0: float, delta: float,
 
 def from_voxels(ctx: Context, phase, lame, lame0, delta: float, cap: int = 0):
     """(C - C0) raised operator and the one-hot phase train; ``phase`` is a
-    host array or a torch uint8 device tensor (read in place)."""
+    host array or a torch uint8 device tensor (read in place), cubic (3D,
+    Voigt 6) or square (plane strain, Voigt 3)."""
     p, keep = _problem(phase, lame, lame0, 0)
-    if p.dim != 3:
-        raise ValueError("from_voxels: a cubic (N, N, N) voxel array")
     l0 = np.ascontiguousarray(lame0, dtype=np.float64)
     h, chi = C.c_void_p(), C.c_void_p()
-    ctx.check(_c.lib().qtt_from_voxels(
-        ctx.h, p.phase, p.phase_on_device, p.n, p.nphase, p.lame, _dp(l0), delta, cap,
+    ctx.check(_c.lib().qtt_from_voxels_dim(
+        ctx.h, p.phase, p.phase_on_device, p.n, p.nphase, p.lame, _dp(l0), delta, cap, p.dim,
         C.byref(h), C.byref(chi)))
     del keep
     return Tensor(ctx, h), Tensor(ctx, chi)

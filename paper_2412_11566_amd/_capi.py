@@ -94,6 +94,7 @@ SIGNATURES = {
     "qtt_green_build": (I, [P, I, D, D, D, PP]),
     "qtt_green_build_scheme": (I, [P, I, D, D, D, I, PP]),
     "qtt_from_voxels": (I, [P, C.POINTER(C.c_uint8), I, I, I, DP, DP, D, I, PP, PP]),
+    "qtt_from_voxels_dim": (I, [P, C.POINTER(C.c_uint8), I, I, I, DP, DP, D, I, I, PP, PP]),
     "qtt_rank_estimate": (I, [P, C.POINTER(C.c_uint8), I, I, I, D, IP, DP]),
     "qtt_rank_estimate_dim": (I, [P, C.POINTER(C.c_uint8), I, I, I, D, I, IP, DP]),
     "sfft_apply": (I, [P, P, P, PP, I, D, I, U64]),

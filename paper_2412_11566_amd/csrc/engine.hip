@@ -2898,12 +2898,20 @@ int qtt_rank_estimate_dim(qtt_ctx* c, const uint8_t* phase, int phase_on_device,
 int qtt_from_voxels(qtt_ctx* c, const uint8_t* phase, int phase_on_device, int n, int nphase,
                     const double* lame, const double lame0[2], double delta, int cap,
                     qtt_tensor** Cm, qtt_tensor** chi) {
-  if (!c || !phase || !lame || !lame0 || !Cm || n < 1 || n > 9 || nphase < 1 || nphase > 16)
+  return qtt_from_voxels_dim(c, phase, phase_on_device, n, nphase, lame, lame0, delta, cap, 3, Cm, chi);
+}
+
+int qtt_from_voxels_dim(qtt_ctx* c, const uint8_t* phase, int phase_on_device, int n, int nphase,
+                        const double* lame, const double lame0[2], double delta, int cap, int dim,
+                        qtt_tensor** Cm, qtt_tensor** chi) {
+  if (!c || !phase || !lame || !lame0 || !Cm || (dim != 2 && dim != 3) || n < 1 || n > (dim == 2 ? 12 : 9) ||
+      nphase < 1 || nphase > 16)
     return QTT_EINVAL;
   QTT_TRY(c, {
     Ctx X{c};
     host::HTT chih;
-    host::HTT cd = stiffness_op(X, phase, phase_on_device != 0, n, nphase, lame, lame0, delta, cap, &chih);
+    host::HTT cd =
+        stiffness_op(X, phase, phase_on_device != 0, n, nphase, lame, lame0, delta, cap, &chih, dim);
     *Cm = new qtt_tensor(*upload_op(X, cd));
     if (chi) {
       // the one-hot train as a train (kind 0, batch 1)

@@ -131,3 +131,38 @@ def test_from_voxels_rank_cap(ctx):
     with pytest.raises(q.QttError) as e:
         q.from_voxels(ctx, bad, p.lame, p.lame0, 1e-10)
     assert e.value.code == q._c.QTT_EINVAL
+
+
+def _diag_train_plane(op_cores):
+    c0 = op_cores[0]
+    out = [c0.reshape(1, 9, c0.shape[3])]
+    for c in op_cores[1:]:
+        out.append(np.stack([c[:, i, i, :] for i in range(c.shape[1])], axis=1))
+    return out
+
+
+@pytest.mark.parametrize("name,N,P", [("circle", 32, 2), ("voronoi", 64, 2), ("spots", 64, 2), ("three", 32, 3)])
+def test_from_voxels_plane_every_pixel(ctx, name, N, P):
+    """Plane-strain geometries (2n binary cores, a 3 x 3 control core): the
+    operator equals the per-pixel plane-strain stiffness minus C0's on every
+    pixel to rounding at accuracy 1e-14, and the one-hot train meets the
+    TT-SVD bound at 1e-8 (Sec. 3, eq. rounding_condition_tt)."""
+    from oracle import plane as P2
+    if name == "three":
+        ph = M.geometry("circle", N, 2, seed=1).astype(np.uint8)
+        ph[M.geometry("square", N, 2, seed=1) == 1] = 2
+    else:
+        ph = M.geometry(name, N, 2, seed=1)
+    lame = np.array([[0.6, 0.4], [5.0, 3.0], [12.0, 9.0]])[:P]
+    l0 = (6.3, 4.7)
+    A, chi = q.from_voxels(ctx, ph, lame, l0, 1e-14)
+    got = Q.tt_full(_diag_train_plane(A.cores())).reshape(3, 3, -1).transpose(2, 0, 1)
+    dC = np.stack([P2.iso_voigt2(*lp) - P2.iso_voigt2(*l0) for lp in lame])
+    ref = dC[ph.ravel()]
+    # rounding level of a TT-SVD over 2n bonds, as for the 3D operator
+    nrm = np.sqrt(ph.size)
+    assert np.abs(got - ref).max() < 1e-12 * nrm * np.abs(ref).max()
+    onehot = np.stack([(ph.ravel() == p) for p in range(P)]).astype(float)
+    _, chi8 = q.from_voxels(ctx, ph, lame, l0, 1e-8)
+    c = Q.tt_full([x[0] for x in chi8.cores()]).reshape(P, -1)
+    assert np.linalg.norm(c - onehot) <= 1e-8 * nrm * (1 + 1e-6)
